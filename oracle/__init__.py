@@ -1,0 +1,225 @@
+"""FP64 CPU oracle for 3D Gaussian ray tracing -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import this
+package. The product path (the HIP library and its Python binding) never imports it.
+
+The numerical work lives in ``grtx_oracle.c`` (plain C, FP64, brute force over every
+ray/Gaussian pair); this module compiles it with gcc on first use and wraps it with
+ctypes. Each wrapper names the part of the paper it follows; the C file's header states
+the full definition.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "grtx_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+GCC_CMD = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+           "-pthread", _SRC, "-o", _LIB_PATH, "-lm"]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle's C source into ``oracle/liboracle.so``."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = GCC_CMD[:-3] + ["-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _p(a, ctype):
+    return None if a is None else a.ctypes.data_as(C.POINTER(ctype))
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            L = C.CDLL(_LIB_PATH)
+            f, d, i32, i64, u32, u64 = C.c_float, C.c_double, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64
+            PF, PD = C.POINTER(f), C.POINTER(d)
+            L.oracle_render.restype = C.c_int
+            L.oracle_render.argtypes = [PF, PF, PF, PF, PF, i64, C.c_int, i64, PF, PF, d, d, d, PD, C.c_int,
+                                        PD, PD, PD, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), PD, PD,
+                                        C.c_int, C.c_int]
+            L.oracle_ray_hits.restype = i64
+            L.oracle_ray_hits.argtypes = [PF, PF, PF, PF, i64, PF, PF, d, d, C.c_int, C.POINTER(i64), PD, PD,
+                                          PD, i64]
+            L.oracle_composite_list.restype = C.c_int
+            L.oracle_composite_list.argtypes = [PF, PF, PF, PF, PF, i64, C.c_int, PF, PF, C.POINTER(i32), i64,
+                                                d, PD, PD, PD, PD]
+            L.oracle_gaussian_aabb.restype = C.c_int
+            L.oracle_gaussian_aabb.argtypes = [PF, PF, PF, PF, i64, d, PD, PD, C.POINTER(i32)]
+            L.oracle_pinhole_rays.restype = C.c_int
+            L.oracle_pinhole_rays.argtypes = [PD, PD, PD, d, C.c_int, C.c_int, PD, PD]
+            L.oracle_morton.restype = C.c_int
+            L.oracle_morton.argtypes = [i64, PF, C.POINTER(u64)]
+            L.oracle_lbvh_topology.restype = C.c_int
+            L.oracle_lbvh_topology.argtypes = [i64, PF, C.POINTER(u64), C.POINTER(u32), C.POINTER(u32),
+                                               C.POINTER(u32)]
+            L.oracle_sh_basis.restype = d
+            L.oracle_sh_basis.argtypes = [C.c_int, C.c_int, PD]
+            L.oracle_icosahedron.restype = C.c_int
+            L.oracle_icosahedron.argtypes = [PD, C.POINTER(i32)]
+            _lib = L
+    return _lib
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _scene_args(scene):
+    return (_f32(scene.means), _f32(scene.scales), _f32(scene.quats), _f32(scene.opacities),
+            _f32(scene.sh.reshape(scene.n, -1)) if scene.sh is not None else None)
+
+
+def render(scene, origins, dirs, alpha_min=1.0 / 255.0, T_min=1e-3, t_near=0.0, bg=(0.0, 0.0, 0.0),
+           key_mode=0, cap=0, nthreads=0):
+    """Brute-force render of the given float32 rays (Eq. 1, Eq. 2, Sec. III-A).
+
+    key_mode 0 orders hits by ellipsoid entry distance, 1 by bounding-icosahedron entry
+    distance. With cap > 0 also returns, per ray, the first `cap` blended ids, the
+    transmittance after each and each hit's key distance."""
+    L = lib()
+    o = _f32(origins).reshape(-1, 3)
+    d = _f32(dirs).reshape(-1, 3)
+    R = o.shape[0]
+    m, s, q, op, sh = _scene_args(scene)
+    rgb = np.zeros((R, 3), np.float64)
+    depth = np.zeros(R, np.float64)
+    opac = np.zeros(R, np.float64)
+    nblend = np.zeros(R, np.int32)
+    nhits = np.zeros(R, np.int32)
+    ids = np.full((R, max(cap, 1)), -1, np.int32) if cap > 0 else None
+    tafter = np.zeros((R, max(cap, 1)), np.float64) if cap > 0 else None
+    tkey = np.zeros((R, max(cap, 1)), np.float64) if cap > 0 else None
+    bga = np.asarray(bg, np.float64)
+    rc = L.oracle_render(_p(m, C.c_float), _p(s, C.c_float), _p(q, C.c_float), _p(op, C.c_float),
+                         _p(sh, C.c_float), scene.n, scene.sh_degree, R, _p(o, C.c_float), _p(d, C.c_float),
+                         alpha_min, T_min, t_near, _p(bga, C.c_double), key_mode,
+                         _p(rgb, C.c_double), _p(depth, C.c_double), _p(opac, C.c_double),
+                         _p(nblend, C.c_int32), _p(nhits, C.c_int32), _p(ids, C.c_int32),
+                         _p(tafter, C.c_double), _p(tkey, C.c_double), cap, nthreads)
+    if rc != 0:
+        raise RuntimeError(f"oracle_render failed ({rc})")
+    out = dict(rgb=rgb, depth=depth, opacity=opac, nblend=nblend, nhits=nhits)
+    if cap > 0:
+        out.update(ids=ids, tafter=tafter, tkey=tkey)
+    return out
+
+
+def ray_hits(scene, origin, direction, alpha_min=1.0 / 255.0, t_near=0.0, key_mode=0):
+    """All hits of one ray sorted by (key distance, id): ids, key, alpha, t_alpha."""
+    L = lib()
+    m, s, q, op, _ = _scene_args(scene)
+    o = _f32(origin).reshape(3)
+    d = _f32(direction).reshape(3)
+    cap = scene.n
+    ids = np.zeros(max(cap, 1), np.int64)
+    tk = np.zeros(max(cap, 1), np.float64)
+    al = np.zeros(max(cap, 1), np.float64)
+    ta = np.zeros(max(cap, 1), np.float64)
+    nh = L.oracle_ray_hits(_p(m, C.c_float), _p(s, C.c_float), _p(q, C.c_float), _p(op, C.c_float), scene.n,
+                           _p(o, C.c_float), _p(d, C.c_float), alpha_min, t_near, key_mode,
+                           _p(ids, C.c_int64), _p(tk, C.c_double), _p(al, C.c_double), _p(ta, C.c_double), cap)
+    if nh < 0:
+        raise RuntimeError("oracle_ray_hits failed")
+    return dict(ids=ids[:nh], t=tk[:nh], alpha=al[:nh], talpha=ta[:nh])
+
+
+def composite_list(scene, origin, direction, ids, alpha_min=1.0 / 255.0, bg=(0.0, 0.0, 0.0)):
+    """Composite an explicit ordered id list along one ray (Eq. 1 with Eq. 2 alphas)."""
+    L = lib()
+    m, s, q, op, sh = _scene_args(scene)
+    o = _f32(origin).reshape(3)
+    d = _f32(direction).reshape(3)
+    lst = np.ascontiguousarray(ids, np.int32)
+    rgb = np.zeros(3, np.float64)
+    dep = np.zeros(1, np.float64)
+    opa = np.zeros(1, np.float64)
+    bga = np.asarray(bg, np.float64)
+    rc = L.oracle_composite_list(_p(m, C.c_float), _p(s, C.c_float), _p(q, C.c_float), _p(op, C.c_float),
+                                 _p(sh, C.c_float), scene.n, scene.sh_degree, _p(o, C.c_float), _p(d, C.c_float),
+                                 _p(lst, C.c_int32), lst.size, alpha_min, _p(bga, C.c_double),
+                                 _p(rgb, C.c_double), _p(dep, C.c_double), _p(opa, C.c_double))
+    if rc != 0:
+        raise RuntimeError("oracle_composite_list failed")
+    return dict(rgb=rgb, depth=float(dep[0]), opacity=float(opa[0]))
+
+
+def gaussian_aabb(scene, alpha_min=1.0 / 255.0):
+    """FP64 axis-aligned bounds of each Gaussian's bounding ellipsoid."""
+    L = lib()
+    m, s, q, op, _ = _scene_args(scene)
+    lo = np.zeros((scene.n, 3), np.float64)
+    hi = np.zeros((scene.n, 3), np.float64)
+    act = np.zeros(scene.n, np.int32)
+    L.oracle_gaussian_aabb(_p(m, C.c_float), _p(s, C.c_float), _p(q, C.c_float), _p(op, C.c_float), scene.n,
+                           alpha_min, _p(lo, C.c_double), _p(hi, C.c_double), _p(act, C.c_int32))
+    return lo, hi, act.astype(bool)
+
+
+def pinhole_rays(camera):
+    """FP64 pinhole primary rays, one per pixel centre, row-major from the top row."""
+    L = lib()
+    W, H = camera.width, camera.height
+    o = np.zeros((W * H, 3), np.float64)
+    d = np.zeros((W * H, 3), np.float64)
+    eye = np.asarray(camera.eye, np.float64)
+    tgt = np.asarray(camera.target, np.float64)
+    up = np.asarray(camera.up, np.float64)
+    rc = L.oracle_pinhole_rays(_p(eye, C.c_double), _p(tgt, C.c_double), _p(up, C.c_double), camera.fov_y_deg,
+                               W, H, _p(o, C.c_double), _p(d, C.c_double))
+    if rc != 0:
+        raise RuntimeError("oracle_pinhole_rays failed")
+    return o, d
+
+
+def morton(means):
+    L = lib()
+    m = _f32(means).reshape(-1, 3)
+    codes = np.zeros(m.shape[0], np.uint64)
+    L.oracle_morton(m.shape[0], _p(m, C.c_float), _p(codes, C.c_uint64))
+    return codes
+
+
+def lbvh_topology(means):
+    """Sorted Morton codes, permutation, child [(n-1),2] and parent [2n-1] arrays."""
+    L = lib()
+    m = _f32(means).reshape(-1, 3)
+    n = m.shape[0]
+    codes = np.zeros(n, np.uint64)
+    perm = np.zeros(n, np.uint32)
+    child = np.zeros((max(n - 1, 1), 2), np.uint32)
+    parent = np.zeros(max(2 * n - 1, 1), np.uint32)
+    rc = L.oracle_lbvh_topology(n, _p(m, C.c_float), _p(codes, C.c_uint64), _p(perm, C.c_uint32),
+                                _p(child, C.c_uint32), _p(parent, C.c_uint32))
+    if rc != 0:
+        raise RuntimeError("oracle_lbvh_topology failed")
+    return dict(codes=codes, perm=perm, child=child[: max(n - 1, 0)], parent=parent[: max(2 * n - 1, 0)])
+
+
+def sh_basis(l, m, direction):
+    L = lib()
+    d = np.ascontiguousarray(direction, np.float64).reshape(3)
+    return L.oracle_sh_basis(l, m, _p(d, C.c_double))
+
+
+def icosahedron():
+    L = lib()
+    v = np.zeros((12, 3), np.float64)
+    f = np.zeros((20, 3), np.int32)
+    L.oracle_icosahedron(_p(v, C.c_double), _p(f, C.c_int32))
+    return v, f

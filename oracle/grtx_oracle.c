@@ -1,0 +1,715 @@
+/*
+ * grtx_oracle.c -- FP64 brute-force reference for 3D Gaussian ray tracing.
+ *
+ * TEST INFRASTRUCTURE ONLY. This file is the oracle that the GPU path is checked
+ * against. It is called by the tests, by the smoke check and by the benchmark's CPU
+ * baseline, and by nothing else; the product path never links or calls it. It shares
+ * no code, header, table or constant with the GPU library.
+ *
+ * What it computes is the plain definition of the rendered image, written out without
+ * any acceleration structure, blocking or reordering:
+ *
+ *   - Gaussians (Sec. II-B): mean mu, covariance Sigma = R S S^T R^T with R the
+ *     rotation of the normalised quaternion (w,x,y,z) and S = diag(s), opacity o,
+ *     real spherical-harmonic colour coefficients.
+ *   - Each Gaussian is bounded by the ellipsoid of Mahalanobis radius rho with
+ *     rho^2 = 2 ln(o / alpha_min): on that surface o*G = alpha_min ("an ellipsoid with
+ *     defined boundaries", Sec. II-B). Gaussians with o <= alpha_min are never hit.
+ *   - Every ray is tested against every Gaussian. A hit is a ray that meets the
+ *     ellipsoid with entry distance t0 > t_near (the smaller root of the quadric).
+ *     Hits are sorted by distance (Sec. III-A: the intersection distance is the depth
+ *     used by the k-buffer), ties by Gaussian index.
+ *   - Alpha of a hit at the point of maximum response along the ray (Eq. 2):
+ *     t_alpha = (mu - o)^T Sigma^-1 d / (d^T Sigma^-1 d), alpha = o * G(o + t_alpha d).
+ *   - Colour from SH evaluated at the normalised ray direction (Sec. III-A), offset by
+ *     0.5 and clamped at zero.
+ *   - Front-to-back compositing (Eq. 1) with early ray termination (Sec. III-A): the
+ *     hit that drops transmittance below T_min is still blended, then the ray stops.
+ *   - Output: colour C + T*bg, depth sum(w_i t_alpha_i), opacity 1 - T.
+ *
+ * Proxy-key mode orders the same hits by the distance at which the ray enters the
+ * Gaussian's bounding icosahedron (20 triangles, inradius 1 in the space where the
+ * bounding ellipsoid is the unit sphere), the bounding mesh of the triangle-based
+ * baseline (Sec. III-C, Observation I).
+ *
+ * The LBVH reference (Morton codes, stable sort, radix tree) gives the topology that
+ * the GPU build must reproduce bit for bit; its tree is the plain top-down definition
+ * (split each key range where the highest differing key bit changes).
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <unistd.h>
+
+#define OR_OK 0
+#define OR_ERR_ARG 1
+#define OR_ERR_MEM 2
+
+/* ------------------------------------------------------------------------------------ */
+/* Small linear algebra                                                                  */
+/* ------------------------------------------------------------------------------------ */
+
+static void quat_to_rot(const float qf[4], double R[3][3]) {
+  double w = qf[0], x = qf[1], y = qf[2], z = qf[3];
+  double n = sqrt(w * w + x * x + y * y + z * z);
+  w /= n; x /= n; y /= n; z /= n;
+  R[0][0] = 1 - 2 * (y * y + z * z); R[0][1] = 2 * (x * y - w * z);     R[0][2] = 2 * (x * z + w * y);
+  R[1][0] = 2 * (x * y + w * z);     R[1][1] = 1 - 2 * (x * x + z * z); R[1][2] = 2 * (y * z - w * x);
+  R[2][0] = 2 * (x * z - w * y);     R[2][1] = 2 * (y * z + w * x);     R[2][2] = 1 - 2 * (x * x + y * y);
+}
+
+static double quad_form(const double M[3][3], const double a[3], const double b[3]) {
+  double s = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) s += a[i] * M[i][j] * b[j];
+  return s;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Real spherical harmonics (orthonormal, Condon-Shortley phase), from the definition    */
+/* Y_l^m = sqrt(2) K_l^|m| P_l^|m|(cos th) {cos(m ph) | sin(|m| ph)}, K from factorials. */
+/* ------------------------------------------------------------------------------------ */
+
+static double factorial(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return f;
+}
+
+/* Associated Legendre P_l^m(x), m >= 0, with the (-1)^m phase. */
+static double legendre_p(int l, int m, double x) {
+  double pmm = 1.0;
+  if (m > 0) {
+    double somx2 = sqrt((1.0 - x) * (1.0 + x));
+    double fact = 1.0;
+    for (int i = 1; i <= m; ++i) {
+      pmm *= -fact * somx2;
+      fact += 2.0;
+    }
+  }
+  if (l == m) return pmm;
+  double pmmp1 = x * (2 * m + 1) * pmm;
+  if (l == m + 1) return pmmp1;
+  double pll = 0.0;
+  for (int ll = m + 2; ll <= l; ++ll) {
+    pll = ((2 * ll - 1) * x * pmmp1 - (ll + m - 1) * pmm) / (ll - m);
+    pmm = pmmp1;
+    pmmp1 = pll;
+  }
+  return pll;
+}
+
+double oracle_sh_basis(int l, int m, const double dir[3]) {
+  double r = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+  double x = dir[0] / r, y = dir[1] / r, z = dir[2] / r;
+  double ct = z;
+  double ph = atan2(y, x);
+  int am = m < 0 ? -m : m;
+  double K = sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * factorial(l - am) / factorial(l + am));
+  double P = legendre_p(l, am, ct);
+  if (m == 0) return K * P;
+  if (m > 0) return sqrt(2.0) * K * cos(m * ph) * P;
+  return sqrt(2.0) * K * sin(am * ph) * P;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Per-Gaussian preparation                                                              */
+/* ------------------------------------------------------------------------------------ */
+
+typedef struct {
+  double mu[3];
+  double sinv[3][3]; /* Sigma^-1 = R S^-2 R^T */
+  double rho2;       /* 2 ln(o / alpha_min) */
+  double opacity;
+  int active;
+  double *tri;       /* proxy mode: 20 triangles x 3 vertices x 3, world space */
+} og_t;
+
+typedef struct {
+  const float *means, *scales, *quats, *opac, *sh;
+  int64_t n;
+  int sh_degree;
+} scene_t;
+
+/* Regular icosahedron with inradius 1: vertices (0,+-1,+-phi) and cyclic permutations,
+ * faces = vertex triples at pairwise distance 2 (the edge length), wound outward, then
+ * scaled so that every face plane is at distance 1 from the centre. */
+static int g_ico_ready = 0;
+static double g_ico_v[12][3];
+static int g_ico_f[20][3];
+static pthread_mutex_t g_ico_lock = PTHREAD_MUTEX_INITIALIZER;
+
+static void ico_init(void) {
+  pthread_mutex_lock(&g_ico_lock);
+  if (g_ico_ready) { pthread_mutex_unlock(&g_ico_lock); return; }
+  const double phi = (1.0 + sqrt(5.0)) / 2.0;
+  int nv = 0;
+  for (int a = -1; a <= 1; a += 2)
+    for (int b = -1; b <= 1; b += 2) {
+      double p[3][3] = {{0, a * 1.0, b * phi}, {a * 1.0, b * phi, 0}, {b * phi, 0, a * 1.0}};
+      for (int c = 0; c < 3; ++c) {
+        g_ico_v[nv][0] = p[c][0]; g_ico_v[nv][1] = p[c][1]; g_ico_v[nv][2] = p[c][2];
+        ++nv;
+      }
+    }
+  int nf = 0;
+  for (int i = 0; i < 12; ++i)
+    for (int j = i + 1; j < 12; ++j)
+      for (int k = j + 1; k < 12; ++k) {
+        int idx[3] = {i, j, k};
+        int ok = 1;
+        for (int e = 0; e < 3 && ok; ++e) {
+          const double *p = g_ico_v[idx[e]], *q = g_ico_v[idx[(e + 1) % 3]];
+          double d2 = (p[0] - q[0]) * (p[0] - q[0]) + (p[1] - q[1]) * (p[1] - q[1]) + (p[2] - q[2]) * (p[2] - q[2]);
+          if (fabs(d2 - 4.0) > 1e-9) ok = 0;
+        }
+        if (!ok) continue;
+        const double *A = g_ico_v[i], *B = g_ico_v[j], *C = g_ico_v[k];
+        double e1[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+        double e2[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+        double nrm[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        double cen = nrm[0] * (A[0] + B[0] + C[0]) + nrm[1] * (A[1] + B[1] + C[1]) + nrm[2] * (A[2] + B[2] + C[2]);
+        if (cen > 0) { g_ico_f[nf][0] = i; g_ico_f[nf][1] = j; g_ico_f[nf][2] = k; }
+        else { g_ico_f[nf][0] = i; g_ico_f[nf][1] = k; g_ico_f[nf][2] = j; }
+        ++nf;
+      }
+  /* inradius: distance from the centre to the plane of a face */
+  const double *A = g_ico_v[g_ico_f[0][0]], *B = g_ico_v[g_ico_f[0][1]], *C = g_ico_v[g_ico_f[0][2]];
+  double e1[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+  double e2[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+  double nrm[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+  double nl = sqrt(nrm[0] * nrm[0] + nrm[1] * nrm[1] + nrm[2] * nrm[2]);
+  double rin = (nrm[0] * A[0] + nrm[1] * A[1] + nrm[2] * A[2]) / nl;
+  for (int v = 0; v < 12; ++v)
+    for (int c = 0; c < 3; ++c) g_ico_v[v][c] /= rin;
+  (void)nf;
+  g_ico_ready = 1;
+  pthread_mutex_unlock(&g_ico_lock);
+}
+
+int oracle_icosahedron(double *verts /* 12x3 */, int32_t *faces /* 20x3 */) {
+  ico_init();
+  memcpy(verts, g_ico_v, sizeof g_ico_v);
+  for (int f = 0; f < 20; ++f)
+    for (int c = 0; c < 3; ++c) faces[f * 3 + c] = g_ico_f[f][c];
+  return OR_OK;
+}
+
+static void prepare_one(const scene_t *s, int64_t i, double alpha_min, int proxy, og_t *g) {
+  double R[3][3];
+  quat_to_rot(s->quats + 4 * i, R);
+  double sc[3] = {s->scales[3 * i], s->scales[3 * i + 1], s->scales[3 * i + 2]};
+  for (int a = 0; a < 3; ++a) g->mu[a] = s->means[3 * i + a];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      double acc = 0.0;
+      for (int k = 0; k < 3; ++k) acc += R[a][k] * R[b][k] / (sc[k] * sc[k]);
+      g->sinv[a][b] = acc;
+    }
+  g->opacity = s->opac[i];
+  g->active = g->opacity > alpha_min;
+  g->rho2 = g->active ? 2.0 * log(g->opacity / alpha_min) : 0.0;
+  g->tri = NULL;
+  if (proxy && g->active) {
+    /* world vertex = mu + R S rho * unit-space vertex */
+    double rho = sqrt(g->rho2);
+    double wv[12][3];
+    for (int v = 0; v < 12; ++v)
+      for (int a = 0; a < 3; ++a) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k) acc += R[a][k] * sc[k] * rho * g_ico_v[v][k];
+        wv[v][a] = g->mu[a] + acc;
+      }
+    g->tri = (double *)malloc(sizeof(double) * 20 * 9);
+    for (int f = 0; f < 20; ++f)
+      for (int c = 0; c < 3; ++c)
+        for (int a = 0; a < 3; ++a) g->tri[f * 9 + c * 3 + a] = wv[g_ico_f[f][c]][a];
+  }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Ray / Gaussian                                                                        */
+/* ------------------------------------------------------------------------------------ */
+
+typedef struct {
+  double t;       /* sort key distance */
+  int64_t id;
+  double alpha;
+  double talpha;
+} hit_t;
+
+/* Ellipsoid entry: smallest root of (o + t d - mu)^T Sigma^-1 (o + t d - mu) = rho^2. */
+static int ellipsoid_entry(const og_t *g, const double o[3], const double d[3], double t_near, double *t0) {
+  if (!g->active) return 0;
+  double f[3] = {o[0] - g->mu[0], o[1] - g->mu[1], o[2] - g->mu[2]};
+  double A = quad_form(g->sinv, d, d);
+  double B = quad_form(g->sinv, f, d);
+  double C = quad_form(g->sinv, f, f) - g->rho2;
+  double disc = B * B - A * C;
+  if (!(disc >= 0.0)) return 0;
+  double t = (-B - sqrt(disc)) / A;
+  if (!(t > t_near)) return 0;
+  *t0 = t;
+  return 1;
+}
+
+/* Eq. 2: alpha at the point of maximum response along the ray. */
+static void max_response(const og_t *g, const double o[3], const double d[3], double *alpha, double *talpha) {
+  double mo[3] = {g->mu[0] - o[0], g->mu[1] - o[1], g->mu[2] - o[2]};
+  double ta = quad_form(g->sinv, mo, d) / quad_form(g->sinv, d, d);
+  double x[3] = {o[0] + ta * d[0] - g->mu[0], o[1] + ta * d[1] - g->mu[1], o[2] + ta * d[2] - g->mu[2]};
+  double G = exp(-0.5 * quad_form(g->sinv, x, x));
+  *alpha = g->opacity * G;
+  *talpha = ta;
+}
+
+/* Smallest t > t_near among the front-facing icosahedron faces the ray crosses. */
+static int proxy_entry(const og_t *g, const double o[3], const double d[3], double t_near, double *tp) {
+  if (!g->tri) return 0;
+  int found = 0;
+  double best = 0.0;
+  for (int f = 0; f < 20; ++f) {
+    const double *A = g->tri + f * 9, *B = A + 3, *C = A + 6;
+    double e1[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+    double e2[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+    double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    double dn = n[0] * d[0] + n[1] * d[1] + n[2] * d[2];
+    if (!(dn < 0.0)) continue; /* back-facing or parallel */
+    /* Moller-Trumbore */
+    double p[3] = {d[1] * e2[2] - d[2] * e2[1], d[2] * e2[0] - d[0] * e2[2], d[0] * e2[1] - d[1] * e2[0]};
+    double det = e1[0] * p[0] + e1[1] * p[1] + e1[2] * p[2];
+    double inv = 1.0 / det;
+    double s[3] = {o[0] - A[0], o[1] - A[1], o[2] - A[2]};
+    double u = (s[0] * p[0] + s[1] * p[1] + s[2] * p[2]) * inv;
+    if (u < 0.0 || u > 1.0) continue;
+    double q[3] = {s[1] * e1[2] - s[2] * e1[1], s[2] * e1[0] - s[0] * e1[2], s[0] * e1[1] - s[1] * e1[0]};
+    double v = (d[0] * q[0] + d[1] * q[1] + d[2] * q[2]) * inv;
+    if (v < 0.0 || u + v > 1.0) continue;
+    double t = (e2[0] * q[0] + e2[1] * q[1] + e2[2] * q[2]) * inv;
+    if (!(t > t_near)) continue;
+    if (!found || t < best) { best = t; found = 1; }
+  }
+  if (found) *tp = best;
+  return found;
+}
+
+/* Sphere validity of a proxy hit: the line meets the bounding ellipsoid. */
+static int line_meets_ellipsoid(const og_t *g, const double o[3], const double d[3]) {
+  if (!g->active) return 0;
+  double f[3] = {o[0] - g->mu[0], o[1] - g->mu[1], o[2] - g->mu[2]};
+  double A = quad_form(g->sinv, d, d);
+  double B = quad_form(g->sinv, f, d);
+  double C = quad_form(g->sinv, f, f) - g->rho2;
+  return B * B - A * C >= 0.0;
+}
+
+static void sh_colour(const scene_t *s, int64_t i, const double d[3], double out[3]) {
+  int K = (s->sh_degree + 1) * (s->sh_degree + 1);
+  const float *c = s->sh + (size_t)i * K * 3;
+  double acc[3] = {0.5, 0.5, 0.5};
+  for (int l = 0; l <= s->sh_degree; ++l)
+    for (int m = -l; m <= l; ++m) {
+      double Y = oracle_sh_basis(l, m, d);
+      int j = l * l + l + m;
+      for (int ch = 0; ch < 3; ++ch) acc[ch] += Y * c[j * 3 + ch];
+    }
+  for (int ch = 0; ch < 3; ++ch) out[ch] = acc[ch] > 0.0 ? acc[ch] : 0.0;
+}
+
+static int hit_cmp(const void *a, const void *b) {
+  const hit_t *x = (const hit_t *)a, *y = (const hit_t *)b;
+  if (x->t < y->t) return -1;
+  if (x->t > y->t) return 1;
+  return (x->id > y->id) - (x->id < y->id);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Render                                                                                */
+/* ------------------------------------------------------------------------------------ */
+
+typedef struct {
+  double alpha_min, T_min, t_near;
+  double bg[3];
+  int key_mode; /* 0: ellipsoid entry; 1: icosahedron entry */
+} params_t;
+
+typedef struct {
+  const scene_t *s;
+  const og_t *g;
+  const params_t *p;
+  const float *ro, *rd;
+  int64_t r0, r1;
+  double *rgb, *depth, *opac;
+  int32_t *nblend, *nhits;
+  int32_t *ids; double *tafter; double *tkey; int cap;
+} job_t;
+
+static void render_one(const job_t *J, int64_t r, hit_t **buf, size_t *bufcap) {
+  const scene_t *s = J->s;
+  const params_t *p = J->p;
+  double o[3] = {J->ro[3 * r], J->ro[3 * r + 1], J->ro[3 * r + 2]};
+  double d[3] = {J->rd[3 * r], J->rd[3 * r + 1], J->rd[3 * r + 2]};
+  size_t nh = 0;
+  for (int64_t i = 0; i < s->n; ++i) {
+    const og_t *g = J->g + i;
+    double key;
+    if (p->key_mode == 0) {
+      if (!ellipsoid_entry(g, o, d, p->t_near, &key)) continue;
+    } else {
+      if (!proxy_entry(g, o, d, p->t_near, &key)) continue;
+      if (!line_meets_ellipsoid(g, o, d)) continue;
+    }
+    if (nh == *bufcap) {
+      *bufcap = *bufcap ? 2 * *bufcap : 256;
+      *buf = (hit_t *)realloc(*buf, *bufcap * sizeof(hit_t));
+    }
+    hit_t *h = *buf + nh++;
+    h->t = key;
+    h->id = i;
+    max_response(g, o, d, &h->alpha, &h->talpha);
+  }
+  qsort(*buf, nh, sizeof(hit_t), hit_cmp);
+  double T = 1.0, C[3] = {0, 0, 0}, D = 0.0;
+  int nb = 0;
+  for (size_t h = 0; h < nh; ++h) {
+    const hit_t *x = *buf + h;
+    double c[3];
+    sh_colour(s, x->id, d, c);
+    double w = T * x->alpha;
+    for (int ch = 0; ch < 3; ++ch) C[ch] += w * c[ch];
+    D += w * x->talpha;
+    T *= (1.0 - x->alpha);
+    if (nb < J->cap) {
+      if (J->ids) J->ids[r * J->cap + nb] = (int32_t)x->id;
+      if (J->tafter) J->tafter[r * J->cap + nb] = T;
+      if (J->tkey) J->tkey[r * J->cap + nb] = x->t;
+    }
+    ++nb;
+    if (T < p->T_min) break;
+  }
+  for (int ch = 0; ch < 3; ++ch) J->rgb[3 * r + ch] = C[ch] + T * p->bg[ch];
+  J->depth[r] = D;
+  J->opac[r] = 1.0 - T;
+  if (J->nblend) J->nblend[r] = nb;
+  if (J->nhits) J->nhits[r] = (int32_t)nh;
+}
+
+static void *render_worker(void *arg) {
+  job_t *J = (job_t *)arg;
+  hit_t *buf = NULL;
+  size_t cap = 0;
+  for (int64_t r = J->r0; r < J->r1; ++r) render_one(J, r, &buf, &cap);
+  free(buf);
+  return NULL;
+}
+
+static int resolve_threads(int nthreads) {
+  if (nthreads > 0) return nthreads;
+  long n = sysconf(_SC_NPROCESSORS_ONLN);
+  return n > 0 ? (int)n : 1;
+}
+
+static og_t *prepare_all(const scene_t *s, double alpha_min, int proxy) {
+  if (proxy) ico_init();
+  og_t *g = (og_t *)malloc(sizeof(og_t) * (size_t)(s->n > 0 ? s->n : 1));
+  if (!g) return NULL;
+  for (int64_t i = 0; i < s->n; ++i) prepare_one(s, i, alpha_min, proxy, g + i);
+  return g;
+}
+
+static void free_all(og_t *g, int64_t n) {
+  if (!g) return;
+  for (int64_t i = 0; i < n; ++i) free(g[i].tri);
+  free(g);
+}
+
+/* Render R rays (float32 origins/directions, as given) against all Gaussians in FP64.
+ * Outputs per ray: rgb[3], depth, opacity; optionally the number of blended hits, the
+ * number of hits, and for the first `cap` blended hits their ids, the transmittance
+ * after each and the sort-key distance. */
+int oracle_render(const float *means, const float *scales, const float *quats, const float *opac,
+                  const float *sh, int64_t n, int sh_degree,
+                  int64_t nrays, const float *ray_o, const float *ray_d,
+                  double alpha_min, double T_min, double t_near, const double *bg, int key_mode,
+                  double *rgb, double *depth, double *opacity, int32_t *nblend, int32_t *nhits,
+                  int32_t *ids, double *tafter, double *tkey, int cap, int nthreads) {
+  if (n < 0 || nrays < 0 || sh_degree < 0 || sh_degree > 3 || !rgb || !depth || !opacity) return OR_ERR_ARG;
+  if (nrays == 0) return OR_OK;
+  scene_t s = {means, scales, quats, opac, sh, n, sh_degree};
+  params_t p = {alpha_min, T_min, t_near, {bg ? bg[0] : 0, bg ? bg[1] : 0, bg ? bg[2] : 0}, key_mode};
+  og_t *g = prepare_all(&s, alpha_min, key_mode == 1);
+  if (!g) return OR_ERR_MEM;
+  int nt = resolve_threads(nthreads);
+  if (nt > nrays) nt = (int)nrays;
+  pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * nt);
+  job_t *jobs = (job_t *)malloc(sizeof(job_t) * nt);
+  for (int t = 0; t < nt; ++t) {
+    job_t J = {&s, g, &p, ray_o, ray_d, nrays * t / nt, nrays * (t + 1) / nt,
+               rgb, depth, opacity, nblend, nhits, ids, tafter, tkey, ids || tafter || tkey ? cap : 0};
+    jobs[t] = J;
+    pthread_create(&th[t], NULL, render_worker, &jobs[t]);
+  }
+  for (int t = 0; t < nt; ++t) pthread_join(th[t], NULL);
+  free(th);
+  free(jobs);
+  free_all(g, n);
+  return OR_OK;
+}
+
+/* All hits of one ray, sorted by (key, id): ids, key distance, alpha, t_alpha. Returns
+ * the number of hits (entries beyond `cap` are not written). */
+int64_t oracle_ray_hits(const float *means, const float *scales, const float *quats, const float *opac,
+                        int64_t n, const float *ray_o, const float *ray_d, double alpha_min, double t_near,
+                        int key_mode, int64_t *ids, double *tkey, double *alpha, double *talpha, int64_t cap) {
+  scene_t s = {means, scales, quats, opac, NULL, n, 0};
+  og_t *g = prepare_all(&s, alpha_min, key_mode == 1);
+  if (!g) return -1;
+  double o[3] = {ray_o[0], ray_o[1], ray_o[2]}, d[3] = {ray_d[0], ray_d[1], ray_d[2]};
+  hit_t *buf = (hit_t *)malloc(sizeof(hit_t) * (size_t)(n > 0 ? n : 1));
+  int64_t nh = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    double key;
+    if (key_mode == 0) {
+      if (!ellipsoid_entry(g + i, o, d, t_near, &key)) continue;
+    } else {
+      if (!proxy_entry(g + i, o, d, t_near, &key)) continue;
+      if (!line_meets_ellipsoid(g + i, o, d)) continue;
+    }
+    buf[nh].t = key;
+    buf[nh].id = i;
+    max_response(g + i, o, d, &buf[nh].alpha, &buf[nh].talpha);
+    ++nh;
+  }
+  qsort(buf, (size_t)nh, sizeof(hit_t), hit_cmp);
+  for (int64_t h = 0; h < nh && h < cap; ++h) {
+    if (ids) ids[h] = buf[h].id;
+    if (tkey) tkey[h] = buf[h].t;
+    if (alpha) alpha[h] = buf[h].alpha;
+    if (talpha) talpha[h] = buf[h].talpha;
+  }
+  free(buf);
+  free_all(g, n);
+  return nh;
+}
+
+/* Composite a given ordered id list along one ray (Eq. 1 with Eq. 2 alphas), without
+ * any hit test and without early termination. */
+int oracle_composite_list(const float *means, const float *scales, const float *quats, const float *opac,
+                          const float *sh, int64_t n, int sh_degree, const float *ray_o, const float *ray_d,
+                          const int32_t *list, int64_t len, double alpha_min, const double *bg,
+                          double *rgb, double *depth, double *opacity) {
+  scene_t s = {means, scales, quats, opac, sh, n, sh_degree};
+  double o[3] = {ray_o[0], ray_o[1], ray_o[2]}, d[3] = {ray_d[0], ray_d[1], ray_d[2]};
+  double T = 1.0, C[3] = {0, 0, 0}, D = 0.0;
+  for (int64_t h = 0; h < len; ++h) {
+    int64_t i = list[h];
+    if (i < 0 || i >= n) return OR_ERR_ARG;
+    og_t g;
+    prepare_one(&s, i, alpha_min, 0, &g);
+    double a, ta, c[3];
+    max_response(&g, o, d, &a, &ta);
+    sh_colour(&s, i, d, c);
+    double w = T * a;
+    for (int ch = 0; ch < 3; ++ch) C[ch] += w * c[ch];
+    D += w * ta;
+    T *= (1.0 - a);
+  }
+  for (int ch = 0; ch < 3; ++ch) rgb[ch] = C[ch] + T * (bg ? bg[ch] : 0.0);
+  *depth = D;
+  *opacity = 1.0 - T;
+  return OR_OK;
+}
+
+/* Axis-aligned bounds of each Gaussian's bounding ellipsoid:
+ * half-extent along axis j = sqrt(e_j^T Sigma e_j) * rho. Inactive Gaussians get
+ * lo = hi = mu and active = 0. */
+int oracle_gaussian_aabb(const float *means, const float *scales, const float *quats, const float *opac,
+                         int64_t n, double alpha_min, double *lo, double *hi, int32_t *active) {
+  for (int64_t i = 0; i < n; ++i) {
+    double R[3][3];
+    quat_to_rot(quats + 4 * i, R);
+    double o = opac[i];
+    int act = o > alpha_min;
+    double rho = act ? sqrt(2.0 * log(o / alpha_min)) : 0.0;
+    for (int j = 0; j < 3; ++j) {
+      double var = 0.0; /* Sigma_jj */
+      for (int k = 0; k < 3; ++k) var += R[j][k] * R[j][k] * (double)scales[3 * i + k] * (double)scales[3 * i + k];
+      double h = act ? rho * sqrt(var) : 0.0;
+      lo[3 * i + j] = (double)means[3 * i + j] - h;
+      hi[3 * i + j] = (double)means[3 * i + j] + h;
+    }
+    active[i] = act;
+  }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Pinhole camera                                                                         */
+/* ------------------------------------------------------------------------------------ */
+
+/* Forward f = normalise(target - eye), right = normalise(f x up), true up = right x f.
+ * Pixel (x, y), row 0 at the top, is sampled at its centre (x + 1/2, y + 1/2):
+ * direction = normalise(f + sx * tan(fov/2) * aspect * right + sy * tan(fov/2) * up) with
+ * sx = 2(x + 1/2)/W - 1, sy = 1 - 2(y + 1/2)/H, aspect = W/H, fov vertical. */
+int oracle_pinhole_rays(const double *eye, const double *target, const double *up, double fov_y_deg,
+                        int width, int height, double *origins, double *dirs) {
+  if (width <= 0 || height <= 0) return OR_ERR_ARG;
+  double f[3] = {target[0] - eye[0], target[1] - eye[1], target[2] - eye[2]};
+  double fl = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  for (int a = 0; a < 3; ++a) f[a] /= fl;
+  double r[3] = {f[1] * up[2] - f[2] * up[1], f[2] * up[0] - f[0] * up[2], f[0] * up[1] - f[1] * up[0]};
+  double rl = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  for (int a = 0; a < 3; ++a) r[a] /= rl;
+  double u[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0]};
+  double th = tan(0.5 * fov_y_deg * M_PI / 180.0);
+  double aspect = (double)width / (double)height;
+  for (int y = 0; y < height; ++y)
+    for (int x = 0; x < width; ++x) {
+      int64_t i = (int64_t)y * width + x;
+      double sx = (2.0 * (x + 0.5) / width - 1.0) * th * aspect;
+      double sy = (1.0 - 2.0 * (y + 0.5) / height) * th;
+      double d[3] = {f[0] + sx * r[0] + sy * u[0], f[1] + sx * r[1] + sy * u[1], f[2] + sx * r[2] + sy * u[2]};
+      double dl = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      for (int a = 0; a < 3; ++a) {
+        origins[3 * i + a] = eye[a];
+        dirs[3 * i + a] = d[a] / dl;
+      }
+    }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* LBVH reference: Morton codes, stable sort, radix tree                                 */
+/* ------------------------------------------------------------------------------------ */
+
+/* 63-bit Morton code of each mean. The quantisation is defined in binary32 arithmetic
+ * (each operation rounded to nearest float), so that it is an exact integer function of
+ * the float inputs:
+ *   lo_j = min_i mu_ij, hi_j = max_i mu_ij, ext_j = hi_j - lo_j,
+ *   scale_j = 2^21 / ext_j (0 if ext_j == 0),
+ *   q_j = clamp(floor((mu_j - lo_j) * scale_j), 0, 2^21 - 1),
+ * and bit 3b+2 / 3b+1 / 3b of the code is bit b of q_x / q_y / q_z. */
+int oracle_morton(int64_t n, const float *means, uint64_t *codes) {
+  if (n <= 0) return OR_OK;
+  volatile float lo[3], hi[3];
+  for (int j = 0; j < 3; ++j) { lo[j] = means[j]; hi[j] = means[j]; }
+  for (int64_t i = 1; i < n; ++i)
+    for (int j = 0; j < 3; ++j) {
+      float v = means[3 * i + j];
+      if (v < lo[j]) lo[j] = v;
+      if (v > hi[j]) hi[j] = v;
+    }
+  volatile float scale[3];
+  for (int j = 0; j < 3; ++j) {
+    volatile float ext = hi[j] - lo[j];
+    scale[j] = ext > 0.0f ? 2097152.0f / ext : 0.0f;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    uint32_t q[3];
+    for (int j = 0; j < 3; ++j) {
+      volatile float rel = means[3 * i + j] - lo[j];
+      volatile float pos = rel * scale[j];
+      float fl = floorf(pos);
+      uint32_t v = fl <= 0.0f ? 0u : (fl >= 2097151.0f ? 2097151u : (uint32_t)fl);
+      q[j] = v;
+    }
+    uint64_t c = 0;
+    for (int b = 0; b < 21; ++b) {
+      c |= (uint64_t)((q[0] >> b) & 1u) << (3 * b + 2);
+      c |= (uint64_t)((q[1] >> b) & 1u) << (3 * b + 1);
+      c |= (uint64_t)((q[2] >> b) & 1u) << (3 * b);
+    }
+    codes[i] = c;
+  }
+  return OR_OK;
+}
+
+static __thread const uint64_t *g_sort_codes;
+static int idx_cmp(const void *a, const void *b) {
+  uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+  uint64_t cx = g_sort_codes[x], cy = g_sort_codes[y];
+  if (cx != cy) return cx < cy ? -1 : 1;
+  return (x > y) - (x < y);
+}
+
+typedef struct {
+  const uint64_t *code; /* sorted */
+  uint32_t *child;      /* [(n-1)*2] */
+  uint32_t *parent;     /* [2n-1]: internal nodes first, then leaves */
+  int64_t n;
+} tree_t;
+
+#define LEAF_FLAG 0x80000000u
+
+/* Key of sorted position i: (code_i, i) as one 95-bit number. Index of the highest
+ * bit in which the keys of positions a and b differ, counted from the top (0 = the
+ * code's bit 62); a larger value means a longer common prefix. */
+static int common_prefix(const tree_t *T, int64_t a, int64_t b) {
+  uint64_t x = T->code[a] ^ T->code[b];
+  if (x) {
+    int p = 0;
+    for (int bit = 62; bit >= 0; --bit, ++p)
+      if ((x >> bit) & 1u) return p;
+  }
+  uint32_t y = (uint32_t)a ^ (uint32_t)b;
+  int p = 63;
+  for (int bit = 31; bit >= 0; --bit, ++p)
+    if ((y >> bit) & 1u) return p;
+  return 95;
+}
+
+/* Node covering sorted positions [first, last] (first < last) has index `self`. Its
+ * split is the last position that shares more than the range's common prefix with
+ * `first`; the left child covers [first, split], the right [split+1, last]. A child
+ * covering a single position is a leaf; otherwise the left child is internal node
+ * `split` and the right child is internal node `split+1`. */
+static void build_range(tree_t *T, int64_t first, int64_t last, uint32_t self) {
+  int range_prefix = common_prefix(T, first, last);
+  int64_t split = first;
+  for (int64_t i = first; i < last; ++i)
+    if (common_prefix(T, first, i) > range_prefix) split = i;
+  uint32_t left, right;
+  if (split == first) {
+    left = LEAF_FLAG | (uint32_t)split;
+    T->parent[(T->n - 1) + split] = self;
+  } else {
+    left = (uint32_t)split;
+    T->parent[split] = self;
+  }
+  if (split + 1 == last) {
+    right = LEAF_FLAG | (uint32_t)(split + 1);
+    T->parent[(T->n - 1) + split + 1] = self;
+  } else {
+    right = (uint32_t)(split + 1);
+    T->parent[split + 1] = self;
+  }
+  T->child[2 * self] = left;
+  T->child[2 * self + 1] = right;
+  if (split != first) build_range(T, first, split, (uint32_t)split);
+  if (split + 1 != last) build_range(T, split + 1, last, (uint32_t)(split + 1));
+}
+
+/* Sort positions by (code, original index) and build the radix tree over them.
+ * Outputs: sorted codes [n], perm [n] (sorted position -> original index), child
+ * [(n-1)*2] (leaf children carry bit 31 and the sorted position), parent [2n-1]
+ * (entries 0..n-2 for internal nodes, n-1+p for leaf p; the root's parent is
+ * 0xFFFFFFFF). Quadratic in the worst case; meant for test sizes. */
+int oracle_lbvh_topology(int64_t n, const float *means, uint64_t *sorted_codes, uint32_t *perm,
+                         uint32_t *child, uint32_t *parent) {
+  if (n <= 0) return OR_OK;
+  uint64_t *codes = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+  if (!codes) return OR_ERR_MEM;
+  oracle_morton(n, means, codes);
+  for (int64_t i = 0; i < n; ++i) perm[i] = (uint32_t)i;
+  g_sort_codes = codes;
+  qsort(perm, (size_t)n, sizeof(uint32_t), idx_cmp);
+  for (int64_t i = 0; i < n; ++i) sorted_codes[i] = codes[perm[i]];
+  free(codes);
+  for (int64_t i = 0; i < 2 * n - 1; ++i) parent[i] = 0xFFFFFFFFu;
+  if (n == 1) return OR_OK;
+  tree_t T = {sorted_codes, child, parent, n};
+  build_range(&T, 0, n - 1, 0);
+  return OR_OK;
+}
