@@ -1,0 +1,177 @@
+"""Benchmark: Gaussian ray tracing of a 100k-Gaussian scene at 800x800, k = 16, on one GPU.
+
+One step is the whole hot path over one frame: pinhole ray generation, the LBVH build
+over the Gaussians (setup, Morton codes, radix sort, radix tree, refit) and the
+multi-round checkpointed trace with blending. Inputs (scene parameters) are resident on
+the GPU before timing starts. Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# algorithmic bytes per unit of work ("Roofline")
+B_NODE = 64          # internal node record: two child boxes + two child references
+B_LEAF = 48          # unit-sphere transform of a leaf (3 x float4)
+B_BLEND_INST = 64    # full instance record re-read for blending
+B_LIST = 16          # one checkpoint / eviction entry written and read back (8 B each way)
+B_RAY = 24 + 20      # ray in (origin, direction); rgb, depth, opacity out
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--k", type=int, default=16)
+    ap.add_argument("--mode", choices=["checkpoint", "restart"], default="checkpoint")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the restart-mode comparison run")
+    ap.add_argument("--cpu-rays", type=int, default=16384)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the ray-sharded multi-GPU "
+              "layout is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2601_20429_amd import grtx, inputs
+
+    cfg = inputs.SCENE100K
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    amin = float(np.float32(cfg["alpha_min"]))
+    scene = inputs.cluster_scene(cfg["seed"], cfg["n"], 3)
+    st = grtx.SceneTensors.from_scene(scene, dev)
+    cam = inputs.orbit_camera(cfg["width"], cfg["height"])
+    R = cam.n_rays
+    mode = grtx.CHECKPOINT if args.mode == "checkpoint" else grtx.RESTART
+    stream = torch.cuda.current_stream()
+    o = torch.empty((R, 3), dtype=torch.float32, device=dev)
+    d = torch.empty((R, 3), dtype=torch.float32, device=dev)
+    out = dict(rgb=torch.empty((R, 3), dtype=torch.float32, device=dev),
+               depth=torch.empty(R, dtype=torch.float32, device=dev),
+               opacity=torch.empty(R, dtype=torch.float32, device=dev))
+    trace_ev = []
+
+    def step(m, record=False):
+        oo, dd = grtx.pinhole_rays(cam, device=dev)
+        bvh = grtx.build(st, alpha_min=amin)
+        if record:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        grtx.trace(bvh, oo, dd, k=args.k, T_min=cfg["T_min"], mode=m, image_width=cam.width, out=out)
+        if record:
+            e1.record(stream)
+            trace_ev.append((e0, e1))
+        return bvh
+
+    def timed(m, steps, warmup):
+        keep = []
+        for _ in range(warmup):
+            keep.append(step(m))
+        torch.cuda.synchronize()
+        keep.clear()
+        trace_ev.clear()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            keep.append(step(m, record=True))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ktimes = [a.elapsed_time(b) for a, b in trace_ev]
+        keep.clear()
+        return (t1 - t0) * 1e3 / steps, float(np.mean(ktimes)), float(np.median(ktimes))
+
+    log(f"scene {cfg['n']} Gaussians, {cam.width}x{cam.height} rays, k={args.k}, mode={args.mode}")
+    ms, k_mean, k_med = timed(mode, args.steps, args.warmup)
+    mrays = R / (ms * 1e-3) / 1e6
+    log(f"step {ms:.3f} ms ({mrays:.1f} Mrays/s); trace kernel mean {k_mean:.3f} ms median {k_med:.3f} ms")
+
+    # counters of the same launch configuration (deterministic, so an untimed run with the
+    # per-ray counters enabled sees exactly the timed work)
+    bvh = grtx.build(st, alpha_min=amin)
+    oo, dd = grtx.pinhole_rays(cam, device=dev)
+    sout = grtx.trace(bvh, oo, dd, k=args.k, T_min=cfg["T_min"], mode=mode, image_width=cam.width, stats=True)
+    torch.cuda.synchronize()
+    stt = sout["stats"].to(torch.int64).sum(0).cpu().numpy()
+    nodes, leaves, rounds, blended, deferred, free, evicted, fallbacks = [int(x) for x in stt]
+    alg_bytes = (B_NODE * nodes + B_LEAF * leaves + (B_BLEND_INST + 4 * 3 * (scene.sh_degree + 1) ** 2) * blended
+                 + B_LIST * (deferred + evicted) + B_RAY * R)
+    achieved = alg_bytes / (k_mean * 1e-3) / 1e9
+    extra = dict(nodes_per_ray=(nodes + leaves) / R, internal_nodes_per_ray=nodes / R, leaf_tests_per_ray=leaves / R,
+                 rounds_per_ray=rounds / R, blended_per_ray=blended / R, deferred_per_ray=deferred / R,
+                 fetch_free_per_ray=free / R, evicted_per_ray=evicted / R, fallbacks=fallbacks,
+                 trace_kernel_ms=k_mean, trace_kernel_ms_median=k_med,
+                 trace_only_mrays_s=R / (k_mean * 1e-3) / 1e6, algorithmic_bytes_per_ray=alg_bytes / R)
+    log("counters", json.dumps(extra))
+
+    if not args.no_compare:
+        other = grtx.RESTART if mode == grtx.CHECKPOINT else grtx.CHECKPOINT
+        ms2, k2, _ = timed(other, max(3, args.steps // 2), 1)
+        sout2 = grtx.trace(bvh, oo, dd, k=args.k, T_min=cfg["T_min"], mode=other, image_width=cam.width,
+                           stats=True)
+        torch.cuda.synchronize()
+        s2 = sout2["stats"].to(torch.int64).sum(0).cpu().numpy()
+        name = "restart" if other == grtx.RESTART else "checkpoint"
+        extra[f"{name}_step_ms"] = ms2
+        extra[f"{name}_mrays_s"] = R / (ms2 * 1e-3) / 1e6
+        extra[f"{name}_trace_kernel_ms"] = k2
+        extra[f"{name}_nodes_per_ray"] = float(s2[0] + s2[1]) / R
+        log(f"{name}: step {ms2:.3f} ms, trace {k2:.3f} ms, nodes/ray {extra[f'{name}_nodes_per_ray']:.1f}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        cores = min(16, os.cpu_count() or 1)
+        ro, rd = oracle.pinhole_rays(cam)
+        idx = inputs.ray_subsample(99, R, args.cpu_rays)
+        ro, rd = ro[idx].astype(np.float32), rd[idx].astype(np.float32)
+        t0 = time.perf_counter()
+        oracle.render(scene, ro, rd, amin, cfg["T_min"], nthreads=cores)
+        dt = time.perf_counter() - t0
+        cpu = dict(value=len(idx) / dt / 1e6, unit="Mrays/s", cores=cores, kind="oracle",
+                   sample=f"{len(idx)} of the {R} primary rays (seeded subsample) against all {cfg['n']} "
+                          f"Gaussians, FP64 brute force, {dt:.1f} s")
+        log("cpu baseline", json.dumps(cpu))
+
+    rec = {
+        "metric": "Mrays/s and nodes visited/ray at k=16; p50/p99 frame latency (serving)",
+        "value": mrays,
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "gaussians": cfg["n"], "width": cam.width, "height": cam.height,
+                   "rays": R, "k": args.k, "mode": args.mode, "sh_degree": 3, "bvh": "sphere-instance LBVH",
+                   "step": "raygen + LBVH build + trace"},
+        "nodes_per_ray": extra["nodes_per_ray"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"k_trace<{16 if args.k > 8 else args.k}>"},
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,220 @@
+/*
+ * grtx.h -- C ABI of the MI355X (gfx950) Gaussian ray tracer.
+ *
+ * The library renders 3D Gaussian scenes by ray tracing (3DGRT pipeline, Sec. III-A:
+ * build an acceleration structure over the Gaussians, generate rays, traverse, sort
+ * hits by distance, alpha-blend). Each Gaussian is a unit sphere after its own affine
+ * ray transform (GRTX-SW, Sec. IV-A); hits are gathered k at a time into a k-buffer
+ * (Sec. III-A, Listing 1) and each round resumes from a per-ray traversal checkpoint
+ * (deferred nodes and evicted hits, GRTX-HW, Sec. IV-B) instead of the root.
+ *
+ * Conventions for every entry point:
+ *   - All functions return grtx_status. On any status other than GRTX_OK the
+ *     out-parameters are left untouched and grtx_last_error() returns a message
+ *     (thread-local; valid until the next call on the same thread).
+ *   - Arguments are validated on the host before any launch.
+ *   - Pointers named "device" must point to device memory of the current HIP device
+ *     (hipMalloc or an equivalent allocator such as PyTorch's). Host pointers are
+ *     named "host".
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). Work is
+ *     enqueued asynchronously on it; the caller synchronises.
+ *   - No exception crosses the ABI.
+ */
+#ifndef GRTX_H
+#define GRTX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GRTX_VERSION 1
+
+typedef enum grtx_status {
+  GRTX_OK = 0,
+  GRTX_ERR_INVALID_ARG = 1,   /* bad argument; nothing was enqueued */
+  GRTX_ERR_OUT_OF_MEMORY = 2, /* a device allocation failed */
+  GRTX_ERR_DEVICE = 3,        /* a HIP call failed; the HIP message is in grtx_last_error() */
+  GRTX_ERR_CAPACITY = 4,      /* a request can never fit the configured budget */
+  GRTX_ERR_NOT_READY = 5,     /* asynchronous result not available yet */
+  GRTX_ERR_INTERNAL = 6
+} grtx_status;
+
+/* Kind of acceleration structure.
+ * SPHERE_INSTANCE: one leaf per Gaussian holding its world->unit-sphere transform; the
+ *   leaf test is "transform the ray, intersect the unit sphere" (Sec. IV-A, bounding
+ *   primitive 1). This is the method's structure.
+ * PROXY20: one leaf per triangle of a bounding icosahedron per Gaussian (20N leaves),
+ *   the monolithic triangle-mesh BVH of the baseline (Sec. III-C, Observation I;
+ *   Sec. IV-A). Hits are ordered by the entry distance through the icosahedron. */
+typedef enum grtx_bvh_kind { GRTX_BVH_SPHERE_INSTANCE = 0, GRTX_BVH_PROXY20 = 1 } grtx_bvh_kind;
+
+/* Tracing mode.
+ * CHECKPOINT: multi-round k-buffer tracing where each round resumes from the previous
+ *   round's deferred nodes and evicted hits (Sec. IV-B, traversal checkpointing and
+ *   replay; Listing 1).
+ * RESTART: each round restarts from the root with t_min = the last blended hit
+ *   (Sec. III-A; the multi-round baseline). Both modes give identical outputs. */
+typedef enum grtx_mode { GRTX_MODE_CHECKPOINT = 0, GRTX_MODE_RESTART = 1 } grtx_mode;
+
+/* Scene parameters (Sec. II-B). All device pointers, float32, C-contiguous:
+ *   means [count,3]; scales [count,3] linear standard deviation per axis;
+ *   quats [count,4] (w,x,y,z), normalised inside; opacities [count];
+ *   sh [count,(sh_degree+1)^2,3] real SH coefficients, band-major, m=-l..l, RGB last.
+ * The library copies what it derives (transforms, boxes, nodes) and BORROWS opacities
+ * and sh: they must stay alive and unchanged until grtx_bvh_destroy. */
+typedef struct grtx_gaussians {
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opacities;
+  const float* sh;
+  int64_t count;     /* >= 0; 0 gives an empty scene */
+  int32_t sh_degree; /* 0..3 */
+  int32_t reserved;
+} grtx_gaussians;
+
+/* alpha_min: each Gaussian is bounded by the ellipsoid on which o*G = alpha_min, i.e.
+ * Mahalanobis radius rho = sqrt(2 ln(o/alpha_min)); Gaussians with o <= alpha_min are
+ * never hit. Must be in (0, 1). */
+typedef struct grtx_build_params {
+  float alpha_min;
+  int32_t reserved[3];
+} grtx_build_params;
+
+typedef struct grtx_bvh grtx_bvh;
+
+typedef struct grtx_bvh_info {
+  int64_t gaussians;
+  int64_t leaves;         /* gaussians (SPHERE_INSTANCE) or 20*gaussians (PROXY20) */
+  int64_t internal_nodes; /* leaves - 1 (0 for fewer than two leaves) */
+  int64_t device_bytes;   /* bytes the handle owns on the device */
+  int32_t kind;
+  int32_t sh_degree;
+  float alpha_min;
+  float root_lo[3];       /* filled only after the build has completed on its stream */
+  float root_hi[3];
+} grtx_bvh_info;
+
+/* Rays: device origins [count,3] and unit-length directions [count,3], float32.
+ * t_near >= 0: hits need an entry distance > t_near. image_width > 0 declares the rays
+ * to be a row-major image of that width; the kernel then schedules them in 8x8 pixel
+ * tiles (results are unaffected). */
+typedef struct grtx_rays {
+  const float* origins;
+  const float* dirs;
+  int64_t count;
+  float t_near;
+  int32_t image_width;
+} grtx_rays;
+
+/* k: k-buffer size, 1..64 (Sec. III-A). T_min: a ray stops after the hit that brings
+ * its transmittance below T_min (early ray termination, Sec. III-A), in [0, 1).
+ * mode: grtx_mode. bg: background colour added with the remaining transmittance.
+ * defer_capacity / evict_capacity: per-ray entries of the checkpoint lists (0 = the
+ * default, 128 each). A ray whose lists overflow falls back to a restart-from-root
+ * round; results are unchanged. */
+typedef struct grtx_trace_params {
+  int32_t k;
+  float T_min;
+  int32_t mode;
+  float bg[3];
+  int32_t defer_capacity;
+  int32_t evict_capacity;
+} grtx_trace_params;
+
+/* Per-ray counters written to grtx_trace_outputs.stats. */
+enum {
+  GRTX_STAT_NODES = 0,      /* internal nodes fetched and tested */
+  GRTX_STAT_LEAVES = 1,     /* leaf primitives fetched and tested */
+  GRTX_STAT_ROUNDS = 2,     /* tracing rounds */
+  GRTX_STAT_BLENDED = 3,    /* hits blended */
+  GRTX_STAT_DEFERRED = 4,   /* checkpoint entries written (node deferrals and copies) */
+  GRTX_STAT_FETCH_FREE = 5, /* checkpoint entries carried forward without a fetch */
+  GRTX_STAT_EVICTED = 6,    /* hits written to the eviction list */
+  GRTX_STAT_FALLBACKS = 7,  /* rounds restarted from the root after a list overflow */
+  GRTX_STATS_FIELDS = 8
+};
+
+/* Outputs, all caller-owned device memory:
+ *   rgb [count,3], depth [count] (sum of w_i t_alpha_i), opacity [count] (1 - T).
+ *   stats: optional [count, GRTX_STATS_FIELDS] uint32.
+ *   hit_ids: optional [count, hit_capacity] int32: ids of the blended Gaussians in blend
+ *     order (the first hit_capacity of them); hit_counts: optional [count] int32, the
+ *     number of blended hits (may exceed hit_capacity). */
+typedef struct grtx_trace_outputs {
+  float* rgb;
+  float* depth;
+  float* opacity;
+  uint32_t* stats;
+  int32_t* hit_ids;
+  int32_t* hit_counts;
+  int32_t hit_capacity;
+  int32_t reserved;
+} grtx_trace_outputs;
+
+/* Pinhole camera (ray generation, Sec. III-A): forward = normalise(target - eye),
+ * right = normalise(forward x up), true up = right x forward; pixel (x, y), row 0 at
+ * the top, sampled at its centre; vertical field of view in degrees. */
+typedef struct grtx_camera {
+  float eye[3];
+  float target[3];
+  float up[3];
+  float fov_y_deg;
+  int32_t width;
+  int32_t height;
+} grtx_camera;
+
+/* Build the acceleration structure (LBVH: Morton codes of the means, stable radix
+ * sort, radix tree, bottom-up refit) over `g`. Enqueued on `stream`; the handle may be
+ * used for grtx_trace on the same stream right away. On success *out receives a new
+ * handle (free it with grtx_bvh_destroy). */
+grtx_status grtx_build(const grtx_gaussians* g, grtx_bvh_kind kind, const grtx_build_params* p,
+                       void* stream, grtx_bvh** out);
+
+/* Sizes and bounds of a built structure (host out-param). Synchronises `bvh`'s build
+ * stream to read the root bounds. */
+grtx_status grtx_bvh_get_info(const grtx_bvh* bvh, grtx_bvh_info* out);
+
+/* Copy the topology into caller-owned DEVICE buffers (each may be NULL to skip):
+ *   child  [internal_nodes,2] uint32: bit 31 set = leaf, low bits = sorted leaf position;
+ *          otherwise an internal node index (0 = root);
+ *   parent [internal_nodes + leaves] uint32: internal nodes first, then leaves in sorted
+ *          order; the root's parent is 0xFFFFFFFF;
+ *   morton [leaves] uint64: sorted Morton codes;
+ *   perm   [leaves] uint32: sorted position -> primitive index (Gaussian index, or
+ *          20*gaussian + face for PROXY20);
+ *   boxes  [internal_nodes + leaves, 6] float32: (lo xyz, hi xyz) of every node, same
+ *          order as parent.
+ * Enqueued on `stream`. */
+grtx_status grtx_bvh_export_topology(const grtx_bvh* bvh, uint32_t* child, uint32_t* parent, uint64_t* morton,
+                                     uint32_t* perm, float* boxes, void* stream);
+
+/* Release a handle and its device memory. NULL is accepted. The caller must make sure
+ * that no enqueued work still uses it. */
+grtx_status grtx_bvh_destroy(grtx_bvh* bvh);
+
+/* Generate width*height pinhole rays into caller-owned device buffers origins/dirs
+ * [width*height,3] float32, row-major from the top row. */
+grtx_status grtx_pinhole_rays(const grtx_camera* cam, float* origins, float* dirs, void* stream);
+
+/* Render `rays` against `bvh` (Sec. III-A pipeline with Sec. IV-B checkpointing).
+ * Deterministic: the same inputs give bit-identical outputs, in either mode and for
+ * any k. The library keeps a per-(device, stream) pool of per-ray checkpoint storage and
+ * grows it on demand (GRTX_ERR_OUT_OF_MEMORY if it cannot). Calls on one stream are
+ * ordered; calls on different streams use different pools. */
+grtx_status grtx_trace(const grtx_bvh* bvh, const grtx_rays* rays, const grtx_trace_params* p,
+                       const grtx_trace_outputs* out, void* stream);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* grtx_last_error(void);
+
+/* GRTX_VERSION of the loaded library. */
+int32_t grtx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRTX_H */

@@ -86,13 +86,15 @@ def _scene_args(scene):
 
 
 def render(scene, origins, dirs, alpha_min=1.0 / 255.0, T_min=1e-3, t_near=0.0, bg=(0.0, 0.0, 0.0),
-           key_mode=0, cap=0, nthreads=0):
+           key_mode=0, cap=0, nthreads=None):
     """Brute-force render of the given float32 rays (Eq. 1, Eq. 2, Sec. III-A).
 
     key_mode 0 orders hits by ellipsoid entry distance, 1 by bounding-icosahedron entry
     distance. With cap > 0 also returns, per ray, the first `cap` blended ids, the
     transmittance after each and each hit's key distance."""
     L = lib()
+    if nthreads is None:
+        nthreads = min(16, os.cpu_count() or 1)
     o = _f32(origins).reshape(-1, 3)
     d = _f32(dirs).reshape(-1, 3)
     R = o.shape[0]

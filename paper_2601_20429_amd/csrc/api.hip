@@ -1,0 +1,148 @@
+// C ABI entry points: argument validation, handle lifetimes, error reporting.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <new>
+
+#include "grtx_internal.h"
+
+namespace grtx {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+}
+
+void clear_error() { g_err[0] = '\0'; }
+
+}  // namespace grtx
+
+using grtx::set_error;
+
+#define CHECK_ARG(cond, ...)        \
+  do {                              \
+    if (!(cond)) {                  \
+      set_error(__VA_ARGS__);       \
+      return GRTX_ERR_INVALID_ARG;  \
+    }                               \
+  } while (0)
+
+extern "C" {
+
+const char* grtx_last_error(void) { return grtx::g_err; }
+
+int32_t grtx_version(void) { return GRTX_VERSION; }
+
+grtx_status grtx_build(const grtx_gaussians* g, grtx_bvh_kind kind, const grtx_build_params* p, void* stream,
+                       grtx_bvh** out) {
+  grtx::clear_error();
+  CHECK_ARG(g && p && out, "grtx_build: null argument");
+  CHECK_ARG(g->count >= 0, "grtx_build: negative Gaussian count");
+  CHECK_ARG(g->count < (int64_t)0x7FFFFFFF / 20, "grtx_build: too many Gaussians (%lld)", (long long)g->count);
+  CHECK_ARG(g->sh_degree >= 0 && g->sh_degree <= 3, "grtx_build: sh_degree must be 0..3, got %d", g->sh_degree);
+  CHECK_ARG(kind == GRTX_BVH_SPHERE_INSTANCE || kind == GRTX_BVH_PROXY20, "grtx_build: unknown kind %d", (int)kind);
+  CHECK_ARG(p->alpha_min > 0.f && p->alpha_min < 1.f, "grtx_build: alpha_min must be in (0,1)");
+  if (g->count > 0)
+    CHECK_ARG(g->means && g->scales && g->quats && g->opacities && g->sh, "grtx_build: null Gaussian array");
+  grtx_bvh* h = new (std::nothrow) grtx_bvh();
+  if (!h) {
+    set_error("grtx_build: host allocation failed");
+    return GRTX_ERR_OUT_OF_MEMORY;
+  }
+  grtx_status st = grtx::build_bvh(g, kind, p->alpha_min, static_cast<hipStream_t>(stream), &h->impl);
+  if (st != GRTX_OK) {
+    char msg[1024];
+    std::strncpy(msg, grtx::g_err, sizeof msg - 1);
+    msg[sizeof msg - 1] = 0;
+    for (void* q : h->impl.allocations) (void)hipFree(q);
+    delete h;
+    set_error("%s", msg);
+    return st;
+  }
+  *out = h;
+  return GRTX_OK;
+}
+
+grtx_status grtx_bvh_get_info(const grtx_bvh* bvh, grtx_bvh_info* out) {
+  grtx::clear_error();
+  CHECK_ARG(bvh && out, "grtx_bvh_get_info: null argument");
+  const grtx::Bvh& b = bvh->impl;
+  grtx_bvh_info info{};
+  info.gaussians = b.n_gauss;
+  info.leaves = b.n_leaves;
+  info.internal_nodes = b.n_leaves > 1 ? b.n_leaves - 1 : 0;
+  info.device_bytes = (int64_t)b.bytes;
+  info.kind = b.kind;
+  info.sh_degree = b.sh_degree;
+  info.alpha_min = b.alpha_min;
+  if (b.n_leaves > 0) {
+    float box[6];
+    GRTX_HIP(hipStreamSynchronize(b.build_stream));
+    GRTX_HIP(hipMemcpy(box, b.root_box, sizeof box, hipMemcpyDeviceToHost));
+    for (int a = 0; a < 3; ++a) {
+      info.root_lo[a] = box[a];
+      info.root_hi[a] = box[3 + a];
+    }
+  }
+  *out = info;
+  return GRTX_OK;
+}
+
+grtx_status grtx_bvh_export_topology(const grtx_bvh* bvh, uint32_t* child, uint32_t* parent, uint64_t* morton,
+                                     uint32_t* perm, float* boxes, void* stream) {
+  grtx::clear_error();
+  CHECK_ARG(bvh, "grtx_bvh_export_topology: null handle");
+  return grtx::export_topology(&bvh->impl, child, parent, morton, perm, boxes, static_cast<hipStream_t>(stream));
+}
+
+grtx_status grtx_bvh_destroy(grtx_bvh* bvh) {
+  grtx::clear_error();
+  if (!bvh) return GRTX_OK;
+  grtx_status st = GRTX_OK;
+  for (void* q : bvh->impl.allocations) {
+    hipError_t e = hipFree(q);
+    if (e != hipSuccess && st == GRTX_OK) {
+      set_error("grtx_bvh_destroy: hipFree failed: %s", hipGetErrorString(e));
+      st = GRTX_ERR_DEVICE;
+    }
+  }
+  delete bvh;
+  return st;
+}
+
+grtx_status grtx_pinhole_rays(const grtx_camera* cam, float* origins, float* dirs, void* stream) {
+  grtx::clear_error();
+  CHECK_ARG(cam && origins && dirs, "grtx_pinhole_rays: null argument");
+  CHECK_ARG(cam->width > 0 && cam->height > 0, "grtx_pinhole_rays: image size must be positive");
+  CHECK_ARG(cam->fov_y_deg > 0.f && cam->fov_y_deg < 180.f, "grtx_pinhole_rays: fov must be in (0,180)");
+  return grtx::pinhole_rays(cam, origins, dirs, static_cast<hipStream_t>(stream));
+}
+
+grtx_status grtx_trace(const grtx_bvh* bvh, const grtx_rays* rays, const grtx_trace_params* p,
+                       const grtx_trace_outputs* out, void* stream) {
+  grtx::clear_error();
+  CHECK_ARG(bvh && rays && p && out, "grtx_trace: null argument");
+  CHECK_ARG(rays->count >= 0 && rays->count < ((int64_t)1 << 40), "grtx_trace: bad ray count");
+  CHECK_ARG(p->k >= 1 && p->k <= 64, "grtx_trace: k must be 1..64, got %d", p->k);
+  CHECK_ARG(p->T_min >= 0.f && p->T_min < 1.f, "grtx_trace: T_min must be in [0,1)");
+  CHECK_ARG(p->mode == GRTX_MODE_CHECKPOINT || p->mode == GRTX_MODE_RESTART, "grtx_trace: unknown mode %d", p->mode);
+  CHECK_ARG(p->defer_capacity >= 0 && p->evict_capacity >= 0 && p->defer_capacity <= (1 << 20) &&
+                p->evict_capacity <= (1 << 20),
+            "grtx_trace: list capacities must be 0..2^20");
+  CHECK_ARG(rays->t_near >= 0.f && std::isfinite(rays->t_near), "grtx_trace: t_near must be finite and >= 0");
+  CHECK_ARG(rays->image_width >= 0, "grtx_trace: negative image width");
+  if (rays->count > 0) {
+    CHECK_ARG(rays->origins && rays->dirs, "grtx_trace: null ray arrays");
+    CHECK_ARG(out->rgb && out->depth && out->opacity, "grtx_trace: null output arrays");
+    CHECK_ARG(!out->hit_ids || out->hit_capacity > 0, "grtx_trace: hit_ids given with hit_capacity <= 0");
+  }
+  return grtx::trace(&bvh->impl, rays, p, out, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,627 @@
+// LBVH construction over Gaussians on gfx950 (Sec. IV-A: one leaf per Gaussian holding
+// its world->unit-sphere transform; the baseline's 20-triangle proxy mesh per Gaussian).
+//
+// Pipeline, all on one stream, no host synchronisation:
+//   bounds of the centroids (two-stage min/max, exact)
+//   63-bit Morton codes (binary32 quantisation with fp contraction off, so the codes are
+//     an exact integer function of the inputs)
+//   stable LSD radix sort of (code, index), 8 passes of 8 bits
+//   radix tree over the sorted (code, position) keys (Karras 2012, one thread per node)
+//   leaf records and leaf boxes in sorted order
+//   bottom-up refit with per-node arrival counters (exact min/max)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "grtx_internal.h"
+
+namespace grtx {
+namespace {
+
+constexpr int kBlock = 256;
+
+// ------------------------------------------------------------------ centroid bounds
+
+__global__ void __launch_bounds__(kBlock) k_bounds_partial(const float* __restrict__ pts, int64_t n,
+                                                           float* __restrict__ partial) {
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    for (int a = 0; a < 3; ++a) {
+      float v = pts[3 * i + a];
+      lo[a] = fminf(lo[a], v);
+      hi[a] = fmaxf(hi[a], v);
+    }
+  }
+  __shared__ float s[6][kBlock];
+  for (int a = 0; a < 3; ++a) {
+    s[a][threadIdx.x] = lo[a];
+    s[3 + a][threadIdx.x] = hi[a];
+  }
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int a = 0; a < 3; ++a) {
+        s[a][threadIdx.x] = fminf(s[a][threadIdx.x], s[a][threadIdx.x + w]);
+        s[3 + a][threadIdx.x] = fmaxf(s[3 + a][threadIdx.x], s[3 + a][threadIdx.x + w]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) partial[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(kBlock) k_bounds_final(const float* __restrict__ partial, int nparts,
+                                                         float* __restrict__ out) {
+  __shared__ float s[6][kBlock];
+  float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (int i = threadIdx.x; i < nparts; i += kBlock)
+    for (int a = 0; a < 3; ++a) {
+      v[a] = fminf(v[a], partial[i * 6 + a]);
+      v[3 + a] = fmaxf(v[3 + a], partial[i * 6 + 3 + a]);
+    }
+  for (int a = 0; a < 6; ++a) s[a][threadIdx.x] = v[a];
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int a = 0; a < 3; ++a) {
+        s[a][threadIdx.x] = fminf(s[a][threadIdx.x], s[a][threadIdx.x + w]);
+        s[3 + a][threadIdx.x] = fmaxf(s[3 + a][threadIdx.x], s[3 + a][threadIdx.x + w]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) out[threadIdx.x] = s[threadIdx.x][0];
+}
+
+// ------------------------------------------------------------------ Morton codes
+
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+  uint64_t x = v & 0x1FFFFFu;
+  x = (x | (x << 32)) & 0x1F00000000FFFFull;
+  x = (x | (x << 16)) & 0x1F0000FF0000FFull;
+  x = (x | (x << 8)) & 0x100F00F00F00F00Full;
+  x = (x | (x << 4)) & 0x10C30C30C30C30C3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+__device__ __forceinline__ uint32_t quantise(float v, float lo, float scale) {
+#pragma clang fp contract(off)
+  float rel = v - lo;
+  float pos = rel * scale;
+  float fl = floorf(pos);
+  return fl <= 0.f ? 0u : (fl >= 2097151.f ? 2097151u : (uint32_t)fl);
+}
+
+__global__ void __launch_bounds__(kBlock) k_morton(const float* __restrict__ pts, int64_t n,
+                                                   const float* __restrict__ bounds, uint64_t* __restrict__ codes,
+                                                   uint32_t* __restrict__ idx) {
+#pragma clang fp contract(off)
+  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i >= n) return;
+  uint32_t q[3];
+  for (int a = 0; a < 3; ++a) {
+    float lo = bounds[a], hi = bounds[3 + a];
+    float ext = hi - lo;
+    float scale = ext > 0.f ? 2097152.f / ext : 0.f;  // correctly rounded division
+    q[a] = quantise(pts[3 * i + a], lo, scale);
+  }
+  codes[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+  idx[i] = (uint32_t)i;
+}
+
+// ------------------------------------------------------------------ radix sort (stable LSD)
+
+constexpr int kRadixItems = 16;
+constexpr int kRadixTile = kBlock * kRadixItems;
+
+__global__ void __launch_bounds__(kBlock) k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+                                                       uint32_t* __restrict__ hist, int nblocks) {
+  __shared__ uint32_t s_cnt[256];
+  s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * kRadixTile;
+  for (int r = 0; r < kRadixItems; ++r) {
+    int64_t i = base + r * kBlock + threadIdx.x;
+    if (i < n) atomicAdd(&s_cnt[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = s_cnt[threadIdx.x];
+}
+
+// Exclusive scan of `n` uint32 in chunks of kScanChunk.
+constexpr int kScanItems = 16;
+constexpr int kScanChunk = kBlock * kScanItems;
+
+__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_tmp, uint32_t* total) {
+  // Hillis-Steele over kBlock values in LDS.
+  s_tmp[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    uint32_t add = threadIdx.x >= off ? s_tmp[threadIdx.x - off] : 0u;
+    __syncthreads();
+    s_tmp[threadIdx.x] += add;
+    __syncthreads();
+  }
+  uint32_t incl = s_tmp[threadIdx.x];
+  *total = s_tmp[kBlock - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+                                                        uint32_t* __restrict__ partial) {
+  __shared__ uint32_t s[kBlock];
+  int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  uint32_t acc = 0;
+  for (int j = 0; j < kScanItems; ++j)
+    if (base + j < n) acc += in[base + j];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+}
+
+// One block: exclusive scan of up to kScanChunk partials in place.
+__global__ void __launch_bounds__(kBlock) k_scan_partials(uint32_t* __restrict__ partial, int n) {
+  __shared__ uint32_t s[kBlock];
+  uint32_t v[kScanItems];
+  uint32_t acc = 0;
+  for (int j = 0; j < kScanItems; ++j) {
+    int i = threadIdx.x * kScanItems + j;
+    v[j] = i < n ? partial[i] : 0u;
+    acc += v[j];
+  }
+  uint32_t tot;
+  uint32_t run = block_exclusive_scan(acc, s, &tot);
+  for (int j = 0; j < kScanItems; ++j) {
+    int i = threadIdx.x * kScanItems + j;
+    if (i < n) partial[i] = run;
+    run += v[j];
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_down(const uint32_t* __restrict__ in, int64_t n,
+                                                      const uint32_t* __restrict__ partial,
+                                                      uint32_t* __restrict__ out) {
+  __shared__ uint32_t s[kBlock];
+  int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t acc = 0;
+  for (int j = 0; j < kScanItems; ++j) {
+    v[j] = base + j < n ? in[base + j] : 0u;
+    acc += v[j];
+  }
+  uint32_t tot;
+  uint32_t run = block_exclusive_scan(acc, s, &tot) + (partial ? partial[blockIdx.x] : 0u);
+  for (int j = 0; j < kScanItems; ++j) {
+    if (base + j < n) out[base + j] = run;
+    run += v[j];
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* __restrict__ keys_in,
+                                                          const uint32_t* __restrict__ vals_in, int64_t n, int shift,
+                                                          const uint32_t* __restrict__ offsets, int nblocks,
+                                                          uint64_t* __restrict__ keys_out,
+                                                          uint32_t* __restrict__ vals_out) {
+  __shared__ uint32_t s_off[256];
+  __shared__ uint32_t s_wcnt[kBlock / 64][256];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+  s_off[threadIdx.x] = offsets[(size_t)threadIdx.x * nblocks + blockIdx.x];
+  int64_t base = (int64_t)blockIdx.x * kRadixTile;
+  for (int r = 0; r < kRadixItems; ++r) {
+    for (int w = 0; w < kBlock / 64; ++w) s_wcnt[w][threadIdx.x] = 0u;
+    __syncthreads();
+    int64_t i = base + r * kBlock + threadIdx.x;
+    bool valid = i < n;
+    uint64_t key = valid ? keys_in[i] : 0ull;
+    uint32_t val = valid ? vals_in[i] : 0u;
+    uint32_t digit = (uint32_t)(key >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < 8; ++b) {
+      bool bit = (digit >> b) & 1u;
+      uint64_t m = __ballot(valid && bit);
+      peers &= bit ? m : ~m;
+    }
+    uint32_t rank = __popcll(peers & lt_mask);
+    if (valid && rank == 0) s_wcnt[wave][digit] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = s_off[digit] + rank;
+      for (int w = 0; w < wave; ++w) pos += s_wcnt[w][digit];
+      keys_out[pos] = key;
+      vals_out[pos] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < kBlock / 64; ++w) add += s_wcnt[w][threadIdx.x];
+    s_off[threadIdx.x] += add;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ radix tree (Karras)
+
+__device__ __forceinline__ int prefix_len(const uint64_t* __restrict__ codes, int64_t n, int64_t i, int64_t j) {
+  if (j < 0 || j >= n) return -1;
+  uint64_t a = codes[i], b = codes[j];
+  if (a != b) return __clzll(a ^ b);
+  return 64 + __clz((uint32_t)i ^ (uint32_t)j);
+}
+
+__global__ void __launch_bounds__(kBlock) k_karras(const uint64_t* __restrict__ codes, int64_t n,
+                                                   uint32_t* __restrict__ child, uint32_t* __restrict__ parent) {
+  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i >= n - 1) return;
+  int d = prefix_len(codes, n, i, i + 1) - prefix_len(codes, n, i, i - 1) > 0 ? 1 : -1;
+  int dmin = prefix_len(codes, n, i, i - d);
+  int64_t lmax = 2;
+  while (prefix_len(codes, n, i, i + lmax * d) > dmin) lmax <<= 1;
+  int64_t l = 0;
+  for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
+    if (prefix_len(codes, n, i, i + (l + t) * d) > dmin) l += t;
+  int64_t j = i + l * d;
+  int dnode = prefix_len(codes, n, i, j);
+  int64_t s = 0;
+  int64_t t = l;
+  do {
+    t = (t + 1) >> 1;
+    if (prefix_len(codes, n, i, i + (s + t) * d) > dnode) s += t;
+  } while (t > 1);
+  int64_t gamma = i + s * d + (d < 0 ? -1 : 0);
+  int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+  uint32_t left, right;
+  if (lo == gamma) {
+    left = kLeafFlag | (uint32_t)gamma;
+    parent[(n - 1) + gamma] = (uint32_t)i;
+  } else {
+    left = (uint32_t)gamma;
+    parent[gamma] = (uint32_t)i;
+  }
+  if (hi == gamma + 1) {
+    right = kLeafFlag | (uint32_t)(gamma + 1);
+    parent[(n - 1) + gamma + 1] = (uint32_t)i;
+  } else {
+    right = (uint32_t)(gamma + 1);
+    parent[gamma + 1] = (uint32_t)i;
+  }
+  child[2 * i] = left;
+  child[2 * i + 1] = right;
+  if (i == 0) parent[0] = kNoParent;
+}
+
+// ------------------------------------------------------------------ leaves
+
+struct GaussIn {
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opac;
+};
+
+__device__ __forceinline__ void quat_rot(const float* q4, float R[3][3]) {
+  float w = q4[0], x = q4[1], y = q4[2], z = q4[3];
+  float inv = rsqrtf(w * w + x * x + y * y + z * z);
+  w *= inv; x *= inv; y *= inv; z *= inv;
+  R[0][0] = 1.f - 2.f * (y * y + z * z); R[0][1] = 2.f * (x * y - w * z);       R[0][2] = 2.f * (x * z + w * y);
+  R[1][0] = 2.f * (x * y + w * z);       R[1][1] = 1.f - 2.f * (x * x + z * z); R[1][2] = 2.f * (y * z - w * x);
+  R[2][0] = 2.f * (x * z - w * y);       R[2][1] = 2.f * (y * z + w * x);       R[2][2] = 1.f - 2.f * (x * x + y * y);
+}
+
+// Relative padding of the leaf boxes: the box must contain the bounding ellipsoid as the
+// leaf test sees it in binary32 (rounding of R, rho and of the transformed ray).
+constexpr float kBoxPad = 1.0f + 1.0f / 128.0f;
+
+struct GaussGeom {
+  float R[3][3];
+  float s[3];
+  float rho;
+  float o;
+  bool active;
+};
+
+__device__ __forceinline__ GaussGeom gauss_geom(const GaussIn& g, int64_t i, float alpha_min) {
+  GaussGeom G;
+  quat_rot(g.quats + 4 * i, G.R);
+  for (int a = 0; a < 3; ++a) G.s[a] = g.scales[3 * i + a];
+  G.o = g.opac[i];
+  G.active = G.o > alpha_min && G.s[0] > 0.f && G.s[1] > 0.f && G.s[2] > 0.f;
+  G.rho = G.active ? sqrtf(2.f * logf(G.o / alpha_min)) : 0.f;
+  return G;
+}
+
+__device__ __forceinline__ void gauss_box(const GaussIn& g, int64_t i, const GaussGeom& G, float lo[3], float hi[3]) {
+  for (int j = 0; j < 3; ++j) {
+    float m = g.means[3 * i + j];
+    float h = 0.f;
+    if (G.active) {
+      float v = 0.f;
+      for (int k = 0; k < 3; ++k) v += G.R[j][k] * G.R[j][k] * G.s[k] * G.s[k];
+      h = G.rho * sqrtf(v) * kBoxPad;
+    }
+    lo[j] = m - h;
+    hi[j] = m + h;
+  }
+}
+
+// Sphere leaves: instance record and box for sorted position p.
+__global__ void __launch_bounds__(kBlock) k_sphere_leaves(GaussIn g, const uint32_t* __restrict__ perm, int64_t n,
+                                                          float alpha_min, float4* __restrict__ inst,
+                                                          float* __restrict__ boxes) {
+  int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (p >= n) return;
+  uint32_t i = perm[p];
+  GaussGeom G = gauss_geom(g, i, alpha_min);
+  float4 r[4];
+  float* rr = reinterpret_cast<float*>(r);
+  for (int a = 0; a < 3; ++a) {
+    // row a of A = column a of R / (rho s_a)
+    float sc = G.active ? 1.f / (G.rho * G.s[a]) : 0.f;
+    rr[4 * a + 0] = G.R[0][a] * sc;
+    rr[4 * a + 1] = G.R[1][a] * sc;
+    rr[4 * a + 2] = G.R[2][a] * sc;
+    rr[4 * a + 3] = g.means[3 * i + a];
+  }
+  rr[12] = G.o;
+  rr[13] = G.active ? log2f(G.o / alpha_min) : 0.f;
+  rr[14] = __uint_as_float(i);
+  rr[15] = __uint_as_float(G.active ? 1u : 0u);
+  for (int q = 0; q < 4; ++q) inst[4 * p + q] = r[q];
+  float lo[3], hi[3];
+  gauss_box(g, i, G, lo, hi);
+  float* bx = boxes + ((n - 1) + p) * 6;
+  for (int a = 0; a < 3; ++a) {
+    bx[a] = lo[a];
+    bx[3 + a] = hi[a];
+  }
+}
+
+// ------------------------------------------------------------------ refit
+
+__device__ __forceinline__ float ld_coherent(const float* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void __launch_bounds__(kBlock) k_refit(int64_t n, const uint32_t* __restrict__ child,
+                                                  const uint32_t* __restrict__ parent, float* boxes,
+                                                  uint32_t* __restrict__ arrivals, float4* __restrict__ nodes) {
+  int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (p >= n) return;
+  uint32_t node = parent[(n - 1) + p];
+  while (node != kNoParent) {
+    __threadfence();
+    if (atomicAdd(&arrivals[node], 1u) == 0u) return;  // the sibling subtree is not done yet
+    __threadfence();
+    uint32_t c[2] = {child[2 * node], child[2 * node + 1]};
+    float cb[2][6];
+    for (int k = 0; k < 2; ++k) {
+      int64_t idx = (c[k] & kLeafFlag) ? (n - 1) + (c[k] & ~kLeafFlag) : c[k];
+      for (int a = 0; a < 6; ++a) cb[k][a] = ld_coherent(boxes + idx * 6 + a);
+    }
+    float* nb = boxes + (int64_t)node * 6;
+    for (int a = 0; a < 3; ++a) {
+      nb[a] = fminf(cb[0][a], cb[1][a]);
+      nb[3 + a] = fmaxf(cb[0][3 + a], cb[1][3 + a]);
+    }
+    nodes[4 * node + 0] = make_float4(cb[0][0], cb[0][1], cb[0][2], cb[0][3]);
+    nodes[4 * node + 1] = make_float4(cb[0][4], cb[0][5], cb[1][0], cb[1][1]);
+    nodes[4 * node + 2] = make_float4(cb[1][2], cb[1][3], cb[1][4], cb[1][5]);
+    nodes[4 * node + 3] = make_float4(__uint_as_float(c[0]), __uint_as_float(c[1]), 0.f, 0.f);
+    node = parent[node];
+  }
+}
+
+// ------------------------------------------------------------------ pinhole rays
+
+__global__ void __launch_bounds__(kBlock) k_pinhole(float3 eye, float3 fwd, float3 right, float3 up, int W, int H,
+                                                    float* __restrict__ origins, float* __restrict__ dirs) {
+  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i >= (int64_t)W * H) return;
+  int y = (int)(i / W), x = (int)(i - (int64_t)y * W);
+  float sx = 2.f * ((float)x + 0.5f) / (float)W - 1.f;
+  float sy = 1.f - 2.f * ((float)y + 0.5f) / (float)H;
+  float dx = fwd.x + sx * right.x + sy * up.x;
+  float dy = fwd.y + sx * right.y + sy * up.y;
+  float dz = fwd.z + sx * right.z + sy * up.z;
+  float inv = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
+  origins[3 * i + 0] = eye.x;
+  origins[3 * i + 1] = eye.y;
+  origins[3 * i + 2] = eye.z;
+  dirs[3 * i + 0] = dx * inv;
+  dirs[3 * i + 1] = dy * inv;
+  dirs[3 * i + 2] = dz * inv;
+}
+
+inline unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + kBlock - 1) / kBlock); }
+
+template <class T>
+grtx_status dalloc(Bvh* b, T** p, size_t count) {
+  size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  void* q = nullptr;
+  GRTX_HIP(hipMalloc(&q, bytes));
+  b->allocations.push_back(q);
+  b->bytes += bytes;
+  *p = static_cast<T*>(q);
+  return GRTX_OK;
+}
+
+#define GRTX_TRY(x)                  \
+  do {                               \
+    grtx_status st_ = (x);           \
+    if (st_ != GRTX_OK) return st_;  \
+  } while (0)
+
+// Scratch buffers of one build, released when the build function returns (stream-ordered
+// frees keep them valid for the enqueued kernels).
+struct Scratch {
+  std::vector<void*> ptrs;
+  hipStream_t s;
+  ~Scratch() {
+    for (void* p : ptrs) (void)hipFreeAsync(p, s);
+  }
+  template <class T>
+  grtx_status get(T** p, size_t count) {
+    void* q = nullptr;
+    GRTX_HIP(hipMallocAsync(&q, std::max<size_t>(count, 1) * sizeof(T), s));
+    ptrs.push_back(q);
+    *p = static_cast<T*>(q);
+    return GRTX_OK;
+  }
+};
+
+// Sort (codes, idx) ascending by code, stable; results in keys/vals (ping-pong with tmp).
+grtx_status radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t* tvals, int64_t n, Scratch& sc,
+                       hipStream_t s) {
+  int nblocks = (int)((n + kRadixTile - 1) / kRadixTile);
+  int64_t hn = (int64_t)256 * nblocks;
+  uint32_t *hist = nullptr, *offs = nullptr, *part = nullptr;
+  int nparts = (int)((hn + kScanChunk - 1) / kScanChunk);
+  if (nparts > kScanChunk) {
+    set_error("radix sort: %lld keys exceed the supported size", (long long)n);
+    return GRTX_ERR_INVALID_ARG;
+  }
+  GRTX_TRY(sc.get(&hist, hn));
+  GRTX_TRY(sc.get(&offs, hn));
+  GRTX_TRY(sc.get(&part, nparts));
+  uint64_t* kin = keys;
+  uint32_t* vin = vals;
+  uint64_t* kout = tkeys;
+  uint32_t* vout = tvals;
+  for (int pass = 0; pass < 8; ++pass) {
+    int shift = 8 * pass;
+    hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kBlock), 0, s, kin, n, shift, hist, nblocks);
+    if (nparts > 1) {
+      hipLaunchKernelGGL(k_scan_reduce, dim3(nparts), dim3(kBlock), 0, s, hist, hn, part);
+      hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, s, part, nparts);
+      hipLaunchKernelGGL(k_scan_down, dim3(nparts), dim3(kBlock), 0, s, hist, hn, part, offs);
+    } else {
+      hipLaunchKernelGGL(k_scan_down, dim3(1), dim3(kBlock), 0, s, hist, hn, (const uint32_t*)nullptr, offs);
+    }
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kBlock), 0, s, kin, vin, n, shift, offs, nblocks, kout,
+                       vout);
+    GRTX_LAUNCH_CHECK();
+    std::swap(kin, kout);
+    std::swap(vin, vout);
+  }
+  // 8 passes: the result is back in (keys, vals)
+  return GRTX_OK;
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+// Build over `n` points (centroids) whose leaf boxes/records are produced by `leaves`.
+grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_min, hipStream_t s, Bvh* b) {
+  b->kind = kind;
+  b->n_gauss = g->count;
+  b->sh_degree = g->sh_degree;
+  b->alpha_min = alpha_min;
+  b->opacities = g->opacities;
+  b->sh = g->sh;
+  b->build_stream = s;
+  GRTX_HIP(hipGetDevice(&b->device));
+  if (kind != GRTX_BVH_SPHERE_INSTANCE) {
+    set_error("bvh kind %d is not available in this build", (int)kind);
+    return GRTX_ERR_INVALID_ARG;
+  }
+  const int64_t n = g->count;
+  b->n_leaves = n;
+  if (n == 0) return GRTX_OK;
+  GaussIn gi{g->means, g->scales, g->quats, g->opacities};
+  const int64_t nint = n - 1;
+  GRTX_TRY(dalloc(b, &b->codes, n));
+  GRTX_TRY(dalloc(b, &b->perm, n));
+  GRTX_TRY(dalloc(b, &b->child, 2 * std::max<int64_t>(nint, 1)));
+  GRTX_TRY(dalloc(b, &b->parent, 2 * n - 1));
+  GRTX_TRY(dalloc(b, &b->boxes, 6 * (2 * n - 1)));
+  GRTX_TRY(dalloc(b, &b->nodes, 4 * std::max<int64_t>(nint, 1)));
+  GRTX_TRY(dalloc(b, &b->inst, 4 * n));
+  b->root_box = b->boxes;  // node 0 (the root, or the only leaf when n == 1)
+
+  Scratch sc{{}, s};
+  float *partial = nullptr, *bounds = nullptr;
+  uint64_t* tkeys = nullptr;
+  uint32_t *tvals = nullptr, *arrivals = nullptr;
+  int nparts = (int)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock);
+  GRTX_TRY(sc.get(&partial, 6 * nparts));
+  GRTX_TRY(sc.get(&bounds, 6));
+  GRTX_TRY(sc.get(&tkeys, n));
+  GRTX_TRY(sc.get(&tvals, n));
+  GRTX_TRY(sc.get(&arrivals, std::max<int64_t>(nint, 1)));
+
+  hipLaunchKernelGGL(k_bounds_partial, dim3(nparts), dim3(kBlock), 0, s, g->means, n, partial);
+  hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(kBlock), 0, s, partial, nparts, bounds);
+  hipLaunchKernelGGL(k_morton, dim3(grid_for(n)), dim3(kBlock), 0, s, g->means, n, bounds, b->codes, b->perm);
+  GRTX_LAUNCH_CHECK();
+  GRTX_TRY(radix_sort(b->codes, b->perm, tkeys, tvals, n, sc, s));
+  hipLaunchKernelGGL(k_sphere_leaves, dim3(grid_for(n)), dim3(kBlock), 0, s, gi, b->perm, n, alpha_min, b->inst,
+                     b->boxes);
+  if (nint > 0) {
+    hipLaunchKernelGGL(k_karras, dim3(grid_for(nint)), dim3(kBlock), 0, s, b->codes, n, b->child, b->parent);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nint)), dim3(kBlock), 0, s, arrivals, nint, 0u);
+    hipLaunchKernelGGL(k_refit, dim3(grid_for(n)), dim3(kBlock), 0, s, n, b->child, b->parent, b->boxes, arrivals,
+                       b->nodes);
+  } else {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, s, b->parent, 1, kNoParent);
+  }
+  GRTX_LAUNCH_CHECK();
+  return GRTX_OK;
+}
+
+grtx_status export_topology(const Bvh* b, uint32_t* child, uint32_t* parent, uint64_t* morton, uint32_t* perm,
+                            float* boxes, hipStream_t s) {
+  const int64_t n = b->n_leaves;
+  if (n == 0) return GRTX_OK;
+  const int64_t nint = n - 1;
+  if (child && nint > 0) GRTX_HIP(hipMemcpyAsync(child, b->child, sizeof(uint32_t) * 2 * nint, hipMemcpyDeviceToDevice, s));
+  if (parent) GRTX_HIP(hipMemcpyAsync(parent, b->parent, sizeof(uint32_t) * (2 * n - 1), hipMemcpyDeviceToDevice, s));
+  if (morton) GRTX_HIP(hipMemcpyAsync(morton, b->codes, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+  if (perm) GRTX_HIP(hipMemcpyAsync(perm, b->perm, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
+  if (boxes) GRTX_HIP(hipMemcpyAsync(boxes, b->boxes, sizeof(float) * 6 * (2 * n - 1), hipMemcpyDeviceToDevice, s));
+  return GRTX_OK;
+}
+
+grtx_status pinhole_rays(const grtx_camera* cam, float* origins, float* dirs, hipStream_t s) {
+  double e[3], f[3], r[3], u[3];
+  for (int a = 0; a < 3; ++a) {
+    e[a] = cam->eye[a];
+    f[a] = (double)cam->target[a] - cam->eye[a];
+  }
+  double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  for (double& x : f) x /= fl;
+  const float* up = cam->up;
+  r[0] = f[1] * up[2] - f[2] * up[1];
+  r[1] = f[2] * up[0] - f[0] * up[2];
+  r[2] = f[0] * up[1] - f[1] * up[0];
+  double rl = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  if (!(fl > 0.0) || !(rl > 0.0)) {
+    set_error("pinhole camera: degenerate eye/target/up");
+    return GRTX_ERR_INVALID_ARG;
+  }
+  for (double& x : r) x /= rl;
+  u[0] = r[1] * f[2] - r[2] * f[1];
+  u[1] = r[2] * f[0] - r[0] * f[2];
+  u[2] = r[0] * f[1] - r[1] * f[0];
+  double th = std::tan(0.5 * (double)cam->fov_y_deg * M_PI / 180.0);
+  double aspect = (double)cam->width / (double)cam->height;
+  float3 E = make_float3((float)e[0], (float)e[1], (float)e[2]);
+  float3 F = make_float3((float)f[0], (float)f[1], (float)f[2]);
+  float3 R = make_float3((float)(r[0] * th * aspect), (float)(r[1] * th * aspect), (float)(r[2] * th * aspect));
+  float3 U = make_float3((float)(u[0] * th), (float)(u[1] * th), (float)(u[2] * th));
+  int64_t n = (int64_t)cam->width * cam->height;
+  hipLaunchKernelGGL(k_pinhole, dim3(grid_for(n)), dim3(kBlock), 0, s, E, F, R, U, cam->width, cam->height, origins,
+                     dirs);
+  GRTX_LAUNCH_CHECK();
+  return GRTX_OK;
+}
+
+}  // namespace grtx

@@ -1,0 +1,104 @@
+// Internal declarations shared by the HIP sources of the library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "grtx.h"
+
+namespace grtx {
+
+// ---------------------------------------------------------------------------------------
+// Device data layout
+// ---------------------------------------------------------------------------------------
+//
+// Internal node record, 64 B (4 x float4), one per internal node in radix-tree order
+// (node 0 = root). It holds the boxes of both children, so one fetch tests both:
+//   q0 = (c0.lo.x, c0.lo.y, c0.lo.z, c0.hi.x)
+//   q1 = (c0.hi.y, c0.hi.z, c1.lo.x, c1.lo.y)
+//   q2 = (c1.lo.z, c1.hi.x, c1.hi.y, c1.hi.z)
+//   q3 = (ref0, ref1, 0, 0) as uint bits; ref = internal node index, or kLeafFlag | leaf.
+//
+// Instance record (SPHERE_INSTANCE leaf), 64 B, in sorted-leaf order:
+//   q0 = (A00, A01, A02, mu.x)   A = rho^-1 S^-1 R^T maps the bounding ellipsoid of the
+//   q1 = (A10, A11, A12, mu.y)   Gaussian onto the unit sphere: u = A (x - mu)
+//   q2 = (A20, A21, A22, mu.z)
+//   q3 = (o, log2(o/alpha_min), gaussian id bits, active bits)
+//
+// Proxy triangle record (PROXY20 leaf), 48 B, in sorted-leaf order:
+//   q0 = (v0.x, v0.y, v0.z, gaussian id bits)
+//   q1 = (v1.x, v1.y, v1.z, 0)
+//   q2 = (v2.x, v2.y, v2.z, 0)
+// For PROXY20 the instance records are stored in Gaussian order instead.
+constexpr uint32_t kLeafFlag = 0x80000000u;
+constexpr uint32_t kNoParent = 0xFFFFFFFFu;
+
+struct Bvh {
+  int device = 0;
+  grtx_bvh_kind kind = GRTX_BVH_SPHERE_INSTANCE;
+  int64_t n_gauss = 0;
+  int64_t n_leaves = 0;
+  int sh_degree = 0;
+  float alpha_min = 0.f;
+  float4* nodes = nullptr;   // [n_leaves-1][4]
+  float4* inst = nullptr;    // [n_gauss][4]
+  float4* tris = nullptr;    // PROXY20: [n_leaves][3]
+  uint64_t* codes = nullptr; // [n_leaves] sorted Morton codes
+  uint32_t* perm = nullptr;  // [n_leaves]
+  uint32_t* child = nullptr; // [n_leaves-1][2]
+  uint32_t* parent = nullptr;// [2 n_leaves - 1]
+  float* boxes = nullptr;    // [2 n_leaves - 1][6]
+  float* root_box = nullptr; // device [6] (points into boxes)
+  const float* opacities = nullptr; // borrowed
+  const float* sh = nullptr;        // borrowed
+  hipStream_t build_stream = nullptr;
+  size_t bytes = 0;
+  std::vector<void*> allocations;
+};
+
+// ---------------------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------------------
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define GRTX_HIP(call)                                                                  \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      ::grtx::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                      \
+      return e_ == hipErrorOutOfMemory ? GRTX_ERR_OUT_OF_MEMORY : GRTX_ERR_DEVICE;      \
+    }                                                                                   \
+  } while (0)
+
+#define GRTX_LAUNCH_CHECK()                                                             \
+  do {                                                                                  \
+    hipError_t e_ = hipGetLastError();                                                  \
+    if (e_ != hipSuccess) {                                                             \
+      ::grtx::set_error("kernel launch failed: %s (%s:%d)", hipGetErrorString(e_),      \
+                        __FILE__, __LINE__);                                            \
+      return GRTX_ERR_DEVICE;                                                           \
+    }                                                                                   \
+  } while (0)
+
+// ---------------------------------------------------------------------------------------
+// Host entry points implemented in the .hip sources
+// ---------------------------------------------------------------------------------------
+grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_min, hipStream_t s, Bvh* b);
+grtx_status export_topology(const Bvh* b, uint32_t* child, uint32_t* parent, uint64_t* morton, uint32_t* perm,
+                            float* boxes, hipStream_t s);
+grtx_status pinhole_rays(const grtx_camera* cam, float* origins, float* dirs, hipStream_t s);
+grtx_status trace(const Bvh* b, const grtx_rays* r, const grtx_trace_params* p, const grtx_trace_outputs* o,
+                  hipStream_t s);
+
+}  // namespace grtx
+
+struct grtx_bvh {
+  grtx::Bvh impl;
+};

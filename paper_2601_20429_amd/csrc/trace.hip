@@ -1,0 +1,699 @@
+// Multi-round k-buffer Gaussian ray tracing with traversal checkpointing, for gfx950.
+//
+// What one ray computes (Sec. III-A; Listing 1; Sec. IV-B):
+//   round r: traverse the BVH, keeping the k closest hits beyond the last blended one in
+//   a sorted k-buffer (any-hit insertion sort; a hit beyond the farthest entry of a full
+//   buffer is rejected and t_max shrinks to the buffer's farthest entry); blend the
+//   k-buffer front to back (Eq. 1, alpha at the maximum response, Eq. 2, colour from SH
+//   and the ray direction); stop once the transmittance falls below T_min (early ray
+//   termination) or fewer than k hits remain.
+//   CHECKPOINT mode: nodes whose entry distance exceeds t_max are written to the ray's
+//   destination checkpoint list, and hits rejected from the k-buffer to its eviction
+//   list; the next round first moves the k closest evicted hits into the k-buffer and
+//   then resumes traversal from the source list (the previous destination list) instead
+//   of the root. Entries whose stored distance already exceeds t_max are carried to the
+//   new destination list without fetching the node.
+//   RESTART mode: every round starts at the root with the interval (last blended hit,
+//   t_max] and nothing is kept between rounds (the multi-round baseline).
+//
+// How it maps to CDNA4 (there is no RT unit, so the RT unit's job is done by the wave):
+//   - persistent waves; each lane owns one ray at a time across all of its rounds;
+//     idle lanes are refilled with a ballot + one atomic per wave; rays are taken in
+//     8x8 pixel tiles when the rays form an image;
+//   - the k-buffer is a register array of 64-bit keys (distance bits << 32 | leaf),
+//     kept sorted by a statically indexed compare-exchange chain;
+//   - the traversal stack is per lane: the top kLdsStack entries in LDS, the rest in a
+//     per-wave HBM region; checkpoint and eviction lists are per-lane HBM lists laid out
+//     [entry][lane] per wave, so lanes that walk their lists in step read whole rows;
+//   - hit keys use the leaf's sorted position, whose Morton order keeps neighbouring
+//     Gaussians close in memory; ties in distance are broken by that position.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+
+#include "grtx_internal.h"
+
+namespace grtx {
+namespace {
+
+constexpr int kTraceBlock = 256;
+constexpr int kWaves = kTraceBlock / 64;
+constexpr int kLdsStack = 16;
+constexpr int kMaxStack = 96;  // > depth of a radix tree over 95-bit keys
+constexpr int kSpillRows = kMaxStack - kLdsStack;
+constexpr int kRefillThreshold = 16;
+constexpr uint64_t kEmptyKey = (0x7F800000ull << 32) | 0xFFFFFFFFull;  // (+inf, max)
+
+enum : int { kIdle = 0, kTrav = 1, kEnd = 2 };
+
+struct TraceArgs {
+  const float4* nodes;
+  const float4* inst;
+  const float* sh;
+  const float* root_box;
+  uint32_t root_ref;
+  int sh_degree;
+  const float* ray_o;
+  const float* ray_d;
+  int64_t n_rays;
+  int64_t n_work;
+  int image_w;
+  int image_h;
+  int tiles_x;
+  float t_near;
+  int k;
+  float T_min;
+  int mode;
+  float bg0, bg1, bg2;
+  float* rgb;
+  float* depth;
+  float* opac;
+  uint32_t* stats;
+  int32_t* hit_ids;
+  int32_t* hit_counts;
+  int hit_cap;
+  uint2* pool;
+  int64_t rows_per_wave;
+  int cap_d;
+  int cap_e;
+  unsigned int* counter;
+};
+
+__device__ __forceinline__ float key_t(uint64_t k) { return __uint_as_float((uint32_t)(k >> 32)); }
+__device__ __forceinline__ uint64_t make_key(float t, uint32_t id) {
+  return ((uint64_t)__float_as_uint(t) << 32) | id;
+}
+
+// Robust reciprocal for the slab test: zero components become a huge finite value of
+// the same sign, so that 0 * inv never produces NaN.
+__device__ __forceinline__ float safe_inv(float d) {
+  const float tiny = 1e-20f;
+  float ad = fabsf(d);
+  return 1.0f / copysignf(ad > tiny ? ad : tiny, d);
+}
+
+struct Slab {
+  float tn, tf;
+};
+
+__device__ __forceinline__ Slab slab(float lox, float loy, float loz, float hix, float hiy, float hiz, float ox,
+                                     float oy, float oz, float ix, float iy, float iz) {
+  float t0x = (lox - ox) * ix, t1x = (hix - ox) * ix;
+  float t0y = (loy - oy) * iy, t1y = (hiy - oy) * iy;
+  float t0z = (loz - oz) * iz, t1z = (hiz - oz) * iz;
+  Slab s;
+  s.tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z));
+  s.tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));
+  return s;
+}
+
+// Real spherical harmonics up to band 3 (orthonormal, Condon-Shortley phase) as
+// polynomials in the unit direction. Y_l^m = sqrt(2) K_l^|m| (-1)^m (cos|sin)(|m| phi)
+// sin^|m|(theta) P_l^(|m|)(cos theta), with K_l^m = sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!)
+// and P_l^(m) the m-th derivative of the Legendre polynomial.
+constexpr double cx_sqrt(double x) {
+  double r = x > 1.0 ? x : 1.0;
+  for (int i = 0; i < 100; ++i) r = 0.5 * (r + x / r);
+  return r;
+}
+constexpr double kPi = 3.14159265358979323846;
+constexpr double K(int l, int am, double fac_ratio) { return cx_sqrt((2.0 * l + 1.0) / (4.0 * kPi) * fac_ratio); }
+constexpr float SH00 = (float)K(0, 0, 1.0);
+constexpr float SH1 = (float)K(1, 0, 1.0);                                   // sqrt(3/4pi)
+constexpr float SH20 = (float)(K(2, 0, 1.0) * 0.5);                          // K20 / 2 * (3z^2 - 1)
+constexpr float SH21 = (float)(cx_sqrt(2.0) * K(2, 1, 1.0 / 6.0) * 3.0);     // -xz, -yz
+constexpr float SH22 = (float)(cx_sqrt(2.0) * K(2, 2, 1.0 / 24.0) * 3.0);    // (x^2-y^2), 2xy
+constexpr float SH30 = (float)(K(3, 0, 1.0) * 0.5);                          // (5z^3 - 3z)
+constexpr float SH31 = (float)(cx_sqrt(2.0) * K(3, 1, 1.0 / 12.0) * 0.5);    // -(15z^2-3) x|y
+constexpr float SH32 = (float)(cx_sqrt(2.0) * K(3, 2, 1.0 / 120.0) * 15.0);  // z (x^2-y^2), 2xyz
+constexpr float SH33 = (float)(cx_sqrt(2.0) * K(3, 3, 1.0 / 720.0) * 15.0);  // -(x^3-3xy^2), -(3x^2y-y^3)
+
+__device__ __forceinline__ void sh_basis(float x, float y, float z, int L, float* Y) {
+  Y[0] = SH00;
+  if (L < 1) return;
+  Y[1] = -SH1 * y;
+  Y[2] = SH1 * z;
+  Y[3] = -SH1 * x;
+  if (L < 2) return;
+  float xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = SH22 * 2.f * x * y;
+  Y[5] = -SH21 * y * z;
+  Y[6] = SH20 * (3.f * zz - 1.f);
+  Y[7] = -SH21 * x * z;
+  Y[8] = SH22 * (xx - yy);
+  if (L < 3) return;
+  Y[9] = -SH33 * (3.f * xx * y - yy * y);
+  Y[10] = SH32 * 2.f * x * y * z;
+  Y[11] = -SH31 * y * (15.f * zz - 3.f);
+  Y[12] = SH30 * (5.f * zz * z - 3.f * z);
+  Y[13] = -SH31 * x * (15.f * zz - 3.f);
+  Y[14] = SH32 * z * (xx - yy);
+  Y[15] = -SH33 * (xx * x - 3.f * x * yy);
+}
+
+template <int K>
+__device__ __forceinline__ uint64_t kbuf_insert(uint64_t (&kb)[K], uint64_t x) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    uint64_t a = kb[j];
+    bool lt = x < a;
+    kb[j] = lt ? x : a;
+    x = lt ? a : x;
+  }
+  return x;
+}
+
+template <int K>
+__device__ __forceinline__ void kbuf_reset(uint64_t (&kb)[K], int k) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) kb[j] = j < K - k ? 0ull : kEmptyKey;
+}
+
+// Sphere leaf: ray in the unit-sphere frame of instance record (r0, r1, r2).
+struct SphereHit {
+  float a, b, c2;  // v.v, u.v, |u x v|^2
+};
+
+__device__ __forceinline__ SphereHit sphere_terms(float4 r0, float4 r1, float4 r2, float ox, float oy, float oz,
+                                                  float dx, float dy, float dz) {
+  float fx = ox - r0.w, fy = oy - r1.w, fz = oz - r2.w;
+  float ux = r0.x * fx + r0.y * fy + r0.z * fz;
+  float uy = r1.x * fx + r1.y * fy + r1.z * fz;
+  float uz = r2.x * fx + r2.y * fy + r2.z * fz;
+  float vx = r0.x * dx + r0.y * dy + r0.z * dz;
+  float vy = r1.x * dx + r1.y * dy + r1.z * dz;
+  float vz = r2.x * dx + r2.y * dy + r2.z * dz;
+  float cx = uy * vz - uz * vy, cy = uz * vx - ux * vz, cz = ux * vy - uy * vx;
+  SphereHit h;
+  h.a = vx * vx + vy * vy + vz * vz;
+  h.b = ux * vx + uy * vy + uz * vz;
+  h.c2 = cx * cx + cy * cy + cz * cz;
+  return h;
+}
+
+template <int K>
+__global__ void __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 4 : 2, 8)))
+k_trace(TraceArgs A) {
+  __shared__ uint2 s_stack[kLdsStack * kTraceBlock];
+  __shared__ uint32_t s_stat[GRTX_STATS_FIELDS][kTraceBlock];  // per-lane counters
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int64_t gwave = ((int64_t)blockIdx.x * kTraceBlock + tid) >> 6;
+  // The wave's rows: [0, kSpillRows) stack spill; two node lists of cap_d rows and two
+  // hit lists of cap_e rows (ping-pong source/destination, selected by `par`); K rows
+  // holding the k-buffer while it is blended. Entry j of lane l is at row j, column l.
+  uint2* wpool = A.pool + gwave * A.rows_per_wave * 64 + lane;
+  const int rowN = kSpillRows;
+  const int rowE = kSpillRows + 2 * A.cap_d;
+  const int rowK = rowE + 2 * A.cap_e;
+#define ROW(r) wpool[(int64_t)(r) * 64]
+#define STAT(f) (++s_stat[f][tid])
+  const bool ckpt = A.mode == GRTX_MODE_CHECKPOINT;
+  const float tnear = A.t_near;
+
+  int state = kIdle;
+  int ray = -1;
+  float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, ix = 0, iy = 0, iz = 0;
+  uint64_t kb[K];
+  kbuf_reset(kb, A.k);
+  uint64_t tmin = 0;  // key of the last blended hit
+  float C0 = 0, C1 = 0, C2 = 0, Dp = 0, T = 1;
+  uint32_t cur_ref = 0;
+  float cur_t = 0;
+  bool has_cur = false;
+  int sp = 0;
+  int par = 0;                              // which list of each pair is the source
+  int nsrc_n = 0, nsrc_i = 0, ndst_n = 0;   // deferred nodes
+  int esrc_n = 0, esrc_i = 0, edst_n = 0;   // evicted hits
+  bool overflow = false;
+  int nblend = 0;
+  bool exhausted = false;
+
+  auto root_start = [&]() __attribute__((always_inline)) {
+    // (Re)start at the root; subtrees that end before tmin are culled.
+    const float* rb = A.root_box;
+    Slab s = slab(rb[0], rb[1], rb[2], rb[3], rb[4], rb[5], ox, oy, oz, ix, iy, iz);
+    float tlo = fmaxf(tnear, key_t(tmin));
+    has_cur = s.tn <= s.tf && s.tf >= tlo;
+    cur_ref = A.root_ref;
+    cur_t = s.tn;
+    sp = 0;
+  };
+
+  auto defer = [&](uint32_t ref, float t) __attribute__((always_inline)) {
+    if (!ckpt) return;
+    if (ndst_n < A.cap_d) {
+      ROW(rowN + (par ^ 1) * A.cap_d + ndst_n) = make_uint2(ref, __float_as_uint(t));
+      ++ndst_n;
+      STAT(GRTX_STAT_DEFERRED);
+    } else {
+      overflow = true;
+    }
+  };
+
+  auto evict = [&](uint64_t key) __attribute__((always_inline)) {
+    if (!ckpt) return;
+    if (edst_n < A.cap_e) {
+      ROW(rowE + (par ^ 1) * A.cap_e + edst_n) = make_uint2((uint32_t)key, (uint32_t)(key >> 32));
+      ++edst_n;
+      STAT(GRTX_STAT_EVICTED);
+    } else {
+      overflow = true;
+    }
+  };
+
+  auto push = [&](uint32_t ref, float t) __attribute__((always_inline)) {
+    // At most one entry per tree level is pending, and a radix tree over 95-bit keys is
+    // at most 95 levels deep, so sp < kMaxStack always; the bound keeps memory safe.
+    uint2 e = make_uint2(ref, __float_as_uint(t));
+    if (sp < kLdsStack)
+      s_stack[sp * kTraceBlock + tid] = e;
+    else if (sp < kMaxStack)
+      ROW(sp - kLdsStack) = e;
+    sp = sp < kMaxStack ? sp + 1 : sp;
+  };
+
+  auto pop = [&]() __attribute__((always_inline)) -> uint2 {
+    --sp;
+    return sp < kLdsStack ? s_stack[sp * kTraceBlock + tid] : ROW(sp - kLdsStack);
+  };
+
+  while (true) {
+    // ---------------------------------------------------------------- refill idle lanes
+    if (!exhausted) {
+      uint64_t idle = __ballot(state == kIdle);
+      if (idle) {
+        int cnt = __popcll(idle);
+        int leader = __ffsll((unsigned long long)idle) - 1;
+        unsigned int base = 0;
+        if (lane == leader) base = atomicAdd(A.counter, (unsigned int)cnt);
+        base = __shfl(base, leader);
+        if ((int64_t)base + cnt >= A.n_work) exhausted = true;
+        if (state == kIdle) {
+          int64_t w = (int64_t)base + __popcll(idle & lt_mask);
+          int r = -1;
+          if (w < A.n_work) {
+            if (A.image_w > 0) {
+              int64_t tile = w >> 6;
+              int within = (int)(w & 63);
+              int64_t ty = tile / A.tiles_x, tx = tile - ty * A.tiles_x;
+              int64_t px = tx * 8 + (within & 7), py = ty * 8 + (within >> 3);
+              if (px < A.image_w && py < A.image_h) r = (int)(py * A.image_w + px);
+            } else {
+              r = (int)w;
+            }
+          }
+          if (r >= 0) {
+            ray = r;
+            const float* ro = A.ray_o + 3 * (int64_t)r;
+            const float* rd = A.ray_d + 3 * (int64_t)r;
+            ox = ro[0]; oy = ro[1]; oz = ro[2];
+            dx = rd[0]; dy = rd[1]; dz = rd[2];
+            ix = safe_inv(dx); iy = safe_inv(dy); iz = safe_inv(dz);
+            kbuf_reset(kb, A.k);
+            tmin = 0;
+            C0 = C1 = C2 = Dp = 0.f;
+            T = 1.f;
+            nblend = 0;
+            par = 0;
+            nsrc_n = nsrc_i = ndst_n = 0;
+            esrc_n = esrc_i = edst_n = 0;
+            overflow = false;
+#pragma unroll
+            for (int f = 0; f < GRTX_STATS_FIELDS; ++f) s_stat[f][tid] = 0u;
+            root_start();
+            state = kTrav;
+          }
+        }
+      }
+    }
+    if (__ballot(state != kIdle) == 0) {
+      if (exhausted) break;
+    }
+
+    // ---------------------------------------------------------------- traversal
+    while (true) {
+      uint64_t trav = __ballot(state == kTrav);
+      if (!trav) break;
+      uint64_t waiting = __ballot(state == kEnd) | (exhausted ? 0ull : __ballot(state == kIdle));
+      if (__popcll(waiting) >= kRefillThreshold) break;
+      if (state == kTrav) {
+      const uint64_t tmax = kb[K - 1];
+      const float tmax_t = key_t(tmax);
+      bool have_key = false;
+      uint64_t key = 0;
+      if (!has_cur) {
+        if (esrc_i < esrc_n) {
+          // hits evicted in earlier rounds compete for the k-buffer first
+          uint2 v = ROW(rowE + par * A.cap_e + esrc_i);
+          ++esrc_i;
+          key = ((uint64_t)v.y << 32) | v.x;
+          have_key = true;
+        } else {
+          uint2 e;
+          bool got = true;
+          if (sp > 0) {
+            e = pop();
+          } else if (nsrc_i < nsrc_n) {
+            e = ROW(rowN + par * A.cap_d + nsrc_i);
+            ++nsrc_i;
+          } else {
+            got = false;
+            state = kEnd;
+          }
+          if (got) {
+            float t = __uint_as_float(e.y);
+            if (t > tmax_t) {
+              defer(e.x, t);  // carried forward without a fetch
+              STAT(GRTX_STAT_FETCH_FREE);
+            } else {
+              cur_ref = e.x;
+              cur_t = t;
+              has_cur = true;
+            }
+          }
+        }
+      }
+
+      if (has_cur) {
+        if (cur_ref & kLeafFlag) {
+          // ---------------------------------------------- leaf: unit-sphere test
+          const uint32_t p = cur_ref & ~kLeafFlag;
+          const float4* ip = A.inst + 4 * (int64_t)p;
+          float4 r0 = ip[0], r1 = ip[1], r2 = ip[2];
+          SphereHit h = sphere_terms(r0, r1, r2, ox, oy, oz, dx, dy, dz);
+          STAT(GRTX_STAT_LEAVES);
+          has_cur = false;
+          if (h.a > 0.f && h.c2 <= h.a) {
+            float t0 = (-h.b - sqrtf(fmaxf(h.a - h.c2, 0.f))) / h.a;
+            // the key never precedes the entry of the leaf's own box, so that every
+            // ancestor's entry distance bounds the keys below it exactly
+            key = make_key(fmaxf(t0, cur_t), p);
+            have_key = t0 > tnear && key > tmin;
+          }
+        } else {
+          // ---------------------------------------------- internal node: both children
+          const float4* np = A.nodes + 4 * (int64_t)cur_ref;
+          float4 q0 = np[0], q1 = np[1], q2 = np[2], q3 = np[3];
+          STAT(GRTX_STAT_NODES);
+          Slab s0 = slab(q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, ox, oy, oz, ix, iy, iz);
+          Slab s1 = slab(q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, ox, oy, oz, ix, iy, iz);
+          const float tlo = fmaxf(tnear, key_t(tmin));
+          bool v0 = s0.tn <= s0.tf && s0.tf >= tlo;
+          bool v1 = s1.tn <= s1.tf && s1.tf >= tlo;
+          uint32_t c0 = __float_as_uint(q3.x), c1 = __float_as_uint(q3.y);
+          if (v0 && s0.tn > tmax_t) {
+            defer(c0, s0.tn);
+            v0 = false;
+          }
+          if (v1 && s1.tn > tmax_t) {
+            defer(c1, s1.tn);
+            v1 = false;
+          }
+          if (v0 && v1) {
+            bool first0 = s0.tn <= s1.tn;
+            push(first0 ? c1 : c0, first0 ? s1.tn : s0.tn);
+            cur_ref = first0 ? c0 : c1;
+            cur_t = first0 ? s0.tn : s1.tn;
+          } else if (v0) {
+            cur_ref = c0;
+            cur_t = s0.tn;
+          } else if (v1) {
+            cur_ref = c1;
+            cur_t = s1.tn;
+          } else {
+            has_cur = false;
+          }
+        }
+      }
+
+      // any-hit: keys beyond the farthest entry of a full k-buffer are rejected into the
+      // eviction list; otherwise the key is inserted and the entry it pushes out of a
+      // full buffer is evicted. The insertion runs under a wave-uniform branch with the
+      // empty key (a no-op) on lanes that have nothing to insert, so the register array
+      // is updated in place.
+      const bool ins = have_key && key <= tmax;
+      if (__ballot(ins)) {
+        uint64_t out = kbuf_insert(kb, ins ? key : kEmptyKey);
+        if (ins && out != kEmptyKey) evict(out);
+      }
+      if (have_key && !ins) evict(key);
+      }  // state == kTrav
+    }
+
+    // ---------------------------------------------------------------- round end: blend
+    if (state == kEnd) {
+      STAT(GRTX_STAT_ROUNDS);
+      const int ncoef = (A.sh_degree + 1) * (A.sh_degree + 1);
+      bool ert = false;
+      // Blend in key order. The k-buffer is parked in the lane's rows so that the blend
+      // loop indexes memory rather than a register array.
+      const uint64_t last = kb[K - 1];
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+        if (j >= K - A.k) ROW(rowK + j) = make_uint2((uint32_t)kb[j], (uint32_t)(kb[j] >> 32));
+#pragma unroll 1
+      for (int j = K - A.k; j < K && !ert; ++j) {
+        const uint2 kv = ROW(rowK + j);
+        const uint64_t x = ((uint64_t)kv.y << 32) | kv.x;
+        if (x == kEmptyKey) break;
+        const uint32_t p = (uint32_t)x;
+        const float4* ip = A.inst + 4 * (int64_t)p;
+        float4 r0 = ip[0], r1 = ip[1], r2 = ip[2], r3 = ip[3];
+        SphereHit h = sphere_terms(r0, r1, r2, ox, oy, oz, dx, dy, dz);
+        const float inva = 1.f / h.a;
+        const float cperp = h.c2 * inva;
+        const float talpha = -h.b * inva;
+        const float alpha = r3.x * exp2f(-r3.y * cperp);
+        const uint32_t gid = __float_as_uint(r3.z);
+        float c[3] = {0.5f, 0.5f, 0.5f};
+        const float dn = rsqrtf(dx * dx + dy * dy + dz * dz);
+        float Y[16];
+        sh_basis(dx * dn, dy * dn, dz * dn, A.sh_degree, Y);
+        if (A.sh_degree == 3) {
+          const float4* sp4 = reinterpret_cast<const float4*>(A.sh + (int64_t)gid * 48);
+#pragma unroll
+          for (int q = 0; q < 12; ++q) {
+            float4 v = sp4[q];
+            const float* vv = reinterpret_cast<const float*>(&v);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int f = 4 * q + e;
+              c[f % 3] += Y[f / 3] * vv[e];
+            }
+          }
+        } else {
+          const float* sc = A.sh + (int64_t)gid * 3 * ncoef;
+#pragma unroll
+          for (int f = 0; f < 16; ++f) {
+            if (f < ncoef) {
+              c[0] += Y[f] * sc[3 * f + 0];
+              c[1] += Y[f] * sc[3 * f + 1];
+              c[2] += Y[f] * sc[3 * f + 2];
+            }
+          }
+        }
+        const float w = T * alpha;
+        C0 += w * fmaxf(c[0], 0.f);
+        C1 += w * fmaxf(c[1], 0.f);
+        C2 += w * fmaxf(c[2], 0.f);
+        Dp += w * talpha;
+        T *= (1.f - alpha);
+        if (A.hit_ids && nblend < A.hit_cap) A.hit_ids[(int64_t)ray * A.hit_cap + nblend] = (int32_t)gid;
+        ++nblend;
+        if (T < A.T_min) ert = true;
+      }
+      const bool full = last != kEmptyKey;
+      const bool done = ert || !full || (ckpt && !overflow && ndst_n == 0 && edst_n == 0);
+      if (done) {
+        A.rgb[3 * (int64_t)ray + 0] = C0 + T * A.bg0;
+        A.rgb[3 * (int64_t)ray + 1] = C1 + T * A.bg1;
+        A.rgb[3 * (int64_t)ray + 2] = C2 + T * A.bg2;
+        A.depth[ray] = Dp;
+        A.opac[ray] = 1.f - T;
+        if (A.hit_counts) A.hit_counts[ray] = nblend;
+        if (A.stats) {
+          s_stat[GRTX_STAT_BLENDED][tid] = (uint32_t)nblend;
+          uint32_t* st = A.stats + (int64_t)ray * GRTX_STATS_FIELDS;
+#pragma unroll
+          for (int f = 0; f < GRTX_STATS_FIELDS; ++f) st[f] = s_stat[f][tid];
+        }
+        state = kIdle;
+      } else {
+        tmin = last;
+        kbuf_reset(kb, A.k);
+        if (!ckpt || overflow) {
+          // restart from the root beyond the last blended hit
+          if (ckpt) STAT(GRTX_STAT_FALLBACKS);
+          overflow = false;
+          nsrc_n = nsrc_i = ndst_n = 0;
+          esrc_n = esrc_i = edst_n = 0;
+          root_start();
+        } else {
+          // resume: this round's destination lists become the next round's sources
+          par ^= 1;
+          nsrc_n = ndst_n;
+          nsrc_i = 0;
+          ndst_n = 0;
+          esrc_n = edst_n;
+          esrc_i = 0;
+          edst_n = 0;
+          has_cur = false;
+          sp = 0;
+        }
+        state = kTrav;
+      }
+    }
+  }
+#undef ROW
+#undef STAT
+}
+
+__global__ void k_reset_counter(unsigned int* c) { *c = 0u; }
+
+__global__ void __launch_bounds__(256) k_fill_background(float* rgb, float* depth, float* opac, uint32_t* stats,
+                                                         int32_t* hit_counts, int64_t n, float b0, float b1,
+                                                         float b2) {
+  int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
+  if (i >= n) return;
+  rgb[3 * i] = b0;
+  rgb[3 * i + 1] = b1;
+  rgb[3 * i + 2] = b2;
+  depth[i] = 0.f;
+  opac[i] = 0.f;
+  if (hit_counts) hit_counts[i] = 0;
+  if (stats)
+    for (int f = 0; f < GRTX_STATS_FIELDS; ++f) stats[i * GRTX_STATS_FIELDS + f] = 0u;
+}
+
+// ------------------------------------------------------------------ per-stream pools
+
+struct Pool {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  unsigned int* counter = nullptr;
+};
+
+std::mutex g_pool_lock;
+std::map<std::pair<int, hipStream_t>, Pool> g_pools;
+
+template <int K>
+grtx_status launch(const TraceArgs& a, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_trace<K>, dim3(blocks), dim3(kTraceBlock), 0, s, a);
+  GRTX_LAUNCH_CHECK();
+  return GRTX_OK;
+}
+
+template <int K>
+int blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<K>, kTraceBlock, 0) != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+
+}  // namespace
+
+grtx_status trace(const Bvh* b, const grtx_rays* r, const grtx_trace_params* p, const grtx_trace_outputs* o,
+                  hipStream_t s) {
+  const int64_t R = r->count;
+  if (R == 0) return GRTX_OK;
+  if (b->n_leaves == 0) {
+    hipLaunchKernelGGL(k_fill_background, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, o->rgb, o->depth,
+                       o->opacity, o->stats, o->hit_counts, R, p->bg[0], p->bg[1], p->bg[2]);
+    GRTX_LAUNCH_CHECK();
+    return GRTX_OK;
+  }
+  int device = 0;
+  GRTX_HIP(hipGetDevice(&device));
+  hipDeviceProp_t prop;
+  static thread_local int cached_dev = -1;
+  static thread_local int cached_cus = 0;
+  if (cached_dev != device) {
+    GRTX_HIP(hipGetDeviceProperties(&prop, device));
+    cached_dev = device;
+    cached_cus = prop.multiProcessorCount;
+  }
+  const int K = p->k <= 4 ? 4 : p->k <= 8 ? 8 : p->k <= 16 ? 16 : p->k <= 32 ? 32 : 64;
+  int bpc = K == 4 ? blocks_per_cu<4>() : K == 8 ? blocks_per_cu<8>() : K == 16 ? blocks_per_cu<16>()
+          : K == 32 ? blocks_per_cu<32>() : blocks_per_cu<64>();
+  int blocks = cached_cus * bpc;
+  // never more waves than rays need
+  int64_t need_blocks = (R + kTraceBlock - 1) / kTraceBlock;
+  if (blocks > need_blocks) blocks = (int)std::max<int64_t>(1, need_blocks);
+
+  const int cap_d = p->defer_capacity > 0 ? p->defer_capacity : 128;
+  const int cap_e = p->evict_capacity > 0 ? p->evict_capacity : 128;
+  const int64_t rows = kSpillRows + 2 * (int64_t)cap_d + 2 * (int64_t)cap_e + K;
+  const size_t need = (size_t)blocks * kWaves * rows * 64 * sizeof(uint2) + 256;
+
+  Pool* pool = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_pool_lock);
+    pool = &g_pools[{device, s}];
+    if (pool->bytes < need) {
+      if (pool->ptr) GRTX_HIP(hipFreeAsync(pool->ptr, s));
+      pool->ptr = nullptr;
+      pool->bytes = 0;
+      size_t want = need + need / 4;
+      GRTX_HIP(hipMallocAsync(&pool->ptr, want, s));
+      pool->bytes = want;
+      pool->counter = reinterpret_cast<unsigned int*>(pool->ptr);
+    }
+  }
+
+  TraceArgs a{};
+  a.nodes = b->nodes;
+  a.inst = b->inst;
+  a.sh = b->sh;
+  a.root_box = b->root_box;
+  a.root_ref = b->n_leaves == 1 ? (kLeafFlag | 0u) : 0u;
+  a.sh_degree = b->sh_degree;
+  a.ray_o = r->origins;
+  a.ray_d = r->dirs;
+  a.n_rays = R;
+  a.t_near = r->t_near;
+  if (r->image_width > 0 && R % r->image_width == 0) {
+    a.image_w = r->image_width;
+    a.image_h = (int)(R / r->image_width);
+    a.tiles_x = (a.image_w + 7) / 8;
+    int64_t tiles_y = (a.image_h + 7) / 8;
+    a.n_work = (int64_t)a.tiles_x * tiles_y * 64;
+  } else {
+    a.image_w = 0;
+    a.image_h = 0;
+    a.tiles_x = 0;
+    a.n_work = R;
+  }
+  a.k = p->k;
+  a.T_min = p->T_min;
+  a.mode = p->mode;
+  a.bg0 = p->bg[0];
+  a.bg1 = p->bg[1];
+  a.bg2 = p->bg[2];
+  a.rgb = o->rgb;
+  a.depth = o->depth;
+  a.opac = o->opacity;
+  a.stats = o->stats;
+  a.hit_ids = o->hit_ids;
+  a.hit_counts = o->hit_counts;
+  a.hit_cap = o->hit_ids ? o->hit_capacity : 0;
+  a.counter = pool->counter;
+  a.pool = reinterpret_cast<uint2*>(reinterpret_cast<char*>(pool->ptr) + 256);
+  a.rows_per_wave = rows;
+  a.cap_d = cap_d;
+  a.cap_e = cap_e;
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, pool->counter);
+  switch (K) {
+    case 4: return launch<4>(a, blocks, s);
+    case 8: return launch<8>(a, blocks, s);
+    case 16: return launch<16>(a, blocks, s);
+    case 32: return launch<32>(a, blocks, s);
+    default: return launch<64>(a, blocks, s);
+  }
+}
+
+}  // namespace grtx

@@ -1,0 +1,242 @@
+"""Python binding of libgrtx.so (include/grtx.h): argument marshalling only.
+
+Every computation runs in the HIP library. PyTorch supplies device memory and the
+current HIP stream; tensors are passed to the C ABI as raw device pointers. If the
+library is not built the import of this module still works, but every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgrtx.so")
+
+OK = 0
+ERR_INVALID_ARG = 1
+ERR_OUT_OF_MEMORY = 2
+ERR_DEVICE = 3
+ERR_CAPACITY = 4
+ERR_NOT_READY = 5
+ERR_INTERNAL = 6
+
+SPHERE_INSTANCE = 0
+PROXY20 = 1
+CHECKPOINT = 0
+RESTART = 1
+
+STAT_NODES, STAT_LEAVES, STAT_ROUNDS, STAT_BLENDED, STAT_DEFERRED, STAT_FETCH_FREE, STAT_EVICTED, \
+    STAT_FALLBACKS = range(8)
+STATS_FIELDS = 8
+
+
+class GrtxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"grtx status {status}: {msg}")
+        self.status = status
+
+
+class _Gaussians(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p), ("opacities", C.c_void_p),
+                ("sh", C.c_void_p), ("count", C.c_int64), ("sh_degree", C.c_int32), ("reserved", C.c_int32)]
+
+
+class _BuildParams(C.Structure):
+    _fields_ = [("alpha_min", C.c_float), ("reserved", C.c_int32 * 3)]
+
+
+class _BvhInfo(C.Structure):
+    _fields_ = [("gaussians", C.c_int64), ("leaves", C.c_int64), ("internal_nodes", C.c_int64),
+                ("device_bytes", C.c_int64), ("kind", C.c_int32), ("sh_degree", C.c_int32),
+                ("alpha_min", C.c_float), ("root_lo", C.c_float * 3), ("root_hi", C.c_float * 3)]
+
+
+class _Rays(C.Structure):
+    _fields_ = [("origins", C.c_void_p), ("dirs", C.c_void_p), ("count", C.c_int64), ("t_near", C.c_float),
+                ("image_width", C.c_int32)]
+
+
+class _TraceParams(C.Structure):
+    _fields_ = [("k", C.c_int32), ("T_min", C.c_float), ("mode", C.c_int32), ("bg", C.c_float * 3),
+                ("defer_capacity", C.c_int32), ("evict_capacity", C.c_int32)]
+
+
+class _TraceOutputs(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p), ("opacity", C.c_void_p), ("stats", C.c_void_p),
+                ("hit_ids", C.c_void_p), ("hit_counts", C.c_void_p), ("hit_capacity", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class _Camera(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("target", C.c_float * 3), ("up", C.c_float * 3), ("fov_y_deg", C.c_float),
+                ("width", C.c_int32), ("height", C.c_int32)]
+
+
+# Every symbol the header declares, with its ctypes signature.
+_SIGNATURES = {
+    "grtx_build": (C.c_int, [C.POINTER(_Gaussians), C.c_int, C.POINTER(_BuildParams), C.c_void_p,
+                             C.POINTER(C.c_void_p)]),
+    "grtx_bvh_get_info": (C.c_int, [C.c_void_p, C.POINTER(_BvhInfo)]),
+    "grtx_bvh_export_topology": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.c_void_p]),
+    "grtx_bvh_destroy": (C.c_int, [C.c_void_p]),
+    "grtx_pinhole_rays": (C.c_int, [C.POINTER(_Camera), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "grtx_trace": (C.c_int, [C.c_void_p, C.POINTER(_Rays), C.POINTER(_TraceParams), C.POINTER(_TraceOutputs),
+                             C.c_void_p]),
+    "grtx_last_error": (C.c_char_p, []),
+    "grtx_version": (C.c_int32, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libgrtx.so. Raises if the library has not been built: there is no fallback."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2601_20429_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != OK:
+        raise GrtxError(status, lib().grtx_last_error().decode(errors="replace"))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_f32(x, device):
+    t = torch.as_tensor(x, dtype=torch.float32, device=device)
+    return t.contiguous()
+
+
+@dataclass
+class SceneTensors:
+    means: torch.Tensor
+    scales: torch.Tensor
+    quats: torch.Tensor
+    opacities: torch.Tensor
+    sh: torch.Tensor
+    sh_degree: int
+
+    @staticmethod
+    def from_scene(scene, device="cuda"):
+        return SceneTensors(_dev_f32(scene.means, device), _dev_f32(scene.scales, device),
+                            _dev_f32(scene.quats, device), _dev_f32(scene.opacities, device),
+                            _dev_f32(scene.sh, device).reshape(scene.n, (int(scene.sh_degree) + 1) ** 2, 3),
+                            int(scene.sh_degree))
+
+    @property
+    def n(self):
+        return int(self.means.shape[0])
+
+
+class Bvh:
+    """Owner of a grtx_bvh handle. Keeps the borrowed scene tensors alive."""
+
+    def __init__(self, handle, scene: SceneTensors, kind: int, alpha_min: float):
+        self.handle = handle
+        self.scene = scene
+        self.kind = kind
+        self.alpha_min = alpha_min
+
+    def close(self):
+        if self.handle:
+            _check(lib().grtx_bvh_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().grtx_bvh_destroy(self.handle)
+        except Exception:
+            pass
+
+    def info(self):
+        inf = _BvhInfo()
+        _check(lib().grtx_bvh_get_info(self.handle, C.byref(inf)))
+        return dict(gaussians=inf.gaussians, leaves=inf.leaves, internal_nodes=inf.internal_nodes,
+                    device_bytes=inf.device_bytes, kind=inf.kind, sh_degree=inf.sh_degree,
+                    alpha_min=inf.alpha_min, root_lo=list(inf.root_lo), root_hi=list(inf.root_hi))
+
+    def export_topology(self, stream=None):
+        inf = self.info()
+        n, m = inf["leaves"], inf["internal_nodes"]
+        dev = self.scene.means.device
+        child = torch.empty((max(m, 1), 2), dtype=torch.int32, device=dev)
+        parent = torch.empty(max(m + n, 1), dtype=torch.int32, device=dev)
+        morton = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+        perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        boxes = torch.empty((max(m + n, 1), 6), dtype=torch.float32, device=dev)
+        _check(lib().grtx_bvh_export_topology(self.handle, _ptr(child), _ptr(parent), _ptr(morton), _ptr(perm),
+                                              _ptr(boxes), _stream(stream)))
+        return dict(child=child[:m], parent=parent[:m + n], morton=morton[:n], perm=perm[:n], boxes=boxes[:m + n])
+
+
+def build(scene: SceneTensors, kind: int = SPHERE_INSTANCE, alpha_min: float = 1.0 / 255.0, stream=None) -> Bvh:
+    g = _Gaussians(scene.means.data_ptr(), scene.scales.data_ptr(), scene.quats.data_ptr(),
+                   scene.opacities.data_ptr(), scene.sh.data_ptr(), scene.n, scene.sh_degree, 0)
+    p = _BuildParams(alpha_min)
+    h = C.c_void_p()
+    _check(lib().grtx_build(C.byref(g), kind, C.byref(p), _stream(stream), C.byref(h)))
+    return Bvh(h, scene, kind, alpha_min)
+
+
+def pinhole_rays(camera, device="cuda", stream=None):
+    n = camera.width * camera.height
+    o = torch.empty((n, 3), dtype=torch.float32, device=device)
+    d = torch.empty((n, 3), dtype=torch.float32, device=device)
+    cam = _Camera((C.c_float * 3)(*camera.eye), (C.c_float * 3)(*camera.target), (C.c_float * 3)(*camera.up),
+                  camera.fov_y_deg, camera.width, camera.height)
+    _check(lib().grtx_pinhole_rays(C.byref(cam), _ptr(o), _ptr(d), _stream(stream)))
+    return o, d
+
+
+def trace(bvh: Bvh, origins: torch.Tensor, dirs: torch.Tensor, k: int = 16, T_min: float = 1e-3,
+          mode: int = CHECKPOINT, bg=(0.0, 0.0, 0.0), t_near: float = 0.0, image_width: int = 0,
+          stats: bool = False, hit_capacity: int = 0, defer_capacity: int = 0, evict_capacity: int = 0,
+          out=None, stream=None):
+    """Render rays; returns dict(rgb [R,3], depth [R], opacity [R], and optionally stats
+    [R,8] int32, hit_ids [R,cap] int32, hit_counts [R] int32)."""
+    R = int(origins.shape[0])
+    dev = origins.device
+    if out is None:
+        out = dict(rgb=torch.empty((R, 3), dtype=torch.float32, device=dev),
+                   depth=torch.empty(R, dtype=torch.float32, device=dev),
+                   opacity=torch.empty(R, dtype=torch.float32, device=dev))
+        if stats:
+            out["stats"] = torch.empty((R, STATS_FIELDS), dtype=torch.int32, device=dev)
+        if hit_capacity > 0:
+            out["hit_ids"] = torch.full((R, hit_capacity), -1, dtype=torch.int32, device=dev)
+            out["hit_counts"] = torch.empty(R, dtype=torch.int32, device=dev)
+    rays = _Rays(origins.data_ptr() if R else None, dirs.data_ptr() if R else None, R, t_near, image_width)
+    prm = _TraceParams(k, T_min, mode, (C.c_float * 3)(*bg), defer_capacity, evict_capacity)
+    o = _TraceOutputs(out["rgb"].data_ptr() if R else None, out["depth"].data_ptr() if R else None,
+                      out["opacity"].data_ptr() if R else None,
+                      out["stats"].data_ptr() if "stats" in out and R else None,
+                      out["hit_ids"].data_ptr() if "hit_ids" in out and R else None,
+                      out["hit_counts"].data_ptr() if "hit_counts" in out and R else None,
+                      int(out["hit_ids"].shape[1]) if "hit_ids" in out else 0, 0)
+    _check(lib().grtx_trace(bvh.handle, C.byref(rays), C.byref(prm), C.byref(o), _stream(stream)))
+    return out
+
+
+def version():
+    return int(lib().grtx_version())

@@ -1,0 +1,74 @@
+"""The C-ABI library loads and exports every symbol the header declares; host-side
+argument validation rejects bad calls before touching a device (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2601_20429_amd import grtx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "grtx.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(grtx_[a-z_0-9]+)\s*\(", src, flags=re.M)))
+
+
+def test_header_symbols_exported():
+    names = _declared_functions()
+    assert "grtx_trace" in names and "grtx_build" in names
+    L = C.CDLL(grtx.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    # the binding knows every declared function
+    assert set(names) <= set(grtx._SIGNATURES), set(names) - set(grtx._SIGNATURES)
+
+
+def test_version_and_null_destroy():
+    L = grtx.lib()
+    assert L.grtx_version() == 1
+    assert L.grtx_bvh_destroy(None) == grtx.OK
+
+
+def test_build_rejects_bad_arguments():
+    L = grtx.lib()
+    h = C.c_void_p()
+    p = grtx._BuildParams(1.0 / 255.0)
+    assert L.grtx_build(None, 0, C.byref(p), None, C.byref(h)) == grtx.ERR_INVALID_ARG
+    assert b"null" in L.grtx_last_error()
+    g = grtx._Gaussians(None, None, None, None, None, 10, 0, 0)
+    assert L.grtx_build(C.byref(g), 0, C.byref(p), None, C.byref(h)) == grtx.ERR_INVALID_ARG
+    g = grtx._Gaussians(None, None, None, None, None, 0, 4, 0)
+    assert L.grtx_build(C.byref(g), 0, C.byref(p), None, C.byref(h)) == grtx.ERR_INVALID_ARG
+    assert b"sh_degree" in L.grtx_last_error()
+    g = grtx._Gaussians(None, None, None, None, None, 0, 0, 0)
+    bad = grtx._BuildParams(1.5)
+    assert L.grtx_build(C.byref(g), 0, C.byref(bad), None, C.byref(h)) == grtx.ERR_INVALID_ARG
+    assert L.grtx_build(C.byref(g), 7, C.byref(p), None, C.byref(h)) == grtx.ERR_INVALID_ARG
+    assert h.value is None  # out-param untouched
+
+
+def test_trace_rejects_bad_arguments():
+    L = grtx.lib()
+    fake = C.c_void_p(1)  # never dereferenced: validation fails first
+    rays = grtx._Rays(None, None, 4, 0.0, 0)
+    out = grtx._TraceOutputs(None, None, None, None, None, None, 0, 0)
+    for k, T, mode, tn in [(0, 1e-3, 0, 0.0), (65, 1e-3, 0, 0.0), (4, 1.0, 0, 0.0), (4, 1e-3, 2, 0.0),
+                           (4, 1e-3, 0, -1.0)]:
+        rays.t_near = tn
+        prm = grtx._TraceParams(k, T, mode, (C.c_float * 3)(0, 0, 0), 0, 0)
+        assert L.grtx_trace(fake, C.byref(rays), C.byref(prm), C.byref(out), None) == grtx.ERR_INVALID_ARG
+    rays.t_near = 0.0
+    prm = grtx._TraceParams(4, 1e-3, 0, (C.c_float * 3)(0, 0, 0), 0, 0)
+    assert L.grtx_trace(fake, C.byref(rays), C.byref(prm), C.byref(out), None) == grtx.ERR_INVALID_ARG
+    assert b"null" in L.grtx_last_error()
+    cam = grtx._Camera((C.c_float * 3)(0, -3, 0), (C.c_float * 3)(0, 0, 0), (C.c_float * 3)(0, 0, 1), 60.0, 0, 4)
+    assert L.grtx_pinhole_rays(C.byref(cam), C.c_void_p(1), C.c_void_p(1), None) == grtx.ERR_INVALID_ARG
+
+
+def test_binding_raises_on_error():
+    with pytest.raises(grtx.GrtxError):
+        grtx._check(grtx.ERR_INVALID_ARG)
