@@ -207,6 +207,32 @@ grtx_status grtx_pinhole_rays(const grtx_camera* cam, float* origins, float* dir
 grtx_status grtx_trace(const grtx_bvh* bvh, const grtx_rays* rays, const grtx_trace_params* p,
                        const grtx_trace_outputs* out, void* stream);
 
+/* Gradients of the Gaussian parameters, caller-owned DEVICE arrays shaped like the inputs
+ * of grtx_gaussians (means [N,3], scales [N,3], quats [N,4], opacities [N],
+ * sh [N,(L+1)^2,3]). grtx_trace_backward ADDS into them (it never zeroes). */
+typedef struct grtx_gaussian_grads {
+  float* means;
+  float* scales;
+  float* quats;
+  float* opacities;
+  float* sh;
+} grtx_gaussian_grads;
+
+/* Backward of grtx_trace (differentiation of Eq. 1 with Eq. 2 alphas and SH colours;
+ * the paper's method is forward-only). `g` must be the parameters `bvh` was built from
+ * and `rays`/`p` those of the forward call. `fwd` holds the forward outputs: rgb, depth,
+ * opacity, hit_ids and hit_counts are required (the forward must have been run with a
+ * hit-id list). grad_rgb [R,3] is dL/drgb; grad_depth [R] and grad_opacity [R] are
+ * optional (NULL = zero). For each ray the blended hits are replayed in order and the
+ * gradient contributions are added to `grads` with FP32 atomics (so the summation order,
+ * and the last bits, vary between runs). Rays with more blended hits than the list holds
+ * contribute only their first hit_capacity hits; their number is written to the optional
+ * device counter `truncated_rays` (uint32, may be NULL). Enqueued on `stream`. */
+grtx_status grtx_trace_backward(const grtx_bvh* bvh, const grtx_gaussians* g, const grtx_rays* rays,
+                                const grtx_trace_params* p, const grtx_trace_outputs* fwd, const float* grad_rgb,
+                                const float* grad_depth, const float* grad_opacity, const grtx_gaussian_grads* grads,
+                                uint32_t* truncated_rays, void* stream);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char* grtx_last_error(void);
 

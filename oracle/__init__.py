@@ -50,17 +50,17 @@ def lib():
             f, d, i32, i64, u32, u64 = C.c_float, C.c_double, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64
             PF, PD = C.POINTER(f), C.POINTER(d)
             L.oracle_render.restype = C.c_int
-            L.oracle_render.argtypes = [PF, PF, PF, PF, PF, i64, C.c_int, i64, PF, PF, d, d, d, PD, C.c_int,
+            L.oracle_render.argtypes = [PD, PD, PD, PD, PD, i64, C.c_int, i64, PD, PD, d, d, d, PD, C.c_int,
                                         PD, PD, PD, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), PD, PD,
                                         C.c_int, C.c_int]
             L.oracle_ray_hits.restype = i64
-            L.oracle_ray_hits.argtypes = [PF, PF, PF, PF, i64, PF, PF, d, d, C.c_int, C.POINTER(i64), PD, PD,
+            L.oracle_ray_hits.argtypes = [PD, PD, PD, PD, i64, PD, PD, d, d, C.c_int, C.POINTER(i64), PD, PD,
                                           PD, i64]
             L.oracle_composite_list.restype = C.c_int
-            L.oracle_composite_list.argtypes = [PF, PF, PF, PF, PF, i64, C.c_int, PF, PF, C.POINTER(i32), i64,
+            L.oracle_composite_list.argtypes = [PD, PD, PD, PD, PD, i64, C.c_int, PD, PD, C.POINTER(i32), i64,
                                                 d, PD, PD, PD, PD]
             L.oracle_gaussian_aabb.restype = C.c_int
-            L.oracle_gaussian_aabb.argtypes = [PF, PF, PF, PF, i64, d, PD, PD, C.POINTER(i32)]
+            L.oracle_gaussian_aabb.argtypes = [PD, PD, PD, PD, i64, d, PD, PD, C.POINTER(i32)]
             L.oracle_pinhole_rays.restype = C.c_int
             L.oracle_pinhole_rays.argtypes = [PD, PD, PD, d, C.c_int, C.c_int, PD, PD]
             L.oracle_morton.restype = C.c_int
@@ -80,14 +80,20 @@ def _f32(a):
     return np.ascontiguousarray(a, dtype=np.float32)
 
 
+def _f64(a):
+    """Widen to FP64 (exact for float32 inputs; FP64 inputs pass through)."""
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
 def _scene_args(scene):
-    return (_f32(scene.means), _f32(scene.scales), _f32(scene.quats), _f32(scene.opacities),
-            _f32(scene.sh.reshape(scene.n, -1)) if scene.sh is not None else None)
+    return (_f64(scene.means), _f64(scene.scales), _f64(scene.quats), _f64(scene.opacities),
+            _f64(scene.sh.reshape(scene.n, -1)) if scene.sh is not None else None)
 
 
 def render(scene, origins, dirs, alpha_min=1.0 / 255.0, T_min=1e-3, t_near=0.0, bg=(0.0, 0.0, 0.0),
            key_mode=0, cap=0, nthreads=None):
-    """Brute-force render of the given float32 rays (Eq. 1, Eq. 2, Sec. III-A).
+    """Brute-force FP64 render of the given rays (Eq. 1, Eq. 2, Sec. III-A). Scene and rays
+    are taken as given (float32 values are widened exactly; FP64 values are used as is).
 
     key_mode 0 orders hits by ellipsoid entry distance, 1 by bounding-icosahedron entry
     distance. With cap > 0 also returns, per ray, the first `cap` blended ids, the
@@ -95,8 +101,8 @@ def render(scene, origins, dirs, alpha_min=1.0 / 255.0, T_min=1e-3, t_near=0.0, 
     L = lib()
     if nthreads is None:
         nthreads = min(16, os.cpu_count() or 1)
-    o = _f32(origins).reshape(-1, 3)
-    d = _f32(dirs).reshape(-1, 3)
+    o = _f64(origins).reshape(-1, 3)
+    d = _f64(dirs).reshape(-1, 3)
     R = o.shape[0]
     m, s, q, op, sh = _scene_args(scene)
     rgb = np.zeros((R, 3), np.float64)
@@ -108,8 +114,8 @@ def render(scene, origins, dirs, alpha_min=1.0 / 255.0, T_min=1e-3, t_near=0.0, 
     tafter = np.zeros((R, max(cap, 1)), np.float64) if cap > 0 else None
     tkey = np.zeros((R, max(cap, 1)), np.float64) if cap > 0 else None
     bga = np.asarray(bg, np.float64)
-    rc = L.oracle_render(_p(m, C.c_float), _p(s, C.c_float), _p(q, C.c_float), _p(op, C.c_float),
-                         _p(sh, C.c_float), scene.n, scene.sh_degree, R, _p(o, C.c_float), _p(d, C.c_float),
+    rc = L.oracle_render(_p(m, C.c_double), _p(s, C.c_double), _p(q, C.c_double), _p(op, C.c_double),
+                         _p(sh, C.c_double), scene.n, scene.sh_degree, R, _p(o, C.c_double), _p(d, C.c_double),
                          alpha_min, T_min, t_near, _p(bga, C.c_double), key_mode,
                          _p(rgb, C.c_double), _p(depth, C.c_double), _p(opac, C.c_double),
                          _p(nblend, C.c_int32), _p(nhits, C.c_int32), _p(ids, C.c_int32),
@@ -126,15 +132,15 @@ def ray_hits(scene, origin, direction, alpha_min=1.0 / 255.0, t_near=0.0, key_mo
     """All hits of one ray sorted by (key distance, id): ids, key, alpha, t_alpha."""
     L = lib()
     m, s, q, op, _ = _scene_args(scene)
-    o = _f32(origin).reshape(3)
-    d = _f32(direction).reshape(3)
+    o = _f64(origin).reshape(3)
+    d = _f64(direction).reshape(3)
     cap = scene.n
     ids = np.zeros(max(cap, 1), np.int64)
     tk = np.zeros(max(cap, 1), np.float64)
     al = np.zeros(max(cap, 1), np.float64)
     ta = np.zeros(max(cap, 1), np.float64)
-    nh = L.oracle_ray_hits(_p(m, C.c_float), _p(s, C.c_float), _p(q, C.c_float), _p(op, C.c_float), scene.n,
-                           _p(o, C.c_float), _p(d, C.c_float), alpha_min, t_near, key_mode,
+    nh = L.oracle_ray_hits(_p(m, C.c_double), _p(s, C.c_double), _p(q, C.c_double), _p(op, C.c_double), scene.n,
+                           _p(o, C.c_double), _p(d, C.c_double), alpha_min, t_near, key_mode,
                            _p(ids, C.c_int64), _p(tk, C.c_double), _p(al, C.c_double), _p(ta, C.c_double), cap)
     if nh < 0:
         raise RuntimeError("oracle_ray_hits failed")
@@ -145,15 +151,15 @@ def composite_list(scene, origin, direction, ids, alpha_min=1.0 / 255.0, bg=(0.0
     """Composite an explicit ordered id list along one ray (Eq. 1 with Eq. 2 alphas)."""
     L = lib()
     m, s, q, op, sh = _scene_args(scene)
-    o = _f32(origin).reshape(3)
-    d = _f32(direction).reshape(3)
+    o = _f64(origin).reshape(3)
+    d = _f64(direction).reshape(3)
     lst = np.ascontiguousarray(ids, np.int32)
     rgb = np.zeros(3, np.float64)
     dep = np.zeros(1, np.float64)
     opa = np.zeros(1, np.float64)
     bga = np.asarray(bg, np.float64)
-    rc = L.oracle_composite_list(_p(m, C.c_float), _p(s, C.c_float), _p(q, C.c_float), _p(op, C.c_float),
-                                 _p(sh, C.c_float), scene.n, scene.sh_degree, _p(o, C.c_float), _p(d, C.c_float),
+    rc = L.oracle_composite_list(_p(m, C.c_double), _p(s, C.c_double), _p(q, C.c_double), _p(op, C.c_double),
+                                 _p(sh, C.c_double), scene.n, scene.sh_degree, _p(o, C.c_double), _p(d, C.c_double),
                                  _p(lst, C.c_int32), lst.size, alpha_min, _p(bga, C.c_double),
                                  _p(rgb, C.c_double), _p(dep, C.c_double), _p(opa, C.c_double))
     if rc != 0:
@@ -168,7 +174,7 @@ def gaussian_aabb(scene, alpha_min=1.0 / 255.0):
     lo = np.zeros((scene.n, 3), np.float64)
     hi = np.zeros((scene.n, 3), np.float64)
     act = np.zeros(scene.n, np.int32)
-    L.oracle_gaussian_aabb(_p(m, C.c_float), _p(s, C.c_float), _p(q, C.c_float), _p(op, C.c_float), scene.n,
+    L.oracle_gaussian_aabb(_p(m, C.c_double), _p(s, C.c_double), _p(q, C.c_double), _p(op, C.c_double), scene.n,
                            alpha_min, _p(lo, C.c_double), _p(hi, C.c_double), _p(act, C.c_int32))
     return lo, hi, act.astype(bool)
 

@@ -51,7 +51,7 @@
 /* Small linear algebra                                                                  */
 /* ------------------------------------------------------------------------------------ */
 
-static void quat_to_rot(const float qf[4], double R[3][3]) {
+static void quat_to_rot(const double qf[4], double R[3][3]) {
   double w = qf[0], x = qf[1], y = qf[2], z = qf[3];
   double n = sqrt(w * w + x * x + y * y + z * z);
   w /= n; x /= n; y /= n; z /= n;
@@ -128,7 +128,7 @@ typedef struct {
 } og_t;
 
 typedef struct {
-  const float *means, *scales, *quats, *opac, *sh;
+  const double *means, *scales, *quats, *opac, *sh;
   int64_t n;
   int sh_degree;
 } scene_t;
@@ -307,7 +307,7 @@ static int line_meets_ellipsoid(const og_t *g, const double o[3], const double d
 
 static void sh_colour(const scene_t *s, int64_t i, const double d[3], double out[3]) {
   int K = (s->sh_degree + 1) * (s->sh_degree + 1);
-  const float *c = s->sh + (size_t)i * K * 3;
+  const double *c = s->sh + (size_t)i * K * 3;
   double acc[3] = {0.5, 0.5, 0.5};
   for (int l = 0; l <= s->sh_degree; ++l)
     for (int m = -l; m <= l; ++m) {
@@ -339,7 +339,7 @@ typedef struct {
   const scene_t *s;
   const og_t *g;
   const params_t *p;
-  const float *ro, *rd;
+  const double *ro, *rd;
   int64_t r0, r1;
   double *rgb, *depth, *opac;
   int32_t *nblend, *nhits;
@@ -425,13 +425,14 @@ static void free_all(og_t *g, int64_t n) {
   free(g);
 }
 
-/* Render R rays (float32 origins/directions, as given) against all Gaussians in FP64.
+/* Render R rays against all Gaussians in FP64 (inputs are FP64; the tests pass float32
+ * values widened exactly, or FP64 values for finite differences).
  * Outputs per ray: rgb[3], depth, opacity; optionally the number of blended hits, the
  * number of hits, and for the first `cap` blended hits their ids, the transmittance
  * after each and the sort-key distance. */
-int oracle_render(const float *means, const float *scales, const float *quats, const float *opac,
-                  const float *sh, int64_t n, int sh_degree,
-                  int64_t nrays, const float *ray_o, const float *ray_d,
+int oracle_render(const double *means, const double *scales, const double *quats, const double *opac,
+                  const double *sh, int64_t n, int sh_degree,
+                  int64_t nrays, const double *ray_o, const double *ray_d,
                   double alpha_min, double T_min, double t_near, const double *bg, int key_mode,
                   double *rgb, double *depth, double *opacity, int32_t *nblend, int32_t *nhits,
                   int32_t *ids, double *tafter, double *tkey, int cap, int nthreads) {
@@ -460,8 +461,8 @@ int oracle_render(const float *means, const float *scales, const float *quats, c
 
 /* All hits of one ray, sorted by (key, id): ids, key distance, alpha, t_alpha. Returns
  * the number of hits (entries beyond `cap` are not written). */
-int64_t oracle_ray_hits(const float *means, const float *scales, const float *quats, const float *opac,
-                        int64_t n, const float *ray_o, const float *ray_d, double alpha_min, double t_near,
+int64_t oracle_ray_hits(const double *means, const double *scales, const double *quats, const double *opac,
+                        int64_t n, const double *ray_o, const double *ray_d, double alpha_min, double t_near,
                         int key_mode, int64_t *ids, double *tkey, double *alpha, double *talpha, int64_t cap) {
   scene_t s = {means, scales, quats, opac, NULL, n, 0};
   og_t *g = prepare_all(&s, alpha_min, key_mode == 1);
@@ -496,8 +497,8 @@ int64_t oracle_ray_hits(const float *means, const float *scales, const float *qu
 
 /* Composite a given ordered id list along one ray (Eq. 1 with Eq. 2 alphas), without
  * any hit test and without early termination. */
-int oracle_composite_list(const float *means, const float *scales, const float *quats, const float *opac,
-                          const float *sh, int64_t n, int sh_degree, const float *ray_o, const float *ray_d,
+int oracle_composite_list(const double *means, const double *scales, const double *quats, const double *opac,
+                          const double *sh, int64_t n, int sh_degree, const double *ray_o, const double *ray_d,
                           const int32_t *list, int64_t len, double alpha_min, const double *bg,
                           double *rgb, double *depth, double *opacity) {
   scene_t s = {means, scales, quats, opac, sh, n, sh_degree};
@@ -525,7 +526,7 @@ int oracle_composite_list(const float *means, const float *scales, const float *
 /* Axis-aligned bounds of each Gaussian's bounding ellipsoid:
  * half-extent along axis j = sqrt(e_j^T Sigma e_j) * rho. Inactive Gaussians get
  * lo = hi = mu and active = 0. */
-int oracle_gaussian_aabb(const float *means, const float *scales, const float *quats, const float *opac,
+int oracle_gaussian_aabb(const double *means, const double *scales, const double *quats, const double *opac,
                          int64_t n, double alpha_min, double *lo, double *hi, int32_t *active) {
   for (int64_t i = 0; i < n; ++i) {
     double R[3][3];

@@ -145,4 +145,38 @@ grtx_status grtx_trace(const grtx_bvh* bvh, const grtx_rays* rays, const grtx_tr
   return grtx::trace(&bvh->impl, rays, p, out, static_cast<hipStream_t>(stream));
 }
 
+grtx_status grtx_trace_backward(const grtx_bvh* bvh, const grtx_gaussians* g, const grtx_rays* rays,
+                                const grtx_trace_params* p, const grtx_trace_outputs* fwd, const float* grad_rgb,
+                                const float* grad_depth, const float* grad_opacity, const grtx_gaussian_grads* grads,
+                                uint32_t* truncated_rays, void* stream) {
+  grtx::clear_error();
+  CHECK_ARG(bvh && g && rays && p && fwd && grads, "grtx_trace_backward: null argument");
+  CHECK_ARG(g->count == bvh->impl.n_gauss && g->sh_degree == bvh->impl.sh_degree,
+            "grtx_trace_backward: Gaussians differ from those the structure was built from");
+  CHECK_ARG(rays->count >= 0 && rays->count < ((int64_t)1 << 40), "grtx_trace_backward: bad ray count");
+  if (rays->count > 0 && g->count > 0) {
+    CHECK_ARG(g->means && g->scales && g->quats && g->opacities && g->sh, "grtx_trace_backward: null Gaussian array");
+    CHECK_ARG(rays->origins && rays->dirs, "grtx_trace_backward: null ray arrays");
+    CHECK_ARG(fwd->rgb && fwd->depth && fwd->opacity && fwd->hit_ids && fwd->hit_counts && fwd->hit_capacity > 0,
+              "grtx_trace_backward: the forward outputs need rgb, depth, opacity and a hit-id list");
+    CHECK_ARG(grad_rgb || grad_depth || grad_opacity, "grtx_trace_backward: no output gradient given");
+    CHECK_ARG(grads->means && grads->scales && grads->quats && grads->opacities && grads->sh,
+              "grtx_trace_backward: null gradient array");
+  }
+  static thread_local unsigned int* own = nullptr;
+  static thread_local int own_dev = -1;
+  unsigned int* tr = truncated_rays;
+  if (!tr) {
+    int dev = 0;
+    GRTX_HIP(hipGetDevice(&dev));
+    if (!own || own_dev != dev) {
+      GRTX_HIP(hipMalloc(&own, sizeof(unsigned int)));
+      own_dev = dev;
+    }
+    tr = own;
+  }
+  return grtx::trace_backward(g, rays, p, fwd, grad_rgb, grad_depth, grad_opacity, grads, tr,
+                              static_cast<hipStream_t>(stream));
+}
+
 }  // extern "C"

@@ -1,0 +1,275 @@
+// Backward pass of the Gaussian ray tracer for gfx950.
+//
+// The forward image of a ray is front-to-back compositing (Eq. 1) of its blended hits,
+// in blend order, with alpha at the point of maximum response (Eq. 2) and colour from
+// SH at the ray direction:
+//   C = sum_i T_i a_i c_i + T_N bg,   D = sum_i T_i a_i t_i,   O = 1 - T_N,
+//   T_i = prod_{j<i} (1 - a_j).
+// With S_i = sum_{j>i} T_j a_j c_j + T_N bg (everything behind hit i):
+//   dC/dc_i = T_i a_i,  dC/da_i = T_i c_i - S_i / (1 - a_i),
+//   dD/dt_i = T_i a_i,  dD/da_i = T_i t_i - (sum_{j>i} T_j a_j t_j) / (1 - a_i),
+//   dO/da_i = T_N / (1 - a_i).
+// The suffix sums come from the forward outputs (C, D, T_N) minus running prefix sums,
+// so one pass in blend order suffices. Per hit, with M = S^-1 R^T, f = o - mu,
+// u = M f, v = M d, t = -(u.v)/(v.v), p = u + t v (closest approach in the whitened
+// frame), m2 = |p|^2 and a = opacity * exp(-m2/2):
+//   dm2/du = 2p, dm2/dv = 2 t p, dt/du = -v/(v.v), dt/dv = -(u + 2 t v)/(v.v),
+//   dL/dM = g_u f^T + g_v d^T, dL/dmu = -M^T g_u, dL/ds_i = -(1/s_i) sum_j g_M[i][j] M[i][j],
+//   dL/dR[j][i] = g_M[i][j] / s_i, then through R(q/|q|) to q; dL/do = dL/da * a / o;
+//   dL/dsh[l,m,ch] = dL/dc_ch * [c_ch > 0] * Y_lm(d).
+// Each ray's contributions are added to the caller's gradient arrays with FP32 atomics.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "grtx_internal.h"
+
+namespace grtx {
+namespace {
+
+constexpr int kBlock = 128;
+
+constexpr double cx_sqrt(double x) {
+  double r = x > 1.0 ? x : 1.0;
+  for (int i = 0; i < 100; ++i) r = 0.5 * (r + x / r);
+  return r;
+}
+constexpr double kPi = 3.14159265358979323846;
+// K_l^m = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!)
+constexpr double Klm(int l, double fac_ratio) { return cx_sqrt((2.0 * l + 1.0) / (4.0 * kPi) * fac_ratio); }
+constexpr float B00 = (float)Klm(0, 1.0);
+constexpr float B1 = (float)Klm(1, 1.0);
+constexpr float B20 = (float)(Klm(2, 1.0) * 0.5);
+constexpr float B21 = (float)(cx_sqrt(2.0) * Klm(2, 1.0 / 6.0) * 3.0);
+constexpr float B22 = (float)(cx_sqrt(2.0) * Klm(2, 1.0 / 24.0) * 3.0);
+constexpr float B30 = (float)(Klm(3, 1.0) * 0.5);
+constexpr float B31 = (float)(cx_sqrt(2.0) * Klm(3, 1.0 / 12.0) * 0.5);
+constexpr float B32 = (float)(cx_sqrt(2.0) * Klm(3, 1.0 / 120.0) * 15.0);
+constexpr float B33 = (float)(cx_sqrt(2.0) * Klm(3, 1.0 / 720.0) * 15.0);
+
+// Real SH basis (orthonormal, Condon-Shortley phase) as polynomials of the unit direction.
+__device__ __forceinline__ void basis(float x, float y, float z, int L, float* Y) {
+  Y[0] = B00;
+  if (L < 1) return;
+  Y[1] = -B1 * y;
+  Y[2] = B1 * z;
+  Y[3] = -B1 * x;
+  if (L < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = B22 * 2.f * x * y;
+  Y[5] = -B21 * y * z;
+  Y[6] = B20 * (3.f * zz - 1.f);
+  Y[7] = -B21 * x * z;
+  Y[8] = B22 * (xx - yy);
+  if (L < 3) return;
+  Y[9] = -B33 * (3.f * xx * y - yy * y);
+  Y[10] = B32 * 2.f * x * y * z;
+  Y[11] = -B31 * y * (15.f * zz - 3.f);
+  Y[12] = B30 * (5.f * zz * z - 3.f * z);
+  Y[13] = -B31 * x * (15.f * zz - 3.f);
+  Y[14] = B32 * z * (xx - yy);
+  Y[15] = -B33 * (xx * x - 3.f * x * yy);
+}
+
+struct BwdArgs {
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opac;
+  const float* sh;
+  int sh_degree;
+  const float* ray_o;
+  const float* ray_d;
+  int64_t n_rays;
+  const float* rgb;
+  const float* depth;
+  const float* opacity;
+  const int32_t* hit_ids;
+  const int32_t* hit_counts;
+  int hit_cap;
+  float bg0, bg1, bg2;
+  const float* g_rgb;
+  const float* g_depth;
+  const float* g_opacity;
+  float* d_means;
+  float* d_scales;
+  float* d_quats;
+  float* d_opac;
+  float* d_sh;
+  unsigned int* truncated;
+};
+
+__global__ void __launch_bounds__(kBlock) k_backward(BwdArgs A) {
+  const int64_t r = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (r >= A.n_rays) return;
+  const float ox = A.ray_o[3 * r], oy = A.ray_o[3 * r + 1], oz = A.ray_o[3 * r + 2];
+  const float dx = A.ray_d[3 * r], dy = A.ray_d[3 * r + 1], dz = A.ray_d[3 * r + 2];
+  int n = A.hit_counts[r];
+  if (n > A.hit_cap) {
+    atomicAdd(A.truncated, 1u);
+    n = A.hit_cap;
+  }
+  if (n == 0) return;
+  const float TN = 1.f - A.opacity[r];
+  const float bg[3] = {A.bg0, A.bg1, A.bg2};
+  float Cf[3], gC[3];
+  for (int ch = 0; ch < 3; ++ch) {
+    Cf[ch] = A.rgb[3 * r + ch];  // includes T_N * bg
+    gC[ch] = A.g_rgb ? A.g_rgb[3 * r + ch] : 0.f;
+  }
+  const float Df = A.depth[r];
+  const float gD = A.g_depth ? A.g_depth[r] : 0.f;
+  const float gO = A.g_opacity ? A.g_opacity[r] : 0.f;
+  const float dn = rsqrtf(dx * dx + dy * dy + dz * dz);
+  float Y[16];
+  basis(dx * dn, dy * dn, dz * dn, A.sh_degree, Y);
+  const int ncoef = (A.sh_degree + 1) * (A.sh_degree + 1);
+
+  float T = 1.f, Cacc[3] = {0.f, 0.f, 0.f}, Dacc = 0.f;
+  for (int h = 0; h < n; ++h) {
+    const int64_t i = A.hit_ids[r * A.hit_cap + h];
+    // ---- recompute the hit
+    const float* q4 = A.quats + 4 * i;
+    const float qn = sqrtf(q4[0] * q4[0] + q4[1] * q4[1] + q4[2] * q4[2] + q4[3] * q4[3]);
+    const float w = q4[0] / qn, x = q4[1] / qn, y = q4[2] / qn, z = q4[3] / qn;
+    float R[3][3];
+    R[0][0] = 1.f - 2.f * (y * y + z * z); R[0][1] = 2.f * (x * y - w * z);       R[0][2] = 2.f * (x * z + w * y);
+    R[1][0] = 2.f * (x * y + w * z);       R[1][1] = 1.f - 2.f * (x * x + z * z); R[1][2] = 2.f * (y * z - w * x);
+    R[2][0] = 2.f * (x * z - w * y);       R[2][1] = 2.f * (y * z + w * x);       R[2][2] = 1.f - 2.f * (x * x + y * y);
+    const float s[3] = {A.scales[3 * i], A.scales[3 * i + 1], A.scales[3 * i + 2]};
+    float M[3][3];  // S^-1 R^T
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) M[a][b] = R[b][a] / s[a];
+    const float f[3] = {ox - A.means[3 * i], oy - A.means[3 * i + 1], oz - A.means[3 * i + 2]};
+    const float dv[3] = {dx, dy, dz};
+    float u[3], v[3];
+    for (int a = 0; a < 3; ++a) {
+      u[a] = M[a][0] * f[0] + M[a][1] * f[1] + M[a][2] * f[2];
+      v[a] = M[a][0] * dv[0] + M[a][1] * dv[1] + M[a][2] * dv[2];
+    }
+    const float vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const float uv = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+    const float ta = -uv / vv;
+    const float p[3] = {u[0] + ta * v[0], u[1] + ta * v[1], u[2] + ta * v[2]};
+    const float m2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+    const float o = A.opac[i];
+    const float G = expf(-0.5f * m2);
+    const float alpha = o * G;
+    float c[3];
+    bool pos[3];
+    const float* shp = A.sh + i * 3 * ncoef;
+    for (int ch = 0; ch < 3; ++ch) {
+      float acc = 0.5f;
+      for (int k = 0; k < 16; ++k)
+        if (k < ncoef) acc += Y[k] * shp[3 * k + ch];
+      pos[ch] = acc > 0.f;
+      c[ch] = pos[ch] ? acc : 0.f;
+    }
+    // ---- compositing derivatives
+    const float wgt = T * alpha;
+    for (int ch = 0; ch < 3; ++ch) Cacc[ch] += wgt * c[ch];
+    Dacc += wgt * ta;
+    const float inv1ma = 1.f / (1.f - alpha);
+    float gA = 0.f;
+    for (int ch = 0; ch < 3; ++ch) {
+      const float behind = Cf[ch] - Cacc[ch];  // S_i (includes T_N bg)
+      gA += gC[ch] * (T * c[ch] - behind * inv1ma);
+    }
+    gA += gD * (T * ta - (Df - Dacc) * inv1ma);
+    gA += gO * (TN * inv1ma);
+    const float gT = gD * wgt;  // dL/dt_alpha
+    T *= (1.f - alpha);
+    // ---- SH
+    for (int ch = 0; ch < 3; ++ch) {
+      if (!pos[ch] || gC[ch] == 0.f) continue;
+      const float gc = gC[ch] * wgt;
+      for (int k = 0; k < 16; ++k)
+        if (k < ncoef) atomicAdd(A.d_sh + i * 3 * ncoef + 3 * k + ch, gc * Y[k]);
+    }
+    (void)bg;
+    // ---- alpha -> opacity, m2
+    atomicAdd(A.d_opac + i, gA * G);
+    const float gm2 = gA * (-0.5f * alpha);
+    float gu[3], gv[3];
+    for (int a = 0; a < 3; ++a) {
+      gu[a] = gm2 * 2.f * p[a] - gT * v[a] / vv;
+      gv[a] = gm2 * 2.f * ta * p[a] - gT * (u[a] + 2.f * ta * v[a]) / vv;
+    }
+    // ---- u = M f, v = M d
+    float gM[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) gM[a][b] = gu[a] * f[b] + gv[a] * dv[b];
+    for (int b = 0; b < 3; ++b) {
+      const float gf = M[0][b] * gu[0] + M[1][b] * gu[1] + M[2][b] * gu[2];
+      atomicAdd(A.d_means + 3 * i + b, -gf);
+    }
+    float gR[3][3];
+    for (int a = 0; a < 3; ++a) {
+      float gs = 0.f;
+      for (int b = 0; b < 3; ++b) {
+        gs += gM[a][b] * M[a][b];
+        gR[b][a] = gM[a][b] / s[a];
+      }
+      atomicAdd(A.d_scales + 3 * i + a, -gs / s[a]);
+    }
+    // ---- R(qhat) -> qhat -> q
+    const float gw = 2.f * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2] - y * gR[2][0] + x * gR[2][1]);
+    const float gx = 2.f * (y * gR[0][1] + z * gR[0][2] + y * gR[1][0] - 2.f * x * gR[1][1] - w * gR[1][2] +
+                            z * gR[2][0] + w * gR[2][1] - 2.f * x * gR[2][2]);
+    const float gy = 2.f * (-2.f * y * gR[0][0] + x * gR[0][1] + w * gR[0][2] + x * gR[1][0] + z * gR[1][2] -
+                            w * gR[2][0] + z * gR[2][1] - 2.f * y * gR[2][2]);
+    const float gz = 2.f * (-2.f * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] - 2.f * z * gR[1][1] +
+                            y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
+    const float dot = w * gw + x * gx + y * gy + z * gz;
+    atomicAdd(A.d_quats + 4 * i + 0, (gw - w * dot) / qn);
+    atomicAdd(A.d_quats + 4 * i + 1, (gx - x * dot) / qn);
+    atomicAdd(A.d_quats + 4 * i + 2, (gy - y * dot) / qn);
+    atomicAdd(A.d_quats + 4 * i + 3, (gz - z * dot) / qn);
+  }
+}
+
+__global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
+
+}  // namespace
+
+grtx_status trace_backward(const grtx_gaussians* g, const grtx_rays* r, const grtx_trace_params* p,
+                           const grtx_trace_outputs* fwd, const float* grad_rgb, const float* grad_depth,
+                           const float* grad_opacity, const grtx_gaussian_grads* grads, unsigned int* truncated,
+                           hipStream_t s) {
+  const int64_t R = r->count;
+  if (R == 0 || g->count == 0) return GRTX_OK;
+  BwdArgs a{};
+  a.means = g->means;
+  a.scales = g->scales;
+  a.quats = g->quats;
+  a.opac = g->opacities;
+  a.sh = g->sh;
+  a.sh_degree = g->sh_degree;
+  a.ray_o = r->origins;
+  a.ray_d = r->dirs;
+  a.n_rays = R;
+  a.rgb = fwd->rgb;
+  a.depth = fwd->depth;
+  a.opacity = fwd->opacity;
+  a.hit_ids = fwd->hit_ids;
+  a.hit_counts = fwd->hit_counts;
+  a.hit_cap = fwd->hit_capacity;
+  a.bg0 = p->bg[0];
+  a.bg1 = p->bg[1];
+  a.bg2 = p->bg[2];
+  a.g_rgb = grad_rgb;
+  a.g_depth = grad_depth;
+  a.g_opacity = grad_opacity;
+  a.d_means = grads->means;
+  a.d_scales = grads->scales;
+  a.d_quats = grads->quats;
+  a.d_opac = grads->opacities;
+  a.d_sh = grads->sh;
+  a.truncated = truncated;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, truncated);
+  hipLaunchKernelGGL(k_backward, dim3((unsigned)((R + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a);
+  GRTX_LAUNCH_CHECK();
+  return GRTX_OK;
+}
+
+}  // namespace grtx

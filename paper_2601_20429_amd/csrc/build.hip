@@ -381,6 +381,86 @@ __global__ void __launch_bounds__(kBlock) k_sphere_leaves(GaussIn g, const uint3
   }
 }
 
+// ------------------------------------------------------------------ proxy mesh (baseline)
+
+// Regular icosahedron of inradius 1 (its faces touch the unit sphere from outside):
+// vertices and outward-wound faces, derived on the host from the definition.
+struct Ico {
+  float v[12][3];
+  unsigned char f[20][3];
+};
+
+// Instance record in Gaussian order (used by the proxy BVH's blending).
+__device__ __forceinline__ void write_instance(const GaussIn& g, uint32_t i, const GaussGeom& G, float alpha_min,
+                                               float4* __restrict__ dst) {
+  float r[16];
+  for (int a = 0; a < 3; ++a) {
+    float sc = G.active ? 1.f / (G.rho * G.s[a]) : 0.f;
+    r[4 * a + 0] = G.R[0][a] * sc;
+    r[4 * a + 1] = G.R[1][a] * sc;
+    r[4 * a + 2] = G.R[2][a] * sc;
+    r[4 * a + 3] = g.means[3 * i + a];
+  }
+  r[12] = G.o;
+  r[13] = G.active ? log2f(G.o / alpha_min) : 0.f;
+  r[14] = __uint_as_float(i);
+  r[15] = __uint_as_float(G.active ? 1u : 0u);
+  for (int q = 0; q < 4; ++q) dst[q] = make_float4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
+}
+
+// Relative and absolute padding of a triangle's box: the binary32 hit distance of a ray
+// crossing the triangle must stay inside the box's slab interval.
+constexpr float kTriPadRel = 1.0f / 1024.0f;
+constexpr float kTriPadAbs = 1.0f / 131072.0f;
+
+// One thread per Gaussian: instance record (Gaussian order), 20 world triangles
+// mu + R diag(rho s) v_ico with their boxes and box centres (triangle order 20 g + face).
+__global__ void __launch_bounds__(kBlock) k_proxy_setup(GaussIn g, int64_t n, float alpha_min, Ico ico,
+                                                        float4* __restrict__ inst, float4* __restrict__ tri,
+                                                        float* __restrict__ tbox, float* __restrict__ cent) {
+  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i >= n) return;
+  GaussGeom G = gauss_geom(g, i, alpha_min);
+  write_instance(g, (uint32_t)i, G, alpha_min, inst + 4 * i);
+  float w[12][3];
+  for (int v = 0; v < 12; ++v)
+    for (int a = 0; a < 3; ++a) {
+      float acc = 0.f;
+      for (int k = 0; k < 3; ++k) acc += G.R[a][k] * (G.rho * G.s[k] * ico.v[v][k]);
+      w[v][a] = g.means[3 * i + a] + acc;  // inactive: rho = 0, a point at mu
+    }
+  for (int f = 0; f < 20; ++f) {
+    const int64_t t = 20 * i + f;
+    const float* A = w[ico.f[f][0]];
+    const float* B = w[ico.f[f][1]];
+    const float* C = w[ico.f[f][2]];
+    tri[3 * t + 0] = make_float4(A[0], A[1], A[2], __uint_as_float((uint32_t)i));
+    tri[3 * t + 1] = make_float4(B[0], B[1], B[2], 0.f);
+    tri[3 * t + 2] = make_float4(C[0], C[1], C[2], 0.f);
+    for (int a = 0; a < 3; ++a) {
+      float lo = fminf(A[a], fminf(B[a], C[a]));
+      float hi = fmaxf(A[a], fmaxf(B[a], C[a]));
+      float pad = (hi - lo) * kTriPadRel + (fabsf(lo) + fabsf(hi)) * kTriPadAbs;
+      tbox[6 * t + a] = lo - pad;
+      tbox[6 * t + 3 + a] = hi + pad;
+      cent[3 * t + a] = 0.5f * (lo + hi);
+    }
+  }
+}
+
+// Gather triangle records and boxes into sorted-leaf order.
+__global__ void __launch_bounds__(kBlock) k_proxy_leaves(const uint32_t* __restrict__ perm, int64_t m,
+                                                         const float4* __restrict__ tri_in,
+                                                         const float* __restrict__ box_in,
+                                                         float4* __restrict__ tri_out, float* __restrict__ boxes) {
+  int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (p >= m) return;
+  uint32_t t = perm[p];
+  for (int q = 0; q < 3; ++q) tri_out[3 * p + q] = tri_in[3 * (int64_t)t + q];
+  float* bx = boxes + ((m - 1) + p) * 6;
+  for (int a = 0; a < 6; ++a) bx[a] = box_in[6 * (int64_t)t + a];
+}
+
 // ------------------------------------------------------------------ refit
 
 __device__ __forceinline__ float ld_coherent(const float* p) {
@@ -520,6 +600,56 @@ __global__ void __launch_bounds__(kBlock) k_fill_u32(uint32_t* p, int64_t n, uin
 }  // namespace
 
 // Build over `n` points (centroids) whose leaf boxes/records are produced by `leaves`.
+// Icosahedron of inradius 1, from its definition: the 12 points (0,+-1,+-phi) and their
+// cyclic permutations; faces are the vertex triples at mutual distance 2 (the edge), wound
+// so that (B-A) x (C-A) points away from the centre; scaled so face planes are at distance 1.
+static Ico make_icosahedron() {
+  const double phi = 0.5 * (1.0 + std::sqrt(5.0));
+  double v[12][3];
+  int nv = 0;
+  for (int sa = -1; sa <= 1; sa += 2)
+    for (int sb = -1; sb <= 1; sb += 2) {
+      const double p[3] = {0.0, (double)sa, sb * phi};
+      for (int rot = 0; rot < 3; ++rot) {
+        for (int a = 0; a < 3; ++a) v[nv][a] = p[(a + 3 - rot) % 3];
+        ++nv;
+      }
+    }
+  Ico ico{};
+  int nf = 0;
+  double inr = 0.0;
+  for (int i = 0; i < 12; ++i)
+    for (int j = i + 1; j < 12; ++j)
+      for (int k = j + 1; k < 12; ++k) {
+        auto d2 = [&](int x, int y) {
+          double s2 = 0.0;
+          for (int a = 0; a < 3; ++a) s2 += (v[x][a] - v[y][a]) * (v[x][a] - v[y][a]);
+          return s2;
+        };
+        if (std::fabs(d2(i, j) - 4.0) > 1e-9 || std::fabs(d2(j, k) - 4.0) > 1e-9 || std::fabs(d2(i, k) - 4.0) > 1e-9)
+          continue;
+        double e1[3], e2[3], nrm[3], cen = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          e1[a] = v[j][a] - v[i][a];
+          e2[a] = v[k][a] - v[i][a];
+        }
+        nrm[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        nrm[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        nrm[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        for (int a = 0; a < 3; ++a) cen += nrm[a] * v[i][a];
+        bool out = cen > 0.0;
+        ico.f[nf][0] = (unsigned char)i;
+        ico.f[nf][1] = (unsigned char)(out ? j : k);
+        ico.f[nf][2] = (unsigned char)(out ? k : j);
+        double nl = std::sqrt(nrm[0] * nrm[0] + nrm[1] * nrm[1] + nrm[2] * nrm[2]);
+        inr = std::fabs(cen) / nl;
+        ++nf;
+      }
+  for (int i = 0; i < 12; ++i)
+    for (int a = 0; a < 3; ++a) ico.v[i][a] = (float)(v[i][a] / inr);
+  return ico;
+}
+
 grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_min, hipStream_t s, Bvh* b) {
   b->kind = kind;
   b->n_gauss = g->count;
@@ -529,46 +659,60 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
   b->sh = g->sh;
   b->build_stream = s;
   GRTX_HIP(hipGetDevice(&b->device));
-  if (kind != GRTX_BVH_SPHERE_INSTANCE) {
-    set_error("bvh kind %d is not available in this build", (int)kind);
-    return GRTX_ERR_INVALID_ARG;
-  }
+  const bool proxy = kind == GRTX_BVH_PROXY20;
   const int64_t n = g->count;
-  b->n_leaves = n;
+  const int64_t m = proxy ? 20 * n : n;  // leaves
+  b->n_leaves = m;
   if (n == 0) return GRTX_OK;
   GaussIn gi{g->means, g->scales, g->quats, g->opacities};
-  const int64_t nint = n - 1;
-  GRTX_TRY(dalloc(b, &b->codes, n));
-  GRTX_TRY(dalloc(b, &b->perm, n));
+  const int64_t nint = m - 1;
+  GRTX_TRY(dalloc(b, &b->codes, m));
+  GRTX_TRY(dalloc(b, &b->perm, m));
   GRTX_TRY(dalloc(b, &b->child, 2 * std::max<int64_t>(nint, 1)));
-  GRTX_TRY(dalloc(b, &b->parent, 2 * n - 1));
-  GRTX_TRY(dalloc(b, &b->boxes, 6 * (2 * n - 1)));
+  GRTX_TRY(dalloc(b, &b->parent, 2 * m - 1));
+  GRTX_TRY(dalloc(b, &b->boxes, 6 * (2 * m - 1)));
   GRTX_TRY(dalloc(b, &b->nodes, 4 * std::max<int64_t>(nint, 1)));
   GRTX_TRY(dalloc(b, &b->inst, 4 * n));
-  b->root_box = b->boxes;  // node 0 (the root, or the only leaf when n == 1)
+  if (proxy) GRTX_TRY(dalloc(b, &b->tris, 3 * m));
+  b->root_box = b->boxes;  // node 0: the root, or the only leaf when m == 1
 
   Scratch sc{{}, s};
-  float *partial = nullptr, *bounds = nullptr;
+  float *partial = nullptr, *bounds = nullptr, *cent = nullptr, *tbox = nullptr;
+  float4* ttmp = nullptr;
   uint64_t* tkeys = nullptr;
   uint32_t *tvals = nullptr, *arrivals = nullptr;
-  int nparts = (int)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock);
+  int nparts = (int)std::min<int64_t>(1024, (m + kBlock - 1) / kBlock);
   GRTX_TRY(sc.get(&partial, 6 * nparts));
   GRTX_TRY(sc.get(&bounds, 6));
-  GRTX_TRY(sc.get(&tkeys, n));
-  GRTX_TRY(sc.get(&tvals, n));
+  GRTX_TRY(sc.get(&tkeys, m));
+  GRTX_TRY(sc.get(&tvals, m));
   GRTX_TRY(sc.get(&arrivals, std::max<int64_t>(nint, 1)));
-
-  hipLaunchKernelGGL(k_bounds_partial, dim3(nparts), dim3(kBlock), 0, s, g->means, n, partial);
+  const float* points = g->means;
+  if (proxy) {
+    GRTX_TRY(sc.get(&cent, 3 * m));
+    GRTX_TRY(sc.get(&tbox, 6 * m));
+    GRTX_TRY(sc.get(&ttmp, 3 * m));
+    static const Ico ico = make_icosahedron();
+    hipLaunchKernelGGL(k_proxy_setup, dim3(grid_for(n)), dim3(kBlock), 0, s, gi, n, alpha_min, ico, b->inst, ttmp,
+                       tbox, cent);
+    points = cent;
+  }
+  hipLaunchKernelGGL(k_bounds_partial, dim3(nparts), dim3(kBlock), 0, s, points, m, partial);
   hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(kBlock), 0, s, partial, nparts, bounds);
-  hipLaunchKernelGGL(k_morton, dim3(grid_for(n)), dim3(kBlock), 0, s, g->means, n, bounds, b->codes, b->perm);
+  hipLaunchKernelGGL(k_morton, dim3(grid_for(m)), dim3(kBlock), 0, s, points, m, bounds, b->codes, b->perm);
   GRTX_LAUNCH_CHECK();
-  GRTX_TRY(radix_sort(b->codes, b->perm, tkeys, tvals, n, sc, s));
-  hipLaunchKernelGGL(k_sphere_leaves, dim3(grid_for(n)), dim3(kBlock), 0, s, gi, b->perm, n, alpha_min, b->inst,
-                     b->boxes);
+  GRTX_TRY(radix_sort(b->codes, b->perm, tkeys, tvals, m, sc, s));
+  if (proxy) {
+    hipLaunchKernelGGL(k_proxy_leaves, dim3(grid_for(m)), dim3(kBlock), 0, s, b->perm, m, ttmp, tbox, b->tris,
+                       b->boxes);
+  } else {
+    hipLaunchKernelGGL(k_sphere_leaves, dim3(grid_for(m)), dim3(kBlock), 0, s, gi, b->perm, m, alpha_min, b->inst,
+                       b->boxes);
+  }
   if (nint > 0) {
-    hipLaunchKernelGGL(k_karras, dim3(grid_for(nint)), dim3(kBlock), 0, s, b->codes, n, b->child, b->parent);
+    hipLaunchKernelGGL(k_karras, dim3(grid_for(nint)), dim3(kBlock), 0, s, b->codes, m, b->child, b->parent);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nint)), dim3(kBlock), 0, s, arrivals, nint, 0u);
-    hipLaunchKernelGGL(k_refit, dim3(grid_for(n)), dim3(kBlock), 0, s, n, b->child, b->parent, b->boxes, arrivals,
+    hipLaunchKernelGGL(k_refit, dim3(grid_for(m)), dim3(kBlock), 0, s, m, b->child, b->parent, b->boxes, arrivals,
                        b->nodes);
   } else {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, s, b->parent, 1, kNoParent);

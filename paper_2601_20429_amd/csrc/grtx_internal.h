@@ -96,6 +96,10 @@ grtx_status export_topology(const Bvh* b, uint32_t* child, uint32_t* parent, uin
 grtx_status pinhole_rays(const grtx_camera* cam, float* origins, float* dirs, hipStream_t s);
 grtx_status trace(const Bvh* b, const grtx_rays* r, const grtx_trace_params* p, const grtx_trace_outputs* o,
                   hipStream_t s);
+grtx_status trace_backward(const grtx_gaussians* g, const grtx_rays* r, const grtx_trace_params* p,
+                           const grtx_trace_outputs* fwd, const float* grad_rgb, const float* grad_depth,
+                           const float* grad_opacity, const grtx_gaussian_grads* grads, unsigned int* truncated,
+                           hipStream_t s);
 
 }  // namespace grtx
 

@@ -39,12 +39,25 @@
 namespace grtx {
 namespace {
 
+#ifndef GRTX_LDS_STACK
+#define GRTX_LDS_STACK 16
+#endif
+#ifndef GRTX_REFILL_THRESHOLD
+#define GRTX_REFILL_THRESHOLD 16
+#endif
+#ifndef GRTX_MIN_WAVES_K16
+#define GRTX_MIN_WAVES_K16 3
+#endif
 constexpr int kTraceBlock = 256;
 constexpr int kWaves = kTraceBlock / 64;
-constexpr int kLdsStack = 16;
-constexpr int kMaxStack = 96;  // > depth of a radix tree over 95-bit keys
+constexpr int kLdsStack = GRTX_LDS_STACK;  // per-lane stack entries held in LDS
+constexpr int kMaxStack = 96;              // > depth of a radix tree over 95-bit keys
 constexpr int kSpillRows = kMaxStack - kLdsStack;
-constexpr int kRefillThreshold = 16;
+constexpr int kRefillThreshold = GRTX_REFILL_THRESHOLD;  // idle lanes that end a traversal burst
+#ifndef GRTX_CHUNKS
+#define GRTX_CHUNKS 1
+#endif
+constexpr int kChunks = GRTX_CHUNKS;  // one per XCD
 constexpr uint64_t kEmptyKey = (0x7F800000ull << 32) | 0xFFFFFFFFull;  // (+inf, max)
 
 enum : int { kIdle = 0, kTrav = 1, kEnd = 2 };
@@ -52,6 +65,7 @@ enum : int { kIdle = 0, kTrav = 1, kEnd = 2 };
 struct TraceArgs {
   const float4* nodes;
   const float4* inst;
+  const float4* tris;
   const float* sh;
   const float* root_box;
   uint32_t root_ref;
@@ -79,7 +93,8 @@ struct TraceArgs {
   int64_t rows_per_wave;
   int cap_d;
   int cap_e;
-  unsigned int* counter;
+  unsigned int* counter;  // kChunks work counters
+  int64_t chunk_len;      // work items per chunk (a multiple of 64)
 };
 
 __device__ __forceinline__ float key_t(uint64_t k) { return __uint_as_float((uint32_t)(k >> 32)); }
@@ -194,24 +209,49 @@ __device__ __forceinline__ SphereHit sphere_terms(float4 r0, float4 r1, float4 r
   return h;
 }
 
-template <int K>
-__global__ void __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 4 : 2, 8)))
-k_trace(TraceArgs A) {
+// Proxy leaf: front-facing crossing of a triangle of the bounding icosahedron. Each edge
+// function is d . (P x Q) over the edge's end points relative to the ray origin, with
+// contraction off: the two triangles that share an edge evaluate it with P and Q swapped
+// and get exactly opposite values, so a ray never slips between two faces of a mesh.
+// Front-facing (outward normal against the ray) means all three are <= 0.
+__device__ __forceinline__ bool proxy_hit(float4 A4, float4 B4, float4 C4, float ox, float oy, float oz, float dx,
+                                          float dy, float dz, float* tout) {
+#pragma clang fp contract(off)
+  const float ax = A4.x - ox, ay = A4.y - oy, az = A4.z - oz;
+  const float bx = B4.x - ox, by = B4.y - oy, bz = B4.z - oz;
+  const float cx = C4.x - ox, cy = C4.y - oy, cz = C4.z - oz;
+  const float sAB = dx * (ay * bz - az * by) + dy * (az * bx - ax * bz) + dz * (ax * by - ay * bx);
+  const float sBC = dx * (by * cz - bz * cy) + dy * (bz * cx - bx * cz) + dz * (bx * cy - by * cx);
+  const float sCA = dx * (cy * az - cz * ay) + dy * (cz * ax - cx * az) + dz * (cx * ay - cy * ax);
+  const float sum = sAB + sBC + sCA;
+  // barycentric weights of A, B, C are sBC, sCA, sAB (over their sum)
+  *tout = (sBC * (ax * dx + ay * dy + az * dz) + sCA * (bx * dx + by * dy + bz * dz) +
+           sAB * (cx * dx + cy * dy + cz * dz)) / sum;
+  return sAB <= 0.f && sBC <= 0.f && sCA <= 0.f && sum < 0.f;
+}
+
+template <int K, bool PROXY, bool STATS>
+__global__ void __launch_bounds__(kTraceBlock)
+    __attribute__((amdgpu_waves_per_eu(K <= 16 ? GRTX_MIN_WAVES_K16 : 2, 8))) k_trace(TraceArgs A) {
   __shared__ uint2 s_stack[kLdsStack * kTraceBlock];
-  __shared__ uint32_t s_stat[GRTX_STATS_FIELDS][kTraceBlock];  // per-lane counters
+  __shared__ uint32_t s_stat[STATS ? GRTX_STATS_FIELDS : 1][kTraceBlock];  // per-lane counters
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
-  const int64_t gwave = ((int64_t)blockIdx.x * kTraceBlock + tid) >> 6;
+  const int gwave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * kTraceBlock + tid) >> 6));
   // The wave's rows: [0, kSpillRows) stack spill; two node lists of cap_d rows and two
   // hit lists of cap_e rows (ping-pong source/destination, selected by `par`); K rows
-  // holding the k-buffer while it is blended. Entry j of lane l is at row j, column l.
-  uint2* wpool = A.pool + gwave * A.rows_per_wave * 64 + lane;
+  // holding the k-buffer while it is blended. Entry j of lane l is at row j, column l;
+  // the wave's base address is uniform and lanes add a 32-bit offset.
+  uint2* const wbase = A.pool + (int64_t)gwave * A.rows_per_wave * 64;
   const int rowN = kSpillRows;
   const int rowE = kSpillRows + 2 * A.cap_d;
   const int rowK = rowE + 2 * A.cap_e;
-#define ROW(r) wpool[(int64_t)(r) * 64]
-#define STAT(f) (++s_stat[f][tid])
+#define ROW(r) wbase[(uint32_t)(r) * 64u + (uint32_t)lane]
+#define STAT(f)                        \
+  do {                                 \
+    if constexpr (STATS) ++s_stat[f][tid]; \
+  } while (0)
   const bool ckpt = A.mode == GRTX_MODE_CHECKPOINT;
   const float tnear = A.t_near;
 
@@ -222,16 +262,20 @@ k_trace(TraceArgs A) {
   kbuf_reset(kb, A.k);
   uint64_t tmin = 0;  // key of the last blended hit
   float C0 = 0, C1 = 0, C2 = 0, Dp = 0, T = 1;
-  uint32_t cur_ref = 0;
+  uint32_t cur_ref = 0;  // item in hand: internal node or leaf (has_cur)
   float cur_t = 0;
-  bool has_cur = false;
+  int has_cur = 0;  // per-lane flags held as integers: fewer live lane masks in SGPRs
+  uint64_t key = 0;      // hit key waiting for the k-buffer (have_key)
+  int have_key = 0;
   int sp = 0;
   int par = 0;                              // which list of each pair is the source
   int nsrc_n = 0, nsrc_i = 0, ndst_n = 0;   // deferred nodes
   int esrc_n = 0, esrc_i = 0, edst_n = 0;   // evicted hits
-  bool overflow = false;
+  int overflow = 0;
   int nblend = 0;
   bool exhausted = false;
+  int chunk = (int)(blockIdx.x % kChunks);
+  int chunks_tried = 0;
 
   auto root_start = [&]() __attribute__((always_inline)) {
     // (Re)start at the root; subtrees that end before tmin are culled.
@@ -255,10 +299,10 @@ k_trace(TraceArgs A) {
     }
   };
 
-  auto evict = [&](uint64_t key) __attribute__((always_inline)) {
+  auto evict = [&](uint64_t k64) __attribute__((always_inline)) {
     if (!ckpt) return;
     if (edst_n < A.cap_e) {
-      ROW(rowE + (par ^ 1) * A.cap_e + edst_n) = make_uint2((uint32_t)key, (uint32_t)(key >> 32));
+      ROW(rowE + (par ^ 1) * A.cap_e + edst_n) = make_uint2((uint32_t)k64, (uint32_t)(k64 >> 32));
       ++edst_n;
       STAT(GRTX_STAT_EVICTED);
     } else {
@@ -284,19 +328,32 @@ k_trace(TraceArgs A) {
 
   while (true) {
     // ---------------------------------------------------------------- refill idle lanes
+    // The work items are split into kChunks contiguous chunks (bands of 8x8 tiles). A
+    // wave starts on the chunk of its XCD (workgroups are dealt round-robin to the 8 XCDs)
+    // and moves on to the next chunk when its own is drained.
     if (!exhausted) {
       uint64_t idle = __ballot(state == kIdle);
       if (idle) {
         int cnt = __popcll(idle);
         int leader = __ffsll((unsigned long long)idle) - 1;
         unsigned int base = 0;
-        if (lane == leader) base = atomicAdd(A.counter, (unsigned int)cnt);
-        base = __shfl(base, leader);
-        if ((int64_t)base + cnt >= A.n_work) exhausted = true;
-        if (state == kIdle) {
-          int64_t w = (int64_t)base + __popcll(idle & lt_mask);
+        int64_t avail = 0;
+        while (true) {
+          if (lane == leader) base = atomicAdd(A.counter + chunk, (unsigned int)cnt);
+          base = __shfl(base, leader);
+          avail = A.chunk_len - (int64_t)base;
+          if (avail > 0) break;
+          chunk = chunk + 1 == kChunks ? 0 : chunk + 1;
+          if (++chunks_tried == kChunks) {
+            exhausted = true;
+            break;
+          }
+        }
+        if (state == kIdle && !exhausted) {
+          int64_t rank = __popcll(idle & lt_mask);
+          int64_t w = (int64_t)chunk * A.chunk_len + base + rank;
           int r = -1;
-          if (w < A.n_work) {
+          if (rank < avail && w < A.n_work) {
             if (A.image_w > 0) {
               int64_t tile = w >> 6;
               int within = (int)(w & 63);
@@ -323,8 +380,11 @@ k_trace(TraceArgs A) {
             nsrc_n = nsrc_i = ndst_n = 0;
             esrc_n = esrc_i = edst_n = 0;
             overflow = false;
+            have_key = false;
+            if constexpr (STATS) {
 #pragma unroll
-            for (int f = 0; f < GRTX_STATS_FIELDS; ++f) s_stat[f][tid] = 0u;
+              for (int f = 0; f < GRTX_STATS_FIELDS; ++f) s_stat[f][tid] = 0u;
+            }
             root_start();
             state = kTrav;
           }
@@ -336,19 +396,22 @@ k_trace(TraceArgs A) {
     }
 
     // ---------------------------------------------------------------- traversal
+    // Each step is either a node step (lanes holding an internal node descend) or a leaf
+    // step (lanes holding a leaf test it, and every pending hit key goes through the
+    // k-buffer insertion). Leaf steps wait until half of the traversing lanes have a leaf
+    // or a key, or until no lane can descend, so the insertion chain runs for many lanes
+    // at once (while-while traversal with postponed leaves, Aila and Laine 2009).
     while (true) {
-      uint64_t trav = __ballot(state == kTrav);
+      const uint64_t trav = __ballot(state == kTrav);
       if (!trav) break;
-      uint64_t waiting = __ballot(state == kEnd) | (exhausted ? 0ull : __ballot(state == kIdle));
+      const uint64_t waiting = __ballot(state == kEnd) | (exhausted ? 0ull : __ballot(state == kIdle));
       if (__popcll(waiting) >= kRefillThreshold) break;
-      if (state == kTrav) {
       const uint64_t tmax = kb[K - 1];
       const float tmax_t = key_t(tmax);
-      bool have_key = false;
-      uint64_t key = 0;
-      if (!has_cur) {
+      if (state == kTrav && !has_cur && !have_key) {
+        // acquire: evicted hits of earlier rounds first, then the stack, then the source
+        // checkpoint list; entries already beyond t_max are carried without a fetch
         if (esrc_i < esrc_n) {
-          // hits evicted in earlier rounds compete for the k-buffer first
           uint2 v = ROW(rowE + par * A.cap_e + esrc_i);
           ++esrc_i;
           key = ((uint64_t)v.y << 32) | v.x;
@@ -368,7 +431,7 @@ k_trace(TraceArgs A) {
           if (got) {
             float t = __uint_as_float(e.y);
             if (t > tmax_t) {
-              defer(e.x, t);  // carried forward without a fetch
+              defer(e.x, t);
               STAT(GRTX_STAT_FETCH_FREE);
             } else {
               cur_ref = e.x;
@@ -378,71 +441,81 @@ k_trace(TraceArgs A) {
           }
         }
       }
-
-      if (has_cur) {
-        if (cur_ref & kLeafFlag) {
-          // ---------------------------------------------- leaf: unit-sphere test
+      const bool leafy = state == kTrav && (have_key || (has_cur && (cur_ref & kLeafFlag)));
+      const bool nodey = state == kTrav && has_cur && !(cur_ref & kLeafFlag);
+      const uint64_t mleaf = __ballot(leafy);
+      const uint64_t mnode = __ballot(nodey);
+      if (mleaf != 0 && (mnode == 0 || 2 * __popcll(mleaf) >= __popcll(trav))) {
+        // ------------------------------------------------ leaf step
+        if (leafy && !have_key) {
           const uint32_t p = cur_ref & ~kLeafFlag;
-          const float4* ip = A.inst + 4 * (int64_t)p;
-          float4 r0 = ip[0], r1 = ip[1], r2 = ip[2];
-          SphereHit h = sphere_terms(r0, r1, r2, ox, oy, oz, dx, dy, dz);
           STAT(GRTX_STAT_LEAVES);
           has_cur = false;
-          if (h.a > 0.f && h.c2 <= h.a) {
-            float t0 = (-h.b - sqrtf(fmaxf(h.a - h.c2, 0.f))) / h.a;
-            // the key never precedes the entry of the leaf's own box, so that every
-            // ancestor's entry distance bounds the keys below it exactly
-            key = make_key(fmaxf(t0, cur_t), p);
-            have_key = t0 > tnear && key > tmin;
-          }
-        } else {
-          // ---------------------------------------------- internal node: both children
-          const float4* np = A.nodes + 4 * (int64_t)cur_ref;
-          float4 q0 = np[0], q1 = np[1], q2 = np[2], q3 = np[3];
-          STAT(GRTX_STAT_NODES);
-          Slab s0 = slab(q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, ox, oy, oz, ix, iy, iz);
-          Slab s1 = slab(q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, ox, oy, oz, ix, iy, iz);
-          const float tlo = fmaxf(tnear, key_t(tmin));
-          bool v0 = s0.tn <= s0.tf && s0.tf >= tlo;
-          bool v1 = s1.tn <= s1.tf && s1.tf >= tlo;
-          uint32_t c0 = __float_as_uint(q3.x), c1 = __float_as_uint(q3.y);
-          if (v0 && s0.tn > tmax_t) {
-            defer(c0, s0.tn);
-            v0 = false;
-          }
-          if (v1 && s1.tn > tmax_t) {
-            defer(c1, s1.tn);
-            v1 = false;
-          }
-          if (v0 && v1) {
-            bool first0 = s0.tn <= s1.tn;
-            push(first0 ? c1 : c0, first0 ? s1.tn : s0.tn);
-            cur_ref = first0 ? c0 : c1;
-            cur_t = first0 ? s0.tn : s1.tn;
-          } else if (v0) {
-            cur_ref = c0;
-            cur_t = s0.tn;
-          } else if (v1) {
-            cur_ref = c1;
-            cur_t = s1.tn;
+          // A key never precedes the entry of the leaf's own box, so every ancestor's
+          // entry distance bounds the keys below it exactly.
+          if constexpr (PROXY) {
+            const float4* tp = A.tris + 3 * (int64_t)p;
+            float4 a4 = tp[0], b4 = tp[1], c4 = tp[2];
+            float tt;
+            const bool hit = proxy_hit(a4, b4, c4, ox, oy, oz, dx, dy, dz, &tt);
+            key = make_key(fmaxf(tt, cur_t), __float_as_uint(a4.w));
+            have_key = hit && tt > tnear && key > tmin;
           } else {
-            has_cur = false;
+            const float4* ip = A.inst + 4 * (int64_t)p;
+            float4 r0 = ip[0], r1 = ip[1], r2 = ip[2];
+            SphereHit h = sphere_terms(r0, r1, r2, ox, oy, oz, dx, dy, dz);
+            if (h.a > 0.f && h.c2 <= h.a) {
+              const float t0 = (-h.b - __builtin_amdgcn_sqrtf(fmaxf(h.a - h.c2, 0.f))) * __builtin_amdgcn_rcpf(h.a);
+              key = make_key(fmaxf(t0, cur_t), p);
+              have_key = t0 > tnear && key > tmin;
+            }
           }
         }
+        // any-hit: keys beyond the farthest entry of a full k-buffer are rejected into
+        // the eviction list; otherwise the key is inserted and the entry it pushes out of
+        // a full buffer is evicted. The chain runs under a wave-uniform branch with the
+        // empty key (a no-op) on lanes without a key, so the registers update in place.
+        const bool ins = have_key && key <= tmax;
+        if (__ballot(ins)) {
+          uint64_t out = kbuf_insert(kb, ins ? key : kEmptyKey);
+          if (ins && out != kEmptyKey) evict(out);
+        }
+        if (have_key && !ins) evict(key);
+        have_key = false;
+      } else if (nodey) {
+        // ------------------------------------------------ node step: both children
+        const float4* np = A.nodes + 4 * (int64_t)cur_ref;
+        float4 q0 = np[0], q1 = np[1], q2 = np[2], q3 = np[3];
+        STAT(GRTX_STAT_NODES);
+        Slab s0 = slab(q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, ox, oy, oz, ix, iy, iz);
+        Slab s1 = slab(q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, ox, oy, oz, ix, iy, iz);
+        const float tlo = fmaxf(tnear, key_t(tmin));
+        bool v0 = s0.tn <= s0.tf && s0.tf >= tlo;
+        bool v1 = s1.tn <= s1.tf && s1.tf >= tlo;
+        uint32_t c0 = __float_as_uint(q3.x), c1 = __float_as_uint(q3.y);
+        if (v0 && s0.tn > tmax_t) {
+          defer(c0, s0.tn);
+          v0 = false;
+        }
+        if (v1 && s1.tn > tmax_t) {
+          defer(c1, s1.tn);
+          v1 = false;
+        }
+        if (v0 && v1) {
+          bool first0 = s0.tn <= s1.tn;
+          push(first0 ? c1 : c0, first0 ? s1.tn : s0.tn);
+          cur_ref = first0 ? c0 : c1;
+          cur_t = first0 ? s0.tn : s1.tn;
+        } else if (v0) {
+          cur_ref = c0;
+          cur_t = s0.tn;
+        } else if (v1) {
+          cur_ref = c1;
+          cur_t = s1.tn;
+        } else {
+          has_cur = false;
+        }
       }
-
-      // any-hit: keys beyond the farthest entry of a full k-buffer are rejected into the
-      // eviction list; otherwise the key is inserted and the entry it pushes out of a
-      // full buffer is evicted. The insertion runs under a wave-uniform branch with the
-      // empty key (a no-op) on lanes that have nothing to insert, so the register array
-      // is updated in place.
-      const bool ins = have_key && key <= tmax;
-      if (__ballot(ins)) {
-        uint64_t out = kbuf_insert(kb, ins ? key : kEmptyKey);
-        if (ins && out != kEmptyKey) evict(out);
-      }
-      if (have_key && !ins) evict(key);
-      }  // state == kTrav
     }
 
     // ---------------------------------------------------------------- round end: blend
@@ -456,6 +529,9 @@ k_trace(TraceArgs A) {
 #pragma unroll
       for (int j = 0; j < K; ++j)
         if (j >= K - A.k) ROW(rowK + j) = make_uint2((uint32_t)kb[j], (uint32_t)(kb[j] >> 32));
+      // proxy keys carry the Gaussian id: a mesh crossed exactly on an edge reports the
+      // same Gaussian twice with adjacent keys; only the first is blended
+      uint32_t prev_id = tmin == 0ull ? 0xFFFFFFFFu : (uint32_t)tmin;
 #pragma unroll 1
       for (int j = K - A.k; j < K && !ert; ++j) {
         const uint2 kv = ROW(rowK + j);
@@ -465,47 +541,55 @@ k_trace(TraceArgs A) {
         const float4* ip = A.inst + 4 * (int64_t)p;
         float4 r0 = ip[0], r1 = ip[1], r2 = ip[2], r3 = ip[3];
         SphereHit h = sphere_terms(r0, r1, r2, ox, oy, oz, dx, dy, dz);
-        const float inva = 1.f / h.a;
-        const float cperp = h.c2 * inva;
-        const float talpha = -h.b * inva;
-        const float alpha = r3.x * exp2f(-r3.y * cperp);
-        const uint32_t gid = __float_as_uint(r3.z);
-        float c[3] = {0.5f, 0.5f, 0.5f};
-        const float dn = rsqrtf(dx * dx + dy * dy + dz * dz);
-        float Y[16];
-        sh_basis(dx * dn, dy * dn, dz * dn, A.sh_degree, Y);
-        if (A.sh_degree == 3) {
-          const float4* sp4 = reinterpret_cast<const float4*>(A.sh + (int64_t)gid * 48);
-#pragma unroll
-          for (int q = 0; q < 12; ++q) {
-            float4 v = sp4[q];
-            const float* vv = reinterpret_cast<const float*>(&v);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const int f = 4 * q + e;
-              c[f % 3] += Y[f / 3] * vv[e];
-            }
-          }
-        } else {
-          const float* sc = A.sh + (int64_t)gid * 3 * ncoef;
-#pragma unroll
-          for (int f = 0; f < 16; ++f) {
-            if (f < ncoef) {
-              c[0] += Y[f] * sc[3 * f + 0];
-              c[1] += Y[f] * sc[3 * f + 1];
-              c[2] += Y[f] * sc[3 * f + 2];
-            }
-          }
+        bool blend = true;
+        if constexpr (PROXY) {
+          // a proxy hit counts only if the ray meets the bounding ellipsoid itself
+          blend = p != prev_id && h.a > 0.f && h.c2 <= h.a;
+          prev_id = p;
         }
-        const float w = T * alpha;
-        C0 += w * fmaxf(c[0], 0.f);
-        C1 += w * fmaxf(c[1], 0.f);
-        C2 += w * fmaxf(c[2], 0.f);
-        Dp += w * talpha;
-        T *= (1.f - alpha);
-        if (A.hit_ids && nblend < A.hit_cap) A.hit_ids[(int64_t)ray * A.hit_cap + nblend] = (int32_t)gid;
-        ++nblend;
-        if (T < A.T_min) ert = true;
+        if (blend) {
+          const float inva = 1.f / h.a;
+          const float cperp = h.c2 * inva;
+          const float talpha = -h.b * inva;
+          const float alpha = r3.x * exp2f(-r3.y * cperp);
+          const uint32_t gid = __float_as_uint(r3.z);
+          float c[3] = {0.5f, 0.5f, 0.5f};
+          const float dn = rsqrtf(dx * dx + dy * dy + dz * dz);
+          float Y[16];
+          sh_basis(dx * dn, dy * dn, dz * dn, A.sh_degree, Y);
+          if (A.sh_degree == 3) {
+            const float4* sp4 = reinterpret_cast<const float4*>(A.sh + (int64_t)gid * 48);
+#pragma unroll
+            for (int q = 0; q < 12; ++q) {
+              float4 v = sp4[q];
+              const float* vv = reinterpret_cast<const float*>(&v);
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const int f = 4 * q + e;
+                c[f % 3] += Y[f / 3] * vv[e];
+              }
+            }
+          } else {
+            const float* sc = A.sh + (int64_t)gid * 3 * ncoef;
+#pragma unroll
+            for (int f = 0; f < 16; ++f) {
+              if (f < ncoef) {
+                c[0] += Y[f] * sc[3 * f + 0];
+                c[1] += Y[f] * sc[3 * f + 1];
+                c[2] += Y[f] * sc[3 * f + 2];
+              }
+            }
+          }
+          const float w = T * alpha;
+          C0 += w * fmaxf(c[0], 0.f);
+          C1 += w * fmaxf(c[1], 0.f);
+          C2 += w * fmaxf(c[2], 0.f);
+          Dp += w * talpha;
+          T *= (1.f - alpha);
+          if (A.hit_ids && nblend < A.hit_cap) A.hit_ids[(int64_t)ray * A.hit_cap + nblend] = (int32_t)gid;
+          ++nblend;
+          if (T < A.T_min) ert = true;
+        }  // blend
       }
       const bool full = last != kEmptyKey;
       const bool done = ert || !full || (ckpt && !overflow && ndst_n == 0 && edst_n == 0);
@@ -516,7 +600,7 @@ k_trace(TraceArgs A) {
         A.depth[ray] = Dp;
         A.opac[ray] = 1.f - T;
         if (A.hit_counts) A.hit_counts[ray] = nblend;
-        if (A.stats) {
+        if constexpr (STATS) {
           s_stat[GRTX_STAT_BLENDED][tid] = (uint32_t)nblend;
           uint32_t* st = A.stats + (int64_t)ray * GRTX_STATS_FIELDS;
 #pragma unroll
@@ -553,7 +637,9 @@ k_trace(TraceArgs A) {
 #undef STAT
 }
 
-__global__ void k_reset_counter(unsigned int* c) { *c = 0u; }
+__global__ void k_reset_counter(unsigned int* c) {
+  if (threadIdx.x < kChunks) c[threadIdx.x] = 0u;
+}
 
 __global__ void __launch_bounds__(256) k_fill_background(float* rgb, float* depth, float* opac, uint32_t* stats,
                                                          int32_t* hit_counts, int64_t n, float b0, float b1,
@@ -581,18 +667,42 @@ struct Pool {
 std::mutex g_pool_lock;
 std::map<std::pair<int, hipStream_t>, Pool> g_pools;
 
-template <int K>
+template <int K, bool PROXY>
 grtx_status launch(const TraceArgs& a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_trace<K>, dim3(blocks), dim3(kTraceBlock), 0, s, a);
+  if (a.stats)
+    hipLaunchKernelGGL((k_trace<K, PROXY, true>), dim3(blocks), dim3(kTraceBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_trace<K, PROXY, false>), dim3(blocks), dim3(kTraceBlock), 0, s, a);
   GRTX_LAUNCH_CHECK();
   return GRTX_OK;
 }
 
-template <int K>
+template <int K, bool PROXY>
 int blocks_per_cu() {
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<K>, kTraceBlock, 0) != hipSuccess || nb < 1) nb = 1;
-  return nb;
+  // the counting and non-counting kernels are sized alike; take the tighter one
+  int nb0 = 0, nb1 = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb0, k_trace<K, PROXY, false>, kTraceBlock, 0) != hipSuccess)
+    nb0 = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb1, k_trace<K, PROXY, true>, kTraceBlock, 0) != hipSuccess)
+    nb1 = 1;
+  return std::max(1, std::min(nb0, nb1));
+}
+
+template <bool PROXY>
+int blocks_per_cu_k(int K) {
+  return K == 4 ? blocks_per_cu<4, PROXY>() : K == 8 ? blocks_per_cu<8, PROXY>() : K == 16 ? blocks_per_cu<16, PROXY>()
+       : K == 32 ? blocks_per_cu<32, PROXY>() : blocks_per_cu<64, PROXY>();
+}
+
+template <bool PROXY>
+grtx_status launch_k(int K, const TraceArgs& a, int blocks, hipStream_t s) {
+  switch (K) {
+    case 4: return launch<4, PROXY>(a, blocks, s);
+    case 8: return launch<8, PROXY>(a, blocks, s);
+    case 16: return launch<16, PROXY>(a, blocks, s);
+    case 32: return launch<32, PROXY>(a, blocks, s);
+    default: return launch<64, PROXY>(a, blocks, s);
+  }
 }
 
 }  // namespace
@@ -618,8 +728,8 @@ grtx_status trace(const Bvh* b, const grtx_rays* r, const grtx_trace_params* p, 
     cached_cus = prop.multiProcessorCount;
   }
   const int K = p->k <= 4 ? 4 : p->k <= 8 ? 8 : p->k <= 16 ? 16 : p->k <= 32 ? 32 : 64;
-  int bpc = K == 4 ? blocks_per_cu<4>() : K == 8 ? blocks_per_cu<8>() : K == 16 ? blocks_per_cu<16>()
-          : K == 32 ? blocks_per_cu<32>() : blocks_per_cu<64>();
+  const bool proxy = b->kind == GRTX_BVH_PROXY20;
+  int bpc = proxy ? blocks_per_cu_k<true>(K) : blocks_per_cu_k<false>(K);
   int blocks = cached_cus * bpc;
   // never more waves than rays need
   int64_t need_blocks = (R + kTraceBlock - 1) / kTraceBlock;
@@ -648,6 +758,7 @@ grtx_status trace(const Bvh* b, const grtx_rays* r, const grtx_trace_params* p, 
   TraceArgs a{};
   a.nodes = b->nodes;
   a.inst = b->inst;
+  a.tris = b->tris;
   a.sh = b->sh;
   a.root_box = b->root_box;
   a.root_ref = b->n_leaves == 1 ? (kLeafFlag | 0u) : 0u;
@@ -686,14 +797,9 @@ grtx_status trace(const Bvh* b, const grtx_rays* r, const grtx_trace_params* p, 
   a.rows_per_wave = rows;
   a.cap_d = cap_d;
   a.cap_e = cap_e;
-  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, pool->counter);
-  switch (K) {
-    case 4: return launch<4>(a, blocks, s);
-    case 8: return launch<8>(a, blocks, s);
-    case 16: return launch<16>(a, blocks, s);
-    case 32: return launch<32>(a, blocks, s);
-    default: return launch<64>(a, blocks, s);
-  }
+  a.chunk_len = ((a.n_work + 64 * kChunks - 1) / (64 * kChunks)) * 64;
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, pool->counter);
+  return proxy ? launch_k<true>(K, a, blocks, s) : launch_k<false>(K, a, blocks, s);
 }
 
 }  // namespace grtx

@@ -70,6 +70,11 @@ class _TraceOutputs(C.Structure):
                 ("reserved", C.c_int32)]
 
 
+class _GaussianGrads(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p), ("opacities", C.c_void_p),
+                ("sh", C.c_void_p)]
+
+
 class _Camera(C.Structure):
     _fields_ = [("eye", C.c_float * 3), ("target", C.c_float * 3), ("up", C.c_float * 3), ("fov_y_deg", C.c_float),
                 ("width", C.c_int32), ("height", C.c_int32)]
@@ -86,6 +91,9 @@ _SIGNATURES = {
     "grtx_pinhole_rays": (C.c_int, [C.POINTER(_Camera), C.c_void_p, C.c_void_p, C.c_void_p]),
     "grtx_trace": (C.c_int, [C.c_void_p, C.POINTER(_Rays), C.POINTER(_TraceParams), C.POINTER(_TraceOutputs),
                              C.c_void_p]),
+    "grtx_trace_backward": (C.c_int, [C.c_void_p, C.POINTER(_Gaussians), C.POINTER(_Rays), C.POINTER(_TraceParams),
+                                      C.POINTER(_TraceOutputs), C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.POINTER(_GaussianGrads), C.c_void_p, C.c_void_p]),
     "grtx_last_error": (C.c_char_p, []),
     "grtx_version": (C.c_int32, []),
 }
@@ -236,6 +244,38 @@ def trace(bvh: Bvh, origins: torch.Tensor, dirs: torch.Tensor, k: int = 16, T_mi
                       int(out["hit_ids"].shape[1]) if "hit_ids" in out else 0, 0)
     _check(lib().grtx_trace(bvh.handle, C.byref(rays), C.byref(prm), C.byref(o), _stream(stream)))
     return out
+
+
+def _gaussians(scene: SceneTensors):
+    return _Gaussians(scene.means.data_ptr(), scene.scales.data_ptr(), scene.quats.data_ptr(),
+                      scene.opacities.data_ptr(), scene.sh.data_ptr(), scene.n, scene.sh_degree, 0)
+
+
+def trace_backward(bvh: Bvh, origins, dirs, fwd: dict, grad_rgb=None, grad_depth=None, grad_opacity=None,
+                   grads: dict = None, k: int = 16, T_min: float = 1e-3, mode: int = CHECKPOINT,
+                   bg=(0.0, 0.0, 0.0), t_near: float = 0.0, stream=None):
+    """Accumulate dL/d(parameters) into `grads` (dict of tensors shaped like the scene
+    arrays; allocated as zeros when None). `fwd` must hold rgb, depth, opacity, hit_ids and
+    hit_counts of the forward call. Returns (grads, truncated_rays tensor)."""
+    sc = bvh.scene
+    dev = sc.means.device
+    if grads is None:
+        grads = dict(means=torch.zeros_like(sc.means), scales=torch.zeros_like(sc.scales),
+                     quats=torch.zeros_like(sc.quats), opacities=torch.zeros_like(sc.opacities),
+                     sh=torch.zeros_like(sc.sh))
+    truncated = torch.zeros(1, dtype=torch.int32, device=dev)
+    R = int(origins.shape[0])
+    rays = _Rays(origins.data_ptr() if R else None, dirs.data_ptr() if R else None, R, t_near, 0)
+    prm = _TraceParams(k, T_min, mode, (C.c_float * 3)(*bg), 0, 0)
+    o = _TraceOutputs(fwd["rgb"].data_ptr(), fwd["depth"].data_ptr(), fwd["opacity"].data_ptr(), None,
+                      fwd["hit_ids"].data_ptr(), fwd["hit_counts"].data_ptr(), int(fwd["hit_ids"].shape[1]), 0)
+    gg = _GaussianGrads(grads["means"].data_ptr(), grads["scales"].data_ptr(), grads["quats"].data_ptr(),
+                        grads["opacities"].data_ptr(), grads["sh"].data_ptr())
+    g = _gaussians(sc)
+    _check(lib().grtx_trace_backward(bvh.handle, C.byref(g), C.byref(rays), C.byref(prm), C.byref(o),
+                                     _ptr(grad_rgb), _ptr(grad_depth), _ptr(grad_opacity), C.byref(gg),
+                                     _ptr(truncated), _stream(stream)))
+    return grads, truncated
 
 
 def version():

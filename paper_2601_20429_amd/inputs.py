@@ -140,6 +140,21 @@ def cluster_scene(seed: int, n: int, sh_degree: int = 3) -> Scene:
     return Scene(_f32(means), _f32(scales), _f32(quats), _f32(opac), _f32(sh), sh_degree)
 
 
+def fd_scene(seed: int = 5, n: int = 500) -> Scene:
+    """Small differentiable test scene: 8 isotropic clusters (sigma 0.2, centres in
+    [-1,1]^3), per-axis scale exp(N(-2.5, 0.4)), uniform rotation, opacity
+    sigmoid(N(0, 1.5)), SH degree 3 (DC ~ N(0, 0.5), higher bands ~ N(0, 0.1))."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(-1.0, 1.0, (8, 3))
+    which = rng.integers(0, 8, n)
+    means = centres[which] + rng.normal(0.0, 0.2, (n, 3))
+    scales = np.exp(rng.normal(-2.5, 0.4, (n, 3)))
+    quats = _unit_quats(rng, n)
+    opac = _sigmoid(rng.normal(0.0, 1.5, n))
+    sh = _sh_coeffs(rng, n, 3, 0.5, 0.1)
+    return Scene(_f32(means), _f32(scales), _f32(quats), _f32(opac), _f32(sh), 3)
+
+
 def perturbed_means(scene: Scene, seed: int, std: float = 0.01) -> Scene:
     """Copy of `scene` with means + N(0, std^2) (target scene of the differentiation case)."""
     rng = np.random.default_rng(seed)

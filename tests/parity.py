@@ -23,6 +23,7 @@ T_ERT = 1e-6
 
 
 def lists_match_with_exceptions(g, o, hits, scene, origin, direction, amin, T_min, tafter):
+    # `hits` holds the oracle's alpha and key distance of every hit on this ray
     """True if GPU list g and oracle list o differ only by the allowed exceptions."""
     alpha = dict(zip(hits["ids"].tolist(), hits["alpha"].tolist()))
     tkey = dict(zip(hits["ids"].tolist(), hits["t"].tolist()))
@@ -51,16 +52,31 @@ def lists_match_with_exceptions(g, o, hits, scene, origin, direction, amin, T_mi
         if g2[j] == o2[j]:
             j += 1
             continue
-        # (ii) adjacent swap of near-equal keys
-        if (j + 1 < len(g2) and g2[j] == o2[j + 1] and g2[j + 1] == o2[j]
-                and abs(tkey.get(g2[j], np.inf) - tkey.get(g2[j + 1], -np.inf)) < T_SWAP):
-            j += 2
-            continue
+        # (ii) near-equal keys may come in either order: an adjacent swap, or a tie cut
+        # by early termination right there (the last blended hit is the other one)
+        if abs(tkey.get(g2[j], np.inf) - tkey.get(o2[j], -np.inf)) < T_SWAP:
+            if j + 1 == len(g2):
+                j += 1
+                continue
+            if g2[j] == o2[j + 1] and g2[j + 1] == o2[j]:
+                j += 2
+                continue
         return False
     return True
 
 
-def compare_render(scene, origins, dirs, gpu, ref, amin, T_min, max_exception_frac=1e-2, label=""):
+def _describe(g, o, hits, tafter, T_min):
+    """First difference of two id lists with the oracle's alpha and key of the ids there."""
+    j = next((i for i in range(min(len(g), len(o))) if g[i] != o[i]), min(len(g), len(o)))
+    alpha = dict(zip(hits["ids"].tolist(), hits["alpha"].tolist()))
+    tkey = dict(zip(hits["ids"].tolist(), hits["t"].tolist()))
+    win = lambda L: [(i, round(alpha.get(i, float("nan")), 7), round(tkey.get(i, float("nan")), 7))
+                     for i in L[max(0, j - 2):j + 3]]
+    return dict(first_diff=j, len_gpu=len(g), len_oracle=len(o), gpu=win(g), oracle=win(o),
+                T_after_last=float(tafter[-1]) if len(tafter) else None, T_min=T_min)
+
+
+def compare_render(scene, origins, dirs, gpu, ref, amin, T_min, max_exception_frac=1e-2, label="", key_mode=0):
     """Compare GPU outputs (numpy dict: rgb, depth, hit_ids, hit_counts) with an oracle
     render (with cap) of the same rays. Returns a summary dict; asserts the rule."""
     R = origins.shape[0]
@@ -81,10 +97,10 @@ def compare_render(scene, origins, dirs, gpu, ref, amin, T_min, max_exception_fr
                 bad.append((r, "exact-list", float(err), g[:8]))
             n_exact += 1
             continue
-        hits = oracle.ray_hits(scene, origins[r], dirs[r], amin)
+        hits = oracle.ray_hits(scene, origins[r], dirs[r], amin, key_mode=key_mode)
         if not lists_match_with_exceptions(g, o, hits, scene, origins[r], dirs[r], amin, T_min,
                                            ref["tafter"][r, :ocount]):
-            bad.append((r, "list", g[:12], o[:12]))
+            bad.append((r, "list", _describe(g, o, hits, ref["tafter"][r, :ocount], T_min)))
             continue
         c = oracle.composite_list(scene, origins[r], dirs[r], g, amin)
         err = max(np.abs(gpu["rgb"][r] - c["rgb"]).max(), abs(gpu["depth"][r] - c["depth"]))

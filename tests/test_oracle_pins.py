@@ -249,8 +249,7 @@ def test_view_dependent_colour_uses_ray_direction():
         d = np.array([0.0, math.sqrt(1 - dz * dz), dz])
         o = -3.0 * d
         r = oracle.render(sc, o[None], d[None], AMIN)
-        dd = np.float32(d).astype(np.float64)
-        dd /= np.linalg.norm(dd)
+        dd = d / np.linalg.norm(d)
         want = max(0.0, 0.5 + c1 * dd[2] * float(np.float32(0.3)))
         assert r["rgb"][0, 0] / r["opacity"][0] == pytest.approx(want, rel=1e-9)
 
@@ -461,3 +460,34 @@ def test_lbvh_reference_topology(n, dup):
     assert (t["perm"] == np.argsort(codes, kind="stable")).all()
     assert (t["codes"] == codes[t["perm"]]).all()
     _check_radix_tree(t["codes"], t["perm"], t["child"], t["parent"], n)
+
+
+def test_oracle_finite_difference_matches_closed_form_gradient():
+    """Central differences of the oracle with FP64 inputs reproduce a closed-form
+    derivative: for a ray along x at distance b from an isotropic Gaussian's centre,
+    alpha = o exp(-b^2 / 2s^2), so d alpha / d mu_y = -alpha b / s^2 and
+    d alpha / d s = alpha b^2 / s^3."""
+    import copy
+    s0, o0, b = 0.1, 0.6, 0.07
+    base = make_scene([[1.0, b, 0.0]], [s0] * 3, opac=o0)
+    sc = copy.deepcopy(base)
+    sc.means = base.means.astype(np.float64)
+    sc.scales = base.scales.astype(np.float64)
+    sc.opacities = base.opacities.astype(np.float64)
+    o32, s32, b32 = float(base.opacities[0]), float(base.scales[0, 0]), float(base.means[0, 1])
+    alpha = o32 * math.exp(-0.5 * b32 ** 2 / s32 ** 2)
+    h = 1e-6
+
+    def opac(scene):
+        return oracle.render(scene, np.zeros((1, 3)), np.array([[1.0, 0.0, 0.0]]), AMIN)["opacity"][0]
+
+    sp, sm = copy.deepcopy(sc), copy.deepcopy(sc)
+    sp.means = sc.means.copy(); sp.means[0, 1] += h
+    sm.means = sc.means.copy(); sm.means[0, 1] -= h
+    assert (opac(sp) - opac(sm)) / (2 * h) == pytest.approx(-alpha * b32 / s32 ** 2, rel=1e-6)
+    sp, sm = copy.deepcopy(sc), copy.deepcopy(sc)
+    sp.scales = sc.scales + h
+    sm.scales = sc.scales - h
+    # isotropic scale change: only the two axes across the ray matter for the offset in y
+    want = alpha * b32 ** 2 / s32 ** 3
+    assert (opac(sp) - opac(sm)) / (2 * h) == pytest.approx(want, rel=1e-6)
