@@ -30,6 +30,72 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def run_serving(n_requests):
+    """Serving workload: four device-resident scenes (100k, 500k, 1M, 3M Gaussians), Poisson
+    arrivals at 200 requests/s, each a random camera on the radius-3 sphere at a resolution
+    drawn from {256^2, 512^2, 800^2, 1920x1080}, k = 16; latency is submission to result."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_2601_20429_amd import grtx, inputs
+
+    cfg = inputs.SERVE
+    amin = float(np.float32(cfg["alpha_min"]))
+    bvhs, tensors = [], []
+    for seed, n in zip(cfg["scene_seeds"], cfg["scene_sizes"]):
+        st = grtx.SceneTensors.from_scene(inputs.cluster_scene(seed, n, 3), "cuda")
+        tensors.append(st)
+        bvhs.append(grtx.build(st, alpha_min=amin))
+    torch.cuda.synchronize()
+    srv = grtx.Server(memory_budget=96 << 30, slots=2, k=cfg["k"], T_min=cfg["T_min"])
+    ids = [srv.add_scene(b) for b in bvhs]
+    rng = np.random.default_rng(cfg["arrival_seed"])
+    gaps = rng.exponential(1.0 / cfg["rate"], n_requests)
+    plan = []
+    for j in range(n_requests):
+        w, h = cfg["resolutions"][int(rng.integers(len(cfg["resolutions"])))]
+        cam = inputs.Camera(inputs.random_orbit_eye(rng), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 60.0, w, h)
+        plan.append((float(gaps[:j + 1].sum()), ids[int(rng.integers(len(ids)))], cam))
+    tickets = []
+    # warm the server's streams with one request per scene (pools, code objects)
+    warm = [srv.submit(i, inputs.orbit_camera(64, 64)) for i in ids]
+    while any(srv.poll(t) is None for t in warm):
+        time.sleep(0.001)
+    for t in warm:
+        srv.release(t)
+
+    def submitter():
+        t0 = time.perf_counter()
+        for at, sid, cam in plan:
+            dt = at - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(srv.submit(sid, cam))
+
+    base = srv.stats()
+    th = threading.Thread(target=submitter)
+    th.start()
+    done = 0
+    while done < n_requests:
+        for t in list(tickets):
+            if t > 0 and srv.poll(t) is not None:
+                srv.release(t)
+                tickets[tickets.index(t)] = -1
+                done += 1
+        time.sleep(0.0005)
+    th.join()
+    st = srv.stats()
+    srv.close()
+    rays = st["rays_completed"] - base["rays_completed"]
+    offered = sum(c.width * c.height for _, _, c in plan) / plan[-1][0] / 1e6
+    return dict(workload=cfg["name"], requests=n_requests, p50_ms=st["p50_ms"], p99_ms=st["p99_ms"],
+                mean_ms=st["mean_ms"], max_ms=st["max_ms"], mrays_s=st["mrays_per_s"], rays=rays,
+                offered_mrays_s=offered, scenes=list(cfg["scene_sizes"]),
+                note="latency percentiles include the warm-up requests")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -40,6 +106,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the restart-mode comparison run")
     ap.add_argument("--cpu-rays", type=int, default=16384)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
+                    help="first copy this many GiB device-to-device (a reference kernel for HBM counters)")
+    ap.add_argument("--serve-requests", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the ray-sharded multi-GPU "
@@ -96,6 +166,14 @@ def main():
         keep.clear()
         return (t1 - t0) * 1e3 / steps, float(np.mean(ktimes)), float(np.median(ktimes))
 
+    if args.calibrate_copy_gib > 0:
+        nb = int(args.calibrate_copy_gib * (1 << 30)) // 4
+        src = torch.ones(nb, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nb * 4} bytes read and written")
+        del src, dst
     log(f"scene {cfg['n']} Gaussians, {cam.width}x{cam.height} rays, k={args.k}, mode={args.mode}")
     ms, k_mean, k_med = timed(mode, args.steps, args.warmup)
     mrays = R / (ms * 1e-3) / 1e6
@@ -133,6 +211,11 @@ def main():
         extra[f"{name}_nodes_per_ray"] = float(s2[0] + s2[1]) / R
         log(f"{name}: step {ms2:.3f} ms, trace {k2:.3f} ms, nodes/ray {extra[f'{name}_nodes_per_ray']:.1f}")
 
+    serving = None
+    if not args.no_serving:
+        serving = run_serving(args.serve_requests)
+        log("serving", json.dumps(serving))
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -168,6 +251,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"k_trace<{16 if args.k > 8 else args.k}>"},
         "cpu_baseline": cpu,
+        "serving": serving,
         "extra": extra,
     }
     print(json.dumps(rec), flush=True)

@@ -233,6 +233,107 @@ grtx_status grtx_trace_backward(const grtx_bvh* bvh, const grtx_gaussians* g, co
                                 const float* grad_depth, const float* grad_opacity, const grtx_gaussian_grads* grads,
                                 uint32_t* truncated_rays, void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Serving: continuous batching of render requests over several device-resident scenes.
+ * A worker thread admits queued requests first come, first served while the memory they
+ * hold fits the budget, packs all admitted requests (any scenes, any resolutions) into
+ * one trace launch per batch, and runs batches on `slots` streams so that a batch formed
+ * while another runs overlaps with it on the device. Results are identical to tracing
+ * each request alone with grtx_pinhole_rays + grtx_trace on its scene.
+ * ------------------------------------------------------------------------------------- */
+typedef struct grtx_server grtx_server;
+
+/* memory_budget: device bytes the server may hold (scene set copy, per-slot checkpoint
+ *   pools, and per request its rays and outputs until released).
+ * slots: streams, i.e. batches that may be in flight at once (0 = 2).
+ * k, T_min, mode, bg: as in grtx_trace_params, for every request.
+ * max_batch_rays: rays per batch (0 = 2^23); larger requests are refused. */
+typedef struct grtx_serve_config {
+  int64_t memory_budget;
+  int32_t slots;
+  int32_t k;
+  float T_min;
+  int32_t mode;
+  int32_t max_batch_rays;
+  float bg[3];
+} grtx_serve_config;
+
+/* A render request: pinhole camera (as grtx_camera) on scene `scene_id`. */
+typedef struct grtx_request {
+  int32_t scene_id;
+  int32_t width;
+  int32_t height;
+  float eye[3];
+  float target[3];
+  float up[3];
+  float fov_y_deg;
+} grtx_request;
+
+/* Result of a finished request: device arrays rgb [H*W,3], depth [H*W], opacity [H*W]
+ * (row-major pixels), owned by the server until grtx_serve_release; timestamps in
+ * seconds since the server was created (submitted, admitted, launched, finished). */
+typedef struct grtx_request_result {
+  const float* rgb;
+  const float* depth;
+  const float* opacity;
+  int32_t width;
+  int32_t height;
+  double t_submit;
+  double t_admit;
+  double t_launch;
+  double t_done;
+} grtx_request_result;
+
+/* Latency percentiles over finished requests (submission to completion), and throughput
+ * over the span from the first launch to the last completion. */
+typedef struct grtx_serve_stats {
+  int64_t submitted;
+  int64_t completed;
+  int64_t rays_completed;
+  int64_t bytes_in_use;
+  int64_t bytes_available;
+  double p50_ms;
+  double p99_ms;
+  double mean_ms;
+  double max_ms;
+  double busy_s;
+  double mrays_per_s;
+} grtx_serve_stats;
+
+/* Device bytes a request holds while admitted (host-only; no device needed). */
+grtx_status grtx_serve_request_bytes(const grtx_request* r, int64_t* bytes);
+
+/* Create a server on the current device. GRTX_ERR_CAPACITY if the budget cannot even
+ * hold the slots' checkpoint pools. */
+grtx_status grtx_serve_create(const grtx_serve_config* cfg, grtx_server** out);
+
+/* Register a built SPHERE_INSTANCE structure (all scenes share one SH degree) before the
+ * first request; its device data is copied into the server's scene set at the first
+ * submit. *scene_id receives the index requests use. The handle may be destroyed after
+ * the first submit. */
+grtx_status grtx_serve_add_scene(grtx_server* s, const grtx_bvh* bvh, int32_t* scene_id);
+
+/* Queue a request; *ticket identifies it. GRTX_ERR_CAPACITY if it can never fit the
+ * budget or the batch size. Thread-safe. */
+grtx_status grtx_serve_submit(grtx_server* s, const grtx_request* r, uint64_t* ticket);
+
+/* GRTX_OK with *res filled once the request has finished, GRTX_ERR_NOT_READY while it
+ * is queued or in flight, GRTX_ERR_DEVICE if its batch failed. Thread-safe. */
+grtx_status grtx_serve_poll(grtx_server* s, uint64_t ticket, grtx_request_result* res);
+
+/* Copy a finished request's outputs into caller-owned DEVICE arrays (rgb [H*W,3],
+ * depth [H*W], opacity [H*W]; each may be NULL), enqueued on `stream`. */
+grtx_status grtx_serve_copy_result(grtx_server* s, uint64_t ticket, float* rgb, float* depth, float* opacity,
+                                   void* stream);
+
+/* Free a finished request's outputs (and its share of the budget). */
+grtx_status grtx_serve_release(grtx_server* s, uint64_t ticket);
+
+grtx_status grtx_serve_get_stats(grtx_server* s, grtx_serve_stats* st);
+
+/* Stop the worker after the batches in flight and free everything. NULL is accepted. */
+grtx_status grtx_serve_destroy(grtx_server* s);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char* grtx_last_error(void);
 

@@ -179,4 +179,89 @@ grtx_status grtx_trace_backward(const grtx_bvh* bvh, const grtx_gaussians* g, co
                               static_cast<hipStream_t>(stream));
 }
 
+grtx_status grtx_serve_request_bytes(const grtx_request* r, int64_t* bytes) {
+  grtx::clear_error();
+  CHECK_ARG(r && bytes, "grtx_serve_request_bytes: null argument");
+  CHECK_ARG(r->width > 0 && r->height > 0, "grtx_serve_request_bytes: image size must be positive");
+  *bytes = grtx::request_bytes(r);
+  return GRTX_OK;
+}
+
+grtx_status grtx_serve_create(const grtx_serve_config* cfg, grtx_server** out) {
+  grtx::clear_error();
+  CHECK_ARG(cfg && out, "grtx_serve_create: null argument");
+  CHECK_ARG(cfg->memory_budget > 0, "grtx_serve_create: memory_budget must be positive");
+  CHECK_ARG(cfg->slots >= 0 && cfg->slots <= 16, "grtx_serve_create: slots must be 0..16");
+  CHECK_ARG(cfg->k >= 1 && cfg->k <= 64, "grtx_serve_create: k must be 1..64");
+  CHECK_ARG(cfg->T_min >= 0.f && cfg->T_min < 1.f, "grtx_serve_create: T_min must be in [0,1)");
+  CHECK_ARG(cfg->mode == GRTX_MODE_CHECKPOINT || cfg->mode == GRTX_MODE_RESTART, "grtx_serve_create: unknown mode");
+  CHECK_ARG(cfg->max_batch_rays >= 0, "grtx_serve_create: negative max_batch_rays");
+  grtx::Server* sv = nullptr;
+  grtx_status st = grtx::serve_create(cfg, &sv);
+  if (st != GRTX_OK) return st;
+  grtx_server* h = new (std::nothrow) grtx_server{sv};
+  if (!h) {
+    grtx::serve_destroy(sv);
+    set_error("grtx_serve_create: host allocation failed");
+    return GRTX_ERR_OUT_OF_MEMORY;
+  }
+  *out = h;
+  return GRTX_OK;
+}
+
+grtx_status grtx_serve_add_scene(grtx_server* s, const grtx_bvh* bvh, int32_t* scene_id) {
+  grtx::clear_error();
+  CHECK_ARG(s && bvh && scene_id, "grtx_serve_add_scene: null argument");
+  return grtx::serve_add_scene(s->impl, &bvh->impl, scene_id);
+}
+
+grtx_status grtx_serve_submit(grtx_server* s, const grtx_request* r, uint64_t* ticket) {
+  grtx::clear_error();
+  CHECK_ARG(s && r && ticket, "grtx_serve_submit: null argument");
+  CHECK_ARG(r->width > 0 && r->height > 0, "grtx_serve_submit: image size must be positive");
+  CHECK_ARG(r->fov_y_deg > 0.f && r->fov_y_deg < 180.f, "grtx_serve_submit: fov must be in (0,180)");
+  return grtx::serve_submit(s->impl, r, ticket);
+}
+
+grtx_status grtx_serve_poll(grtx_server* s, uint64_t ticket, grtx_request_result* res) {
+  grtx::clear_error();
+  CHECK_ARG(s && res, "grtx_serve_poll: null argument");
+  return grtx::serve_poll(s->impl, ticket, res);
+}
+
+grtx_status grtx_serve_copy_result(grtx_server* s, uint64_t ticket, float* rgb, float* depth, float* opacity,
+                                   void* stream) {
+  grtx::clear_error();
+  CHECK_ARG(s, "grtx_serve_copy_result: null argument");
+  grtx_request_result r{};
+  grtx_status st = grtx::serve_poll(s->impl, ticket, &r);
+  if (st != GRTX_OK) return st;
+  const size_t n = (size_t)r.width * r.height;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (rgb) GRTX_HIP(hipMemcpyAsync(rgb, r.rgb, sizeof(float) * 3 * n, hipMemcpyDeviceToDevice, hs));
+  if (depth) GRTX_HIP(hipMemcpyAsync(depth, r.depth, sizeof(float) * n, hipMemcpyDeviceToDevice, hs));
+  if (opacity) GRTX_HIP(hipMemcpyAsync(opacity, r.opacity, sizeof(float) * n, hipMemcpyDeviceToDevice, hs));
+  return GRTX_OK;
+}
+
+grtx_status grtx_serve_release(grtx_server* s, uint64_t ticket) {
+  grtx::clear_error();
+  CHECK_ARG(s, "grtx_serve_release: null argument");
+  return grtx::serve_release(s->impl, ticket);
+}
+
+grtx_status grtx_serve_get_stats(grtx_server* s, grtx_serve_stats* st) {
+  grtx::clear_error();
+  CHECK_ARG(s && st, "grtx_serve_get_stats: null argument");
+  return grtx::serve_stats(s->impl, st);
+}
+
+grtx_status grtx_serve_destroy(grtx_server* s) {
+  grtx::clear_error();
+  if (!s) return GRTX_OK;
+  grtx_status st = grtx::serve_destroy(s->impl);
+  delete s;
+  return st;
+}
+
 }  // extern "C"

@@ -592,6 +592,13 @@ grtx_status radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t
   return GRTX_OK;
 }
 
+// Root entry: the root's box and reference (internal node 0, or leaf 0 for one leaf).
+__global__ void k_write_root(const float* __restrict__ box, uint32_t ref, float* __restrict__ roots) {
+  if (threadIdx.x < 6) roots[threadIdx.x] = box[threadIdx.x];
+  if (threadIdx.x == 6) roots[6] = __uint_as_float(ref);
+  if (threadIdx.x == 7) roots[7] = 0.f;
+}
+
 __global__ void __launch_bounds__(kBlock) k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   if (i < n) p[i] = v;
@@ -675,6 +682,7 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
   GRTX_TRY(dalloc(b, &b->inst, 4 * n));
   if (proxy) GRTX_TRY(dalloc(b, &b->tris, 3 * m));
   b->root_box = b->boxes;  // node 0: the root, or the only leaf when m == 1
+  GRTX_TRY(dalloc(b, &b->roots, 8));
 
   Scratch sc{{}, s};
   float *partial = nullptr, *bounds = nullptr, *cent = nullptr, *tbox = nullptr;
@@ -717,6 +725,7 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
   } else {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, s, b->parent, 1, kNoParent);
   }
+  hipLaunchKernelGGL(k_write_root, dim3(1), dim3(64), 0, s, b->root_box, m == 1 ? (kLeafFlag | 0u) : 0u, b->roots);
   GRTX_LAUNCH_CHECK();
   return GRTX_OK;
 }

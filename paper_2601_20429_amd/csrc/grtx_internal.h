@@ -54,6 +54,7 @@ struct Bvh {
   uint32_t* parent = nullptr;// [2 n_leaves - 1]
   float* boxes = nullptr;    // [2 n_leaves - 1][6]
   float* root_box = nullptr; // device [6] (points into boxes)
+  float* roots = nullptr;    // device [8]: root box, root reference bits, 0
   const float* opacities = nullptr; // borrowed
   const float* sh = nullptr;        // borrowed
   hipStream_t build_stream = nullptr;
@@ -96,6 +97,35 @@ grtx_status export_topology(const Bvh* b, uint32_t* child, uint32_t* parent, uin
 grtx_status pinhole_rays(const grtx_camera* cam, float* origins, float* dirs, hipStream_t s);
 grtx_status trace(const Bvh* b, const grtx_rays* r, const grtx_trace_params* p, const grtx_trace_outputs* o,
                   hipStream_t s);
+
+// What the trace kernel reads of a scene, or of several scenes merged into one address
+// space (serving): then `ray_scene` gives each ray's scene and `roots` holds one root
+// entry (8 floats) per scene.
+struct TraceScene {
+  const float4* nodes;
+  const float4* inst;
+  const float4* tris;
+  const float* sh;
+  int sh_degree;
+  const float* roots;
+  const int32_t* ray_scene;
+  grtx_bvh_kind kind;
+  int64_t n_leaves;
+};
+grtx_status launch_trace(const TraceScene& sc, const grtx_rays* r, const grtx_trace_params* p,
+                         const grtx_trace_outputs* o, hipStream_t s);
+// Bytes of the per-stream checkpoint pool a trace with k-buffer width K allocates.
+int64_t trace_pool_bytes(int K, int cap_d, int cap_e);
+
+struct Server;
+int64_t request_bytes(const grtx_request* r);
+grtx_status serve_create(const grtx_serve_config* cfg, Server** out);
+grtx_status serve_add_scene(Server* sv, const Bvh* b, int32_t* scene_id);
+grtx_status serve_submit(Server* sv, const grtx_request* r, uint64_t* ticket);
+grtx_status serve_poll(Server* sv, uint64_t ticket, grtx_request_result* res);
+grtx_status serve_release(Server* sv, uint64_t ticket);
+grtx_status serve_stats(Server* sv, grtx_serve_stats* st);
+grtx_status serve_destroy(Server* sv);
 grtx_status trace_backward(const grtx_gaussians* g, const grtx_rays* r, const grtx_trace_params* p,
                            const grtx_trace_outputs* fwd, const float* grad_rgb, const float* grad_depth,
                            const float* grad_opacity, const grtx_gaussian_grads* grads, unsigned int* truncated,
@@ -105,4 +135,8 @@ grtx_status trace_backward(const grtx_gaussians* g, const grtx_rays* r, const gr
 
 struct grtx_bvh {
   grtx::Bvh impl;
+};
+
+struct grtx_server {
+  grtx::Server* impl;
 };

@@ -67,8 +67,8 @@ struct TraceArgs {
   const float4* inst;
   const float4* tris;
   const float* sh;
-  const float* root_box;
-  uint32_t root_ref;
+  const float* roots;         // per scene: root box (lo xyz, hi xyz), root ref bits, 0
+  const int32_t* ray_scene;   // per ray scene index, or null (scene 0)
   int sh_degree;
   const float* ray_o;
   const float* ray_d;
@@ -257,6 +257,7 @@ __global__ void __launch_bounds__(kTraceBlock)
 
   int state = kIdle;
   int ray = -1;
+  int sid = 0;  // scene of the lane's ray
   float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, ix = 0, iy = 0, iz = 0;
   uint64_t kb[K];
   kbuf_reset(kb, A.k);
@@ -279,11 +280,11 @@ __global__ void __launch_bounds__(kTraceBlock)
 
   auto root_start = [&]() __attribute__((always_inline)) {
     // (Re)start at the root; subtrees that end before tmin are culled.
-    const float* rb = A.root_box;
+    const float* rb = A.roots + 8 * sid;
     Slab s = slab(rb[0], rb[1], rb[2], rb[3], rb[4], rb[5], ox, oy, oz, ix, iy, iz);
     float tlo = fmaxf(tnear, key_t(tmin));
     has_cur = s.tn <= s.tf && s.tf >= tlo;
-    cur_ref = A.root_ref;
+    cur_ref = __float_as_uint(rb[6]);
     cur_t = s.tn;
     sp = 0;
   };
@@ -366,6 +367,7 @@ __global__ void __launch_bounds__(kTraceBlock)
           }
           if (r >= 0) {
             ray = r;
+            sid = A.ray_scene ? A.ray_scene[r] : 0;
             const float* ro = A.ray_o + 3 * (int64_t)r;
             const float* rd = A.ray_d + 3 * (int64_t)r;
             ox = ro[0]; oy = ro[1]; oz = ro[2];
@@ -707,11 +709,27 @@ grtx_status launch_k(int K, const TraceArgs& a, int blocks, hipStream_t s) {
 
 }  // namespace
 
+int64_t trace_pool_bytes(int K, int cap_d, int cap_e) {
+  int device = 0, cus = 0;
+  if (hipGetDevice(&device) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+  const int64_t blocks = (int64_t)cus * blocks_per_cu_k<false>(K);
+  const int64_t rows = kSpillRows + 2 * (int64_t)cap_d + 2 * (int64_t)cap_e + K;
+  const int64_t need = blocks * kWaves * rows * 64 * (int64_t)sizeof(uint2) + 256;
+  return need + need / 4;
+}
+
 grtx_status trace(const Bvh* b, const grtx_rays* r, const grtx_trace_params* p, const grtx_trace_outputs* o,
                   hipStream_t s) {
+  TraceScene sc{b->nodes, b->inst, b->tris, b->sh, b->sh_degree, b->roots, nullptr, b->kind, b->n_leaves};
+  return launch_trace(sc, r, p, o, s);
+}
+
+grtx_status launch_trace(const TraceScene& b, const grtx_rays* r, const grtx_trace_params* p,
+                         const grtx_trace_outputs* o, hipStream_t s) {
   const int64_t R = r->count;
   if (R == 0) return GRTX_OK;
-  if (b->n_leaves == 0) {
+  if (b.n_leaves == 0) {
     hipLaunchKernelGGL(k_fill_background, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, o->rgb, o->depth,
                        o->opacity, o->stats, o->hit_counts, R, p->bg[0], p->bg[1], p->bg[2]);
     GRTX_LAUNCH_CHECK();
@@ -728,7 +746,7 @@ grtx_status trace(const Bvh* b, const grtx_rays* r, const grtx_trace_params* p, 
     cached_cus = prop.multiProcessorCount;
   }
   const int K = p->k <= 4 ? 4 : p->k <= 8 ? 8 : p->k <= 16 ? 16 : p->k <= 32 ? 32 : 64;
-  const bool proxy = b->kind == GRTX_BVH_PROXY20;
+  const bool proxy = b.kind == GRTX_BVH_PROXY20;
   int bpc = proxy ? blocks_per_cu_k<true>(K) : blocks_per_cu_k<false>(K);
   int blocks = cached_cus * bpc;
   // never more waves than rays need
@@ -756,13 +774,13 @@ grtx_status trace(const Bvh* b, const grtx_rays* r, const grtx_trace_params* p, 
   }
 
   TraceArgs a{};
-  a.nodes = b->nodes;
-  a.inst = b->inst;
-  a.tris = b->tris;
-  a.sh = b->sh;
-  a.root_box = b->root_box;
-  a.root_ref = b->n_leaves == 1 ? (kLeafFlag | 0u) : 0u;
-  a.sh_degree = b->sh_degree;
+  a.nodes = b.nodes;
+  a.inst = b.inst;
+  a.tris = b.tris;
+  a.sh = b.sh;
+  a.roots = b.roots;
+  a.ray_scene = b.ray_scene;
+  a.sh_degree = b.sh_degree;
   a.ray_o = r->origins;
   a.ray_d = r->dirs;
   a.n_rays = R;

@@ -80,6 +80,29 @@ class _Camera(C.Structure):
                 ("width", C.c_int32), ("height", C.c_int32)]
 
 
+class _ServeConfig(C.Structure):
+    _fields_ = [("memory_budget", C.c_int64), ("slots", C.c_int32), ("k", C.c_int32), ("T_min", C.c_float),
+                ("mode", C.c_int32), ("max_batch_rays", C.c_int32), ("bg", C.c_float * 3)]
+
+
+class _Request(C.Structure):
+    _fields_ = [("scene_id", C.c_int32), ("width", C.c_int32), ("height", C.c_int32), ("eye", C.c_float * 3),
+                ("target", C.c_float * 3), ("up", C.c_float * 3), ("fov_y_deg", C.c_float)]
+
+
+class _RequestResult(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p), ("opacity", C.c_void_p), ("width", C.c_int32),
+                ("height", C.c_int32), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_launch", C.c_double), ("t_done", C.c_double)]
+
+
+class _ServeStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rays_completed", C.c_int64),
+                ("bytes_in_use", C.c_int64), ("bytes_available", C.c_int64), ("p50_ms", C.c_double),
+                ("p99_ms", C.c_double), ("mean_ms", C.c_double), ("max_ms", C.c_double), ("busy_s", C.c_double),
+                ("mrays_per_s", C.c_double)]
+
+
 # Every symbol the header declares, with its ctypes signature.
 _SIGNATURES = {
     "grtx_build": (C.c_int, [C.POINTER(_Gaussians), C.c_int, C.POINTER(_BuildParams), C.c_void_p,
@@ -94,6 +117,15 @@ _SIGNATURES = {
     "grtx_trace_backward": (C.c_int, [C.c_void_p, C.POINTER(_Gaussians), C.POINTER(_Rays), C.POINTER(_TraceParams),
                                       C.POINTER(_TraceOutputs), C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.POINTER(_GaussianGrads), C.c_void_p, C.c_void_p]),
+    "grtx_serve_request_bytes": (C.c_int, [C.POINTER(_Request), C.POINTER(C.c_int64)]),
+    "grtx_serve_create": (C.c_int, [C.POINTER(_ServeConfig), C.POINTER(C.c_void_p)]),
+    "grtx_serve_add_scene": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
+    "grtx_serve_submit": (C.c_int, [C.c_void_p, C.POINTER(_Request), C.POINTER(C.c_uint64)]),
+    "grtx_serve_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(_RequestResult)]),
+    "grtx_serve_copy_result": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "grtx_serve_release": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "grtx_serve_get_stats": (C.c_int, [C.c_void_p, C.POINTER(_ServeStats)]),
+    "grtx_serve_destroy": (C.c_int, [C.c_void_p]),
     "grtx_last_error": (C.c_char_p, []),
     "grtx_version": (C.c_int32, []),
 }
@@ -276,6 +308,83 @@ def trace_backward(bvh: Bvh, origins, dirs, fwd: dict, grad_rgb=None, grad_depth
                                      _ptr(grad_rgb), _ptr(grad_depth), _ptr(grad_opacity), C.byref(gg),
                                      _ptr(truncated), _stream(stream)))
     return grads, truncated
+
+
+def _request(scene_id, camera):
+    return _Request(scene_id, camera.width, camera.height, (C.c_float * 3)(*camera.eye),
+                    (C.c_float * 3)(*camera.target), (C.c_float * 3)(*camera.up), camera.fov_y_deg)
+
+
+def request_bytes(camera):
+    b = C.c_int64()
+    _check(lib().grtx_serve_request_bytes(C.byref(_request(0, camera)), C.byref(b)))
+    return int(b.value)
+
+
+class Server:
+    """Continuous-batching render server (grtx_serve_*)."""
+
+    def __init__(self, memory_budget, slots=2, k=16, T_min=1e-3, mode=CHECKPOINT, max_batch_rays=0,
+                 bg=(0.0, 0.0, 0.0)):
+        cfg = _ServeConfig(int(memory_budget), slots, k, T_min, mode, max_batch_rays, (C.c_float * 3)(*bg))
+        h = C.c_void_p()
+        _check(lib().grtx_serve_create(C.byref(cfg), C.byref(h)))
+        self.handle = h
+        self._bvhs = []
+
+    def add_scene(self, bvh: Bvh) -> int:
+        sid = C.c_int32()
+        _check(lib().grtx_serve_add_scene(self.handle, bvh.handle, C.byref(sid)))
+        self._bvhs.append(bvh)
+        return int(sid.value)
+
+    def submit(self, scene_id, camera) -> int:
+        t = C.c_uint64()
+        _check(lib().grtx_serve_submit(self.handle, C.byref(_request(scene_id, camera)), C.byref(t)))
+        return int(t.value)
+
+    def poll(self, ticket):
+        """None while pending; else a dict of timestamps and the image size."""
+        r = _RequestResult()
+        st = lib().grtx_serve_poll(self.handle, ticket, C.byref(r))
+        if st == ERR_NOT_READY:
+            return None
+        _check(st)
+        return dict(width=r.width, height=r.height, t_submit=r.t_submit, t_admit=r.t_admit, t_launch=r.t_launch,
+                    t_done=r.t_done)
+
+    def result(self, ticket, device="cuda", stream=None):
+        info = self.poll(ticket)
+        if info is None:
+            return None
+        n = info["width"] * info["height"]
+        out = dict(rgb=torch.empty((n, 3), dtype=torch.float32, device=device),
+                   depth=torch.empty(n, dtype=torch.float32, device=device),
+                   opacity=torch.empty(n, dtype=torch.float32, device=device))
+        _check(lib().grtx_serve_copy_result(self.handle, ticket, _ptr(out["rgb"]), _ptr(out["depth"]),
+                                            _ptr(out["opacity"]), _stream(stream)))
+        out.update(info)
+        return out
+
+    def release(self, ticket):
+        _check(lib().grtx_serve_release(self.handle, ticket))
+
+    def stats(self):
+        st = _ServeStats()
+        _check(lib().grtx_serve_get_stats(self.handle, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in _ServeStats._fields_}
+
+    def close(self):
+        if self.handle:
+            _check(lib().grtx_serve_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().grtx_serve_destroy(self.handle)
+        except Exception:
+            pass
 
 
 def version():

@@ -72,3 +72,22 @@ def test_trace_rejects_bad_arguments():
 def test_binding_raises_on_error():
     with pytest.raises(grtx.GrtxError):
         grtx._check(grtx.ERR_INVALID_ARG)
+
+
+def test_serving_request_bytes_and_validation():
+    """Admission accounting is host-only: a request holds its rays (24 B origin and
+    direction + 4 B scene index), batch outputs (20 B) and its own outputs (20 B) per
+    pixel. Bad server configurations are refused before any device call."""
+    from paper_2601_20429_amd import inputs
+    cam = inputs.orbit_camera(800, 600)
+    assert grtx.request_bytes(cam) == 800 * 600 * 68
+    L = grtx.lib()
+    h = C.c_void_p()
+    for cfg in [grtx._ServeConfig(0, 2, 16, 1e-3, 0, 0, (C.c_float * 3)()),
+                grtx._ServeConfig(1 << 30, 2, 0, 1e-3, 0, 0, (C.c_float * 3)()),
+                grtx._ServeConfig(1 << 30, 2, 16, 1.0, 0, 0, (C.c_float * 3)()),
+                grtx._ServeConfig(1 << 30, 99, 16, 1e-3, 0, 0, (C.c_float * 3)()),
+                grtx._ServeConfig(1 << 30, 2, 16, 1e-3, 5, 0, (C.c_float * 3)())]:
+        assert L.grtx_serve_create(C.byref(cfg), C.byref(h)) == grtx.ERR_INVALID_ARG
+    assert h.value is None
+    assert L.grtx_serve_destroy(None) == grtx.OK
