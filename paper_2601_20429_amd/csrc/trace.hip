@@ -58,10 +58,6 @@ constexpr int kRefillThreshold = GRTX_REFILL_THRESHOLD;  // idle lanes that end 
 #define GRTX_CHUNKS 1
 #endif
 constexpr int kChunks = GRTX_CHUNKS;  // one per XCD
-// Pool header: the work counters at offset 0, the launch's argument block at
-// kArgsOffset, the per-wave rows from kPoolHeader on.
-constexpr size_t kArgsOffset = 256;
-constexpr size_t kPoolHeader = 1024;
 constexpr uint64_t kEmptyKey = (0x7F800000ull << 32) | 0xFFFFFFFFull;  // (+inf, max)
 
 enum : int { kIdle = 0, kTrav = 1, kEnd = 2 };
@@ -100,8 +96,6 @@ struct TraceArgs {
   unsigned int* counter;  // kChunks work counters
   int64_t chunk_len;      // work items per chunk (a multiple of 64)
 };
-static_assert(sizeof(TraceArgs) <= kPoolHeader - kArgsOffset, "argument block exceeds the pool header");
-
 
 __device__ __forceinline__ float key_t(uint64_t k) { return __uint_as_float((uint32_t)(k >> 32)); }
 __device__ __forceinline__ uint64_t make_key(float t, uint32_t id) {
@@ -238,9 +232,7 @@ __device__ __forceinline__ bool proxy_hit(float4 A4, float4 B4, float4 C4, float
 
 template <int K, bool PROXY, bool STATS>
 __global__ void __launch_bounds__(kTraceBlock)
-    __attribute__((amdgpu_waves_per_eu(K <= 16 ? GRTX_MIN_WAVES_K16 : 2, 8))) k_trace(TraceArgs A, const TraceArgs* __restrict__ Cp) {
-  // A: arguments of the traversal loop (kernel arguments); Cp: the same block in device
-  // memory, read for the fields used at ray start and at blend only.
+    __attribute__((amdgpu_waves_per_eu(K <= 16 ? GRTX_MIN_WAVES_K16 : 2, 8))) k_trace(TraceArgs A) {
   __shared__ uint2 s_stack[kLdsStack * kTraceBlock];
   __shared__ uint32_t s_stat[STATS ? GRTX_STATS_FIELDS : 1][kTraceBlock];  // per-lane counters
   const int tid = threadIdx.x;
@@ -268,7 +260,7 @@ __global__ void __launch_bounds__(kTraceBlock)
   int sid = 0;  // scene of the lane's ray
   float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, ix = 0, iy = 0, iz = 0;
   uint64_t kb[K];
-  kbuf_reset(kb, Cp->k);
+  kbuf_reset(kb, A.k);
   uint64_t tmin = 0;  // key of the last blended hit
   float C0 = 0, C1 = 0, C2 = 0, Dp = 0, T = 1;
   uint32_t cur_ref = 0;  // item in hand: internal node or leaf (has_cur)
@@ -288,7 +280,7 @@ __global__ void __launch_bounds__(kTraceBlock)
 
   auto root_start = [&]() __attribute__((always_inline)) {
     // (Re)start at the root; subtrees that end before tmin are culled.
-    const float* rb = Cp->roots + 8 * sid;
+    const float* rb = A.roots + 8 * sid;
     Slab s = slab(rb[0], rb[1], rb[2], rb[3], rb[4], rb[5], ox, oy, oz, ix, iy, iz);
     float tlo = fmaxf(tnear, key_t(tmin));
     has_cur = s.tn <= s.tf && s.tf >= tlo;
@@ -348,9 +340,9 @@ __global__ void __launch_bounds__(kTraceBlock)
         unsigned int base = 0;
         int64_t avail = 0;
         while (true) {
-          if (lane == leader) base = atomicAdd(Cp->counter + chunk, (unsigned int)cnt);
+          if (lane == leader) base = atomicAdd(A.counter + chunk, (unsigned int)cnt);
           base = __shfl(base, leader);
-          avail = Cp->chunk_len - (int64_t)base;
+          avail = A.chunk_len - (int64_t)base;
           if (avail > 0) break;
           chunk = chunk + 1 == kChunks ? 0 : chunk + 1;
           if (++chunks_tried == kChunks) {
@@ -360,28 +352,28 @@ __global__ void __launch_bounds__(kTraceBlock)
         }
         if (state == kIdle && !exhausted) {
           int64_t rank = __popcll(idle & lt_mask);
-          int64_t w = (int64_t)chunk * Cp->chunk_len + base + rank;
+          int64_t w = (int64_t)chunk * A.chunk_len + base + rank;
           int r = -1;
-          if (rank < avail && w < Cp->n_work) {
-            if (Cp->image_w > 0) {
+          if (rank < avail && w < A.n_work) {
+            if (A.image_w > 0) {
               int64_t tile = w >> 6;
               int within = (int)(w & 63);
-              int64_t ty = tile / Cp->tiles_x, tx = tile - ty * Cp->tiles_x;
+              int64_t ty = tile / A.tiles_x, tx = tile - ty * A.tiles_x;
               int64_t px = tx * 8 + (within & 7), py = ty * 8 + (within >> 3);
-              if (px < Cp->image_w && py < Cp->image_h) r = (int)(py * Cp->image_w + px);
+              if (px < A.image_w && py < A.image_h) r = (int)(py * A.image_w + px);
             } else {
               r = (int)w;
             }
           }
           if (r >= 0) {
             ray = r;
-            sid = Cp->ray_scene ? Cp->ray_scene[r] : 0;
-            const float* ro = Cp->ray_o + 3 * (int64_t)r;
-            const float* rd = Cp->ray_d + 3 * (int64_t)r;
+            sid = A.ray_scene ? A.ray_scene[r] : 0;
+            const float* ro = A.ray_o + 3 * (int64_t)r;
+            const float* rd = A.ray_d + 3 * (int64_t)r;
             ox = ro[0]; oy = ro[1]; oz = ro[2];
             dx = rd[0]; dy = rd[1]; dz = rd[2];
             ix = safe_inv(dx); iy = safe_inv(dy); iz = safe_inv(dz);
-            kbuf_reset(kb, Cp->k);
+            kbuf_reset(kb, A.k);
             tmin = 0;
             C0 = C1 = C2 = Dp = 0.f;
             T = 1.f;
@@ -531,19 +523,19 @@ __global__ void __launch_bounds__(kTraceBlock)
     // ---------------------------------------------------------------- round end: blend
     if (state == kEnd) {
       STAT(GRTX_STAT_ROUNDS);
-      const int ncoef = (Cp->sh_degree + 1) * (Cp->sh_degree + 1);
+      const int ncoef = (A.sh_degree + 1) * (A.sh_degree + 1);
       bool ert = false;
       // Blend in key order. The k-buffer is parked in the lane's rows so that the blend
       // loop indexes memory rather than a register array.
       const uint64_t last = kb[K - 1];
 #pragma unroll
       for (int j = 0; j < K; ++j)
-        if (j >= K - Cp->k) ROW(rowK + j) = make_uint2((uint32_t)kb[j], (uint32_t)(kb[j] >> 32));
+        if (j >= K - A.k) ROW(rowK + j) = make_uint2((uint32_t)kb[j], (uint32_t)(kb[j] >> 32));
       // proxy keys carry the Gaussian id: a mesh crossed exactly on an edge reports the
       // same Gaussian twice with adjacent keys; only the first is blended
       uint32_t prev_id = tmin == 0ull ? 0xFFFFFFFFu : (uint32_t)tmin;
 #pragma unroll 1
-      for (int j = K - Cp->k; j < K && !ert; ++j) {
+      for (int j = K - A.k; j < K && !ert; ++j) {
         const uint2 kv = ROW(rowK + j);
         const uint64_t x = ((uint64_t)kv.y << 32) | kv.x;
         if (x == kEmptyKey) break;
@@ -566,9 +558,9 @@ __global__ void __launch_bounds__(kTraceBlock)
           float c[3] = {0.5f, 0.5f, 0.5f};
           const float dn = rsqrtf(dx * dx + dy * dy + dz * dz);
           float Y[16];
-          sh_basis(dx * dn, dy * dn, dz * dn, Cp->sh_degree, Y);
-          if (Cp->sh_degree == 3) {
-            const float4* sp4 = reinterpret_cast<const float4*>(Cp->sh + (int64_t)gid * 48);
+          sh_basis(dx * dn, dy * dn, dz * dn, A.sh_degree, Y);
+          if (A.sh_degree == 3) {
+            const float4* sp4 = reinterpret_cast<const float4*>(A.sh + (int64_t)gid * 48);
 #pragma unroll
             for (int q = 0; q < 12; ++q) {
               float4 v = sp4[q];
@@ -580,7 +572,7 @@ __global__ void __launch_bounds__(kTraceBlock)
               }
             }
           } else {
-            const float* sc = Cp->sh + (int64_t)gid * 3 * ncoef;
+            const float* sc = A.sh + (int64_t)gid * 3 * ncoef;
 #pragma unroll
             for (int f = 0; f < 16; ++f) {
               if (f < ncoef) {
@@ -596,30 +588,30 @@ __global__ void __launch_bounds__(kTraceBlock)
           C2 += w * fmaxf(c[2], 0.f);
           Dp += w * talpha;
           T *= (1.f - alpha);
-          if (Cp->hit_ids && nblend < Cp->hit_cap) Cp->hit_ids[(int64_t)ray * Cp->hit_cap + nblend] = (int32_t)gid;
+          if (A.hit_ids && nblend < A.hit_cap) A.hit_ids[(int64_t)ray * A.hit_cap + nblend] = (int32_t)gid;
           ++nblend;
-          if (T < Cp->T_min) ert = true;
+          if (T < A.T_min) ert = true;
         }  // blend
       }
       const bool full = last != kEmptyKey;
       const bool done = ert || !full || (ckpt && !overflow && ndst_n == 0 && edst_n == 0);
       if (done) {
-        Cp->rgb[3 * (int64_t)ray + 0] = C0 + T * Cp->bg0;
-        Cp->rgb[3 * (int64_t)ray + 1] = C1 + T * Cp->bg1;
-        Cp->rgb[3 * (int64_t)ray + 2] = C2 + T * Cp->bg2;
-        Cp->depth[ray] = Dp;
-        Cp->opac[ray] = 1.f - T;
-        if (Cp->hit_counts) Cp->hit_counts[ray] = nblend;
+        A.rgb[3 * (int64_t)ray + 0] = C0 + T * A.bg0;
+        A.rgb[3 * (int64_t)ray + 1] = C1 + T * A.bg1;
+        A.rgb[3 * (int64_t)ray + 2] = C2 + T * A.bg2;
+        A.depth[ray] = Dp;
+        A.opac[ray] = 1.f - T;
+        if (A.hit_counts) A.hit_counts[ray] = nblend;
         if constexpr (STATS) {
           s_stat[GRTX_STAT_BLENDED][tid] = (uint32_t)nblend;
-          uint32_t* st = Cp->stats + (int64_t)ray * GRTX_STATS_FIELDS;
+          uint32_t* st = A.stats + (int64_t)ray * GRTX_STATS_FIELDS;
 #pragma unroll
           for (int f = 0; f < GRTX_STATS_FIELDS; ++f) st[f] = s_stat[f][tid];
         }
         state = kIdle;
       } else {
         tmin = last;
-        kbuf_reset(kb, Cp->k);
+        kbuf_reset(kb, A.k);
         if (!ckpt || overflow) {
           // restart from the root beyond the last blended hit
           if (ckpt) STAT(GRTX_STAT_FALLBACKS);
@@ -647,13 +639,8 @@ __global__ void __launch_bounds__(kTraceBlock)
 #undef STAT
 }
 
-// Zeroes the work counters and stores the launch's argument block in device memory.
-// The trace kernel reads its rarely used arguments (outputs, image shape, colour
-// constants) from there rather than from kernel arguments: the latter would be held in
-// scalar registers for the whole kernel and spill.
-__global__ void k_trace_setup(TraceArgs a, TraceArgs* dst, unsigned int* c) {
+__global__ void k_reset_counter(unsigned int* c) {
   if (threadIdx.x < kChunks) c[threadIdx.x] = 0u;
-  if (threadIdx.x == 0) *dst = a;
 }
 
 __global__ void __launch_bounds__(256) k_fill_background(float* rgb, float* depth, float* opac, uint32_t* stats,
@@ -683,11 +670,11 @@ std::mutex g_pool_lock;
 std::map<std::pair<int, hipStream_t>, Pool> g_pools;
 
 template <int K, bool PROXY>
-grtx_status launch(const TraceArgs& a, TraceArgs* dargs, int blocks, hipStream_t s) {
+grtx_status launch(const TraceArgs& a, int blocks, hipStream_t s) {
   if (a.stats)
-    hipLaunchKernelGGL((k_trace<K, PROXY, true>), dim3(blocks), dim3(kTraceBlock), 0, s, a, dargs);
+    hipLaunchKernelGGL((k_trace<K, PROXY, true>), dim3(blocks), dim3(kTraceBlock), 0, s, a);
   else
-    hipLaunchKernelGGL((k_trace<K, PROXY, false>), dim3(blocks), dim3(kTraceBlock), 0, s, a, dargs);
+    hipLaunchKernelGGL((k_trace<K, PROXY, false>), dim3(blocks), dim3(kTraceBlock), 0, s, a);
   GRTX_LAUNCH_CHECK();
   return GRTX_OK;
 }
@@ -710,13 +697,13 @@ int blocks_per_cu_k(int K) {
 }
 
 template <bool PROXY>
-grtx_status launch_k(int K, const TraceArgs& a, TraceArgs* dargs, int blocks, hipStream_t s) {
+grtx_status launch_k(int K, const TraceArgs& a, int blocks, hipStream_t s) {
   switch (K) {
-    case 4: return launch<4, PROXY>(a, dargs, blocks, s);
-    case 8: return launch<8, PROXY>(a, dargs, blocks, s);
-    case 16: return launch<16, PROXY>(a, dargs, blocks, s);
-    case 32: return launch<32, PROXY>(a, dargs, blocks, s);
-    default: return launch<64, PROXY>(a, dargs, blocks, s);
+    case 4: return launch<4, PROXY>(a, blocks, s);
+    case 8: return launch<8, PROXY>(a, blocks, s);
+    case 16: return launch<16, PROXY>(a, blocks, s);
+    case 32: return launch<32, PROXY>(a, blocks, s);
+    default: return launch<64, PROXY>(a, blocks, s);
   }
 }
 
@@ -728,7 +715,7 @@ int64_t trace_pool_bytes(int K, int cap_d, int cap_e) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
   const int64_t blocks = (int64_t)cus * blocks_per_cu_k<false>(K);
   const int64_t rows = kSpillRows + 2 * (int64_t)cap_d + 2 * (int64_t)cap_e + K;
-  const int64_t need = blocks * kWaves * rows * 64 * (int64_t)sizeof(uint2) + kPoolHeader;
+  const int64_t need = blocks * kWaves * rows * 64 * (int64_t)sizeof(uint2) + 256;
   return need + need / 4;
 }
 
@@ -769,7 +756,7 @@ grtx_status launch_trace(const TraceScene& b, const grtx_rays* r, const grtx_tra
   const int cap_d = p->defer_capacity > 0 ? p->defer_capacity : 128;
   const int cap_e = p->evict_capacity > 0 ? p->evict_capacity : 128;
   const int64_t rows = kSpillRows + 2 * (int64_t)cap_d + 2 * (int64_t)cap_e + K;
-  const size_t need = (size_t)blocks * kWaves * rows * 64 * sizeof(uint2) + kPoolHeader;
+  const size_t need = (size_t)blocks * kWaves * rows * 64 * sizeof(uint2) + 256;
 
   Pool* pool = nullptr;
   {
@@ -824,15 +811,13 @@ grtx_status launch_trace(const TraceScene& b, const grtx_rays* r, const grtx_tra
   a.hit_counts = o->hit_counts;
   a.hit_cap = o->hit_ids ? o->hit_capacity : 0;
   a.counter = pool->counter;
-  a.pool = reinterpret_cast<uint2*>(reinterpret_cast<char*>(pool->ptr) + kPoolHeader);
+  a.pool = reinterpret_cast<uint2*>(reinterpret_cast<char*>(pool->ptr) + 256);
   a.rows_per_wave = rows;
   a.cap_d = cap_d;
   a.cap_e = cap_e;
   a.chunk_len = ((a.n_work + 64 * kChunks - 1) / (64 * kChunks)) * 64;
-  TraceArgs* dargs = reinterpret_cast<TraceArgs*>(reinterpret_cast<char*>(pool->ptr) + kArgsOffset);
-  hipLaunchKernelGGL(k_trace_setup, dim3(1), dim3(64), 0, s, a, dargs, pool->counter);
-  GRTX_LAUNCH_CHECK();
-  return proxy ? launch_k<true>(K, a, dargs, blocks, s) : launch_k<false>(K, a, dargs, blocks, s);
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, pool->counter);
+  return proxy ? launch_k<true>(K, a, blocks, s) : launch_k<false>(K, a, blocks, s);
 }
 
 }  // namespace grtx
