@@ -74,26 +74,143 @@ def run_serving(n_requests):
                 time.sleep(dt)
             tickets.append(srv.submit(sid, cam))
 
-    base = srv.stats()
     th = threading.Thread(target=submitter)
     th.start()
     done = 0
+    lat, wait, service, pixels = [], [], [], 0
+    t_first, t_last = None, None
     while done < n_requests:
-        for t in list(tickets):
-            if t > 0 and srv.poll(t) is not None:
-                srv.release(t)
-                tickets[tickets.index(t)] = -1
-                done += 1
+        for j, t in enumerate(list(tickets)):
+            if t > 0:
+                r = srv.poll(t)
+                if r is not None:
+                    lat.append(r["t_done"] - r["t_submit"])
+                    wait.append(r["t_admit"] - r["t_submit"])
+                    service.append(r["t_done"] - r["t_admit"])
+                    pixels += r["width"] * r["height"]
+                    t_first = r["t_submit"] if t_first is None else min(t_first, r["t_submit"])
+                    t_last = r["t_done"] if t_last is None else max(t_last, r["t_done"])
+                    srv.release(t)
+                    tickets[j] = -1
+                    done += 1
         time.sleep(0.0005)
     th.join()
-    st = srv.stats()
     srv.close()
-    rays = st["rays_completed"] - base["rays_completed"]
+    lat, wait, service = (np.array(x) * 1e3 for x in (lat, wait, service))
     offered = sum(c.width * c.height for _, _, c in plan) / plan[-1][0] / 1e6
-    return dict(workload=cfg["name"], requests=n_requests, p50_ms=st["p50_ms"], p99_ms=st["p99_ms"],
-                mean_ms=st["mean_ms"], max_ms=st["max_ms"], mrays_s=st["mrays_per_s"], rays=rays,
-                offered_mrays_s=offered, scenes=list(cfg["scene_sizes"]),
-                note="latency percentiles include the warm-up requests")
+    return dict(workload=cfg["name"], requests=n_requests, p50_ms=float(np.percentile(lat, 50)),
+                p99_ms=float(np.percentile(lat, 99)), mean_ms=float(lat.mean()), max_ms=float(lat.max()),
+                queue_wait_p50_ms=float(np.percentile(wait, 50)), service_p50_ms=float(np.percentile(service, 50)),
+                service_p99_ms=float(np.percentile(service, 99)),
+                mrays_s=pixels / (t_last - t_first) / 1e6, rays=pixels, offered_mrays_s=offered,
+                scenes=list(cfg["scene_sizes"]),
+                note="latency = submission to completion of each timed request; service = admission to completion")
+
+
+def time_launch(fn, stream, reps):
+    """Mean duration (ms) of what `fn` enqueues on `stream`, from HIP events on that stream."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return sum(ts) / len(ts)
+
+
+def run_proxy(st, cam, cfg, k, stream):
+    """The same frame traced over the 20-face proxy BVH (one BVH leaf per triangle)."""
+    import numpy as np
+    import torch
+
+    from paper_2601_20429_amd import grtx
+    amin = float(np.float32(cfg["alpha_min"]))
+    o, d = grtx.pinhole_rays(cam)
+    t0 = time.perf_counter()
+    pb = grtx.build(st, alpha_min=amin, kind=grtx.PROXY20)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    res = {}
+    for m, name in [(grtx.CHECKPOINT, "checkpoint"), (grtx.RESTART, "restart")]:
+        out = grtx.trace(pb, o, d, k=k, T_min=cfg["T_min"], mode=m, image_width=cam.width)
+        ms = time_launch(lambda: grtx.trace(pb, o, d, k=k, T_min=cfg["T_min"], mode=m, image_width=cam.width,
+                                            out=out), stream, 3)
+        s = grtx.trace(pb, o, d, k=k, T_min=cfg["T_min"], mode=m, image_width=cam.width, stats=True)
+        stt = s["stats"].to(torch.int64).sum(0).cpu().numpy()
+        res[f"proxy_{name}_trace_ms"] = ms
+        res[f"proxy_{name}_mrays_s"] = cam.n_rays / (ms * 1e-3) / 1e6
+        res[f"proxy_{name}_nodes_per_ray"] = float(stt[0] + stt[1]) / cam.n_rays
+    info = pb.info()
+    res["proxy_build_ms"] = build_ms
+    res["proxy_bvh_bytes"] = int(info["device_bytes"])
+    del pb
+    return res
+
+
+def run_backward(stream):
+    """Differentiation workload: 200k Gaussians, 512x512 rays, k = 16; the forward pass keeps
+    each ray's blended ids, the backward kernel replays them."""
+    import numpy as np
+    import torch
+
+    from paper_2601_20429_amd import grtx, inputs
+    cfg = inputs.DIFF200K
+    st = grtx.SceneTensors.from_scene(inputs.cluster_scene(cfg["seed"], cfg["n"], 3), "cuda")
+    cam = inputs.orbit_camera(cfg["width"], cfg["height"])
+    o, d = grtx.pinhole_rays(cam)
+    bvh = grtx.build(st, alpha_min=float(np.float32(cfg["alpha_min"])))
+    fwd = grtx.trace(bvh, o, d, k=cfg["k"], T_min=cfg["T_min"], hit_capacity=256)
+    g_rgb = torch.ones_like(fwd["rgb"])
+    f_ms = time_launch(lambda: grtx.trace(bvh, o, d, k=cfg["k"], T_min=cfg["T_min"], hit_capacity=256, out=fwd),
+                       stream, 3)
+    b_ms = time_launch(lambda: grtx.trace_backward(bvh, o, d, fwd, grad_rgb=g_rgb, k=cfg["k"], T_min=cfg["T_min"]),
+                       stream, 3)
+    R = cam.n_rays
+    return dict(workload=cfg["name"], forward_with_ids_ms=f_ms, backward_ms=b_ms,
+                backward_mrays_s=R / (b_ms * 1e-3) / 1e6,
+                note="backward_ms includes zeroing the gradient arrays")
+
+
+def kernel_k(k):
+    return 4 if k <= 4 else 8 if k <= 8 else 16 if k <= 16 else 32 if k <= 32 else 64
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_trace_k16_scene100k_hbm_traffic.txt")
+TRACE_SOURCES = [os.path.join(ROOT, "paper_2601_20429_amd", "csrc", f) for f in ("trace.hip", "grtx_internal.h")]
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRACE_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(args):
+    """HBM bytes per launch of the timed kernel from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None when that
+    summary was taken on other kernel sources or another launch configuration."""
+    if args.k != 16 or args.mode != "checkpoint" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    fields = {}
+    with open(TRAFFIC_PROFILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(" "):
+                key, _, val = line.partition(":")
+                fields[key.strip()] = val.strip()
+    if fields.get("source_sha256") != source_digest():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def main():
@@ -110,6 +227,8 @@ def main():
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="first copy this many GiB device-to-device (a reference kernel for HBM counters)")
     ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--no-proxy", action="store_true", help="skip the 20-face proxy BVH comparison")
+    ap.add_argument("--no-backward", action="store_true", help="skip the backward-pass timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the ray-sharded multi-GPU "
@@ -211,6 +330,16 @@ def main():
         extra[f"{name}_nodes_per_ray"] = float(s2[0] + s2[1]) / R
         log(f"{name}: step {ms2:.3f} ms, trace {k2:.3f} ms, nodes/ray {extra[f'{name}_nodes_per_ray']:.1f}")
 
+    info = bvh.info()
+    extra["bvh_bytes"] = int(info["device_bytes"])
+    if not args.no_proxy:
+        extra.update(run_proxy(st, cam, cfg, args.k, stream))
+        log("proxy", json.dumps({k: v for k, v in extra.items() if k.startswith("proxy")}))
+    backward = None
+    if not args.no_backward:
+        backward = run_backward(stream)
+        log("backward", json.dumps(backward))
+
     serving = None
     if not args.no_serving:
         serving = run_serving(args.serve_requests)
@@ -249,9 +378,11 @@ def main():
                    "step": "raygen + LBVH build + trace"},
         "nodes_per_ray": extra["nodes_per_ray"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"k_trace<{16 if args.k > 8 else args.k}>"},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args),
+                     "kernel": f"k_trace<{kernel_k(args.k)}>"},
         "cpu_baseline": cpu,
         "serving": serving,
+        "backward": backward,
         "extra": extra,
     }
     print(json.dumps(rec), flush=True)
