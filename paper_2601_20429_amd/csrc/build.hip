@@ -255,7 +255,8 @@ __device__ __forceinline__ int prefix_len(const uint64_t* __restrict__ codes, in
 }
 
 __global__ void __launch_bounds__(kBlock) k_karras(const uint64_t* __restrict__ codes, int64_t n,
-                                                   uint32_t* __restrict__ child, uint32_t* __restrict__ parent) {
+                                                   uint32_t* __restrict__ child, uint32_t* __restrict__ parent,
+                                                   uint2* __restrict__ range) {
   int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   if (i >= n - 1) return;
   int d = prefix_len(codes, n, i, i + 1) - prefix_len(codes, n, i, i - 1) > 0 ? 1 : -1;
@@ -292,6 +293,7 @@ __global__ void __launch_bounds__(kBlock) k_karras(const uint64_t* __restrict__ 
   }
   child[2 * i] = left;
   child[2 * i + 1] = right;
+  range[i] = make_uint2((uint32_t)lo, (uint32_t)hi);
   if (i == 0) parent[0] = kNoParent;
 }
 
@@ -463,36 +465,124 @@ __global__ void __launch_bounds__(kBlock) k_proxy_leaves(const uint32_t* __restr
 
 // ------------------------------------------------------------------ refit
 
-__device__ __forceinline__ float ld_coherent(const float* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Refit in two phases. An internal node of the radix tree covers a contiguous range of
+// sorted leaves. "Small" nodes (at most kRefitSmall leaves) take their children's boxes
+// straight from the leaf boxes of the two sub-ranges: no ordering between threads is
+// needed. The few "top" nodes above them are refitted bottom-up by one workgroup, which
+// orders its threads with workgroup-scope atomics; a grid-wide bottom-up pass would need a
+// device-scope fence per node, which on a multi-XCD part writes back the whole L2.
+constexpr int64_t kRefitSmall = 128;
+constexpr int kTopBlock = 1024;
+
+__device__ __forceinline__ bool is_small(uint32_t c, const uint2* __restrict__ range) {
+  if (c & kLeafFlag) return true;
+  uint2 r = range[c];
+  return (int64_t)r.y - r.x + 1 <= kRefitSmall;
 }
 
-__global__ void __launch_bounds__(kBlock) k_refit(int64_t n, const uint32_t* __restrict__ child,
-                                                  const uint32_t* __restrict__ parent, float* boxes,
-                                                  uint32_t* __restrict__ arrivals, float4* __restrict__ nodes) {
-  int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (p >= n) return;
-  uint32_t node = parent[(n - 1) + p];
-  while (node != kNoParent) {
-    __threadfence();
-    if (atomicAdd(&arrivals[node], 1u) == 0u) return;  // the sibling subtree is not done yet
-    __threadfence();
-    uint32_t c[2] = {child[2 * node], child[2 * node + 1]};
-    float cb[2][6];
-    for (int k = 0; k < 2; ++k) {
-      int64_t idx = (c[k] & kLeafFlag) ? (n - 1) + (c[k] & ~kLeafFlag) : c[k];
-      for (int a = 0; a < 6; ++a) cb[k][a] = ld_coherent(boxes + idx * 6 + a);
-    }
-    float* nb = boxes + (int64_t)node * 6;
+__device__ __forceinline__ void range_box(const float* __restrict__ leaf_boxes, uint32_t lo, uint32_t hi, float b[6]) {
+  b[0] = b[1] = b[2] = INFINITY;
+  b[3] = b[4] = b[5] = -INFINITY;
+  uint32_t q = lo;
+  for (; q + 3 <= hi; q += 4) {
+    float v[4][6];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int a = 0; a < 6; ++a) v[u][a] = leaf_boxes[(int64_t)(q + u) * 6 + a];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        b[a] = fminf(b[a], v[u][a]);
+        b[3 + a] = fmaxf(b[3 + a], v[u][3 + a]);
+      }
+  }
+  for (; q <= hi; ++q)
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
-      nb[a] = fminf(cb[0][a], cb[1][a]);
-      nb[3 + a] = fmaxf(cb[0][3 + a], cb[1][3 + a]);
+      b[a] = fminf(b[a], leaf_boxes[(int64_t)q * 6 + a]);
+      b[3 + a] = fmaxf(b[3 + a], leaf_boxes[(int64_t)q * 6 + 3 + a]);
     }
-    nodes[4 * node + 0] = make_float4(cb[0][0], cb[0][1], cb[0][2], cb[0][3]);
-    nodes[4 * node + 1] = make_float4(cb[0][4], cb[0][5], cb[1][0], cb[1][1]);
-    nodes[4 * node + 2] = make_float4(cb[1][2], cb[1][3], cb[1][4], cb[1][5]);
-    nodes[4 * node + 3] = make_float4(__uint_as_float(c[0]), __uint_as_float(c[1]), 0.f, 0.f);
-    node = parent[node];
+}
+
+__device__ __forceinline__ void write_node(float4* __restrict__ nodes, float* __restrict__ boxes, uint32_t node,
+                                           const float (&b0)[6], const float (&b1)[6], uint32_t c0, uint32_t c1) {
+  nodes[4 * (int64_t)node + 0] = make_float4(b0[0], b0[1], b0[2], b0[3]);
+  nodes[4 * (int64_t)node + 1] = make_float4(b0[4], b0[5], b1[0], b1[1]);
+  nodes[4 * (int64_t)node + 2] = make_float4(b1[2], b1[3], b1[4], b1[5]);
+  nodes[4 * (int64_t)node + 3] = make_float4(__uint_as_float(c0), __uint_as_float(c1), 0.f, 0.f);
+  float* nb = boxes + (int64_t)node * 6;
+  for (int a = 0; a < 3; ++a) {
+    nb[a] = fminf(b0[a], b1[a]);
+    nb[3 + a] = fmaxf(b0[3 + a], b1[3 + a]);
+  }
+}
+
+// Phase 1: every small internal node; also lists the top nodes whose children are both
+// small (the top phase starts there).
+__global__ void __launch_bounds__(kBlock) k_refit_small(int64_t n, const uint32_t* __restrict__ child,
+                                                        const uint2* __restrict__ range, float* __restrict__ boxes,
+                                                        float4* __restrict__ nodes, uint32_t* __restrict__ ready,
+                                                        uint32_t* __restrict__ n_ready) {
+  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  bool top_ready = false;
+  if (i < n - 1) {
+    const uint2 r = range[i];
+    const uint32_t c0 = child[2 * i], c1 = child[2 * i + 1];
+    if ((int64_t)r.y - r.x + 1 <= kRefitSmall) {
+      const uint32_t split = c0 & ~kLeafFlag;  // last leaf of the left child
+      float b0[6], b1[6];
+      const float* leaf_boxes = boxes + (n - 1) * 6;
+      range_box(leaf_boxes, r.x, split, b0);
+      range_box(leaf_boxes, split + 1, r.y, b1);
+      write_node(nodes, boxes, (uint32_t)i, b0, b1, c0, c1);
+    } else {
+      top_ready = is_small(c0, range) && is_small(c1, range);
+    }
+  }
+  const uint64_t m = __ballot(top_ready);
+  if (m) {
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(n_ready, (uint32_t)__popcll(m));
+    base = __shfl(base, leader);
+    if (top_ready) ready[base + __popcll(m & ((1ull << lane) - 1))] = (uint32_t)i;
+  }
+}
+
+__device__ __forceinline__ void child_box(const float* boxes, int64_t n, uint32_t c, float b[6]) {
+  const int64_t idx = (c & kLeafFlag) ? (n - 1) + (c & ~kLeafFlag) : c;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) b[a] = boxes[idx * 6 + a];
+}
+
+// Phase 2: one workgroup. A thread starts at a ready top node and climbs; at a parent with
+// two top children the first arrival stops and the second continues.
+__global__ void __launch_bounds__(kTopBlock) k_refit_top(int64_t n, const uint32_t* __restrict__ child,
+                                                         const uint32_t* __restrict__ parent,
+                                                         const uint2* __restrict__ range, float* boxes,
+                                                         float4* __restrict__ nodes, const uint32_t* __restrict__ ready,
+                                                         const uint32_t* __restrict__ n_ready,
+                                                         uint32_t* __restrict__ arrivals) {
+  const uint32_t cnt = *n_ready;
+  for (uint32_t w = threadIdx.x; w < cnt; w += kTopBlock) {
+    uint32_t node = ready[w];
+    while (true) {
+      const uint32_t c0 = child[2 * (int64_t)node], c1 = child[2 * (int64_t)node + 1];
+      float b0[6], b1[6];
+      child_box(boxes, n, c0, b0);
+      child_box(boxes, n, c1, b1);
+      write_node(nodes, boxes, node, b0, b1, c0, c1);
+      const uint32_t p = parent[node];
+      if (p == kNoParent) break;
+      const bool two = !is_small(child[2 * (int64_t)p], range) && !is_small(child[2 * (int64_t)p + 1], range);
+      // release this node's box to the sibling's thread; acquire the sibling's box
+      if (two && __hip_atomic_fetch_add(&arrivals[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == 0u)
+        break;
+      node = p;
+    }
   }
 }
 
@@ -694,7 +784,11 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
   GRTX_TRY(sc.get(&bounds, 6));
   GRTX_TRY(sc.get(&tkeys, m));
   GRTX_TRY(sc.get(&tvals, m));
-  GRTX_TRY(sc.get(&arrivals, std::max<int64_t>(nint, 1)));
+  uint2* range = nullptr;
+  uint32_t* ready = nullptr;
+  GRTX_TRY(sc.get(&arrivals, nint + 1));  // per internal node, then the ready-list length
+  GRTX_TRY(sc.get(&range, std::max<int64_t>(nint, 1)));
+  GRTX_TRY(sc.get(&ready, std::max<int64_t>(nint, 1)));
   const float* points = g->means;
   if (proxy) {
     GRTX_TRY(sc.get(&cent, 3 * m));
@@ -718,10 +812,13 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
                        b->boxes);
   }
   if (nint > 0) {
-    hipLaunchKernelGGL(k_karras, dim3(grid_for(nint)), dim3(kBlock), 0, s, b->codes, m, b->child, b->parent);
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nint)), dim3(kBlock), 0, s, arrivals, nint, 0u);
-    hipLaunchKernelGGL(k_refit, dim3(grid_for(m)), dim3(kBlock), 0, s, m, b->child, b->parent, b->boxes, arrivals,
-                       b->nodes);
+    hipLaunchKernelGGL(k_karras, dim3(grid_for(nint)), dim3(kBlock), 0, s, b->codes, m, b->child, b->parent,
+                       range);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nint + 1)), dim3(kBlock), 0, s, arrivals, nint + 1, 0u);
+    hipLaunchKernelGGL(k_refit_small, dim3(grid_for(nint)), dim3(kBlock), 0, s, m, b->child, range, b->boxes,
+                       b->nodes, ready, arrivals + nint);
+    hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(kTopBlock), 0, s, m, b->child, b->parent, range, b->boxes,
+                       b->nodes, ready, arrivals + nint, arrivals);
   } else {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, s, b->parent, 1, kNoParent);
   }
