@@ -506,12 +506,8 @@ __device__ __forceinline__ void range_box(const float* __restrict__ leaf_boxes, 
     }
 }
 
-__device__ __forceinline__ void write_node(float4* __restrict__ nodes, float* __restrict__ boxes, uint32_t node,
-                                           const float (&b0)[6], const float (&b1)[6], uint32_t c0, uint32_t c1) {
-  nodes[4 * (int64_t)node + 0] = make_float4(b0[0], b0[1], b0[2], b0[3]);
-  nodes[4 * (int64_t)node + 1] = make_float4(b0[4], b0[5], b1[0], b1[1]);
-  nodes[4 * (int64_t)node + 2] = make_float4(b1[2], b1[3], b1[4], b1[5]);
-  nodes[4 * (int64_t)node + 3] = make_float4(__uint_as_float(c0), __uint_as_float(c1), 0.f, 0.f);
+__device__ __forceinline__ void write_box(float* __restrict__ boxes, uint32_t node, const float (&b0)[6],
+                                          const float (&b1)[6]) {
   float* nb = boxes + (int64_t)node * 6;
   for (int a = 0; a < 3; ++a) {
     nb[a] = fminf(b0[a], b1[a]);
@@ -523,7 +519,7 @@ __device__ __forceinline__ void write_node(float4* __restrict__ nodes, float* __
 // small (the top phase starts there).
 __global__ void __launch_bounds__(kBlock) k_refit_small(int64_t n, const uint32_t* __restrict__ child,
                                                         const uint2* __restrict__ range, float* __restrict__ boxes,
-                                                        float4* __restrict__ nodes, uint32_t* __restrict__ ready,
+                                                        uint32_t* __restrict__ ready,
                                                         uint32_t* __restrict__ n_ready) {
   const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   bool top_ready = false;
@@ -536,7 +532,7 @@ __global__ void __launch_bounds__(kBlock) k_refit_small(int64_t n, const uint32_
       const float* leaf_boxes = boxes + (n - 1) * 6;
       range_box(leaf_boxes, r.x, split, b0);
       range_box(leaf_boxes, split + 1, r.y, b1);
-      write_node(nodes, boxes, (uint32_t)i, b0, b1, c0, c1);
+      write_box(boxes, (uint32_t)i, b0, b1);
     } else {
       top_ready = is_small(c0, range) && is_small(c1, range);
     }
@@ -563,7 +559,7 @@ __device__ __forceinline__ void child_box(const float* boxes, int64_t n, uint32_
 __global__ void __launch_bounds__(kTopBlock) k_refit_top(int64_t n, const uint32_t* __restrict__ child,
                                                          const uint32_t* __restrict__ parent,
                                                          const uint2* __restrict__ range, float* boxes,
-                                                         float4* __restrict__ nodes, const uint32_t* __restrict__ ready,
+                                                         const uint32_t* __restrict__ ready,
                                                          const uint32_t* __restrict__ n_ready,
                                                          uint32_t* __restrict__ arrivals) {
   const uint32_t cnt = *n_ready;
@@ -574,7 +570,7 @@ __global__ void __launch_bounds__(kTopBlock) k_refit_top(int64_t n, const uint32
       float b0[6], b1[6];
       child_box(boxes, n, c0, b0);
       child_box(boxes, n, c1, b1);
-      write_node(nodes, boxes, node, b0, b1, c0, c1);
+      write_box(boxes, node, b0, b1);
       const uint32_t p = parent[node];
       if (p == kNoParent) break;
       const bool two = !is_small(child[2 * (int64_t)p], range) && !is_small(child[2 * (int64_t)p + 1], range);
@@ -584,6 +580,48 @@ __global__ void __launch_bounds__(kTopBlock) k_refit_top(int64_t n, const uint32
       node = p;
     }
   }
+}
+
+// Four-wide node records (layout in grtx_internal.h), written once every box is final.
+__global__ void __launch_bounds__(kBlock) k_wide(int64_t n, const uint32_t* __restrict__ child,
+                                                 const float* __restrict__ boxes, float4* __restrict__ nodes) {
+  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i >= n - 1) return;
+  uint32_t ref[4] = {kNoChild, kNoChild, kNoChild, kNoChild};
+  int cnt = 0;
+  for (int k = 0; k < 2; ++k) {
+    const uint32_t c = child[2 * i + k];
+    if (c & kLeafFlag) {
+      ref[cnt++] = c;
+    } else {
+      ref[cnt++] = child[2 * (int64_t)c];
+      ref[cnt++] = child[2 * (int64_t)c + 1];
+    }
+  }
+  float lo[3][4], hi[3][4];
+  for (int j = 0; j < 4; ++j) {
+    if (ref[j] == kNoChild) {
+      for (int a = 0; a < 3; ++a) {
+        lo[a][j] = INFINITY;
+        hi[a][j] = -INFINITY;
+      }
+      continue;
+    }
+    float b[6];
+    child_box(boxes, n, ref[j], b);
+    for (int a = 0; a < 3; ++a) {
+      lo[a][j] = b[a];
+      hi[a][j] = b[3 + a];
+    }
+  }
+  float4* r = nodes + (int64_t)kNodeF4 * i;
+  for (int a = 0; a < 3; ++a) {
+    r[a] = make_float4(lo[a][0], lo[a][1], lo[a][2], lo[a][3]);
+    r[3 + a] = make_float4(hi[a][0], hi[a][1], hi[a][2], hi[a][3]);
+  }
+  r[6] = make_float4(__uint_as_float(ref[0]), __uint_as_float(ref[1]), __uint_as_float(ref[2]),
+                     __uint_as_float(ref[3]));
+  r[7] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 // ------------------------------------------------------------------ pinhole rays
@@ -768,7 +806,7 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
   GRTX_TRY(dalloc(b, &b->child, 2 * std::max<int64_t>(nint, 1)));
   GRTX_TRY(dalloc(b, &b->parent, 2 * m - 1));
   GRTX_TRY(dalloc(b, &b->boxes, 6 * (2 * m - 1)));
-  GRTX_TRY(dalloc(b, &b->nodes, 4 * std::max<int64_t>(nint, 1)));
+  GRTX_TRY(dalloc(b, &b->nodes, kNodeF4 * std::max<int64_t>(nint, 1)));
   GRTX_TRY(dalloc(b, &b->inst, 4 * n));
   if (proxy) GRTX_TRY(dalloc(b, &b->tris, 3 * m));
   b->root_box = b->boxes;  // node 0: the root, or the only leaf when m == 1
@@ -816,9 +854,10 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
                        range);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nint + 1)), dim3(kBlock), 0, s, arrivals, nint + 1, 0u);
     hipLaunchKernelGGL(k_refit_small, dim3(grid_for(nint)), dim3(kBlock), 0, s, m, b->child, range, b->boxes,
-                       b->nodes, ready, arrivals + nint);
+                       ready, arrivals + nint);
     hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(kTopBlock), 0, s, m, b->child, b->parent, range, b->boxes,
-                       b->nodes, ready, arrivals + nint, arrivals);
+                       ready, arrivals + nint, arrivals);
+    hipLaunchKernelGGL(k_wide, dim3(grid_for(nint)), dim3(kBlock), 0, s, m, b->child, b->boxes, b->nodes);
   } else {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, s, b->parent, 1, kNoParent);
   }

@@ -17,13 +17,17 @@ namespace grtx {
 // Device data layout
 // ---------------------------------------------------------------------------------------
 //
-// Internal node record, 64 B (4 x float4), one per internal node in radix-tree order
-// (node 0 = root). It holds the boxes of both children, so one fetch tests both:
-//   q0 = (c0.lo.x, c0.lo.y, c0.lo.z, c0.hi.x)
-//   q1 = (c0.hi.y, c0.hi.z, c1.lo.x, c1.lo.y)
-//   q2 = (c1.lo.z, c1.hi.x, c1.hi.y, c1.hi.z)
-//   q3 = (ref0, ref1, 0, 0) as uint bits; ref = internal node index, or kLeafFlag | leaf.
-//
+// Node record, 128 B (8 x float4, one L2 line), one per internal node of the binary radix
+// tree (node 0 = root). A record lists up to four children: the node's two children, each
+// internal one replaced by its own two children, so a traversal from the root visits only
+// every other level of the binary tree and tests four boxes per fetch (records of nodes
+// at odd depth are never reached). Child j's box and reference:
+//   q0 = lo.x[0..3]   q1 = lo.y[0..3]   q2 = lo.z[0..3]
+//   q3 = hi.x[0..3]   q4 = hi.y[0..3]   q5 = hi.z[0..3]
+//   q6 = ref[0..3] as uint bits: internal node index, kLeafFlag | leaf, or kNoChild
+//   q7 = 0
+constexpr int kNodeF4 = 8;
+
 // Instance record (SPHERE_INSTANCE leaf), 64 B, in sorted-leaf order:
 //   q0 = (A00, A01, A02, mu.x)   A = rho^-1 S^-1 R^T maps the bounding ellipsoid of the
 //   q1 = (A10, A11, A12, mu.y)   Gaussian onto the unit sphere: u = A (x - mu)
@@ -37,6 +41,7 @@ namespace grtx {
 // For PROXY20 the instance records are stored in Gaussian order instead.
 constexpr uint32_t kLeafFlag = 0x80000000u;
 constexpr uint32_t kNoParent = 0xFFFFFFFFu;
+constexpr uint32_t kNoChild = 0xFFFFFFFFu;
 
 struct Bvh {
   int device = 0;
@@ -45,7 +50,7 @@ struct Bvh {
   int64_t n_leaves = 0;
   int sh_degree = 0;
   float alpha_min = 0.f;
-  float4* nodes = nullptr;   // [n_leaves-1][4]
+  float4* nodes = nullptr;   // [n_leaves-1][kNodeF4]
   float4* inst = nullptr;    // [n_gauss][4]
   float4* tris = nullptr;    // PROXY20: [n_leaves][3]
   uint64_t* codes = nullptr; // [n_leaves] sorted Morton codes

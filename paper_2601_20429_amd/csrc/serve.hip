@@ -33,18 +33,24 @@ constexpr int kMaxBatchRequests = 1024;
 
 // ------------------------------------------------------------------ scene-set merge
 
+__device__ __forceinline__ uint32_t rebase(uint32_t r, uint32_t node_base, uint32_t leaf_base) {
+  if (r == kNoChild) return r;
+  return (r & kLeafFlag) ? (kLeafFlag | ((r & ~kLeafFlag) + leaf_base)) : r + node_base;
+}
+
 __global__ void k_merge_nodes(const float4* __restrict__ src, int64_t n, uint32_t node_base, uint32_t leaf_base,
                               float4* __restrict__ dst) {
   int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   if (i >= n) return;
-  dst[4 * i + 0] = src[4 * i + 0];
-  dst[4 * i + 1] = src[4 * i + 1];
-  dst[4 * i + 2] = src[4 * i + 2];
-  float4 q = src[4 * i + 3];
-  uint32_t c0 = __float_as_uint(q.x), c1 = __float_as_uint(q.y);
-  c0 = (c0 & kLeafFlag) ? (kLeafFlag | ((c0 & ~kLeafFlag) + leaf_base)) : c0 + node_base;
-  c1 = (c1 & kLeafFlag) ? (kLeafFlag | ((c1 & ~kLeafFlag) + leaf_base)) : c1 + node_base;
-  dst[4 * i + 3] = make_float4(__uint_as_float(c0), __uint_as_float(c1), 0.f, 0.f);
+  const float4* a = src + (int64_t)kNodeF4 * i;
+  float4* b = dst + (int64_t)kNodeF4 * i;
+  for (int q = 0; q < 6; ++q) b[q] = a[q];
+  const float4 r = a[6];
+  b[6] = make_float4(__uint_as_float(rebase(__float_as_uint(r.x), node_base, leaf_base)),
+                     __uint_as_float(rebase(__float_as_uint(r.y), node_base, leaf_base)),
+                     __uint_as_float(rebase(__float_as_uint(r.z), node_base, leaf_base)),
+                     __uint_as_float(rebase(__float_as_uint(r.w), node_base, leaf_base)));
+  b[7] = a[7];
 }
 
 __global__ void k_merge_inst(const float4* __restrict__ src, int64_t n, uint32_t gauss_base,
@@ -63,9 +69,7 @@ __global__ void k_merge_root(const float* __restrict__ src, uint32_t node_base, 
                              float* __restrict__ dst) {
   if (threadIdx.x < 6) dst[threadIdx.x] = src[threadIdx.x];
   if (threadIdx.x == 6) {
-    uint32_t r = __float_as_uint(src[6]);
-    r = (r & kLeafFlag) ? (kLeafFlag | ((r & ~kLeafFlag) + leaf_base)) : r + node_base;
-    dst[6] = __uint_as_float(r);
+    dst[6] = __uint_as_float(rebase(__float_as_uint(src[6]), node_base, leaf_base));
   }
   if (threadIdx.x == 7) dst[7] = 0.f;
 }
@@ -233,7 +237,7 @@ grtx_status sv_alloc(Server* sv, T** p, size_t count) {
 grtx_status freeze(Server* sv) {
   if (sv->frozen) return GRTX_OK;
   hipStream_t s = sv->slots[0].stream;
-  SV_TRY(sv_alloc(sv, &sv->nodes, 4 * (size_t)std::max<int64_t>(sv->total_nodes, 1)));
+  SV_TRY(sv_alloc(sv, &sv->nodes, kNodeF4 * (size_t)std::max<int64_t>(sv->total_nodes, 1)));
   SV_TRY(sv_alloc(sv, &sv->inst, 4 * (size_t)sv->total_gauss));
   const int ncoef = (sv->sh_degree + 1) * (sv->sh_degree + 1);
   SV_TRY(sv_alloc(sv, &sv->sh, (size_t)sv->total_gauss * 3 * ncoef));
@@ -244,7 +248,7 @@ grtx_status freeze(Server* sv) {
     const int64_t nint = b->n_leaves - 1;
     if (nint > 0)
       hipLaunchKernelGGL(k_merge_nodes, dim3((unsigned)((nint + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, b->nodes,
-                         nint, (uint32_t)node_base, (uint32_t)leaf_base, sv->nodes + 4 * node_base);
+                         nint, (uint32_t)node_base, (uint32_t)leaf_base, sv->nodes + kNodeF4 * node_base);
     hipLaunchKernelGGL(k_merge_inst, dim3((unsigned)((b->n_gauss + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                        b->inst, b->n_gauss, (uint32_t)gauss_base, sv->inst + 4 * leaf_base);
     GRTX_HIP(hipMemcpyAsync(sv->sh + gauss_base * 3 * ncoef, b->sh, sizeof(float) * 3 * ncoef * b->n_gauss,

@@ -51,7 +51,9 @@ namespace {
 constexpr int kTraceBlock = 256;
 constexpr int kWaves = kTraceBlock / 64;
 constexpr int kLdsStack = GRTX_LDS_STACK;  // per-lane stack entries held in LDS
-constexpr int kMaxStack = 96;              // > depth of a radix tree over 95-bit keys
+// A radix tree over 95-bit keys is at most 96 levels deep, so a path visits at most 48
+// four-wide records, each leaving at most three entries pending.
+constexpr int kMaxStack = 3 * 48 + 16;
 constexpr int kSpillRows = kMaxStack - kLdsStack;
 constexpr int kRefillThreshold = GRTX_REFILL_THRESHOLD;  // idle lanes that end a traversal burst
 #ifndef GRTX_CHUNKS
@@ -312,8 +314,8 @@ __global__ void __launch_bounds__(kTraceBlock)
   };
 
   auto push = [&](uint32_t ref, float t) __attribute__((always_inline)) {
-    // At most one entry per tree level is pending, and a radix tree over 95-bit keys is
-    // at most 95 levels deep, so sp < kMaxStack always; the bound keeps memory safe.
+    // At most three entries per visited record are pending (see kMaxStack), so
+    // sp < kMaxStack always; the bound keeps memory safe.
     uint2 e = make_uint2(ref, __float_as_uint(t));
     if (sp < kLdsStack)
       s_stack[sp * kTraceBlock + tid] = e;
@@ -485,38 +487,47 @@ __global__ void __launch_bounds__(kTraceBlock)
         if (have_key && !ins) evict(key);
         have_key = false;
       } else if (nodey) {
-        // ------------------------------------------------ node step: both children
-        const float4* np = A.nodes + 4 * (int64_t)cur_ref;
-        float4 q0 = np[0], q1 = np[1], q2 = np[2], q3 = np[3];
+        // ------------------------------------------------ node step: four children
+        const float4* np = A.nodes + kNodeF4 * (int64_t)cur_ref;
+        const float4 lx = np[0], ly = np[1], lz = np[2], hx = np[3], hy = np[4], hz = np[5], rf = np[6];
         STAT(GRTX_STAT_NODES);
-        Slab s0 = slab(q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, ox, oy, oz, ix, iy, iz);
-        Slab s1 = slab(q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, ox, oy, oz, ix, iy, iz);
         const float tlo = fmaxf(tnear, key_t(tmin));
-        bool v0 = s0.tn <= s0.tf && s0.tf >= tlo;
-        bool v1 = s1.tn <= s1.tf && s1.tf >= tlo;
-        uint32_t c0 = __float_as_uint(q3.x), c1 = __float_as_uint(q3.y);
-        if (v0 && s0.tn > tmax_t) {
-          defer(c0, s0.tn);
-          v0 = false;
+        const float lxa[4] = {lx.x, lx.y, lx.z, lx.w}, lya[4] = {ly.x, ly.y, ly.z, ly.w};
+        const float lza[4] = {lz.x, lz.y, lz.z, lz.w}, hxa[4] = {hx.x, hx.y, hx.z, hx.w};
+        const float hya[4] = {hy.x, hy.y, hy.z, hy.w}, hza[4] = {hz.x, hz.y, hz.z, hz.w};
+        uint32_t c[4] = {__float_as_uint(rf.x), __float_as_uint(rf.y), __float_as_uint(rf.z), __float_as_uint(rf.w)};
+        float t[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          Slab sj = slab(lxa[j], lya[j], lza[j], hxa[j], hya[j], hza[j], ox, oy, oz, ix, iy, iz);
+          bool v = c[j] != kNoChild && sj.tn <= sj.tf && sj.tf >= tlo;
+          if (v && sj.tn > tmax_t) {
+            defer(c[j], sj.tn);
+            v = false;
+          }
+          t[j] = v ? sj.tn : INFINITY;
         }
-        if (v1 && s1.tn > tmax_t) {
-          defer(c1, s1.tn);
-          v1 = false;
-        }
-        if (v0 && v1) {
-          bool first0 = s0.tn <= s1.tn;
-          push(first0 ? c1 : c0, first0 ? s1.tn : s0.tn);
-          cur_ref = first0 ? c0 : c1;
-          cur_t = first0 ? s0.tn : s1.tn;
-        } else if (v0) {
-          cur_ref = c0;
-          cur_t = s0.tn;
-        } else if (v1) {
-          cur_ref = c1;
-          cur_t = s1.tn;
-        } else {
-          has_cur = false;
-        }
+        // near-to-far order of the children still in play (sorting network on (t, ref))
+        auto cswap = [&](int a, int b) __attribute__((always_inline)) {
+          const bool sw = t[b] < t[a];
+          const float ta = t[a], tb = t[b];
+          const uint32_t ca = c[a], cb = c[b];
+          t[a] = sw ? tb : ta;
+          t[b] = sw ? ta : tb;
+          c[a] = sw ? cb : ca;
+          c[b] = sw ? ca : cb;
+        };
+        cswap(0, 1);
+        cswap(2, 3);
+        cswap(0, 2);
+        cswap(1, 3);
+        cswap(1, 2);
+        if (t[3] < INFINITY) push(c[3], t[3]);
+        if (t[2] < INFINITY) push(c[2], t[2]);
+        if (t[1] < INFINITY) push(c[1], t[1]);
+        has_cur = t[0] < INFINITY;
+        cur_ref = c[0];
+        cur_t = t[0];
       }
     }
 
