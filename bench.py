@@ -19,7 +19,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # algorithmic bytes per unit of work ("Roofline")
-B_NODE = 128         # node record: four child boxes + four child references
+B_NODE = 64          # node record: four quantized child boxes + four child references
 B_LEAF = 48          # unit-sphere transform of a leaf (3 x float4)
 B_BLEND_INST = 64    # full instance record re-read for blending
 B_LIST = 16          # one checkpoint / eviction entry written and read back (8 B each way)

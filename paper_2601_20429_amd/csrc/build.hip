@@ -598,30 +598,39 @@ __global__ void __launch_bounds__(kBlock) k_wide(int64_t n, const uint32_t* __re
       ref[cnt++] = child[2 * (int64_t)c + 1];
     }
   }
-  float lo[3][4], hi[3][4];
-  for (int j = 0; j < 4; ++j) {
-    if (ref[j] == kNoChild) {
-      for (int a = 0; a < 3; ++a) {
-        lo[a][j] = INFINITY;
-        hi[a][j] = -INFINITY;
-      }
-      continue;
+  const float* own = boxes + 6 * i;  // the union of the children's boxes
+  float org[3], step[3];
+  uint32_t wlo[3] = {0u, 0u, 0u}, whi[3] = {0u, 0u, 0u};
+  for (int a = 0; a < 3; ++a) {
+    org[a] = own[a];
+    const double ext = (double)own[3 + a] - (double)own[a];
+    int e = -126;
+    if (ext > 0.0) {
+      (void)frexp(ext / 254.0, &e);  // ext / 254 <= 2^e
+      e = e < -126 ? -126 : e;
     }
+    step[a] = ldexpf(1.0f, e);
+  }
+  for (int j = 0; j < cnt; ++j) {
     float b[6];
     child_box(boxes, n, ref[j], b);
     for (int a = 0; a < 3; ++a) {
-      lo[a][j] = b[a];
-      hi[a][j] = b[3 + a];
+      const double s = (double)step[a];
+      double ql = floor(((double)b[a] - (double)org[a]) / s);
+      double qh = ceil(((double)b[3 + a] - (double)org[a]) / s);
+      ql = ql < 0.0 ? 0.0 : ql > 255.0 ? 255.0 : ql;
+      qh = qh < 0.0 ? 0.0 : qh > 255.0 ? 255.0 : qh;
+      wlo[a] |= (uint32_t)ql << (8 * j);
+      whi[a] |= (uint32_t)qh << (8 * j);
     }
   }
   float4* r = nodes + (int64_t)kNodeF4 * i;
-  for (int a = 0; a < 3; ++a) {
-    r[a] = make_float4(lo[a][0], lo[a][1], lo[a][2], lo[a][3]);
-    r[3 + a] = make_float4(hi[a][0], hi[a][1], hi[a][2], hi[a][3]);
-  }
-  r[6] = make_float4(__uint_as_float(ref[0]), __uint_as_float(ref[1]), __uint_as_float(ref[2]),
-                     __uint_as_float(ref[3]));
-  r[7] = make_float4(0.f, 0.f, 0.f, 0.f);
+  r[0] = make_float4(org[0], org[1], org[2], step[0]);
+  r[1] = make_float4(step[1], step[2], __uint_as_float(ref[0]), __uint_as_float(ref[1]));
+  r[2] = make_float4(__uint_as_float(ref[2]), __uint_as_float(ref[3]), __uint_as_float(wlo[0]),
+                     __uint_as_float(wlo[1]));
+  r[3] = make_float4(__uint_as_float(wlo[2]), __uint_as_float(whi[0]), __uint_as_float(whi[1]),
+                     __uint_as_float(whi[2]));
 }
 
 // ------------------------------------------------------------------ pinhole rays

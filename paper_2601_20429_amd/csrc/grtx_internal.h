@@ -17,16 +17,21 @@ namespace grtx {
 // Device data layout
 // ---------------------------------------------------------------------------------------
 //
-// Node record, 128 B (8 x float4, one L2 line), one per internal node of the binary radix
-// tree (node 0 = root). A record lists up to four children: the node's two children, each
-// internal one replaced by its own two children, so a traversal from the root visits only
-// every other level of the binary tree and tests four boxes per fetch (records of nodes
-// at odd depth are never reached). Child j's box and reference:
-//   q0 = lo.x[0..3]   q1 = lo.y[0..3]   q2 = lo.z[0..3]
-//   q3 = hi.x[0..3]   q4 = hi.y[0..3]   q5 = hi.z[0..3]
-//   q6 = ref[0..3] as uint bits: internal node index, kLeafFlag | leaf, or kNoChild
-//   q7 = 0
-constexpr int kNodeF4 = 8;
+// Node record, 64 B (4 x float4), one per internal node of the binary radix tree (node 0
+// = root). A record lists up to four children: the node's two children, each internal
+// one replaced by its own two, so a traversal from the root visits every other level of
+// the binary tree (records of nodes at odd depth are never reached). The children's boxes
+// are stored on an 8-bit grid over the node's own box: per axis a an origin o_a (the box
+// minimum) and a power-of-two step s_a with extent / s_a <= 254; child j's planes are
+// o_a + q * s_a with q rounded outward (lo down, hi up), so each stored box contains
+// the child's exact box.
+//   q0 = (o.x, o.y, o.z, s.x)
+//   q1 = (s.y, s.z, ref0, ref1)
+//   q2 = (ref2, ref3, qlo.x, qlo.y)
+//   q3 = (qlo.z, qhi.x, qhi.y, qhi.z)
+// ref = internal node index, kLeafFlag | leaf, or kNoChild (as uint bits); each q word
+// holds one plane of the four children, child j in byte j.
+constexpr int kNodeF4 = 4;
 
 // Instance record (SPHERE_INSTANCE leaf), 64 B, in sorted-leaf order:
 //   q0 = (A00, A01, A02, mu.x)   A = rho^-1 S^-1 R^T maps the bounding ellipsoid of the

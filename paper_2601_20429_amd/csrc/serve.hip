@@ -44,13 +44,15 @@ __global__ void k_merge_nodes(const float4* __restrict__ src, int64_t n, uint32_
   if (i >= n) return;
   const float4* a = src + (int64_t)kNodeF4 * i;
   float4* b = dst + (int64_t)kNodeF4 * i;
-  for (int q = 0; q < 6; ++q) b[q] = a[q];
-  const float4 r = a[6];
-  b[6] = make_float4(__uint_as_float(rebase(__float_as_uint(r.x), node_base, leaf_base)),
-                     __uint_as_float(rebase(__float_as_uint(r.y), node_base, leaf_base)),
-                     __uint_as_float(rebase(__float_as_uint(r.z), node_base, leaf_base)),
-                     __uint_as_float(rebase(__float_as_uint(r.w), node_base, leaf_base)));
-  b[7] = a[7];
+  float4 q1 = a[1], q2 = a[2];
+  q1.z = __uint_as_float(rebase(__float_as_uint(q1.z), node_base, leaf_base));
+  q1.w = __uint_as_float(rebase(__float_as_uint(q1.w), node_base, leaf_base));
+  q2.x = __uint_as_float(rebase(__float_as_uint(q2.x), node_base, leaf_base));
+  q2.y = __uint_as_float(rebase(__float_as_uint(q2.y), node_base, leaf_base));
+  b[0] = a[0];
+  b[1] = q1;
+  b[2] = q2;
+  b[3] = a[3];
 }
 
 __global__ void k_merge_inst(const float4* __restrict__ src, int64_t n, uint32_t gauss_base,

@@ -488,24 +488,37 @@ __global__ void __launch_bounds__(kTraceBlock)
         have_key = false;
       } else if (nodey) {
         // ------------------------------------------------ node step: four children
+        // Slab distances straight from the 8-bit planes: t = q * (s * inv) + (o - ray) * inv.
+        // A child's entry is raised to at least the entry of the node in hand, so entries
+        // never decrease along a path whatever the rounding, and a node whose entry exceeds
+        // t_max holds no key at or below t_max (keys are clamped to their leaf's entry).
         const float4* np = A.nodes + kNodeF4 * (int64_t)cur_ref;
-        const float4 lx = np[0], ly = np[1], lz = np[2], hx = np[3], hy = np[4], hz = np[5], rf = np[6];
+        const float4 q0 = np[0], q1 = np[1], q2 = np[2], q3 = np[3];
         STAT(GRTX_STAT_NODES);
         const float tlo = fmaxf(tnear, key_t(tmin));
-        const float lxa[4] = {lx.x, lx.y, lx.z, lx.w}, lya[4] = {ly.x, ly.y, ly.z, ly.w};
-        const float lza[4] = {lz.x, lz.y, lz.z, lz.w}, hxa[4] = {hx.x, hx.y, hx.z, hx.w};
-        const float hya[4] = {hy.x, hy.y, hy.z, hy.w}, hza[4] = {hz.x, hz.y, hz.z, hz.w};
-        uint32_t c[4] = {__float_as_uint(rf.x), __float_as_uint(rf.y), __float_as_uint(rf.z), __float_as_uint(rf.w)};
+        const float Ax = q0.w * ix, Ay = q1.x * iy, Az = q1.y * iz;
+        const float Bx = (q0.x - ox) * ix, By = (q0.y - oy) * iy, Bz = (q0.z - oz) * iz;
+        const uint32_t wlx = __float_as_uint(q2.z), wly = __float_as_uint(q2.w), wlz = __float_as_uint(q3.x);
+        const uint32_t whx = __float_as_uint(q3.y), why = __float_as_uint(q3.z), whz = __float_as_uint(q3.w);
+        uint32_t c[4] = {__float_as_uint(q1.z), __float_as_uint(q1.w), __float_as_uint(q2.x), __float_as_uint(q2.y)};
         float t[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          Slab sj = slab(lxa[j], lya[j], lza[j], hxa[j], hya[j], hza[j], ox, oy, oz, ix, iy, iz);
-          bool v = c[j] != kNoChild && sj.tn <= sj.tf && sj.tf >= tlo;
-          if (v && sj.tn > tmax_t) {
-            defer(c[j], sj.tn);
+          const float t0x = fmaf((float)((wlx >> (8 * j)) & 0xFFu), Ax, Bx);
+          const float t1x = fmaf((float)((whx >> (8 * j)) & 0xFFu), Ax, Bx);
+          const float t0y = fmaf((float)((wly >> (8 * j)) & 0xFFu), Ay, By);
+          const float t1y = fmaf((float)((why >> (8 * j)) & 0xFFu), Ay, By);
+          const float t0z = fmaf((float)((wlz >> (8 * j)) & 0xFFu), Az, Bz);
+          const float t1z = fmaf((float)((whz >> (8 * j)) & 0xFFu), Az, Bz);
+          const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z));
+          const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));
+          const float te = fmaxf(tn, cur_t);
+          bool v = c[j] != kNoChild && tn <= tf && tf >= tlo;
+          if (v && te > tmax_t) {
+            defer(c[j], te);
             v = false;
           }
-          t[j] = v ? sj.tn : INFINITY;
+          t[j] = v ? te : INFINITY;
         }
         // near-to-far order of the children still in play (sorting network on (t, ref))
         auto cswap = [&](int a, int b) __attribute__((always_inline)) {
