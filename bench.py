@@ -152,6 +152,38 @@ def run_proxy(st, cam, cfg, k, stream):
     return res
 
 
+def run_scene3m(stream, ks=(16, 32)):
+    """Largest workload: 3M Gaussians, 1920x1080 primary rays (8x8 tiles) plus 2M
+    incoherent rays, k = 16 and 32, checkpointing. Rates count both ray sets."""
+    import numpy as np
+    import torch
+
+    from paper_2601_20429_amd import grtx, inputs
+    cfg = inputs.SCENE3M
+    amin = float(np.float32(cfg["alpha_min"]))
+    st = grtx.SceneTensors.from_scene(inputs.cluster_scene(cfg["seed"], cfg["n"], 3), "cuda")
+    cam = inputs.orbit_camera(cfg["width"], cfg["height"])
+    po, pd = grtx.pinhole_rays(cam)
+    io, id_ = (torch.from_numpy(a).cuda() for a in inputs.incoherent_rays(cfg["incoherent_seed"], cfg["incoherent"]))
+    bvh = grtx.build(st, alpha_min=amin)
+    build_ms = time_launch(lambda: grtx.build(st, alpha_min=amin), stream, 3)
+    res = dict(workload=cfg["name"], build_ms=build_ms, rays=cam.n_rays + cfg["incoherent"])
+    for k in ks:
+        for label, o, d, w in [("primary", po, pd, cam.width), ("incoherent", io, id_, 0)]:
+            out = grtx.trace(bvh, o, d, k=k, T_min=cfg["T_min"], image_width=w)
+            ms = time_launch(lambda: grtx.trace(bvh, o, d, k=k, T_min=cfg["T_min"], image_width=w, out=out),
+                             stream, 3)
+            stt = grtx.trace(bvh, o, d, k=k, T_min=cfg["T_min"], image_width=w, stats=True)["stats"]
+            stt = stt.to(torch.int64).sum(0).cpu().numpy()
+            n = int(o.shape[0])
+            res[f"k{k}_{label}_ms"] = ms
+            res[f"k{k}_{label}_mrays_s"] = n / (ms * 1e-3) / 1e6
+            res[f"k{k}_{label}_nodes_per_ray"] = float(stt[0] + stt[1]) / n
+            del out
+        res[f"k{k}_mrays_s"] = res["rays"] / ((res[f"k{k}_primary_ms"] + res[f"k{k}_incoherent_ms"]) * 1e-3) / 1e6
+    return res
+
+
 def run_backward(stream):
     """Differentiation workload: 200k Gaussians, 512x512 rays, k = 16; the forward pass keeps
     each ray's blended ids, the backward kernel replays them."""
@@ -229,6 +261,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--no-proxy", action="store_true", help="skip the 20-face proxy BVH comparison")
     ap.add_argument("--no-backward", action="store_true", help="skip the backward-pass timing")
+    ap.add_argument("--no-scene3m", action="store_true", help="skip the 3M-Gaussian workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the ray-sharded multi-GPU "
@@ -340,6 +373,11 @@ def main():
         backward = run_backward(stream)
         log("backward", json.dumps(backward))
 
+    scene3m = None
+    if not args.no_scene3m:
+        scene3m = run_scene3m(stream)
+        log("scene3m", json.dumps(scene3m))
+
     serving = None
     if not args.no_serving:
         serving = run_serving(args.serve_requests)
@@ -383,6 +421,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "backward": backward,
+        "scene3m": scene3m,
         "extra": extra,
     }
     print(json.dumps(rec), flush=True)

@@ -310,6 +310,33 @@ def test_full_size_scene100k_sampled():
     say(s)
 
 
+@pytest.mark.parametrize("k", [16, 32])
+def test_scene3m_full_size_sampled(k):
+    """The largest workload at full size: 3M Gaussians, all 1920x1080 primary rays (8x8
+    tile scheduling) and 2M incoherent rays (origins uniform in the scene box, directions
+    uniform on the sphere), k = 16 and 32, checkpointing; sampled rays of both sets against
+    the oracle's brute force over all 3M Gaussians."""
+    cfg = inputs.SCENE3M
+    say("scene 3M full size, k", k)
+    scene = inputs.cluster_scene(cfg["seed"], cfg["n"], 3)
+    cam = inputs.orbit_camera(cfg["width"], cfg["height"])
+    ro, rd = oracle_rays(cam)
+    io, id_ = inputs.incoherent_rays(cfg["incoherent_seed"], cfg["incoherent"])
+    bvh = build(scene)
+    for label, o, d, width, seed in [("primary", ro, rd, cfg["width"], 7), ("incoherent", io, id_, 0, 8)]:
+        out = grtx.trace(bvh, dev(o), dev(d), k=k, T_min=T_MIN, image_width=width, hit_capacity=512, stats=True)
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(out["rgb"]).all())
+        assert int(out["stats"][:, grtx.STAT_ROUNDS].min()) >= 1  # every ray was finished
+        idx = inputs.ray_subsample(seed, o.shape[0], 192)
+        ti = torch.from_numpy(idx).cuda()
+        sub = {name: v.index_select(0, ti).cpu().numpy() for name, v in out.items()}
+        ref = oracle.render(scene, o[idx], d[idx], AMIN, T_MIN, cap=512)
+        s = parity.compare_render(scene, o[idx], d[idx], sub, ref, AMIN, T_MIN, label=f"3M {label} k={k}")
+        say(s)
+        del out
+
+
 # ------------------------------------------------------------------------ proxy-mesh baseline
 
 @pytest.mark.parametrize("mode", [grtx.CHECKPOINT, grtx.RESTART])
