@@ -232,9 +232,13 @@ __device__ __forceinline__ bool proxy_hit(float4 A4, float4 B4, float4 C4, float
   return sAB <= 0.f && sBC <= 0.f && sCA <= 0.f && sum < 0.f;
 }
 
+// Occupancy target: three waves per SIMD for k <= 16 (168 VGPRs, no spills of note);
+// one wave for larger buffers, which lets the compiler keep the k-buffer and its
+// insertion copies in registers and AGPRs instead of scratch (k = 32: 16 ms against
+// 26 ms at two waves on the 100k-Gaussian frame; k = 64: 37 ms against 163 ms).
 template <int K, bool PROXY, bool STATS>
 __global__ void __launch_bounds__(kTraceBlock)
-    __attribute__((amdgpu_waves_per_eu(K <= 16 ? GRTX_MIN_WAVES_K16 : 2, 8))) k_trace(TraceArgs A) {
+    __attribute__((amdgpu_waves_per_eu(K <= 16 ? GRTX_MIN_WAVES_K16 : 1, 8))) k_trace(TraceArgs A) {
   __shared__ uint2 s_stack[kLdsStack * kTraceBlock];
   __shared__ uint32_t s_stat[STATS ? GRTX_STATS_FIELDS : 1][kTraceBlock];  // per-lane counters
   const int tid = threadIdx.x;
