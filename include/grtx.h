@@ -113,8 +113,8 @@ typedef struct grtx_rays {
  * its transmittance below T_min (early ray termination, Sec. III-A), in [0, 1).
  * mode: grtx_mode. bg: background colour added with the remaining transmittance.
  * defer_capacity / evict_capacity: per-ray entries of the checkpoint lists (0 = the
- * default, 128 each). A ray whose lists overflow falls back to a restart-from-root
- * round; results are unchanged. */
+ * defaults, 256 deferred nodes and 128 evicted hits). A ray whose lists overflow falls
+ * back to a restart-from-root round; results are unchanged. */
 typedef struct grtx_trace_params {
   int32_t k;
   float T_min;

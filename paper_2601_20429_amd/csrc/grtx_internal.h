@@ -47,6 +47,11 @@ constexpr int kNodeF4 = 4;
 constexpr uint32_t kLeafFlag = 0x80000000u;
 constexpr uint32_t kNoParent = 0xFFFFFFFFu;
 constexpr uint32_t kNoChild = 0xFFFFFFFFu;
+// Default per-ray capacities of the checkpoint (deferred node) and eviction lists. A ray
+// that overflows one falls back to a restart-from-root round, which the other lanes of
+// its wave wait for; at 256 deferred entries such rounds are rare on scene-scale inputs.
+constexpr int kDefaultDeferCap = 256;
+constexpr int kDefaultEvictCap = 128;
 
 struct Bvh {
   int device = 0;

@@ -452,7 +452,7 @@ grtx_status serve_create(const grtx_serve_config* cfg, Server** out) {
   }
   // the checkpoint pool of each slot's trace launches counts against the budget
   const int K = cfg->k <= 4 ? 4 : cfg->k <= 8 ? 8 : cfg->k <= 16 ? 16 : cfg->k <= 32 ? 32 : 64;
-  sv->pool_bytes_per_slot = trace_pool_bytes(K, 128, 128);
+  sv->pool_bytes_per_slot = trace_pool_bytes(K, kDefaultDeferCap, kDefaultEvictCap);
   sv->available = cfg->memory_budget - sv->cfg.slots * sv->pool_bytes_per_slot;
   if (sv->available <= 0) {
     set_error("grtx_serve_create: budget %lld bytes is below the %d slots' checkpoint pools (%lld bytes each)",

@@ -43,7 +43,7 @@ namespace {
 #define GRTX_LDS_STACK 16
 #endif
 #ifndef GRTX_REFILL_THRESHOLD
-#define GRTX_REFILL_THRESHOLD 16
+#define GRTX_REFILL_THRESHOLD 24
 #endif
 #ifndef GRTX_MIN_WAVES_K16
 #define GRTX_MIN_WAVES_K16 3
@@ -781,8 +781,8 @@ grtx_status launch_trace(const TraceScene& b, const grtx_rays* r, const grtx_tra
   int64_t need_blocks = (R + kTraceBlock - 1) / kTraceBlock;
   if (blocks > need_blocks) blocks = (int)std::max<int64_t>(1, need_blocks);
 
-  const int cap_d = p->defer_capacity > 0 ? p->defer_capacity : 128;
-  const int cap_e = p->evict_capacity > 0 ? p->evict_capacity : 128;
+  const int cap_d = p->defer_capacity > 0 ? p->defer_capacity : kDefaultDeferCap;
+  const int cap_e = p->evict_capacity > 0 ? p->evict_capacity : kDefaultEvictCap;
   const int64_t rows = kSpillRows + 2 * (int64_t)cap_d + 2 * (int64_t)cap_e + K;
   const size_t need = (size_t)blocks * kWaves * rows * 64 * sizeof(uint2) + 256;
 
