@@ -124,7 +124,8 @@ def time_launch(fn, stream, reps):
 
 
 def run_proxy(st, cam, cfg, k, stream):
-    """The same frame traced over the 20-face proxy BVH (one BVH leaf per triangle)."""
+    """The same frame traced over the 20-face proxy BVH (one BVH leaf per triangle) and over
+    instances of one shared icosahedron (one leaf per Gaussian)."""
     import numpy as np
     import torch
 
@@ -149,6 +150,40 @@ def run_proxy(st, cam, cfg, k, stream):
     res["proxy_build_ms"] = build_ms
     res["proxy_bvh_bytes"] = int(info["device_bytes"])
     del pb
+    # instances of one shared icosahedron: the proxy's keys with the sphere's BVH size
+    ib = grtx.build(st, alpha_min=amin, kind=grtx.ICO_INSTANCE)
+    for m, name in [(grtx.CHECKPOINT, "checkpoint"), (grtx.RESTART, "restart")]:
+        out = grtx.trace(ib, o, d, k=k, T_min=cfg["T_min"], mode=m, image_width=cam.width)
+        ms = time_launch(lambda: grtx.trace(ib, o, d, k=k, T_min=cfg["T_min"], mode=m, image_width=cam.width,
+                                            out=out), stream, 3)
+        s = grtx.trace(ib, o, d, k=k, T_min=cfg["T_min"], mode=m, image_width=cam.width, stats=True)
+        stt = s["stats"].to(torch.int64).sum(0).cpu().numpy()
+        res[f"ico_{name}_trace_ms"] = ms
+        res[f"ico_{name}_mrays_s"] = cam.n_rays / (ms * 1e-3) / 1e6
+        res[f"ico_{name}_nodes_per_ray"] = float(stt[0] + stt[1]) / cam.n_rays
+    res["ico_bvh_bytes"] = int(ib.info()["device_bytes"])
+    return res
+
+
+def run_ksweep(bvh, o, d, cam, cfg, stream, ks=(4, 8, 16, 32, 64)):
+    """k-buffer size sweep on the same frame, checkpoint and restart: trace time and
+    per-ray fetches and rounds (the cost of re-traversal against the cost of larger
+    buffers)."""
+    import torch
+
+    from paper_2601_20429_amd import grtx
+    res = {}
+    for k in ks:
+        for m, name in [(grtx.CHECKPOINT, "checkpoint"), (grtx.RESTART, "restart")]:
+            out = grtx.trace(bvh, o, d, k=k, T_min=cfg["T_min"], mode=m, image_width=cam.width)
+            ms = time_launch(lambda: grtx.trace(bvh, o, d, k=k, T_min=cfg["T_min"], mode=m, image_width=cam.width,
+                                                out=out), stream, 3)
+            stt = grtx.trace(bvh, o, d, k=k, T_min=cfg["T_min"], mode=m, image_width=cam.width, stats=True)["stats"]
+            stt = stt.to(torch.int64).sum(0).cpu().numpy()
+            R = cam.n_rays
+            res[f"k{k}_{name}"] = dict(ms=round(ms, 3), mrays_s=round(R / (ms * 1e-3) / 1e6, 2),
+                                       nodes_per_ray=round(float(stt[0] + stt[1]) / R, 1),
+                                       rounds_per_ray=round(float(stt[2]) / R, 3))
     return res
 
 
@@ -262,6 +297,7 @@ def main():
     ap.add_argument("--no-proxy", action="store_true", help="skip the 20-face proxy BVH comparison")
     ap.add_argument("--no-backward", action="store_true", help="skip the backward-pass timing")
     ap.add_argument("--no-scene3m", action="store_true", help="skip the 3M-Gaussian workload")
+    ap.add_argument("--no-ksweep", action="store_true", help="skip the k-buffer size sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the ray-sharded multi-GPU "
@@ -367,11 +403,15 @@ def main():
     extra["bvh_bytes"] = int(info["device_bytes"])
     if not args.no_proxy:
         extra.update(run_proxy(st, cam, cfg, args.k, stream))
-        log("proxy", json.dumps({k: v for k, v in extra.items() if k.startswith("proxy")}))
+        log("proxy", json.dumps({k: v for k, v in extra.items() if k.startswith(("proxy", "ico"))}))
     backward = None
     if not args.no_backward:
         backward = run_backward(stream)
         log("backward", json.dumps(backward))
+
+    if not args.no_ksweep:
+        extra["ksweep"] = run_ksweep(bvh, oo, dd, cam, cfg, stream)
+        log("ksweep", json.dumps(extra["ksweep"]))
 
     scene3m = None
     if not args.no_scene3m:

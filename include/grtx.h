@@ -47,8 +47,16 @@ typedef enum grtx_status {
  *   primitive 1). This is the method's structure.
  * PROXY20: one leaf per triangle of a bounding icosahedron per Gaussian (20N leaves),
  *   the monolithic triangle-mesh BVH of the baseline (Sec. III-C, Observation I;
- *   Sec. IV-A). Hits are ordered by the entry distance through the icosahedron. */
-typedef enum grtx_bvh_kind { GRTX_BVH_SPHERE_INSTANCE = 0, GRTX_BVH_PROXY20 = 1 } grtx_bvh_kind;
+ *   Sec. IV-A). Hits are ordered by the entry distance through the icosahedron.
+ * ICO_INSTANCE: one leaf per Gaussian holding its transform, like SPHERE_INSTANCE, but
+ *   the leaf test is the shared icosahedron (inradius 1) in the unit frame: the
+ *   instanced-mesh configuration between the two (Sec. IV-A, one BLAS shared by all
+ *   instances; Sec. V's intermediate design). Keys and images equal PROXY20's. */
+typedef enum grtx_bvh_kind {
+  GRTX_BVH_SPHERE_INSTANCE = 0,
+  GRTX_BVH_PROXY20 = 1,
+  GRTX_BVH_ICO_INSTANCE = 2
+} grtx_bvh_kind;
 
 /* Tracing mode.
  * CHECKPOINT: multi-round k-buffer tracing where each round resumes from the previous
@@ -87,7 +95,7 @@ typedef struct grtx_bvh grtx_bvh;
 
 typedef struct grtx_bvh_info {
   int64_t gaussians;
-  int64_t leaves;         /* gaussians (SPHERE_INSTANCE) or 20*gaussians (PROXY20) */
+  int64_t leaves;         /* gaussians (SPHERE_INSTANCE, ICO_INSTANCE) or 20*gaussians (PROXY20) */
   int64_t internal_nodes; /* leaves - 1 (0 for fewer than two leaves) */
   int64_t device_bytes;   /* bytes the handle owns on the device */
   int32_t kind;

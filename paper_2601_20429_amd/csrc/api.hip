@@ -46,7 +46,8 @@ grtx_status grtx_build(const grtx_gaussians* g, grtx_bvh_kind kind, const grtx_b
   CHECK_ARG(g->count >= 0, "grtx_build: negative Gaussian count");
   CHECK_ARG(g->count < (int64_t)0x7FFFFFFF / 20, "grtx_build: too many Gaussians (%lld)", (long long)g->count);
   CHECK_ARG(g->sh_degree >= 0 && g->sh_degree <= 3, "grtx_build: sh_degree must be 0..3, got %d", g->sh_degree);
-  CHECK_ARG(kind == GRTX_BVH_SPHERE_INSTANCE || kind == GRTX_BVH_PROXY20, "grtx_build: unknown kind %d", (int)kind);
+  CHECK_ARG(kind == GRTX_BVH_SPHERE_INSTANCE || kind == GRTX_BVH_PROXY20 || kind == GRTX_BVH_ICO_INSTANCE,
+            "grtx_build: unknown kind %d", (int)kind);
   CHECK_ARG(p->alpha_min > 0.f && p->alpha_min < 1.f, "grtx_build: alpha_min must be in (0,1)");
   if (g->count > 0)
     CHECK_ARG(g->means && g->scales && g->quats && g->opacities && g->sh, "grtx_build: null Gaussian array");

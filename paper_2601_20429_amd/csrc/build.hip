@@ -337,14 +337,18 @@ __device__ __forceinline__ GaussGeom gauss_geom(const GaussIn& g, int64_t i, flo
   return G;
 }
 
-__device__ __forceinline__ void gauss_box(const GaussIn& g, int64_t i, const GaussGeom& G, float lo[3], float hi[3]) {
+// Box of the bounding ellipsoid scaled by `scale` about mu (1 for the sphere leaf; the
+// icosahedron's circumradius over its inradius for the icosahedron instance leaf, whose
+// mesh lies inside that scaled ellipsoid).
+__device__ __forceinline__ void gauss_box(const GaussIn& g, int64_t i, const GaussGeom& G, float scale, float lo[3],
+                                          float hi[3]) {
   for (int j = 0; j < 3; ++j) {
     float m = g.means[3 * i + j];
     float h = 0.f;
     if (G.active) {
       float v = 0.f;
       for (int k = 0; k < 3; ++k) v += G.R[j][k] * G.R[j][k] * G.s[k] * G.s[k];
-      h = G.rho * sqrtf(v) * kBoxPad;
+      h = G.rho * sqrtf(v) * (kBoxPad * scale);
     }
     lo[j] = m - h;
     hi[j] = m + h;
@@ -353,7 +357,7 @@ __device__ __forceinline__ void gauss_box(const GaussIn& g, int64_t i, const Gau
 
 // Sphere leaves: instance record and box for sorted position p.
 __global__ void __launch_bounds__(kBlock) k_sphere_leaves(GaussIn g, const uint32_t* __restrict__ perm, int64_t n,
-                                                          float alpha_min, float4* __restrict__ inst,
+                                                          float alpha_min, float box_scale, float4* __restrict__ inst,
                                                           float* __restrict__ boxes) {
   int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   if (p >= n) return;
@@ -375,7 +379,7 @@ __global__ void __launch_bounds__(kBlock) k_sphere_leaves(GaussIn g, const uint3
   rr[15] = __uint_as_float(G.active ? 1u : 0u);
   for (int q = 0; q < 4; ++q) inst[4 * p + q] = r[q];
   float lo[3], hi[3];
-  gauss_box(g, i, G, lo, hi);
+  gauss_box(g, i, G, box_scale, lo, hi);
   float* bx = boxes + ((n - 1) + p) * 6;
   for (int a = 0; a < 3; ++a) {
     bx[a] = lo[a];
@@ -855,8 +859,13 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
     hipLaunchKernelGGL(k_proxy_leaves, dim3(grid_for(m)), dim3(kBlock), 0, s, b->perm, m, ttmp, tbox, b->tris,
                        b->boxes);
   } else {
-    hipLaunchKernelGGL(k_sphere_leaves, dim3(grid_for(m)), dim3(kBlock), 0, s, gi, b->perm, m, alpha_min, b->inst,
-                       b->boxes);
+    float box_scale = 1.f;
+    if (kind == GRTX_BVH_ICO_INSTANCE) {
+      static const Ico ico = make_icosahedron();
+      box_scale = std::sqrt(ico.v[0][0] * ico.v[0][0] + ico.v[0][1] * ico.v[0][1] + ico.v[0][2] * ico.v[0][2]);
+    }
+    hipLaunchKernelGGL(k_sphere_leaves, dim3(grid_for(m)), dim3(kBlock), 0, s, gi, b->perm, m, alpha_min, box_scale,
+                       b->inst, b->boxes);
   }
   if (nint > 0) {
     hipLaunchKernelGGL(k_karras, dim3(grid_for(nint)), dim3(kBlock), 0, s, b->codes, m, b->child, b->parent,

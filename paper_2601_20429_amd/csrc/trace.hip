@@ -236,7 +236,55 @@ __device__ __forceinline__ bool proxy_hit(float4 A4, float4 B4, float4 C4, float
 // one wave for larger buffers, which lets the compiler keep the k-buffer and its
 // insertion copies in registers and AGPRs instead of scratch (k = 32: 16 ms against
 // 26 ms at two waves on the 100k-Gaussian frame; k = 64: 37 ms against 163 ms).
-template <int K, bool PROXY, bool STATS>
+// Leaf tests: unit sphere of an instance, a world-space proxy triangle, or the shared
+// icosahedron (inradius 1) of an instance.
+enum : int { kLeafSphere = 0, kLeafTri = 1, kLeafIco = 2 };
+
+// Face normals of the regular icosahedron with vertices at the cyclic permutations of
+// (0, +-1, +-phi): the directions (+-1, +-1, +-1) and the cyclic permutations of
+// (+-1/phi, 0, +-phi), all of length sqrt(3). Scaled to inradius 1 every face plane is
+// n . x = 1 with n the unit normal.
+constexpr float kPhi = (float)1.6180339887498948482;
+constexpr float kInvPhi = (float)0.6180339887498948482;
+constexpr float kInvSqrt3 = (float)0.57735026918962576451;
+
+// Entry distance of the ray through the icosahedron in the unit frame of an instance
+// record (rows of A with mu in the fourth lane): the convex-polytope slab test, entry =
+// the last crossing of a face plane met from outside, exit = the first crossing from
+// inside. The ray parameter is the world one (the map is affine). A ray starting inside
+// has its entry behind the origin and is rejected by the caller's t > t_near test.
+__device__ __forceinline__ bool ico_entry(float4 r0, float4 r1, float4 r2, float ox, float oy, float oz, float dx,
+                                          float dy, float dz, float* tout) {
+  const float fx = ox - r0.w, fy = oy - r1.w, fz = oz - r2.w;
+  const float u[3] = {r0.x * fx + r0.y * fy + r0.z * fz, r1.x * fx + r1.y * fy + r1.z * fz,
+                      r2.x * fx + r2.y * fy + r2.z * fz};
+  const float v[3] = {r0.x * dx + r0.y * dy + r0.z * dz, r1.x * dx + r1.y * dy + r1.z * dz,
+                      r2.x * dx + r2.y * dy + r2.z * dz};
+  float te = -INFINITY, tx = INFINITY;
+  bool outside_parallel = false;
+  auto face = [&](float nx, float ny, float nz) __attribute__((always_inline)) {
+    const float nu = nx * u[0] + ny * u[1] + nz * u[2];
+    const float nv = nx * v[0] + ny * v[1] + nz * v[2];
+    const float t = (1.f - nu) / nv;
+    if (nv < 0.f) te = fmaxf(te, t);
+    if (nv > 0.f) tx = fminf(tx, t);
+    if (nv == 0.f && nu > 1.f) outside_parallel = true;
+  };
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    face((q & 1 ? -kInvSqrt3 : kInvSqrt3), (q & 2 ? -kInvSqrt3 : kInvSqrt3), (q & 4 ? -kInvSqrt3 : kInvSqrt3));
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float a = (q & 1 ? -kInvPhi : kInvPhi) * kInvSqrt3, b = (q & 2 ? -kPhi : kPhi) * kInvSqrt3;
+    face(a, 0.f, b);
+    face(0.f, b, a);
+    face(b, a, 0.f);
+  }
+  *tout = te;
+  return !outside_parallel && te <= tx;
+}
+
+template <int K, int LEAF, bool STATS>
 __global__ void __launch_bounds__(kTraceBlock)
     __attribute__((amdgpu_waves_per_eu(K <= 16 ? GRTX_MIN_WAVES_K16 : 1, 8))) k_trace(TraceArgs A) {
   __shared__ uint2 s_stack[kLdsStack * kTraceBlock];
@@ -461,12 +509,18 @@ __global__ void __launch_bounds__(kTraceBlock)
           has_cur = false;
           // A key never precedes the entry of the leaf's own box, so every ancestor's
           // entry distance bounds the keys below it exactly.
-          if constexpr (PROXY) {
+          if constexpr (LEAF == kLeafTri) {
             const float4* tp = A.tris + 3 * (int64_t)p;
             float4 a4 = tp[0], b4 = tp[1], c4 = tp[2];
             float tt;
             const bool hit = proxy_hit(a4, b4, c4, ox, oy, oz, dx, dy, dz, &tt);
             key = make_key(fmaxf(tt, cur_t), __float_as_uint(a4.w));
+            have_key = hit && tt > tnear && key > tmin;
+          } else if constexpr (LEAF == kLeafIco) {
+            const float4* ip = A.inst + 4 * (int64_t)p;
+            float tt;
+            const bool hit = ico_entry(ip[0], ip[1], ip[2], ox, oy, oz, dx, dy, dz, &tt);
+            key = make_key(fmaxf(tt, cur_t), p);
             have_key = hit && tt > tnear && key > tmin;
           } else {
             const float4* ip = A.inst + 4 * (int64_t)p;
@@ -572,7 +626,7 @@ __global__ void __launch_bounds__(kTraceBlock)
         float4 r0 = ip[0], r1 = ip[1], r2 = ip[2], r3 = ip[3];
         SphereHit h = sphere_terms(r0, r1, r2, ox, oy, oz, dx, dy, dz);
         bool blend = true;
-        if constexpr (PROXY) {
+        if constexpr (LEAF != kLeafSphere) {
           // a proxy hit counts only if the ray meets the bounding ellipsoid itself
           blend = p != prev_id && h.a > 0.f && h.c2 <= h.a;
           prev_id = p;
@@ -697,41 +751,41 @@ struct Pool {
 std::mutex g_pool_lock;
 std::map<std::pair<int, hipStream_t>, Pool> g_pools;
 
-template <int K, bool PROXY>
+template <int K, int LEAF>
 grtx_status launch(const TraceArgs& a, int blocks, hipStream_t s) {
   if (a.stats)
-    hipLaunchKernelGGL((k_trace<K, PROXY, true>), dim3(blocks), dim3(kTraceBlock), 0, s, a);
+    hipLaunchKernelGGL((k_trace<K, LEAF, true>), dim3(blocks), dim3(kTraceBlock), 0, s, a);
   else
-    hipLaunchKernelGGL((k_trace<K, PROXY, false>), dim3(blocks), dim3(kTraceBlock), 0, s, a);
+    hipLaunchKernelGGL((k_trace<K, LEAF, false>), dim3(blocks), dim3(kTraceBlock), 0, s, a);
   GRTX_LAUNCH_CHECK();
   return GRTX_OK;
 }
 
-template <int K, bool PROXY>
+template <int K, int LEAF>
 int blocks_per_cu() {
   // the counting and non-counting kernels are sized alike; take the tighter one
   int nb0 = 0, nb1 = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb0, k_trace<K, PROXY, false>, kTraceBlock, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb0, k_trace<K, LEAF, false>, kTraceBlock, 0) != hipSuccess)
     nb0 = 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb1, k_trace<K, PROXY, true>, kTraceBlock, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb1, k_trace<K, LEAF, true>, kTraceBlock, 0) != hipSuccess)
     nb1 = 1;
   return std::max(1, std::min(nb0, nb1));
 }
 
-template <bool PROXY>
+template <int LEAF>
 int blocks_per_cu_k(int K) {
-  return K == 4 ? blocks_per_cu<4, PROXY>() : K == 8 ? blocks_per_cu<8, PROXY>() : K == 16 ? blocks_per_cu<16, PROXY>()
-       : K == 32 ? blocks_per_cu<32, PROXY>() : blocks_per_cu<64, PROXY>();
+  return K == 4 ? blocks_per_cu<4, LEAF>() : K == 8 ? blocks_per_cu<8, LEAF>() : K == 16 ? blocks_per_cu<16, LEAF>()
+       : K == 32 ? blocks_per_cu<32, LEAF>() : blocks_per_cu<64, LEAF>();
 }
 
-template <bool PROXY>
+template <int LEAF>
 grtx_status launch_k(int K, const TraceArgs& a, int blocks, hipStream_t s) {
   switch (K) {
-    case 4: return launch<4, PROXY>(a, blocks, s);
-    case 8: return launch<8, PROXY>(a, blocks, s);
-    case 16: return launch<16, PROXY>(a, blocks, s);
-    case 32: return launch<32, PROXY>(a, blocks, s);
-    default: return launch<64, PROXY>(a, blocks, s);
+    case 4: return launch<4, LEAF>(a, blocks, s);
+    case 8: return launch<8, LEAF>(a, blocks, s);
+    case 16: return launch<16, LEAF>(a, blocks, s);
+    case 32: return launch<32, LEAF>(a, blocks, s);
+    default: return launch<64, LEAF>(a, blocks, s);
   }
 }
 
@@ -774,8 +828,9 @@ grtx_status launch_trace(const TraceScene& b, const grtx_rays* r, const grtx_tra
     cached_cus = prop.multiProcessorCount;
   }
   const int K = p->k <= 4 ? 4 : p->k <= 8 ? 8 : p->k <= 16 ? 16 : p->k <= 32 ? 32 : 64;
-  const bool proxy = b.kind == GRTX_BVH_PROXY20;
-  int bpc = proxy ? blocks_per_cu_k<true>(K) : blocks_per_cu_k<false>(K);
+  const int leaf = b.kind == GRTX_BVH_PROXY20 ? kLeafTri : b.kind == GRTX_BVH_ICO_INSTANCE ? kLeafIco : kLeafSphere;
+  int bpc = leaf == kLeafTri ? blocks_per_cu_k<kLeafTri>(K)
+          : leaf == kLeafIco ? blocks_per_cu_k<kLeafIco>(K) : blocks_per_cu_k<kLeafSphere>(K);
   int blocks = cached_cus * bpc;
   // never more waves than rays need
   int64_t need_blocks = (R + kTraceBlock - 1) / kTraceBlock;
@@ -845,7 +900,8 @@ grtx_status launch_trace(const TraceScene& b, const grtx_rays* r, const grtx_tra
   a.cap_e = cap_e;
   a.chunk_len = ((a.n_work + 64 * kChunks - 1) / (64 * kChunks)) * 64;
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, pool->counter);
-  return proxy ? launch_k<true>(K, a, blocks, s) : launch_k<false>(K, a, blocks, s);
+  return leaf == kLeafTri ? launch_k<kLeafTri>(K, a, blocks, s)
+       : leaf == kLeafIco ? launch_k<kLeafIco>(K, a, blocks, s) : launch_k<kLeafSphere>(K, a, blocks, s);
 }
 
 }  // namespace grtx

@@ -25,6 +25,7 @@ ERR_INTERNAL = 6
 
 SPHERE_INSTANCE = 0
 PROXY20 = 1
+ICO_INSTANCE = 2
 CHECKPOINT = 0
 RESTART = 1
 

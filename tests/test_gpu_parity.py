@@ -369,6 +369,43 @@ def test_proxy_scene100k_parity_sampled():
         assert np.array_equal(g[key], g2[key]), key
 
 
+# ------------------------------------------------------------------ instanced icosahedron
+
+@pytest.mark.parametrize("mode", [grtx.CHECKPOINT, grtx.RESTART])
+def test_ico_instance_plain_parity(mode):
+    """Instances of one shared icosahedron (inradius 1 in each Gaussian's unit frame): the
+    same keys as the 20-triangle proxy mesh, checked against the oracle's proxy-key mode."""
+    say("ico instance plain mode", mode)
+    scene = inputs.small_scene(1, 1000)
+    o, d = oracle_rays(inputs.orbit_camera(64, 64))
+    bvh = build(scene, grtx.ICO_INSTANCE)
+    assert bvh.info()["leaves"] == scene.n
+    g = render(bvh, o, d, k=4, mode=mode, cap=256)
+    ref = oracle.render(scene, o, d, AMIN, T_MIN, key_mode=1, cap=256)
+    s = parity.compare_render(scene, o, d, g, ref, AMIN, T_MIN, label=f"ico plain mode={mode}", key_mode=1)
+    say(s)
+
+
+def test_ico_instance_scene100k_parity_sampled():
+    """100k scene-scale Gaussians, sampled primary and incoherent rays, k = 16: against the
+    oracle's proxy key, and checkpoint equal to restart; the images equal the proxy mesh's
+    up to the allowed exceptions."""
+    say("ico instance 100k")
+    scene = inputs.cluster_scene(2, 100_000, 3)
+    o, d = oracle_rays(inputs.orbit_camera(800, 800))
+    idx = inputs.ray_subsample(98, o.shape[0], 768)
+    io, id_ = inputs.incoherent_rays(77, 256)
+    o, d = np.concatenate([o[idx], io]), np.concatenate([d[idx], id_])
+    bvh = build(scene, grtx.ICO_INSTANCE)
+    g = render(bvh, o, d, k=16, cap=512)
+    ref = oracle.render(scene, o, d, AMIN, T_MIN, key_mode=1, cap=512)
+    s = parity.compare_render(scene, o, d, g, ref, AMIN, T_MIN, label="ico 100k", key_mode=1)
+    say(s)
+    g2 = render(bvh, o, d, k=16, mode=grtx.RESTART, cap=512)
+    for key in ["rgb", "depth", "hit_ids", "hit_counts"]:
+        assert np.array_equal(g[key], g2[key]), key
+
+
 def test_proxy_topology_and_boxes():
     say("proxy topology")
     from tests.test_oracle_pins import _check_radix_tree
