@@ -17,10 +17,17 @@
 //   dL/dM = g_u f^T + g_v d^T, dL/dmu = -M^T g_u, dL/ds_i = -(1/s_i) sum_j g_M[i][j] M[i][j],
 //   dL/dR[j][i] = g_M[i][j] / s_i, then through R(q/|q|) to q; dL/do = dL/da * a / o;
 //   dL/dsh[l,m,ch] = dL/dc_ch * [c_ch > 0] * Y_lm(d).
-// Each ray's contributions are added to the caller's gradient arrays with FP32 atomics.
+// The sum over rays is done without atomics and in a fixed order: a first kernel writes
+// one 64-byte record per (ray, blended hit) with the hit's gradients of mean, scale,
+// rotation and opacity and the three colour factors dL/dc * T a [c > 0]; the records
+// are sorted by Gaussian (stable radix sort, so ray order is kept inside a Gaussian);
+// one wave per Gaussian then sums its records (dL/dsh = colour factor x Y(ray direction))
+// and adds the totals to the caller's arrays. Results are deterministic.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "grtx_internal.h"
 
@@ -91,25 +98,39 @@ struct BwdArgs {
   const float* g_rgb;
   const float* g_depth;
   const float* g_opacity;
-  float* d_means;
-  float* d_scales;
-  float* d_quats;
-  float* d_opac;
-  float* d_sh;
+  int64_t n_gauss;
+  const uint32_t* pair_off;  // per ray: first record
+  float4* rec;               // per (ray, hit): 4 x float4
+  uint64_t* key;             // per record: Gaussian index
+  uint32_t* val;             // per record: its own index (permuted by the sort)
   unsigned int* truncated;
 };
 
-__global__ void __launch_bounds__(kBlock) k_backward(BwdArgs A) {
+// Record layout: q0 = (dmu.xyz, ds.x), q1 = (ds.yz, dq.wx), q2 = (dq.yz, do, gc.r),
+// q3 = (gc.g, gc.b, ray index bits, 0).
+
+// Records per ray (the blended hits the forward pass listed, at most hit_cap).
+__global__ void __launch_bounds__(kBlock) k_bwd_count(const int32_t* __restrict__ hit_counts, int64_t n, int cap,
+                                                      uint32_t* __restrict__ cnt, unsigned int* truncated) {
+  const int64_t r = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (r >= n) return;
+  int c = hit_counts[r];
+  if (c > cap) {
+    atomicAdd(truncated, 1u);
+    c = cap;
+  }
+  cnt[r] = (uint32_t)(c < 0 ? 0 : c);
+}
+
+__global__ void __launch_bounds__(kBlock) k_bwd_pairs(BwdArgs A) {
   const int64_t r = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   if (r >= A.n_rays) return;
   const float ox = A.ray_o[3 * r], oy = A.ray_o[3 * r + 1], oz = A.ray_o[3 * r + 2];
   const float dx = A.ray_d[3 * r], dy = A.ray_d[3 * r + 1], dz = A.ray_d[3 * r + 2];
   int n = A.hit_counts[r];
-  if (n > A.hit_cap) {
-    atomicAdd(A.truncated, 1u);
-    n = A.hit_cap;
-  }
-  if (n == 0) return;
+  n = n > A.hit_cap ? A.hit_cap : n;
+  if (n <= 0) return;
+  const uint32_t base = A.pair_off[r];
   const float TN = 1.f - A.opacity[r];
   const float bg[3] = {A.bg0, A.bg1, A.bg2};
   float Cf[3], gC[3];
@@ -128,6 +149,13 @@ __global__ void __launch_bounds__(kBlock) k_backward(BwdArgs A) {
   float T = 1.f, Cacc[3] = {0.f, 0.f, 0.f}, Dacc = 0.f;
   for (int h = 0; h < n; ++h) {
     const int64_t i = A.hit_ids[r * A.hit_cap + h];
+    if (i < 0 || i >= A.n_gauss) {  // not a Gaussian of this scene: an empty record, sorted last
+      const uint32_t pi = base + (uint32_t)h;
+      for (int q = 0; q < 4; ++q) A.rec[4 * (int64_t)pi + q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      A.key[pi] = (uint64_t)A.n_gauss;
+      A.val[pi] = pi;
+      continue;
+    }
     // ---- recompute the hit
     const float* q4 = A.quats + 4 * i;
     const float qn = sqrtf(q4[0] * q4[0] + q4[1] * q4[1] + q4[2] * q4[2] + q4[3] * q4[3]);
@@ -179,16 +207,12 @@ __global__ void __launch_bounds__(kBlock) k_backward(BwdArgs A) {
     gA += gO * (TN * inv1ma);
     const float gT = gD * wgt;  // dL/dt_alpha
     T *= (1.f - alpha);
-    // ---- SH
-    for (int ch = 0; ch < 3; ++ch) {
-      if (!pos[ch] || gC[ch] == 0.f) continue;
-      const float gc = gC[ch] * wgt;
-      for (int k = 0; k < 16; ++k)
-        if (k < ncoef) atomicAdd(A.d_sh + i * 3 * ncoef + 3 * k + ch, gc * Y[k]);
-    }
+    // ---- SH: the colour factors (dL/dsh = factor x Y is formed per Gaussian)
+    float gcol[3];
+    for (int ch = 0; ch < 3; ++ch) gcol[ch] = pos[ch] ? gC[ch] * wgt : 0.f;
     (void)bg;
     // ---- alpha -> opacity, m2
-    atomicAdd(A.d_opac + i, gA * G);
+    const float g_op = gA * G;
     const float gm2 = gA * (-0.5f * alpha);
     float gu[3], gv[3];
     for (int a = 0; a < 3; ++a) {
@@ -199,10 +223,8 @@ __global__ void __launch_bounds__(kBlock) k_backward(BwdArgs A) {
     float gM[3][3];
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) gM[a][b] = gu[a] * f[b] + gv[a] * dv[b];
-    for (int b = 0; b < 3; ++b) {
-      const float gf = M[0][b] * gu[0] + M[1][b] * gu[1] + M[2][b] * gu[2];
-      atomicAdd(A.d_means + 3 * i + b, -gf);
-    }
+    float g_mu[3], g_s[3];
+    for (int b = 0; b < 3; ++b) g_mu[b] = -(M[0][b] * gu[0] + M[1][b] * gu[1] + M[2][b] * gu[2]);
     float gR[3][3];
     for (int a = 0; a < 3; ++a) {
       float gs = 0.f;
@@ -210,7 +232,7 @@ __global__ void __launch_bounds__(kBlock) k_backward(BwdArgs A) {
         gs += gM[a][b] * M[a][b];
         gR[b][a] = gM[a][b] / s[a];
       }
-      atomicAdd(A.d_scales + 3 * i + a, -gs / s[a]);
+      g_s[a] = -gs / s[a];
     }
     // ---- R(qhat) -> qhat -> q
     const float gw = 2.f * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2] - y * gR[2][0] + x * gR[2][1]);
@@ -221,14 +243,131 @@ __global__ void __launch_bounds__(kBlock) k_backward(BwdArgs A) {
     const float gz = 2.f * (-2.f * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] - 2.f * z * gR[1][1] +
                             y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
     const float dot = w * gw + x * gx + y * gy + z * gz;
-    atomicAdd(A.d_quats + 4 * i + 0, (gw - w * dot) / qn);
-    atomicAdd(A.d_quats + 4 * i + 1, (gx - x * dot) / qn);
-    atomicAdd(A.d_quats + 4 * i + 2, (gy - y * dot) / qn);
-    atomicAdd(A.d_quats + 4 * i + 3, (gz - z * dot) / qn);
+    const uint32_t pi = base + (uint32_t)h;
+    float4* rp = A.rec + 4 * (int64_t)pi;
+    rp[0] = make_float4(g_mu[0], g_mu[1], g_mu[2], g_s[0]);
+    rp[1] = make_float4(g_s[1], g_s[2], (gw - w * dot) / qn, (gx - x * dot) / qn);
+    rp[2] = make_float4((gy - y * dot) / qn, (gz - z * dot) / qn, g_op, gcol[0]);
+    rp[3] = make_float4(gcol[1], gcol[2], __uint_as_float((uint32_t)r), 0.f);
+    A.key[pi] = (uint64_t)i;
+    A.val[pi] = pi;
+  }
+}
+
+// Per Gaussian: [first[g], last[g]) in the sorted records (empty when untouched).
+__global__ void __launch_bounds__(kBlock) k_bwd_segments(const uint64_t* __restrict__ key, int64_t P, int64_t n_gauss,
+                                                         uint32_t* __restrict__ first, uint32_t* __restrict__ last) {
+  const int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (p >= P) return;
+  const uint64_t k = key[p];
+  if (k >= (uint64_t)n_gauss) return;
+  if (p == 0 || key[p - 1] != k) first[k] = (uint32_t)p;
+  if (p == P - 1 || key[p + 1] != k) last[k] = (uint32_t)(p + 1);
+}
+
+struct ReduceArgs {
+  const float4* rec;
+  const uint32_t* order;  // sorted position -> record
+  const uint32_t* first;
+  const uint32_t* last;
+  const float* ray_d;
+  int sh_degree;
+  int64_t n_gauss;
+  float* d_means;
+  float* d_scales;
+  float* d_quats;
+  float* d_opac;
+  float* d_sh;
+};
+
+__device__ __forceinline__ float wave_sum(float v) {
+  // fixed butterfly: the same order on every run
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// One wave per Gaussian: lanes take the Gaussian's records in sorted order with stride 64,
+// sum them, and the wave adds the totals to the caller's arrays (no other wave writes
+// them, so plain read-add-write).
+__global__ void __launch_bounds__(kBlock) k_bwd_reduce(ReduceArgs A) {
+  const int64_t g = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (g >= A.n_gauss) return;
+  const uint32_t b = A.first[g], e = A.last[g];
+  if (e <= b) return;
+  const int ncoef = (A.sh_degree + 1) * (A.sh_degree + 1);
+  float acc[11];
+  float sh[16][3];
+#pragma unroll
+  for (int q = 0; q < 11; ++q) acc[q] = 0.f;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) sh[k][0] = sh[k][1] = sh[k][2] = 0.f;
+  for (uint32_t p = b + lane; p < e; p += 64) {
+    const float4* rp = A.rec + 4 * (int64_t)A.order[p];
+    const float4 q0 = rp[0], q1 = rp[1], q2 = rp[2], q3 = rp[3];
+    acc[0] += q0.x; acc[1] += q0.y; acc[2] += q0.z; acc[3] += q0.w;
+    acc[4] += q1.x; acc[5] += q1.y; acc[6] += q1.z; acc[7] += q1.w;
+    acc[8] += q2.x; acc[9] += q2.y; acc[10] += q2.z;
+    const int64_t r = __float_as_uint(q3.z);
+    const float dx = A.ray_d[3 * r], dy = A.ray_d[3 * r + 1], dz = A.ray_d[3 * r + 2];
+    const float dn = rsqrtf(dx * dx + dy * dy + dz * dz);
+    float Y[16];
+    basis(dx * dn, dy * dn, dz * dn, A.sh_degree, Y);
+    const float gc[3] = {q2.w, q3.x, q3.y};
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (k < ncoef) {
+        sh[k][0] += gc[0] * Y[k];
+        sh[k][1] += gc[1] * Y[k];
+        sh[k][2] += gc[2] * Y[k];
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < 11; ++q) acc[q] = wave_sum(acc[q]);
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (k < ncoef) {
+      sh[k][0] = wave_sum(sh[k][0]);
+      sh[k][1] = wave_sum(sh[k][1]);
+      sh[k][2] = wave_sum(sh[k][2]);
+    }
+  if (lane == 0) {
+    for (int a = 0; a < 3; ++a) A.d_means[3 * g + a] += acc[a];
+    for (int a = 0; a < 3; ++a) A.d_scales[3 * g + a] += acc[3 + a];
+    for (int a = 0; a < 4; ++a) A.d_quats[4 * g + a] += acc[6 + a];
+    A.d_opac[g] += acc[10];
+    for (int k = 0; k < 16; ++k)
+      if (k < ncoef)
+        for (int ch = 0; ch < 3; ++ch) A.d_sh[g * 3 * ncoef + 3 * k + ch] += sh[k][ch];
   }
 }
 
 __global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
+
+__global__ void __launch_bounds__(kBlock) k_fill_u32_bwd(uint32_t* p, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+inline unsigned grid(int64_t n, int per = kBlock) { return (unsigned)std::max<int64_t>(1, (n + per - 1) / per); }
+
+// Stream-ordered scratch of one backward call.
+struct BwdScratch {
+  std::vector<void*> ptrs;
+  hipStream_t s;
+  ~BwdScratch() {
+    for (void* p : ptrs) (void)hipFreeAsync(p, s);
+  }
+  template <class T>
+  grtx_status get(T** p, size_t count) {
+    void* q = nullptr;
+    GRTX_HIP(hipMallocAsync(&q, std::max<size_t>(count, 1) * sizeof(T), s));
+    ptrs.push_back(q);
+    *p = static_cast<T*>(q);
+    return GRTX_OK;
+  }
+};
 
 }  // namespace
 
@@ -237,7 +376,30 @@ grtx_status trace_backward(const grtx_gaussians* g, const grtx_rays* r, const gr
                            const float* grad_opacity, const grtx_gaussian_grads* grads, unsigned int* truncated,
                            hipStream_t s) {
   const int64_t R = r->count;
-  if (R == 0 || g->count == 0) return GRTX_OK;
+  const int64_t N = g->count;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, truncated);
+  GRTX_LAUNCH_CHECK();
+  if (R == 0 || N == 0) return GRTX_OK;
+  if ((double)R * (double)std::max(fwd->hit_capacity, 0) >= 4294967295.0) {
+    set_error("trace_backward: %lld rays x %d listed hits exceed 2^32 records", (long long)R, fwd->hit_capacity);
+    return GRTX_ERR_INVALID_ARG;
+  }
+  BwdScratch sc{{}, s};
+  // 1. records per ray and their offsets (one host read of the total)
+  uint32_t *cnt = nullptr, *off = nullptr;
+  GRTX_TRY(sc.get(&cnt, R));
+  GRTX_TRY(sc.get(&off, R));
+  hipLaunchKernelGGL(k_bwd_count, dim3(grid(R)), dim3(kBlock), 0, s, fwd->hit_counts, R, fwd->hit_capacity, cnt,
+                     truncated);
+  GRTX_LAUNCH_CHECK();
+  GRTX_TRY(exclusive_scan_u32(cnt, off, R, s));
+  uint32_t tail[2] = {0u, 0u};
+  GRTX_HIP(hipMemcpyAsync(&tail[0], off + (R - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  GRTX_HIP(hipMemcpyAsync(&tail[1], cnt + (R - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  GRTX_HIP(hipStreamSynchronize(s));
+  const int64_t P = (int64_t)tail[0] + tail[1];
+  if (P == 0) return GRTX_OK;
+  // 2. one record per (ray, blended hit)
   BwdArgs a{};
   a.means = g->means;
   a.scales = g->scales;
@@ -260,14 +422,40 @@ grtx_status trace_backward(const grtx_gaussians* g, const grtx_rays* r, const gr
   a.g_rgb = grad_rgb;
   a.g_depth = grad_depth;
   a.g_opacity = grad_opacity;
-  a.d_means = grads->means;
-  a.d_scales = grads->scales;
-  a.d_quats = grads->quats;
-  a.d_opac = grads->opacities;
-  a.d_sh = grads->sh;
+  a.n_gauss = N;
+  a.pair_off = off;
+  GRTX_TRY(sc.get(&a.rec, 4 * P));
+  GRTX_TRY(sc.get(&a.key, P));
+  GRTX_TRY(sc.get(&a.val, P));
   a.truncated = truncated;
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, truncated);
-  hipLaunchKernelGGL(k_backward, dim3((unsigned)((R + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_bwd_pairs, dim3(grid(R)), dim3(kBlock), 0, s, a);
+  GRTX_LAUNCH_CHECK();
+  // 3. group by Gaussian, keeping ray order inside a Gaussian
+  int bits = 1;  // keys are 0..N (N marks a record of no Gaussian)
+  while (bits < 63 && ((int64_t)1 << bits) <= N) ++bits;
+
+  GRTX_TRY(sort_by_key(a.key, a.val, P, bits, s));
+  // 4. segments and per-Gaussian sums
+  uint32_t *first = nullptr, *last = nullptr;
+  GRTX_TRY(sc.get(&first, N));
+  GRTX_TRY(sc.get(&last, N));
+  hipLaunchKernelGGL(k_fill_u32_bwd, dim3(grid(N)), dim3(kBlock), 0, s, first, N);
+  hipLaunchKernelGGL(k_fill_u32_bwd, dim3(grid(N)), dim3(kBlock), 0, s, last, N);
+  hipLaunchKernelGGL(k_bwd_segments, dim3(grid(P)), dim3(kBlock), 0, s, a.key, P, N, first, last);
+  ReduceArgs ra{};
+  ra.rec = a.rec;
+  ra.order = a.val;
+  ra.first = first;
+  ra.last = last;
+  ra.ray_d = r->dirs;
+  ra.sh_degree = g->sh_degree;
+  ra.n_gauss = N;
+  ra.d_means = grads->means;
+  ra.d_scales = grads->scales;
+  ra.d_quats = grads->quats;
+  ra.d_opac = grads->opacities;
+  ra.d_sh = grads->sh;
+  hipLaunchKernelGGL(k_bwd_reduce, dim3(grid(N * 64)), dim3(kBlock), 0, s, ra);
   GRTX_LAUNCH_CHECK();
   return GRTX_OK;
 }

@@ -671,11 +671,6 @@ grtx_status dalloc(Bvh* b, T** p, size_t count) {
   return GRTX_OK;
 }
 
-#define GRTX_TRY(x)                  \
-  do {                               \
-    grtx_status st_ = (x);           \
-    if (st_ != GRTX_OK) return st_;  \
-  } while (0)
 
 // Scratch buffers of one build, released when the build function returns (stream-ordered
 // frees keep them valid for the enqueued kernels).
@@ -697,7 +692,7 @@ struct Scratch {
 
 // Sort (codes, idx) ascending by code, stable; results in keys/vals (ping-pong with tmp).
 grtx_status radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t* tvals, int64_t n, Scratch& sc,
-                       hipStream_t s) {
+                       hipStream_t s, int passes = 8) {
   int nblocks = (int)((n + kRadixTile - 1) / kRadixTile);
   int64_t hn = (int64_t)256 * nblocks;
   uint32_t *hist = nullptr, *offs = nullptr, *part = nullptr;
@@ -713,7 +708,7 @@ grtx_status radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t
   uint32_t* vin = vals;
   uint64_t* kout = tkeys;
   uint32_t* vout = tvals;
-  for (int pass = 0; pass < 8; ++pass) {
+  for (int pass = 0; pass < passes; ++pass) {
     int shift = 8 * pass;
     hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kBlock), 0, s, kin, n, shift, hist, nblocks);
     if (nparts > 1) {
@@ -729,7 +724,10 @@ grtx_status radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t
     std::swap(kin, kout);
     std::swap(vin, vout);
   }
-  // 8 passes: the result is back in (keys, vals)
+  if (kin != keys) {  // an odd number of passes leaves the result in the temporaries
+    GRTX_HIP(hipMemcpyAsync(keys, kin, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+    GRTX_HIP(hipMemcpyAsync(vals, vin, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
+  }
   return GRTX_OK;
 }
 
@@ -929,6 +927,38 @@ grtx_status pinhole_rays(const grtx_camera* cam, float* origins, float* dirs, hi
                      dirs);
   GRTX_LAUNCH_CHECK();
   return GRTX_OK;
+}
+
+grtx_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return GRTX_OK;
+  Scratch sc{{}, s};
+  const int nparts = (int)((n + kScanChunk - 1) / kScanChunk);
+  if (nparts > kScanChunk) {
+    set_error("scan: %lld values exceed the supported size", (long long)n);
+    return GRTX_ERR_INVALID_ARG;
+  }
+  if (nparts > 1) {
+    uint32_t* part = nullptr;
+    GRTX_TRY(sc.get(&part, nparts));
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nparts), dim3(kBlock), 0, s, in, n, part);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, s, part, nparts);
+    hipLaunchKernelGGL(k_scan_down, dim3(nparts), dim3(kBlock), 0, s, in, n, part, out);
+  } else {
+    hipLaunchKernelGGL(k_scan_down, dim3(1), dim3(kBlock), 0, s, in, n, (const uint32_t*)nullptr, out);
+  }
+  GRTX_LAUNCH_CHECK();
+  return GRTX_OK;
+}
+
+grtx_status sort_by_key(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, hipStream_t s) {
+  if (n <= 1) return GRTX_OK;
+  Scratch sc{{}, s};
+  uint64_t* tkeys = nullptr;
+  uint32_t* tvals = nullptr;
+  GRTX_TRY(sc.get(&tkeys, n));
+  GRTX_TRY(sc.get(&tvals, n));
+  const int passes = std::max(1, std::min(8, (key_bits + 7) / 8));
+  return radix_sort(keys, vals, tkeys, tvals, n, sc, s, passes);
 }
 
 }  // namespace grtx

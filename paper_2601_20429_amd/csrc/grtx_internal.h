@@ -83,6 +83,13 @@ struct Bvh {
 void set_error(const char* fmt, ...);
 void clear_error();
 
+// Propagate a non-OK status from a library call.
+#define GRTX_TRY(x)                  \
+  do {                               \
+    grtx_status st_ = (x);           \
+    if (st_ != GRTX_OK) return st_;  \
+  } while (0)
+
 #define GRTX_HIP(call)                                                                  \
   do {                                                                                  \
     hipError_t e_ = (call);                                                             \
@@ -141,6 +148,12 @@ grtx_status serve_poll(Server* sv, uint64_t ticket, grtx_request_result* res);
 grtx_status serve_release(Server* sv, uint64_t ticket);
 grtx_status serve_stats(Server* sv, grtx_serve_stats* st);
 grtx_status serve_destroy(Server* sv);
+// Device utilities of the build, reused by the backward pass (stream-ordered scratch).
+// Exclusive prefix sum of n uint32 values.
+grtx_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
+// Stable LSD radix sort of (keys, vals) by the low key_bits bits of the keys, in place.
+grtx_status sort_by_key(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, hipStream_t s);
+
 grtx_status trace_backward(const grtx_gaussians* g, const grtx_rays* r, const grtx_trace_params* p,
                            const grtx_trace_outputs* fwd, const float* grad_rgb, const float* grad_depth,
                            const float* grad_opacity, const grtx_gaussian_grads* grads, unsigned int* truncated,

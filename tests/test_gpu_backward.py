@@ -112,8 +112,8 @@ def test_gradients_match_oracle_finite_differences():
 
 
 def test_backward_is_repeatable_and_finite_at_scale():
-    """200k-Gaussian scene, 512x512 rays, k = 16: gradients are finite and two runs agree
-    to within FP32 atomic-accumulation order."""
+    """200k-Gaussian scene, 512x512 rays, k = 16: gradients are finite and two runs are
+    bit-identical (the per-Gaussian sums run in a fixed order)."""
     say("backward 200k 512x512")
     cfg = inputs.DIFF200K
     scene = inputs.cluster_scene(cfg["seed"], cfg["n"], 3)
@@ -129,6 +129,5 @@ def test_backward_is_repeatable_and_finite_at_scale():
     for k in g1:
         a, b = g1[k], g2[k]
         assert torch.isfinite(a).all(), k
-        scale = float(a.abs().max()) + 1e-30
-        assert float((a - b).abs().max()) <= 1e-4 * scale, k
+        assert torch.equal(a, b), k
     assert float(g1["opacities"].abs().sum()) > 0
