@@ -591,16 +591,28 @@ __global__ void __launch_bounds__(kBlock) k_wide(int64_t n, const uint32_t* __re
                                                  const float* __restrict__ boxes, float4* __restrict__ nodes) {
   const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   if (i >= n - 1) return;
-  uint32_t ref[4] = {kNoChild, kNoChild, kNoChild, kNoChild};
-  int cnt = 0;
-  for (int k = 0; k < 2; ++k) {
-    const uint32_t c = child[2 * i + k];
-    if (c & kLeafFlag) {
-      ref[cnt++] = c;
-    } else {
-      ref[cnt++] = child[2 * (int64_t)c];
-      ref[cnt++] = child[2 * (int64_t)c + 1];
+  // Start from the two children and open the internal entry of largest surface area
+  // until there are four entries or none is internal (greedy collapse; every internal
+  // node has a record, so a record may list nodes from any depth below it).
+  uint32_t ref[4] = {child[2 * i], child[2 * i + 1], kNoChild, kNoChild};
+  int cnt = 2;
+  while (cnt < 4) {
+    int best = -1;
+    float best_area = -1.f;
+    for (int j = 0; j < cnt; ++j) {
+      if (ref[j] & kLeafFlag) continue;
+      const float* bb = boxes + 6 * (int64_t)ref[j];
+      const float ex = bb[3] - bb[0], ey = bb[4] - bb[1], ez = bb[5] - bb[2];
+      const float area = ex * ey + ey * ez + ez * ex;
+      if (area > best_area) {
+        best_area = area;
+        best = j;
+      }
     }
+    if (best < 0) break;
+    const uint32_t c = ref[best];
+    ref[best] = child[2 * (int64_t)c];
+    ref[cnt++] = child[2 * (int64_t)c + 1];
   }
   const float* own = boxes + 6 * i;  // the union of the children's boxes
   float org[3], step[3];

@@ -18,9 +18,10 @@ namespace grtx {
 // ---------------------------------------------------------------------------------------
 //
 // Node record, 64 B (4 x float4), one per internal node of the binary radix tree (node 0
-// = root). A record lists up to four children: the node's two children, each internal
-// one replaced by its own two, so a traversal from the root visits every other level of
-// the binary tree (records of nodes at odd depth are never reached). The children's boxes
+// = root). A record lists up to four descendants that partition its leaves: starting
+// from the node's two children, the internal entry of largest surface area is replaced
+// by its two children until there are four (records of nodes that no traversal reaches
+// are built but never read). The children's boxes
 // are stored on an 8-bit grid over the node's own box: per axis a an origin o_a (the box
 // minimum) and a power-of-two step s_a with extent / s_a <= 254; child j's planes are
 // o_a + q * s_a with q rounded outward (lo down, hi up), so each stored box contains

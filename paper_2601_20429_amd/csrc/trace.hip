@@ -51,9 +51,10 @@ namespace {
 constexpr int kTraceBlock = 256;
 constexpr int kWaves = kTraceBlock / 64;
 constexpr int kLdsStack = GRTX_LDS_STACK;  // per-lane stack entries held in LDS
-// A radix tree over 95-bit keys is at most 96 levels deep, so a path visits at most 48
-// four-wide records, each leaving at most three entries pending.
-constexpr int kMaxStack = 3 * 48 + 16;
+// A radix tree over 95-bit keys is at most 96 levels deep; a record's children lie one
+// to three levels below it, so a path visits at most 96 records, each leaving at most
+// three entries pending.
+constexpr int kMaxStack = 3 * 96 + 16;
 constexpr int kSpillRows = kMaxStack - kLdsStack;
 constexpr int kRefillThreshold = GRTX_REFILL_THRESHOLD;  // idle lanes that end a traversal burst
 #ifndef GRTX_CHUNKS
