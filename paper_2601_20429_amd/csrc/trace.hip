@@ -43,7 +43,7 @@ namespace {
 #define GRTX_LDS_STACK 16
 #endif
 #ifndef GRTX_REFILL_THRESHOLD
-#define GRTX_REFILL_THRESHOLD 24
+#define GRTX_REFILL_THRESHOLD 32
 #endif
 #ifndef GRTX_MIN_WAVES_K16
 #define GRTX_MIN_WAVES_K16 3
@@ -453,11 +453,12 @@ __global__ void __launch_bounds__(kTraceBlock)
     }
 
     // ---------------------------------------------------------------- traversal
-    // Each step is either a node step (lanes holding an internal node descend) or a leaf
-    // step (lanes holding a leaf test it, and every pending hit key goes through the
-    // k-buffer insertion). Leaf steps wait until half of the traversing lanes have a leaf
-    // or a key, or until no lane can descend, so the insertion chain runs for many lanes
-    // at once (while-while traversal with postponed leaves, Aila and Laine 2009).
+    // Each iteration runs a node step for the lanes holding an internal node (they descend
+    // one record) and then a leaf step for the lanes holding a leaf, including a leaf the
+    // node step has just reached, or a pending hit key (the leaf is tested and every key
+    // goes through the k-buffer insertion). Both steps in one iteration ("if-if" in Aila
+    // and Laine's terms) measured faster here than alternating whole-wave node and leaf
+    // steps: every traversing lane progresses in every iteration.
     while (true) {
       const uint64_t trav = __ballot(state == kTrav);
       if (!trav) break;
@@ -498,11 +499,68 @@ __global__ void __launch_bounds__(kTraceBlock)
           }
         }
       }
-      const bool leafy = state == kTrav && (have_key || (has_cur && (cur_ref & kLeafFlag)));
       const bool nodey = state == kTrav && has_cur && !(cur_ref & kLeafFlag);
-      const uint64_t mleaf = __ballot(leafy);
-      const uint64_t mnode = __ballot(nodey);
-      if (mleaf != 0 && (mnode == 0 || 2 * __popcll(mleaf) >= __popcll(trav))) {
+      if (__ballot(nodey) != 0) {
+        if (nodey) {
+          // ------------------------------------------------ node step: four children
+          // Slab distances straight from the 8-bit planes: t = q * (s * inv) + (o - ray) * inv.
+          // A child's entry is raised to at least the entry of the node in hand, so entries
+          // never decrease along a path whatever the rounding, and a node whose entry exceeds
+          // t_max holds no key at or below t_max (keys are clamped to their leaf's entry).
+          const float4* np = A.nodes + kNodeF4 * (int64_t)cur_ref;
+          const float4 q0 = np[0], q1 = np[1], q2 = np[2], q3 = np[3];
+          STAT(GRTX_STAT_NODES);
+          const float tlo = fmaxf(tnear, key_t(tmin));
+          const float Ax = q0.w * ix, Ay = q1.x * iy, Az = q1.y * iz;
+          const float Bx = (q0.x - ox) * ix, By = (q0.y - oy) * iy, Bz = (q0.z - oz) * iz;
+          const uint32_t wlx = __float_as_uint(q2.z), wly = __float_as_uint(q2.w), wlz = __float_as_uint(q3.x);
+          const uint32_t whx = __float_as_uint(q3.y), why = __float_as_uint(q3.z), whz = __float_as_uint(q3.w);
+          uint32_t c[4] = {__float_as_uint(q1.z), __float_as_uint(q1.w), __float_as_uint(q2.x), __float_as_uint(q2.y)};
+          float t[4];
+  #pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float t0x = fmaf((float)((wlx >> (8 * j)) & 0xFFu), Ax, Bx);
+            const float t1x = fmaf((float)((whx >> (8 * j)) & 0xFFu), Ax, Bx);
+            const float t0y = fmaf((float)((wly >> (8 * j)) & 0xFFu), Ay, By);
+            const float t1y = fmaf((float)((why >> (8 * j)) & 0xFFu), Ay, By);
+            const float t0z = fmaf((float)((wlz >> (8 * j)) & 0xFFu), Az, Bz);
+            const float t1z = fmaf((float)((whz >> (8 * j)) & 0xFFu), Az, Bz);
+            const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z));
+            const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));
+            const float te = fmaxf(tn, cur_t);
+            bool v = c[j] != kNoChild && tn <= tf && tf >= tlo;
+            if (v && te > tmax_t) {
+              defer(c[j], te);
+              v = false;
+            }
+            t[j] = v ? te : INFINITY;
+          }
+          // near-to-far order of the children still in play (sorting network on (t, ref))
+          auto cswap = [&](int a, int b) __attribute__((always_inline)) {
+            const bool sw = t[b] < t[a];
+            const float ta = t[a], tb = t[b];
+            const uint32_t ca = c[a], cb = c[b];
+            t[a] = sw ? tb : ta;
+            t[b] = sw ? ta : tb;
+            c[a] = sw ? cb : ca;
+            c[b] = sw ? ca : cb;
+          };
+          cswap(0, 1);
+          cswap(2, 3);
+          cswap(0, 2);
+          cswap(1, 3);
+          cswap(1, 2);
+          if (t[3] < INFINITY) push(c[3], t[3]);
+          if (t[2] < INFINITY) push(c[2], t[2]);
+          if (t[1] < INFINITY) push(c[1], t[1]);
+          has_cur = t[0] < INFINITY;
+          cur_ref = c[0];
+          cur_t = t[0];
+        }
+      }
+      // lanes holding a leaf (also one just reached by the node step above) or a key
+      const bool leafy = state == kTrav && (have_key || (has_cur && (cur_ref & kLeafFlag)));
+      if (__ballot(leafy)) {
         // ------------------------------------------------ leaf step
         if (leafy && !have_key) {
           const uint32_t p = cur_ref & ~kLeafFlag;
@@ -545,61 +603,6 @@ __global__ void __launch_bounds__(kTraceBlock)
         }
         if (have_key && !ins) evict(key);
         have_key = false;
-      } else if (nodey) {
-        // ------------------------------------------------ node step: four children
-        // Slab distances straight from the 8-bit planes: t = q * (s * inv) + (o - ray) * inv.
-        // A child's entry is raised to at least the entry of the node in hand, so entries
-        // never decrease along a path whatever the rounding, and a node whose entry exceeds
-        // t_max holds no key at or below t_max (keys are clamped to their leaf's entry).
-        const float4* np = A.nodes + kNodeF4 * (int64_t)cur_ref;
-        const float4 q0 = np[0], q1 = np[1], q2 = np[2], q3 = np[3];
-        STAT(GRTX_STAT_NODES);
-        const float tlo = fmaxf(tnear, key_t(tmin));
-        const float Ax = q0.w * ix, Ay = q1.x * iy, Az = q1.y * iz;
-        const float Bx = (q0.x - ox) * ix, By = (q0.y - oy) * iy, Bz = (q0.z - oz) * iz;
-        const uint32_t wlx = __float_as_uint(q2.z), wly = __float_as_uint(q2.w), wlz = __float_as_uint(q3.x);
-        const uint32_t whx = __float_as_uint(q3.y), why = __float_as_uint(q3.z), whz = __float_as_uint(q3.w);
-        uint32_t c[4] = {__float_as_uint(q1.z), __float_as_uint(q1.w), __float_as_uint(q2.x), __float_as_uint(q2.y)};
-        float t[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const float t0x = fmaf((float)((wlx >> (8 * j)) & 0xFFu), Ax, Bx);
-          const float t1x = fmaf((float)((whx >> (8 * j)) & 0xFFu), Ax, Bx);
-          const float t0y = fmaf((float)((wly >> (8 * j)) & 0xFFu), Ay, By);
-          const float t1y = fmaf((float)((why >> (8 * j)) & 0xFFu), Ay, By);
-          const float t0z = fmaf((float)((wlz >> (8 * j)) & 0xFFu), Az, Bz);
-          const float t1z = fmaf((float)((whz >> (8 * j)) & 0xFFu), Az, Bz);
-          const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z));
-          const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));
-          const float te = fmaxf(tn, cur_t);
-          bool v = c[j] != kNoChild && tn <= tf && tf >= tlo;
-          if (v && te > tmax_t) {
-            defer(c[j], te);
-            v = false;
-          }
-          t[j] = v ? te : INFINITY;
-        }
-        // near-to-far order of the children still in play (sorting network on (t, ref))
-        auto cswap = [&](int a, int b) __attribute__((always_inline)) {
-          const bool sw = t[b] < t[a];
-          const float ta = t[a], tb = t[b];
-          const uint32_t ca = c[a], cb = c[b];
-          t[a] = sw ? tb : ta;
-          t[b] = sw ? ta : tb;
-          c[a] = sw ? cb : ca;
-          c[b] = sw ? ca : cb;
-        };
-        cswap(0, 1);
-        cswap(2, 3);
-        cswap(0, 2);
-        cswap(1, 3);
-        cswap(1, 2);
-        if (t[3] < INFINITY) push(c[3], t[3]);
-        if (t[2] < INFINITY) push(c[2], t[2]);
-        if (t[1] < INFINITY) push(c[1], t[1]);
-        has_cur = t[0] < INFINITY;
-        cur_ref = c[0];
-        cur_t = t[0];
       }
     }
 
