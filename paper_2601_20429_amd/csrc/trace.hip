@@ -294,15 +294,17 @@ __global__ void __launch_bounds__(kTraceBlock)
   const int lane = tid & 63;
   const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
   const int gwave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * kTraceBlock + tid) >> 6));
-  // The wave's rows: [0, kSpillRows) stack spill; two node lists of cap_d rows and two
-  // hit lists of cap_e rows (ping-pong source/destination, selected by `par`); K rows
-  // holding the k-buffer while it is blended. Entry j of lane l is at row j, column l;
-  // the wave's base address is uniform and lanes add a 32-bit offset.
+  // The wave's region: first each lane's own entries, lane l at [l * rowK, (l + 1) * rowK):
+  // [0, kSpillRows) stack spill, two node lists of cap_d entries and two hit lists of
+  // cap_e entries (ping-pong source/destination, selected by `par`); a lane's appends and
+  // reads walk its own lines. Then K rows holding the k-buffers while they are blended,
+  // entry j of lane l at row j, column l: all blending lanes write row j together.
   uint2* const wbase = A.pool + (int64_t)gwave * A.rows_per_wave * 64;
   const int rowN = kSpillRows;
   const int rowE = kSpillRows + 2 * A.cap_d;
   const int rowK = rowE + 2 * A.cap_e;
 #define ROW(r) wbase[(uint32_t)(r) * 64u + (uint32_t)lane]
+#define LROW(r) wbase[(uint32_t)lane * (uint32_t)rowK + (uint32_t)(r)]
 #define STAT(f)                        \
   do {                                 \
     if constexpr (STATS) ++s_stat[f][tid]; \
@@ -347,7 +349,7 @@ __global__ void __launch_bounds__(kTraceBlock)
   auto defer = [&](uint32_t ref, float t) __attribute__((always_inline)) {
     if (!ckpt) return;
     if (ndst_n < A.cap_d) {
-      ROW(rowN + (par ^ 1) * A.cap_d + ndst_n) = make_uint2(ref, __float_as_uint(t));
+      LROW(rowN + (par ^ 1) * A.cap_d + ndst_n) = make_uint2(ref, __float_as_uint(t));
       ++ndst_n;
       STAT(GRTX_STAT_DEFERRED);
     } else {
@@ -358,7 +360,7 @@ __global__ void __launch_bounds__(kTraceBlock)
   auto evict = [&](uint64_t k64) __attribute__((always_inline)) {
     if (!ckpt) return;
     if (edst_n < A.cap_e) {
-      ROW(rowE + (par ^ 1) * A.cap_e + edst_n) = make_uint2((uint32_t)k64, (uint32_t)(k64 >> 32));
+      LROW(rowE + (par ^ 1) * A.cap_e + edst_n) = make_uint2((uint32_t)k64, (uint32_t)(k64 >> 32));
       ++edst_n;
       STAT(GRTX_STAT_EVICTED);
     } else {
@@ -373,13 +375,13 @@ __global__ void __launch_bounds__(kTraceBlock)
     if (sp < kLdsStack)
       s_stack[sp * kTraceBlock + tid] = e;
     else if (sp < kMaxStack)
-      ROW(sp - kLdsStack) = e;
+      LROW(sp - kLdsStack) = e;
     sp = sp < kMaxStack ? sp + 1 : sp;
   };
 
   auto pop = [&]() __attribute__((always_inline)) -> uint2 {
     --sp;
-    return sp < kLdsStack ? s_stack[sp * kTraceBlock + tid] : ROW(sp - kLdsStack);
+    return sp < kLdsStack ? s_stack[sp * kTraceBlock + tid] : LROW(sp - kLdsStack);
   };
 
   while (true) {
@@ -470,7 +472,7 @@ __global__ void __launch_bounds__(kTraceBlock)
         // acquire: evicted hits of earlier rounds first, then the stack, then the source
         // checkpoint list; entries already beyond t_max are carried without a fetch
         if (esrc_i < esrc_n) {
-          uint2 v = ROW(rowE + par * A.cap_e + esrc_i);
+          uint2 v = LROW(rowE + par * A.cap_e + esrc_i);
           ++esrc_i;
           key = ((uint64_t)v.y << 32) | v.x;
           have_key = true;
@@ -480,7 +482,7 @@ __global__ void __launch_bounds__(kTraceBlock)
           if (sp > 0) {
             e = pop();
           } else if (nsrc_i < nsrc_n) {
-            e = ROW(rowN + par * A.cap_d + nsrc_i);
+            e = LROW(rowN + par * A.cap_d + nsrc_i);
             ++nsrc_i;
           } else {
             got = false;
@@ -722,6 +724,7 @@ __global__ void __launch_bounds__(kTraceBlock)
     }
   }
 #undef ROW
+#undef LROW
 #undef STAT
 }
 
