@@ -370,7 +370,7 @@ static void render_one(const job_t *J, int64_t r, hit_t **buf, size_t *bufcap) {
     h->id = i;
     max_response(g, o, d, &h->alpha, &h->talpha);
   }
-  qsort(*buf, nh, sizeof(hit_t), hit_cmp);
+  if (nh > 1) qsort(*buf, nh, sizeof(hit_t), hit_cmp); /* qsort's array may not be NULL */
   double T = 1.0, C[3] = {0, 0, 0}, D = 0.0;
   int nb = 0;
   for (size_t h = 0; h < nh; ++h) {
@@ -483,7 +483,7 @@ int64_t oracle_ray_hits(const double *means, const double *scales, const double 
     max_response(g + i, o, d, &buf[nh].alpha, &buf[nh].talpha);
     ++nh;
   }
-  qsort(buf, (size_t)nh, sizeof(hit_t), hit_cmp);
+  if (nh > 1) qsort(buf, (size_t)nh, sizeof(hit_t), hit_cmp);
   for (int64_t h = 0; h < nh && h < cap; ++h) {
     if (ids) ids[h] = buf[h].id;
     if (tkey) tkey[h] = buf[h].t;
