@@ -121,8 +121,10 @@ typedef struct grtx_rays {
  * its transmittance below T_min (early ray termination, Sec. III-A), in [0, 1).
  * mode: grtx_mode. bg: background colour added with the remaining transmittance.
  * defer_capacity / evict_capacity: per-ray entries of the checkpoint lists (0 = the
- * defaults, 256 deferred nodes and 128 evicted hits). A ray whose lists overflow falls
- * back to a restart-from-root round; results are unchanged. */
+ * defaults: 256 deferred nodes and 128 evicted hits, or 1024 and 256 for structures of
+ * more than a million leaves). A ray whose lists overflow falls back to a
+ * restart-from-root round; results are unchanged. The lists live in a per-stream pool
+ * of 512 B x (288 + 2 x defer + 2 x evict + k) per wave in flight. */
 typedef struct grtx_trace_params {
   int32_t k;
   float T_min;

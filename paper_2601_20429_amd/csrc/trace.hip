@@ -843,8 +843,8 @@ grtx_status launch_trace(const TraceScene& b, const grtx_rays* r, const grtx_tra
   int64_t need_blocks = (R + kTraceBlock - 1) / kTraceBlock;
   if (blocks > need_blocks) blocks = (int)std::max<int64_t>(1, need_blocks);
 
-  const int cap_d = p->defer_capacity > 0 ? p->defer_capacity : kDefaultDeferCap;
-  const int cap_e = p->evict_capacity > 0 ? p->evict_capacity : kDefaultEvictCap;
+  const int cap_d = p->defer_capacity > 0 ? p->defer_capacity : default_defer_cap(b.n_leaves);
+  const int cap_e = p->evict_capacity > 0 ? p->evict_capacity : default_evict_cap(b.n_leaves);
   const int64_t rows = kSpillRows + 2 * (int64_t)cap_d + 2 * (int64_t)cap_e + K;
   const size_t need = (size_t)blocks * kWaves * rows * 64 * sizeof(uint2) + 256;
 
