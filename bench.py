@@ -18,7 +18,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-# algorithmic bytes per unit of work ("Roofline")
+# algorithmic bytes per unit of work: what one node fetch, leaf test, blended hit, list
+# entry and ray must move at least
 B_NODE = 64          # node record: four quantized child boxes + four child references
 B_LEAF = 48          # unit-sphere transform of a leaf (3 x float4)
 B_BLEND_INST = 64    # full instance record re-read for blending
@@ -300,8 +301,8 @@ def main():
     ap.add_argument("--no-ksweep", action="store_true", help="skip the k-buffer size sweep")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the ray-sharded multi-GPU "
-              "layout is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); sharding the rays over "
+              "several GPUs is not built", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
