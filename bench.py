@@ -31,10 +31,11 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def run_serving(n_requests):
+def run_serving(n_requests, rates):
     """Serving workload: four device-resident scenes (100k, 500k, 1M, 3M Gaussians), Poisson
-    arrivals at 200 requests/s, each a random camera on the radius-3 sphere at a resolution
-    drawn from {256^2, 512^2, 800^2, 1920x1080}, k = 16; latency is submission to result."""
+    arrivals, each a random camera on the radius-3 sphere at a resolution drawn from
+    {256^2, 512^2, 800^2, 1920x1080}, k = 16; latency is submission to result. One server,
+    one run of `n_requests` per arrival rate (requests/s)."""
     import threading
 
     import numpy as np
@@ -52,14 +53,6 @@ def run_serving(n_requests):
     torch.cuda.synchronize()
     srv = grtx.Server(memory_budget=96 << 30, slots=2, k=cfg["k"], T_min=cfg["T_min"])
     ids = [srv.add_scene(b) for b in bvhs]
-    rng = np.random.default_rng(cfg["arrival_seed"])
-    gaps = rng.exponential(1.0 / cfg["rate"], n_requests)
-    plan = []
-    for j in range(n_requests):
-        w, h = cfg["resolutions"][int(rng.integers(len(cfg["resolutions"])))]
-        cam = inputs.Camera(inputs.random_orbit_eye(rng), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 60.0, w, h)
-        plan.append((float(gaps[:j + 1].sum()), ids[int(rng.integers(len(ids)))], cam))
-    tickets = []
     # warm the server's streams with one request per scene (pools, code objects)
     warm = [srv.submit(i, inputs.orbit_camera(64, 64)) for i in ids]
     while any(srv.poll(t) is None for t in warm):
@@ -67,45 +60,61 @@ def run_serving(n_requests):
     for t in warm:
         srv.release(t)
 
-    def submitter():
-        t0 = time.perf_counter()
-        for at, sid, cam in plan:
-            dt = at - (time.perf_counter() - t0)
-            if dt > 0:
-                time.sleep(dt)
-            tickets.append(srv.submit(sid, cam))
+    def measure(rate):
+        rng = np.random.default_rng(cfg["arrival_seed"])
+        gaps = rng.exponential(1.0 / rate, n_requests)
+        plan = []
+        for j in range(n_requests):
+            w, h = cfg["resolutions"][int(rng.integers(len(cfg["resolutions"])))]
+            cam = inputs.Camera(inputs.random_orbit_eye(rng), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 60.0, w, h)
+            plan.append((float(gaps[:j + 1].sum()), ids[int(rng.integers(len(ids)))], cam))
+        tickets = []
 
-    th = threading.Thread(target=submitter)
-    th.start()
-    done = 0
-    lat, wait, service, pixels = [], [], [], 0
-    t_first, t_last = None, None
-    while done < n_requests:
-        for j, t in enumerate(list(tickets)):
-            if t > 0:
-                r = srv.poll(t)
-                if r is not None:
-                    lat.append(r["t_done"] - r["t_submit"])
-                    wait.append(r["t_admit"] - r["t_submit"])
-                    service.append(r["t_done"] - r["t_admit"])
-                    pixels += r["width"] * r["height"]
-                    t_first = r["t_submit"] if t_first is None else min(t_first, r["t_submit"])
-                    t_last = r["t_done"] if t_last is None else max(t_last, r["t_done"])
-                    srv.release(t)
-                    tickets[j] = -1
-                    done += 1
-        time.sleep(0.0005)
-    th.join()
+        def submitter():
+            t0 = time.perf_counter()
+            for at, sid, cam in plan:
+                dt = at - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                tickets.append(srv.submit(sid, cam))
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        done = 0
+        lat, wait, service, pixels = [], [], [], 0
+        t_first, t_last = None, None
+        while done < n_requests:
+            for j, t in enumerate(list(tickets)):
+                if t > 0:
+                    r = srv.poll(t)
+                    if r is not None:
+                        lat.append(r["t_done"] - r["t_submit"])
+                        wait.append(r["t_admit"] - r["t_submit"])
+                        service.append(r["t_done"] - r["t_admit"])
+                        pixels += r["width"] * r["height"]
+                        t_first = r["t_submit"] if t_first is None else min(t_first, r["t_submit"])
+                        t_last = r["t_done"] if t_last is None else max(t_last, r["t_done"])
+                        srv.release(t)
+                        tickets[j] = -1
+                        done += 1
+            time.sleep(0.0005)
+        th.join()
+        lat, wait, service = (np.array(x) * 1e3 for x in (lat, wait, service))
+        offered = sum(c.width * c.height for _, _, c in plan) / plan[-1][0] / 1e6
+        return dict(workload=cfg["name"] if rate == cfg["rate"] else f"serve-4scenes-poisson{rate:g}",
+                    rate=rate, requests=n_requests, p50_ms=float(np.percentile(lat, 50)),
+                    p99_ms=float(np.percentile(lat, 99)), mean_ms=float(lat.mean()), max_ms=float(lat.max()),
+                    queue_wait_p50_ms=float(np.percentile(wait, 50)),
+                    service_p50_ms=float(np.percentile(service, 50)),
+                    service_p99_ms=float(np.percentile(service, 99)),
+                    mrays_s=pixels / (t_last - t_first) / 1e6, rays=pixels, offered_mrays_s=offered,
+                    scenes=list(cfg["scene_sizes"]),
+                    note="latency = submission to completion of each timed request; "
+                         "service = admission to completion")
+
+    out = [measure(r) for r in rates]
     srv.close()
-    lat, wait, service = (np.array(x) * 1e3 for x in (lat, wait, service))
-    offered = sum(c.width * c.height for _, _, c in plan) / plan[-1][0] / 1e6
-    return dict(workload=cfg["name"], requests=n_requests, p50_ms=float(np.percentile(lat, 50)),
-                p99_ms=float(np.percentile(lat, 99)), mean_ms=float(lat.mean()), max_ms=float(lat.max()),
-                queue_wait_p50_ms=float(np.percentile(wait, 50)), service_p50_ms=float(np.percentile(service, 50)),
-                service_p99_ms=float(np.percentile(service, 99)),
-                mrays_s=pixels / (t_last - t_first) / 1e6, rays=pixels, offered_mrays_s=offered,
-                scenes=list(cfg["scene_sizes"]),
-                note="latency = submission to completion of each timed request; service = admission to completion")
+    return out
 
 
 def time_launch(fn, stream, reps):
@@ -295,6 +304,8 @@ def main():
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="first copy this many GiB device-to-device (a reference kernel for HBM counters)")
     ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-low-rate", type=float, default=30.0,
+                    help="second serving run at this arrival rate (requests/s), below the server's capacity")
     ap.add_argument("--no-proxy", action="store_true", help="skip the 20-face proxy BVH comparison")
     ap.add_argument("--no-backward", action="store_true", help="skip the backward-pass timing")
     ap.add_argument("--no-scene3m", action="store_true", help="skip the 3M-Gaussian workload")
@@ -421,8 +432,10 @@ def main():
 
     serving = None
     if not args.no_serving:
-        serving = run_serving(args.serve_requests)
+        serving, below = run_serving(args.serve_requests, (inputs.SERVE["rate"], args.serve_low_rate))
         log("serving", json.dumps(serving))
+        log("serving below capacity", json.dumps(below))
+        extra["serving_below_capacity"] = below
 
     cpu = None
     if not args.no_cpu_baseline:
