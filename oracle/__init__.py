@@ -50,15 +50,17 @@ def lib():
             f, d, i32, i64, u32, u64 = C.c_float, C.c_double, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64
             PF, PD = C.POINTER(f), C.POINTER(d)
             L.oracle_render.restype = C.c_int
-            L.oracle_render.argtypes = [PD, PD, PD, PD, PD, i64, C.c_int, i64, PD, PD, d, d, d, PD, C.c_int,
-                                        PD, PD, PD, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), PD, PD,
-                                        C.c_int, C.c_int]
+            L.oracle_render.argtypes = [PD, PD, PD, PD, PD, i64, C.c_int, i64, PD, PD, PD, PD, d, d, d, PD,
+                                        C.c_int, PD, PD, PD, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), PD,
+                                        PD, C.c_int, C.c_int]
             L.oracle_ray_hits.restype = i64
-            L.oracle_ray_hits.argtypes = [PD, PD, PD, PD, i64, PD, PD, d, d, C.c_int, C.POINTER(i64), PD, PD,
+            L.oracle_ray_hits.argtypes = [PD, PD, PD, PD, i64, PD, PD, d, d, d, C.c_int, C.POINTER(i64), PD, PD,
                                           PD, i64]
             L.oracle_composite_list.restype = C.c_int
             L.oracle_composite_list.argtypes = [PD, PD, PD, PD, PD, i64, C.c_int, PD, PD, C.POINTER(i32), i64,
-                                                d, PD, PD, PD, PD]
+                                                d, d, PD, PD, PD, PD]
+            L.oracle_object_rays.restype = C.c_int
+            L.oracle_object_rays.argtypes = [PD, PD, d, i64, PD, PD, d, PD, PD, PD, PD, C.POINTER(i32)]
             L.oracle_gaussian_aabb.restype = C.c_int
             L.oracle_gaussian_aabb.argtypes = [PD, PD, PD, PD, i64, d, PD, PD, C.POINTER(i32)]
             L.oracle_pinhole_rays.restype = C.c_int
@@ -91,13 +93,15 @@ def _scene_args(scene):
 
 
 def render(scene, origins, dirs, alpha_min=1.0 / 255.0, T_min=1e-3, t_near=0.0, bg=(0.0, 0.0, 0.0),
-           key_mode=0, cap=0, nthreads=None):
+           key_mode=0, cap=0, nthreads=None, t_far=None, trans0=None):
     """Brute-force FP64 render of the given rays (Eq. 1, Eq. 2, Sec. III-A). Scene and rays
     are taken as given (float32 values are widened exactly; FP64 values are used as is).
 
     key_mode 0 orders hits by ellipsoid entry distance, 1 by bounding-icosahedron entry
     distance. With cap > 0 also returns, per ray, the first `cap` blended ids, the
-    transmittance after each and each hit's key distance."""
+    transmittance after each and each hit's key distance. t_far [R] bounds the rays (hits
+    need key < t_far; bounded rays get no background); trans0 [R] is the transmittance
+    each ray starts with (both optional)."""
     L = lib()
     if nthreads is None:
         nthreads = min(16, os.cpu_count() or 1)
@@ -114,9 +118,11 @@ def render(scene, origins, dirs, alpha_min=1.0 / 255.0, T_min=1e-3, t_near=0.0, 
     tafter = np.zeros((R, max(cap, 1)), np.float64) if cap > 0 else None
     tkey = np.zeros((R, max(cap, 1)), np.float64) if cap > 0 else None
     bga = np.asarray(bg, np.float64)
+    tf = None if t_far is None else _f64(t_far).reshape(R)
+    t0 = None if trans0 is None else _f64(trans0).reshape(R)
     rc = L.oracle_render(_p(m, C.c_double), _p(s, C.c_double), _p(q, C.c_double), _p(op, C.c_double),
                          _p(sh, C.c_double), scene.n, scene.sh_degree, R, _p(o, C.c_double), _p(d, C.c_double),
-                         alpha_min, T_min, t_near, _p(bga, C.c_double), key_mode,
+                         _p(tf, C.c_double), _p(t0, C.c_double), alpha_min, T_min, t_near, _p(bga, C.c_double), key_mode,
                          _p(rgb, C.c_double), _p(depth, C.c_double), _p(opac, C.c_double),
                          _p(nblend, C.c_int32), _p(nhits, C.c_int32), _p(ids, C.c_int32),
                          _p(tafter, C.c_double), _p(tkey, C.c_double), cap, nthreads)
@@ -128,8 +134,9 @@ def render(scene, origins, dirs, alpha_min=1.0 / 255.0, T_min=1e-3, t_near=0.0, 
     return out
 
 
-def ray_hits(scene, origin, direction, alpha_min=1.0 / 255.0, t_near=0.0, key_mode=0):
-    """All hits of one ray sorted by (key distance, id): ids, key, alpha, t_alpha."""
+def ray_hits(scene, origin, direction, alpha_min=1.0 / 255.0, t_near=0.0, key_mode=0, t_far=np.inf):
+    """All hits of one ray with key in (t_near, t_far), sorted by (key distance, id): ids,
+    key, alpha, t_alpha."""
     L = lib()
     m, s, q, op, _ = _scene_args(scene)
     o = _f64(origin).reshape(3)
@@ -140,15 +147,16 @@ def ray_hits(scene, origin, direction, alpha_min=1.0 / 255.0, t_near=0.0, key_mo
     al = np.zeros(max(cap, 1), np.float64)
     ta = np.zeros(max(cap, 1), np.float64)
     nh = L.oracle_ray_hits(_p(m, C.c_double), _p(s, C.c_double), _p(q, C.c_double), _p(op, C.c_double), scene.n,
-                           _p(o, C.c_double), _p(d, C.c_double), alpha_min, t_near, key_mode,
+                           _p(o, C.c_double), _p(d, C.c_double), alpha_min, t_near, float(t_far), key_mode,
                            _p(ids, C.c_int64), _p(tk, C.c_double), _p(al, C.c_double), _p(ta, C.c_double), cap)
     if nh < 0:
         raise RuntimeError("oracle_ray_hits failed")
     return dict(ids=ids[:nh], t=tk[:nh], alpha=al[:nh], talpha=ta[:nh])
 
 
-def composite_list(scene, origin, direction, ids, alpha_min=1.0 / 255.0, bg=(0.0, 0.0, 0.0)):
-    """Composite an explicit ordered id list along one ray (Eq. 1 with Eq. 2 alphas)."""
+def composite_list(scene, origin, direction, ids, alpha_min=1.0 / 255.0, bg=(0.0, 0.0, 0.0), trans0=1.0):
+    """Composite an explicit ordered id list along one ray (Eq. 1 with Eq. 2 alphas),
+    starting from transmittance trans0."""
     L = lib()
     m, s, q, op, sh = _scene_args(scene)
     o = _f64(origin).reshape(3)
@@ -160,11 +168,74 @@ def composite_list(scene, origin, direction, ids, alpha_min=1.0 / 255.0, bg=(0.0
     bga = np.asarray(bg, np.float64)
     rc = L.oracle_composite_list(_p(m, C.c_double), _p(s, C.c_double), _p(q, C.c_double), _p(op, C.c_double),
                                  _p(sh, C.c_double), scene.n, scene.sh_degree, _p(o, C.c_double), _p(d, C.c_double),
-                                 _p(lst, C.c_int32), lst.size, alpha_min, _p(bga, C.c_double),
+                                 _p(lst, C.c_int32), lst.size, alpha_min, float(trans0), _p(bga, C.c_double),
                                  _p(rgb, C.c_double), _p(dep, C.c_double), _p(opa, C.c_double))
     if rc != 0:
         raise RuntimeError("oracle_composite_list failed")
     return dict(rgb=rgb, depth=float(dep[0]), opacity=float(opa[0]))
+
+
+def object_rays(objects, origins, dirs, t_near=0.0):
+    """Where each ray meets the glass sphere or the mirror of `objects` (a dict with
+    optional "sphere" = (cx, cy, cz, r, ior), "mirror" = (m, u, v) as 9 numbers, "eps")
+    and the continuation ray there (Sec. II-A; the secondary-ray experiment of Sec. VI).
+    Returns t_far, next_o, next_d, path and kind (0 none, 1 mirror, 2 glass, 3 glass
+    without a way out)."""
+    L = lib()
+    o = _f64(origins).reshape(-1, 3)
+    d = _f64(dirs).reshape(-1, 3)
+    R = o.shape[0]
+    sph = objects.get("sphere")
+    mir = objects.get("mirror")
+    sph = None if sph is None else _f64(sph).reshape(5)
+    mir = None if mir is None else _f64(mir).reshape(9)
+    out = dict(t_far=np.zeros(R), next_o=np.zeros((R, 3)), next_d=np.zeros((R, 3)), path=np.zeros(R),
+               kind=np.zeros(R, np.int32))
+    rc = L.oracle_object_rays(_p(sph, C.c_double), _p(mir, C.c_double), float(objects.get("eps", 1e-4)), R,
+                              _p(o, C.c_double), _p(d, C.c_double), t_near, _p(out["t_far"], C.c_double),
+                              _p(out["next_o"], C.c_double), _p(out["next_d"], C.c_double),
+                              _p(out["path"], C.c_double), _p(out["kind"], C.c_int32))
+    if rc != 0:
+        raise RuntimeError("oracle_object_rays failed")
+    return out
+
+
+def render_with_objects(scene, origins, dirs, objects, bounces=1, alpha_min=1.0 / 255.0, T_min=1e-3, t_near=0.0,
+                        bg=(0.0, 0.0, 0.0), key_mode=0, trans0=None, nthreads=None, levels=None):
+    """Render rays through a scene with a glass sphere and a mirror, following up to
+    `bounces` object interactions per ray. Each ray segment is an ordinary render bounded
+    by t_far; a segment that reaches its surface with T >= T_min continues as the
+    continuation ray, starting from that transmittance, and its result is added:
+      rgb   = rgb_1 + rgb_2
+      depth = depth_1 + depth_2 + path * (T_1 - T_2)   (distances along the bent path)
+      opacity = opacity_2                              (1 - the final transmittance)
+    With `levels` (a list) each level's rays and outputs are appended to it."""
+    o = _f64(origins).reshape(-1, 3)
+    d = _f64(dirs).reshape(-1, 3)
+    R = o.shape[0]
+    if bounces > 0:
+        ob = object_rays(objects, o, d, t_near)
+        t_far = ob["t_far"]
+    else:
+        ob = None
+        t_far = None
+    out = render(scene, o, d, alpha_min, T_min, t_near, bg, key_mode, nthreads=nthreads, t_far=t_far,
+                 trans0=trans0)
+    if levels is not None:
+        levels.append(dict(origins=o, dirs=d, objects=ob, out={k: v.copy() for k, v in out.items()}, trans0=trans0))
+    if ob is None:
+        return out
+    T1 = 1.0 - out["opacity"]
+    cont = np.flatnonzero(((ob["kind"] == 1) | (ob["kind"] == 2)) & (T1 >= T_min))
+    if cont.size == 0:
+        return out
+    sub = render_with_objects(scene, ob["next_o"][cont], ob["next_d"][cont], objects, bounces - 1, alpha_min, T_min,
+                              0.0, bg, key_mode, trans0=T1[cont], nthreads=nthreads, levels=levels)
+    T2 = 1.0 - sub["opacity"]
+    out["rgb"][cont] += sub["rgb"]
+    out["depth"][cont] += sub["depth"] + ob["path"][cont] * (T1[cont] - T2)
+    out["opacity"][cont] = sub["opacity"]
+    return out
 
 
 def gaussian_aabb(scene, alpha_min=1.0 / 255.0):

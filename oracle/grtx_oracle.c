@@ -26,6 +26,9 @@
  *   - Front-to-back compositing (Eq. 1) with early ray termination (Sec. III-A): the
  *     hit that drops transmittance below T_min is still blended, then the ray stops.
  *   - Output: colour C + T*bg, depth sum(w_i t_alpha_i), opacity 1 - T.
+ *   - A ray may be bounded by a surface at distance t_far (hits need key < t_far; the
+ *     surface hides the background) and may start with a transmittance below one, the
+ *     part of the light left after what an earlier ray segment blended.
  *
  * Proxy-key mode orders the same hits by the distance at which the ray enters the
  * Gaussian's bounding icosahedron (20 triangles, inradius 1 in the space where the
@@ -344,6 +347,7 @@ typedef struct {
   double *rgb, *depth, *opac;
   int32_t *nblend, *nhits;
   int32_t *ids; double *tafter; double *tkey; int cap;
+  const double *tfar, *trans0; /* per ray, may be NULL: unbounded, T starts at 1 */
 } job_t;
 
 static void render_one(const job_t *J, int64_t r, hit_t **buf, size_t *bufcap) {
@@ -351,6 +355,7 @@ static void render_one(const job_t *J, int64_t r, hit_t **buf, size_t *bufcap) {
   const params_t *p = J->p;
   double o[3] = {J->ro[3 * r], J->ro[3 * r + 1], J->ro[3 * r + 2]};
   double d[3] = {J->rd[3 * r], J->rd[3 * r + 1], J->rd[3 * r + 2]};
+  const double tfar = J->tfar ? J->tfar[r] : INFINITY;
   size_t nh = 0;
   for (int64_t i = 0; i < s->n; ++i) {
     const og_t *g = J->g + i;
@@ -361,6 +366,7 @@ static void render_one(const job_t *J, int64_t r, hit_t **buf, size_t *bufcap) {
       if (!proxy_entry(g, o, d, p->t_near, &key)) continue;
       if (!line_meets_ellipsoid(g, o, d)) continue;
     }
+    if (!(key < tfar)) continue; /* beyond the surface that ends the ray */
     if (nh == *bufcap) {
       *bufcap = *bufcap ? 2 * *bufcap : 256;
       *buf = (hit_t *)realloc(*buf, *bufcap * sizeof(hit_t));
@@ -371,7 +377,7 @@ static void render_one(const job_t *J, int64_t r, hit_t **buf, size_t *bufcap) {
     max_response(g, o, d, &h->alpha, &h->talpha);
   }
   if (nh > 1) qsort(*buf, nh, sizeof(hit_t), hit_cmp); /* qsort's array may not be NULL */
-  double T = 1.0, C[3] = {0, 0, 0}, D = 0.0;
+  double T = J->trans0 ? J->trans0[r] : 1.0, C[3] = {0, 0, 0}, D = 0.0;
   int nb = 0;
   for (size_t h = 0; h < nh; ++h) {
     const hit_t *x = *buf + h;
@@ -389,7 +395,9 @@ static void render_one(const job_t *J, int64_t r, hit_t **buf, size_t *bufcap) {
     ++nb;
     if (T < p->T_min) break;
   }
-  for (int ch = 0; ch < 3; ++ch) J->rgb[3 * r + ch] = C[ch] + T * p->bg[ch];
+  /* the background shows only through rays that no surface ends */
+  const double bgw = isinf(tfar) ? T : 0.0;
+  for (int ch = 0; ch < 3; ++ch) J->rgb[3 * r + ch] = C[ch] + bgw * p->bg[ch];
   J->depth[r] = D;
   J->opac[r] = 1.0 - T;
   if (J->nblend) J->nblend[r] = nb;
@@ -427,12 +435,15 @@ static void free_all(og_t *g, int64_t n) {
 
 /* Render R rays against all Gaussians in FP64 (inputs are FP64; the tests pass float32
  * values widened exactly, or FP64 values for finite differences).
- * Outputs per ray: rgb[3], depth, opacity; optionally the number of blended hits, the
- * number of hits, and for the first `cap` blended hits their ids, the transmittance
- * after each and the sort-key distance. */
+ * t_far [R] (may be NULL = unbounded): hits need key < t_far and a bounded ray gets no
+ * background. trans0 [R] (may be NULL = 1): transmittance the ray starts with.
+ * Outputs per ray: rgb[3], depth, opacity (1 - T); optionally the number of blended
+ * hits, the number of hits, and for the first `cap` blended hits their ids, the
+ * transmittance after each and the sort-key distance. */
 int oracle_render(const double *means, const double *scales, const double *quats, const double *opac,
                   const double *sh, int64_t n, int sh_degree,
                   int64_t nrays, const double *ray_o, const double *ray_d,
+                  const double *t_far, const double *trans0,
                   double alpha_min, double T_min, double t_near, const double *bg, int key_mode,
                   double *rgb, double *depth, double *opacity, int32_t *nblend, int32_t *nhits,
                   int32_t *ids, double *tafter, double *tkey, int cap, int nthreads) {
@@ -448,7 +459,8 @@ int oracle_render(const double *means, const double *scales, const double *quats
   job_t *jobs = (job_t *)malloc(sizeof(job_t) * nt);
   for (int t = 0; t < nt; ++t) {
     job_t J = {&s, g, &p, ray_o, ray_d, nrays * t / nt, nrays * (t + 1) / nt,
-               rgb, depth, opacity, nblend, nhits, ids, tafter, tkey, ids || tafter || tkey ? cap : 0};
+               rgb, depth, opacity, nblend, nhits, ids, tafter, tkey, ids || tafter || tkey ? cap : 0,
+               t_far, trans0};
     jobs[t] = J;
     pthread_create(&th[t], NULL, render_worker, &jobs[t]);
   }
@@ -459,11 +471,13 @@ int oracle_render(const double *means, const double *scales, const double *quats
   return OR_OK;
 }
 
-/* All hits of one ray, sorted by (key, id): ids, key distance, alpha, t_alpha. Returns
- * the number of hits (entries beyond `cap` are not written). */
+/* All hits of one ray with key in (t_near, t_far), sorted by (key, id): ids, key
+ * distance, alpha, t_alpha. Returns the number of hits (entries beyond `cap` are not
+ * written). */
 int64_t oracle_ray_hits(const double *means, const double *scales, const double *quats, const double *opac,
                         int64_t n, const double *ray_o, const double *ray_d, double alpha_min, double t_near,
-                        int key_mode, int64_t *ids, double *tkey, double *alpha, double *talpha, int64_t cap) {
+                        double t_far, int key_mode, int64_t *ids, double *tkey, double *alpha, double *talpha,
+                        int64_t cap) {
   scene_t s = {means, scales, quats, opac, NULL, n, 0};
   og_t *g = prepare_all(&s, alpha_min, key_mode == 1);
   if (!g) return -1;
@@ -478,6 +492,7 @@ int64_t oracle_ray_hits(const double *means, const double *scales, const double 
       if (!proxy_entry(g + i, o, d, t_near, &key)) continue;
       if (!line_meets_ellipsoid(g + i, o, d)) continue;
     }
+    if (!(key < t_far)) continue;
     buf[nh].t = key;
     buf[nh].id = i;
     max_response(g + i, o, d, &buf[nh].alpha, &buf[nh].talpha);
@@ -496,14 +511,14 @@ int64_t oracle_ray_hits(const double *means, const double *scales, const double 
 }
 
 /* Composite a given ordered id list along one ray (Eq. 1 with Eq. 2 alphas), without
- * any hit test and without early termination. */
+ * any hit test and without early termination, starting from transmittance trans0. */
 int oracle_composite_list(const double *means, const double *scales, const double *quats, const double *opac,
                           const double *sh, int64_t n, int sh_degree, const double *ray_o, const double *ray_d,
-                          const int32_t *list, int64_t len, double alpha_min, const double *bg,
+                          const int32_t *list, int64_t len, double alpha_min, double trans0, const double *bg,
                           double *rgb, double *depth, double *opacity) {
   scene_t s = {means, scales, quats, opac, sh, n, sh_degree};
   double o[3] = {ray_o[0], ray_o[1], ray_o[2]}, d[3] = {ray_d[0], ray_d[1], ray_d[2]};
-  double T = 1.0, C[3] = {0, 0, 0}, D = 0.0;
+  double T = trans0, C[3] = {0, 0, 0}, D = 0.0;
   for (int64_t h = 0; h < len; ++h) {
     int64_t i = list[h];
     if (i < 0 || i >= n) return OR_ERR_ARG;
@@ -578,6 +593,153 @@ int oracle_pinhole_rays(const double *eye, const double *target, const double *u
         dirs[3 * i + a] = d[a] / dl;
       }
     }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Secondary rays: a refracting glass sphere and a reflecting rectangular mirror         */
+/* ------------------------------------------------------------------------------------ */
+/*
+ * A ray tracer follows light past a surface by casting a new ray from the intersection
+ * point (Sec. II-A); the paper's secondary-ray experiment adds a glass sphere and a
+ * rectangular mirror to each scene and traces the rays they spawn (Sec. VI). Reading:
+ *   - a ray ends at its first object surface beyond t_near + eps: it blends the
+ *     Gaussians whose key is below that distance t_far, and what lies beyond comes from
+ *     the continuation ray, which starts with the transmittance the first segment left;
+ *   - mirror: the parallelogram m + x u + y v, |x| <= 1, |y| <= 1 (u, v orthogonal),
+ *     two-sided, perfect reflection d - 2 (d.n) n;
+ *   - glass sphere (centre c, radius r, relative index ior): solid, so no Gaussian
+ *     inside it is seen; the ray refracts in by Snell's law, crosses along a chord and
+ *     refracts out; total internal reflection sends it along another chord, and after
+ *     OR_MAX_INSIDE chords the ray ends without a continuation;
+ *   - all light follows the one continuation ray (no Fresnel split, no absorption);
+ *   - eps keeps a continuation ray from meeting the surface it starts on again.
+ * kind per ray: 0 no object, 1 mirror, 2 glass, 3 glass without a way out.
+ */
+#define OR_MAX_INSIDE 8
+
+static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* Both roots of |o + t d - c|^2 = r^2 (t0 <= t1); 0 when the line misses the sphere. */
+static int sphere_roots(const double c[3], double r, const double o[3], const double d[3], double *t0,
+                        double *t1) {
+  double f[3] = {o[0] - c[0], o[1] - c[1], o[2] - c[2]};
+  double a = dot3(d, d), b = dot3(f, d), cc = dot3(f, f) - r * r;
+  double disc = b * b - a * cc;
+  if (!(disc >= 0.0)) return 0;
+  double sq = sqrt(disc);
+  *t0 = (-b - sq) / a;
+  *t1 = (-b + sq) / a;
+  return 1;
+}
+
+/* Snell's law, n1 sin(theta1) = n2 sin(theta2), with the refracted ray in the plane of
+ * incidence: unit d meets a surface whose unit normal n faces the ray (d.n < 0); eta =
+ * n1/n2. Returns 0 on total internal reflection. */
+static int refract_dir(const double d[3], const double n[3], double eta, double out[3]) {
+  double ci = -dot3(d, n);
+  double k = 1.0 - eta * eta * (1.0 - ci * ci);
+  if (k < 0.0) return 0;
+  double s = eta * ci - sqrt(k);
+  for (int a = 0; a < 3; ++a) out[a] = eta * d[a] + s * n[a];
+  return 1;
+}
+
+static void reflect_dir(const double d[3], const double n[3], double out[3]) {
+  double dn = dot3(d, n);
+  for (int a = 0; a < 3; ++a) out[a] = d[a] - 2.0 * dn * n[a];
+}
+
+/* Distance to the mirror parallelogram beyond tmin, and its unit normal. */
+static int mirror_hit(const double *mir, const double o[3], const double d[3], double tmin, double *t,
+                      double n[3]) {
+  const double *m = mir, *u = mir + 3, *v = mir + 6;
+  double c[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
+  double cl = sqrt(dot3(c, c));
+  if (!(cl > 0.0)) return 0;
+  for (int a = 0; a < 3; ++a) n[a] = c[a] / cl;
+  double dn = dot3(d, n);
+  if (dn == 0.0) return 0;
+  double mo[3] = {m[0] - o[0], m[1] - o[1], m[2] - o[2]};
+  double th = dot3(mo, n) / dn;
+  if (!(th > tmin)) return 0;
+  double q[3] = {o[0] + th * d[0] - m[0], o[1] + th * d[1] - m[1], o[2] + th * d[2] - m[2]};
+  double x = dot3(q, u) / dot3(u, u), y = dot3(q, v) / dot3(v, v);
+  if (!(fabs(x) <= 1.0 && fabs(y) <= 1.0)) return 0;
+  *t = th;
+  return 1;
+}
+
+/* Per ray: t_far (distance to the first object surface beyond t_near + eps, or +inf),
+ * the continuation ray (origin, unit direction; zero when there is none), the length of
+ * the bent path from the ray origin to the continuation origin, and the kind.
+ * sphere = (cx, cy, cz, r, ior) or NULL; mirror = (m, u, v) or NULL. */
+int oracle_object_rays(const double *sphere, const double *mirror, double eps, int64_t nrays, const double *ray_o,
+                       const double *ray_d, double t_near, double *t_far, double *next_o, double *next_d,
+                       double *path, int32_t *kind) {
+  if (nrays < 0 || !t_far || !next_o || !next_d || !path || !kind) return OR_ERR_ARG;
+  const int has_sphere = sphere && sphere[3] > 0.0;
+  for (int64_t r = 0; r < nrays; ++r) {
+    const double o[3] = {ray_o[3 * r], ray_o[3 * r + 1], ray_o[3 * r + 2]};
+    const double d[3] = {ray_d[3 * r], ray_d[3 * r + 1], ray_d[3 * r + 2]};
+    const double tmin = t_near + eps;
+    double ts = INFINITY, tm = INFINITY, t0, t1, nm[3];
+    if (has_sphere && sphere_roots(sphere, sphere[3], o, d, &t0, &t1)) ts = t0 > tmin ? t0 : t1 > tmin ? t1 : INFINITY;
+    if (mirror && !mirror_hit(mirror, o, d, tmin, &tm, nm)) tm = INFINITY;
+    double *no = next_o + 3 * r, *nd = next_d + 3 * r;
+    for (int a = 0; a < 3; ++a) no[a] = nd[a] = 0.0;
+    path[r] = 0.0;
+    kind[r] = 0;
+    t_far[r] = INFINITY;
+    if (isinf(ts) && isinf(tm)) continue;
+    if (tm < ts) {
+      for (int a = 0; a < 3; ++a) no[a] = o[a] + tm * d[a];
+      reflect_dir(d, nm, nd);
+      t_far[r] = path[r] = tm;
+      kind[r] = 1;
+      continue;
+    }
+    const double *c = sphere;
+    const double rad = sphere[3], ior = sphere[4];
+    double p[3], dir[3] = {d[0], d[1], d[2]}, len = ts, n[3];
+    for (int a = 0; a < 3; ++a) p[a] = o[a] + ts * d[a];
+    for (int a = 0; a < 3; ++a) n[a] = (p[a] - c[a]) / rad;
+    t_far[r] = ts;
+    kind[r] = 3;
+    if (dot3(dir, n) < 0.0) {
+      /* entering from outside: refract in (or reflect away when ior < 1 forbids entry) */
+      double in[3];
+      if (!refract_dir(dir, n, 1.0 / ior, in)) {
+        for (int a = 0; a < 3; ++a) no[a] = p[a];
+        reflect_dir(dir, n, nd);
+        path[r] = len;
+        kind[r] = 2;
+        continue;
+      }
+      for (int a = 0; a < 3; ++a) dir[a] = in[a];
+      if (!sphere_roots(c, rad, p, dir, &t0, &t1)) t1 = 0.0;
+      len += t1;
+      for (int a = 0; a < 3; ++a) p[a] += t1 * dir[a];
+    }
+    /* at the surface from inside: refract out, or reflect along another chord */
+    for (int seg = 0; seg < OR_MAX_INSIDE; ++seg) {
+      double nout[3], nin[3], out[3];
+      for (int a = 0; a < 3; ++a) nout[a] = (p[a] - c[a]) / rad;
+      for (int a = 0; a < 3; ++a) nin[a] = -nout[a];
+      if (refract_dir(dir, nin, ior, out)) {
+        for (int a = 0; a < 3; ++a) no[a] = p[a];
+        for (int a = 0; a < 3; ++a) nd[a] = out[a];
+        kind[r] = 2;
+        break;
+      }
+      reflect_dir(dir, nout, out);
+      for (int a = 0; a < 3; ++a) dir[a] = out[a];
+      if (!sphere_roots(c, rad, p, dir, &t0, &t1)) t1 = 0.0;
+      len += t1;
+      for (int a = 0; a < 3; ++a) p[a] += t1 * dir[a];
+    }
+    path[r] = len;
+  }
   return OR_OK;
 }
 

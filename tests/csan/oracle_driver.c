@@ -7,17 +7,21 @@
 
 int oracle_render(const double *means, const double *scales, const double *quats, const double *opac,
                   const double *sh, int64_t n, int sh_degree, int64_t nrays, const double *ray_o,
-                  const double *ray_d, double alpha_min, double T_min, double t_near, const double *bg,
-                  int key_mode, double *rgb, double *depth, double *opacity, int32_t *nblend, int32_t *nhits,
-                  int32_t *ids, double *tafter, double *tkey, int cap, int nthreads);
+                  const double *ray_d, const double *t_far, const double *trans0, double alpha_min, double T_min,
+                  double t_near, const double *bg, int key_mode, double *rgb, double *depth, double *opacity,
+                  int32_t *nblend, int32_t *nhits, int32_t *ids, double *tafter, double *tkey, int cap, int nthreads);
 int64_t oracle_ray_hits(const double *means, const double *scales, const double *quats, const double *opac,
                         int64_t n, const double *ray_o, const double *ray_d, double alpha_min, double t_near,
-                        int key_mode, int64_t *ids, double *tkey, double *alpha, double *talpha, int64_t cap);
+                        double t_far, int key_mode, int64_t *ids, double *tkey, double *alpha, double *talpha,
+                        int64_t cap);
 int oracle_pinhole_rays(const double *eye, const double *target, const double *up, double fov_y_deg, int width,
                         int height, double *origins, double *dirs);
 int oracle_lbvh_topology(int64_t n, const float *means, uint64_t *sorted_codes, uint32_t *perm, uint32_t *child,
                          uint32_t *parent);
 int oracle_icosahedron(double *verts, int32_t *faces);
+int oracle_object_rays(const double *sphere, const double *mirror, double eps, int64_t nrays, const double *ray_o,
+                       const double *ray_d, double t_near, double *t_far, double *next_o, double *next_d,
+                       double *path, int32_t *kind);
 
 static uint64_t state = 0x9E3779B97F4A7C15ull;
 static double urand(void) { /* xorshift64*, a plain test-input generator */
@@ -49,12 +53,26 @@ int main(void) {
   int32_t *nb = malloc(sizeof(int32_t) * R), *nh = malloc(sizeof(int32_t) * R), *ids = malloc(sizeof(int32_t) * R * CAP);
   double *ta = malloc(sizeof(double) * R * CAP), *tk = malloc(sizeof(double) * R * CAP);
   for (int key_mode = 0; key_mode <= 1; ++key_mode)
-    if (oracle_render(means, scales, quats, opac, sh, N, L, R, o, d, 1.0 / 255.0, 1e-3, 0.0, NULL, key_mode, rgb,
-                      dep, op, nb, nh, ids, ta, tk, CAP, 4))
+    if (oracle_render(means, scales, quats, opac, sh, N, L, R, o, d, NULL, NULL, 1.0 / 255.0, 1e-3, 0.0, NULL,
+                      key_mode, rgb, dep, op, nb, nh, ids, ta, tk, CAP, 4))
       return 2;
   int64_t hid[CAP];
   double hk[CAP], ha[CAP], ht[CAP];
-  if (oracle_ray_hits(means, scales, quats, opac, N, o, d, 1.0 / 255.0, 0.0, 0, hid, hk, ha, ht, CAP) < 0) return 3;
+  if (oracle_ray_hits(means, scales, quats, opac, N, o, d, 1.0 / 255.0, 0.0, 1e30, 0, hid, hk, ha, ht, CAP) < 0)
+    return 3;
+  /* objects, then the bounded render of the primary rays and of the continuation rays */
+  double sphere[5] = {0.2, 0.0, 0.1, 0.5, 1.5};
+  double mirror[9] = {-0.5, 0.3, -0.2, 0.6, 0.0, 0.2, 0.0, 0.5, 0.0};
+  double *tf = malloc(sizeof(double) * R), *no = malloc(sizeof(double) * 3 * R), *nd = malloc(sizeof(double) * 3 * R);
+  double *pl = malloc(sizeof(double) * R), *t0 = malloc(sizeof(double) * R);
+  int32_t *kd = malloc(sizeof(int32_t) * R);
+  if (oracle_object_rays(sphere, mirror, 1e-4, R, o, d, 0.0, tf, no, nd, pl, kd)) return 6;
+  for (int r = 0; r < R; ++r) t0[r] = 0.5 + 0.5 * urand();
+  if (oracle_render(means, scales, quats, opac, sh, N, L, R, o, d, tf, t0, 1.0 / 255.0, 1e-3, 0.0, NULL, 0, rgb,
+                    dep, op, nb, nh, ids, ta, tk, CAP, 4))
+    return 7;
+  if (oracle_object_rays(sphere, mirror, 1e-4, R, no, nd, 0.0, tf, o, d, pl, kd)) return 8;
+  free(tf); free(no); free(nd); free(pl); free(t0); free(kd);
   uint64_t *codes = malloc(sizeof(uint64_t) * N);
   uint32_t *perm = malloc(sizeof(uint32_t) * N), *child = malloc(sizeof(uint32_t) * 2 * (N - 1));
   uint32_t *parent = malloc(sizeof(uint32_t) * (2 * N - 1));
