@@ -175,6 +175,68 @@ def run_proxy(st, cam, cfg, k, stream):
     return res
 
 
+def run_secondary(bvh, cam, k, stream):
+    """Secondary rays: the 100k scene with a glass sphere and a mirror. The primary rays
+    end at the objects (t_far); the reflected and refracted rays continue from there with
+    the transmittance left. Each ray type is traced in checkpoint and restart mode (the
+    checkpoint speedup per ray type), and the whole chain (object rays, bounded trace,
+    gathering, continuation trace, composite) is timed end to end."""
+    import torch
+
+    from paper_2601_20429_amd import grtx, inputs
+    cfg = inputs.SECONDARY
+    T_min = cfg["T_min"]
+    objs = inputs.secondary_objects(cfg["objects_seed"])
+    o, d = grtx.pinhole_rays(cam)
+    ob = grtx.object_rays(objs, o, d)
+    res = dict(workload=cfg["name"], primary_rays=cam.n_rays)
+    res["object_rays_ms"] = time_launch(lambda: grtx.object_rays(objs, o, d), stream, 5)
+
+    def trace_both(label, oo, dd, **kw):
+        out = None
+        for m, name in [(grtx.CHECKPOINT, "checkpoint"), (grtx.RESTART, "restart")]:
+            out = grtx.trace(bvh, oo, dd, k=k, T_min=T_min, mode=m, **kw)
+            ms = time_launch(lambda: grtx.trace(bvh, oo, dd, k=k, T_min=T_min, mode=m, out=out, **kw), stream, 5)
+            stt = grtx.trace(bvh, oo, dd, k=k, T_min=T_min, mode=m, stats=True, **kw)["stats"]
+            stt = stt.to(torch.int64).sum(0).cpu().numpy()
+            n = int(oo.shape[0])
+            res[f"{label}_{name}_ms"] = ms
+            res[f"{label}_{name}_mrays_s"] = n / (ms * 1e-3) / 1e6
+            res[f"{label}_{name}_nodes_per_ray"] = float(stt[0] + stt[1]) / n
+        res[f"{label}_checkpoint_speedup"] = res[f"{label}_restart_ms"] / res[f"{label}_checkpoint_ms"]
+        return out
+
+    prim = trace_both("primary", o, d, image_width=cam.width, t_far=ob["t_far"])
+    cont = grtx.continue_rays(ob["kind"], prim["opacity"], ob["next_o"], ob["next_d"], T_min)
+    res["secondary_rays"] = int(cont["index"].shape[0])
+    res["gather_ms"] = time_launch(lambda: grtx.continue_rays(ob["kind"], prim["opacity"], ob["next_o"],
+                                                              ob["next_d"], T_min), stream, 5)
+    sec = trace_both("secondary", cont["origins"], cont["dirs"], transmittance=cont["transmittance"])
+    base = {key: v.clone() for key, v in prim.items()}
+
+    def composite():
+        for key in base:
+            prim[key].copy_(base[key])
+        grtx.continue_composite(cont, ob["path"], sec, prim)
+
+    res["composite_ms_with_reset"] = time_launch(composite, stream, 5)
+    for m, name in [(grtx.CHECKPOINT, "checkpoint"), (grtx.RESTART, "restart")]:
+        ms = time_launch(lambda: grtx.trace_with_objects(bvh, o, d, objs, k=k, T_min=T_min, mode=m,
+                                                         image_width=cam.width), stream, 3)
+        res[f"chain_{name}_ms"] = ms
+        res[f"chain_{name}_mrays_s"] = (cam.n_rays + res["secondary_rays"]) / (ms * 1e-3) / 1e6
+    for m, name in [(grtx.CHECKPOINT, "checkpoint"), (grtx.RESTART, "restart")]:
+        fo = grtx.trace_with_objects(bvh, o, d, objs, k=k, T_min=T_min, mode=m, image_width=cam.width, fused=True)
+        ms = time_launch(lambda: grtx.trace(bvh, o, d, k=k, T_min=T_min, mode=m, image_width=cam.width,
+                                            t_far=ob["t_far"], continuation=ob, out=fo), stream, 5)
+        res[f"fused_{name}_trace_ms"] = ms
+        res[f"fused_{name}_mrays_s"] = (cam.n_rays + res["secondary_rays"]) / (ms * 1e-3) / 1e6
+    res["note"] = ("chain_ms includes the host wait for the number of continuation rays; fused_trace_ms is the one "
+                   "trace launch that continues the rays itself (object rays excluded, "
+                   f"{res['object_rays_ms']:.3f} ms)")
+    return res
+
+
 def run_ksweep(bvh, o, d, cam, cfg, stream, ks=(4, 8, 16, 32, 64)):
     """k-buffer size sweep on the same frame, checkpoint and restart: trace time and
     per-ray fetches and rounds (the cost of re-traversal against the cost of larger
@@ -310,6 +372,7 @@ def main():
     ap.add_argument("--no-backward", action="store_true", help="skip the backward-pass timing")
     ap.add_argument("--no-scene3m", action="store_true", help="skip the 3M-Gaussian workload")
     ap.add_argument("--no-ksweep", action="store_true", help="skip the k-buffer size sweep")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the secondary-ray workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); sharding the rays over "
@@ -416,6 +479,9 @@ def main():
     if not args.no_proxy:
         extra.update(run_proxy(st, cam, cfg, args.k, stream))
         log("proxy", json.dumps({k: v for k, v in extra.items() if k.startswith(("proxy", "ico"))}))
+    if not args.no_secondary:
+        extra["secondary"] = run_secondary(bvh, cam, args.k, stream)
+        log("secondary", json.dumps(extra["secondary"]))
     backward = None
     if not args.no_backward:
         backward = run_backward(stream)

@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define GRTX_VERSION 1
+#define GRTX_VERSION 2
 
 typedef enum grtx_status {
   GRTX_OK = 0,
@@ -108,13 +108,32 @@ typedef struct grtx_bvh_info {
 /* Rays: device origins [count,3] and unit-length directions [count,3], float32.
  * t_near >= 0: hits need an entry distance > t_near. image_width > 0 declares the rays
  * to be a row-major image of that width; the kernel then schedules them in 8x8 pixel
- * tiles (results are unaffected). */
+ * tiles (results are unaffected).
+ * Optional, for ray paths traced in segments (secondary rays, below):
+ *   t_far [count] float32 (NULL = unbounded): the ray ends on a surface at that distance;
+ *     hits need a key distance < t_far, and a bounded ray (t_far < +inf) gets no
+ *     background, which the surface hides.
+ *   transmittance [count] float32 (NULL = 1): the transmittance the ray starts with, the
+ *     light an earlier segment of its path left; blending weights scale with it, and
+ *     early termination compares the running transmittance with T_min.
+ *   next_origins, next_dirs [count,3], path [count], kind [count] (all four or none; the
+ *     outputs of grtx_object_rays; needs t_far and t_near = 0): a ray whose kind is MIRROR
+ *     or GLASS and which reaches its t_far with transmittance >= T_min goes on, in the same
+ *     launch, along its continuation ray (unbounded). The outputs are then those of the
+ *     whole path, as grtx_continue_rays, a trace and grtx_continue_composite give them
+ *     (equal up to rounding order), and hit_ids lists both segments' hits in order. */
 typedef struct grtx_rays {
   const float* origins;
   const float* dirs;
   int64_t count;
   float t_near;
   int32_t image_width;
+  const float* t_far;
+  const float* transmittance;
+  const float* next_origins;
+  const float* next_dirs;
+  const float* path;
+  const int32_t* kind;
 } grtx_rays;
 
 /* k: k-buffer size, 1..64 (Sec. III-A). T_min: a ray stops after the hit that brings
@@ -217,6 +236,79 @@ grtx_status grtx_pinhole_rays(const grtx_camera* cam, float* origins, float* dir
 grtx_status grtx_trace(const grtx_bvh* bvh, const grtx_rays* rays, const grtx_trace_params* p,
                        const grtx_trace_outputs* out, void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Secondary rays: ray continuation at a surface (Sec. II-A), with the two objects of the
+ * paper's secondary-ray experiment, a glass sphere and a rectangular mirror placed in
+ * the scene (Sec. VI). A path is traced in segments. grtx_object_rays finds where each
+ * ray meets an object and the ray that continues from there; grtx_trace renders the
+ * segment up to that surface (rays.t_far); grtx_continue_rays gathers the continuation
+ * rays of the segments that reached their surface; grtx_trace renders those, starting
+ * from the transmittance left (rays.transmittance); grtx_continue_composite adds their
+ * results to the segments they continue. Repeating the steps follows further bounces.
+ * ------------------------------------------------------------------------------------- */
+
+/* Glass sphere: centre, radius (<= 0: none), index of refraction relative to the
+ * surroundings (> 0). Mirror: the parallelogram centre + x u + y v, |x| <= 1, |y| <= 1,
+ * u and v orthogonal half-axes (u x v = 0: none). Object hits need a distance
+ * > t_near + surface_eps (0 = 1e-4), so that a continuation ray does not meet the
+ * surface it starts on. */
+typedef struct grtx_objects {
+  float sphere_center[3];
+  float sphere_radius;
+  float sphere_ior;
+  float mirror_center[3];
+  float mirror_u[3];
+  float mirror_v[3];
+  float surface_eps;
+} grtx_objects;
+
+/* What a ray met (grtx_object_rays kind). */
+typedef enum grtx_object_kind {
+  GRTX_OBJECT_NONE = 0,
+  GRTX_OBJECT_MIRROR = 1,
+  GRTX_OBJECT_GLASS = 2,
+  GRTX_OBJECT_GLASS_TRAPPED = 3 /* still inside after 8 chords of total internal reflection */
+} grtx_object_kind;
+
+/* For each ray of `rays` (origins, dirs, count, t_near; t_far and transmittance are not
+ * read): t_far [count], the distance to the first object surface (+inf if none); the
+ * continuation ray next_origins / next_dirs [count,3] (unit direction; zeros where there
+ * is none); path [count], the length of the bent path from the ray origin to the
+ * continuation origin; kind [count] (grtx_object_kind). Mirror: two-sided, perfect
+ * reflection d - 2 (d.n) n. Glass: solid (no Gaussian inside it is seen); Snell
+ * refraction in, along the chord, refraction out; total internal reflection follows
+ * further chords, at most 8. All light follows the one continuation ray (no Fresnel
+ * split, no absorption). Outputs are caller-owned device arrays. Enqueued on `stream`.
+ * ERR_INVALID_ARG for a non-positive index, or mirror half-axes that are not orthogonal
+ * (|u.v| > 1e-4 |u||v|). */
+grtx_status grtx_object_rays(const grtx_objects* obj, const grtx_rays* rays, float* t_far, float* next_origins,
+                             float* next_dirs, float* path, int32_t* kind, void* stream);
+
+/* Gather continuation rays: ray i continues if kind[i] is MIRROR or GLASS and its
+ * segment reached the surface, i.e. it left transmittance T = 1 - opacity[i] >= T_min
+ * (early termination did not stop it). For the continuing rays in increasing i, writes
+ * cont_origins / cont_dirs [n,3] (copies of next_origins / next_dirs), cont_transmittance
+ * [n] = T and cont_index [n] = i into caller-owned device buffers of `count` entries, and
+ * n into *n_cont (host memory). Enqueued on `stream`; the call waits once on `stream` to
+ * read n. Scratch of 8 B per ray is allocated and freed in stream order. */
+grtx_status grtx_continue_rays(int64_t count, const int32_t* kind, const float* opacity, float T_min,
+                               const float* next_origins, const float* next_dirs, float* cont_origins,
+                               float* cont_dirs, float* cont_transmittance, int32_t* cont_index, int64_t* n_cont,
+                               void* stream);
+
+/* Add the results of n continuation rays (cont_rgb [n,3], cont_depth [n], cont_opacity
+ * [n], the outputs of grtx_trace over the gathered rays with their transmittance) to the
+ * segments they continue, in place, for i = cont_index[j]:
+ *   rgb[i]     += cont_rgb[j]
+ *   depth[i]   += cont_depth[j] + path[i] * (cont_transmittance[j] - (1 - cont_opacity[j]))
+ *   opacity[i]  = cont_opacity[j]
+ * so depth sums distances along the bent path and opacity is one minus the path's final
+ * transmittance. cont_index entries must be distinct. Enqueued on `stream`. */
+grtx_status grtx_continue_composite(int64_t n, const int32_t* cont_index, const float* cont_transmittance,
+                                    const float* path, const float* cont_rgb, const float* cont_depth,
+                                    const float* cont_opacity, float* rgb, float* depth, float* opacity,
+                                    void* stream);
+
 /* Gradients of the Gaussian parameters, caller-owned DEVICE arrays shaped like the inputs
  * of grtx_gaussians (means [N,3], scales [N,3], quats [N,4], opacities [N],
  * sh [N,(L+1)^2,3]). grtx_trace_backward ADDS into them (it never zeroes). */
@@ -241,7 +333,8 @@ typedef struct grtx_gaussian_grads {
  * `truncated_rays` (uint32, may be NULL). Enqueued on `stream`; the call waits once on
  * the stream for the number of hit records (scratch of 76 B per record is taken from
  * the stream's pool and released in stream order). ERR_INVALID_ARG when rays x
- * hit_capacity reaches 2^32. */
+ * hit_capacity reaches 2^32, or for rays with t_far or transmittance (the backward pass
+ * covers unbounded rays that start with transmittance 1 and have no continuation). */
 grtx_status grtx_trace_backward(const grtx_bvh* bvh, const grtx_gaussians* g, const grtx_rays* rays,
                                 const grtx_trace_params* p, const grtx_trace_outputs* fwd, const float* grad_rgb,
                                 const float* grad_depth, const float* grad_opacity, const grtx_gaussian_grads* grads,

@@ -138,6 +138,12 @@ grtx_status grtx_trace(const grtx_bvh* bvh, const grtx_rays* rays, const grtx_tr
             "grtx_trace: list capacities must be 0..2^20");
   CHECK_ARG(rays->t_near >= 0.f && std::isfinite(rays->t_near), "grtx_trace: t_near must be finite and >= 0");
   CHECK_ARG(rays->image_width >= 0, "grtx_trace: negative image width");
+  {
+    const int nc = !!rays->next_origins + !!rays->next_dirs + !!rays->path + !!rays->kind;
+    CHECK_ARG(nc == 0 || nc == 4, "grtx_trace: give all four continuation arrays or none");
+    CHECK_ARG(nc == 0 || (rays->t_far && rays->t_near == 0.f),
+              "grtx_trace: continuation rays need t_far and t_near = 0");
+  }
   if (rays->count > 0) {
     CHECK_ARG(rays->origins && rays->dirs, "grtx_trace: null ray arrays");
     CHECK_ARG(out->rgb && out->depth && out->opacity, "grtx_trace: null output arrays");
@@ -161,6 +167,9 @@ grtx_status grtx_trace_backward(const grtx_bvh* bvh, const grtx_gaussians* g, co
     CHECK_ARG(fwd->rgb && fwd->depth && fwd->opacity && fwd->hit_ids && fwd->hit_counts && fwd->hit_capacity > 0,
               "grtx_trace_backward: the forward outputs need rgb, depth, opacity and a hit-id list");
     CHECK_ARG(grad_rgb || grad_depth || grad_opacity, "grtx_trace_backward: no output gradient given");
+    CHECK_ARG(!rays->t_far && !rays->transmittance && !rays->kind,
+              "grtx_trace_backward: rays with t_far, a starting transmittance or continuation rays are not "
+              "supported");
     CHECK_ARG(grads->means && grads->scales && grads->quats && grads->opacities && grads->sh,
               "grtx_trace_backward: null gradient array");
   }
@@ -178,6 +187,65 @@ grtx_status grtx_trace_backward(const grtx_bvh* bvh, const grtx_gaussians* g, co
   }
   return grtx::trace_backward(g, rays, p, fwd, grad_rgb, grad_depth, grad_opacity, grads, tr,
                               static_cast<hipStream_t>(stream));
+}
+
+grtx_status grtx_object_rays(const grtx_objects* obj, const grtx_rays* rays, float* t_far, float* next_origins,
+                             float* next_dirs, float* path, int32_t* kind, void* stream) {
+  grtx::clear_error();
+  CHECK_ARG(obj && rays, "grtx_object_rays: null argument");
+  CHECK_ARG(rays->count >= 0 && rays->count < ((int64_t)1 << 40), "grtx_object_rays: bad ray count");
+  CHECK_ARG(rays->t_near >= 0.f && std::isfinite(rays->t_near), "grtx_object_rays: t_near must be finite and >= 0");
+  CHECK_ARG(obj->surface_eps >= 0.f && std::isfinite(obj->surface_eps), "grtx_object_rays: bad surface_eps");
+  bool finite = std::isfinite(obj->sphere_radius) && std::isfinite(obj->sphere_ior);
+  for (int a = 0; a < 3; ++a)
+    finite = finite && std::isfinite(obj->sphere_center[a]) && std::isfinite(obj->mirror_center[a]) &&
+             std::isfinite(obj->mirror_u[a]) && std::isfinite(obj->mirror_v[a]);
+  CHECK_ARG(finite, "grtx_object_rays: non-finite object parameter");
+  CHECK_ARG(obj->sphere_radius <= 0.f || obj->sphere_ior > 0.f, "grtx_object_rays: sphere_ior must be positive");
+  {
+    double uu = 0, vv = 0, uv = 0;
+    for (int a = 0; a < 3; ++a) {
+      uu += (double)obj->mirror_u[a] * obj->mirror_u[a];
+      vv += (double)obj->mirror_v[a] * obj->mirror_v[a];
+      uv += (double)obj->mirror_u[a] * obj->mirror_v[a];
+    }
+    CHECK_ARG(std::fabs(uv) <= 1e-4 * std::sqrt(uu * vv), "grtx_object_rays: mirror half-axes must be orthogonal");
+  }
+  if (rays->count > 0) {
+    CHECK_ARG(rays->origins && rays->dirs, "grtx_object_rays: null ray arrays");
+    CHECK_ARG(t_far && next_origins && next_dirs && path && kind, "grtx_object_rays: null output array");
+  }
+  return grtx::object_rays(obj, rays, t_far, next_origins, next_dirs, path, kind, static_cast<hipStream_t>(stream));
+}
+
+grtx_status grtx_continue_rays(int64_t count, const int32_t* kind, const float* opacity, float T_min,
+                               const float* next_origins, const float* next_dirs, float* cont_origins,
+                               float* cont_dirs, float* cont_transmittance, int32_t* cont_index, int64_t* n_cont,
+                               void* stream) {
+  grtx::clear_error();
+  CHECK_ARG(n_cont, "grtx_continue_rays: null n_cont");
+  CHECK_ARG(count >= 0 && count < ((int64_t)1 << 31), "grtx_continue_rays: count must be 0..2^31-1");
+  CHECK_ARG(T_min >= 0.f && T_min < 1.f, "grtx_continue_rays: T_min must be in [0,1)");
+  if (count > 0)
+    CHECK_ARG(kind && opacity && next_origins && next_dirs && cont_origins && cont_dirs && cont_transmittance &&
+                  cont_index,
+              "grtx_continue_rays: null array");
+  return grtx::continue_rays(count, kind, opacity, T_min, next_origins, next_dirs, cont_origins, cont_dirs,
+                             cont_transmittance, cont_index, n_cont, static_cast<hipStream_t>(stream));
+}
+
+grtx_status grtx_continue_composite(int64_t n, const int32_t* cont_index, const float* cont_transmittance,
+                                    const float* path, const float* cont_rgb, const float* cont_depth,
+                                    const float* cont_opacity, float* rgb, float* depth, float* opacity,
+                                    void* stream) {
+  grtx::clear_error();
+  CHECK_ARG(n >= 0 && n < ((int64_t)1 << 31), "grtx_continue_composite: n must be 0..2^31-1");
+  if (n > 0)
+    CHECK_ARG(cont_index && cont_transmittance && path && cont_rgb && cont_depth && cont_opacity && rgb && depth &&
+                  opacity,
+              "grtx_continue_composite: null array");
+  return grtx::continue_composite(n, cont_index, cont_transmittance, path, cont_rgb, cont_depth, cont_opacity, rgb,
+                                  depth, opacity, static_cast<hipStream_t>(stream));
 }
 
 grtx_status grtx_serve_request_bytes(const grtx_request* r, int64_t* bytes) {

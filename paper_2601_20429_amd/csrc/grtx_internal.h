@@ -161,6 +161,16 @@ grtx_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, hip
 // Stable LSD radix sort of (keys, vals) by the low key_bits bits of the keys, in place.
 grtx_status sort_by_key(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, hipStream_t s);
 
+// Secondary rays (objects.hip).
+grtx_status object_rays(const grtx_objects* obj, const grtx_rays* r, float* t_far, float* next_o, float* next_d,
+                        float* path, int32_t* kind, hipStream_t s);
+grtx_status continue_rays(int64_t count, const int32_t* kind, const float* opacity, float T_min,
+                          const float* next_o, const float* next_d, float* co, float* cd, float* ct, int32_t* ci,
+                          int64_t* n_cont, hipStream_t s);
+grtx_status continue_composite(int64_t n, const int32_t* idx, const float* trans, const float* path,
+                               const float* crgb, const float* cdepth, const float* copac, float* rgb, float* depth,
+                               float* opac, hipStream_t s);
+
 grtx_status trace_backward(const grtx_gaussians* g, const grtx_rays* r, const grtx_trace_params* p,
                            const grtx_trace_outputs* fwd, const float* grad_rgb, const float* grad_depth,
                            const float* grad_opacity, const grtx_gaussian_grads* grads, unsigned int* truncated,

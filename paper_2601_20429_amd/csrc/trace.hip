@@ -75,6 +75,12 @@ struct TraceArgs {
   int sh_degree;
   const float* ray_o;
   const float* ray_d;
+  const float* ray_tfar;      // per ray surface distance, or null (unbounded)
+  const float* ray_trans;     // per ray starting transmittance, or null (1)
+  const float* ray_next_o;    // continuation rays (all four, or all null)
+  const float* ray_next_d;
+  const float* ray_path;
+  const int32_t* ray_kind;
   int64_t n_rays;
   int64_t n_work;
   int image_w;
@@ -98,6 +104,7 @@ struct TraceArgs {
   int cap_e;
   unsigned int* counter;  // kChunks work counters
   int64_t chunk_len;      // work items per chunk (a multiple of 64)
+  const uint32_t* tile_order;  // processing order of the 8x8 tiles, or null (row-major)
 };
 
 __device__ __forceinline__ float key_t(uint64_t k) { return __uint_as_float((uint32_t)(k >> 32)); }
@@ -316,6 +323,7 @@ __global__ void __launch_bounds__(kTraceBlock)
   int ray = -1;
   int sid = 0;  // scene of the lane's ray
   float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, ix = 0, iy = 0, iz = 0;
+  float tfar = INFINITY;  // the ray ends on a surface there: keys must stay below it
   uint64_t kb[K];
   kbuf_reset(kb, A.k);
   uint64_t tmin = 0;  // key of the last blended hit
@@ -340,7 +348,8 @@ __global__ void __launch_bounds__(kTraceBlock)
     const float* rb = A.roots + 8 * sid;
     Slab s = slab(rb[0], rb[1], rb[2], rb[3], rb[4], rb[5], ox, oy, oz, ix, iy, iz);
     float tlo = fmaxf(tnear, key_t(tmin));
-    has_cur = s.tn <= s.tf && s.tf >= tlo;
+    const float tf = fminf(s.tf, tfar);
+    has_cur = s.tn <= tf && tf >= tlo;
     cur_ref = __float_as_uint(rb[6]);
     cur_t = s.tn;
     sp = 0;
@@ -413,7 +422,7 @@ __global__ void __launch_bounds__(kTraceBlock)
           int r = -1;
           if (rank < avail && w < A.n_work) {
             if (A.image_w > 0) {
-              int64_t tile = w >> 6;
+              int64_t tile = A.tile_order ? (int64_t)A.tile_order[w >> 6] : w >> 6;
               int within = (int)(w & 63);
               int64_t ty = tile / A.tiles_x, tx = tile - ty * A.tiles_x;
               int64_t px = tx * 8 + (within & 7), py = ty * 8 + (within >> 3);
@@ -430,10 +439,11 @@ __global__ void __launch_bounds__(kTraceBlock)
             ox = ro[0]; oy = ro[1]; oz = ro[2];
             dx = rd[0]; dy = rd[1]; dz = rd[2];
             ix = safe_inv(dx); iy = safe_inv(dy); iz = safe_inv(dz);
+            tfar = A.ray_tfar ? A.ray_tfar[r] : INFINITY;
             kbuf_reset(kb, A.k);
             tmin = 0;
             C0 = C1 = C2 = Dp = 0.f;
-            T = 1.f;
+            T = A.ray_trans ? A.ray_trans[r] : 1.f;
             nblend = 0;
             par = 0;
             nsrc_n = nsrc_i = ndst_n = 0;
@@ -528,7 +538,7 @@ __global__ void __launch_bounds__(kTraceBlock)
             const float t0z = fmaf((float)((wlz >> (8 * j)) & 0xFFu), Az, Bz);
             const float t1z = fmaf((float)((whz >> (8 * j)) & 0xFFu), Az, Bz);
             const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z));
-            const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));
+            const float tf = fminf(fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)), tfar);
             const float te = fmaxf(tn, cur_t);
             bool v = c[j] != kNoChild && tn <= tf && tf >= tlo;
             if (v && te > tmax_t) {
@@ -576,13 +586,13 @@ __global__ void __launch_bounds__(kTraceBlock)
             float tt;
             const bool hit = proxy_hit(a4, b4, c4, ox, oy, oz, dx, dy, dz, &tt);
             key = make_key(fmaxf(tt, cur_t), __float_as_uint(a4.w));
-            have_key = hit && tt > tnear && key > tmin;
+            have_key = hit && tt > tnear && tt < tfar && key > tmin;
           } else if constexpr (LEAF == kLeafIco) {
             const float4* ip = A.inst + 4 * (int64_t)p;
             float tt;
             const bool hit = ico_entry(ip[0], ip[1], ip[2], ox, oy, oz, dx, dy, dz, &tt);
             key = make_key(fmaxf(tt, cur_t), p);
-            have_key = hit && tt > tnear && key > tmin;
+            have_key = hit && tt > tnear && tt < tfar && key > tmin;
           } else {
             const float4* ip = A.inst + 4 * (int64_t)p;
             float4 r0 = ip[0], r1 = ip[1], r2 = ip[2];
@@ -590,7 +600,7 @@ __global__ void __launch_bounds__(kTraceBlock)
             if (h.a > 0.f && h.c2 <= h.a) {
               const float t0 = (-h.b - __builtin_amdgcn_sqrtf(fmaxf(h.a - h.c2, 0.f))) * __builtin_amdgcn_rcpf(h.a);
               key = make_key(fmaxf(t0, cur_t), p);
-              have_key = t0 > tnear && key > tmin;
+              have_key = t0 > tnear && t0 < tfar && key > tmin;
             }
           }
         }
@@ -683,10 +693,39 @@ __global__ void __launch_bounds__(kTraceBlock)
       }
       const bool full = last != kEmptyKey;
       const bool done = ert || !full || (ckpt && !overflow && ndst_n == 0 && edst_n == 0);
-      if (done) {
-        A.rgb[3 * (int64_t)ray + 0] = C0 + T * A.bg0;
-        A.rgb[3 * (int64_t)ray + 1] = C1 + T * A.bg1;
-        A.rgb[3 * (int64_t)ray + 2] = C2 + T * A.bg2;
+      // A segment that reached its surface with T >= T_min goes on along its reflected or
+      // refracted ray in the same lane: colour, transmittance and the hit list carry over,
+      // and the continuation's distances start at the bent path length.
+      bool cont = false;
+      if (done && A.ray_kind && tfar != INFINITY && T >= A.T_min) {
+        const int kd = A.ray_kind[ray];
+        cont = kd == GRTX_OBJECT_MIRROR || kd == GRTX_OBJECT_GLASS;
+      }
+      if (cont) {
+        const float* no = A.ray_next_o + 3 * (int64_t)ray;
+        const float* nd = A.ray_next_d + 3 * (int64_t)ray;
+        ox = no[0]; oy = no[1]; oz = no[2];
+        dx = nd[0]; dy = nd[1]; dz = nd[2];
+        ix = safe_inv(dx); iy = safe_inv(dy); iz = safe_inv(dz);
+        Dp = fmaf(A.ray_path[ray], T, Dp);
+        tfar = INFINITY;
+        kbuf_reset(kb, A.k);
+        tmin = 0;
+        par = 0;
+        nsrc_n = nsrc_i = ndst_n = 0;
+        esrc_n = esrc_i = edst_n = 0;
+        overflow = false;
+        root_start();
+        state = kTrav;
+      } else if (done) {
+        // the background shows only through rays that no surface ends
+        const float bgT = tfar == INFINITY ? T : 0.f;
+        A.rgb[3 * (int64_t)ray + 0] = C0 + bgT * A.bg0;
+        A.rgb[3 * (int64_t)ray + 1] = C1 + bgT * A.bg1;
+        A.rgb[3 * (int64_t)ray + 2] = C2 + bgT * A.bg2;
+        // a continued ray (its bound was lifted): the continuation's weights sum to
+        // T_switch - T, so take path * T back off
+        if (A.ray_kind && tfar == INFINITY && A.ray_tfar[ray] != INFINITY) Dp = fmaf(-A.ray_path[ray], T, Dp);
         A.depth[ray] = Dp;
         A.opac[ray] = 1.f - T;
         if (A.hit_counts) A.hit_counts[ray] = nblend;
@@ -732,16 +771,48 @@ __global__ void k_reset_counter(unsigned int* c) {
   if (threadIdx.x < kChunks) c[threadIdx.x] = 0u;
 }
 
+// Tile order for rays that continue past an object: the tiles holding such rays go first.
+// Those rays run longest (two segments); started last, they would set the end of the
+// launch, while rows of tiles in image order keep neighbouring rays together.
+__global__ void __launch_bounds__(256) k_tile_heavy(const int32_t* __restrict__ kind, int w, int h, int tiles_x,
+                                                    int64_t n_tiles, uint32_t* __restrict__ flag) {
+  const int64_t t = blockIdx.x * (int64_t)256 + threadIdx.x;
+  if (t >= n_tiles) return;
+  const int64_t ty = t / tiles_x, tx = t - ty * tiles_x;
+  uint32_t f = 0;
+  for (int j = 0; j < 64; ++j) {
+    const int64_t px = tx * 8 + (j & 7), py = ty * 8 + (j >> 3);
+    if (px < w && py < h) {
+      const int k = kind[py * w + px];
+      f |= (k == GRTX_OBJECT_MIRROR || k == GRTX_OBJECT_GLASS) ? 1u : 0u;
+    }
+  }
+  flag[t] = f;
+}
+
+__global__ void __launch_bounds__(256) k_tile_order(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ pos,
+                                                    int64_t n_tiles, uint32_t* __restrict__ order) {
+  const int64_t t = blockIdx.x * (int64_t)256 + threadIdx.x;
+  if (t >= n_tiles) return;
+  const int64_t heavy = (int64_t)pos[n_tiles - 1] + flag[n_tiles - 1];
+  const int64_t dst = flag[t] ? (int64_t)pos[t] : heavy + (t - (int64_t)pos[t]);
+  order[dst] = (uint32_t)t;
+}
+
+// Outputs of rays that meet nothing (a structure without leaves).
 __global__ void __launch_bounds__(256) k_fill_background(float* rgb, float* depth, float* opac, uint32_t* stats,
-                                                         int32_t* hit_counts, int64_t n, float b0, float b1,
+                                                         int32_t* hit_counts, const float* tfar,
+                                                         const float* trans, int64_t n, float b0, float b1,
                                                          float b2) {
   int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
   if (i >= n) return;
-  rgb[3 * i] = b0;
-  rgb[3 * i + 1] = b1;
-  rgb[3 * i + 2] = b2;
+  const float T = trans ? trans[i] : 1.f;
+  const float bgT = !tfar || tfar[i] == INFINITY ? T : 0.f;
+  rgb[3 * i] = bgT * b0;
+  rgb[3 * i + 1] = bgT * b1;
+  rgb[3 * i + 2] = bgT * b2;
   depth[i] = 0.f;
-  opac[i] = 0.f;
+  opac[i] = 1.f - T;
   if (hit_counts) hit_counts[i] = 0;
   if (stats)
     for (int f = 0; f < GRTX_STATS_FIELDS; ++f) stats[i * GRTX_STATS_FIELDS + f] = 0u;
@@ -820,7 +891,8 @@ grtx_status launch_trace(const TraceScene& b, const grtx_rays* r, const grtx_tra
   if (R == 0) return GRTX_OK;
   if (b.n_leaves == 0) {
     hipLaunchKernelGGL(k_fill_background, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, o->rgb, o->depth,
-                       o->opacity, o->stats, o->hit_counts, R, p->bg[0], p->bg[1], p->bg[2]);
+                       o->opacity, o->stats, o->hit_counts, r->t_far, r->transmittance, R, p->bg[0], p->bg[1],
+                       p->bg[2]);
     GRTX_LAUNCH_CHECK();
     return GRTX_OK;
   }
@@ -873,6 +945,12 @@ grtx_status launch_trace(const TraceScene& b, const grtx_rays* r, const grtx_tra
   a.sh_degree = b.sh_degree;
   a.ray_o = r->origins;
   a.ray_d = r->dirs;
+  a.ray_tfar = r->t_far;
+  a.ray_trans = r->transmittance;
+  a.ray_next_o = r->next_origins;
+  a.ray_next_d = r->next_dirs;
+  a.ray_path = r->path;
+  a.ray_kind = r->kind;
   a.n_rays = R;
   a.t_near = r->t_near;
   if (r->image_width > 0 && R % r->image_width == 0) {
@@ -906,9 +984,29 @@ grtx_status launch_trace(const TraceScene& b, const grtx_rays* r, const grtx_tra
   a.cap_d = cap_d;
   a.cap_e = cap_e;
   a.chunk_len = ((a.n_work + 64 * kChunks - 1) / (64 * kChunks)) * 64;
+  uint32_t* order_buf = nullptr;
+  if (r->kind && a.image_w > 0) {
+    const int64_t nt = a.n_work / 64;
+    GRTX_HIP(hipMallocAsync(reinterpret_cast<void**>(&order_buf), 3 * (size_t)nt * sizeof(uint32_t), s));
+    uint32_t* flag = order_buf;
+    uint32_t* pos = flag + nt;
+    uint32_t* order = pos + nt;
+    const unsigned g = (unsigned)((nt + 255) / 256);
+    hipLaunchKernelGGL(k_tile_heavy, dim3(g), dim3(256), 0, s, r->kind, a.image_w, a.image_h, a.tiles_x, nt, flag);
+    grtx_status st = exclusive_scan_u32(flag, pos, nt, s);
+    if (st != GRTX_OK) {
+      (void)hipFreeAsync(order_buf, s);
+      return st;
+    }
+    hipLaunchKernelGGL(k_tile_order, dim3(g), dim3(256), 0, s, flag, pos, nt, order);
+    a.tile_order = order;
+  }
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, pool->counter);
-  return leaf == kLeafTri ? launch_k<kLeafTri>(K, a, blocks, s)
-       : leaf == kLeafIco ? launch_k<kLeafIco>(K, a, blocks, s) : launch_k<kLeafSphere>(K, a, blocks, s);
+  const grtx_status st = leaf == kLeafTri ? launch_k<kLeafTri>(K, a, blocks, s)
+                       : leaf == kLeafIco ? launch_k<kLeafIco>(K, a, blocks, s)
+                                          : launch_k<kLeafSphere>(K, a, blocks, s);
+  if (order_buf) GRTX_HIP(hipFreeAsync(order_buf, s));
+  return st;
 }
 
 }  // namespace grtx

@@ -32,6 +32,7 @@ RESTART = 1
 STAT_NODES, STAT_LEAVES, STAT_ROUNDS, STAT_BLENDED, STAT_DEFERRED, STAT_FETCH_FREE, STAT_EVICTED, \
     STAT_FALLBACKS = range(8)
 STATS_FIELDS = 8
+OBJECT_NONE, OBJECT_MIRROR, OBJECT_GLASS, OBJECT_GLASS_TRAPPED = range(4)
 
 
 class GrtxError(RuntimeError):
@@ -57,7 +58,14 @@ class _BvhInfo(C.Structure):
 
 class _Rays(C.Structure):
     _fields_ = [("origins", C.c_void_p), ("dirs", C.c_void_p), ("count", C.c_int64), ("t_near", C.c_float),
-                ("image_width", C.c_int32)]
+                ("image_width", C.c_int32), ("t_far", C.c_void_p), ("transmittance", C.c_void_p),
+                ("next_origins", C.c_void_p), ("next_dirs", C.c_void_p), ("path", C.c_void_p), ("kind", C.c_void_p)]
+
+
+class _Objects(C.Structure):
+    _fields_ = [("sphere_center", C.c_float * 3), ("sphere_radius", C.c_float), ("sphere_ior", C.c_float),
+                ("mirror_center", C.c_float * 3), ("mirror_u", C.c_float * 3), ("mirror_v", C.c_float * 3),
+                ("surface_eps", C.c_float)]
 
 
 class _TraceParams(C.Structure):
@@ -118,6 +126,13 @@ _SIGNATURES = {
     "grtx_trace_backward": (C.c_int, [C.c_void_p, C.POINTER(_Gaussians), C.POINTER(_Rays), C.POINTER(_TraceParams),
                                       C.POINTER(_TraceOutputs), C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.POINTER(_GaussianGrads), C.c_void_p, C.c_void_p]),
+    "grtx_object_rays": (C.c_int, [C.POINTER(_Objects), C.POINTER(_Rays), C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p]),
+    "grtx_continue_rays": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_float, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64),
+                                     C.c_void_p]),
+    "grtx_continue_composite": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "grtx_serve_request_bytes": (C.c_int, [C.POINTER(_Request), C.POINTER(C.c_int64)]),
     "grtx_serve_create": (C.c_int, [C.POINTER(_ServeConfig), C.POINTER(C.c_void_p)]),
     "grtx_serve_add_scene": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
@@ -253,9 +268,13 @@ def pinhole_rays(camera, device="cuda", stream=None):
 def trace(bvh: Bvh, origins: torch.Tensor, dirs: torch.Tensor, k: int = 16, T_min: float = 1e-3,
           mode: int = CHECKPOINT, bg=(0.0, 0.0, 0.0), t_near: float = 0.0, image_width: int = 0,
           stats: bool = False, hit_capacity: int = 0, defer_capacity: int = 0, evict_capacity: int = 0,
-          out=None, stream=None):
+          out=None, stream=None, t_far: torch.Tensor = None, transmittance: torch.Tensor = None,
+          continuation: dict = None):
     """Render rays; returns dict(rgb [R,3], depth [R], opacity [R], and optionally stats
-    [R,8] int32, hit_ids [R,cap] int32, hit_counts [R] int32)."""
+    [R,8] int32, hit_ids [R,cap] int32, hit_counts [R] int32). t_far [R] bounds the rays at
+    a surface; transmittance [R] is what each ray starts with (both optional float32).
+    continuation: the dict of `object_rays` (next_o, next_d, path, kind); rays that reach
+    their surface then go on along their continuation ray in the same launch."""
     R = int(origins.shape[0])
     dev = origins.device
     if out is None:
@@ -267,7 +286,14 @@ def trace(bvh: Bvh, origins: torch.Tensor, dirs: torch.Tensor, k: int = 16, T_mi
         if hit_capacity > 0:
             out["hit_ids"] = torch.full((R, hit_capacity), -1, dtype=torch.int32, device=dev)
             out["hit_counts"] = torch.empty(R, dtype=torch.int32, device=dev)
-    rays = _Rays(origins.data_ptr() if R else None, dirs.data_ptr() if R else None, R, t_near, image_width)
+    rays = _Rays(origins.data_ptr() if R else None, dirs.data_ptr() if R else None, R, t_near, image_width,
+                 t_far.data_ptr() if t_far is not None and R else None,
+                 transmittance.data_ptr() if transmittance is not None and R else None)
+    if continuation is not None and R:
+        rays.next_origins = continuation["next_o"].data_ptr()
+        rays.next_dirs = continuation["next_d"].data_ptr()
+        rays.path = continuation["path"].data_ptr()
+        rays.kind = continuation["kind"].data_ptr()
     prm = _TraceParams(k, T_min, mode, (C.c_float * 3)(*bg), defer_capacity, evict_capacity)
     o = _TraceOutputs(out["rgb"].data_ptr() if R else None, out["depth"].data_ptr() if R else None,
                       out["opacity"].data_ptr() if R else None,
@@ -276,6 +302,96 @@ def trace(bvh: Bvh, origins: torch.Tensor, dirs: torch.Tensor, k: int = 16, T_mi
                       out["hit_counts"].data_ptr() if "hit_counts" in out and R else None,
                       int(out["hit_ids"].shape[1]) if "hit_ids" in out else 0, 0)
     _check(lib().grtx_trace(bvh.handle, C.byref(rays), C.byref(prm), C.byref(o), _stream(stream)))
+    return out
+
+
+def _objects(objects: dict):
+    """grtx_objects from a dict with optional "sphere" = (cx, cy, cz, r, ior), "mirror" =
+    (m, u, v) as 9 numbers and "eps"."""
+    sph = list(objects.get("sphere") or (0.0, 0.0, 0.0, 0.0, 1.0))
+    mir = list(objects.get("mirror") or (0.0,) * 9)
+    f3 = lambda a: (C.c_float * 3)(*[float(x) for x in a])
+    return _Objects(f3(sph[0:3]), float(sph[3]), float(sph[4]), f3(mir[0:3]), f3(mir[3:6]), f3(mir[6:9]),
+                    float(objects.get("eps", 0.0)))
+
+
+def object_rays(objects: dict, origins: torch.Tensor, dirs: torch.Tensor, t_near: float = 0.0, stream=None):
+    """grtx_object_rays: t_far [R], next_o / next_d [R,3], path [R], kind [R] int32."""
+    R = int(origins.shape[0])
+    dev = origins.device
+    out = dict(t_far=torch.empty(R, dtype=torch.float32, device=dev),
+               next_o=torch.empty((R, 3), dtype=torch.float32, device=dev),
+               next_d=torch.empty((R, 3), dtype=torch.float32, device=dev),
+               path=torch.empty(R, dtype=torch.float32, device=dev),
+               kind=torch.empty(R, dtype=torch.int32, device=dev))
+    rays = _Rays(origins.data_ptr() if R else None, dirs.data_ptr() if R else None, R, t_near, 0, None, None)
+    ob = _objects(objects)
+    _check(lib().grtx_object_rays(C.byref(ob), C.byref(rays), _ptr(out["t_far"]), _ptr(out["next_o"]),
+                                  _ptr(out["next_d"]), _ptr(out["path"]), _ptr(out["kind"]), _stream(stream)))
+    return out
+
+
+def continue_rays(kind, opacity, next_o, next_d, T_min: float = 1e-3, stream=None):
+    """grtx_continue_rays: the continuing rays (origins, dirs [n,3], transmittance [n],
+    index [n] int32) of segments that reached their surface."""
+    R = int(kind.shape[0])
+    dev = kind.device
+    co = torch.empty((R, 3), dtype=torch.float32, device=dev)
+    cd = torch.empty((R, 3), dtype=torch.float32, device=dev)
+    ct = torch.empty(R, dtype=torch.float32, device=dev)
+    ci = torch.empty(R, dtype=torch.int32, device=dev)
+    n = C.c_int64()
+    _check(lib().grtx_continue_rays(R, _ptr(kind), _ptr(opacity), T_min, _ptr(next_o), _ptr(next_d), _ptr(co),
+                                    _ptr(cd), _ptr(ct), _ptr(ci), C.byref(n), _stream(stream)))
+    m = int(n.value)
+    return dict(origins=co[:m], dirs=cd[:m], transmittance=ct[:m], index=ci[:m])
+
+
+def continue_composite(cont: dict, path, cont_out: dict, out: dict, stream=None):
+    """grtx_continue_composite: add the continuation results `cont_out` of the rays in
+    `cont` to the segment outputs `out` (rgb, depth, opacity, in place)."""
+    n = int(cont["index"].shape[0])
+    _check(lib().grtx_continue_composite(n, _ptr(cont["index"]), _ptr(cont["transmittance"]), _ptr(path),
+                                         _ptr(cont_out["rgb"]), _ptr(cont_out["depth"]), _ptr(cont_out["opacity"]),
+                                         _ptr(out["rgb"]), _ptr(out["depth"]), _ptr(out["opacity"]),
+                                         _stream(stream)))
+    return out
+
+
+def trace_with_objects(bvh: Bvh, origins: torch.Tensor, dirs: torch.Tensor, objects: dict, bounces: int = 1,
+                       t_near: float = 0.0, T_min: float = 1e-3, transmittance: torch.Tensor = None,
+                       levels: list = None, stream=None, fused: bool = False, **trace_kw):
+    """Render rays through a scene holding a glass sphere and a mirror, following up to
+    `bounces` object interactions per ray: object rays, the bounded trace, the gathered
+    continuation rays traced from the transmittance left, and their composite. Returns
+    the outputs of `trace`; with `levels` (a list) each level's rays and outputs are
+    appended to it. fused (one bounce): the continuation runs inside the same trace
+    launch instead."""
+    if fused:
+        if bounces != 1 or levels is not None:
+            raise ValueError("the fused continuation follows exactly one bounce and records no levels")
+        ob = object_rays(objects, origins, dirs, t_near, stream=stream)
+        return trace(bvh, origins, dirs, T_min=T_min, t_near=t_near, t_far=ob["t_far"],
+                     transmittance=transmittance, continuation=ob, stream=stream, **trace_kw)
+    if bounces <= 0:
+        out = trace(bvh, origins, dirs, T_min=T_min, t_near=t_near, transmittance=transmittance, stream=stream,
+                    **trace_kw)
+        if levels is not None:
+            levels.append(dict(origins=origins, dirs=dirs, objects=None, out=out, transmittance=transmittance))
+        return out
+    ob = object_rays(objects, origins, dirs, t_near, stream=stream)
+    out = trace(bvh, origins, dirs, T_min=T_min, t_near=t_near, t_far=ob["t_far"], transmittance=transmittance,
+                stream=stream, **trace_kw)
+    if levels is not None:
+        levels.append(dict(origins=origins, dirs=dirs, objects=ob, out={k: v.clone() for k, v in out.items()},
+                           transmittance=transmittance))
+    cont = continue_rays(ob["kind"], out["opacity"], ob["next_o"], ob["next_d"], T_min, stream=stream)
+    if cont["index"].shape[0] == 0:
+        return out
+    kw = {k: v for k, v in trace_kw.items() if k not in ("image_width", "out")}
+    sub = trace_with_objects(bvh, cont["origins"], cont["dirs"], objects, bounces - 1, 0.0, T_min,
+                             cont["transmittance"], levels, stream, **kw)
+    continue_composite(cont, ob["path"], sub, out, stream=stream)
     return out
 
 
@@ -298,7 +414,7 @@ def trace_backward(bvh: Bvh, origins, dirs, fwd: dict, grad_rgb=None, grad_depth
                      sh=torch.zeros_like(sc.sh))
     truncated = torch.zeros(1, dtype=torch.int32, device=dev)
     R = int(origins.shape[0])
-    rays = _Rays(origins.data_ptr() if R else None, dirs.data_ptr() if R else None, R, t_near, 0)
+    rays = _Rays(origins.data_ptr() if R else None, dirs.data_ptr() if R else None, R, t_near, 0, None, None)
     prm = _TraceParams(k, T_min, mode, (C.c_float * 3)(*bg), 0, 0)
     o = _TraceOutputs(fwd["rgb"].data_ptr(), fwd["depth"].data_ptr(), fwd["opacity"].data_ptr(), None,
                       fwd["hit_ids"].data_ptr(), fwd["hit_counts"].data_ptr(), int(fwd["hit_ids"].shape[1]), 0)

@@ -195,6 +195,29 @@ def ray_subsample(seed: int, total: int, count: int) -> np.ndarray:
     return np.sort(rng.choice(total, size=count, replace=False)).astype(np.int64)
 
 
+def secondary_objects(seed: int = 60) -> dict:
+    """A glass sphere and a rectangular mirror at seeded random places in front of the
+    orbit camera at (0, -3, 0) (the secondary-ray experiment places one of each in every
+    scene). Sphere: centre uniform in [-0.8, 0.8] x [-1, 0] x [-0.5, 0.5], radius uniform
+    in [0.35, 0.5], index 1.5. Mirror: centre uniform in [-1, 1] x [0, 0.8] x [-0.5, 0.5],
+    normal (s * U(0.6, 1.4), -1, N(0, 0.3)) normalised with a random sign s (turned
+    towards the camera and to one side, so that reflections run through the scene),
+    half-axes 0.7 and 0.5 orthogonal to it. Returns {"sphere": (cx, cy, cz, r, ior),
+    "mirror": (m, u, v) as 9 numbers, "eps": 1e-4} in float32-representable values."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform([-0.8, -1.0, -0.5], [0.8, 0.0, 0.5])
+    r = rng.uniform(0.35, 0.5)
+    m = rng.uniform([-1.0, 0.0, -0.5], [1.0, 0.8, 0.5])
+    n = np.array([rng.choice([-1.0, 1.0]) * rng.uniform(0.6, 1.4), -1.0, rng.normal(0.0, 0.3)])
+    n /= np.linalg.norm(n)
+    a = np.cross(n, [0.0, 0.0, 1.0])
+    a /= np.linalg.norm(a)
+    b = np.cross(n, a)
+    u, v = 0.7 * a, 0.5 * b
+    f = lambda x: [float(np.float32(t)) for t in np.ravel(x)]
+    return {"sphere": tuple(f(c) + f(r) + [1.5]), "mirror": tuple(f(m) + f(u) + f(v)), "eps": 1e-4}
+
+
 # Named workloads. Sizes follow the plain-method case, the scene-scale cases, the
 # differentiation case and the serving case.
 PLAIN = dict(name="plain-1k-64x64-k4", seed=1, n=1000, width=64, height=64, k=4,
@@ -207,6 +230,8 @@ SCENE3M = dict(name="scene-3M-1920x1080+2Mincoherent-k16", seed=3, n=3_000_000, 
 DIFF200K = dict(name="diff-200k-512x512-k16", seed=4, n=200_000, width=512, height=512, k=16,
                 target_seed=44, fd_seed=5, fd_n=500, fd_width=32, fd_height=32,
                 alpha_min=1.0 / 255.0, T_min=1e-3)
+SECONDARY = dict(name="scene-100k-800x800-k16+glass+mirror", seed=2, n=100_000, width=800, height=800, k=16,
+                 objects_seed=60, alpha_min=1.0 / 255.0, T_min=1e-3)
 SERVE = dict(name="serve-4scenes-poisson200", scene_seeds=(10, 11, 12, 13),
              scene_sizes=(100_000, 500_000, 1_000_000, 3_000_000), rate=200.0, arrival_seed=50,
              resolutions=((256, 256), (512, 512), (800, 800), (1920, 1080)), k=16,

@@ -5,10 +5,12 @@ Rule (tolerances of the method's stated FP32 bar):
      (i)   ids whose FP64 alpha is within 1e-5 of alpha_min may be present or absent;
      (ii)  adjacent hits whose key distances differ by < 1e-5 may swap;
      (iii) the last hit may be extra or missing when the oracle's transmittance after
-           that hit is within 1e-6 of T_min.
+           that hit is within 1e-6 of T_min;
+     (iv)  for a ray bounded by a surface at t_far, hits whose key is within 1e-5 of
+           t_far may be present or absent.
   2. Identical lists: |rgb - oracle| <= 1e-4 per channel and |depth - oracle| <= 1e-4.
   3. Lists that differ only by allowed exceptions: the same bound against the oracle's
-     re-composition of the GPU's own list.
+     re-composition of the GPU's own list (from the ray's starting transmittance).
 """
 from __future__ import annotations
 
@@ -22,11 +24,16 @@ T_SWAP = 1e-5
 T_ERT = 1e-6
 
 
-def lists_match_with_exceptions(g, o, hits, scene, origin, direction, amin, T_min, tafter):
+def lists_match_with_exceptions(g, o, hits, scene, origin, direction, amin, T_min, tafter, t_far=np.inf):
     # `hits` holds the oracle's alpha and key distance of every hit on this ray
     """True if GPU list g and oracle list o differ only by the allowed exceptions."""
     alpha = dict(zip(hits["ids"].tolist(), hits["alpha"].tolist()))
     tkey = dict(zip(hits["ids"].tolist(), hits["t"].tolist()))
+    if np.isfinite(t_far):
+        # (iv) hits at the bounding surface
+        near = {i for i, t in tkey.items() if abs(t - t_far) < T_SWAP}
+        g = [i for i in g if i not in near]
+        o = [i for i in o if i not in near]
 
     def a_of(i):
         if i in alpha:
@@ -76,10 +83,14 @@ def _describe(g, o, hits, tafter, T_min):
                 T_after_last=float(tafter[-1]) if len(tafter) else None, T_min=T_min)
 
 
-def compare_render(scene, origins, dirs, gpu, ref, amin, T_min, max_exception_frac=1e-2, label="", key_mode=0):
+def compare_render(scene, origins, dirs, gpu, ref, amin, T_min, max_exception_frac=1e-2, label="", key_mode=0,
+                   t_far=None, trans0=None, bg=(0.0, 0.0, 0.0)):
     """Compare GPU outputs (numpy dict: rgb, depth, hit_ids, hit_counts) with an oracle
-    render (with cap) of the same rays. Returns a summary dict; asserts the rule."""
+    render (with cap) of the same rays, which may be bounded (t_far) and start with a
+    transmittance (trans0). Returns a summary dict; asserts the rule."""
     R = origins.shape[0]
+    tf = np.full(R, np.inf) if t_far is None else np.asarray(t_far, np.float64)
+    t0 = np.ones(R) if trans0 is None else np.asarray(trans0, np.float64)
     cap = gpu["hit_ids"].shape[1]
     n_exact = n_exc = 0
     worst = 0.0
@@ -99,10 +110,11 @@ def compare_render(scene, origins, dirs, gpu, ref, amin, T_min, max_exception_fr
             continue
         hits = oracle.ray_hits(scene, origins[r], dirs[r], amin, key_mode=key_mode)
         if not lists_match_with_exceptions(g, o, hits, scene, origins[r], dirs[r], amin, T_min,
-                                           ref["tafter"][r, :ocount]):
+                                           ref["tafter"][r, :ocount], tf[r]):
             bad.append((r, "list", _describe(g, o, hits, ref["tafter"][r, :ocount], T_min)))
             continue
-        c = oracle.composite_list(scene, origins[r], dirs[r], g, amin)
+        c = oracle.composite_list(scene, origins[r], dirs[r], g, amin, bg=bg if np.isinf(tf[r]) else (0, 0, 0),
+                                  trans0=t0[r])
         err = max(np.abs(gpu["rgb"][r] - c["rgb"]).max(), abs(gpu["depth"][r] - c["depth"]))
         worst = max(worst, err)
         if err > TOL:

@@ -29,7 +29,7 @@ def test_header_symbols_exported():
 
 def test_version_and_null_destroy():
     L = grtx.lib()
-    assert L.grtx_version() == 1
+    assert L.grtx_version() == 2
     assert L.grtx_bvh_destroy(None) == grtx.OK
 
 
@@ -67,6 +67,35 @@ def test_trace_rejects_bad_arguments():
     assert b"null" in L.grtx_last_error()
     cam = grtx._Camera((C.c_float * 3)(0, -3, 0), (C.c_float * 3)(0, 0, 0), (C.c_float * 3)(0, 0, 1), 60.0, 0, 4)
     assert L.grtx_pinhole_rays(C.byref(cam), C.c_void_p(1), C.c_void_p(1), None) == grtx.ERR_INVALID_ARG
+
+
+def test_secondary_ray_calls_reject_bad_arguments():
+    L = grtx.lib()
+    fake = C.c_void_p(1)  # never dereferenced: validation fails first
+    rays = grtx._Rays(fake, fake, 4, 0.0, 0, None, None)
+    ok = dict(sphere=(0, 0, 0, 0.5, 1.5), mirror=(1, 0, 0, 0, 0.4, 0, 0, 0, 0.3))
+    for objs in [dict(ok, sphere=(0, 0, 0, 0.5, 0.0)), dict(ok, sphere=(0, 0, 0, 0.5, -1.0)),
+                 dict(ok, mirror=(1, 0, 0, 0, 0.4, 0, 0, 0.3, 0.3)), dict(ok, eps=-1.0),
+                 dict(ok, sphere=(float("nan"), 0, 0, 0.5, 1.5))]:
+        ob = grtx._objects(objs)
+        assert L.grtx_object_rays(C.byref(ob), C.byref(rays), fake, fake, fake, fake, fake, None) == \
+            grtx.ERR_INVALID_ARG, objs
+    ob = grtx._objects(ok)
+    assert L.grtx_object_rays(C.byref(ob), C.byref(rays), None, fake, fake, fake, fake, None) == grtx.ERR_INVALID_ARG
+    assert b"null" in L.grtx_last_error()
+    assert L.grtx_object_rays(None, C.byref(rays), fake, fake, fake, fake, fake, None) == grtx.ERR_INVALID_ARG
+    n = C.c_int64(-7)
+    assert L.grtx_continue_rays(-1, fake, fake, 1e-3, fake, fake, fake, fake, fake, fake, C.byref(n), None) == \
+        grtx.ERR_INVALID_ARG
+    assert L.grtx_continue_rays(4, fake, fake, 1.0, fake, fake, fake, fake, fake, fake, C.byref(n), None) == \
+        grtx.ERR_INVALID_ARG
+    assert L.grtx_continue_rays(4, None, fake, 1e-3, fake, fake, fake, fake, fake, fake, C.byref(n), None) == \
+        grtx.ERR_INVALID_ARG
+    assert n.value == -7  # out-param untouched
+    assert L.grtx_continue_composite(-1, *([fake] * 9), None) == grtx.ERR_INVALID_ARG
+    assert L.grtx_continue_composite(3, None, *([fake] * 8), None) == grtx.ERR_INVALID_ARG
+    # zero rays: nothing to do, no device touched
+    assert L.grtx_continue_composite(0, *([None] * 9), None) == grtx.OK
 
 
 def test_binding_raises_on_error():

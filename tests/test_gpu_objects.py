@@ -1,0 +1,368 @@
+"""Secondary rays on the GPU against the FP64 oracle, through the C ABI: where rays meet
+the glass sphere and the mirror and how they continue, traces of rays bounded by a
+surface or starting from a transmittance, the gathering of continuation rays and the
+composite of a continued path. Needs an MI355X and the built library."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2601_20429_amd import inputs
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2601_20429_amd import grtx  # noqa: E402
+
+AMIN = float(np.float32(1.0 / 255.0))
+T_MIN = 1e-3
+OBJS = inputs.secondary_objects(60)
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(out):
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def build(scene, kind=grtx.SPHERE_INSTANCE):
+    return grtx.build(grtx.SceneTensors.from_scene(scene, "cuda"), kind=kind, alpha_min=AMIN)
+
+
+def f32(a):
+    """Round to binary32 and widen back: the value both sides then use."""
+    return np.asarray(a, np.float64).astype(np.float32)
+
+
+# ------------------------------------------------------------------------ object rays
+
+def _sensitivity(objs, o, d, delta=1e-6, trials=4, seed=5):
+    """Per ray, how far the oracle's object-ray outputs move per unit change of the ray
+    (largest over random perturbations of size delta), and whether the kind changes."""
+    base = oracle.object_rays(objs, o, d)
+    rng = np.random.default_rng(seed)
+    sens = np.zeros(o.shape[0])
+    flips = np.zeros(o.shape[0], bool)
+    for _ in range(trials):
+        po = o + delta * rng.standard_normal(o.shape)
+        pd = d + delta * rng.standard_normal(d.shape)
+        pd /= np.linalg.norm(pd, axis=1, keepdims=True)
+        p = oracle.object_rays(objs, po, pd)
+        flips |= p["kind"] != base["kind"]
+        fin = np.isfinite(base["t_far"]) & np.isfinite(p["t_far"])
+        ch = np.zeros(o.shape[0])
+        ch[fin] = np.maximum(np.abs(p["t_far"][fin] - base["t_far"][fin]), np.abs(p["path"][fin] - base["path"][fin]))
+        ch = np.maximum(ch, np.abs(p["next_o"] - base["next_o"]).max(1))
+        ch = np.maximum(ch, np.abs(p["next_d"] - base["next_d"]).max(1))
+        sens = np.maximum(sens, ch / delta)
+    return base, sens, flips
+
+
+def check_object_rays(objs, o, d, label):
+    """GPU grtx_object_rays against the oracle. A binary32 computation moves the outputs
+    about as much as perturbing the ray by ~1e-6, so each ray gets the tolerance
+    2e-5 + 1e-5 * S, with S the oracle's own sensitivity to such a perturbation. Rays
+    whose kind the oracle itself changes under the perturbation sit on a silhouette or
+    an edge and may differ in kind (at most 0.2% of the rays)."""
+    g = host(grtx.object_rays(objs, dev(o), dev(d)))
+    ref, sens, flips = _sensitivity(objs, o.astype(np.float64), d.astype(np.float64))
+    same = g["kind"] == ref["kind"]
+    assert (same | flips).all(), (label, np.flatnonzero(~(same | flips))[:5])
+    assert (~same).sum() <= 2e-3 * o.shape[0] + 1, (label, int((~same).sum()))
+    m = same & ~flips
+    tol = 2e-5 + 1e-5 * sens[m]
+    gk = g["kind"][m]
+    assert (np.isinf(g["t_far"][m]) == (gk == grtx.OBJECT_NONE)).all()
+    fin = gk != grtx.OBJECT_NONE
+    err = np.zeros(m.sum())
+    err[fin] = np.maximum(np.abs(g["t_far"][m][fin] - ref["t_far"][m][fin]),
+                          np.abs(g["path"][m][fin] - ref["path"][m][fin]))
+    err = np.maximum(err, np.abs(g["next_o"][m] - ref["next_o"][m]).max(1))
+    err = np.maximum(err, np.abs(g["next_d"][m] - ref["next_d"][m]).max(1))
+    bad = np.flatnonzero(err > tol)
+    assert bad.size == 0, (label, bad[:5], err[bad[:5]], tol[bad[:5]])
+    cont = np.isin(g["kind"], (grtx.OBJECT_MIRROR, grtx.OBJECT_GLASS))
+    np.testing.assert_allclose(np.linalg.norm(g["next_d"][cont], axis=1), 1.0, atol=1e-6)
+    return dict(rays=o.shape[0], kinds=np.bincount(g["kind"], minlength=4).tolist(), edge=int((~same).sum()),
+                worst=float(err.max(initial=0.0)))
+
+
+def test_object_rays_match_oracle():
+    say("object rays, pinhole + incoherent")
+    o, d = oracle.pinhole_rays(inputs.orbit_camera(256, 256))
+    say(check_object_rays(OBJS, f32(o), f32(d), "pinhole"))
+    io, id_ = inputs.incoherent_rays(34, 20000)
+    say(check_object_rays(OBJS, io, id_, "incoherent"))
+
+
+def test_object_rays_special_cases():
+    """Index 1 glass passes rays straight; a ray starting inside the glass leaves it;
+    total internal reflection ends a ray inside (kind 3); no objects, no hits; zero rays."""
+    say("object rays special")
+    o = np.float32([[0.0, -3.0, 0.0], [0.0, 0.1, 0.0], [0.0, 0.45, 0.0], [5.0, 5.0, 5.0]])
+    d = np.float32([[0.0, 1.0, 0.0], [1.0, 0.0, 0.0], [1.0, 0.0, 0.0], [1.0, 0.0, 0.0]])
+    glass1 = {"sphere": (0.0, 0.0, 0.0, 0.5, 1.0)}
+    g = host(grtx.object_rays(glass1, dev(o), dev(d)))
+    assert g["kind"].tolist() == [2, 2, 2, 0]
+    np.testing.assert_allclose(g["next_d"][:3], d[:3], atol=1e-7)
+    np.testing.assert_allclose(g["next_o"][0], [0.0, 0.5, 0.0], atol=1e-6)
+    glass = {"sphere": (0.0, 0.0, 0.0, 0.5, 1.5)}
+    g = host(grtx.object_rays(glass, dev(o), dev(d)))
+    ref = oracle.object_rays(glass, o, d)
+    assert g["kind"].tolist() == ref["kind"].tolist() == [2, 2, 3, 0]
+    np.testing.assert_allclose(g["path"][:3], ref["path"][:3], atol=1e-5)
+    none = host(grtx.object_rays({}, dev(o), dev(d)))
+    assert (none["kind"] == 0).all() and np.isinf(none["t_far"]).all() and not none["next_d"].any()
+    z = grtx.object_rays(OBJS, dev(np.zeros((0, 3))), dev(np.zeros((0, 3))))
+    assert z["kind"].shape == (0,)
+
+
+# ------------------------------------------------------------------------ gathering, composite
+
+@pytest.mark.parametrize("R", [1, 255, 257, 100_003])
+def test_continue_rays_exact(R):
+    """The continuation set is an integer decision taken in binary32 on both sides
+    (kind is MIRROR or GLASS and 1 - opacity >= T_min): indices, copies and
+    transmittances are bit-exact, in ray order."""
+    say("continue rays", R)
+    rng = np.random.default_rng(R)
+    kind = rng.integers(0, 4, R).astype(np.int32)
+    op = rng.uniform(0.0, 1.0, R).astype(np.float32)
+    op[::7] = np.float32(1.0) - np.float32(T_MIN)       # exactly at the threshold
+    op[::11] = np.nextafter(op[::11].dtype.type(1.0) - np.float32(T_MIN), np.float32(1.0))
+    no = rng.standard_normal((R, 3)).astype(np.float32)
+    nd = rng.standard_normal((R, 3)).astype(np.float32)
+    c = grtx.continue_rays(dev(kind, torch.int32), dev(op), dev(no), dev(nd), T_MIN)
+    c = host(c)
+    sel = np.flatnonzero(np.isin(kind, (1, 2)) & ((np.float32(1.0) - op) >= np.float32(T_MIN)))
+    assert c["index"].tolist() == sel.tolist()
+    assert np.array_equal(c["origins"], no[sel]) and np.array_equal(c["dirs"], nd[sel])
+    assert np.array_equal(c["transmittance"], np.float32(1.0) - op[sel])
+
+
+def test_continue_composite_matches_oracle_formula():
+    """The composite of a continued path, fed with the oracle's own segment results:
+    colour adds, depth adds with the continuation's weights shifted by the path length,
+    opacity is the continuation's."""
+    say("composite")
+    scene = inputs.small_scene(1, 1000)
+    o, d = oracle.pinhole_rays(inputs.orbit_camera(48, 48))
+    levels = []
+    final = oracle.render_with_objects(scene, o, d, OBJS, bounces=1, alpha_min=AMIN, T_min=T_MIN, levels=levels)
+    assert len(levels) == 2
+    L0, L1 = levels
+    T1 = 1.0 - L0["out"]["opacity"]
+    cont = np.flatnonzero(np.isin(L0["objects"]["kind"], (1, 2)) & (T1 >= T_MIN))
+    assert cont.size == L1["origins"].shape[0] > 20
+    out = {k: dev(L0["out"][k]) for k in ("rgb", "depth", "opacity")}
+    cc = dict(index=dev(cont, torch.int32), transmittance=dev(T1[cont]))
+    sub = {k: dev(L1["out"][k]) for k in ("rgb", "depth", "opacity")}
+    grtx.continue_composite(cc, dev(L0["objects"]["path"]), sub, out)
+    g = host(out)
+    for k in ("rgb", "depth", "opacity"):
+        np.testing.assert_allclose(g[k], final[k], atol=2e-5, err_msg=k)
+
+
+# ------------------------------------------------------------------------ bounded / attenuated traces
+
+@pytest.mark.parametrize("kind", [grtx.SPHERE_INSTANCE, grtx.PROXY20, grtx.ICO_INSTANCE])
+@pytest.mark.parametrize("mode", [grtx.CHECKPOINT, grtx.RESTART])
+def test_bounded_trace_parity(kind, mode):
+    """Rays bounded by the objects' surfaces (the oracle's t_far, in binary32) and, for
+    every other ray, a starting transmittance in [0.002, 1]; background (0.1, 0.2, 0.3)
+    only where unbounded. 1k Gaussians, 64x64, k = 4."""
+    say("bounded trace", kind, mode)
+    scene = inputs.small_scene(1, 1000)
+    o, d = oracle.pinhole_rays(inputs.orbit_camera(64, 64))
+    o, d = f32(o), f32(d)
+    ob = oracle.object_rays(OBJS, o, d)
+    t_far = f32(ob["t_far"])
+    rng = np.random.default_rng(9)
+    trans = f32(np.where(np.arange(o.shape[0]) % 2 == 1, rng.uniform(0.002, 1.0, o.shape[0]), 1.0))
+    bg = (0.1, 0.2, 0.3)
+    bvh = build(scene, kind)
+    g = host(grtx.trace(bvh, dev(o), dev(d), k=4, T_min=T_MIN, mode=mode, bg=bg, hit_capacity=256,
+                        t_far=dev(t_far), transmittance=dev(trans)))
+    key_mode = 0 if kind == grtx.SPHERE_INSTANCE else 1
+    ref = oracle.render(scene, o, d, AMIN, T_MIN, bg=bg, key_mode=key_mode, cap=256, t_far=t_far, trans0=trans)
+    assert (ref["nblend"][np.isfinite(t_far)] > 0).any()
+    s = parity.compare_render(scene, o, d, g, ref, AMIN, T_MIN, label=f"bounded {kind} {mode}", key_mode=key_mode,
+                              t_far=t_far, trans0=trans, bg=bg)
+    say(s)
+
+
+def test_bounded_modes_and_k_bit_identical():
+    say("bounded modes/k identity")
+    scene = inputs.cluster_scene(2, 100_000, 3)
+    cam = inputs.orbit_camera(160, 120)
+    o, d = grtx.pinhole_rays(cam)
+    ob = grtx.object_rays(OBJS, o, d)
+    trans = torch.linspace(0.01, 1.0, o.shape[0], device="cuda")
+    bvh = build(scene)
+    base = None
+    for k in [16, 1, 4, 32]:
+        for mode in [grtx.CHECKPOINT, grtx.RESTART]:
+            cur = host(grtx.trace(bvh, o, d, k=k, T_min=T_MIN, mode=mode, image_width=cam.width, hit_capacity=64,
+                                  t_far=ob["t_far"], transmittance=trans))
+            if base is None:
+                base = cur
+                continue
+            for key in ["rgb", "depth", "opacity", "hit_counts", "hit_ids"]:
+                assert np.array_equal(cur[key], base[key]), (k, mode, key)
+
+
+def test_backward_refuses_bounded_rays():
+    say("backward refuses bounded rays")
+    scene = inputs.small_scene(1, 1000)
+    bvh = build(scene)
+    o, d = grtx.pinhole_rays(inputs.orbit_camera(8, 8))
+    fwd = grtx.trace(bvh, o, d, k=4, hit_capacity=32)
+    L = grtx.lib()
+    import ctypes as C
+    tf = torch.full((64,), 2.0, device="cuda")
+    rays = grtx._Rays(o.data_ptr(), d.data_ptr(), 64, 0.0, 0, tf.data_ptr(), None)
+    prm = grtx._TraceParams(4, T_MIN, 0, (C.c_float * 3)(0, 0, 0), 0, 0)
+    fo = grtx._TraceOutputs(fwd["rgb"].data_ptr(), fwd["depth"].data_ptr(), fwd["opacity"].data_ptr(), None,
+                            fwd["hit_ids"].data_ptr(), fwd["hit_counts"].data_ptr(), 32, 0)
+    grads = {k: torch.zeros_like(getattr(bvh.scene, k)) for k in ("means", "scales", "quats", "opacities", "sh")}
+    gg = grtx._GaussianGrads(*[grads[k].data_ptr() for k in ("means", "scales", "quats", "opacities", "sh")])
+    g = grtx._gaussians(bvh.scene)
+    gr = torch.ones((64, 3), device="cuda")
+    st = L.grtx_trace_backward(bvh.handle, C.byref(g), C.byref(rays), C.byref(prm), C.byref(fo),
+                               C.c_void_p(gr.data_ptr()), None, None, C.byref(gg), None, None)
+    assert st == grtx.ERR_INVALID_ARG
+    assert b"t_far" in L.grtx_last_error()
+
+
+# ------------------------------------------------------------------------ the workload at full size
+
+def test_secondary_scene100k_sampled():
+    """100k Gaussians with the glass sphere and the mirror, sampled 800x800 pixels: the
+    bounded primary segment and the continuation segment (the oracle's continuation rays
+    in binary32, starting from the oracle's transmittance) each against the oracle by the
+    per-ray rule; then the whole GPU chain against the oracle's chain, whose difference
+    comes only from continuation rays computed in binary32 rather than FP64 (bounded here
+    by the per-ray trace tolerance at the 99th percentile and ten times it at worst)."""
+    say("secondary 100k sampled")
+    cfg = inputs.SECONDARY
+    scene = inputs.cluster_scene(cfg["seed"], cfg["n"], 3)
+    o, d = oracle.pinhole_rays(inputs.orbit_camera(cfg["width"], cfg["height"]))
+    idx = inputs.ray_subsample(101, o.shape[0], 1024)
+    o, d = f32(o[idx]), f32(d[idx])
+    bvh = build(scene)
+    ob = oracle.object_rays(OBJS, o, d)
+    t_far = f32(ob["t_far"])
+    g0 = host(grtx.trace(bvh, dev(o), dev(d), k=16, T_min=T_MIN, hit_capacity=512, t_far=dev(t_far)))
+    r0 = oracle.render(scene, o, d, AMIN, T_MIN, cap=512, t_far=t_far)
+    say(parity.compare_render(scene, o, d, g0, r0, AMIN, T_MIN, label="primary segment", t_far=t_far))
+    T1 = 1.0 - r0["opacity"]
+    cont = np.flatnonzero(np.isin(ob["kind"], (1, 2)) & (T1 >= T_MIN))
+    assert cont.size > 100
+    co, cd, ct = f32(ob["next_o"][cont]), f32(ob["next_d"][cont]), f32(T1[cont])
+    g1 = host(grtx.trace(bvh, dev(co), dev(cd), k=16, T_min=T_MIN, hit_capacity=512, transmittance=dev(ct)))
+    r1 = oracle.render(scene, co, cd, AMIN, T_MIN, cap=512, trans0=ct)
+    say(parity.compare_render(scene, co, cd, g1, r1, AMIN, T_MIN, label="continuation segment", trans0=ct))
+    # the whole chain on the GPU
+    full = host(grtx.trace_with_objects(bvh, dev(o), dev(d), OBJS, bounces=1, k=16, T_min=T_MIN))
+    ref = oracle.render_with_objects(scene, o, d, OBJS, bounces=1, alpha_min=AMIN, T_min=T_MIN)
+    err = np.abs(full["rgb"] - ref["rgb"]).max(1)
+    say(dict(median=float(np.median(err)), p99=float(np.quantile(err, 0.99)), max=float(err.max())))
+    assert np.median(err) < 1e-5 and np.quantile(err, 0.99) < 1e-4 and err.max() < 1e-3
+
+
+def test_fused_continuation_matches_chain():
+    """The continuation run inside the trace launch gives the three-call chain's outputs up
+    to rounding order (transmittance taken exactly instead of as 1 - opacity, colour
+    accumulated in one sum), with both segments' hits in one list; checkpoint and restart
+    bit-identical; continuation arrays without t_far are refused."""
+    say("fused continuation")
+    scene = inputs.cluster_scene(2, 100_000, 3)
+    cam = inputs.orbit_camera(200, 150)
+    o, d = grtx.pinhole_rays(cam)
+    bvh = build(scene)
+    bg = (0.05, 0.1, 0.2)
+    lv = []
+    chain = host(grtx.trace_with_objects(bvh, o, d, OBJS, k=16, T_min=T_MIN, bg=bg, levels=lv))
+    fused = {}
+    for mode in (grtx.CHECKPOINT, grtx.RESTART):
+        fused[mode] = host(grtx.trace_with_objects(bvh, o, d, OBJS, k=16, T_min=T_MIN, bg=bg, mode=mode, fused=True,
+                                                   hit_capacity=512))
+    for key in ("rgb", "depth", "opacity", "hit_ids", "hit_counts"):
+        assert np.array_equal(fused[grtx.CHECKPOINT][key], fused[grtx.RESTART][key]), key
+    f = fused[grtx.CHECKPOINT]
+    for key, tol in (("rgb", 2e-6), ("depth", 2e-5), ("opacity", 2e-6)):
+        np.testing.assert_allclose(f[key], chain[key], atol=tol, err_msg=key)
+    # the hit list of a continued ray is the primary segment's list then the continuation's
+    ob = host(lv[0]["objects"])
+    T1 = 1 - host(lv[0]["out"])["opacity"]
+    cont = np.flatnonzero(np.isin(ob["kind"], (1, 2)) & (T1 >= T_MIN))
+    assert cont.size > 500
+    seg = host(grtx.trace(bvh, o, d, k=16, T_min=T_MIN, hit_capacity=512, t_far=lv[0]["objects"]["t_far"]))
+    nc = f["hit_counts"]
+    for r in cont[:: max(1, cont.size // 50)]:
+        n0 = int(seg["hit_counts"][r])
+        assert f["hit_ids"][r, :n0].tolist() == seg["hit_ids"][r, :n0].tolist()
+        assert nc[r] >= n0
+    with pytest.raises(grtx.GrtxError):
+        grtx.trace(bvh, o, d, continuation=lv[0]["objects"])
+
+
+def test_secondary_full_size_launch():
+    """The benchmark's launches at full size: object rays of all 800x800 pixels against
+    the oracle, the bounded trace of the whole frame (8x8 tiles) and the trace of every
+    continuation ray (the oracle's, in binary32, with seeded starting transmittances),
+    sampled rays of both against the oracle; checkpoint and restart chains bit-identical."""
+    say("secondary full size")
+    cfg = inputs.SECONDARY
+    scene = inputs.cluster_scene(cfg["seed"], cfg["n"], 3)
+    cam = inputs.orbit_camera(cfg["width"], cfg["height"])
+    o, d = oracle.pinhole_rays(cam)
+    o, d = f32(o), f32(d)
+    say(check_object_rays(OBJS, o, d, "full frame"))
+    bvh = build(scene)
+    ob = oracle.object_rays(OBJS, o, d)
+    t_far = f32(ob["t_far"])
+    g0 = grtx.trace(bvh, dev(o), dev(d), k=16, T_min=T_MIN, image_width=cfg["width"], hit_capacity=512,
+                    stats=True, t_far=dev(t_far))
+    g0 = host(g0)
+    assert (g0["stats"][:, grtx.STAT_ROUNDS] >= 1).all()
+    idx = inputs.ray_subsample(102, o.shape[0], 512)
+    r0 = oracle.render(scene, o[idx], d[idx], AMIN, T_MIN, cap=512, t_far=t_far[idx])
+    say(parity.compare_render(scene, o[idx], d[idx], {k: v[idx] for k, v in g0.items()}, r0, AMIN, T_MIN,
+                              label="full primary segment", t_far=t_far[idx]))
+    sel = np.flatnonzero(np.isin(ob["kind"], (1, 2)))
+    co, cd = f32(ob["next_o"][sel]), f32(ob["next_d"][sel])
+    ct = f32(np.random.default_rng(103).uniform(0.02, 1.0, sel.size))
+    g1 = host(grtx.trace(bvh, dev(co), dev(cd), k=16, T_min=T_MIN, hit_capacity=512, stats=True,
+                         transmittance=dev(ct)))
+    assert (g1["stats"][:, grtx.STAT_ROUNDS] >= 1).all()
+    j = inputs.ray_subsample(104, sel.size, 512)
+    r1 = oracle.render(scene, co[j], cd[j], AMIN, T_MIN, cap=512, trans0=ct[j])
+    say(parity.compare_render(scene, co[j], cd[j], {k: v[j] for k, v in g1.items()}, r1, AMIN, T_MIN,
+                              label="full continuation segment", trans0=ct[j]))
+    oo, dd = dev(o), dev(d)
+    a = host(grtx.trace_with_objects(bvh, oo, dd, OBJS, k=16, T_min=T_MIN, mode=grtx.CHECKPOINT,
+                                     image_width=cfg["width"]))
+    b = host(grtx.trace_with_objects(bvh, oo, dd, OBJS, k=16, T_min=T_MIN, mode=grtx.RESTART,
+                                     image_width=cfg["width"]))
+    for key in ("rgb", "depth", "opacity"):
+        assert np.array_equal(a[key], b[key]), key
