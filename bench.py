@@ -361,7 +361,7 @@ def main():
     ap.add_argument("--mode", choices=["checkpoint", "restart"], default="checkpoint")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the restart-mode comparison run")
-    ap.add_argument("--cpu-rays", type=int, default=16384)
+    ap.add_argument("--cpu-rays", type=int, default=196608)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="first copy this many GiB device-to-device (a reference kernel for HBM counters)")

@@ -33,6 +33,9 @@
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <numeric>
+#include <tuple>
+#include <vector>
 
 #include "grtx_internal.h"
 
@@ -774,10 +777,12 @@ __global__ void k_reset_counter(unsigned int* c) {
 // Tile order for rays that continue past an object: the tiles holding such rays go first.
 // Those rays run longest (two segments); started last, they would set the end of the
 // launch, while rows of tiles in image order keep neighbouring rays together.
-__global__ void __launch_bounds__(256) k_tile_heavy(const int32_t* __restrict__ kind, int w, int h, int tiles_x,
-                                                    int64_t n_tiles, uint32_t* __restrict__ flag) {
-  const int64_t t = blockIdx.x * (int64_t)256 + threadIdx.x;
-  if (t >= n_tiles) return;
+__global__ void __launch_bounds__(256) k_tile_heavy(const int32_t* __restrict__ kind, const uint32_t* __restrict__ base,
+                                                    int w, int h, int tiles_x, int64_t n_tiles,
+                                                    uint32_t* __restrict__ flag) {
+  const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
+  if (i >= n_tiles) return;
+  const int64_t t = base[i];
   const int64_t ty = t / tiles_x, tx = t - ty * tiles_x;
   uint32_t f = 0;
   for (int j = 0; j < 64; ++j) {
@@ -787,16 +792,18 @@ __global__ void __launch_bounds__(256) k_tile_heavy(const int32_t* __restrict__ 
       f |= (k == GRTX_OBJECT_MIRROR || k == GRTX_OBJECT_GLASS) ? 1u : 0u;
     }
   }
-  flag[t] = f;
+  flag[i] = f;
 }
 
-__global__ void __launch_bounds__(256) k_tile_order(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ pos,
-                                                    int64_t n_tiles, uint32_t* __restrict__ order) {
-  const int64_t t = blockIdx.x * (int64_t)256 + threadIdx.x;
-  if (t >= n_tiles) return;
+// Stable partition of the base order: flagged tiles first.
+__global__ void __launch_bounds__(256) k_tile_order(const uint32_t* __restrict__ base, const uint32_t* __restrict__ flag,
+                                                    const uint32_t* __restrict__ pos, int64_t n_tiles,
+                                                    uint32_t* __restrict__ order) {
+  const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
+  if (i >= n_tiles) return;
   const int64_t heavy = (int64_t)pos[n_tiles - 1] + flag[n_tiles - 1];
-  const int64_t dst = flag[t] ? (int64_t)pos[t] : heavy + (t - (int64_t)pos[t]);
-  order[dst] = (uint32_t)t;
+  const int64_t dst = flag[i] ? (int64_t)pos[i] : heavy + (i - (int64_t)pos[i]);
+  order[dst] = base[i];
 }
 
 // Outputs of rays that meet nothing (a structure without leaves).
@@ -828,6 +835,37 @@ struct Pool {
 
 std::mutex g_pool_lock;
 std::map<std::pair<int, hipStream_t>, Pool> g_pools;
+
+// Centre-out tile order of an image: rings of tiles by distance from the image centre,
+// each ring by angle. Rays near the centre of an object-centred view cross the most
+// Gaussians; started first, they no longer set the end of the launch, and the tiles in
+// flight together stay one compact region. Computed once per (device, tile grid) on the
+// host and kept on the device until the process ends.
+std::mutex g_order_lock;
+std::map<std::tuple<int, int, int>, uint32_t*> g_orders;
+
+grtx_status centre_out_order(int device, int tiles_x, int tiles_y, const uint32_t** out) {
+  std::lock_guard<std::mutex> g(g_order_lock);
+  auto& slot = g_orders[std::make_tuple(device, tiles_x, tiles_y)];
+  if (!slot) {
+    const int64_t n = (int64_t)tiles_x * tiles_y;
+    std::vector<uint32_t> order(n);
+    std::iota(order.begin(), order.end(), 0u);
+    std::vector<std::pair<int64_t, double>> key(n);
+    const double cx = 0.5 * (tiles_x - 1), cy = 0.5 * (tiles_y - 1);
+    for (int64_t t = 0; t < n; ++t) {
+      const double dx = (double)(t % tiles_x) - cx, dy = (double)(t / tiles_x) - cy;
+      key[t] = {(int64_t)std::floor(std::sqrt(dx * dx + dy * dy)), std::atan2(dy, dx)};
+    }
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return key[a] < key[b]; });
+    uint32_t* d = nullptr;
+    GRTX_HIP(hipMalloc(reinterpret_cast<void**>(&d), sizeof(uint32_t) * (size_t)n));
+    GRTX_HIP(hipMemcpy(d, order.data(), sizeof(uint32_t) * (size_t)n, hipMemcpyHostToDevice));
+    slot = d;
+  }
+  *out = slot;
+  return GRTX_OK;
+}
 
 template <int K, int LEAF>
 grtx_status launch(const TraceArgs& a, int blocks, hipStream_t s) {
@@ -985,21 +1023,28 @@ grtx_status launch_trace(const TraceScene& b, const grtx_rays* r, const grtx_tra
   a.cap_e = cap_e;
   a.chunk_len = ((a.n_work + 64 * kChunks - 1) / (64 * kChunks)) * 64;
   uint32_t* order_buf = nullptr;
-  if (r->kind && a.image_w > 0) {
-    const int64_t nt = a.n_work / 64;
-    GRTX_HIP(hipMallocAsync(reinterpret_cast<void**>(&order_buf), 3 * (size_t)nt * sizeof(uint32_t), s));
-    uint32_t* flag = order_buf;
-    uint32_t* pos = flag + nt;
-    uint32_t* order = pos + nt;
-    const unsigned g = (unsigned)((nt + 255) / 256);
-    hipLaunchKernelGGL(k_tile_heavy, dim3(g), dim3(256), 0, s, r->kind, a.image_w, a.image_h, a.tiles_x, nt, flag);
-    grtx_status st = exclusive_scan_u32(flag, pos, nt, s);
-    if (st != GRTX_OK) {
-      (void)hipFreeAsync(order_buf, s);
-      return st;
+  if (a.image_w > 0) {
+    const uint32_t* base = nullptr;
+    GRTX_TRY(centre_out_order(device, a.tiles_x, (int)(a.n_work / 64 / a.tiles_x), &base));
+    a.tile_order = base;
+    if (r->kind) {
+      // rays that go on past an object run longest: their tiles first
+      const int64_t nt = a.n_work / 64;
+      GRTX_HIP(hipMallocAsync(reinterpret_cast<void**>(&order_buf), 3 * (size_t)nt * sizeof(uint32_t), s));
+      uint32_t* flag = order_buf;
+      uint32_t* pos = flag + nt;
+      uint32_t* order = pos + nt;
+      const unsigned g = (unsigned)((nt + 255) / 256);
+      hipLaunchKernelGGL(k_tile_heavy, dim3(g), dim3(256), 0, s, r->kind, base, a.image_w, a.image_h, a.tiles_x, nt,
+                         flag);
+      grtx_status st = exclusive_scan_u32(flag, pos, nt, s);
+      if (st != GRTX_OK) {
+        (void)hipFreeAsync(order_buf, s);
+        return st;
+      }
+      hipLaunchKernelGGL(k_tile_order, dim3(g), dim3(256), 0, s, base, flag, pos, nt, order);
+      a.tile_order = order;
     }
-    hipLaunchKernelGGL(k_tile_order, dim3(g), dim3(256), 0, s, flag, pos, nt, order);
-    a.tile_order = order;
   }
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, pool->counter);
   const grtx_status st = leaf == kLeafTri ? launch_k<kLeafTri>(K, a, blocks, s)

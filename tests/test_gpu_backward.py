@@ -69,7 +69,7 @@ def test_gradients_match_oracle_finite_differences():
 
     s64 = _as64(scene)
     L0, ids0, nb0 = _loss_oracle(s64, o, d, target)
-    assert abs(L0 - float(loss)) < 1e-3 * max(1.0, abs(L0))
+    assert abs(L0 - float(loss.detach())) < 1e-3 * max(1.0, abs(L0))
     used = np.unique(np.concatenate([ids0[r, :nb0[r]] for r in range(len(nb0))]))
     assert used.size > 50
     rng = np.random.default_rng(0)
