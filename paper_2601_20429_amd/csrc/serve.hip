@@ -88,6 +88,7 @@ struct ReqDev {
   int64_t ray_offset;  // first batch ray of the request
   int32_t scene;
   int32_t tiled;       // rays in 8x8 tiles (width and height multiples of 8)
+  const uint32_t* order;  // tile processing order (centre-out) when tiled
   float* rgb;          // request outputs, row-major pixels
   float* depth;
   float* opacity;
@@ -105,7 +106,7 @@ __device__ __forceinline__ int find_request(const ReqDev* __restrict__ rq, int n
 __device__ __forceinline__ int64_t pixel_of(const ReqDev& q, int64_t j) {
   if (!q.tiled) return j;
   const int64_t tiles_x = q.width / 8;
-  const int64_t tile = j >> 6;
+  const int64_t tile = q.order[j >> 6];
   const int within = (int)(j & 63);
   const int64_t ty = tile / tiles_x, tx = tile - ty * tiles_x;
   return (ty * 8 + (within >> 3)) * q.width + tx * 8 + (within & 7);
@@ -312,6 +313,8 @@ grtx_status launch_batch(Server* sv, Server::Slot& slot, const std::vector<uint6
   for (size_t i = 0; i < rq.size(); ++i) {
     ReqDev& q = slot.table_host[i];
     camera_basis(rq[i].r, q);
+    q.order = nullptr;
+    if (q.tiled) GRTX_TRY(centre_out_order(sv->device, q.width / 8, q.height / 8, &q.order));
     q.ray_offset = off;
     q.scene = rq[i].r.scene_id;
     const int64_t n = rq[i].rays;

@@ -836,37 +836,6 @@ struct Pool {
 std::mutex g_pool_lock;
 std::map<std::pair<int, hipStream_t>, Pool> g_pools;
 
-// Centre-out tile order of an image: rings of tiles by distance from the image centre,
-// each ring by angle. Rays near the centre of an object-centred view cross the most
-// Gaussians; started first, they no longer set the end of the launch, and the tiles in
-// flight together stay one compact region. Computed once per (device, tile grid) on the
-// host and kept on the device until the process ends.
-std::mutex g_order_lock;
-std::map<std::tuple<int, int, int>, uint32_t*> g_orders;
-
-grtx_status centre_out_order(int device, int tiles_x, int tiles_y, const uint32_t** out) {
-  std::lock_guard<std::mutex> g(g_order_lock);
-  auto& slot = g_orders[std::make_tuple(device, tiles_x, tiles_y)];
-  if (!slot) {
-    const int64_t n = (int64_t)tiles_x * tiles_y;
-    std::vector<uint32_t> order(n);
-    std::iota(order.begin(), order.end(), 0u);
-    std::vector<std::pair<int64_t, double>> key(n);
-    const double cx = 0.5 * (tiles_x - 1), cy = 0.5 * (tiles_y - 1);
-    for (int64_t t = 0; t < n; ++t) {
-      const double dx = (double)(t % tiles_x) - cx, dy = (double)(t / tiles_x) - cy;
-      key[t] = {(int64_t)std::floor(std::sqrt(dx * dx + dy * dy)), std::atan2(dy, dx)};
-    }
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return key[a] < key[b]; });
-    uint32_t* d = nullptr;
-    GRTX_HIP(hipMalloc(reinterpret_cast<void**>(&d), sizeof(uint32_t) * (size_t)n));
-    GRTX_HIP(hipMemcpy(d, order.data(), sizeof(uint32_t) * (size_t)n, hipMemcpyHostToDevice));
-    slot = d;
-  }
-  *out = slot;
-  return GRTX_OK;
-}
-
 template <int K, int LEAF>
 grtx_status launch(const TraceArgs& a, int blocks, hipStream_t s) {
   if (a.stats)
@@ -906,6 +875,37 @@ grtx_status launch_k(int K, const TraceArgs& a, int blocks, hipStream_t s) {
 }
 
 }  // namespace
+
+// Centre-out tile order of an image: rings of tiles by distance from the image centre,
+// each ring by angle. Rays near the centre of an object-centred view cross the most
+// Gaussians; started first, they no longer set the end of the launch, and the tiles in
+// flight together stay one compact region. Computed once per (device, tile grid) on the
+// host and kept on the device until the process ends.
+std::mutex g_order_lock;
+std::map<std::tuple<int, int, int>, uint32_t*> g_orders;
+
+grtx_status centre_out_order(int device, int tiles_x, int tiles_y, const uint32_t** out) {
+  std::lock_guard<std::mutex> g(g_order_lock);
+  auto& slot = g_orders[std::make_tuple(device, tiles_x, tiles_y)];
+  if (!slot) {
+    const int64_t n = (int64_t)tiles_x * tiles_y;
+    std::vector<uint32_t> order(n);
+    std::iota(order.begin(), order.end(), 0u);
+    std::vector<std::pair<int64_t, double>> key(n);
+    const double cx = 0.5 * (tiles_x - 1), cy = 0.5 * (tiles_y - 1);
+    for (int64_t t = 0; t < n; ++t) {
+      const double dx = (double)(t % tiles_x) - cx, dy = (double)(t / tiles_x) - cy;
+      key[t] = {(int64_t)std::floor(std::sqrt(dx * dx + dy * dy)), std::atan2(dy, dx)};
+    }
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return key[a] < key[b]; });
+    uint32_t* d = nullptr;
+    GRTX_HIP(hipMalloc(reinterpret_cast<void**>(&d), sizeof(uint32_t) * (size_t)n));
+    GRTX_HIP(hipMemcpy(d, order.data(), sizeof(uint32_t) * (size_t)n, hipMemcpyHostToDevice));
+    slot = d;
+  }
+  *out = slot;
+  return GRTX_OK;
+}
 
 int64_t trace_pool_bytes(int K, int cap_d, int cap_e) {
   int device = 0, cus = 0;
