@@ -744,6 +744,35 @@ grtx_status radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t
 }
 
 // Root entry: the root's box and reference (internal node 0, or leaf 0 for one leaf).
+// Cut of the tree for per-tile cost estimates of image traces (the trace takes the
+// heaviest tiles first): every node of at most `cut` leaves whose parent has more (or that
+// is the root). Nodes are numbered internal first, then leaves, as in `parent`.
+__device__ __forceinline__ uint32_t leaves_below(int64_t i, int64_t nint, const uint2* __restrict__ range) {
+  return i < nint ? range[i].y - range[i].x + 1u : 1u;
+}
+
+__global__ void k_cut_flags(int64_t nn, int64_t nint, const uint32_t* __restrict__ parent,
+                            const uint2* __restrict__ range, uint32_t cut, uint32_t* __restrict__ flag) {
+  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i >= nn) return;
+  const uint32_t p = parent[i];
+  const bool big_parent = p == kNoParent || leaves_below(p, nint, range) > cut;
+  flag[i] = leaves_below(i, nint, range) <= cut && big_parent ? 1u : 0u;
+}
+
+// Records (lo xyz, leaf count) (hi xyz, 0) of the cut nodes, in node order, up to kCutCap.
+__global__ void k_cut_write(int64_t nn, int64_t nint, const uint32_t* __restrict__ flag,
+                            const uint32_t* __restrict__ pos, const uint2* __restrict__ range,
+                            const float* __restrict__ boxes, float4* __restrict__ cutrec, uint32_t* __restrict__ n_cut) {
+  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i >= nn) return;
+  if (i == nn - 1) *n_cut = pos[i] + flag[i];
+  if (!flag[i] || pos[i] >= (uint32_t)kCutCap) return;
+  const float* bx = boxes + 6 * i;
+  cutrec[2 * (int64_t)pos[i]] = make_float4(bx[0], bx[1], bx[2], (float)leaves_below(i, nint, range));
+  cutrec[2 * (int64_t)pos[i] + 1] = make_float4(bx[3], bx[4], bx[5], 0.f);
+}
+
 __global__ void k_write_root(const float* __restrict__ box, uint32_t ref, float* __restrict__ roots) {
   if (threadIdx.x < 6) roots[threadIdx.x] = box[threadIdx.x];
   if (threadIdx.x == 6) roots[6] = __uint_as_float(ref);
@@ -834,6 +863,8 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
   if (proxy) GRTX_TRY(dalloc(b, &b->tris, 3 * m));
   b->root_box = b->boxes;  // node 0: the root, or the only leaf when m == 1
   GRTX_TRY(dalloc(b, &b->roots, 8));
+  GRTX_TRY(dalloc(b, &b->cut, 2 * (size_t)kCutCap));
+  GRTX_TRY(dalloc(b, &b->n_cut, 1));
 
   Scratch sc{{}, s};
   float *partial = nullptr, *bounds = nullptr, *cent = nullptr, *tbox = nullptr;
@@ -890,6 +921,20 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, s, b->parent, 1, kNoParent);
   }
   hipLaunchKernelGGL(k_write_root, dim3(1), dim3(64), 0, s, b->root_box, m == 1 ? (kLeafFlag | 0u) : 0u, b->roots);
+  if (2 * m - 1 > (int64_t)kScanChunk * kScanChunk) {
+    // beyond one scan's reach: no cut, the trace keeps its centre-out order
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, s, b->n_cut, 1, 0u);
+  } else {
+    const int64_t nn = 2 * m - 1;
+    uint32_t *cflag = nullptr, *cpos = nullptr;
+    GRTX_TRY(sc.get(&cflag, nn));
+    GRTX_TRY(sc.get(&cpos, nn));
+    const uint32_t cut = (uint32_t)std::max<int64_t>(1, m / kCutDiv);
+    hipLaunchKernelGGL(k_cut_flags, dim3(grid_for(nn)), dim3(kBlock), 0, s, nn, nint, b->parent, range, cut, cflag);
+    GRTX_TRY(exclusive_scan_u32(cflag, cpos, nn, s));
+    hipLaunchKernelGGL(k_cut_write, dim3(grid_for(nn)), dim3(kBlock), 0, s, nn, nint, cflag, cpos, range, b->boxes,
+                       b->cut, b->n_cut);
+  }
   GRTX_LAUNCH_CHECK();
   return GRTX_OK;
 }

@@ -47,6 +47,10 @@ constexpr int kNodeF4 = 4;
 // For PROXY20 the instance records are stored in Gaussian order instead.
 constexpr uint32_t kLeafFlag = 0x80000000u;
 constexpr uint32_t kNoParent = 0xFFFFFFFFu;
+// Cut of the radix tree kept for cost estimates of image traces: the largest subtrees of at
+// most max(1, leaves / kCutDiv) leaves, at most kCutCap of them.
+constexpr int64_t kCutDiv = 2048;
+constexpr int kCutCap = 16384;
 constexpr uint32_t kNoChild = 0xFFFFFFFFu;
 // Default per-ray capacities of the checkpoint (deferred node) and eviction lists. A ray
 // that overflows one falls back to a restart-from-root round, which the other lanes of
@@ -77,6 +81,8 @@ struct Bvh {
   float* boxes = nullptr;    // [2 n_leaves - 1][6]
   float* root_box = nullptr; // device [6] (points into boxes)
   float* roots = nullptr;    // device [8]: root box, root reference bits, 0
+  float4* cut = nullptr;     // [kCutCap][2]: subtree boxes (lo, leaf count) (hi, 0), see k_cut_write
+  uint32_t* n_cut = nullptr; // device [1]: entries of `cut` (may exceed kCutCap; read the minimum)
   const float* opacities = nullptr; // borrowed
   const float* sh = nullptr;        // borrowed
   hipStream_t build_stream = nullptr;
@@ -140,6 +146,8 @@ struct TraceScene {
   const int32_t* ray_scene;
   grtx_bvh_kind kind;
   int64_t n_leaves;
+  const float4* cut = nullptr;      // subtree cut for tile cost estimates, or null
+  const uint32_t* n_cut = nullptr;
 };
 grtx_status launch_trace(const TraceScene& sc, const grtx_rays* r, const grtx_trace_params* p,
                          const grtx_trace_outputs* o, hipStream_t s);

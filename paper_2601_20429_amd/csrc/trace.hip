@@ -774,6 +774,47 @@ __global__ void k_reset_counter(unsigned int* c) {
   if (threadIdx.x < kChunks) c[threadIdx.x] = 0u;
 }
 
+// Per-tile cost estimate from the tree's subtree cut: the leaf counts of the cut subtrees
+// whose boxes the tile's centre ray crosses (how many Gaussians lie near the ray). A block
+// takes 16 tiles (positions of the base order); its 16 slices of threads share out the cut.
+// The key is the estimate's eighth-octave bucket, largest first, for a one-pass stable sort
+// that keeps the base order within a bucket.
+constexpr int kEstTiles = 16;
+__global__ void __launch_bounds__(256) k_tile_estimate(const float4* __restrict__ cut,
+                                                       const uint32_t* __restrict__ n_cut,
+                                                       const float* __restrict__ ro, const float* __restrict__ rd,
+                                                       int w, int h, int tiles_x, int64_t n_tiles,
+                                                       const uint32_t* __restrict__ base,
+                                                       uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  __shared__ float part[kEstTiles][256 / kEstTiles + 1];
+  const int ti = threadIdx.x % kEstTiles, sl = threadIdx.x / kEstTiles;
+  const int64_t i = blockIdx.x * (int64_t)kEstTiles + ti;
+  float acc = 0.f;
+  if (i < n_tiles) {
+    const int64_t t = base[i];
+    const int64_t ty = t / tiles_x, tx = t - ty * tiles_x;
+    const int64_t px = tx * 8 + 4 < w ? tx * 8 + 4 : w - 1, py = ty * 8 + 4 < h ? ty * 8 + 4 : h - 1;
+    const int64_t r = py * w + px;
+    const float ox = ro[3 * r], oy = ro[3 * r + 1], oz = ro[3 * r + 2];
+    const float ix = safe_inv(rd[3 * r]), iy = safe_inv(rd[3 * r + 1]), iz = safe_inv(rd[3 * r + 2]);
+    const int n = (int)min(*n_cut, (uint32_t)kCutCap);
+    for (int j = sl; j < n; j += 256 / kEstTiles) {
+      const float4 lo = cut[2 * j], hi = cut[2 * j + 1];
+      const Slab sb = slab(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, ox, oy, oz, ix, iy, iz);
+      if (sb.tn <= sb.tf && sb.tf >= 0.f) acc += lo.w;
+    }
+  }
+  part[ti][sl] = acc;
+  __syncthreads();
+  if (sl == 0 && i < n_tiles) {
+    float sum = 0.f;
+    for (int q = 0; q < 256 / kEstTiles; ++q) sum += part[ti][q];
+    const int b = min(255, (int)(8.f * log2f(1.f + sum)));
+    keys[i] = (uint64_t)(255 - b);
+    vals[i] = base[i];
+  }
+}
+
 // Tile order for rays that continue past an object: the tiles holding such rays go first.
 // Those rays run longest (two segments); started last, they would set the end of the
 // launch, while rows of tiles in image order keep neighbouring rays together.
@@ -919,7 +960,8 @@ int64_t trace_pool_bytes(int K, int cap_d, int cap_e) {
 
 grtx_status trace(const Bvh* b, const grtx_rays* r, const grtx_trace_params* p, const grtx_trace_outputs* o,
                   hipStream_t s) {
-  TraceScene sc{b->nodes, b->inst, b->tris, b->sh, b->sh_degree, b->roots, nullptr, b->kind, b->n_leaves};
+  TraceScene sc{b->nodes, b->inst, b->tris, b->sh, b->sh_degree, b->roots, nullptr, b->kind, b->n_leaves, b->cut,
+                b->n_cut};
   return launch_trace(sc, r, p, o, s);
 }
 
@@ -1024,20 +1066,36 @@ grtx_status launch_trace(const TraceScene& b, const grtx_rays* r, const grtx_tra
   a.chunk_len = ((a.n_work + 64 * kChunks - 1) / (64 * kChunks)) * 64;
   uint32_t* order_buf = nullptr;
   if (a.image_w > 0) {
+    // Tiles heaviest first, so that the longest rays do not start last: by estimated cost
+    // where the structure carries a subtree cut, centre-out within equal estimates.
+    const int64_t nt = a.n_work / 64;
     const uint32_t* base = nullptr;
-    GRTX_TRY(centre_out_order(device, a.tiles_x, (int)(a.n_work / 64 / a.tiles_x), &base));
+    GRTX_TRY(centre_out_order(device, a.tiles_x, (int)(nt / a.tiles_x), &base));
+    // scratch: estimate keys (8 B) and order (4 B) per tile, then three more words per tile
+    // for the continuation partition
+    GRTX_HIP(hipMallocAsync(reinterpret_cast<void**>(&order_buf), 6 * (size_t)nt * sizeof(uint32_t), s));
+    if (b.cut) {
+      uint64_t* keys = reinterpret_cast<uint64_t*>(order_buf);
+      uint32_t* est_order = order_buf + 2 * nt;
+      hipLaunchKernelGGL(k_tile_estimate, dim3((unsigned)((nt + kEstTiles - 1) / kEstTiles)), dim3(256), 0, s, b.cut,
+                         b.n_cut, r->origins, r->dirs, a.image_w, a.image_h, a.tiles_x, nt, base, keys, est_order);
+      grtx_status st = sort_by_key(keys, est_order, nt, 8, s);
+      if (st != GRTX_OK) {
+        (void)hipFreeAsync(order_buf, s);
+        return st;
+      }
+      base = est_order;
+    }
     a.tile_order = base;
     if (r->kind) {
       // rays that go on past an object run longest: their tiles first
-      const int64_t nt = a.n_work / 64;
-      GRTX_HIP(hipMallocAsync(reinterpret_cast<void**>(&order_buf), 3 * (size_t)nt * sizeof(uint32_t), s));
-      uint32_t* flag = order_buf;
+      uint32_t* flag = order_buf + 3 * nt;
       uint32_t* pos = flag + nt;
       uint32_t* order = pos + nt;
       const unsigned g = (unsigned)((nt + 255) / 256);
       hipLaunchKernelGGL(k_tile_heavy, dim3(g), dim3(256), 0, s, r->kind, base, a.image_w, a.image_h, a.tiles_x, nt,
                          flag);
-      grtx_status st = exclusive_scan_u32(flag, pos, nt, s);
+      const grtx_status st = exclusive_scan_u32(flag, pos, nt, s);
       if (st != GRTX_OK) {
         (void)hipFreeAsync(order_buf, s);
         return st;
