@@ -776,39 +776,55 @@ __global__ void k_reset_counter(unsigned int* c) {
 
 // Per-tile cost estimate from the tree's subtree cut: the leaf counts of the cut subtrees
 // whose boxes the tile's centre ray crosses (how many Gaussians lie near the ray). A block
-// takes 16 tiles (positions of the base order); its 16 slices of threads share out the cut.
-// The key is the estimate's eighth-octave bucket, largest first, for a one-pass stable sort
-// that keeps the base order within a bucket.
-constexpr int kEstTiles = 16;
+// takes kEstTiles tiles (positions of the base order) in slices of threads that share out
+// the cut, read in chunks through LDS. The key is the estimate's eighth-octave bucket,
+// largest first, for a one-pass stable sort that keeps the base order within a bucket.
+constexpr int kEstTiles = 8;
+constexpr int kEstSlices = 256 / kEstTiles;
 __global__ void __launch_bounds__(256) k_tile_estimate(const float4* __restrict__ cut,
                                                        const uint32_t* __restrict__ n_cut,
                                                        const float* __restrict__ ro, const float* __restrict__ rd,
                                                        int w, int h, int tiles_x, int64_t n_tiles,
                                                        const uint32_t* __restrict__ base,
                                                        uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  __shared__ float part[kEstTiles][256 / kEstTiles + 1];
+  __shared__ float4 s_cut[2 * 256];
+  __shared__ float part[kEstSlices][kEstTiles];
   const int ti = threadIdx.x % kEstTiles, sl = threadIdx.x / kEstTiles;
   const int64_t i = blockIdx.x * (int64_t)kEstTiles + ti;
-  float acc = 0.f;
+  float ox = 0.f, oy = 0.f, oz = 0.f, ix = 0.f, iy = 0.f, iz = 0.f;
   if (i < n_tiles) {
     const int64_t t = base[i];
     const int64_t ty = t / tiles_x, tx = t - ty * tiles_x;
     const int64_t px = tx * 8 + 4 < w ? tx * 8 + 4 : w - 1, py = ty * 8 + 4 < h ? ty * 8 + 4 : h - 1;
     const int64_t r = py * w + px;
-    const float ox = ro[3 * r], oy = ro[3 * r + 1], oz = ro[3 * r + 2];
-    const float ix = safe_inv(rd[3 * r]), iy = safe_inv(rd[3 * r + 1]), iz = safe_inv(rd[3 * r + 2]);
-    const int n = (int)min(*n_cut, (uint32_t)kCutCap);
-    for (int j = sl; j < n; j += 256 / kEstTiles) {
-      const float4 lo = cut[2 * j], hi = cut[2 * j + 1];
+    ox = ro[3 * r];
+    oy = ro[3 * r + 1];
+    oz = ro[3 * r + 2];
+    ix = safe_inv(rd[3 * r]);
+    iy = safe_inv(rd[3 * r + 1]);
+    iz = safe_inv(rd[3 * r + 2]);
+  }
+  const int n = (int)min(*n_cut, (uint32_t)kCutCap);
+  float acc = 0.f;
+  for (int c0 = 0; c0 < n; c0 += 256) {
+    const int m = min(256, n - c0);
+    __syncthreads();
+    if ((int)threadIdx.x < m) {
+      s_cut[2 * threadIdx.x] = cut[2 * (c0 + threadIdx.x)];
+      s_cut[2 * threadIdx.x + 1] = cut[2 * (c0 + threadIdx.x) + 1];
+    }
+    __syncthreads();
+    for (int j = sl; j < m; j += kEstSlices) {
+      const float4 lo = s_cut[2 * j], hi = s_cut[2 * j + 1];
       const Slab sb = slab(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, ox, oy, oz, ix, iy, iz);
       if (sb.tn <= sb.tf && sb.tf >= 0.f) acc += lo.w;
     }
   }
-  part[ti][sl] = acc;
+  part[sl][ti] = acc;
   __syncthreads();
   if (sl == 0 && i < n_tiles) {
     float sum = 0.f;
-    for (int q = 0; q < 256 / kEstTiles; ++q) sum += part[ti][q];
+    for (int q = 0; q < kEstSlices; ++q) sum += part[q][ti];
     const int b = min(255, (int)(8.f * log2f(1.f + sum)));
     keys[i] = (uint64_t)(255 - b);
     vals[i] = base[i];
