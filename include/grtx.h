@@ -85,10 +85,16 @@ typedef struct grtx_gaussians {
 
 /* alpha_min: each Gaussian is bounded by the ellipsoid on which o*G = alpha_min, i.e.
  * Mahalanobis radius rho = sqrt(2 ln(o/alpha_min)); Gaussians with o <= alpha_min are
- * never hit. Must be in (0, 1). */
+ * never hit. Must be in (0, 1).
+ * plain_lbvh: nonzero keeps the radix tree exactly as the LBVH construction gives it (the
+ * topology grtx_bvh_export_topology then reports is the plain Karras tree of the sorted
+ * Morton codes); 0 (default) rebuilds small treelets of it bottom-up into the topology of
+ * least surface-area cost. Leaves keep their sorted order either way, and traced results
+ * are identical; only the internal nodes, and so the work per ray, differ. */
 typedef struct grtx_build_params {
   float alpha_min;
-  int32_t reserved[3];
+  int32_t plain_lbvh;
+  int32_t reserved[2];
 } grtx_build_params;
 
 typedef struct grtx_bvh grtx_bvh;
@@ -196,7 +202,8 @@ typedef struct grtx_camera {
 } grtx_camera;
 
 /* Build the acceleration structure (LBVH: Morton codes of the means, stable radix
- * sort, radix tree, bottom-up refit) over `g`. Enqueued on `stream`; the handle may be
+ * sort, radix tree, bottom-up refit, then, unless p->plain_lbvh, one bottom-up pass of
+ * treelet restructuring) over `g`. Enqueued on `stream`; the handle may be
  * used for grtx_trace on the same stream right away. On success *out receives a new
  * handle (free it with grtx_bvh_destroy). */
 grtx_status grtx_build(const grtx_gaussians* g, grtx_bvh_kind kind, const grtx_build_params* p,

@@ -56,7 +56,8 @@ grtx_status grtx_build(const grtx_gaussians* g, grtx_bvh_kind kind, const grtx_b
     set_error("grtx_build: host allocation failed");
     return GRTX_ERR_OUT_OF_MEMORY;
   }
-  grtx_status st = grtx::build_bvh(g, kind, p->alpha_min, static_cast<hipStream_t>(stream), &h->impl);
+  grtx_status st =
+      grtx::build_bvh(g, kind, p->alpha_min, p->plain_lbvh == 0, static_cast<hipStream_t>(stream), &h->impl);
   if (st != GRTX_OK) {
     char msg[1024];
     std::strncpy(msg, grtx::g_err, sizeof msg - 1);

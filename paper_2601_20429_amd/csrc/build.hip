@@ -744,15 +744,296 @@ grtx_status radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t
 }
 
 // Root entry: the root's box and reference (internal node 0, or leaf 0 for one leaf).
+// ------------------------------------------------------------------ treelet restructuring
+// One bottom-up pass over the radix tree that rebuilds, at every internal node, the
+// treelet of the node and its largest descendants (up to kTreeletLeaves treelet leaves,
+// opened by largest surface area) into the binary topology of least surface-area cost,
+// found by dynamic programming over the subsets of the treelet leaves (restructuring after
+// Karras and Aila's treelet optimisation). Leaves keep their sorted positions, so the
+// leaf order of the instances and every traced result are unchanged; only internal nodes
+// are rewired, each keeping its index. A node is processed by the second of the two
+// threads that reach it from its children, after both subtrees are final.
+constexpr int kTreeletLeaves = 5;
+constexpr float kCostNode = 1.2f;  // surface-area cost of visiting an internal node
+constexpr float kCostLeaf = 1.f;   // ... of testing a leaf
+
+__device__ __forceinline__ float half_area(const float* __restrict__ b) {
+  const float ex = fmaxf(b[3] - b[0], 0.f), ey = fmaxf(b[4] - b[1], 0.f), ez = fmaxf(b[5] - b[2], 0.f);
+  return ex * ey + ey * ez + ez * ex;
+}
+
+__device__ __forceinline__ uint32_t node_of(uint32_t c, int64_t nint) {
+  return (c & kLeafFlag) ? (uint32_t)(nint + (c & ~kLeafFlag)) : c;
+}
+__device__ __forceinline__ uint32_t ref_of(uint32_t u, int64_t nint) {
+  return (int64_t)u >= nint ? kLeafFlag | (uint32_t)(u - nint) : u;
+}
+
+// Per-thread work arrays of the subset dynamic programme live in LDS, entry-major
+// ([entry][thread]), so that lanes index them independently.
+constexpr int kSubtreeLeaves = 256;
+constexpr int kSets = 1 << kTreeletLeaves;
+struct TreeletLds {
+  float copt[kSets][kSubtreeLeaves];
+  uint8_t split[kSets][kSubtreeLeaves];
+  int stack_set[kTreeletLeaves][kSubtreeLeaves];
+  uint32_t stack_node[kTreeletLeaves][kSubtreeLeaves];
+};
+
+// Subset dynamic programme over NL treelet leaves, unrolled at compile time so that every
+// subset and split index is a constant (the costs stay in registers); the chosen splits and
+// costs then go to the thread's LDS column for the rebuild.
+template <int NL>
+__device__ __forceinline__ void treelet_dp(const float (&lb)[kTreeletLeaves][6], const float (&lcost)[kTreeletLeaves],
+                                           TreeletLds& L, int tid) {
+  float copt[1 << NL];
+#pragma unroll
+  for (int S = 1; S < (1 << NL); ++S) {
+    if ((S & (S - 1)) == 0) {
+      copt[S] = lcost[__builtin_ctz(S)];
+      L.copt[S][tid] = copt[S];
+      continue;
+    }
+    float b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+    for (int q = 0; q < NL; ++q)
+      if (S >> q & 1) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          b[a] = fminf(b[a], lb[q][a]);
+          b[3 + a] = fmaxf(b[3 + a], lb[q][3 + a]);
+        }
+      }
+    float best = INFINITY;
+    int bp = 0;
+#pragma unroll
+    for (int P = 1; P < S; ++P) {
+      if ((P & S) != P || !(P & S & -S)) continue;  // each split once: the part holding the lowest leaf
+      const float c = copt[P] + copt[S ^ P];
+      if (c < best) {
+        best = c;
+        bp = P;
+      }
+    }
+    copt[S] = kCostNode * half_area(b) + best;
+    L.copt[S][tid] = copt[S];
+    L.split[S][tid] = (uint8_t)bp;
+  }
+}
+
+__device__ void restructure(uint32_t p, int64_t nint, uint32_t* __restrict__ child, uint32_t* __restrict__ parent,
+                            float* __restrict__ boxes, float* __restrict__ cost, uint32_t* __restrict__ count,
+                            TreeletLds& L, int tid) {
+  // treelet leaves (registers, constant indices only) and its internal nodes
+  uint32_t leaf[kTreeletLeaves], inner[kTreeletLeaves - 1];
+  float larea[kTreeletLeaves];
+#pragma unroll
+  for (int q = 0; q < kTreeletLeaves; ++q) {
+    leaf[q] = 0u;
+    larea[q] = -1.f;
+  }
+#pragma unroll
+  for (int q = 0; q < kTreeletLeaves - 1; ++q) inner[q] = p;
+  int nl = 2;
+  leaf[0] = node_of(child[2 * (int64_t)p], nint);
+  leaf[1] = node_of(child[2 * (int64_t)p + 1], nint);
+  larea[0] = half_area(boxes + 6 * (int64_t)leaf[0]);
+  larea[1] = half_area(boxes + 6 * (int64_t)leaf[1]);
+#pragma unroll
+  for (int step = 0; step < kTreeletLeaves - 2; ++step) {
+    // open the internal treelet leaf of largest surface area
+    int best = -1;
+    float ba = -1.f;
+#pragma unroll
+    for (int q = 0; q < kTreeletLeaves; ++q)
+      if (q < nl && (int64_t)leaf[q] < nint && larea[q] > ba) {
+        ba = larea[q];
+        best = q;
+      }
+    if (best < 0) break;
+    uint32_t x = 0u;
+#pragma unroll
+    for (int q = 0; q < kTreeletLeaves; ++q)
+      if (q == best) x = leaf[q];
+    inner[step + 1] = x;
+    const uint32_t c0 = node_of(child[2 * (int64_t)x], nint), c1 = node_of(child[2 * (int64_t)x + 1], nint);
+    const float a0 = half_area(boxes + 6 * (int64_t)c0), a1 = half_area(boxes + 6 * (int64_t)c1);
+#pragma unroll
+    for (int q = 0; q < kTreeletLeaves; ++q) {
+      if (q == best) {
+        leaf[q] = c0;
+        larea[q] = a0;
+      }
+      if (q == nl) {
+        leaf[q] = c1;
+        larea[q] = a1;
+      }
+    }
+    ++nl;
+  }
+  // the treelet leaves' boxes, counts and costs, read once
+  float lb[kTreeletLeaves][6];
+  uint32_t lcnt[kTreeletLeaves];
+  float lcost[kTreeletLeaves];
+#pragma unroll
+  for (int q = 0; q < kTreeletLeaves; ++q) {
+    if (q < nl) {
+      const float* bq = boxes + 6 * (int64_t)leaf[q];
+#pragma unroll
+      for (int a = 0; a < 6; ++a) lb[q][a] = bq[a];
+      lcnt[q] = (int64_t)leaf[q] >= nint ? 1u : count[leaf[q]];
+      lcost[q] = cost[leaf[q]];
+    } else {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        lb[q][a] = INFINITY;
+        lb[q][3 + a] = -INFINITY;
+      }
+      lcnt[q] = 0u;
+      lcost[q] = 0.f;
+    }
+  }
+  auto set_box = [&](int S, float b[6]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      b[a] = INFINITY;
+      b[3 + a] = -INFINITY;
+    }
+#pragma unroll
+    for (int q = 0; q < kTreeletLeaves; ++q)
+      if (S >> q & 1) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          b[a] = fminf(b[a], lb[q][a]);
+          b[3 + a] = fmaxf(b[3 + a], lb[q][3 + a]);
+        }
+      }
+  };
+  // optimal cost of every subset of the treelet leaves and the split that reaches it
+  const int full = (1 << nl) - 1;
+  if (nl == kTreeletLeaves) treelet_dp<kTreeletLeaves>(lb, lcost, L, tid);
+  else if (nl == 4) treelet_dp<4>(lb, lcost, L, tid);
+  else if (nl == 3) treelet_dp<3>(lb, lcost, L, tid);
+  else treelet_dp<2>(lb, lcost, L, tid);
+  // rebuild top-down, reusing the treelet's internal nodes (p stays the root)
+  int sp = 0, next = 1;
+  L.stack_set[0][tid] = full;
+  L.stack_node[0][tid] = p;
+  sp = 1;
+  while (sp > 0) {
+    --sp;
+    const int S = L.stack_set[sp][tid];
+    const uint32_t node = L.stack_node[sp][tid];
+    const int P = L.split[S][tid];
+    for (int k = 0; k < 2; ++k) {
+      const int X = k == 0 ? P : S ^ P;
+      uint32_t c = 0u;
+      if ((X & (X - 1)) == 0) {
+#pragma unroll
+        for (int q = 0; q < kTreeletLeaves; ++q)
+          if (X == (1 << q)) c = leaf[q];
+      } else {
+#pragma unroll
+        for (int q = 1; q < kTreeletLeaves - 1; ++q)
+          if (q == next) c = inner[q];
+        ++next;
+        L.stack_set[sp][tid] = X;
+        L.stack_node[sp][tid] = c;
+        ++sp;
+      }
+      child[2 * (int64_t)node + k] = ref_of(c, nint);
+      parent[c] = node;
+    }
+    float b[6];
+    set_box(S, b);
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int q = 0; q < kTreeletLeaves; ++q)
+      if (S >> q & 1) cnt += lcnt[q];
+    float* nb = boxes + 6 * (int64_t)node;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) nb[a] = b[a];
+    cost[node] = L.copt[S][tid];
+    count[node] = cnt;
+  }
+}
+
+// The pass runs per subtree of at most kSubtreeLeaves leaves whose parent has more (the
+// nodes above keep the radix tree's topology): one workgroup takes a subtree, its threads
+// its leaves (a contiguous run [lo, hi] of sorted positions). The subtree's internal nodes
+// are exactly the indices lo..hi-1 of the radix tree (each internal node is numbered after
+// one end of its range), and restructuring only permutes them, so the arrival counters of
+// the bottom-up hand-over sit in LDS at index - lo, ordered with workgroup-scope fences.
+// Workgroups draw subtrees from a queue.
+__global__ void __launch_bounds__(kSubtreeLeaves) k_treelet(int64_t m, const uint32_t* __restrict__ roots,
+                                                            const uint32_t* __restrict__ n_roots,
+                                                            unsigned int* __restrict__ queue,
+                                                            const uint2* __restrict__ range, uint32_t* child,
+                                                            uint32_t* parent, float* boxes, float* cost,
+                                                            uint32_t* count) {
+  __shared__ TreeletLds L;
+  __shared__ uint32_t s_item;
+  __shared__ uint32_t s_arrive[kSubtreeLeaves];
+  const int64_t nint = m - 1;
+  const uint32_t nr = *n_roots;
+  const int tid = threadIdx.x;
+  while (true) {
+    if (tid == 0) s_item = atomicAdd(queue, 1u);
+    __syncthreads();
+    const uint32_t item = s_item;
+    __syncthreads();
+    if (item >= nr) return;
+    const uint32_t r = roots[item];
+    const int64_t lo = (int64_t)r < nint ? (int64_t)range[r].x : (int64_t)r - nint;
+    const int64_t n = (int64_t)r < nint ? (int64_t)range[r].y - range[r].x + 1 : 1;
+    s_arrive[tid] = 0u;
+    __syncthreads();
+    if ((int64_t)tid < n) {
+      const uint32_t u = (uint32_t)(nint + lo + tid);
+      cost[u] = kCostLeaf * half_area(boxes + 6 * (int64_t)u);
+      if (u != r) {
+        uint32_t p = parent[u];
+        while (true) {
+          // the first thread to arrive leaves; the second sees both subtrees
+          if ((uint64_t)((int64_t)p - lo) >= (uint64_t)kSubtreeLeaves) break;  // outside the run: never
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+          if (atomicAdd(&s_arrive[p - lo], 1u) == 0u) break;
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+          restructure(p, nint, child, parent, boxes, cost, count, L, tid);
+          if (p == r) break;
+          p = parent[p];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Subtree roots for the restructuring pass: nodes of at most `limit` leaves whose parent
+// has more (or that are the root), listed in node order.
+__global__ void k_subtree_roots(int64_t nn, const uint32_t* __restrict__ flag, const uint32_t* __restrict__ pos,
+                                uint32_t* __restrict__ roots, uint32_t* __restrict__ n_roots) {
+  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i >= nn) return;
+  if (i == nn - 1) *n_roots = pos[i] + flag[i];
+  if (flag[i]) roots[pos[i]] = (uint32_t)i;
+}
+
+__global__ void __launch_bounds__(kBlock) k_range_count(int64_t nint, const uint2* __restrict__ range,
+                                                        uint32_t* __restrict__ count) {
+  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i < nint) count[i] = range[i].y - range[i].x + 1u;
+}
+
 // Cut of the tree for per-tile cost estimates of image traces (the trace takes the
 // heaviest tiles first): every node of at most `cut` leaves whose parent has more (or that
 // is the root). Nodes are numbered internal first, then leaves, as in `parent`.
-__device__ __forceinline__ uint32_t leaves_below(int64_t i, int64_t nint, const uint2* __restrict__ range) {
-  return i < nint ? range[i].y - range[i].x + 1u : 1u;
+__device__ __forceinline__ uint32_t leaves_below(int64_t i, int64_t nint, const uint32_t* __restrict__ count) {
+  return i < nint ? count[i] : 1u;
 }
 
 __global__ void k_cut_flags(int64_t nn, int64_t nint, const uint32_t* __restrict__ parent,
-                            const uint2* __restrict__ range, uint32_t cut, uint32_t* __restrict__ flag) {
+                            const uint32_t* __restrict__ range, uint32_t cut, uint32_t* __restrict__ flag) {
   const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   if (i >= nn) return;
   const uint32_t p = parent[i];
@@ -762,7 +1043,7 @@ __global__ void k_cut_flags(int64_t nn, int64_t nint, const uint32_t* __restrict
 
 // Records (lo xyz, leaf count) (hi xyz, 0) of the cut nodes, in node order, up to kCutCap.
 __global__ void k_cut_write(int64_t nn, int64_t nint, const uint32_t* __restrict__ flag,
-                            const uint32_t* __restrict__ pos, const uint2* __restrict__ range,
+                            const uint32_t* __restrict__ pos, const uint32_t* __restrict__ range,
                             const float* __restrict__ boxes, float4* __restrict__ cutrec, uint32_t* __restrict__ n_cut) {
   const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   if (i >= nn) return;
@@ -837,7 +1118,8 @@ static Ico make_icosahedron() {
   return ico;
 }
 
-grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_min, hipStream_t s, Bvh* b) {
+grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_min, bool restructure_tree,
+                      hipStream_t s, Bvh* b) {
   b->kind = kind;
   b->n_gauss = g->count;
   b->sh_degree = g->sh_degree;
@@ -878,9 +1160,12 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
   GRTX_TRY(sc.get(&tvals, m));
   uint2* range = nullptr;
   uint32_t* ready = nullptr;
+  uint32_t* count = nullptr;  // leaves below each internal node
+  float* sah = nullptr;       // surface-area cost of each node's subtree (restructuring)
   GRTX_TRY(sc.get(&arrivals, nint + 1));  // per internal node, then the ready-list length
   GRTX_TRY(sc.get(&range, std::max<int64_t>(nint, 1)));
   GRTX_TRY(sc.get(&ready, std::max<int64_t>(nint, 1)));
+  GRTX_TRY(sc.get(&count, std::max<int64_t>(nint, 1)));
   const float* points = g->means;
   if (proxy) {
     GRTX_TRY(sc.get(&cent, 3 * m));
@@ -916,6 +1201,26 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
                        ready, arrivals + nint);
     hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(kTopBlock), 0, s, m, b->child, b->parent, range, b->boxes,
                        ready, arrivals + nint, arrivals);
+    hipLaunchKernelGGL(k_range_count, dim3(grid_for(nint)), dim3(kBlock), 0, s, nint, range, count);
+    if (restructure_tree && nint > 1 && 2 * m - 1 <= (int64_t)kScanChunk * kScanChunk) {
+      const int64_t nn = 2 * m - 1;
+      uint32_t *rflag = nullptr, *rpos = nullptr, *roots = nullptr, *nroots = nullptr;
+      GRTX_TRY(sc.get(&sah, nn));
+      GRTX_TRY(sc.get(&rflag, nn));
+      GRTX_TRY(sc.get(&rpos, nn));
+      GRTX_TRY(sc.get(&roots, m));
+      GRTX_TRY(sc.get(&nroots, 2));  // count, then the work queue
+      hipLaunchKernelGGL(k_cut_flags, dim3(grid_for(nn)), dim3(kBlock), 0, s, nn, nint, b->parent, count,
+                         (uint32_t)kSubtreeLeaves, rflag);
+      GRTX_TRY(exclusive_scan_u32(rflag, rpos, nn, s));
+      hipLaunchKernelGGL(k_subtree_roots, dim3(grid_for(nn)), dim3(kBlock), 0, s, nn, rflag, rpos, roots, nroots);
+      hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, s, nroots + 1, 1, 0u);
+      int dev = 0, cus = 0;
+      GRTX_HIP(hipGetDevice(&dev));
+      GRTX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+      hipLaunchKernelGGL(k_treelet, dim3(std::max(1, 4 * cus)), dim3(kSubtreeLeaves), 0, s, m, roots, nroots,
+                         nroots + 1, range, b->child, b->parent, b->boxes, sah, count);
+    }
     hipLaunchKernelGGL(k_wide, dim3(grid_for(nint)), dim3(kBlock), 0, s, m, b->child, b->boxes, b->nodes);
   } else {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, s, b->parent, 1, kNoParent);
@@ -930,9 +1235,9 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
     GRTX_TRY(sc.get(&cflag, nn));
     GRTX_TRY(sc.get(&cpos, nn));
     const uint32_t cut = (uint32_t)std::max<int64_t>(1, m / kCutDiv);
-    hipLaunchKernelGGL(k_cut_flags, dim3(grid_for(nn)), dim3(kBlock), 0, s, nn, nint, b->parent, range, cut, cflag);
+    hipLaunchKernelGGL(k_cut_flags, dim3(grid_for(nn)), dim3(kBlock), 0, s, nn, nint, b->parent, count, cut, cflag);
     GRTX_TRY(exclusive_scan_u32(cflag, cpos, nn, s));
-    hipLaunchKernelGGL(k_cut_write, dim3(grid_for(nn)), dim3(kBlock), 0, s, nn, nint, cflag, cpos, range, b->boxes,
+    hipLaunchKernelGGL(k_cut_write, dim3(grid_for(nn)), dim3(kBlock), 0, s, nn, nint, cflag, cpos, count, b->boxes,
                        b->cut, b->n_cut);
   }
   GRTX_LAUNCH_CHECK();

@@ -126,7 +126,8 @@ void clear_error();
 // ---------------------------------------------------------------------------------------
 // Host entry points implemented in the .hip sources
 // ---------------------------------------------------------------------------------------
-grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_min, hipStream_t s, Bvh* b);
+grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_min, bool restructure_tree,
+                      hipStream_t s, Bvh* b);
 grtx_status export_topology(const Bvh* b, uint32_t* child, uint32_t* parent, uint64_t* morton, uint32_t* perm,
                             float* boxes, hipStream_t s);
 grtx_status pinhole_rays(const grtx_camera* cam, float* origins, float* dirs, hipStream_t s);

@@ -47,7 +47,7 @@ class _Gaussians(C.Structure):
 
 
 class _BuildParams(C.Structure):
-    _fields_ = [("alpha_min", C.c_float), ("reserved", C.c_int32 * 3)]
+    _fields_ = [("alpha_min", C.c_float), ("plain_lbvh", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class _BvhInfo(C.Structure):
@@ -246,10 +246,13 @@ class Bvh:
         return dict(child=child[:m], parent=parent[:m + n], morton=morton[:n], perm=perm[:n], boxes=boxes[:m + n])
 
 
-def build(scene: SceneTensors, kind: int = SPHERE_INSTANCE, alpha_min: float = 1.0 / 255.0, stream=None) -> Bvh:
+def build(scene: SceneTensors, kind: int = SPHERE_INSTANCE, alpha_min: float = 1.0 / 255.0, stream=None,
+          plain_lbvh: bool = False) -> Bvh:
+    """grtx_build. plain_lbvh keeps the radix tree as the LBVH construction gives it (no
+    treelet restructuring); traced results are the same either way."""
     g = _Gaussians(scene.means.data_ptr(), scene.scales.data_ptr(), scene.quats.data_ptr(),
                    scene.opacities.data_ptr(), scene.sh.data_ptr(), scene.n, scene.sh_degree, 0)
-    p = _BuildParams(alpha_min)
+    p = _BuildParams(alpha_min, 1 if plain_lbvh else 0)
     h = C.c_void_p()
     _check(lib().grtx_build(C.byref(g), kind, C.byref(p), _stream(stream), C.byref(h)))
     return Bvh(h, scene, kind, alpha_min)

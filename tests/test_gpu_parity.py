@@ -37,9 +37,9 @@ def dev(a, dtype=torch.float32):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
 
 
-def build(scene, kind=grtx.SPHERE_INSTANCE):
+def build(scene, kind=grtx.SPHERE_INSTANCE, plain_lbvh=False):
     st = grtx.SceneTensors.from_scene(scene, "cuda")
-    return grtx.build(st, kind=kind, alpha_min=AMIN)
+    return grtx.build(st, kind=kind, alpha_min=AMIN, plain_lbvh=plain_lbvh)
 
 
 def render(bvh, o, d, k=16, mode=grtx.CHECKPOINT, cap=256, **kw):
@@ -69,7 +69,7 @@ def test_topology_bit_exact(case):
         if case.startswith("dups"):
             means[::3] = means[0]
         scene = make_scene(means, [0.05] * 3, quats=rng.standard_normal((n, 4)), opac=0.5)
-    bvh = build(scene)
+    bvh = build(scene, plain_lbvh=True)
     t = bvh.export_topology()
     torch.cuda.synchronize()
     ref = oracle.lbvh_topology(scene.means)
@@ -81,6 +81,81 @@ def test_topology_bit_exact(case):
     assert (t["parent"].cpu().numpy().view(np.uint32) == ref["parent"]).all()
     info = bvh.info()
     assert info["leaves"] == n and info["internal_nodes"] == max(n - 1, 0)
+
+
+def _check_tree(t, n):
+    """A valid binary tree over n leaves: every node but the root is the child of exactly
+    one internal node, parents agree, and every internal box is the exact union of its
+    children's boxes. Returns the surface-area cost (internal 1.2 x area, leaf 1.0 x area)
+    relative to the root's area."""
+    child = t["child"].cpu().numpy().view(np.uint32).astype(np.int64)
+    parent = t["parent"].cpu().numpy().view(np.uint32).astype(np.int64)
+    boxes = t["boxes"].cpu().numpy().astype(np.float64)
+    nint = n - 1
+    uid = np.where(child & 0x80000000, nint + (child & 0x7FFFFFFF), child)
+    seen = np.bincount(uid.ravel(), minlength=nint + n)
+    assert seen[0] == 0 and (seen[1:] == 1).all()
+    for k in range(2):
+        assert (parent[uid[:, k]] == np.arange(nint)).all()
+    assert parent[0] == 0xFFFFFFFF
+    lo = np.minimum(boxes[uid[:, 0], :3], boxes[uid[:, 1], :3])
+    hi = np.maximum(boxes[uid[:, 0], 3:], boxes[uid[:, 1], 3:])
+    assert (boxes[:nint, :3] == lo).all() and (boxes[:nint, 3:] == hi).all()
+    e = np.maximum(boxes[:, 3:] - boxes[:, :3], 0)
+    area = e[:, 0] * e[:, 1] + e[:, 1] * e[:, 2] + e[:, 2] * e[:, 0]
+    return (1.2 * area[:nint].sum() + area[nint:].sum()) / area[0]
+
+
+@pytest.mark.parametrize("case", ["n2", "n3", "n5", "n100", "dups257", "plain1k", "scene100k", "proxy2k"])
+def test_restructured_tree_valid_and_cheaper(case):
+    """Treelet restructuring keeps a valid tree over the same sorted leaves (Morton codes
+    and permutation unchanged), with exact boxes, and never raises the surface-area cost."""
+    say("restructured tree", case)
+    kind = grtx.SPHERE_INSTANCE
+    if case == "plain1k":
+        scene = inputs.small_scene(1, 1000)
+    elif case == "scene100k":
+        scene = inputs.cluster_scene(2, 100_000, 0)
+    elif case == "proxy2k":
+        scene, kind = inputs.cluster_scene(2, 2000, 0), grtx.PROXY20
+    else:
+        n = int(case[1:] if case[0] == "n" else case[4:])
+        rng = np.random.default_rng(n)
+        means = rng.uniform(-1, 1, (n, 3))
+        if case.startswith("dups"):
+            means[::3] = means[0]
+        scene = make_scene(means, [0.05] * 3, quats=rng.standard_normal((n, 4)), opac=0.5)
+    a = build(scene, kind, plain_lbvh=True)
+    b = build(scene, kind)
+    ta, tb = a.export_topology(), b.export_topology()
+    torch.cuda.synchronize()
+    n = a.info()["leaves"]
+    assert torch.equal(ta["morton"], tb["morton"]) and torch.equal(ta["perm"], tb["perm"])
+    assert torch.equal(ta["boxes"][n - 1:], tb["boxes"][n - 1:])  # leaf boxes
+    ca, cb = _check_tree(ta, n), _check_tree(tb, n)
+    assert cb <= ca * (1 + 1e-6), (ca, cb)
+    say(dict(case=case, sah_plain=round(ca, 2), sah_restructured=round(cb, 2)))
+
+
+@pytest.mark.parametrize("kind", [grtx.SPHERE_INSTANCE, grtx.PROXY20, grtx.ICO_INSTANCE])
+def test_restructured_tree_renders_identically(kind):
+    """Results do not depend on the tree: the plain radix tree and the restructured one
+    give bit-identical outputs and hit lists, in both modes."""
+    say("restructured renders", kind)
+    scene = inputs.cluster_scene(2, 20_000 if kind == grtx.PROXY20 else 100_000, 3)
+    cam = inputs.orbit_camera(160, 120)
+    o, d = grtx.pinhole_rays(cam)
+    a = build(scene, kind, plain_lbvh=True)
+    b = build(scene, kind)
+    for mode in (grtx.CHECKPOINT, grtx.RESTART):
+        ra = grtx.trace(a, o, d, k=8, T_min=T_MIN, mode=mode, image_width=cam.width, hit_capacity=128, stats=True)
+        rb = grtx.trace(b, o, d, k=8, T_min=T_MIN, mode=mode, image_width=cam.width, hit_capacity=128, stats=True)
+        torch.cuda.synchronize()
+        for key in ("rgb", "depth", "opacity", "hit_ids", "hit_counts"):
+            assert torch.equal(ra[key], rb[key]), (mode, key)
+        fa = int(ra["stats"][:, grtx.STAT_NODES].sum())
+        fb = int(rb["stats"][:, grtx.STAT_NODES].sum())
+        say(dict(mode=mode, node_fetches_plain=fa, node_fetches_restructured=fb))
 
 
 def test_boxes_conservative_and_tight():
@@ -410,7 +485,7 @@ def test_proxy_topology_and_boxes():
     say("proxy topology")
     from tests.test_oracle_pins import _check_radix_tree
     scene = inputs.cluster_scene(5, 400, 0)
-    bvh = build(scene, grtx.PROXY20)
+    bvh = build(scene, grtx.PROXY20, plain_lbvh=True)
     t = bvh.export_topology()
     m = 20 * scene.n
     codes = t["morton"].cpu().numpy().view(np.uint64)
