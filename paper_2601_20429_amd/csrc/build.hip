@@ -821,7 +821,7 @@ __device__ __forceinline__ void treelet_dp(const float (&lb)[kTreeletLeaves][6],
   }
 }
 
-__device__ void restructure(uint32_t p, int64_t nint, uint32_t* __restrict__ child, uint32_t* __restrict__ parent,
+__device__ __forceinline__ void restructure(uint32_t p, int64_t nint, uint32_t* __restrict__ child, uint32_t* __restrict__ parent,
                             float* __restrict__ boxes, float* __restrict__ cost, uint32_t* __restrict__ count,
                             TreeletLds& L, int tid) {
   // treelet leaves (registers, constant indices only) and its internal nodes
@@ -1006,6 +1006,30 @@ __global__ void __launch_bounds__(kSubtreeLeaves) k_treelet(int64_t m, const uin
       }
     }
     __syncthreads();
+  }
+}
+
+// The nodes above the subtrees, in a second pass for trees of more than kTopPassLeaves
+// leaves (below that the top part is a few hundred nodes and the pass costs more than it
+// saves): a thread per subtree root walks up, the second arrival at a node restructures
+// it. Threads of different workgroups hand over here, so the counters are agent-scope
+// atomics in global memory.
+constexpr int64_t kTopPassLeaves = (int64_t)1 << 20;
+__global__ void __launch_bounds__(kSubtreeLeaves) k_treelet_top(int64_t m, const uint32_t* __restrict__ roots,
+                                                                const uint32_t* __restrict__ n_roots,
+                                                                uint32_t* child, uint32_t* parent, float* boxes,
+                                                                float* cost, uint32_t* count,
+                                                                uint32_t* arrivals) {
+  __shared__ TreeletLds L;
+  const int tid = threadIdx.x;
+  const int64_t k = blockIdx.x * (int64_t)kSubtreeLeaves + tid;
+  if (k >= (int64_t)*n_roots) return;
+  const int64_t nint = m - 1;
+  uint32_t p = parent[roots[k]];
+  while (p != kNoParent) {
+    if (__hip_atomic_fetch_add(arrivals + p, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 0u) return;
+    restructure(p, nint, child, parent, boxes, cost, count, L, tid);
+    p = parent[p];
   }
 }
 
@@ -1220,6 +1244,12 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
       GRTX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
       hipLaunchKernelGGL(k_treelet, dim3(std::max(1, 4 * cus)), dim3(kSubtreeLeaves), 0, s, m, roots, nroots,
                          nroots + 1, range, b->child, b->parent, b->boxes, sah, count);
+      if (m > kTopPassLeaves) {
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nint + 1)), dim3(kBlock), 0, s, arrivals, nint + 1, 0u);
+        hipLaunchKernelGGL(k_treelet_top, dim3((unsigned)((m + kSubtreeLeaves - 1) / kSubtreeLeaves)),
+                           dim3(kSubtreeLeaves), 0, s, m, roots, nroots, b->child, b->parent, b->boxes, sah, count,
+                           arrivals);
+      }
     }
     hipLaunchKernelGGL(k_wide, dim3(grid_for(nint)), dim3(kBlock), 0, s, m, b->child, b->boxes, b->nodes);
   } else {

@@ -106,7 +106,8 @@ def _check_tree(t, n):
     return (1.2 * area[:nint].sum() + area[nint:].sum()) / area[0]
 
 
-@pytest.mark.parametrize("case", ["n2", "n3", "n5", "n100", "dups257", "plain1k", "scene100k", "proxy2k"])
+@pytest.mark.parametrize("case", ["n2", "n3", "n5", "n100", "dups257", "plain1k", "scene100k", "proxy2k",
+                                  "scene1100k"])
 def test_restructured_tree_valid_and_cheaper(case):
     """Treelet restructuring keeps a valid tree over the same sorted leaves (Morton codes
     and permutation unchanged), with exact boxes, and never raises the surface-area cost."""
@@ -118,6 +119,8 @@ def test_restructured_tree_valid_and_cheaper(case):
         scene = inputs.cluster_scene(2, 100_000, 0)
     elif case == "proxy2k":
         scene, kind = inputs.cluster_scene(2, 2000, 0), grtx.PROXY20
+    elif case == "scene1100k":  # above a million leaves: the pass over the top of the tree runs too
+        scene = inputs.cluster_scene(6, 1_100_000, 0)
     else:
         n = int(case[1:] if case[0] == "n" else case[4:])
         rng = np.random.default_rng(n)
@@ -137,12 +140,13 @@ def test_restructured_tree_valid_and_cheaper(case):
     say(dict(case=case, sah_plain=round(ca, 2), sah_restructured=round(cb, 2)))
 
 
-@pytest.mark.parametrize("kind", [grtx.SPHERE_INSTANCE, grtx.PROXY20, grtx.ICO_INSTANCE])
-def test_restructured_tree_renders_identically(kind):
+@pytest.mark.parametrize("kind,n", [(grtx.SPHERE_INSTANCE, 100_000), (grtx.PROXY20, 20_000),
+                                    (grtx.ICO_INSTANCE, 100_000), (grtx.SPHERE_INSTANCE, 1_100_000)])
+def test_restructured_tree_renders_identically(kind, n):
     """Results do not depend on the tree: the plain radix tree and the restructured one
     give bit-identical outputs and hit lists, in both modes."""
-    say("restructured renders", kind)
-    scene = inputs.cluster_scene(2, 20_000 if kind == grtx.PROXY20 else 100_000, 3)
+    say("restructured renders", kind, n)
+    scene = inputs.cluster_scene(2, n, 3)
     cam = inputs.orbit_camera(160, 120)
     o, d = grtx.pinhole_rays(cam)
     a = build(scene, kind, plain_lbvh=True)
