@@ -237,6 +237,42 @@ def run_secondary(bvh, cam, k, stream):
     return res
 
 
+def run_two_streams(st, cam, cfg, k, steps, warmup=2):
+    """The same step (raygen + build + trace of one frame) issued on two streams in turn, so
+    that consecutive frames overlap: the next frame's build and first rays fill the GPU
+    while the last rays of the previous frame finish. Reported beside the sequential step
+    as whole-job throughput of the same work."""
+    import numpy as np
+    import torch
+
+    from paper_2601_20429_amd import grtx
+    amin = float(np.float32(cfg["alpha_min"]))
+    dev = torch.device("cuda:0")
+    streams = [torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)]
+    R = cam.n_rays
+    outs = [dict(rgb=torch.empty((R, 3), dtype=torch.float32, device=dev),
+                 depth=torch.empty(R, dtype=torch.float32, device=dev),
+                 opacity=torch.empty(R, dtype=torch.float32, device=dev)) for _ in streams]
+
+    def step(i):
+        s = streams[i % 2]
+        with torch.cuda.stream(s):
+            oo, dd = grtx.pinhole_rays(cam, device=dev, stream=s)
+            bvh = grtx.build(st, alpha_min=amin, stream=s)
+            grtx.trace(bvh, oo, dd, k=k, T_min=cfg["T_min"], image_width=cam.width, out=outs[i % 2], stream=s)
+        return bvh, oo, dd
+
+    keep = [step(i) for i in range(warmup)]
+    torch.cuda.synchronize()
+    keep.clear()
+    t0 = time.perf_counter()
+    keep = [step(i) for i in range(steps)]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    keep.clear()
+    return dict(two_stream_step_ms=ms, two_stream_mrays_s=R / (ms * 1e-3) / 1e6)
+
+
 def run_ksweep(bvh, o, d, cam, cfg, stream, ks=(4, 8, 16, 32, 64)):
     """k-buffer size sweep on the same frame, checkpoint and restart: trace time and
     per-ray fetches and rounds (the cost of re-traversal against the cost of larger
@@ -476,6 +512,9 @@ def main():
 
     info = bvh.info()
     extra["bvh_bytes"] = int(info["device_bytes"])
+    if not args.no_compare:
+        extra.update(run_two_streams(st, cam, cfg, args.k, args.steps))
+        log(f"two streams: step {extra['two_stream_step_ms']:.3f} ms ({extra['two_stream_mrays_s']:.1f} Mrays/s)")
     if not args.no_proxy:
         extra.update(run_proxy(st, cam, cfg, args.k, stream))
         log("proxy", json.dumps({k: v for k, v in extra.items() if k.startswith(("proxy", "ico"))}))
