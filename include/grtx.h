@@ -296,8 +296,8 @@ grtx_status grtx_object_rays(const grtx_objects* obj, const grtx_rays* rays, flo
  * (early termination did not stop it). For the continuing rays in increasing i, writes
  * cont_origins / cont_dirs [n,3] (copies of next_origins / next_dirs), cont_transmittance
  * [n] = T and cont_index [n] = i into caller-owned device buffers of `count` entries, and
- * n into *n_cont (host memory). Enqueued on `stream`; the call waits once on `stream` to
- * read n. Scratch of 8 B per ray is allocated and freed in stream order. */
+ * n into *n_cont (host memory). count <= 2^24. Enqueued on `stream`; the call waits once
+ * on `stream` to read n. Scratch of 8 B per ray is allocated and freed in stream order. */
 grtx_status grtx_continue_rays(int64_t count, const int32_t* kind, const float* opacity, float T_min,
                                const float* next_origins, const float* next_dirs, float* cont_origins,
                                float* cont_dirs, float* cont_transmittance, int32_t* cont_index, int64_t* n_cont,

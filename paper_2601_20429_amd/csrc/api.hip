@@ -225,7 +225,7 @@ grtx_status grtx_continue_rays(int64_t count, const int32_t* kind, const float* 
                                void* stream) {
   grtx::clear_error();
   CHECK_ARG(n_cont, "grtx_continue_rays: null n_cont");
-  CHECK_ARG(count >= 0 && count < ((int64_t)1 << 31), "grtx_continue_rays: count must be 0..2^31-1");
+  CHECK_ARG(count >= 0 && count <= ((int64_t)1 << 24), "grtx_continue_rays: count must be 0..2^24");
   CHECK_ARG(T_min >= 0.f && T_min < 1.f, "grtx_continue_rays: T_min must be in [0,1)");
   if (count > 0)
     CHECK_ARG(kind && opacity && next_origins && next_dirs && cont_origins && cont_dirs && cont_transmittance &&

@@ -85,8 +85,9 @@ def test_secondary_ray_calls_reject_bad_arguments():
     assert b"null" in L.grtx_last_error()
     assert L.grtx_object_rays(None, C.byref(rays), fake, fake, fake, fake, fake, None) == grtx.ERR_INVALID_ARG
     n = C.c_int64(-7)
-    assert L.grtx_continue_rays(-1, fake, fake, 1e-3, fake, fake, fake, fake, fake, fake, C.byref(n), None) == \
-        grtx.ERR_INVALID_ARG
+    for bad_count in (-1, (1 << 24) + 1):
+        assert L.grtx_continue_rays(bad_count, fake, fake, 1e-3, fake, fake, fake, fake, fake, fake, C.byref(n),
+                                    None) == grtx.ERR_INVALID_ARG
     assert L.grtx_continue_rays(4, fake, fake, 1.0, fake, fake, fake, fake, fake, fake, C.byref(n), None) == \
         grtx.ERR_INVALID_ARG
     assert L.grtx_continue_rays(4, None, fake, 1e-3, fake, fake, fake, fake, fake, fake, C.byref(n), None) == \
