@@ -552,9 +552,16 @@ def main():
         t0 = time.perf_counter()
         oracle.render(scene, ro, rd, amin, cfg["T_min"], nthreads=cores)
         dt = time.perf_counter() - t0
+        cpu_model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+        except OSError:
+            pass
         cpu = dict(value=len(idx) / dt / 1e6, unit="Mrays/s", cores=cores, kind="oracle",
                    sample=f"{len(idx)} of the {R} primary rays (seeded subsample) against all {cfg['n']} "
-                          f"Gaussians, FP64 brute force, {dt:.1f} s")
+                          f"Gaussians, FP64 brute force, {dt:.1f} s",
+                   host_cpu=cpu_model, host_threads_visible=os.cpu_count())
         log("cpu baseline", json.dumps(cpu))
 
     rec = {
