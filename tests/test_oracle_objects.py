@@ -175,6 +175,25 @@ def test_starting_transmittance_scales_and_shortens(tau):
     np.testing.assert_allclose(r["rgb"][0], tau * dc_colour([0.7, 0.1, 0.4]) * (1 - (1 - o32) ** nstar), rtol=1e-12)
 
 
+def test_bound_applies_to_the_proxy_key():
+    """The surface bound compares the key that orders the hits: in proxy-key mode the
+    icosahedron entry, which precedes the ellipsoid entry. A ray through the centre of one
+    Gaussian bounded between the two entries blends it with the proxy key only."""
+    sig, o = 0.05, 0.8
+    sc = make_scene([[2.0, 0.0, 0.0]], [sig] * 3, opac=o, rgb=[0.9, 0.2, 0.1])
+    ray_o, ray_d = np.zeros((1, 3)), np.array([[1.0, 0.0, 0.0]])
+    hp = oracle.ray_hits(sc, ray_o[0], ray_d[0], AMIN, key_mode=1)
+    hs = oracle.ray_hits(sc, ray_o[0], ray_d[0], AMIN, key_mode=0)
+    t_proxy, t_sphere = float(hp["t"][0]), float(hs["t"][0])
+    rho = rho_of(float(np.float32(o)), AMIN) * float(np.float32(sig))
+    assert t_sphere == pytest.approx(2.0 - rho, abs=1e-9) and t_proxy < t_sphere - 1e-4
+    t_far = [0.5 * (t_proxy + t_sphere)]
+    rp = oracle.render(sc, ray_o, ray_d, AMIN, key_mode=1, t_far=t_far, cap=2)
+    rs = oracle.render(sc, ray_o, ray_d, AMIN, key_mode=0, t_far=t_far, cap=2)
+    assert rp["nblend"][0] == 1 and rs["nblend"][0] == 0
+    assert rp["opacity"][0] == pytest.approx(float(np.float32(o)), rel=1e-12)
+
+
 # ---------------------------------------------------------------- identities of the whole chain
 
 def _scene_above_plane(seed, n, zmin):
