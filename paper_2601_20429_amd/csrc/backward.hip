@@ -352,22 +352,6 @@ __global__ void __launch_bounds__(kBlock) k_fill_u32_bwd(uint32_t* p, int64_t n)
 
 inline unsigned grid(int64_t n, int per = kBlock) { return (unsigned)std::max<int64_t>(1, (n + per - 1) / per); }
 
-// Stream-ordered scratch of one backward call.
-struct BwdScratch {
-  std::vector<void*> ptrs;
-  hipStream_t s;
-  ~BwdScratch() {
-    for (void* p : ptrs) (void)hipFreeAsync(p, s);
-  }
-  template <class T>
-  grtx_status get(T** p, size_t count) {
-    void* q = nullptr;
-    GRTX_HIP(hipMallocAsync(&q, std::max<size_t>(count, 1) * sizeof(T), s));
-    ptrs.push_back(q);
-    *p = static_cast<T*>(q);
-    return GRTX_OK;
-  }
-};
 
 }  // namespace
 
@@ -384,7 +368,7 @@ grtx_status trace_backward(const grtx_gaussians* g, const grtx_rays* r, const gr
     set_error("trace_backward: %lld rays x %d listed hits exceed 2^32 records", (long long)R, fwd->hit_capacity);
     return GRTX_ERR_INVALID_ARG;
   }
-  BwdScratch sc{{}, s};
+  Scratch sc(s);
   // 1. records per ray and their offsets (one host read of the total)
   uint32_t *cnt = nullptr, *off = nullptr;
   GRTX_TRY(sc.get(&cnt, R));

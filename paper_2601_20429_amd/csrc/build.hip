@@ -12,7 +12,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <cmath>
+#include <type_traits>
 
 #include "grtx_internal.h"
 
@@ -672,37 +675,8 @@ __global__ void __launch_bounds__(kBlock) k_pinhole(float3 eye, float3 fwd, floa
 
 inline unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + kBlock - 1) / kBlock); }
 
-template <class T>
-grtx_status dalloc(Bvh* b, T** p, size_t count) {
-  size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-  void* q = nullptr;
-  GRTX_HIP(hipMalloc(&q, bytes));
-  b->allocations.push_back(q);
-  b->bytes += bytes;
-  *p = static_cast<T*>(q);
-  return GRTX_OK;
-}
 
 
-// Scratch buffers of one build, released when the build function returns (stream-ordered
-// frees keep them valid for the enqueued kernels).
-struct Scratch {
-  std::vector<void*> ptrs;
-  hipStream_t s;
-  ~Scratch() {
-    for (void* p : ptrs) (void)hipFreeAsync(p, s);
-  }
-  template <class T>
-  grtx_status get(T** p, size_t count) {
-    void* q = nullptr;
-    GRTX_HIP(hipMallocAsync(&q, std::max<size_t>(count, 1) * sizeof(T), s));
-    ptrs.push_back(q);
-    *p = static_cast<T*>(q);
-    return GRTX_OK;
-  }
-};
-
-// Sort (codes, idx) ascending by code, stable; results in keys/vals (ping-pong with tmp).
 grtx_status radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t* tvals, int64_t n, Scratch& sc,
                        hipStream_t s, int passes = 8) {
   int nblocks = (int)((n + kRadixTile - 1) / kRadixTile);
@@ -1142,6 +1116,69 @@ static Ico make_icosahedron() {
   return ico;
 }
 
+struct ScratchArena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t top = 0;      // bytes handed out from the arena
+  size_t logical = 0;  // bytes handed out in total, overflow included
+  size_t high = 0;     // largest `logical` seen
+  int depth = 0;       // live Scratch objects
+};
+
+namespace {
+std::mutex g_arena_lock;
+std::map<std::pair<int, hipStream_t>, ScratchArena> g_arenas;
+}  // namespace
+
+Scratch::Scratch(hipStream_t s) : s_(s) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  {
+    std::lock_guard<std::mutex> g(g_arena_lock);
+    arena_ = &g_arenas[{dev, s}];
+  }
+  mark_ = arena_->top;
+  logical_mark_ = arena_->logical;
+  ++arena_->depth;
+}
+
+grtx_status Scratch::raw(void** p, size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  ScratchArena& a = *arena_;
+  a.logical += bytes;
+  a.high = std::max(a.high, a.logical);
+  if (a.base && a.top + bytes <= a.cap) {
+    *p = a.base + a.top;
+    a.top += bytes;
+    return GRTX_OK;
+  }
+  void* q = nullptr;
+  GRTX_HIP(hipMallocAsync(&q, bytes, s_));
+  extra_.push_back(q);
+  *p = q;
+  return GRTX_OK;
+}
+
+Scratch::~Scratch() {
+  for (void* q : extra_) (void)hipFreeAsync(q, s_);
+  ScratchArena& a = *arena_;
+  a.top = mark_;
+  a.logical = logical_mark_;
+  if (--a.depth == 0 && a.high > a.cap) {
+    if (a.base) (void)hipFreeAsync(a.base, s_);
+    a.base = nullptr;
+    a.cap = 0;
+    const size_t want = a.high + a.high / 4;
+    void* q = nullptr;
+    if (hipMallocAsync(&q, want, s_) == hipSuccess) {
+      a.base = static_cast<char*>(q);
+      a.cap = want;
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+}
+
 grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_min, bool restructure_tree,
                       hipStream_t s, Bvh* b) {
   b->kind = kind;
@@ -1159,20 +1196,38 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
   if (n == 0) return GRTX_OK;
   GaussIn gi{g->means, g->scales, g->quats, g->opacities};
   const int64_t nint = m - 1;
-  GRTX_TRY(dalloc(b, &b->codes, m));
-  GRTX_TRY(dalloc(b, &b->perm, m));
-  GRTX_TRY(dalloc(b, &b->child, 2 * std::max<int64_t>(nint, 1)));
-  GRTX_TRY(dalloc(b, &b->parent, 2 * m - 1));
-  GRTX_TRY(dalloc(b, &b->boxes, 6 * (2 * m - 1)));
-  GRTX_TRY(dalloc(b, &b->nodes, kNodeF4 * std::max<int64_t>(nint, 1)));
-  GRTX_TRY(dalloc(b, &b->inst, 4 * n));
-  if (proxy) GRTX_TRY(dalloc(b, &b->tris, 3 * m));
+  // every array the handle owns in one allocation (each hipMalloc costs host time per frame)
+  auto layout = [&](auto&& put) {
+    put(&b->codes, m);
+    put(&b->perm, m);
+    put(&b->child, 2 * std::max<int64_t>(nint, 1));
+    put(&b->parent, 2 * m - 1);
+    put(&b->boxes, 6 * (2 * m - 1));
+    put(&b->nodes, kNodeF4 * std::max<int64_t>(nint, 1));
+    put(&b->inst, 4 * n);
+    if (proxy) put(&b->tris, 3 * m);
+    put(&b->roots, 8);
+    put(&b->cut, 2 * (int64_t)kCutCap);
+    put(&b->n_cut, 1);
+  };
+  size_t total = 0;
+  layout([&](auto** p, int64_t count) {
+    total = (total + 255) & ~(size_t)255;
+    total += (size_t)std::max<int64_t>(count, 1) * sizeof(**p);
+  });
+  void* block = nullptr;
+  GRTX_HIP(hipMalloc(&block, total));
+  b->allocations.push_back(block);
+  b->bytes += total;
+  size_t off = 0;
+  layout([&](auto** p, int64_t count) {
+    off = (off + 255) & ~(size_t)255;
+    *p = reinterpret_cast<std::remove_reference_t<decltype(*p)>>(static_cast<char*>(block) + off);
+    off += (size_t)std::max<int64_t>(count, 1) * sizeof(**p);
+  });
   b->root_box = b->boxes;  // node 0: the root, or the only leaf when m == 1
-  GRTX_TRY(dalloc(b, &b->roots, 8));
-  GRTX_TRY(dalloc(b, &b->cut, 2 * (size_t)kCutCap));
-  GRTX_TRY(dalloc(b, &b->n_cut, 1));
 
-  Scratch sc{{}, s};
+  Scratch sc(s);
   float *partial = nullptr, *bounds = nullptr, *cent = nullptr, *tbox = nullptr;
   float4* ttmp = nullptr;
   uint64_t* tkeys = nullptr;
@@ -1323,7 +1378,7 @@ grtx_status pinhole_rays(const grtx_camera* cam, float* origins, float* dirs, hi
 
 grtx_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s) {
   if (n <= 0) return GRTX_OK;
-  Scratch sc{{}, s};
+  Scratch sc(s);
   const int nparts = (int)((n + kScanChunk - 1) / kScanChunk);
   if (nparts > kScanChunk) {
     set_error("scan: %lld values exceed the supported size", (long long)n);
@@ -1344,7 +1399,7 @@ grtx_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, hip
 
 grtx_status sort_by_key(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, hipStream_t s) {
   if (n <= 1) return GRTX_OK;
-  Scratch sc{{}, s};
+  Scratch sc(s);
   uint64_t* tkeys = nullptr;
   uint32_t* tvals = nullptr;
   GRTX_TRY(sc.get(&tkeys, n));

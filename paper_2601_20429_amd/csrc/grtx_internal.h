@@ -167,6 +167,36 @@ grtx_status serve_poll(Server* sv, uint64_t ticket, grtx_request_result* res);
 grtx_status serve_release(Server* sv, uint64_t ticket);
 grtx_status serve_stats(Server* sv, grtx_serve_stats* st);
 grtx_status serve_destroy(Server* sv);
+// Stream-ordered scratch memory for one call. Regions come from a per-(device, stream)
+// arena in last-in-first-out order and return to it when the Scratch ends, so calls on one
+// stream reuse the same memory without an allocation or a free each time (the work that
+// used a region is ordered before any later use on that stream). A request beyond the
+// arena is met by hipMallocAsync and freed in stream order; when the outermost scratch of
+// a stream ends, the arena grows to the largest demand seen. A stream must be driven by
+// one host thread at a time.
+struct ScratchArena;
+class Scratch {
+ public:
+  explicit Scratch(hipStream_t s);
+  ~Scratch();
+  Scratch(const Scratch&) = delete;
+  Scratch& operator=(const Scratch&) = delete;
+  grtx_status raw(void** p, size_t bytes);
+  template <class T>
+  grtx_status get(T** p, size_t count) {
+    void* q = nullptr;
+    grtx_status st = raw(&q, (count > 0 ? count : 1) * sizeof(T));
+    if (st == GRTX_OK) *p = static_cast<T*>(q);
+    return st;
+  }
+
+ private:
+  ScratchArena* arena_ = nullptr;
+  hipStream_t s_;
+  size_t mark_ = 0, logical_mark_ = 0;
+  std::vector<void*> extra_;
+};
+
 // Device utilities of the build, reused by the backward pass (stream-ordered scratch).
 // Exclusive prefix sum of n uint32 values.
 grtx_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);

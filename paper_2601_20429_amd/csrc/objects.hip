@@ -237,8 +237,9 @@ grtx_status continue_rays(int64_t count, const int32_t* kind, const float* opaci
     *n_cont = 0;
     return GRTX_OK;
   }
+  Scratch sc(s);
   uint32_t* flags = nullptr;
-  GRTX_HIP(hipMallocAsync(reinterpret_cast<void**>(&flags), sizeof(uint32_t) * 2 * (size_t)count, s));
+  GRTX_TRY(sc.get(&flags, 2 * (size_t)count));
   uint32_t* offs = flags + count;
   grtx_status st = GRTX_OK;
   hipLaunchKernelGGL(k_cont_flags, dim3(grid_of(count)), dim3(kObjBlock), 0, s, kind, opacity, T_min, count, flags);
@@ -262,11 +263,10 @@ grtx_status continue_rays(int64_t count, const int32_t* kind, const float* opaci
     set_error("continue_rays: reading the count failed");
     st = GRTX_ERR_DEVICE;
   }
-  const hipError_t ef = hipFreeAsync(flags, s);
   const hipError_t es = hipStreamSynchronize(s);
   if (st != GRTX_OK) return st;
-  if (ef != hipSuccess || es != hipSuccess) {
-    set_error("continue_rays: %s", hipGetErrorString(ef != hipSuccess ? ef : es));
+  if (es != hipSuccess) {
+    set_error("continue_rays: %s", hipGetErrorString(es));
     return GRTX_ERR_DEVICE;
   }
   *n_cont = (int64_t)tail[0] + tail[1];

@@ -1081,6 +1081,7 @@ grtx_status launch_trace(const TraceScene& b, const grtx_rays* r, const grtx_tra
   a.cap_e = cap_e;
   a.chunk_len = ((a.n_work + 64 * kChunks - 1) / (64 * kChunks)) * 64;
   uint32_t* order_buf = nullptr;
+  Scratch order_scratch(s);
   if (a.image_w > 0) {
     // Tiles heaviest first, so that the longest rays do not start last: by estimated cost
     // where the structure carries a subtree cut, centre-out within equal estimates.
@@ -1089,17 +1090,13 @@ grtx_status launch_trace(const TraceScene& b, const grtx_rays* r, const grtx_tra
     GRTX_TRY(centre_out_order(device, a.tiles_x, (int)(nt / a.tiles_x), &base));
     // scratch: estimate keys (8 B) and order (4 B) per tile, then three more words per tile
     // for the continuation partition
-    GRTX_HIP(hipMallocAsync(reinterpret_cast<void**>(&order_buf), 6 * (size_t)nt * sizeof(uint32_t), s));
+    GRTX_TRY(order_scratch.get(&order_buf, 6 * (size_t)nt));
     if (b.cut) {
       uint64_t* keys = reinterpret_cast<uint64_t*>(order_buf);
       uint32_t* est_order = order_buf + 2 * nt;
       hipLaunchKernelGGL(k_tile_estimate, dim3((unsigned)((nt + kEstTiles - 1) / kEstTiles)), dim3(256), 0, s, b.cut,
                          b.n_cut, r->origins, r->dirs, a.image_w, a.image_h, a.tiles_x, nt, base, keys, est_order);
-      grtx_status st = sort_by_key(keys, est_order, nt, 8, s);
-      if (st != GRTX_OK) {
-        (void)hipFreeAsync(order_buf, s);
-        return st;
-      }
+      GRTX_TRY(sort_by_key(keys, est_order, nt, 8, s));
       base = est_order;
     }
     a.tile_order = base;
@@ -1111,21 +1108,14 @@ grtx_status launch_trace(const TraceScene& b, const grtx_rays* r, const grtx_tra
       const unsigned g = (unsigned)((nt + 255) / 256);
       hipLaunchKernelGGL(k_tile_heavy, dim3(g), dim3(256), 0, s, r->kind, base, a.image_w, a.image_h, a.tiles_x, nt,
                          flag);
-      const grtx_status st = exclusive_scan_u32(flag, pos, nt, s);
-      if (st != GRTX_OK) {
-        (void)hipFreeAsync(order_buf, s);
-        return st;
-      }
+      GRTX_TRY(exclusive_scan_u32(flag, pos, nt, s));
       hipLaunchKernelGGL(k_tile_order, dim3(g), dim3(256), 0, s, base, flag, pos, nt, order);
       a.tile_order = order;
     }
   }
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, pool->counter);
-  const grtx_status st = leaf == kLeafTri ? launch_k<kLeafTri>(K, a, blocks, s)
-                       : leaf == kLeafIco ? launch_k<kLeafIco>(K, a, blocks, s)
-                                          : launch_k<kLeafSphere>(K, a, blocks, s);
-  if (order_buf) GRTX_HIP(hipFreeAsync(order_buf, s));
-  return st;
+  return leaf == kLeafTri ? launch_k<kLeafTri>(K, a, blocks, s)
+       : leaf == kLeafIco ? launch_k<kLeafIco>(K, a, blocks, s) : launch_k<kLeafSphere>(K, a, blocks, s);
 }
 
 }  // namespace grtx
