@@ -205,6 +205,32 @@ __global__ void __launch_bounds__(kBlock) k_scan_down(const uint32_t* __restrict
   }
 }
 
+// Exclusive scan of up to a few chunks in one workgroup, chunk after chunk with a running
+// carry: one launch where the three-kernel scan would spend two more on a tiny partial pass.
+constexpr int kScanLoopChunks = 8;
+__global__ void __launch_bounds__(kBlock) k_scan_loop(const uint32_t* __restrict__ in, int64_t n,
+                                                      uint32_t* __restrict__ out) {
+  __shared__ uint32_t s[kBlock];
+  uint32_t carry = 0;
+  for (int64_t c0 = 0; c0 < n; c0 += kScanChunk) {
+    const int64_t base = c0 + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t acc = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+      v[j] = base + j < n ? in[base + j] : 0u;
+      acc += v[j];
+    }
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(acc, s, &tot) + carry;
+    for (int j = 0; j < kScanItems; ++j) {
+      if (base + j < n) out[base + j] = run;
+      run += v[j];
+    }
+    carry += tot;
+    __syncthreads();
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* __restrict__ keys_in,
                                                           const uint32_t* __restrict__ vals_in, int64_t n, int shift,
                                                           const uint32_t* __restrict__ offsets, int nblocks,
@@ -697,7 +723,9 @@ grtx_status radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t
   for (int pass = 0; pass < passes; ++pass) {
     int shift = 8 * pass;
     hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kBlock), 0, s, kin, n, shift, hist, nblocks);
-    if (nparts > 1) {
+    if (nparts > 1 && nparts <= kScanLoopChunks) {
+      hipLaunchKernelGGL(k_scan_loop, dim3(1), dim3(kBlock), 0, s, hist, hn, offs);
+    } else if (nparts > 1) {
       hipLaunchKernelGGL(k_scan_reduce, dim3(nparts), dim3(kBlock), 0, s, hist, hn, part);
       hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, s, part, nparts);
       hipLaunchKernelGGL(k_scan_down, dim3(nparts), dim3(kBlock), 0, s, hist, hn, part, offs);
@@ -1384,7 +1412,9 @@ grtx_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, hip
     set_error("scan: %lld values exceed the supported size", (long long)n);
     return GRTX_ERR_INVALID_ARG;
   }
-  if (nparts > 1) {
+  if (nparts > 1 && nparts <= kScanLoopChunks) {
+    hipLaunchKernelGGL(k_scan_loop, dim3(1), dim3(kBlock), 0, s, in, n, out);
+  } else if (nparts > 1) {
     uint32_t* part = nullptr;
     GRTX_TRY(sc.get(&part, nparts));
     hipLaunchKernelGGL(k_scan_reduce, dim3(nparts), dim3(kBlock), 0, s, in, n, part);
