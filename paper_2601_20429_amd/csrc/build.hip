@@ -114,21 +114,29 @@ __global__ void __launch_bounds__(kBlock) k_morton(const float* __restrict__ pts
 
 // ------------------------------------------------------------------ radix sort (stable LSD)
 
+// Keys per thread: 16 for large sorts; 4 up to kRadixSmall keys, so that a sort of a few
+// hundred thousand keys still spreads over ~100 workgroups instead of ~25.
 constexpr int kRadixItems = 16;
-constexpr int kRadixTile = kBlock * kRadixItems;
+constexpr int kRadixItemsSmall = 4;
+constexpr int64_t kRadixSmall = (int64_t)256 * kBlock * kRadixItemsSmall;
+// Up to this many workgroups, each scatter workgroup derives its own offsets from the
+// histogram table (a digit's counts over all workgroups), so no scan launch is needed.
+constexpr int kRadixFusedBlocks = 256;
 
 __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
-                                                       uint32_t* __restrict__ hist, int nblocks) {
+                                                       int items, uint32_t* __restrict__ hist, int nblocks,
+                                                       bool fused) {
   __shared__ uint32_t s_cnt[256];
   s_cnt[threadIdx.x] = 0;
   __syncthreads();
-  int64_t base = (int64_t)blockIdx.x * kRadixTile;
-  for (int r = 0; r < kRadixItems; ++r) {
+  int64_t base = (int64_t)blockIdx.x * kBlock * items;
+  for (int r = 0; r < items; ++r) {
     int64_t i = base + r * kBlock + threadIdx.x;
     if (i < n) atomicAdd(&s_cnt[(keys[i] >> shift) & 255u], 1u);
   }
   __syncthreads();
-  hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = s_cnt[threadIdx.x];
+  // digit-major ([digit][workgroup]) for the scan; workgroup-major rows for the fused scatter
+  hist[fused ? (size_t)blockIdx.x * 256 + threadIdx.x : (size_t)threadIdx.x * nblocks + blockIdx.x] = s_cnt[threadIdx.x];
 }
 
 // Exclusive scan of `n` uint32 in chunks of kScanChunk.
@@ -231,19 +239,36 @@ __global__ void __launch_bounds__(kBlock) k_scan_loop(const uint32_t* __restrict
   }
 }
 
+// `offsets` is either the scanned histogram table ([digit][workgroup], exclusive), or, with
+// `fused`, the raw counts in workgroup-major rows: then thread d adds digit d's counts of the
+// workgroups before this one, and a block scan over the 256 digit totals gives the digit's
+// start.
 __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* __restrict__ keys_in,
                                                           const uint32_t* __restrict__ vals_in, int64_t n, int shift,
-                                                          const uint32_t* __restrict__ offsets, int nblocks,
-                                                          uint64_t* __restrict__ keys_out,
+                                                          int items, const uint32_t* __restrict__ offsets,
+                                                          int nblocks, bool fused, uint64_t* __restrict__ keys_out,
                                                           uint32_t* __restrict__ vals_out) {
   __shared__ uint32_t s_off[256];
   __shared__ uint32_t s_wcnt[kBlock / 64][256];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
-  s_off[threadIdx.x] = offsets[(size_t)threadIdx.x * nblocks + blockIdx.x];
-  int64_t base = (int64_t)blockIdx.x * kRadixTile;
-  for (int r = 0; r < kRadixItems; ++r) {
+  if (fused) {
+    uint32_t before = 0, total = 0;
+#pragma unroll 8
+    for (int b = 0; b < nblocks; ++b) {
+      const uint32_t c = offsets[(size_t)b * 256 + threadIdx.x];
+      total += c;
+      before += b < (int)blockIdx.x ? c : 0u;
+    }
+    uint32_t all;
+    const uint32_t start = block_exclusive_scan(total, &s_wcnt[0][0], &all);
+    s_off[threadIdx.x] = start + before;
+  } else {
+    s_off[threadIdx.x] = offsets[(size_t)threadIdx.x * nblocks + blockIdx.x];
+  }
+  int64_t base = (int64_t)blockIdx.x * kBlock * items;
+  for (int r = 0; r < items; ++r) {
     for (int w = 0; w < kBlock / 64; ++w) s_wcnt[w][threadIdx.x] = 0u;
     __syncthreads();
     int64_t i = base + r * kBlock + threadIdx.x;
@@ -705,7 +730,10 @@ inline unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, (n +
 
 grtx_status radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t* tvals, int64_t n, Scratch& sc,
                        hipStream_t s, int passes = 8) {
-  int nblocks = (int)((n + kRadixTile - 1) / kRadixTile);
+  const int items = n <= kRadixSmall ? kRadixItemsSmall : kRadixItems;
+  const int64_t tile = (int64_t)kBlock * items;
+  int nblocks = (int)((n + tile - 1) / tile);
+  const bool fused = nblocks <= kRadixFusedBlocks;
   int64_t hn = (int64_t)256 * nblocks;
   uint32_t *hist = nullptr, *offs = nullptr, *part = nullptr;
   int nparts = (int)((hn + kScanChunk - 1) / kScanChunk);
@@ -722,8 +750,10 @@ grtx_status radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t
   uint32_t* vout = tvals;
   for (int pass = 0; pass < passes; ++pass) {
     int shift = 8 * pass;
-    hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kBlock), 0, s, kin, n, shift, hist, nblocks);
-    if (nparts > 1 && nparts <= kScanLoopChunks) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kBlock), 0, s, kin, n, shift, items, hist, nblocks, fused);
+    if (fused) {
+      // the scatter turns the counts into offsets itself
+    } else if (nparts > 1 && nparts <= kScanLoopChunks) {
       hipLaunchKernelGGL(k_scan_loop, dim3(1), dim3(kBlock), 0, s, hist, hn, offs);
     } else if (nparts > 1) {
       hipLaunchKernelGGL(k_scan_reduce, dim3(nparts), dim3(kBlock), 0, s, hist, hn, part);
@@ -732,8 +762,8 @@ grtx_status radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t
     } else {
       hipLaunchKernelGGL(k_scan_down, dim3(1), dim3(kBlock), 0, s, hist, hn, (const uint32_t*)nullptr, offs);
     }
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kBlock), 0, s, kin, vin, n, shift, offs, nblocks, kout,
-                       vout);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kBlock), 0, s, kin, vin, n, shift, items,
+                       fused ? hist : offs, nblocks, fused, kout, vout);
     GRTX_LAUNCH_CHECK();
     std::swap(kin, kout);
     std::swap(vin, vout);
