@@ -392,8 +392,18 @@ __global__ void __launch_bounds__(kTraceBlock)
   };
 
   auto pop = [&]() __attribute__((always_inline)) -> uint2 {
+    // Two loads of different types in two branches: one load through a selected pointer
+    // (what the compiler makes of two alike loads) is a flat load, which waits on LDS and
+    // HBM alike.
     --sp;
-    return sp < kLdsStack ? s_stack[sp * kTraceBlock + tid] : LROW(sp - kLdsStack);
+    uint2 e;
+    if (sp < kLdsStack) {
+      e = s_stack[sp * kTraceBlock + tid];
+    } else {
+      const uint64_t v = *reinterpret_cast<const uint64_t*>(&LROW(sp - kLdsStack));
+      e = make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+    }
+    return e;
   };
 
   while (true) {
