@@ -313,7 +313,9 @@ __global__ void __launch_bounds__(kTraceBlock)
   const int rowN = kSpillRows;
   const int rowE = kSpillRows + 2 * A.cap_d;
   const int rowK = rowE + 2 * A.cap_e;
-#define ROW(r) wbase[(uint32_t)(r) * 64u + (uint32_t)lane]
+  uint2* const park = wbase + (int64_t)rowK * 64 + lane;
+// k-buffer park entry j of this lane, at 64-bit offsets from one base (`pk`, see below)
+#define PARK(j) pk[(int64_t)(j) * 64]
 #define LROW(r) wbase[(uint32_t)lane * (uint32_t)rowK + (uint32_t)(r)]
 #define STAT(f)                        \
   do {                                 \
@@ -639,17 +641,24 @@ __global__ void __launch_bounds__(kTraceBlock)
       // Blend in key order. The k-buffer is parked in the lane's rows so that the blend
       // loop indexes memory rather than a register array.
       const uint64_t last = kb[K - 1];
+      // The base passes through an empty asm statement so that the compiler cannot hoist
+      // the sixteen entry addresses out of the ray loop (where they would be spilled); the
+      // offsets fold into the store and load instructions.
+      uint2* pk = park;
+      asm volatile("" : "+v"(pk));
 #pragma unroll
       for (int j = 0; j < K; ++j)
-        if (j >= K - A.k) ROW(rowK + j) = make_uint2((uint32_t)kb[j], (uint32_t)(kb[j] >> 32));
+        if (j >= K - A.k) PARK(j) = make_uint2((uint32_t)kb[j], (uint32_t)(kb[j] >> 32));
       // proxy keys carry the Gaussian id: a mesh crossed exactly on an edge reports the
       // same Gaussian twice with adjacent keys; only the first is blended
       uint32_t prev_id = tmin == 0ull ? 0xFFFFFFFFu : (uint32_t)tmin;
+      // the next entry's key is read while the current one blends
+      uint2 kv = PARK(K - A.k);
 #pragma unroll 1
       for (int j = K - A.k; j < K && !ert; ++j) {
-        const uint2 kv = ROW(rowK + j);
         const uint64_t x = ((uint64_t)kv.y << 32) | kv.x;
         if (x == kEmptyKey) break;
+        if (j + 1 < K) kv = PARK(j + 1);
         const uint32_t p = (uint32_t)x;
         const float4* ip = A.inst + 4 * (int64_t)p;
         float4 r0 = ip[0], r1 = ip[1], r2 = ip[2], r3 = ip[3];
@@ -775,7 +784,7 @@ __global__ void __launch_bounds__(kTraceBlock)
       }
     }
   }
-#undef ROW
+#undef PARK
 #undef LROW
 #undef STAT
 }
