@@ -641,11 +641,13 @@ __global__ void __launch_bounds__(kTraceBlock)
       // Blend in key order. The k-buffer is parked in the lane's rows so that the blend
       // loop indexes memory rather than a register array.
       const uint64_t last = kb[K - 1];
-      // The base passes through an empty asm statement so that the compiler cannot hoist
-      // the sixteen entry addresses out of the ray loop (where they would be spilled); the
-      // offsets fold into the store and load instructions.
-      uint2* pk = park;
-      asm volatile("" : "+v"(pk));
+      // The base gets an offset that passes through an empty asm statement (it is zero), so
+      // that the compiler cannot hoist the sixteen entry addresses out of the ray loop
+      // (where they would be spilled); the offsets fold into the store and load
+      // instructions, and the pointer stays a global one.
+      int opaque_zero = 0;
+      asm volatile("" : "+s"(opaque_zero));
+      uint2* const pk = park + opaque_zero;
 #pragma unroll
       for (int j = 0; j < K; ++j)
         if (j >= K - A.k) PARK(j) = make_uint2((uint32_t)kb[j], (uint32_t)(kb[j] >> 32));
@@ -658,7 +660,7 @@ __global__ void __launch_bounds__(kTraceBlock)
       for (int j = K - A.k; j < K && !ert; ++j) {
         const uint64_t x = ((uint64_t)kv.y << 32) | kv.x;
         if (x == kEmptyKey) break;
-        if (j + 1 < K) kv = PARK(j + 1);
+        kv = PARK(j + 1 < K ? j + 1 : j);  // unconditional: no join right after the load
         const uint32_t p = (uint32_t)x;
         const float4* ip = A.inst + 4 * (int64_t)p;
         float4 r0 = ip[0], r1 = ip[1], r2 = ip[2], r3 = ip[3];
@@ -670,10 +672,12 @@ __global__ void __launch_bounds__(kTraceBlock)
           prev_id = p;
         }
         if (blend) {
-          const float inva = 1.f / h.a;
+          // hardware reciprocal and exp2 (about 1 ulp each); the exponent lies in
+          // [-log2(o / alpha_min), 0], far from the denormal range a library exp2f guards
+          const float inva = __builtin_amdgcn_rcpf(h.a);
           const float cperp = h.c2 * inva;
           const float talpha = -h.b * inva;
-          const float alpha = r3.x * exp2f(-r3.y * cperp);
+          const float alpha = r3.x * __builtin_amdgcn_exp2f(-r3.y * cperp);
           const uint32_t gid = __float_as_uint(r3.z);
           float c[3] = {0.5f, 0.5f, 0.5f};
           const float dn = rsqrtf(dx * dx + dy * dy + dz * dz);
