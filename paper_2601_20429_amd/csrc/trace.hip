@@ -184,14 +184,17 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, int L, float
 
 template <int K>
 __device__ __forceinline__ uint64_t kbuf_insert(uint64_t (&kb)[K], uint64_t x) {
+  // The buffer is sorted, so "x < kb[j]" holds from x's place on: every compare is against
+  // x itself (independent, one per entry) and entry j takes x at that place, its
+  // predecessor after it, and stays before it. Returns the entry pushed out (or x).
+  bool lt[K];
 #pragma unroll
-  for (int j = 0; j < K; ++j) {
-    uint64_t a = kb[j];
-    bool lt = x < a;
-    kb[j] = lt ? x : a;
-    x = lt ? a : x;
-  }
-  return x;
+  for (int j = 0; j < K; ++j) lt[j] = x < kb[j];
+  const uint64_t out = lt[K - 1] ? kb[K - 1] : x;
+#pragma unroll
+  for (int j = K - 1; j > 0; --j) kb[j] = lt[j - 1] ? kb[j - 1] : (lt[j] ? x : kb[j]);
+  kb[0] = lt[0] ? x : kb[0];
+  return out;
 }
 
 template <int K>
