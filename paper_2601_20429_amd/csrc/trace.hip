@@ -298,9 +298,21 @@ __device__ __forceinline__ bool ico_entry(float4 r0, float4 r1, float4 r2, float
   return !outside_parallel && te <= tx;
 }
 
+// The kernel's arguments, read again from the argument segment (scalar loads) at each use
+// site inside the ray loop: the empty asm statement hides that the pointer is the same every
+// time, so the compiler does not hold every field in scalar registers for the whole kernel
+// (too many: they were spilled into vector-register lanes and read back with VALU
+// instructions). The trace kernel takes one argument, so it sits at offset 0.
+typedef const __attribute__((address_space(4))) TraceArgs KernArgs;
+__device__ __forceinline__ KernArgs& kernel_args() {
+  auto p = (KernArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(p));
+  return *p;
+}
+
 template <int K, int LEAF, bool STATS>
 __global__ void __launch_bounds__(kTraceBlock)
-    __attribute__((amdgpu_waves_per_eu(K <= 16 ? GRTX_MIN_WAVES_K16 : 1, 8))) k_trace(TraceArgs A) {
+    __attribute__((amdgpu_waves_per_eu(K <= 16 ? GRTX_MIN_WAVES_K16 : 1, 8))) k_trace(TraceArgs Args) {
   __shared__ uint2 s_stack[kLdsStack * kTraceBlock];
   __shared__ uint32_t s_stat[STATS ? GRTX_STATS_FIELDS : 1][kTraceBlock];  // per-lane counters
   const int tid = threadIdx.x;
@@ -312,10 +324,10 @@ __global__ void __launch_bounds__(kTraceBlock)
   // cap_e entries (ping-pong source/destination, selected by `par`); a lane's appends and
   // reads walk its own lines. Then K rows holding the k-buffers while they are blended,
   // entry j of lane l at row j, column l: all blending lanes write row j together.
-  uint2* const wbase = A.pool + (int64_t)gwave * A.rows_per_wave * 64;
+  uint2* const wbase = Args.pool + (int64_t)gwave * Args.rows_per_wave * 64;
   const int rowN = kSpillRows;
-  const int rowE = kSpillRows + 2 * A.cap_d;
-  const int rowK = rowE + 2 * A.cap_e;
+  const int rowE = kSpillRows + 2 * Args.cap_d;
+  const int rowK = rowE + 2 * Args.cap_e;
   uint2* const park = wbase + (int64_t)rowK * 64 + lane;
 // k-buffer park entry j of this lane, at 64-bit offsets from one base (`pk`, see below)
 #define PARK(j) pk[(int64_t)(j) * 64]
@@ -324,8 +336,8 @@ __global__ void __launch_bounds__(kTraceBlock)
   do {                                 \
     if constexpr (STATS) ++s_stat[f][tid]; \
   } while (0)
-  const bool ckpt = A.mode == GRTX_MODE_CHECKPOINT;
-  const float tnear = A.t_near;
+  const bool ckpt = Args.mode == GRTX_MODE_CHECKPOINT;
+  const float tnear = Args.t_near;
 
   int state = kIdle;
   int ray = -1;
@@ -333,7 +345,7 @@ __global__ void __launch_bounds__(kTraceBlock)
   float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, ix = 0, iy = 0, iz = 0;
   float tfar = INFINITY;  // the ray ends on a surface there: keys must stay below it
   uint64_t kb[K];
-  kbuf_reset(kb, A.k);
+  kbuf_reset(kb, Args.k);
   uint64_t tmin = 0;  // key of the last blended hit
   float C0 = 0, C1 = 0, C2 = 0, Dp = 0, T = 1;
   uint32_t cur_ref = 0;  // item in hand: internal node or leaf (has_cur)
@@ -353,7 +365,7 @@ __global__ void __launch_bounds__(kTraceBlock)
 
   auto root_start = [&]() __attribute__((always_inline)) {
     // (Re)start at the root; subtrees that end before tmin are culled.
-    const float* rb = A.roots + 8 * sid;
+    const float* rb = Args.roots + 8 * sid;
     Slab s = slab(rb[0], rb[1], rb[2], rb[3], rb[4], rb[5], ox, oy, oz, ix, iy, iz);
     float tlo = fmaxf(tnear, key_t(tmin));
     const float tf = fminf(s.tf, tfar);
@@ -365,8 +377,8 @@ __global__ void __launch_bounds__(kTraceBlock)
 
   auto defer = [&](uint32_t ref, float t) __attribute__((always_inline)) {
     if (!ckpt) return;
-    if (ndst_n < A.cap_d) {
-      LROW(rowN + (par ^ 1) * A.cap_d + ndst_n) = make_uint2(ref, __float_as_uint(t));
+    if (ndst_n < Args.cap_d) {
+      LROW(rowN + (par ^ 1) * Args.cap_d + ndst_n) = make_uint2(ref, __float_as_uint(t));
       ++ndst_n;
       STAT(GRTX_STAT_DEFERRED);
     } else {
@@ -376,8 +388,8 @@ __global__ void __launch_bounds__(kTraceBlock)
 
   auto evict = [&](uint64_t k64) __attribute__((always_inline)) {
     if (!ckpt) return;
-    if (edst_n < A.cap_e) {
-      LROW(rowE + (par ^ 1) * A.cap_e + edst_n) = make_uint2((uint32_t)k64, (uint32_t)(k64 >> 32));
+    if (edst_n < Args.cap_e) {
+      LROW(rowE + (par ^ 1) * Args.cap_e + edst_n) = make_uint2((uint32_t)k64, (uint32_t)(k64 >> 32));
       ++edst_n;
       STAT(GRTX_STAT_EVICTED);
     } else {
@@ -412,6 +424,7 @@ __global__ void __launch_bounds__(kTraceBlock)
   };
 
   while (true) {
+    KernArgs& A = kernel_args();
     // ---------------------------------------------------------------- refill idle lanes
     // The work items are split into kChunks contiguous chunks (bands of 8x8 tiles). A
     // wave starts on the chunk of its XCD (workgroups are dealt round-robin to the 8 XCDs)
