@@ -48,8 +48,10 @@ namespace {
 #ifndef GRTX_REFILL_THRESHOLD
 #define GRTX_REFILL_THRESHOLD 32
 #endif
-#ifndef GRTX_MIN_WAVES_K16
-#define GRTX_MIN_WAVES_K16 3
+// Waves per SIMD the trace kernel is register-budgeted for up to k = 32 (at most 170
+// VGPRs): three, which k <= 32 reach without scratch; k = 64 keeps the compiler's choice.
+#ifndef GRTX_MIN_WAVES
+#define GRTX_MIN_WAVES 3
 #endif
 constexpr int kTraceBlock = 256;
 constexpr int kWaves = kTraceBlock / 64;
@@ -312,7 +314,7 @@ __device__ __forceinline__ KernArgs& kernel_args() {
 
 template <int K, int LEAF, bool STATS>
 __global__ void __launch_bounds__(kTraceBlock)
-    __attribute__((amdgpu_waves_per_eu(K <= 16 ? GRTX_MIN_WAVES_K16 : 1, 8))) k_trace(TraceArgs Args) {
+    __attribute__((amdgpu_waves_per_eu(K <= 32 ? GRTX_MIN_WAVES : 1, 8))) k_trace(TraceArgs Args) {
   __shared__ uint2 s_stack[kLdsStack * kTraceBlock];
   __shared__ uint32_t s_stat[STATS ? GRTX_STATS_FIELDS : 1][kTraceBlock];  // per-lane counters
   const int tid = threadIdx.x;
@@ -700,11 +702,14 @@ __global__ void __launch_bounds__(kTraceBlock)
           float Y[16];
           sh_basis(dx * dn, dy * dn, dz * dn, A.sh_degree, Y);
           if (A.sh_degree == 3) {
+            // all twelve loads in flight at once, then the sums
             const float4* sp4 = reinterpret_cast<const float4*>(A.sh + (int64_t)gid * 48);
+            float4 shv[12];
+#pragma unroll
+            for (int q = 0; q < 12; ++q) shv[q] = sp4[q];
 #pragma unroll
             for (int q = 0; q < 12; ++q) {
-              float4 v = sp4[q];
-              const float* vv = reinterpret_cast<const float*>(&v);
+              const float* vv = reinterpret_cast<const float*>(&shv[q]);
 #pragma unroll
               for (int e = 0; e < 4; ++e) {
                 const int f = 4 * q + e;
@@ -733,6 +738,9 @@ __global__ void __launch_bounds__(kTraceBlock)
           if (T < A.T_min) ert = true;
         }  // blend
       }
+      // every path below starts the buffer afresh (a finished lane's on its next ray), so
+      // the old entries are dead from the park on and hold no registers through the blend
+      kbuf_reset(kb, A.k);
       const bool full = last != kEmptyKey;
       const bool done = ert || !full || (ckpt && !overflow && ndst_n == 0 && edst_n == 0);
       // A segment that reached its surface with T >= T_min goes on along its reflected or
@@ -751,7 +759,6 @@ __global__ void __launch_bounds__(kTraceBlock)
         ix = safe_inv(dx); iy = safe_inv(dy); iz = safe_inv(dz);
         Dp = fmaf(A.ray_path[ray], T, Dp);
         tfar = INFINITY;
-        kbuf_reset(kb, A.k);
         tmin = 0;
         par = 0;
         nsrc_n = nsrc_i = ndst_n = 0;
@@ -780,7 +787,6 @@ __global__ void __launch_bounds__(kTraceBlock)
         state = kIdle;
       } else {
         tmin = last;
-        kbuf_reset(kb, A.k);
         if (!ckpt || overflow) {
           // restart from the root beyond the last blended hit
           if (ckpt) STAT(GRTX_STAT_FALLBACKS);
