@@ -560,18 +560,24 @@ __global__ void __launch_bounds__(kTraceBlock)
           const float Bx = (q0.x - ox) * ix, By = (q0.y - oy) * iy, Bz = (q0.z - oz) * iz;
           const uint32_t wlx = __float_as_uint(q2.z), wly = __float_as_uint(q2.w), wlz = __float_as_uint(q3.x);
           const uint32_t whx = __float_as_uint(q3.y), why = __float_as_uint(q3.z), whz = __float_as_uint(q3.w);
+          // The entry plane of an axis is the low one where the ray's direction is positive
+          // (t grows with the plane coordinate, and the rounding of fma keeps that order), so
+          // the planes are chosen once per record instead of a min and a max per child.
+          const uint32_t wnx = ix < 0.f ? whx : wlx, wfx = ix < 0.f ? wlx : whx;
+          const uint32_t wny = iy < 0.f ? why : wly, wfy = iy < 0.f ? wly : why;
+          const uint32_t wnz = iz < 0.f ? whz : wlz, wfz = iz < 0.f ? wlz : whz;
           uint32_t c[4] = {__float_as_uint(q1.z), __float_as_uint(q1.w), __float_as_uint(q2.x), __float_as_uint(q2.y)};
           float t[4];
   #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const float t0x = fmaf((float)((wlx >> (8 * j)) & 0xFFu), Ax, Bx);
-            const float t1x = fmaf((float)((whx >> (8 * j)) & 0xFFu), Ax, Bx);
-            const float t0y = fmaf((float)((wly >> (8 * j)) & 0xFFu), Ay, By);
-            const float t1y = fmaf((float)((why >> (8 * j)) & 0xFFu), Ay, By);
-            const float t0z = fmaf((float)((wlz >> (8 * j)) & 0xFFu), Az, Bz);
-            const float t1z = fmaf((float)((whz >> (8 * j)) & 0xFFu), Az, Bz);
-            const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z));
-            const float tf = fminf(fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)), tfar);
+            const float tnx = fmaf((float)((wnx >> (8 * j)) & 0xFFu), Ax, Bx);
+            const float tfx = fmaf((float)((wfx >> (8 * j)) & 0xFFu), Ax, Bx);
+            const float tny = fmaf((float)((wny >> (8 * j)) & 0xFFu), Ay, By);
+            const float tfy = fmaf((float)((wfy >> (8 * j)) & 0xFFu), Ay, By);
+            const float tnz = fmaf((float)((wnz >> (8 * j)) & 0xFFu), Az, Bz);
+            const float tfz = fmaf((float)((wfz >> (8 * j)) & 0xFFu), Az, Bz);
+            const float tn = fmaxf(fmaxf(tnx, tny), tnz);
+            const float tf = fminf(fminf(fminf(tfx, tfy), tfz), tfar);
             const float te = fmaxf(tn, cur_t);
             bool v = c[j] != kNoChild && tn <= tf && tf >= tlo;
             if (v && te > tmax_t) {
