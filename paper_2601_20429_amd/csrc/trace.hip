@@ -345,6 +345,7 @@ __global__ void __launch_bounds__(kTraceBlock)
   int ray = -1;
   int sid = 0;  // scene of the lane's ray
   float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, ix = 0, iy = 0, iz = 0;
+  float oix = 0, oiy = 0, oiz = 0;  // origin times inverse direction, for the slab fma
   float tfar = INFINITY;  // the ray ends on a surface there: keys must stay below it
   uint64_t kb[K];
   kbuf_reset(kb, Args.k);
@@ -472,6 +473,7 @@ __global__ void __launch_bounds__(kTraceBlock)
             ox = ro[0]; oy = ro[1]; oz = ro[2];
             dx = rd[0]; dy = rd[1]; dz = rd[2];
             ix = safe_inv(dx); iy = safe_inv(dy); iz = safe_inv(dz);
+            oix = ox * ix; oiy = oy * iy; oiz = oz * iz;
             tfar = A.ray_tfar ? A.ray_tfar[r] : INFINITY;
             kbuf_reset(kb, A.k);
             tmin = 0;
@@ -557,7 +559,9 @@ __global__ void __launch_bounds__(kTraceBlock)
           STAT(GRTX_STAT_NODES);
           const float tlo = fmaxf(tnear, key_t(tmin));
           const float Ax = q0.w * ix, Ay = q1.x * iy, Az = q1.y * iz;
-          const float Bx = (q0.x - ox) * ix, By = (q0.y - oy) * iy, Bz = (q0.z - oz) * iz;
+          // (record origin - ray origin) * inv as one fma per axis; the rounding differs from
+          // the subtract-then-multiply form by a few ulps, far inside the leaf boxes' padding
+          const float Bx = fmaf(q0.x, ix, -oix), By = fmaf(q0.y, iy, -oiy), Bz = fmaf(q0.z, iz, -oiz);
           const uint32_t wlx = __float_as_uint(q2.z), wly = __float_as_uint(q2.w), wlz = __float_as_uint(q3.x);
           const uint32_t whx = __float_as_uint(q3.y), why = __float_as_uint(q3.z), whz = __float_as_uint(q3.w);
           // The entry plane of an axis is the low one where the ray's direction is positive
@@ -579,7 +583,7 @@ __global__ void __launch_bounds__(kTraceBlock)
             const float tn = fmaxf(fmaxf(tnx, tny), tnz);
             const float tf = fminf(fminf(fminf(tfx, tfy), tfz), tfar);
             const float te = fmaxf(tn, cur_t);
-            bool v = c[j] != kNoChild && tn <= tf && tf >= tlo;
+            bool v = c[j] != kNoChild && fmaxf(tn, tlo) <= tf;  // entered, and not ended before tlo
             if (v && te > tmax_t) {
               defer(c[j], te);
               v = false;
@@ -763,6 +767,7 @@ __global__ void __launch_bounds__(kTraceBlock)
         ox = no[0]; oy = no[1]; oz = no[2];
         dx = nd[0]; dy = nd[1]; dz = nd[2];
         ix = safe_inv(dx); iy = safe_inv(dy); iz = safe_inv(dz);
+        oix = ox * ix; oiy = oy * iy; oiz = oz * iz;
         Dp = fmaf(A.ray_path[ray], T, Dp);
         tfar = INFINITY;
         tmin = 0;
