@@ -310,9 +310,13 @@ __device__ __forceinline__ int prefix_len(const uint64_t* __restrict__ codes, in
 
 __global__ void __launch_bounds__(kBlock) k_karras(const uint64_t* __restrict__ codes, int64_t n,
                                                    uint32_t* __restrict__ child, uint32_t* __restrict__ parent,
-                                                   uint2* __restrict__ range) {
+                                                   uint2* __restrict__ range, uint32_t* __restrict__ count,
+                                                   uint32_t* __restrict__ arrivals) {
   int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   if (i >= n - 1) return;
+  // the refit's arrival counters (n - 1 nodes, then the ready-list length) start at zero
+  arrivals[i] = 0u;
+  if (i == 0) arrivals[n - 1] = 0u;
   int d = prefix_len(codes, n, i, i + 1) - prefix_len(codes, n, i, i - 1) > 0 ? 1 : -1;
   int dmin = prefix_len(codes, n, i, i - d);
   int64_t lmax = 2;
@@ -348,6 +352,7 @@ __global__ void __launch_bounds__(kBlock) k_karras(const uint64_t* __restrict__ 
   child[2 * i] = left;
   child[2 * i + 1] = right;
   range[i] = make_uint2((uint32_t)lo, (uint32_t)hi);
+  count[i] = (uint32_t)(hi - lo + 1);  // leaves below the node
   if (i == 0) parent[0] = kNoParent;
 }
 
@@ -1075,11 +1080,6 @@ __global__ void k_subtree_roots(int64_t nn, const uint32_t* __restrict__ flag, c
   if (flag[i]) roots[pos[i]] = (uint32_t)i;
 }
 
-__global__ void __launch_bounds__(kBlock) k_range_count(int64_t nint, const uint2* __restrict__ range,
-                                                        uint32_t* __restrict__ count) {
-  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (i < nint) count[i] = range[i].y - range[i].x + 1u;
-}
 
 // Cut of the tree for per-tile cost estimates of image traces (the trace takes the
 // heaviest tiles first): every node of at most `cut` leaves whose parent has more (or that
@@ -1332,13 +1332,11 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
   }
   if (nint > 0) {
     hipLaunchKernelGGL(k_karras, dim3(grid_for(nint)), dim3(kBlock), 0, s, b->codes, m, b->child, b->parent,
-                       range);
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nint + 1)), dim3(kBlock), 0, s, arrivals, nint + 1, 0u);
+                       range, count, arrivals);
     hipLaunchKernelGGL(k_refit_small, dim3(grid_for(nint)), dim3(kBlock), 0, s, m, b->child, range, b->boxes,
                        ready, arrivals + nint);
     hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(kTopBlock), 0, s, m, b->child, b->parent, range, b->boxes,
                        ready, arrivals + nint, arrivals);
-    hipLaunchKernelGGL(k_range_count, dim3(grid_for(nint)), dim3(kBlock), 0, s, nint, range, count);
     if (restructure_tree && nint > 1 && 2 * m - 1 <= (int64_t)kScanChunk * kScanChunk) {
       const int64_t nn = 2 * m - 1;
       uint32_t *rflag = nullptr, *rpos = nullptr, *roots = nullptr, *nroots = nullptr;
