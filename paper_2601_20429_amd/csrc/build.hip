@@ -808,7 +808,7 @@ __device__ __forceinline__ uint32_t ref_of(uint32_t u, int64_t nint) {
 
 // Per-thread work arrays of the subset dynamic programme live in LDS, entry-major
 // ([entry][thread]), so that lanes index them independently.
-constexpr int kSubtreeLeaves = 128;  // 256-leaf runs built the 3M tree 4% slower (100k: same)
+constexpr int kSubtreeLeaves = 256;
 constexpr int kSets = 1 << kTreeletLeaves;
 struct TreeletLds {
   float copt[kSets][kSubtreeLeaves];
@@ -1353,7 +1353,7 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
       int dev = 0, cus = 0;
       GRTX_HIP(hipGetDevice(&dev));
       GRTX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-      hipLaunchKernelGGL(k_treelet, dim3(std::max(1, 8 * cus)), dim3(kSubtreeLeaves), 0, s, m, roots, nroots,
+      hipLaunchKernelGGL(k_treelet, dim3(std::max(1, 4 * cus)), dim3(kSubtreeLeaves), 0, s, m, roots, nroots,
                          nroots + 1, range, b->child, b->parent, b->boxes, sah, count);
       if (m > kTopPassLeaves) {
         hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nint + 1)), dim3(kBlock), 0, s, arrivals, nint + 1, 0u);
