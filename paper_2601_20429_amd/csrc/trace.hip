@@ -21,10 +21,12 @@
 //     idle lanes are refilled with a ballot + one atomic per wave; rays are taken in
 //     8x8 pixel tiles when the rays form an image;
 //   - the k-buffer is a register array of 64-bit keys (distance bits << 32 | leaf),
-//     kept sorted by a statically indexed compare-exchange chain;
+//     kept sorted; a key is inserted by comparing it with every entry at once (statically
+//     indexed, no dependent chain);
 //   - the traversal stack is per lane: the top kLdsStack entries in LDS, the rest in a
-//     per-wave HBM region; checkpoint and eviction lists are per-lane HBM lists laid out
-//     [entry][lane] per wave, so lanes that walk their lists in step read whole rows;
+//     per-wave HBM region, where each lane also keeps its checkpoint and eviction lists
+//     in a contiguous block of its own (its appends and reads walk its own cache lines);
+//     k-buffers are parked there [entry][lane] for the blend;
 //   - hit keys use the leaf's sorted position, whose Morton order keeps neighbouring
 //     Gaussians close in memory; ties in distance are broken by that position.
 #include <hip/hip_runtime.h>
@@ -65,7 +67,9 @@ constexpr int kRefillThreshold = GRTX_REFILL_THRESHOLD;  // idle lanes that end 
 #ifndef GRTX_CHUNKS
 #define GRTX_CHUNKS 1
 #endif
-constexpr int kChunks = GRTX_CHUNKS;  // one per XCD
+// Work queues. One shared queue keeps a launch's heaviest-first order; one per XCD (8)
+// measured slower.
+constexpr int kChunks = GRTX_CHUNKS;
 constexpr uint64_t kEmptyKey = (0x7F800000ull << 32) | 0xFFFFFFFFull;  // (+inf, max)
 
 enum : int { kIdle = 0, kTrav = 1, kEnd = 2 };
@@ -248,10 +252,6 @@ __device__ __forceinline__ bool proxy_hit(float4 A4, float4 B4, float4 C4, float
   return sAB <= 0.f && sBC <= 0.f && sCA <= 0.f && sum < 0.f;
 }
 
-// Occupancy target: three waves per SIMD for k <= 16 (168 VGPRs, no spills of note);
-// one wave for larger buffers, which lets the compiler keep the k-buffer and its
-// insertion copies in registers and AGPRs instead of scratch (k = 32: 16 ms against
-// 26 ms at two waves on the 100k-Gaussian frame; k = 64: 37 ms against 163 ms).
 // Leaf tests: unit sphere of an instance, a world-space proxy triangle, or the shared
 // icosahedron (inradius 1) of an instance.
 enum : int { kLeafSphere = 0, kLeafTri = 1, kLeafIco = 2 };
@@ -429,9 +429,10 @@ __global__ void __launch_bounds__(kTraceBlock)
   while (true) {
     KernArgs& A = kernel_args();
     // ---------------------------------------------------------------- refill idle lanes
-    // The work items are split into kChunks contiguous chunks (bands of 8x8 tiles). A
-    // wave starts on the chunk of its XCD (workgroups are dealt round-robin to the 8 XCDs)
-    // and moves on to the next chunk when its own is drained.
+    // The work items are split into kChunks contiguous chunks, each with its own counter
+    // (one chunk by default). With several, a wave starts on chunk blockIdx % kChunks
+    // (workgroups are dealt round-robin to the 8 XCDs) and moves on to the next chunk when
+    // its own is drained.
     if (!exhausted) {
       uint64_t idle = __ballot(state == kIdle);
       if (idle) {
@@ -649,7 +650,7 @@ __global__ void __launch_bounds__(kTraceBlock)
         }
         // any-hit: keys beyond the farthest entry of a full k-buffer are rejected into
         // the eviction list; otherwise the key is inserted and the entry it pushes out of
-        // a full buffer is evicted. The chain runs under a wave-uniform branch with the
+        // a full buffer is evicted. The insertion runs under a wave-uniform branch with the
         // empty key (a no-op) on lanes without a key, so the registers update in place.
         const bool ins = have_key && key <= tmax;
         if (__ballot(ins)) {
@@ -670,7 +671,7 @@ __global__ void __launch_bounds__(kTraceBlock)
       // loop indexes memory rather than a register array.
       const uint64_t last = kb[K - 1];
       // The base gets an offset that passes through an empty asm statement (it is zero), so
-      // that the compiler cannot hoist the sixteen entry addresses out of the ray loop
+      // that the compiler cannot hoist the K entry addresses out of the ray loop
       // (where they would be spilled); the offsets fold into the store and load
       // instructions, and the pointer stays a global one.
       int opaque_zero = 0;
