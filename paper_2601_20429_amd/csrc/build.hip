@@ -9,6 +9,11 @@
 //   radix tree over the sorted (code, position) keys (Karras 2012, one thread per node)
 //   leaf records and leaf boxes in sorted order
 //   bottom-up refit with per-node arrival counters (exact min/max)
+//   treelet restructuring by surface-area cost (5-leaf treelets, one workgroup per subtree
+//     of at most 256 leaves, the nodes above in a second pass beyond a million leaves),
+//     unless the plain radix tree is asked for
+//   collapse to four-wide quantised node records, and a subtree cut kept for the trace's
+//     per-tile cost estimates
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
