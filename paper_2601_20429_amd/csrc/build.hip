@@ -534,18 +534,21 @@ __global__ void __launch_bounds__(kBlock) k_proxy_leaves(const uint32_t* __restr
 // ------------------------------------------------------------------ refit
 
 // Refit in two phases. An internal node of the radix tree covers a contiguous range of
-// sorted leaves. "Small" nodes (at most kRefitSmall leaves) take their children's boxes
+// sorted leaves. "Small" nodes (at most `small` leaves) take their children's boxes
 // straight from the leaf boxes of the two sub-ranges: no ordering between threads is
 // needed. The few "top" nodes above them are refitted bottom-up by one workgroup, which
 // orders its threads with workgroup-scope atomics; a grid-wide bottom-up pass would need a
 // device-scope fence per node, which on a multi-XCD part writes back the whole L2.
-constexpr int64_t kRefitSmall = 128;
+// The limit grows with the tree: 128 leaves up to a million leaves; 1024 above, where the
+// top phase would otherwise walk tens of thousands of nodes in one workgroup (at 3M leaves
+// the two phases took 0.24 + 0.71 ms with 128, 0.58 + 0.10 ms with 1024).
+inline int64_t refit_small_limit(int64_t m) { return m > ((int64_t)1 << 20) ? 1024 : 128; }
 constexpr int kTopBlock = 1024;
 
-__device__ __forceinline__ bool is_small(uint32_t c, const uint2* __restrict__ range) {
+__device__ __forceinline__ bool is_small(uint32_t c, const uint2* __restrict__ range, int64_t small) {
   if (c & kLeafFlag) return true;
   uint2 r = range[c];
-  return (int64_t)r.y - r.x + 1 <= kRefitSmall;
+  return (int64_t)r.y - r.x + 1 <= small;
 }
 
 __device__ __forceinline__ void range_box(const float* __restrict__ leaf_boxes, uint32_t lo, uint32_t hi, float b[6]) {
@@ -588,13 +591,13 @@ __device__ __forceinline__ void write_box(float* __restrict__ boxes, uint32_t no
 __global__ void __launch_bounds__(kBlock) k_refit_small(int64_t n, const uint32_t* __restrict__ child,
                                                         const uint2* __restrict__ range, float* __restrict__ boxes,
                                                         uint32_t* __restrict__ ready,
-                                                        uint32_t* __restrict__ n_ready) {
+                                                        uint32_t* __restrict__ n_ready, int64_t small) {
   const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   bool top_ready = false;
   if (i < n - 1) {
     const uint2 r = range[i];
     const uint32_t c0 = child[2 * i], c1 = child[2 * i + 1];
-    if ((int64_t)r.y - r.x + 1 <= kRefitSmall) {
+    if ((int64_t)r.y - r.x + 1 <= small) {
       const uint32_t split = c0 & ~kLeafFlag;  // last leaf of the left child
       float b0[6], b1[6];
       const float* leaf_boxes = boxes + (n - 1) * 6;
@@ -602,7 +605,7 @@ __global__ void __launch_bounds__(kBlock) k_refit_small(int64_t n, const uint32_
       range_box(leaf_boxes, split + 1, r.y, b1);
       write_box(boxes, (uint32_t)i, b0, b1);
     } else {
-      top_ready = is_small(c0, range) && is_small(c1, range);
+      top_ready = is_small(c0, range, small) && is_small(c1, range, small);
     }
   }
   const uint64_t m = __ballot(top_ready);
@@ -629,7 +632,7 @@ __global__ void __launch_bounds__(kTopBlock) k_refit_top(int64_t n, const uint32
                                                          const uint2* __restrict__ range, float* boxes,
                                                          const uint32_t* __restrict__ ready,
                                                          const uint32_t* __restrict__ n_ready,
-                                                         uint32_t* __restrict__ arrivals) {
+                                                         uint32_t* __restrict__ arrivals, int64_t small) {
   const uint32_t cnt = *n_ready;
   for (uint32_t w = threadIdx.x; w < cnt; w += kTopBlock) {
     uint32_t node = ready[w];
@@ -641,7 +644,8 @@ __global__ void __launch_bounds__(kTopBlock) k_refit_top(int64_t n, const uint32
       write_box(boxes, node, b0, b1);
       const uint32_t p = parent[node];
       if (p == kNoParent) break;
-      const bool two = !is_small(child[2 * (int64_t)p], range) && !is_small(child[2 * (int64_t)p + 1], range);
+      const bool two =
+          !is_small(child[2 * (int64_t)p], range, small) && !is_small(child[2 * (int64_t)p + 1], range, small);
       // release this node's box to the sibling's thread; acquire the sibling's box
       if (two && __hip_atomic_fetch_add(&arrivals[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == 0u)
         break;
@@ -1339,9 +1343,9 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
     hipLaunchKernelGGL(k_karras, dim3(grid_for(nint)), dim3(kBlock), 0, s, b->codes, m, b->child, b->parent,
                        range, count, arrivals);
     hipLaunchKernelGGL(k_refit_small, dim3(grid_for(nint)), dim3(kBlock), 0, s, m, b->child, range, b->boxes,
-                       ready, arrivals + nint);
+                       ready, arrivals + nint, refit_small_limit(m));
     hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(kTopBlock), 0, s, m, b->child, b->parent, range, b->boxes,
-                       ready, arrivals + nint, arrivals);
+                       ready, arrivals + nint, arrivals, refit_small_limit(m));
     if (restructure_tree && nint > 1 && 2 * m - 1 <= (int64_t)kScanChunk * kScanChunk) {
       const int64_t nn = 2 * m - 1;
       uint32_t *rflag = nullptr, *rpos = nullptr, *roots = nullptr, *nroots = nullptr;
