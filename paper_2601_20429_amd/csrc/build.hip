@@ -816,22 +816,29 @@ __device__ __forceinline__ uint32_t ref_of(uint32_t u, int64_t nint) {
 }
 
 // Per-thread work arrays of the subset dynamic programme live in LDS, entry-major
-// ([entry][thread]), so that lanes index them independently.
-constexpr int kSubtreeLeaves = 256;
+// ([entry][thread]), so that lanes index them independently; NS threads per workgroup,
+// one per leaf of its subtree.
 constexpr int kSets = 1 << kTreeletLeaves;
+template <int NS>
 struct TreeletLds {
-  float copt[kSets][kSubtreeLeaves];
-  uint8_t split[kSets][kSubtreeLeaves];
-  int stack_set[kTreeletLeaves][kSubtreeLeaves];
-  uint32_t stack_node[kTreeletLeaves][kSubtreeLeaves];
+  float copt[kSets][NS];
+  uint8_t split[kSets][NS];
+  int stack_set[kTreeletLeaves][NS];
+  uint32_t stack_node[kTreeletLeaves][NS];
 };
+// Subtree size of the per-subtree pass: 256 leaves, 128 above a million leaves. Smaller
+// subtrees give shorter bottom-up chains and twice the workgroups per CU (at 3M leaves the
+// two passes took 1.43 + 0.30 ms against 1.59 + 0.23 ms, trace time unchanged), but leave
+// more nodes above them untouched where no second pass runs (100k: 0.7% more node visits
+// per ray).
+inline int subtree_leaves(int64_t m) { return m > ((int64_t)1 << 20) ? 128 : 256; }
 
 // Subset dynamic programme over NL treelet leaves, unrolled at compile time so that every
 // subset and split index is a constant (the costs stay in registers); the chosen splits and
 // costs then go to the thread's LDS column for the rebuild.
-template <int NL>
+template <int NL, class Lds>
 __device__ __forceinline__ void treelet_dp(const float (&lb)[kTreeletLeaves][6], const float (&lcost)[kTreeletLeaves],
-                                           TreeletLds& L, int tid) {
+                                           Lds& L, int tid) {
   float copt[1 << NL];
 #pragma unroll
   for (int S = 1; S < (1 << NL); ++S) {
@@ -867,9 +874,10 @@ __device__ __forceinline__ void treelet_dp(const float (&lb)[kTreeletLeaves][6],
   }
 }
 
+template <class Lds>
 __device__ __forceinline__ void restructure(uint32_t p, int64_t nint, uint32_t* __restrict__ child, uint32_t* __restrict__ parent,
                             float* __restrict__ boxes, float* __restrict__ cost, uint32_t* __restrict__ count,
-                            TreeletLds& L, int tid) {
+                            Lds& L, int tid) {
   // treelet leaves (registers, constant indices only) and its internal nodes
   uint32_t leaf[kTreeletLeaves], inner[kTreeletLeaves - 1];
   float larea[kTreeletLeaves];
@@ -1004,22 +1012,23 @@ __device__ __forceinline__ void restructure(uint32_t p, int64_t nint, uint32_t* 
   }
 }
 
-// The pass runs per subtree of at most kSubtreeLeaves leaves whose parent has more (the
+// The pass runs per subtree of at most NS leaves whose parent has more (the
 // nodes above keep the radix tree's topology): one workgroup takes a subtree, its threads
 // its leaves (a contiguous run [lo, hi] of sorted positions). The subtree's internal nodes
 // are exactly the indices lo..hi-1 of the radix tree (each internal node is numbered after
 // one end of its range), and restructuring only permutes them, so the arrival counters of
 // the bottom-up hand-over sit in LDS at index - lo, ordered with workgroup-scope fences.
 // Workgroups draw subtrees from a queue.
-__global__ void __launch_bounds__(kSubtreeLeaves) k_treelet(int64_t m, const uint32_t* __restrict__ roots,
+template <int NS>
+__global__ void __launch_bounds__(NS) k_treelet(int64_t m, const uint32_t* __restrict__ roots,
                                                             const uint32_t* __restrict__ n_roots,
                                                             unsigned int* __restrict__ queue,
                                                             const uint2* __restrict__ range, uint32_t* child,
                                                             uint32_t* parent, float* boxes, float* cost,
                                                             uint32_t* count) {
-  __shared__ TreeletLds L;
+  __shared__ TreeletLds<NS> L;
   __shared__ uint32_t s_item;
-  __shared__ uint32_t s_arrive[kSubtreeLeaves];
+  __shared__ uint32_t s_arrive[NS];
   const int64_t nint = m - 1;
   const uint32_t nr = *n_roots;
   const int tid = threadIdx.x;
@@ -1041,7 +1050,7 @@ __global__ void __launch_bounds__(kSubtreeLeaves) k_treelet(int64_t m, const uin
         uint32_t p = parent[u];
         while (true) {
           // the first thread to arrive leaves; the second sees both subtrees
-          if ((uint64_t)((int64_t)p - lo) >= (uint64_t)kSubtreeLeaves) break;  // outside the run: never
+          if ((uint64_t)((int64_t)p - lo) >= (uint64_t)NS) break;  // outside the run: never
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
           if (atomicAdd(&s_arrive[p - lo], 1u) == 0u) break;
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -1061,14 +1070,15 @@ __global__ void __launch_bounds__(kSubtreeLeaves) k_treelet(int64_t m, const uin
 // it. Threads of different workgroups hand over here, so the counters are agent-scope
 // atomics in global memory.
 constexpr int64_t kTopPassLeaves = (int64_t)1 << 20;
-__global__ void __launch_bounds__(kSubtreeLeaves) k_treelet_top(int64_t m, const uint32_t* __restrict__ roots,
+template <int NS>
+__global__ void __launch_bounds__(NS) k_treelet_top(int64_t m, const uint32_t* __restrict__ roots,
                                                                 const uint32_t* __restrict__ n_roots,
                                                                 uint32_t* child, uint32_t* parent, float* boxes,
                                                                 float* cost, uint32_t* count,
                                                                 uint32_t* arrivals) {
-  __shared__ TreeletLds L;
+  __shared__ TreeletLds<NS> L;
   const int tid = threadIdx.x;
-  const int64_t k = blockIdx.x * (int64_t)kSubtreeLeaves + tid;
+  const int64_t k = blockIdx.x * (int64_t)NS + tid;
   if (k >= (int64_t)*n_roots) return;
   const int64_t nint = m - 1;
   uint32_t p = parent[roots[k]];
@@ -1354,21 +1364,32 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
       GRTX_TRY(sc.get(&rpos, nn));
       GRTX_TRY(sc.get(&roots, m));
       GRTX_TRY(sc.get(&nroots, 2));  // count, then the work queue
+      const int ns = subtree_leaves(m);
       hipLaunchKernelGGL(k_cut_flags, dim3(grid_for(nn)), dim3(kBlock), 0, s, nn, nint, b->parent, count,
-                         (uint32_t)kSubtreeLeaves, rflag);
+                         (uint32_t)ns, rflag);
       GRTX_TRY(exclusive_scan_u32(rflag, rpos, nn, s));
       hipLaunchKernelGGL(k_subtree_roots, dim3(grid_for(nn)), dim3(kBlock), 0, s, nn, rflag, rpos, roots, nroots);
       hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, s, nroots + 1, 1, 0u);
       int dev = 0, cus = 0;
       GRTX_HIP(hipGetDevice(&dev));
       GRTX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-      hipLaunchKernelGGL(k_treelet, dim3(std::max(1, 4 * cus)), dim3(kSubtreeLeaves), 0, s, m, roots, nroots,
-                         nroots + 1, range, b->child, b->parent, b->boxes, sah, count);
+      // workgroups: four per CU at 256 threads, eight at 128 (the queue hands out subtrees)
+      const unsigned groups = (unsigned)std::max(1, 4 * cus * (256 / ns));
+      if (ns == 256)
+        hipLaunchKernelGGL(k_treelet<256>, dim3(groups), dim3(256), 0, s, m, roots, nroots, nroots + 1, range,
+                           b->child, b->parent, b->boxes, sah, count);
+      else
+        hipLaunchKernelGGL(k_treelet<128>, dim3(groups), dim3(128), 0, s, m, roots, nroots, nroots + 1, range,
+                           b->child, b->parent, b->boxes, sah, count);
       if (m > kTopPassLeaves) {
         hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nint + 1)), dim3(kBlock), 0, s, arrivals, nint + 1, 0u);
-        hipLaunchKernelGGL(k_treelet_top, dim3((unsigned)((m + kSubtreeLeaves - 1) / kSubtreeLeaves)),
-                           dim3(kSubtreeLeaves), 0, s, m, roots, nroots, b->child, b->parent, b->boxes, sah, count,
-                           arrivals);
+        const unsigned top_groups = (unsigned)((m + ns - 1) / ns);
+        if (ns == 256)
+          hipLaunchKernelGGL(k_treelet_top<256>, dim3(top_groups), dim3(256), 0, s, m, roots, nroots, b->child,
+                             b->parent, b->boxes, sah, count, arrivals);
+        else
+          hipLaunchKernelGGL(k_treelet_top<128>, dim3(top_groups), dim3(128), 0, s, m, roots, nroots, b->child,
+                             b->parent, b->boxes, sah, count, arrivals);
       }
     }
     hipLaunchKernelGGL(k_wide, dim3(grid_for(nint)), dim3(kBlock), 0, s, m, b->child, b->boxes, b->nodes);
