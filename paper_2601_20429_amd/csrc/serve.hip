@@ -357,7 +357,12 @@ grtx_status launch_batch(Server* sv, Server::Slot& slot, const std::vector<uint6
 
 void admit_locked(Server* sv) {
   while (!sv->queued.empty()) {
-    auto& r = sv->reqs[sv->queued.front()];
+    auto it = sv->reqs.find(sv->queued.front());
+    if (it == sv->reqs.end()) {  // released while queued
+      sv->queued.pop_front();
+      continue;
+    }
+    auto& r = it->second;
     if (sv->in_use + r.bytes > sv->available) break;  // first come, first served
     void* q = nullptr;
     if (hipMalloc(&q, sizeof(float) * 5 * r.rays) != hipSuccess) break;
@@ -572,6 +577,12 @@ grtx_status serve_release(Server* sv, uint64_t ticket) {
   if (it->second.state == 1 || it->second.state == 2) {
     set_error("grtx_serve_release: request %llu is still in flight", (unsigned long long)ticket);
     return GRTX_ERR_NOT_READY;
+  }
+  if (it->second.state == 0) {
+    // withdrawn before admission: it leaves the queue and is never launched or counted
+    auto q = std::find(sv->queued.begin(), sv->queued.end(), ticket);
+    if (q != sv->queued.end()) sv->queued.erase(q);
+    --sv->submitted;
   }
   if (it->second.out) {
     GRTX_HIP(hipFree(it->second.out));
