@@ -485,7 +485,7 @@ def main():
     sout = grtx.trace(bvh, oo, dd, k=args.k, T_min=cfg["T_min"], mode=mode, image_width=cam.width, stats=True)
     torch.cuda.synchronize()
     stt = sout["stats"].to(torch.int64).sum(0).cpu().numpy()
-    nodes, leaves, rounds, blended, deferred, free, evicted, fallbacks = [int(x) for x in stt]
+    nodes, leaves, rounds, blended, deferred, free, evicted, fallbacks = [int(x) for x in stt[:8]]
     alg_bytes = (B_NODE * nodes + B_LEAF * leaves + (B_BLEND_INST + 4 * 3 * (scene.sh_degree + 1) ** 2) * blended
                  + B_LIST * (deferred + evicted) + B_RAY * R)
     achieved = alg_bytes / (k_mean * 1e-3) / 1e9

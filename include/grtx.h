@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define GRTX_VERSION 2
+#define GRTX_VERSION 3
 
 typedef enum grtx_status {
   GRTX_OK = 0,
@@ -90,12 +90,22 @@ typedef struct grtx_gaussians {
  * topology grtx_bvh_export_topology then reports is the plain Karras tree of the sorted
  * Morton codes); 0 (default) rebuilds small treelets of it bottom-up into the topology of
  * least surface-area cost. Leaves keep their sorted order either way, and traced results
- * are identical; only the internal nodes, and so the work per ray, differ. */
+ * are identical; only the internal nodes, and so the work per ray, differ.
+ * max_depth: the deepest tree the build keeps, in internal nodes on a root-to-leaf path
+ * (0 = GRTX_MAX_TREE_DEPTH, the depth the trace's traversal stack is sized for; at most
+ * that). The plain radix tree over distinct 95-bit (Morton code, position) keys is never
+ * deeper than 96; a restructured tree that comes out deeper is replaced on the device by
+ * the plain one (grtx_bvh_info reports which). */
 typedef struct grtx_build_params {
   float alpha_min;
   int32_t plain_lbvh;
-  int32_t reserved[2];
+  int32_t max_depth;
+  int32_t reserved;
 } grtx_build_params;
+
+/* Deepest tree the trace supports: its per-lane stack holds 3 * GRTX_MAX_TREE_DEPTH + 16
+ * entries, and a four-wide record leaves at most three entries pending per level. */
+#define GRTX_MAX_TREE_DEPTH 96
 
 typedef struct grtx_bvh grtx_bvh;
 
@@ -109,6 +119,9 @@ typedef struct grtx_bvh_info {
   float alpha_min;
   float root_lo[3];       /* filled only after the build has completed on its stream */
   float root_hi[3];
+  int32_t depth;          /* internal nodes on the longest root-to-leaf path (0: < 2 leaves) */
+  int32_t restructured;   /* 1: treelet-restructured tree; 0: plain radix tree (asked for,
+                             or the restructured tree exceeded max_depth) */
 } grtx_bvh_info;
 
 /* Rays: device origins [count,3] and unit-length directions [count,3], float32.
@@ -169,7 +182,9 @@ enum {
   GRTX_STAT_FETCH_FREE = 5, /* checkpoint entries carried forward without a fetch */
   GRTX_STAT_EVICTED = 6,    /* hits written to the eviction list */
   GRTX_STAT_FALLBACKS = 7,  /* rounds restarted from the root after a list overflow */
-  GRTX_STATS_FIELDS = 8
+  GRTX_STAT_STACK_DROPS = 8, /* traversal-stack entries lost to a full stack; zero for every
+                                tree the build keeps (depth <= GRTX_MAX_TREE_DEPTH) */
+  GRTX_STATS_FIELDS = 9
 };
 
 /* Outputs, all caller-owned device memory:
@@ -209,8 +224,8 @@ typedef struct grtx_camera {
 grtx_status grtx_build(const grtx_gaussians* g, grtx_bvh_kind kind, const grtx_build_params* p,
                        void* stream, grtx_bvh** out);
 
-/* Sizes and bounds of a built structure (host out-param). Synchronises `bvh`'s build
- * stream to read the root bounds. */
+/* Sizes, bounds and depth of a built structure (host out-param). Synchronises `bvh`'s
+ * build stream to read the root bounds and the depth. */
 grtx_status grtx_bvh_get_info(const grtx_bvh* bvh, grtx_bvh_info* out);
 
 /* Copy the topology into caller-owned DEVICE buffers (each may be NULL to skip):

@@ -49,6 +49,8 @@ grtx_status grtx_build(const grtx_gaussians* g, grtx_bvh_kind kind, const grtx_b
   CHECK_ARG(kind == GRTX_BVH_SPHERE_INSTANCE || kind == GRTX_BVH_PROXY20 || kind == GRTX_BVH_ICO_INSTANCE,
             "grtx_build: unknown kind %d", (int)kind);
   CHECK_ARG(p->alpha_min > 0.f && p->alpha_min < 1.f, "grtx_build: alpha_min must be in (0,1)");
+  CHECK_ARG(p->max_depth >= 0 && p->max_depth <= GRTX_MAX_TREE_DEPTH, "grtx_build: max_depth must be 0..%d",
+            GRTX_MAX_TREE_DEPTH);
   if (g->count > 0)
     CHECK_ARG(g->means && g->scales && g->quats && g->opacities && g->sh, "grtx_build: null Gaussian array");
   grtx_bvh* h = new (std::nothrow) grtx_bvh();
@@ -57,7 +59,8 @@ grtx_status grtx_build(const grtx_gaussians* g, grtx_bvh_kind kind, const grtx_b
     return GRTX_ERR_OUT_OF_MEMORY;
   }
   grtx_status st =
-      grtx::build_bvh(g, kind, p->alpha_min, p->plain_lbvh == 0, static_cast<hipStream_t>(stream), &h->impl);
+      grtx::build_bvh(g, kind, p->alpha_min, p->plain_lbvh == 0, p->max_depth > 0 ? p->max_depth : GRTX_MAX_TREE_DEPTH,
+                      static_cast<hipStream_t>(stream), &h->impl);
   if (st != GRTX_OK) {
     char msg[1024];
     std::strncpy(msg, grtx::g_err, sizeof msg - 1);
@@ -85,12 +88,16 @@ grtx_status grtx_bvh_get_info(const grtx_bvh* bvh, grtx_bvh_info* out) {
   info.alpha_min = b.alpha_min;
   if (b.n_leaves > 0) {
     float box[6];
+    uint32_t depth[2] = {0u, 0u};
     GRTX_HIP(hipStreamSynchronize(b.build_stream));
     GRTX_HIP(hipMemcpy(box, b.root_box, sizeof box, hipMemcpyDeviceToHost));
+    GRTX_HIP(hipMemcpy(depth, b.depth, sizeof depth, hipMemcpyDeviceToHost));
     for (int a = 0; a < 3; ++a) {
       info.root_lo[a] = box[a];
       info.root_hi[a] = box[3 + a];
     }
+    info.depth = (int32_t)depth[0];
+    info.restructured = (int32_t)depth[1];
   }
   *out = info;
   return GRTX_OK;

@@ -1140,6 +1140,73 @@ __global__ void __launch_bounds__(kBlock) k_fill_u32(uint32_t* p, int64_t n, uin
   if (i < n) p[i] = v;
 }
 
+// ------------------------------------------------------------------ tree depth
+// Depth of the tree in internal nodes on the longest root-to-leaf path, which bounds the
+// trace's traversal stack (a four-wide record leaves at most three entries pending per
+// level). One thread per leaf climbs towards the root carrying the number of internal
+// nodes below it on its path and raises the per-node maximum `h`; it stops where a path at
+// least as long has already been recorded, so most climbs end after a few steps. The
+// root is node 0. A climb longer than `cap` stops there and records cap + 1 at the root
+// (the tree is then too deep whatever its exact depth).
+__global__ void __launch_bounds__(kBlock) k_tree_height(int64_t m, const uint32_t* __restrict__ parent,
+                                                        uint32_t* __restrict__ h, int cap,
+                                                        const uint32_t* __restrict__ only_if) {
+  if (only_if && *only_if == 0u) return;
+  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i >= m) return;
+  uint32_t p = parent[(m - 1) + i];
+  uint32_t d = 1;
+  while (p != kNoParent) {
+    if (d > (uint32_t)cap) {
+      atomicMax(h, (uint32_t)cap + 1u);
+      return;
+    }
+    if (atomicMax(h + p, d) >= d) return;
+    ++d;
+    p = parent[p];
+  }
+}
+
+// Saved topology of the plain radix tree, put back when the restructured tree is deeper
+// than `max_depth` (the plain tree over distinct 95-bit keys is at most 96 deep): child,
+// parent, the internal boxes and leaf counts. `deep[0]` records the decision for the
+// later kernels, which also recompute the depth of the tree put back into `h2`.
+struct PlainTree {
+  const uint32_t* child;
+  const uint32_t* parent;
+  const float* boxes;
+  const uint32_t* count;
+};
+__global__ void __launch_bounds__(kBlock) k_restore_plain(int64_t m, const uint32_t* __restrict__ h, int max_depth,
+                                                          PlainTree saved, uint32_t* __restrict__ child,
+                                                          uint32_t* __restrict__ parent, float* __restrict__ boxes,
+                                                          uint32_t* __restrict__ count, uint32_t* __restrict__ h2,
+                                                          uint32_t* __restrict__ deep) {
+  const bool too_deep = h[0] > (uint32_t)max_depth;
+  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i == 0) deep[0] = too_deep ? 1u : 0u;
+  if (!too_deep) return;
+  const int64_t nint = m - 1;
+  if (i < nint) {
+    child[2 * i] = saved.child[2 * i];
+    child[2 * i + 1] = saved.child[2 * i + 1];
+    for (int a = 0; a < 6; ++a) boxes[6 * i + a] = saved.boxes[6 * i + a];
+    count[i] = saved.count[i];
+    h2[i] = 0u;
+  }
+  if (i < 2 * m - 1) parent[i] = saved.parent[i];
+}
+
+// Final depth and kind of the tree: out[0] = depth, out[1] = 1 if the restructured tree
+// was kept. `deep` and `h2` are null when no restructuring ran.
+__global__ void k_depth_store(const uint32_t* __restrict__ h, const uint32_t* __restrict__ deep,
+                              const uint32_t* __restrict__ h2, uint32_t* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  const bool restored = deep && deep[0] != 0u;
+  out[0] = restored ? h2[0] : h[0];
+  out[1] = deep && !restored ? 1u : 0u;
+}
+
 }  // namespace
 
 // Build over `n` points (centroids) whose leaf boxes/records are produced by `leaves`.
@@ -1257,7 +1324,7 @@ Scratch::~Scratch() {
 }
 
 grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_min, bool restructure_tree,
-                      hipStream_t s, Bvh* b) {
+                      int max_depth, hipStream_t s, Bvh* b) {
   b->kind = kind;
   b->n_gauss = g->count;
   b->sh_degree = g->sh_degree;
@@ -1286,6 +1353,7 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
     put(&b->roots, 8);
     put(&b->cut, 2 * (int64_t)kCutCap);
     put(&b->n_cut, 1);
+    put(&b->depth, 2);
   };
   size_t total = 0;
   layout([&](auto** p, int64_t count) {
@@ -1356,7 +1424,23 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
                        ready, arrivals + nint, refit_small_limit(m));
     hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(kTopBlock), 0, s, m, b->child, b->parent, range, b->boxes,
                        ready, arrivals + nint, arrivals, refit_small_limit(m));
-    if (restructure_tree && nint > 1 && 2 * m - 1 <= (int64_t)kScanChunk * kScanChunk) {
+    const bool restructure = restructure_tree && nint > 1 && 2 * m - 1 <= (int64_t)kScanChunk * kScanChunk;
+    PlainTree saved{};
+    if (restructure) {
+      // keep the plain tree in case the restructured one comes out too deep
+      uint32_t *sc_child = nullptr, *sc_parent = nullptr, *sc_count = nullptr;
+      float* sc_boxes = nullptr;
+      GRTX_TRY(sc.get(&sc_child, 2 * nint));
+      GRTX_TRY(sc.get(&sc_parent, 2 * m - 1));
+      GRTX_TRY(sc.get(&sc_boxes, 6 * nint));
+      GRTX_TRY(sc.get(&sc_count, nint));
+      GRTX_HIP(hipMemcpyAsync(sc_child, b->child, sizeof(uint32_t) * 2 * nint, hipMemcpyDeviceToDevice, s));
+      GRTX_HIP(hipMemcpyAsync(sc_parent, b->parent, sizeof(uint32_t) * (2 * m - 1), hipMemcpyDeviceToDevice, s));
+      GRTX_HIP(hipMemcpyAsync(sc_boxes, b->boxes, sizeof(float) * 6 * nint, hipMemcpyDeviceToDevice, s));
+      GRTX_HIP(hipMemcpyAsync(sc_count, count, sizeof(uint32_t) * nint, hipMemcpyDeviceToDevice, s));
+      saved = PlainTree{sc_child, sc_parent, sc_boxes, sc_count};
+    }
+    if (restructure) {
       const int64_t nn = 2 * m - 1;
       uint32_t *rflag = nullptr, *rpos = nullptr, *roots = nullptr, *nroots = nullptr;
       GRTX_TRY(sc.get(&sah, nn));
@@ -1392,9 +1476,24 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
                              b->parent, b->boxes, sah, count, arrivals);
       }
     }
+    // depth of the tree (the refit's arrival counters are free again and hold the heights)
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nint)), dim3(kBlock), 0, s, arrivals, nint, 0u);
+    hipLaunchKernelGGL(k_tree_height, dim3(grid_for(m)), dim3(kBlock), 0, s, m, b->parent, arrivals,
+                       restructure ? max_depth : GRTX_MAX_TREE_DEPTH, (const uint32_t*)nullptr);
+    uint32_t *deep = nullptr, *h2 = nullptr;
+    if (restructure) {
+      GRTX_TRY(sc.get(&deep, 1));
+      GRTX_TRY(sc.get(&h2, nint));
+      hipLaunchKernelGGL(k_restore_plain, dim3(grid_for(2 * m - 1)), dim3(kBlock), 0, s, m, arrivals, max_depth, saved,
+                         b->child, b->parent, b->boxes, count, h2, deep);
+      hipLaunchKernelGGL(k_tree_height, dim3(grid_for(m)), dim3(kBlock), 0, s, m, b->parent, h2, GRTX_MAX_TREE_DEPTH,
+                         deep);
+    }
+    hipLaunchKernelGGL(k_depth_store, dim3(1), dim3(64), 0, s, arrivals, deep, h2, b->depth);
     hipLaunchKernelGGL(k_wide, dim3(grid_for(nint)), dim3(kBlock), 0, s, m, b->child, b->boxes, b->nodes);
   } else {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, s, b->parent, 1, kNoParent);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, s, b->depth, 2, 0u);
   }
   hipLaunchKernelGGL(k_write_root, dim3(1), dim3(64), 0, s, b->root_box, m == 1 ? (kLeafFlag | 0u) : 0u, b->roots);
   if (2 * m - 1 > (int64_t)kScanChunk * kScanChunk) {

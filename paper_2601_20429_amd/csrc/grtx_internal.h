@@ -83,6 +83,7 @@ struct Bvh {
   float* roots = nullptr;    // device [8]: root box, root reference bits, 0
   float4* cut = nullptr;     // [kCutCap][2]: subtree boxes (lo, leaf count) (hi, 0), see k_cut_write
   uint32_t* n_cut = nullptr; // device [1]: entries of `cut` (may exceed kCutCap; read the minimum)
+  uint32_t* depth = nullptr; // device [2]: tree depth in internal nodes, 1 if restructured
   const float* opacities = nullptr; // borrowed
   const float* sh = nullptr;        // borrowed
   hipStream_t build_stream = nullptr;
@@ -127,7 +128,7 @@ void clear_error();
 // Host entry points implemented in the .hip sources
 // ---------------------------------------------------------------------------------------
 grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_min, bool restructure_tree,
-                      hipStream_t s, Bvh* b);
+                      int max_depth, hipStream_t s, Bvh* b);
 grtx_status export_topology(const Bvh* b, uint32_t* child, uint32_t* parent, uint64_t* morton, uint32_t* perm,
                             float* boxes, hipStream_t s);
 grtx_status pinhole_rays(const grtx_camera* cam, float* origins, float* dirs, hipStream_t s);

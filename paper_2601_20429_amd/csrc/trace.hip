@@ -58,10 +58,11 @@ namespace {
 constexpr int kTraceBlock = 256;
 constexpr int kWaves = kTraceBlock / 64;
 constexpr int kLdsStack = GRTX_LDS_STACK;  // per-lane stack entries held in LDS
-// A radix tree over 95-bit keys is at most 96 levels deep; a record's children lie one
-// to three levels below it, so a path visits at most 96 records, each leaving at most
-// three entries pending.
-constexpr int kMaxStack = 3 * 96 + 16;
+// The build keeps no tree deeper than GRTX_MAX_TREE_DEPTH internal nodes on a path (it
+// measures the restructured tree and falls back to the plain radix tree, at most 96 deep
+// over distinct 95-bit keys); a record's children lie one to three levels below it, so a
+// path visits at most that many records, each leaving at most three entries pending.
+constexpr int kMaxStack = 3 * GRTX_MAX_TREE_DEPTH + 16;
 constexpr int kSpillRows = kMaxStack - kLdsStack;
 constexpr int kRefillThreshold = GRTX_REFILL_THRESHOLD;  // idle lanes that end a traversal burst
 #ifndef GRTX_CHUNKS
@@ -402,12 +403,15 @@ __global__ void __launch_bounds__(kTraceBlock)
 
   auto push = [&](uint32_t ref, float t) __attribute__((always_inline)) {
     // At most three entries per visited record are pending (see kMaxStack), so
-    // sp < kMaxStack always; the bound keeps memory safe.
+    // sp < kMaxStack always; the bound keeps memory safe, and an entry it would drop is
+    // counted (GRTX_STAT_STACK_DROPS, zero on every tree the build keeps).
     uint2 e = make_uint2(ref, __float_as_uint(t));
     if (sp < kLdsStack)
       s_stack[sp * kTraceBlock + tid] = e;
     else if (sp < kMaxStack)
       LROW(sp - kLdsStack) = e;
+    else
+      STAT(GRTX_STAT_STACK_DROPS);
     sp = sp < kMaxStack ? sp + 1 : sp;
   };
 

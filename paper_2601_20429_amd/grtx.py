@@ -30,8 +30,9 @@ CHECKPOINT = 0
 RESTART = 1
 
 STAT_NODES, STAT_LEAVES, STAT_ROUNDS, STAT_BLENDED, STAT_DEFERRED, STAT_FETCH_FREE, STAT_EVICTED, \
-    STAT_FALLBACKS = range(8)
-STATS_FIELDS = 8
+    STAT_FALLBACKS, STAT_STACK_DROPS = range(9)
+STATS_FIELDS = 9
+MAX_TREE_DEPTH = 96
 OBJECT_NONE, OBJECT_MIRROR, OBJECT_GLASS, OBJECT_GLASS_TRAPPED = range(4)
 
 
@@ -47,13 +48,15 @@ class _Gaussians(C.Structure):
 
 
 class _BuildParams(C.Structure):
-    _fields_ = [("alpha_min", C.c_float), ("plain_lbvh", C.c_int32), ("reserved", C.c_int32 * 2)]
+    _fields_ = [("alpha_min", C.c_float), ("plain_lbvh", C.c_int32), ("max_depth", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class _BvhInfo(C.Structure):
     _fields_ = [("gaussians", C.c_int64), ("leaves", C.c_int64), ("internal_nodes", C.c_int64),
                 ("device_bytes", C.c_int64), ("kind", C.c_int32), ("sh_degree", C.c_int32),
-                ("alpha_min", C.c_float), ("root_lo", C.c_float * 3), ("root_hi", C.c_float * 3)]
+                ("alpha_min", C.c_float), ("root_lo", C.c_float * 3), ("root_hi", C.c_float * 3),
+                ("depth", C.c_int32), ("restructured", C.c_int32)]
 
 
 class _Rays(C.Structure):
@@ -230,7 +233,8 @@ class Bvh:
         _check(lib().grtx_bvh_get_info(self.handle, C.byref(inf)))
         return dict(gaussians=inf.gaussians, leaves=inf.leaves, internal_nodes=inf.internal_nodes,
                     device_bytes=inf.device_bytes, kind=inf.kind, sh_degree=inf.sh_degree,
-                    alpha_min=inf.alpha_min, root_lo=list(inf.root_lo), root_hi=list(inf.root_hi))
+                    alpha_min=inf.alpha_min, root_lo=list(inf.root_lo), root_hi=list(inf.root_hi),
+                    depth=inf.depth, restructured=inf.restructured)
 
     def export_topology(self, stream=None):
         inf = self.info()
@@ -247,12 +251,13 @@ class Bvh:
 
 
 def build(scene: SceneTensors, kind: int = SPHERE_INSTANCE, alpha_min: float = 1.0 / 255.0, stream=None,
-          plain_lbvh: bool = False) -> Bvh:
+          plain_lbvh: bool = False, max_depth: int = 0) -> Bvh:
     """grtx_build. plain_lbvh keeps the radix tree as the LBVH construction gives it (no
-    treelet restructuring); traced results are the same either way."""
+    treelet restructuring); traced results are the same either way. A restructured tree
+    deeper than max_depth (0 = MAX_TREE_DEPTH) is replaced by the plain one."""
     g = _Gaussians(scene.means.data_ptr(), scene.scales.data_ptr(), scene.quats.data_ptr(),
                    scene.opacities.data_ptr(), scene.sh.data_ptr(), scene.n, scene.sh_degree, 0)
-    p = _BuildParams(alpha_min, 1 if plain_lbvh else 0)
+    p = _BuildParams(alpha_min, 1 if plain_lbvh else 0, max_depth)
     h = C.c_void_p()
     _check(lib().grtx_build(C.byref(g), kind, C.byref(p), _stream(stream), C.byref(h)))
     return Bvh(h, scene, kind, alpha_min)
@@ -274,7 +279,7 @@ def trace(bvh: Bvh, origins: torch.Tensor, dirs: torch.Tensor, k: int = 16, T_mi
           out=None, stream=None, t_far: torch.Tensor = None, transmittance: torch.Tensor = None,
           continuation: dict = None):
     """Render rays; returns dict(rgb [R,3], depth [R], opacity [R], and optionally stats
-    [R,8] int32, hit_ids [R,cap] int32, hit_counts [R] int32). t_far [R] bounds the rays at
+    [R,9] int32, hit_ids [R,cap] int32, hit_counts [R] int32). t_far [R] bounds the rays at
     a surface; transmittance [R] is what each ray starts with (both optional float32).
     continuation: the dict of `object_rays` (next_o, next_d, path, kind); rays that reach
     their surface then go on along their continuation ray in the same launch."""

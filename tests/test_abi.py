@@ -29,7 +29,7 @@ def test_header_symbols_exported():
 
 def test_version_and_null_destroy():
     L = grtx.lib()
-    assert L.grtx_version() == 2
+    assert L.grtx_version() == 3
     assert L.grtx_bvh_destroy(None) == grtx.OK
 
 
@@ -48,6 +48,10 @@ def test_build_rejects_bad_arguments():
     bad = grtx._BuildParams(1.5)
     assert L.grtx_build(C.byref(g), 0, C.byref(bad), None, C.byref(h)) == grtx.ERR_INVALID_ARG
     assert L.grtx_build(C.byref(g), 7, C.byref(p), None, C.byref(h)) == grtx.ERR_INVALID_ARG
+    for md in (-1, grtx.MAX_TREE_DEPTH + 1):
+        bad = grtx._BuildParams(1.0 / 255.0, 0, md)
+        assert L.grtx_build(C.byref(g), 0, C.byref(bad), None, C.byref(h)) == grtx.ERR_INVALID_ARG
+        assert b"max_depth" in L.grtx_last_error()
     assert h.value is None  # out-param untouched
 
 
@@ -65,6 +69,7 @@ def test_trace_rejects_bad_arguments():
     prm = grtx._TraceParams(4, 1e-3, 0, (C.c_float * 3)(0, 0, 0), 0, 0)
     assert L.grtx_trace(fake, C.byref(rays), C.byref(prm), C.byref(out), None) == grtx.ERR_INVALID_ARG
     assert b"null" in L.grtx_last_error()
+
     cam = grtx._Camera((C.c_float * 3)(0, -3, 0), (C.c_float * 3)(0, 0, 0), (C.c_float * 3)(0, 0, 1), 60.0, 0, 4)
     assert L.grtx_pinhole_rays(C.byref(cam), C.c_void_p(1), C.c_void_p(1), None) == grtx.ERR_INVALID_ARG
 

@@ -81,6 +81,21 @@ def test_topology_bit_exact(case):
     assert (t["parent"].cpu().numpy().view(np.uint32) == ref["parent"]).all()
     info = bvh.info()
     assert info["leaves"] == n and info["internal_nodes"] == max(n - 1, 0)
+    assert info["restructured"] == 0 and info["depth"] == tree_depth(ref["child"], n)
+
+
+def tree_depth(child, n):
+    """Internal nodes on the longest root-to-leaf path of a tree given by its child array
+    (bit 31 = leaf), by a breadth-first walk from the root (node 0)."""
+    if n < 2:
+        return 0
+    child = np.asarray(child, np.uint32).reshape(-1, 2)
+    level, depth = np.array([0], np.int64), 0
+    while level.size:
+        depth += 1
+        c = child[level].ravel()
+        level = (c[(c & 0x80000000) == 0]).astype(np.int64)
+    return depth
 
 
 def _check_tree(t, n):
@@ -160,6 +175,67 @@ def test_restructured_tree_renders_identically(kind, n):
         fa = int(ra["stats"][:, grtx.STAT_NODES].sum())
         fb = int(rb["stats"][:, grtx.STAT_NODES].sum())
         say(dict(mode=mode, node_fetches_plain=fa, node_fetches_restructured=fb))
+
+
+@pytest.mark.parametrize("case", ["scene100k", "proxy100k", "scene1100k", "scene3m"])
+def test_tree_depth_within_stack_bound(case):
+    """The build measures the depth of the tree it keeps; every kept tree fits the trace's
+    traversal stack (3 entries per level), and traces over it lose no stack entry. The
+    measured depth equals a breadth-first walk of the exported child array."""
+    say("tree depth", case)
+    kind, n, seed = grtx.SPHERE_INSTANCE, 100_000, 2
+    if case == "proxy100k":
+        kind = grtx.PROXY20
+    elif case == "scene1100k":
+        n, seed = 1_100_000, 6
+    elif case == "scene3m":
+        n, seed = inputs.SCENE3M["n"], inputs.SCENE3M["seed"]
+    scene = inputs.cluster_scene(seed, n, 3)
+    bvh = build(scene, kind)
+    info = bvh.info()
+    t = bvh.export_topology()
+    torch.cuda.synchronize()
+    m = info["leaves"]
+    assert 0 < info["depth"] <= grtx.MAX_TREE_DEPTH
+    assert info["restructured"] == 1
+    assert info["depth"] == tree_depth(t["child"].cpu().numpy().view(np.uint32), m)
+    cam = inputs.orbit_camera(256, 256)
+    po, pd = grtx.pinhole_rays(cam)
+    io, id_ = (dev(a) for a in inputs.incoherent_rays(33, 16384))
+    drops = 0
+    for o, d, w in [(po, pd, cam.width), (io, id_, 0)]:
+        for mode in (grtx.CHECKPOINT, grtx.RESTART):
+            st = grtx.trace(bvh, o, d, k=16, T_min=T_MIN, mode=mode, image_width=w, stats=True)["stats"]
+            torch.cuda.synchronize()
+            drops += int(st[:, grtx.STAT_STACK_DROPS].sum())
+    say(dict(case=case, leaves=m, depth=info["depth"], stack_drops=drops))
+    assert drops == 0
+
+
+def test_too_deep_restructured_tree_falls_back_to_plain():
+    """A restructured tree deeper than the build's max_depth is replaced on the device by
+    the plain radix tree: the same topology and boxes as a plain build, identical images."""
+    say("depth fallback")
+    scene = inputs.cluster_scene(2, 100_000, 3)
+    plain = build(scene, plain_lbvh=True)
+    restr = build(scene)
+    dp, dr = plain.info()["depth"], restr.info()["depth"]
+    assert restr.info()["restructured"] == 1 and dr > 1
+    st = grtx.SceneTensors.from_scene(scene, "cuda")
+    fb = grtx.build(st, alpha_min=AMIN, max_depth=dr - 1)
+    info = fb.info()
+    say(dict(plain_depth=dp, restructured_depth=dr, fallback=info))
+    assert info["restructured"] == 0 and info["depth"] == dp
+    a, b = plain.export_topology(), fb.export_topology()
+    for key in ("child", "parent", "morton", "perm", "boxes"):
+        assert torch.equal(a[key], b[key]), key
+    cam = inputs.orbit_camera(128, 96)
+    o, d = grtx.pinhole_rays(cam)
+    ra = grtx.trace(plain, o, d, k=16, T_min=T_MIN, image_width=cam.width, hit_capacity=128)
+    rb = grtx.trace(fb, o, d, k=16, T_min=T_MIN, image_width=cam.width, hit_capacity=128)
+    torch.cuda.synchronize()
+    for key in ("rgb", "depth", "opacity", "hit_ids", "hit_counts"):
+        assert torch.equal(ra[key], rb[key]), key
 
 
 def test_boxes_conservative_and_tight():
