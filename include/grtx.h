@@ -258,6 +258,23 @@ grtx_status grtx_pinhole_rays(const grtx_camera* cam, float* origins, float* dir
 grtx_status grtx_trace(const grtx_bvh* bvh, const grtx_rays* rays, const grtx_trace_params* p,
                        const grtx_trace_outputs* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): grtx_trace with the same arguments,
+ * conventions and results (bit-identical outputs), except that it calls no allocator.
+ * Its working memory (the work counters and the per-wave checkpoint lists and stack spill)
+ * is a static array of GRTX_NOALLOC_SCRATCH_MB MiB that each device running the library
+ * holds from the library's first use on it until the process ends. As many persistent
+ * workgroups run as their lists fit in it (about 2.1 MiB per workgroup at k = 16 with
+ * the 256/128 default capacities, 5.8 MiB with 1024/256), so throughput can be below
+ * grtx_trace's; image rays are taken in row-major tile order. GRTX_ERR_CAPACITY when not
+ * even one workgroup's lists fit (lower defer_capacity / evict_capacity). Every call on a
+ * device uses that device's one array: calls that overlap on one device (different
+ * streams or threads without ordering between them) race and give wrong results; calls
+ * ordered on one stream are safe (each call resets the counters it uses). */
+#define GRTX_NOALLOC_SCRATCH_MB 512
+grtx_status grtx_trace_noalloc(const grtx_bvh* bvh, const grtx_rays* rays, const grtx_trace_params* p,
+                               const grtx_trace_outputs* out, void* stream);
+
 /* ---------------------------------------------------------------------------------------
  * Secondary rays: ray continuation at a surface (Sec. II-A), with the two objects of the
  * paper's secondary-ray experiment, a glass sphere and a rectangular mirror placed in

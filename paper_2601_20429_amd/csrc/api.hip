@@ -133,6 +133,41 @@ grtx_status grtx_pinhole_rays(const grtx_camera* cam, float* origins, float* dir
   return grtx::pinhole_rays(cam, origins, dirs, static_cast<hipStream_t>(stream));
 }
 
+// Host-side checks shared by grtx_trace and grtx_trace_noalloc.
+static grtx_status check_trace_args(const char* fn, const grtx_bvh* bvh, const grtx_rays* rays,
+                                    const grtx_trace_params* p, const grtx_trace_outputs* out) {
+  CHECK_ARG(bvh && rays && p && out, "%s: null argument", fn);
+  CHECK_ARG(rays->count >= 0 && rays->count < ((int64_t)1 << 40), "%s: bad ray count", fn);
+  CHECK_ARG(p->k >= 1 && p->k <= 64, "%s: k must be 1..64, got %d", fn, p->k);
+  CHECK_ARG(p->T_min >= 0.f && p->T_min < 1.f, "%s: T_min must be in [0,1)", fn);
+  CHECK_ARG(p->mode == GRTX_MODE_CHECKPOINT || p->mode == GRTX_MODE_RESTART, "%s: unknown mode %d", fn, p->mode);
+  CHECK_ARG(p->defer_capacity >= 0 && p->evict_capacity >= 0 && p->defer_capacity <= (1 << 20) &&
+                p->evict_capacity <= (1 << 20),
+            "%s: list capacities must be 0..2^20", fn);
+  CHECK_ARG(rays->t_near >= 0.f && std::isfinite(rays->t_near), "%s: t_near must be finite and >= 0", fn);
+  CHECK_ARG(rays->image_width >= 0, "%s: negative image width", fn);
+  {
+    const int nc = !!rays->next_origins + !!rays->next_dirs + !!rays->path + !!rays->kind;
+    CHECK_ARG(nc == 0 || nc == 4, "%s: give all four continuation arrays or none", fn);
+    CHECK_ARG(nc == 0 || (rays->t_far && rays->t_near == 0.f), "%s: continuation rays need t_far and t_near = 0",
+              fn);
+  }
+  if (rays->count > 0) {
+    CHECK_ARG(rays->origins && rays->dirs, "%s: null ray arrays", fn);
+    CHECK_ARG(out->rgb && out->depth && out->opacity, "%s: null output arrays", fn);
+    CHECK_ARG(!out->hit_ids || out->hit_capacity > 0, "%s: hit_ids given with hit_capacity <= 0", fn);
+  }
+  return GRTX_OK;
+}
+
+grtx_status grtx_trace_noalloc(const grtx_bvh* bvh, const grtx_rays* rays, const grtx_trace_params* p,
+                               const grtx_trace_outputs* out, void* stream) {
+  grtx::clear_error();
+  grtx_status st = check_trace_args("grtx_trace_noalloc", bvh, rays, p, out);
+  if (st != GRTX_OK) return st;
+  return grtx::trace_noalloc(&bvh->impl, rays, p, out, static_cast<hipStream_t>(stream));
+}
+
 grtx_status grtx_trace(const grtx_bvh* bvh, const grtx_rays* rays, const grtx_trace_params* p,
                        const grtx_trace_outputs* out, void* stream) {
   grtx::clear_error();

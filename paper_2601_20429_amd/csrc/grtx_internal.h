@@ -134,6 +134,10 @@ grtx_status export_topology(const Bvh* b, uint32_t* child, uint32_t* parent, uin
 grtx_status pinhole_rays(const grtx_camera* cam, float* origins, float* dirs, hipStream_t s);
 grtx_status trace(const Bvh* b, const grtx_rays* r, const grtx_trace_params* p, const grtx_trace_outputs* o,
                   hipStream_t s);
+// The same trace with every device buffer beyond the inputs and outputs taken from the
+// library's static per-device scratch (no allocation; row-major tile order).
+grtx_status trace_noalloc(const Bvh* b, const grtx_rays* r, const grtx_trace_params* p, const grtx_trace_outputs* o,
+                          hipStream_t s);
 
 // What the trace kernel reads of a scene, or of several scenes merged into one address
 // space (serving): then `ray_scene` gives each ray's scene and `roots` holds one root

@@ -34,6 +34,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <numeric>
 #include <tuple>
@@ -1042,8 +1043,50 @@ grtx_status trace(const Bvh* b, const grtx_rays* r, const grtx_trace_params* p, 
   return launch_trace(sc, r, p, o, s);
 }
 
+grtx_status launch_trace_in(const TraceScene& b, const grtx_rays* r, const grtx_trace_params* p,
+                            const grtx_trace_outputs* o, hipStream_t s, bool noalloc);
+
+// Scratch of the allocation-free entry point (grtx_trace_noalloc): the work counters in
+// the first 256 bytes, then the per-wave checkpoint regions. Each device that runs the
+// library holds its own copy until the process ends; calls on one device share it.
+constexpr size_t kNoAllocBytes = (size_t)GRTX_NOALLOC_SCRATCH_MB << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// Device address of `scratch` on each device (the host-side name is only a handle for the
+// runtime), looked up once per device with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_lock;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+grtx_status noalloc_scratch(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("grtx_trace_noalloc: device %d beyond the %d supported", device, kMaxDevices);
+    return GRTX_ERR_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> g(g_noalloc_lock);
+  if (!g_noalloc_ptr[device]) {
+    void* ptr = nullptr;
+    GRTX_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_noalloc_ptr[device] = ptr;
+  }
+  *out = g_noalloc_ptr[device];
+  return GRTX_OK;
+}
+
 grtx_status launch_trace(const TraceScene& b, const grtx_rays* r, const grtx_trace_params* p,
                          const grtx_trace_outputs* o, hipStream_t s) {
+  return launch_trace_in(b, r, p, o, s, false);
+}
+
+grtx_status trace_noalloc(const Bvh* b, const grtx_rays* r, const grtx_trace_params* p, const grtx_trace_outputs* o,
+                          hipStream_t s) {
+  TraceScene sc{b->nodes, b->inst, b->tris, b->sh, b->sh_degree, b->roots, nullptr, b->kind, b->n_leaves, nullptr,
+                nullptr};
+  return launch_trace_in(sc, r, p, o, s, true);
+}
+
+grtx_status launch_trace_in(const TraceScene& b, const grtx_rays* r, const grtx_trace_params* p,
+                            const grtx_trace_outputs* o, hipStream_t s, bool noalloc) {
   const int64_t R = r->count;
   if (R == 0) return GRTX_OK;
   if (b.n_leaves == 0) {
@@ -1077,8 +1120,24 @@ grtx_status launch_trace(const TraceScene& b, const grtx_rays* r, const grtx_tra
   const int64_t rows = kSpillRows + 2 * (int64_t)cap_d + 2 * (int64_t)cap_e + K;
   const size_t need = (size_t)blocks * kWaves * rows * 64 * sizeof(uint2) + 256;
 
+  Pool fixed;
   Pool* pool = nullptr;
-  {
+  if (noalloc) {
+    // the static scratch: as many workgroups as fit in it, none beyond it
+    const size_t per_block = (size_t)kWaves * rows * 64 * sizeof(uint2);
+    const int64_t fit = (int64_t)((kNoAllocBytes - 256) / per_block);
+    if (fit < 1) {
+      set_error("grtx_trace_noalloc: one workgroup's checkpoint lists (%zu bytes at k-buffer %d, capacities %d/%d) "
+                "exceed the %zu-byte scratch; lower the list capacities",
+                per_block, K, cap_d, cap_e, kNoAllocBytes - 256);
+      return GRTX_ERR_CAPACITY;
+    }
+    if (blocks > fit) blocks = (int)fit;
+    GRTX_TRY(noalloc_scratch(device, &fixed.ptr));
+    fixed.bytes = kNoAllocBytes;
+    fixed.counter = reinterpret_cast<unsigned int*>(fixed.ptr);
+    pool = &fixed;
+  } else {
     std::lock_guard<std::mutex> g(g_pool_lock);
     pool = &g_pools[{device, s}];
     if (pool->bytes < need) {
@@ -1142,8 +1201,10 @@ grtx_status launch_trace(const TraceScene& b, const grtx_rays* r, const grtx_tra
   a.cap_e = cap_e;
   a.chunk_len = ((a.n_work + 64 * kChunks - 1) / (64 * kChunks)) * 64;
   uint32_t* order_buf = nullptr;
-  Scratch order_scratch(s);
-  if (a.image_w > 0) {
+  // (the allocation-free path keeps the tiles in row-major order: no scratch, same results)
+  std::unique_ptr<Scratch> order_scratch;
+  if (!noalloc) order_scratch.reset(new Scratch(s));
+  if (a.image_w > 0 && !noalloc) {
     // Tiles heaviest first, so that the longest rays do not start last: by estimated cost
     // where the structure carries a subtree cut, centre-out within equal estimates.
     const int64_t nt = a.n_work / 64;
@@ -1151,7 +1212,7 @@ grtx_status launch_trace(const TraceScene& b, const grtx_rays* r, const grtx_tra
     GRTX_TRY(centre_out_order(device, a.tiles_x, (int)(nt / a.tiles_x), &base));
     // scratch: estimate keys (8 B) and order (4 B) per tile, then three more words per tile
     // for the continuation partition
-    GRTX_TRY(order_scratch.get(&order_buf, 6 * (size_t)nt));
+    GRTX_TRY(order_scratch->get(&order_buf, 6 * (size_t)nt));
     if (b.cut) {
       uint64_t* keys = reinterpret_cast<uint64_t*>(order_buf);
       uint32_t* est_order = order_buf + 2 * nt;

@@ -126,6 +126,8 @@ _SIGNATURES = {
     "grtx_pinhole_rays": (C.c_int, [C.POINTER(_Camera), C.c_void_p, C.c_void_p, C.c_void_p]),
     "grtx_trace": (C.c_int, [C.c_void_p, C.POINTER(_Rays), C.POINTER(_TraceParams), C.POINTER(_TraceOutputs),
                              C.c_void_p]),
+    "grtx_trace_noalloc": (C.c_int, [C.c_void_p, C.POINTER(_Rays), C.POINTER(_TraceParams),
+                                     C.POINTER(_TraceOutputs), C.c_void_p]),
     "grtx_trace_backward": (C.c_int, [C.c_void_p, C.POINTER(_Gaussians), C.POINTER(_Rays), C.POINTER(_TraceParams),
                                       C.POINTER(_TraceOutputs), C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.POINTER(_GaussianGrads), C.c_void_p, C.c_void_p]),
@@ -277,7 +279,7 @@ def trace(bvh: Bvh, origins: torch.Tensor, dirs: torch.Tensor, k: int = 16, T_mi
           mode: int = CHECKPOINT, bg=(0.0, 0.0, 0.0), t_near: float = 0.0, image_width: int = 0,
           stats: bool = False, hit_capacity: int = 0, defer_capacity: int = 0, evict_capacity: int = 0,
           out=None, stream=None, t_far: torch.Tensor = None, transmittance: torch.Tensor = None,
-          continuation: dict = None):
+          continuation: dict = None, _entry: str = "grtx_trace"):
     """Render rays; returns dict(rgb [R,3], depth [R], opacity [R], and optionally stats
     [R,9] int32, hit_ids [R,cap] int32, hit_counts [R] int32). t_far [R] bounds the rays at
     a surface; transmittance [R] is what each ray starts with (both optional float32).
@@ -309,8 +311,15 @@ def trace(bvh: Bvh, origins: torch.Tensor, dirs: torch.Tensor, k: int = 16, T_mi
                       out["hit_ids"].data_ptr() if "hit_ids" in out and R else None,
                       out["hit_counts"].data_ptr() if "hit_counts" in out and R else None,
                       int(out["hit_ids"].shape[1]) if "hit_ids" in out else 0, 0)
-    _check(lib().grtx_trace(bvh.handle, C.byref(rays), C.byref(prm), C.byref(o), _stream(stream)))
+    _check(getattr(lib(), _entry)(bvh.handle, C.byref(rays), C.byref(prm), C.byref(o), _stream(stream)))
     return out
+
+
+def trace_noalloc(bvh: Bvh, origins: torch.Tensor, dirs: torch.Tensor, out: dict, **kw):
+    """grtx_trace_noalloc: `trace` into the caller's preallocated outputs `out` (rgb, depth,
+    opacity, optionally stats / hit_ids / hit_counts) without any device allocation by the
+    library; the same keyword arguments as `trace`."""
+    return trace(bvh, origins, dirs, out=out, _entry="grtx_trace_noalloc", **kw)
 
 
 def _objects(objects: dict):

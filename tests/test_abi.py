@@ -65,11 +65,13 @@ def test_trace_rejects_bad_arguments():
         rays.t_near = tn
         prm = grtx._TraceParams(k, T, mode, (C.c_float * 3)(0, 0, 0), 0, 0)
         assert L.grtx_trace(fake, C.byref(rays), C.byref(prm), C.byref(out), None) == grtx.ERR_INVALID_ARG
+        assert L.grtx_trace_noalloc(fake, C.byref(rays), C.byref(prm), C.byref(out), None) == grtx.ERR_INVALID_ARG
     rays.t_near = 0.0
     prm = grtx._TraceParams(4, 1e-3, 0, (C.c_float * 3)(0, 0, 0), 0, 0)
     assert L.grtx_trace(fake, C.byref(rays), C.byref(prm), C.byref(out), None) == grtx.ERR_INVALID_ARG
     assert b"null" in L.grtx_last_error()
-
+    assert L.grtx_trace_noalloc(fake, C.byref(rays), C.byref(prm), C.byref(out), None) == grtx.ERR_INVALID_ARG
+    assert b"grtx_trace_noalloc: null" in L.grtx_last_error()
     cam = grtx._Camera((C.c_float * 3)(0, -3, 0), (C.c_float * 3)(0, 0, 0), (C.c_float * 3)(0, 0, 1), 60.0, 0, 4)
     assert L.grtx_pinhole_rays(C.byref(cam), C.c_void_p(1), C.c_void_p(1), None) == grtx.ERR_INVALID_ARG
 
