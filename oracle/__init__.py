@@ -67,9 +67,9 @@ def lib():
             L.oracle_pinhole_rays.argtypes = [PD, PD, PD, d, C.c_int, C.c_int, PD, PD]
             L.oracle_morton.restype = C.c_int
             L.oracle_morton.argtypes = [i64, PF, C.POINTER(u64)]
-            L.oracle_lbvh_topology.restype = C.c_int
-            L.oracle_lbvh_topology.argtypes = [i64, PF, C.POINTER(u64), C.POINTER(u32), C.POINTER(u32),
-                                               C.POINTER(u32)]
+            L.oracle_lbvh_topology_search.restype = C.c_int
+            L.oracle_lbvh_topology_search.argtypes = [i64, PF, C.POINTER(u64), C.POINTER(u32), C.POINTER(u32),
+                                                      C.POINTER(u32), C.c_int]
             L.oracle_sh_basis.restype = d
             L.oracle_sh_basis.argtypes = [C.c_int, C.c_int, PD]
             L.oracle_icosahedron.restype = C.c_int
@@ -274,8 +274,10 @@ def morton(means):
     return codes
 
 
-def lbvh_topology(means):
-    """Sorted Morton codes, permutation, child [(n-1),2] and parent [2n-1] arrays."""
+def lbvh_topology(means, linear=False):
+    """Sorted Morton codes, permutation, child [(n-1),2] and parent [2n-1] arrays. Each
+    node's split is found by bisection, or with `linear` by testing every position of its
+    key range (the definition as written, quadratic; small sizes)."""
     L = lib()
     m = _f32(means).reshape(-1, 3)
     n = m.shape[0]
@@ -283,8 +285,8 @@ def lbvh_topology(means):
     perm = np.zeros(n, np.uint32)
     child = np.zeros((max(n - 1, 1), 2), np.uint32)
     parent = np.zeros(max(2 * n - 1, 1), np.uint32)
-    rc = L.oracle_lbvh_topology(n, _p(m, C.c_float), _p(codes, C.c_uint64), _p(perm, C.c_uint32),
-                                _p(child, C.c_uint32), _p(parent, C.c_uint32))
+    rc = L.oracle_lbvh_topology_search(n, _p(m, C.c_float), _p(codes, C.c_uint64), _p(perm, C.c_uint32),
+                                       _p(child, C.c_uint32), _p(parent, C.c_uint32), 1 if linear else 0)
     if rc != 0:
         raise RuntimeError("oracle_lbvh_topology failed")
     return dict(codes=codes, perm=perm, child=child[: max(n - 1, 0)], parent=parent[: max(2 * n - 1, 0)])

@@ -827,12 +827,27 @@ static int common_prefix(const tree_t *T, int64_t a, int64_t b) {
  * split is the last position that shares more than the range's common prefix with
  * `first`; the left child covers [first, split], the right [split+1, last]. A child
  * covering a single position is a leaf; otherwise the left child is internal node
- * `split` and the right child is internal node `split+1`. */
-static void build_range(tree_t *T, int64_t first, int64_t last, uint32_t self) {
+ * `split` and the right child is internal node `split+1`.
+ * The split is found either by testing every position of the range (`linear`), or by
+ * bisection: along sorted keys the common prefix with `first` never grows, so the
+ * positions sharing more than the range's prefix form a run starting at `first`. */
+static void build_range(tree_t *T, int64_t first, int64_t last, uint32_t self, int linear) {
   int range_prefix = common_prefix(T, first, last);
   int64_t split = first;
-  for (int64_t i = first; i < last; ++i)
-    if (common_prefix(T, first, i) > range_prefix) split = i;
+  if (linear) {
+    for (int64_t i = first; i < last; ++i)
+      if (common_prefix(T, first, i) > range_prefix) split = i;
+  } else {
+    int64_t lo = first, hi = last - 1; /* common_prefix(first, first) = 95 > range_prefix */
+    while (lo < hi) {
+      int64_t mid = lo + (hi - lo + 1) / 2;
+      if (common_prefix(T, first, mid) > range_prefix)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    split = lo;
+  }
   uint32_t left, right;
   if (split == first) {
     left = LEAF_FLAG | (uint32_t)split;
@@ -850,17 +865,18 @@ static void build_range(tree_t *T, int64_t first, int64_t last, uint32_t self) {
   }
   T->child[2 * self] = left;
   T->child[2 * self + 1] = right;
-  if (split != first) build_range(T, first, split, (uint32_t)split);
-  if (split + 1 != last) build_range(T, split + 1, last, (uint32_t)(split + 1));
+  if (split != first) build_range(T, first, split, (uint32_t)split, linear);
+  if (split + 1 != last) build_range(T, split + 1, last, (uint32_t)(split + 1), linear);
 }
 
 /* Sort positions by (code, original index) and build the radix tree over them.
  * Outputs: sorted codes [n], perm [n] (sorted position -> original index), child
  * [(n-1)*2] (leaf children carry bit 31 and the sorted position), parent [2n-1]
  * (entries 0..n-2 for internal nodes, n-1+p for leaf p; the root's parent is
- * 0xFFFFFFFF). Quadratic in the worst case; meant for test sizes. */
-int oracle_lbvh_topology(int64_t n, const float *means, uint64_t *sorted_codes, uint32_t *perm,
-                         uint32_t *child, uint32_t *parent) {
+ * 0xFFFFFFFF). With `linear` every split is found by testing each position of its
+ * range (quadratic in the worst case; small sizes), otherwise by bisection. */
+int oracle_lbvh_topology_search(int64_t n, const float *means, uint64_t *sorted_codes, uint32_t *perm,
+                                uint32_t *child, uint32_t *parent, int linear) {
   if (n <= 0) return OR_OK;
   uint64_t *codes = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
   if (!codes) return OR_ERR_MEM;
@@ -873,6 +889,11 @@ int oracle_lbvh_topology(int64_t n, const float *means, uint64_t *sorted_codes, 
   for (int64_t i = 0; i < 2 * n - 1; ++i) parent[i] = 0xFFFFFFFFu;
   if (n == 1) return OR_OK;
   tree_t T = {sorted_codes, child, parent, n};
-  build_range(&T, 0, n - 1, 0);
+  build_range(&T, 0, n - 1, 0, linear);
   return OR_OK;
+}
+
+int oracle_lbvh_topology(int64_t n, const float *means, uint64_t *sorted_codes, uint32_t *perm,
+                         uint32_t *child, uint32_t *parent) {
+  return oracle_lbvh_topology_search(n, means, sorted_codes, perm, child, parent, 0);
 }

@@ -55,13 +55,21 @@ def oracle_rays(cam):
 
 # ------------------------------------------------------------------------ build
 
-@pytest.mark.parametrize("case", ["n1", "n2", "n3", "n100", "plain1k", "dups257", "scene100k"])
+@pytest.mark.parametrize("case", ["n1", "n2", "n3", "n100", "plain1k", "dups257", "scene100k", "scene1100k",
+                                  "scene3m"])
 def test_topology_bit_exact(case):
+    """Morton codes, the stable sort's permutation and the plain radix tree (child and
+    parent arrays, and its depth) bit for bit against the oracle. Above 1,048,576 keys
+    (1.1M, and the 3M-Gaussian workload) the radix sort takes its scan-kernel path."""
     say("topology", case)
     if case == "plain1k":
         scene = inputs.small_scene(1, 1000)
     elif case == "scene100k":
         scene = inputs.cluster_scene(2, 100_000, 0)
+    elif case == "scene1100k":
+        scene = inputs.cluster_scene(6, 1_100_000, 0)
+    elif case == "scene3m":
+        scene = inputs.cluster_scene(inputs.SCENE3M["seed"], inputs.SCENE3M["n"], 0)
     else:
         n = int(case[1:] if case[0] == "n" else case[4:])
         rng = np.random.default_rng(n)

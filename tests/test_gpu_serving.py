@@ -69,6 +69,53 @@ def test_mix_equals_alone():
     srv.close()
 
 
+def test_served_requests_match_oracle():
+    """The serving workload's scenes (100k, 500k, 1M and 3M Gaussians) at each of its
+    resolutions (256x256, 512x512, 800x800, 1920x1080), all sixteen requests in one mix:
+    every served image equals the request's camera traced alone bit for bit, and that trace
+    matches the oracle on sampled pixels by the per-ray rule (which chains the served
+    output to the oracle)."""
+    import oracle
+    from tests import parity
+    cfg = inputs.SERVE
+    say("serving vs oracle")
+    scenes = [inputs.cluster_scene(seed, n, 3) for seed, n in zip(cfg["scene_seeds"], cfg["scene_sizes"])]
+    bvhs = [grtx.build(grtx.SceneTensors.from_scene(s, "cuda"), alpha_min=AMIN) for s in scenes]
+    torch.cuda.synchronize()
+    srv = grtx.Server(memory_budget=64 << 30, slots=2, k=cfg["k"], T_min=cfg["T_min"])
+    ids = [srv.add_scene(b) for b in bvhs]
+    rng = np.random.default_rng(51)
+    reqs = []
+    for sid in ids:
+        for w, h in cfg["resolutions"]:
+            cam = inputs.Camera(inputs.random_orbit_eye(rng), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 60.0, w, h)
+            reqs.append((sid, cam, srv.submit(sid, cam)))
+    t0 = time.time()
+    pending = {t for _, _, t in reqs}
+    while pending and time.time() - t0 < 120:
+        pending = {t for t in pending if srv.poll(t) is None}
+        time.sleep(0.001)
+    assert not pending, "requests did not finish"
+    for j, (sid, cam, t) in enumerate(reqs):
+        got = srv.result(t)
+        o, d = grtx.pinhole_rays(cam)
+        alone = grtx.trace(bvhs[sid], o, d, k=cfg["k"], T_min=cfg["T_min"], image_width=cam.width, hit_capacity=512)
+        torch.cuda.synchronize()
+        for key in ["rgb", "depth", "opacity"]:
+            assert torch.equal(got[key], alone[key]), (t, key)
+        srv.release(t)
+        idx = inputs.ray_subsample(200 + j, cam.n_rays, 48)
+        ti = torch.from_numpy(idx).cuda()
+        sub = {key: v.index_select(0, ti).cpu().numpy() for key, v in alone.items()}
+        so, sd = o.index_select(0, ti).cpu().numpy(), d.index_select(0, ti).cpu().numpy()
+        ref = oracle.render(scenes[sid], so, sd, AMIN, cfg["T_min"], cap=512)
+        s = parity.compare_render(scenes[sid], so, sd, sub, ref, AMIN, cfg["T_min"],
+                                  label=f"served scene {cfg['scene_sizes'][sid]} {cam.width}x{cam.height}")
+        say(cfg["scene_sizes"][sid], f"{cam.width}x{cam.height}", s)
+    assert srv.stats()["bytes_in_use"] == 0
+    srv.close()
+
+
 def test_request_too_large_is_refused():
     say("serving capacity")
     scene = inputs.cluster_scene(10, 20_000, 3)

@@ -462,6 +462,23 @@ def test_lbvh_reference_topology(n, dup):
     _check_radix_tree(t["codes"], t["perm"], t["child"], t["parent"], n)
 
 
+@pytest.mark.parametrize("n,dup", [(2, False), (3, False), (100, False), (1000, False), (4000, False), (257, True),
+                                   (3000, True)])
+def test_lbvh_bisection_equals_linear_split_search(n, dup):
+    """The oracle's split search by bisection (used at the 1.1M and 3M sizes) gives exactly
+    the tree of the linear search over each key range (the definition as written)."""
+    rng = np.random.default_rng(1000 + n)
+    m = rng.uniform(-1, 1, (n, 3)).astype(np.float32)
+    if dup:
+        m[::3] = m[0]
+        m[1::7] = m[1]
+    a = oracle.lbvh_topology(m, linear=True)
+    b = oracle.lbvh_topology(m)
+    for key in ("codes", "perm", "child", "parent"):
+        assert np.array_equal(a[key], b[key]), key
+    _check_radix_tree(b["codes"], b["perm"], b["child"], b["parent"], n)
+
+
 def test_oracle_finite_difference_matches_closed_form_gradient():
     """Central differences of the oracle with FP64 inputs reproduce a closed-form
     derivative: for a ray along x at distance b from an isotropic Gaussian's centre,
