@@ -159,9 +159,9 @@ typedef struct grtx_rays {
  * its transmittance below T_min (early ray termination, Sec. III-A), in [0, 1).
  * mode: grtx_mode. bg: background colour added with the remaining transmittance.
  * defer_capacity / evict_capacity: per-ray entries of the checkpoint lists (0 = the
- * defaults: 256 deferred nodes and 128 evicted hits, or 1024 and 256 for structures of
- * more than a million leaves). A ray whose lists overflow falls back to a
- * restart-from-root round; results are unchanged. The lists live in a per-stream pool
+ * defaults: 256 deferred nodes and 128 evicted hits, or 2048 and 512 for structures of
+ * more than a million leaves), rounded up to a multiple of 4. A ray whose lists
+ * overflow falls back to a restart-from-root round; results are unchanged. The lists live in a per-stream pool
  * of 512 B x (288 + 2 x defer + 2 x evict + k) per wave in flight. */
 typedef struct grtx_trace_params {
   int32_t k;
@@ -265,7 +265,7 @@ grtx_status grtx_trace(const grtx_bvh* bvh, const grtx_rays* rays, const grtx_tr
  * is a static array of GRTX_NOALLOC_SCRATCH_MB MiB that each device running the library
  * holds from the library's first use on it until the process ends. As many persistent
  * workgroups run as their lists fit in it (about 2.1 MiB per workgroup at k = 16 with
- * the 256/128 default capacities, 5.8 MiB with 1024/256), so throughput can be below
+ * the 256/128 default capacities, 11 MiB with 2048/512), so throughput can be below
  * grtx_trace's; image rays are taken in row-major tile order. GRTX_ERR_CAPACITY when not
  * even one workgroup's lists fit (lower defer_capacity / evict_capacity). Every call on a
  * device uses that device's one array: calls that overlap on one device (different

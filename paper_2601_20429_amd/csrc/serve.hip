@@ -339,8 +339,8 @@ grtx_status launch_batch(Server* sv, Server::Slot& slot, const std::vector<uint6
   p.T_min = sv->cfg.T_min;
   p.mode = sv->cfg.mode;
   for (int a = 0; a < 3; ++a) p.bg[a] = sv->cfg.bg[a];
-  p.defer_capacity = kLargeDeferCap;  // what the slot pools were reserved for
-  p.evict_capacity = kLargeEvictCap;
+  p.defer_capacity = kServeDeferCap;  // what the slot pools were reserved for
+  p.evict_capacity = kServeEvictCap;
   grtx_trace_outputs out{};
   out.rgb = slot.out;
   out.depth = slot.out + 3 * total;
@@ -462,7 +462,7 @@ grtx_status serve_create(const grtx_serve_config* cfg, Server** out) {
   }
   // the checkpoint pool of each slot's trace launches counts against the budget
   const int K = cfg->k <= 4 ? 4 : cfg->k <= 8 ? 8 : cfg->k <= 16 ? 16 : cfg->k <= 32 ? 32 : 64;
-  sv->pool_bytes_per_slot = trace_pool_bytes(K, kLargeDeferCap, kLargeEvictCap);
+  sv->pool_bytes_per_slot = trace_pool_bytes(K, kServeDeferCap, kServeEvictCap);
   sv->available = cfg->memory_budget - sv->cfg.slots * sv->pool_bytes_per_slot;
   if (sv->available <= 0) {
     set_error("grtx_serve_create: budget %lld bytes is below the %d slots' checkpoint pools (%lld bytes each)",

@@ -66,6 +66,13 @@ constexpr int kLdsStack = GRTX_LDS_STACK;  // per-lane stack entries held in LDS
 constexpr int kMaxStack = 3 * GRTX_MAX_TREE_DEPTH + 16;
 constexpr int kSpillRows = kMaxStack - kLdsStack;
 constexpr int kRefillThreshold = GRTX_REFILL_THRESHOLD;  // idle lanes that end a traversal burst
+// Deferred-node list appends gather in LDS and go out to the lane's HBM block kStage
+// entries at a time (one contiguous write of kStage x 8 B instead of kStage scattered
+// 8-B writes from the wave). List capacities are rounded up to a multiple of kStage.
+#ifndef GRTX_STAGE
+#define GRTX_STAGE 8
+#endif
+constexpr int kStage = GRTX_STAGE;
 #ifndef GRTX_CHUNKS
 #define GRTX_CHUNKS 1
 #endif
@@ -318,6 +325,7 @@ template <int K, int LEAF, bool STATS>
 __global__ void __launch_bounds__(kTraceBlock)
     __attribute__((amdgpu_waves_per_eu(K <= 32 ? GRTX_MIN_WAVES : 1, 8))) k_trace(TraceArgs Args) {
   __shared__ uint2 s_stack[kLdsStack * kTraceBlock];
+  __shared__ uint2 s_dst[kStage * kTraceBlock];  // destination node-list entries not yet written out
   __shared__ uint32_t s_stat[STATS ? GRTX_STATS_FIELDS : 1][kTraceBlock];  // per-lane counters
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -380,11 +388,22 @@ __global__ void __launch_bounds__(kTraceBlock)
     sp = 0;
   };
 
+  // the destination node list's chunk at `pos` (a multiple of kStage) from LDS to HBM
+  auto flush_dst = [&](int pos) __attribute__((always_inline)) {
+    uint4* q = reinterpret_cast<uint4*>(&LROW(rowN + (par ^ 1) * Args.cap_d + pos));
+#pragma unroll
+    for (int j = 0; j < kStage / 2; ++j) {
+      const uint2 a = s_dst[(2 * j) * kTraceBlock + tid], b = s_dst[(2 * j + 1) * kTraceBlock + tid];
+      q[j] = make_uint4(a.x, a.y, b.x, b.y);
+    }
+  };
+
   auto defer = [&](uint32_t ref, float t) __attribute__((always_inline)) {
     if (!ckpt) return;
     if (ndst_n < Args.cap_d) {
-      LROW(rowN + (par ^ 1) * Args.cap_d + ndst_n) = make_uint2(ref, __float_as_uint(t));
+      s_dst[(ndst_n & (kStage - 1)) * kTraceBlock + tid] = make_uint2(ref, __float_as_uint(t));
       ++ndst_n;
+      if ((ndst_n & (kStage - 1)) == 0) flush_dst(ndst_n - kStage);
       STAT(GRTX_STAT_DEFERRED);
     } else {
       overflow = true;
@@ -812,7 +831,9 @@ __global__ void __launch_bounds__(kTraceBlock)
           esrc_n = esrc_i = edst_n = 0;
           root_start();
         } else {
-          // resume: this round's destination lists become the next round's sources
+          // resume: this round's destination lists become the next round's sources (the
+          // last, partial chunk of deferred nodes goes out first)
+          if (ndst_n & (kStage - 1)) flush_dst(ndst_n & ~(kStage - 1));
           par ^= 1;
           nsrc_n = ndst_n;
           nsrc_i = 0;
@@ -965,22 +986,27 @@ grtx_status launch(const TraceArgs& a, int blocks, hipStream_t s) {
   return GRTX_OK;
 }
 
+// Resident workgroups per CU of one kernel variant (the counting variant holds its
+// counters in LDS and may fit fewer; each launch takes its own kernel's figure, results
+// do not depend on it).
 template <int K, int LEAF>
-int blocks_per_cu() {
-  // the counting and non-counting kernels are sized alike; take the tighter one
-  int nb0 = 0, nb1 = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb0, k_trace<K, LEAF, false>, kTraceBlock, 0) != hipSuccess)
-    nb0 = 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb1, k_trace<K, LEAF, true>, kTraceBlock, 0) != hipSuccess)
-    nb1 = 1;
-  return std::max(1, std::min(nb0, nb1));
+int blocks_per_cu(bool stats) {
+  int nb = 0;
+  const hipError_t e = stats ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<K, LEAF, true>, kTraceBlock, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<K, LEAF, false>, kTraceBlock, 0);
+  return e == hipSuccess ? std::max(1, nb) : 1;
 }
 
 template <int LEAF>
-int blocks_per_cu_k(int K) {
-  return K == 4 ? blocks_per_cu<4, LEAF>() : K == 8 ? blocks_per_cu<8, LEAF>() : K == 16 ? blocks_per_cu<16, LEAF>()
-       : K == 32 ? blocks_per_cu<32, LEAF>() : blocks_per_cu<64, LEAF>();
+int blocks_per_cu_k(int K, bool stats) {
+  return K == 4 ? blocks_per_cu<4, LEAF>(stats) : K == 8 ? blocks_per_cu<8, LEAF>(stats)
+       : K == 16 ? blocks_per_cu<16, LEAF>(stats) : K == 32 ? blocks_per_cu<32, LEAF>(stats)
+       : blocks_per_cu<64, LEAF>(stats);
 }
+
+// List capacities as the kernel uses them: the default for the structure's size when 0,
+// rounded up to whole LDS staging chunks.
+inline int stage_round(int c) { return (c + kStage - 1) / kStage * kStage; }
 
 template <int LEAF>
 grtx_status launch_k(int K, const TraceArgs& a, int blocks, hipStream_t s) {
@@ -1030,7 +1056,10 @@ int64_t trace_pool_bytes(int K, int cap_d, int cap_e) {
   int device = 0, cus = 0;
   if (hipGetDevice(&device) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
-  const int64_t blocks = (int64_t)cus * blocks_per_cu_k<false>(K);
+  const int64_t blocks = (int64_t)cus * std::max(blocks_per_cu_k<kLeafSphere>(K, false),
+                                                 blocks_per_cu_k<kLeafSphere>(K, true));
+  cap_d = stage_round(cap_d);
+  cap_e = stage_round(cap_e);
   const int64_t rows = kSpillRows + 2 * (int64_t)cap_d + 2 * (int64_t)cap_e + K;
   const int64_t need = blocks * kWaves * rows * 64 * (int64_t)sizeof(uint2) + 256;
   return need + need / 4;
@@ -1108,15 +1137,16 @@ grtx_status launch_trace_in(const TraceScene& b, const grtx_rays* r, const grtx_
   }
   const int K = p->k <= 4 ? 4 : p->k <= 8 ? 8 : p->k <= 16 ? 16 : p->k <= 32 ? 32 : 64;
   const int leaf = b.kind == GRTX_BVH_PROXY20 ? kLeafTri : b.kind == GRTX_BVH_ICO_INSTANCE ? kLeafIco : kLeafSphere;
-  int bpc = leaf == kLeafTri ? blocks_per_cu_k<kLeafTri>(K)
-          : leaf == kLeafIco ? blocks_per_cu_k<kLeafIco>(K) : blocks_per_cu_k<kLeafSphere>(K);
+  const bool stats = o->stats != nullptr;
+  int bpc = leaf == kLeafTri ? blocks_per_cu_k<kLeafTri>(K, stats)
+          : leaf == kLeafIco ? blocks_per_cu_k<kLeafIco>(K, stats) : blocks_per_cu_k<kLeafSphere>(K, stats);
   int blocks = cached_cus * bpc;
   // never more waves than rays need
   int64_t need_blocks = (R + kTraceBlock - 1) / kTraceBlock;
   if (blocks > need_blocks) blocks = (int)std::max<int64_t>(1, need_blocks);
 
-  const int cap_d = p->defer_capacity > 0 ? p->defer_capacity : default_defer_cap(b.n_leaves);
-  const int cap_e = p->evict_capacity > 0 ? p->evict_capacity : default_evict_cap(b.n_leaves);
+  const int cap_d = stage_round(p->defer_capacity > 0 ? p->defer_capacity : default_defer_cap(b.n_leaves));
+  const int cap_e = stage_round(p->evict_capacity > 0 ? p->evict_capacity : default_evict_cap(b.n_leaves));
   const int64_t rows = kSpillRows + 2 * (int64_t)cap_d + 2 * (int64_t)cap_e + K;
   const size_t need = (size_t)blocks * kWaves * rows * 64 * sizeof(uint2) + 256;
 
