@@ -1,11 +1,16 @@
-"""Benchmark: Gaussian ray tracing of a 100k-Gaussian scene at 800x800, k = 16, on one GPU.
+"""Benchmark: Gaussian ray tracing of the 3M-Gaussian workload on one GPU.
 
-One step is the whole hot path over one frame: pinhole ray generation, the LBVH build
-over the Gaussians (setup, Morton codes, radix sort, radix tree, refit) and the
-multi-round checkpointed trace with blending. Inputs (scene parameters) are resident on
-the GPU before timing starts. Prints one JSON line.
+One step is the whole hot path over one batch of the workload (3M Gaussians, SH degree 3,
+1920x1080 primary rays plus 2M incoherent rays, k = 16, checkpointed tracing): pinhole
+ray generation, the LBVH build over the Gaussians (setup, Morton codes, radix sort, radix
+tree, refit, treelet restructuring, four-wide records) and the multi-round trace with
+blending of both ray sets. Inputs (scene parameters, incoherent rays) are resident on the
+GPU before timing starts. The value is rays per second over the step (both ray sets).
+Beside it: the same step in restart-from-root mode and at k = 32, the 100k-Gaussian
+frame (restart, proxy BVH, k sweep, secondary rays), the backward pass and serving.
+Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--headline-only]
 """
 import argparse
 import json
@@ -21,10 +26,33 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # algorithmic bytes per unit of work: what one node fetch, leaf test, blended hit, list
 # entry and ray must move at least
 B_NODE = 64          # node record: four quantized child boxes + four child references
-B_LEAF = 48          # unit-sphere transform of a leaf (3 x float4)
+B_LEAF = 48          # unit-sphere transform of a leaf (3 x float4); a proxy triangle is 48 B too
 B_BLEND_INST = 64    # full instance record re-read for blending
 B_LIST = 16          # one checkpoint / eviction entry written and read back (8 B each way)
 B_RAY = 24 + 20      # ray in (origin, direction); rgb, depth, opacity out
+STAT_NAMES = ("nodes", "leaves", "rounds", "blended", "deferred", "fetch_free", "evicted", "fallbacks",
+              "stack_drops")
+
+
+def alg_bytes(c, sh_degree, rays):
+    """Algorithmic bytes of a trace from its summed per-ray counters `c` (dict)."""
+    return (B_NODE * c["nodes"] + B_LEAF * c["leaves"]
+            + (B_BLEND_INST + 4 * 3 * (sh_degree + 1) ** 2) * c["blended"]
+            + B_LIST * (c["deferred"] + c["evicted"]) + B_RAY * rays)
+
+
+def stat_sums(out):
+    import torch
+    v = out["stats"].to(torch.int64).sum(0).cpu().numpy()
+    return {name: int(x) for name, x in zip(STAT_NAMES, v)}
+
+
+def per_ray(c, rays):
+    return dict(nodes_per_ray=(c["nodes"] + c["leaves"]) / rays, internal_nodes_per_ray=c["nodes"] / rays,
+                leaf_tests_per_ray=c["leaves"] / rays, rounds_per_ray=c["rounds"] / rays,
+                blended_per_ray=c["blended"] / rays, deferred_per_ray=c["deferred"] / rays,
+                fetch_free_per_ray=c["fetch_free"] / rays, evicted_per_ray=c["evicted"] / rays,
+                fallbacks=c["fallbacks"], stack_drops=c["stack_drops"])
 
 
 def log(*a):
@@ -151,11 +179,11 @@ def run_proxy(st, cam, cfg, k, stream):
         out = grtx.trace(pb, o, d, k=k, T_min=cfg["T_min"], mode=m, image_width=cam.width)
         ms = time_launch(lambda: grtx.trace(pb, o, d, k=k, T_min=cfg["T_min"], mode=m, image_width=cam.width,
                                             out=out), stream, 3)
-        s = grtx.trace(pb, o, d, k=k, T_min=cfg["T_min"], mode=m, image_width=cam.width, stats=True)
-        stt = s["stats"].to(torch.int64).sum(0).cpu().numpy()
+        c = stat_sums(grtx.trace(pb, o, d, k=k, T_min=cfg["T_min"], mode=m, image_width=cam.width, stats=True))
         res[f"proxy_{name}_trace_ms"] = ms
         res[f"proxy_{name}_mrays_s"] = cam.n_rays / (ms * 1e-3) / 1e6
-        res[f"proxy_{name}_nodes_per_ray"] = float(stt[0] + stt[1]) / cam.n_rays
+        res[f"proxy_{name}_nodes_per_ray"] = float(c["nodes"] + c["leaves"]) / cam.n_rays
+        res[f"proxy_{name}_algorithmic_GBs"] = alg_bytes(c, st.sh_degree, cam.n_rays) / (ms * 1e-3) / 1e9
     info = pb.info()
     res["proxy_build_ms"] = build_ms
     res["proxy_bvh_bytes"] = int(info["device_bytes"])
@@ -166,11 +194,11 @@ def run_proxy(st, cam, cfg, k, stream):
         out = grtx.trace(ib, o, d, k=k, T_min=cfg["T_min"], mode=m, image_width=cam.width)
         ms = time_launch(lambda: grtx.trace(ib, o, d, k=k, T_min=cfg["T_min"], mode=m, image_width=cam.width,
                                             out=out), stream, 3)
-        s = grtx.trace(ib, o, d, k=k, T_min=cfg["T_min"], mode=m, image_width=cam.width, stats=True)
-        stt = s["stats"].to(torch.int64).sum(0).cpu().numpy()
+        c = stat_sums(grtx.trace(ib, o, d, k=k, T_min=cfg["T_min"], mode=m, image_width=cam.width, stats=True))
         res[f"ico_{name}_trace_ms"] = ms
         res[f"ico_{name}_mrays_s"] = cam.n_rays / (ms * 1e-3) / 1e6
-        res[f"ico_{name}_nodes_per_ray"] = float(stt[0] + stt[1]) / cam.n_rays
+        res[f"ico_{name}_nodes_per_ray"] = float(c["nodes"] + c["leaves"]) / cam.n_rays
+        res[f"ico_{name}_algorithmic_GBs"] = alg_bytes(c, st.sh_degree, cam.n_rays) / (ms * 1e-3) / 1e9
     res["ico_bvh_bytes"] = int(ib.info()["device_bytes"])
     return res
 
@@ -295,38 +323,6 @@ def run_ksweep(bvh, o, d, cam, cfg, stream, ks=(4, 8, 16, 32, 64)):
     return res
 
 
-def run_scene3m(stream, ks=(16, 32)):
-    """Largest workload: 3M Gaussians, 1920x1080 primary rays (8x8 tiles) plus 2M
-    incoherent rays, k = 16 and 32, checkpointing. Rates count both ray sets."""
-    import numpy as np
-    import torch
-
-    from paper_2601_20429_amd import grtx, inputs
-    cfg = inputs.SCENE3M
-    amin = float(np.float32(cfg["alpha_min"]))
-    st = grtx.SceneTensors.from_scene(inputs.cluster_scene(cfg["seed"], cfg["n"], 3), "cuda")
-    cam = inputs.orbit_camera(cfg["width"], cfg["height"])
-    po, pd = grtx.pinhole_rays(cam)
-    io, id_ = (torch.from_numpy(a).cuda() for a in inputs.incoherent_rays(cfg["incoherent_seed"], cfg["incoherent"]))
-    bvh = grtx.build(st, alpha_min=amin)
-    build_ms = time_launch(lambda: grtx.build(st, alpha_min=amin), stream, 3)
-    res = dict(workload=cfg["name"], build_ms=build_ms, rays=cam.n_rays + cfg["incoherent"])
-    for k in ks:
-        for label, o, d, w in [("primary", po, pd, cam.width), ("incoherent", io, id_, 0)]:
-            out = grtx.trace(bvh, o, d, k=k, T_min=cfg["T_min"], image_width=w)
-            ms = time_launch(lambda: grtx.trace(bvh, o, d, k=k, T_min=cfg["T_min"], image_width=w, out=out),
-                             stream, 3)
-            stt = grtx.trace(bvh, o, d, k=k, T_min=cfg["T_min"], image_width=w, stats=True)["stats"]
-            stt = stt.to(torch.int64).sum(0).cpu().numpy()
-            n = int(o.shape[0])
-            res[f"k{k}_{label}_ms"] = ms
-            res[f"k{k}_{label}_mrays_s"] = n / (ms * 1e-3) / 1e6
-            res[f"k{k}_{label}_nodes_per_ray"] = float(stt[0] + stt[1]) / n
-            del out
-        res[f"k{k}_mrays_s"] = res["rays"] / ((res[f"k{k}_primary_ms"] + res[f"k{k}_incoherent_ms"]) * 1e-3) / 1e6
-    return res
-
-
 def run_backward(stream):
     """Differentiation workload: 200k Gaussians, 512x512 rays, k = 16; the forward pass keeps
     each ray's blended ids, the backward kernel replays them."""
@@ -355,7 +351,7 @@ def kernel_k(k):
     return 4 if k <= 4 else 8 if k <= 8 else 16 if k <= 16 else 32 if k <= 32 else 64
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_trace_k16_scene100k_hbm_traffic.txt")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_trace_k16_scene3m_hbm_traffic.txt")
 TRACE_SOURCES = [os.path.join(ROOT, "paper_2601_20429_amd", "csrc", f) for f in ("trace.hip", "grtx_internal.h")]
 
 
@@ -368,18 +364,27 @@ def source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(args):
-    """HBM bytes per launch of the timed kernel from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None when that
-    summary was taken on other kernel sources or another launch configuration."""
-    if args.k != 16 or args.mode != "checkpoint" or not os.path.exists(TRAFFIC_PROFILE):
-        return None
+def profile_fields(path):
+    """`key: value` lines of a committed counter summary."""
     fields = {}
-    with open(TRAFFIC_PROFILE) as fh:
+    if not os.path.exists(path):
+        return fields
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith(" "):
                 key, _, val = line.partition(":")
                 fields[key.strip()] = val.strip()
+    return fields
+
+
+def measured_traffic(args):
+    """HBM bytes per launch of the timed trace kernel from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration, mean over the step's
+    two launches), or None when that summary was taken on other kernel sources or another
+    launch configuration."""
+    if args.k != 16 or args.mode != "checkpoint":
+        return None
+    fields = profile_fields(TRAFFIC_PROFILE)
     if fields.get("source_sha256") != source_digest():
         return None
     try:
@@ -388,83 +393,242 @@ def measured_traffic(args):
         return None
 
 
+class Workload3M:
+    """The 3M-Gaussian workload, resident on the GPU: scene parameters, the 2M incoherent
+    rays and output buffers for both ray sets."""
+
+    def __init__(self, dev):
+        import numpy as np
+        import torch
+
+        from paper_2601_20429_amd import grtx, inputs
+        self.cfg = cfg = inputs.SCENE3M
+        self.amin = float(np.float32(cfg["alpha_min"]))
+        self.scene = inputs.cluster_scene(cfg["seed"], cfg["n"], 3)
+        self.st = grtx.SceneTensors.from_scene(self.scene, dev)
+        self.cam = inputs.orbit_camera(cfg["width"], cfg["height"])
+        io, id_ = inputs.incoherent_rays(cfg["incoherent_seed"], cfg["incoherent"])
+        self.io, self.id = torch.from_numpy(io).to(dev), torch.from_numpy(id_).to(dev)
+        self.n_prim, self.n_inc = self.cam.n_rays, cfg["incoherent"]
+        self.rays = self.n_prim + self.n_inc
+        mk = lambda R: dict(rgb=torch.empty((R, 3), dtype=torch.float32, device=dev),
+                            depth=torch.empty(R, dtype=torch.float32, device=dev),
+                            opacity=torch.empty(R, dtype=torch.float32, device=dev))
+        self.out_p, self.out_i = mk(self.n_prim), mk(self.n_inc)
+        self.dev = dev
+
+    def step(self, k, mode, events=None):
+        """One step: raygen + build + trace of both ray sets; with `events` (a list), HIP
+        events on the launch stream bracket each trace call."""
+        import torch
+
+        from paper_2601_20429_amd import grtx
+        stream = torch.cuda.current_stream()
+        po, pd = grtx.pinhole_rays(self.cam, device=self.dev)
+        bvh = grtx.build(self.st, alpha_min=self.amin)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)] if events is not None else None
+        if ev:
+            ev[0].record(stream)
+        grtx.trace(bvh, po, pd, k=k, T_min=self.cfg["T_min"], mode=mode, image_width=self.cam.width, out=self.out_p)
+        if ev:
+            ev[1].record(stream)
+        grtx.trace(bvh, self.io, self.id, k=k, T_min=self.cfg["T_min"], mode=mode, out=self.out_i)
+        if ev:
+            ev[2].record(stream)
+            events.append(ev)
+        return bvh
+
+    def timed(self, k, mode, steps, warmup):
+        """Step time (ms, host clock over `steps` synchronised steps) and the mean launch
+        time (ms, HIP events) of the primary and incoherent traces."""
+        import numpy as np
+        import torch
+        keep = [self.step(k, mode) for _ in range(warmup)]
+        torch.cuda.synchronize()
+        keep.clear()
+        ev = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            keep.append(self.step(k, mode, ev))
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        prim = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
+        inc = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+        keep.clear()
+        return ms, prim, inc
+
+    def counters(self, k, mode):
+        """Summed per-ray counters of both ray sets (deterministic: an untimed run with the
+        counters on sees exactly the timed work)."""
+        import torch
+
+        from paper_2601_20429_amd import grtx
+        po, pd = grtx.pinhole_rays(self.cam, device=self.dev)
+        bvh = grtx.build(self.st, alpha_min=self.amin)
+        cp = stat_sums(grtx.trace(bvh, po, pd, k=k, T_min=self.cfg["T_min"], mode=mode,
+                                  image_width=self.cam.width, stats=True))
+        ci = stat_sums(grtx.trace(bvh, self.io, self.id, k=k, T_min=self.cfg["T_min"], mode=mode, stats=True))
+        torch.cuda.synchronize()
+        info = bvh.info()
+        return cp, ci, info
+
+    def summary(self, k, mode, steps, warmup):
+        ms, tp, ti = self.timed(k, mode, steps, warmup)
+        cp, ci, info = self.counters(k, mode)
+        bp = alg_bytes(cp, 3, self.n_prim)
+        bi = alg_bytes(ci, 3, self.n_inc)
+        return dict(k=k, mode="checkpoint" if mode == 0 else "restart", step_ms=ms,
+                    mrays_s=self.rays / (ms * 1e-3) / 1e6,
+                    primary_trace_ms=tp, incoherent_trace_ms=ti,
+                    primary_mrays_s=self.n_prim / (tp * 1e-3) / 1e6,
+                    incoherent_mrays_s=self.n_inc / (ti * 1e-3) / 1e6,
+                    primary=per_ray(cp, self.n_prim), incoherent=per_ray(ci, self.n_inc),
+                    nodes_per_ray=(cp["nodes"] + cp["leaves"] + ci["nodes"] + ci["leaves"]) / self.rays,
+                    algorithmic_bytes_primary=bp, algorithmic_bytes_incoherent=bi,
+                    primary_algorithmic_GBs=bp / (tp * 1e-3) / 1e9,
+                    incoherent_algorithmic_GBs=bi / (ti * 1e-3) / 1e9,
+                    trace_algorithmic_GBs=(bp + bi) / ((tp + ti) * 1e-3) / 1e9,
+                    tree_depth=info["depth"], bvh_bytes=info["device_bytes"])
+
+
+def run_frame100k(args, stream):
+    """The 100k-Gaussian 800x800 frame (k = 16): step (raygen + build + trace), the
+    trace's counters, restart mode, two streams in turn, the proxy BVHs, the k sweep and
+    the secondary-ray workload."""
+    import numpy as np
+    import torch
+
+    from paper_2601_20429_amd import grtx, inputs
+    cfg = inputs.SCENE100K
+    dev = torch.device("cuda:0")
+    amin = float(np.float32(cfg["alpha_min"]))
+    st = grtx.SceneTensors.from_scene(inputs.cluster_scene(cfg["seed"], cfg["n"], 3), dev)
+    cam = inputs.orbit_camera(cfg["width"], cfg["height"])
+    R = cam.n_rays
+    out = dict(rgb=torch.empty((R, 3), dtype=torch.float32, device=dev),
+               depth=torch.empty(R, dtype=torch.float32, device=dev),
+               opacity=torch.empty(R, dtype=torch.float32, device=dev))
+    res = dict(workload=cfg["name"])
+
+    def timed(m, steps, warmup):
+        ev = []
+
+        def step(record):
+            oo, dd = grtx.pinhole_rays(cam, device=dev)
+            bvh = grtx.build(st, alpha_min=amin)
+            if record:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            grtx.trace(bvh, oo, dd, k=args.k, T_min=cfg["T_min"], mode=m, image_width=cam.width, out=out)
+            if record:
+                e1.record(stream)
+                ev.append((e0, e1))
+            return bvh
+        keep = [step(False) for _ in range(warmup)]
+        torch.cuda.synchronize()
+        keep.clear()
+        t0 = time.perf_counter()
+        keep = [step(True) for _ in range(steps)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        return ms, float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    bvh = grtx.build(st, alpha_min=amin)
+    oo, dd = grtx.pinhole_rays(cam, device=dev)
+    for m, name in [(grtx.CHECKPOINT, "checkpoint"), (grtx.RESTART, "restart")]:
+        ms, kms = timed(m, args.steps, 2)
+        c = stat_sums(grtx.trace(bvh, oo, dd, k=args.k, T_min=cfg["T_min"], mode=m, image_width=cam.width,
+                                 stats=True))
+        res[name] = dict(step_ms=ms, mrays_s=R / (ms * 1e-3) / 1e6, trace_ms=kms,
+                         trace_mrays_s=R / (kms * 1e-3) / 1e6,
+                         trace_algorithmic_GBs=alg_bytes(c, 3, R) / (kms * 1e-3) / 1e9,
+                         algorithmic_bytes_per_ray=alg_bytes(c, 3, R) / R, **per_ray(c, R))
+        log(f"100k {name}: step {ms:.3f} ms, trace {kms:.3f} ms, nodes/ray {res[name]['nodes_per_ray']:.1f}")
+    res["checkpoint_speedup_trace"] = res["restart"]["trace_ms"] / res["checkpoint"]["trace_ms"]
+    res["bvh_bytes"] = int(bvh.info()["device_bytes"])
+    if not args.no_compare:
+        res.update(run_two_streams(st, cam, cfg, args.k, args.steps))
+    if not args.no_proxy:
+        res.update(run_proxy(st, cam, cfg, args.k, stream))
+        log("proxy", json.dumps({k: v for k, v in res.items() if k.startswith(("proxy", "ico"))}))
+    if not args.no_secondary:
+        res["secondary"] = run_secondary(bvh, cam, args.k, stream)
+        log("secondary", json.dumps(res["secondary"]))
+    if not args.no_ksweep:
+        res["ksweep"] = run_ksweep(bvh, oo, dd, cam, cfg, stream)
+        log("ksweep", json.dumps(res["ksweep"]))
+    return res
+
+
+def cpu_baseline(work, sample_rays):
+    """The oracle (FP64 brute force over every ray/Gaussian pair) on a seeded sample of the
+    step's rays, on the host threads this process may use."""
+    import numpy as np
+
+    import oracle
+    from paper_2601_20429_amd import inputs
+    threads = int(os.environ.get("OMP_NUM_THREADS") or 0) or len(os.sched_getaffinity(0))
+    po, pd = oracle.pinhole_rays(work.cam)
+    io, id_ = inputs.incoherent_rays(work.cfg["incoherent_seed"], work.cfg["incoherent"])
+    idx = inputs.ray_subsample(99, work.rays, sample_rays)
+    ip, ii = idx[idx < work.n_prim], idx[idx >= work.n_prim] - work.n_prim
+    ro = np.concatenate([po[ip].astype(np.float32), io[ii]])
+    rd = np.concatenate([pd[ip].astype(np.float32), id_[ii]])
+    t0 = time.perf_counter()
+    oracle.render(work.scene, ro, rd, work.amin, work.cfg["T_min"], nthreads=threads)
+    dt = time.perf_counter() - t0
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return dict(value=len(idx) / dt / 1e6, unit="Mrays/s", cores=threads, kind="oracle",
+                sample=f"{len(idx)} of the step's {work.rays} rays ({len(ip)} primary, {len(ii)} incoherent; "
+                       f"seeded subsample) against all {work.cfg['n']} Gaussians, FP64 brute force, {dt:.1f} s",
+                host_cpu=cpu_model, host_threads_visible=os.cpu_count())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--mode", choices=["checkpoint", "restart"], default="checkpoint")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-compare", action="store_true", help="skip the restart-mode comparison run")
-    ap.add_argument("--cpu-rays", type=int, default=196608)
+    ap.add_argument("--no-compare", action="store_true", help="skip the restart-mode and k = 32 runs of the step")
+    ap.add_argument("--cpu-rays", type=int, default=4096)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="first copy this many GiB device-to-device (a reference kernel for HBM counters)")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-low-rate", type=float, default=30.0,
                     help="second serving run at this arrival rate (requests/s), below the server's capacity")
+    ap.add_argument("--no-frame100k", action="store_true", help="skip the 100k-Gaussian frame measurements")
     ap.add_argument("--no-proxy", action="store_true", help="skip the 20-face proxy BVH comparison")
     ap.add_argument("--no-backward", action="store_true", help="skip the backward-pass timing")
-    ap.add_argument("--no-scene3m", action="store_true", help="skip the 3M-Gaussian workload")
     ap.add_argument("--no-ksweep", action="store_true", help="skip the k-buffer size sweep")
     ap.add_argument("--no-secondary", action="store_true", help="skip the secondary-ray workload")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed step and its counters (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); sharding the rays over "
               "several GPUs is not built", file=sys.stderr)
         sys.exit(2)
+    if args.headline_only:
+        args.no_cpu_baseline = args.no_compare = args.no_serving = args.no_frame100k = True
+        args.no_backward = True
 
-    import numpy as np
     import torch
 
     from paper_2601_20429_amd import grtx, inputs
 
-    cfg = inputs.SCENE100K
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
-    amin = float(np.float32(cfg["alpha_min"]))
-    scene = inputs.cluster_scene(cfg["seed"], cfg["n"], 3)
-    st = grtx.SceneTensors.from_scene(scene, dev)
-    cam = inputs.orbit_camera(cfg["width"], cfg["height"])
-    R = cam.n_rays
-    mode = grtx.CHECKPOINT if args.mode == "checkpoint" else grtx.RESTART
     stream = torch.cuda.current_stream()
-    o = torch.empty((R, 3), dtype=torch.float32, device=dev)
-    d = torch.empty((R, 3), dtype=torch.float32, device=dev)
-    out = dict(rgb=torch.empty((R, 3), dtype=torch.float32, device=dev),
-               depth=torch.empty(R, dtype=torch.float32, device=dev),
-               opacity=torch.empty(R, dtype=torch.float32, device=dev))
-    trace_ev = []
-
-    def step(m, record=False):
-        oo, dd = grtx.pinhole_rays(cam, device=dev)
-        bvh = grtx.build(st, alpha_min=amin)
-        if record:
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-        grtx.trace(bvh, oo, dd, k=args.k, T_min=cfg["T_min"], mode=m, image_width=cam.width, out=out)
-        if record:
-            e1.record(stream)
-            trace_ev.append((e0, e1))
-        return bvh
-
-    def timed(m, steps, warmup):
-        keep = []
-        for _ in range(warmup):
-            keep.append(step(m))
-        torch.cuda.synchronize()
-        keep.clear()
-        trace_ev.clear()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            keep.append(step(m, record=True))
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ktimes = [a.elapsed_time(b) for a, b in trace_ev]
-        keep.clear()
-        return (t1 - t0) * 1e3 / steps, float(np.mean(ktimes)), float(np.median(ktimes))
-
+    mode = grtx.CHECKPOINT if args.mode == "checkpoint" else grtx.RESTART
     if args.calibrate_copy_gib > 0:
         nb = int(args.calibrate_copy_gib * (1 << 30)) // 4
         src = torch.ones(nb, dtype=torch.float32, device=dev)
@@ -473,121 +637,84 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {nb * 4} bytes read and written")
         del src, dst
-    log(f"scene {cfg['n']} Gaussians, {cam.width}x{cam.height} rays, k={args.k}, mode={args.mode}")
-    ms, k_mean, k_med = timed(mode, args.steps, args.warmup)
-    mrays = R / (ms * 1e-3) / 1e6
-    log(f"step {ms:.3f} ms ({mrays:.1f} Mrays/s); trace kernel mean {k_mean:.3f} ms median {k_med:.3f} ms")
 
-    # counters of the same launch configuration (deterministic, so an untimed run with the
-    # per-ray counters enabled sees exactly the timed work)
-    bvh = grtx.build(st, alpha_min=amin)
-    oo, dd = grtx.pinhole_rays(cam, device=dev)
-    sout = grtx.trace(bvh, oo, dd, k=args.k, T_min=cfg["T_min"], mode=mode, image_width=cam.width, stats=True)
-    torch.cuda.synchronize()
-    stt = sout["stats"].to(torch.int64).sum(0).cpu().numpy()
-    nodes, leaves, rounds, blended, deferred, free, evicted, fallbacks = [int(x) for x in stt[:8]]
-    alg_bytes = (B_NODE * nodes + B_LEAF * leaves + (B_BLEND_INST + 4 * 3 * (scene.sh_degree + 1) ** 2) * blended
-                 + B_LIST * (deferred + evicted) + B_RAY * R)
-    achieved = alg_bytes / (k_mean * 1e-3) / 1e9
-    extra = dict(nodes_per_ray=(nodes + leaves) / R, internal_nodes_per_ray=nodes / R, leaf_tests_per_ray=leaves / R,
-                 rounds_per_ray=rounds / R, blended_per_ray=blended / R, deferred_per_ray=deferred / R,
-                 fetch_free_per_ray=free / R, evicted_per_ray=evicted / R, fallbacks=fallbacks,
-                 trace_kernel_ms=k_mean, trace_kernel_ms_median=k_med,
-                 trace_only_mrays_s=R / (k_mean * 1e-3) / 1e6, algorithmic_bytes_per_ray=alg_bytes / R)
-    log("counters", json.dumps(extra))
+    work = Workload3M(dev)
+    log(f"workload {work.cfg['name']}: {work.cfg['n']} Gaussians, {work.n_prim} + {work.n_inc} rays, k={args.k}, "
+        f"mode={args.mode}")
+    head = work.summary(args.k, mode, args.steps, args.warmup)
+    log("headline", json.dumps(head))
+    extra = dict(headline=head)
+    # the dominant kernel: the trace, launched twice per step (primary frame, incoherent rays)
+    launch_ms = 0.5 * (head["primary_trace_ms"] + head["incoherent_trace_ms"])
+    launch_bytes = 0.5 * (head["algorithmic_bytes_primary"] + head["algorithmic_bytes_incoherent"])
+    achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": f"k_trace<{kernel_k(args.k)}, 0, false>",
+                "per_launch": "mean of the step's two launches (1920x1080 primary frame, 2M incoherent rays)",
+                "algorithmic_bytes_per_launch": launch_bytes, "launch_ms": launch_ms,
+                "hbm_measured_GBs": None if traffic is None else traffic / (launch_ms * 1e-3) / 1e9,
+                "hbm_measured_frac": None if traffic is None else traffic / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "limiter": profile_fields(TRAFFIC_PROFILE).get("limiter")}
 
     if not args.no_compare:
         other = grtx.RESTART if mode == grtx.CHECKPOINT else grtx.CHECKPOINT
-        ms2, k2, _ = timed(other, max(3, args.steps // 2), 1)
-        sout2 = grtx.trace(bvh, oo, dd, k=args.k, T_min=cfg["T_min"], mode=other, image_width=cam.width,
-                           stats=True)
-        torch.cuda.synchronize()
-        s2 = sout2["stats"].to(torch.int64).sum(0).cpu().numpy()
-        name = "restart" if other == grtx.RESTART else "checkpoint"
-        extra[f"{name}_step_ms"] = ms2
-        extra[f"{name}_mrays_s"] = R / (ms2 * 1e-3) / 1e6
-        extra[f"{name}_trace_kernel_ms"] = k2
-        extra[f"{name}_nodes_per_ray"] = float(s2[0] + s2[1]) / R
-        log(f"{name}: step {ms2:.3f} ms, trace {k2:.3f} ms, nodes/ray {extra[f'{name}_nodes_per_ray']:.1f}")
+        extra["restart" if other == grtx.RESTART else "checkpoint"] = cmp = work.summary(
+            args.k, other, max(3, args.steps // 2), 1)
+        log("compare", json.dumps(cmp))
+        extra["k32"] = k32 = work.summary(32, mode, max(3, args.steps // 2), 1)
+        log("k32", json.dumps(k32))
+        if mode == grtx.CHECKPOINT:
+            extra["checkpoint_speedup_step"] = cmp["step_ms"] / head["step_ms"]
+            extra["checkpoint_speedup_trace"] = (cmp["primary_trace_ms"] + cmp["incoherent_trace_ms"]) / (
+                head["primary_trace_ms"] + head["incoherent_trace_ms"])
 
-    info = bvh.info()
-    extra["bvh_bytes"] = int(info["device_bytes"])
-    if not args.no_compare:
-        extra.update(run_two_streams(st, cam, cfg, args.k, args.steps))
-        log(f"two streams: step {extra['two_stream_step_ms']:.3f} ms ({extra['two_stream_mrays_s']:.1f} Mrays/s)")
-    if not args.no_proxy:
-        extra.update(run_proxy(st, cam, cfg, args.k, stream))
-        log("proxy", json.dumps({k: v for k, v in extra.items() if k.startswith(("proxy", "ico"))}))
-    if not args.no_secondary:
-        extra["secondary"] = run_secondary(bvh, cam, args.k, stream)
-        log("secondary", json.dumps(extra["secondary"]))
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(work, args.cpu_rays)
+        log("cpu baseline", json.dumps(cpu))
+    del work
+    torch.cuda.empty_cache()
+
+    if not args.no_frame100k:
+        extra["scene100k"] = run_frame100k(args, stream)
     backward = None
     if not args.no_backward:
         backward = run_backward(stream)
         log("backward", json.dumps(backward))
-
-    if not args.no_ksweep:
-        extra["ksweep"] = run_ksweep(bvh, oo, dd, cam, cfg, stream)
-        log("ksweep", json.dumps(extra["ksweep"]))
-
-    scene3m = None
-    if not args.no_scene3m:
-        scene3m = run_scene3m(stream)
-        log("scene3m", json.dumps(scene3m))
-
     serving = None
     if not args.no_serving:
         serving, below = run_serving(args.serve_requests, (inputs.SERVE["rate"], args.serve_low_rate))
         log("serving", json.dumps(serving))
         log("serving below capacity", json.dumps(below))
         extra["serving_below_capacity"] = below
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        cores = min(16, os.cpu_count() or 1)
-        ro, rd = oracle.pinhole_rays(cam)
-        idx = inputs.ray_subsample(99, R, args.cpu_rays)
-        ro, rd = ro[idx].astype(np.float32), rd[idx].astype(np.float32)
-        t0 = time.perf_counter()
-        oracle.render(scene, ro, rd, amin, cfg["T_min"], nthreads=cores)
-        dt = time.perf_counter() - t0
-        cpu_model = ""
-        try:
-            with open("/proc/cpuinfo") as f:
-                cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
-        except OSError:
-            pass
-        cpu = dict(value=len(idx) / dt / 1e6, unit="Mrays/s", cores=cores, kind="oracle",
-                   sample=f"{len(idx)} of the {R} primary rays (seeded subsample) against all {cfg['n']} "
-                          f"Gaussians, FP64 brute force, {dt:.1f} s",
-                   host_cpu=cpu_model, host_threads_visible=os.cpu_count())
-        log("cpu baseline", json.dumps(cpu))
+    extra["paper_reference"] = (
+        "paper (Vulkan-Sim, 8 SMs at 1365 MHz; 6 scenes of 0.76-2.43 M Gaussians at 128x128, k = 8): "
+        "GRTX 4.36x over the 20-triangle baseline on average, checkpointing alone 1.94x, 2.37x fewer node "
+        "fetches from checkpointing; no absolute rays/s is given")
 
     rec = {
         "metric": "Mrays/s and nodes visited/ray at k=16; p50/p99 frame latency (serving)",
-        "value": mrays,
+        "value": head["mrays_s"],
         "unit": "Mrays/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": head["step_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": cfg["name"], "gaussians": cfg["n"], "width": cam.width, "height": cam.height,
-                   "rays": R, "k": args.k, "mode": args.mode, "sh_degree": 3, "bvh": "sphere-instance LBVH",
-                   "step": "raygen + LBVH build + trace"},
-        "nodes_per_ray": extra["nodes_per_ray"],
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args),
-                     "kernel": f"k_trace<{kernel_k(args.k)}>"},
+        "config": {"workload": inputs.SCENE3M["name"], "gaussians": 3_000_000, "primary_rays": 1920 * 1080,
+                   "incoherent_rays": 2_000_000, "k": args.k, "mode": args.mode, "sh_degree": 3,
+                   "bvh": "sphere-instance LBVH", "step": "raygen + LBVH build + trace of both ray sets"},
+        "nodes_per_ray": head["nodes_per_ray"],
+        "roofline": roofline,
         "cpu_baseline": cpu,
         "serving": serving,
         "backward": backward,
-        "scene3m": scene3m,
         "extra": extra,
     }
     print(json.dumps(rec), flush=True)
