@@ -325,7 +325,8 @@ def run_ksweep(bvh, o, d, cam, cfg, stream, ks=(4, 8, 16, 32, 64)):
 
 def run_backward(stream):
     """Differentiation workload: 200k Gaussians, 512x512 rays, k = 16; the forward pass keeps
-    each ray's blended ids, the backward kernel replays them."""
+    each ray's blended ids, the backward pass replays them (and, timed separately, traces
+    the rays again itself when given no list)."""
     import numpy as np
     import torch
 
@@ -335,16 +336,37 @@ def run_backward(stream):
     cam = inputs.orbit_camera(cfg["width"], cfg["height"])
     o, d = grtx.pinhole_rays(cam)
     bvh = grtx.build(st, alpha_min=float(np.float32(cfg["alpha_min"])))
-    fwd = grtx.trace(bvh, o, d, k=cfg["k"], T_min=cfg["T_min"], hit_capacity=256)
+    cap = 256
+    fwd = grtx.trace(bvh, o, d, k=cfg["k"], T_min=cfg["T_min"], hit_capacity=cap)
     g_rgb = torch.ones_like(fwd["rgb"])
-    f_ms = time_launch(lambda: grtx.trace(bvh, o, d, k=cfg["k"], T_min=cfg["T_min"], hit_capacity=256, out=fwd),
+    grads = dict(means=torch.zeros_like(st.means), scales=torch.zeros_like(st.scales),
+                 quats=torch.zeros_like(st.quats), opacities=torch.zeros_like(st.opacities),
+                 sh=torch.zeros_like(st.sh))
+    f_ms = time_launch(lambda: grtx.trace(bvh, o, d, k=cfg["k"], T_min=cfg["T_min"], hit_capacity=cap, out=fwd),
                        stream, 3)
-    b_ms = time_launch(lambda: grtx.trace_backward(bvh, o, d, fwd, grad_rgb=g_rgb, k=cfg["k"], T_min=cfg["T_min"]),
-                       stream, 3)
+    b_ms = time_launch(lambda: grtx.trace_backward(bvh, o, d, fwd, grad_rgb=g_rgb, grads=grads, k=cfg["k"],
+                                                   T_min=cfg["T_min"]), stream, 5)
+    r_ms = time_launch(lambda: grtx.trace_backward(bvh, o, d, None, grad_rgb=g_rgb, grads=grads, k=cfg["k"],
+                                                   T_min=cfg["T_min"], hit_capacity=cap), stream, 3)
     R = cam.n_rays
+    counts = fwd["hit_counts"].clamp(max=cap)
+    P = int(counts.sum())
+    ids = fwd["hit_ids"][fwd["hit_ids"] >= 0]
+    touched = int(torch.unique(ids).numel())
+    ncoef = 3 * (st.sh_degree + 1) ** 2
+    params = 4 * (3 + 3 + 4 + 1 + ncoef)  # one Gaussian's parameters (or gradients)
+    passes = (max(1, int(np.ceil(np.log2(st.n + 1)))) + 7) // 8
+    per_record = params + 4 + (64 + 12) + passes * 2 * 12 + (64 + 4 + 12)
+    alg = P * per_record + R * (24 + 20 + 12) + touched * 2 * params
     return dict(workload=cfg["name"], forward_with_ids_ms=f_ms, backward_ms=b_ms,
-                backward_mrays_s=R / (b_ms * 1e-3) / 1e6,
-                note="backward_ms includes zeroing the gradient arrays")
+                backward_mrays_s=R / (b_ms * 1e-3) / 1e6, backward_retrace_ms=r_ms,
+                hit_records=P, records_per_ray=P / R, touched_gaussians=touched,
+                algorithmic_bytes=alg, algorithmic_GBs=alg / (b_ms * 1e-3) / 1e9,
+                algorithmic_frac=alg / (b_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                note=("bytes per hit record: the Gaussian's parameters re-read, its id, the 64-B record and "
+                      "its 12-B sort key written, the sort passes, the record, order and ray direction read "
+                      "back; per ray: ray, forward outputs, output gradient; per touched Gaussian: its "
+                      "gradient read and written. backward_retrace_ms traces the rays again inside the call"))
 
 
 def kernel_k(k):
@@ -612,6 +634,8 @@ def main():
     ap.add_argument("--no-secondary", action="store_true", help="skip the secondary-ray workload")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed step and its counters (for profiler runs)")
+    ap.add_argument("--backward-only", action="store_true",
+                    help="only the backward-pass timing, printed as its JSON object (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); sharding the rays over "
@@ -637,6 +661,10 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {nb * 4} bytes read and written")
         del src, dst
+
+    if args.backward_only:
+        print(json.dumps(run_backward(stream)), flush=True)
+        return
 
     work = Workload3M(dev)
     log(f"workload {work.cfg['name']}: {work.cfg['n']} Gaussians, {work.n_prim} + {work.n_inc} rays, k={args.k}, "

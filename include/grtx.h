@@ -361,19 +361,23 @@ typedef struct grtx_gaussian_grads {
 
 /* Backward of grtx_trace (differentiation of Eq. 1 with Eq. 2 alphas and SH colours;
  * the paper's method is forward-only). `g` must be the parameters `bvh` was built from
- * and `rays`/`p` those of the forward call. `fwd` holds the forward outputs: rgb, depth,
- * opacity, hit_ids and hit_counts are required (the forward must have been run with a
- * hit-id list). grad_rgb [R,3] is dL/drgb; grad_depth [R] and grad_opacity [R] are
- * optional (NULL = zero). For each ray the blended hits are replayed in order; the
- * per-hit contributions are grouped by Gaussian (sorted, ray order kept) and summed in a
- * fixed order, then added to `grads` (which the caller zeroes): results are
- * deterministic. Rays with more blended hits than the list holds contribute only their
- * first hit_capacity hits; their number is written to the optional device counter
- * `truncated_rays` (uint32, may be NULL). Enqueued on `stream`; the call waits once on
- * the stream for the number of hit records (scratch of 76 B per record is taken from
- * the stream's pool and released in stream order). ERR_INVALID_ARG when rays x
- * hit_capacity reaches 2^32, or for rays with t_far or transmittance (the backward pass
- * covers unbounded rays that start with transmittance 1 and have no continuation). */
+ * and `rays`/`p` those of the forward call. `fwd` holds the forward outputs:
+ *   - with fwd->hit_ids (and hit_counts, hit_capacity > 0): rgb, depth and opacity are
+ *     required too, and the blended hits are read from the list;
+ *   - with fwd->hit_ids NULL: the rays are traced again (grtx_trace with `p`, which is
+ *     deterministic and so gives the forward's outputs) into internal lists of
+ *     fwd->hit_capacity entries per ray (0 = 256); fwd's other fields are not read.
+ * grad_rgb [R,3] is dL/drgb; grad_depth [R] and grad_opacity [R] are optional (NULL =
+ * zero). For each ray the blended hits are replayed in order; the per-hit contributions
+ * are grouped by Gaussian (sorted, ray order kept) and summed in a fixed order, then
+ * added to `grads` (which the caller zeroes): results are deterministic. Rays with more
+ * blended hits than the list holds contribute only their first hit_capacity hits; their
+ * number is written to the optional device counter `truncated_rays` (uint32, may be
+ * NULL). Enqueued on `stream` without any host wait: the number of hit records stays on
+ * the device, and scratch of about 88 B x rays x hit_capacity is taken from the
+ * stream's pool and released in stream order. ERR_INVALID_ARG when rays x hit_capacity
+ * reaches 2^32, or for rays with t_far or transmittance (the backward pass covers
+ * unbounded rays that start with transmittance 1 and have no continuation). */
 grtx_status grtx_trace_backward(const grtx_bvh* bvh, const grtx_gaussians* g, const grtx_rays* rays,
                                 const grtx_trace_params* p, const grtx_trace_outputs* fwd, const float* grad_rgb,
                                 const float* grad_depth, const float* grad_opacity, const grtx_gaussian_grads* grads,

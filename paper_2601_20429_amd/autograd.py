@@ -9,6 +9,7 @@ means, scales, quats, opacities and sh; rays receive none.
 """
 from __future__ import annotations
 
+import warnings
 from dataclasses import dataclass
 
 import torch
@@ -26,6 +27,9 @@ class RenderSettings:
     kind: int = grtx.SPHERE_INSTANCE
     bg: tuple = (0.0, 0.0, 0.0)
     hit_capacity: int = 512
+    # after each backward, read the number of rays whose blended hits overflowed the list
+    # (a device-to-host read) and warn: their gradients miss the hits past the list
+    check_truncation: bool = True
 
 
 class GRTXRender(torch.autograd.Function):
@@ -56,6 +60,12 @@ class GRTXRender(torch.autograd.Function):
             grad_opacity=None if g_opac is None else g_opac.contiguous(),
             k=s.k, T_min=s.T_min, mode=s.mode, bg=s.bg)
         ctx.truncated = truncated
+        if s.check_truncation:
+            n = int(truncated.item())
+            if n > 0:
+                warnings.warn(f"GRTXRender.backward: {n} rays blended more hits than hit_capacity="
+                              f"{s.hit_capacity}; their gradients cover only the first {s.hit_capacity} hits",
+                              RuntimeWarning)
         return grads["means"], grads["scales"], grads["quats"], grads["opacities"], grads["sh"], None, None, None
 
 

@@ -207,8 +207,13 @@ grtx_status grtx_trace_backward(const grtx_bvh* bvh, const grtx_gaussians* g, co
   if (rays->count > 0 && g->count > 0) {
     CHECK_ARG(g->means && g->scales && g->quats && g->opacities && g->sh, "grtx_trace_backward: null Gaussian array");
     CHECK_ARG(rays->origins && rays->dirs, "grtx_trace_backward: null ray arrays");
-    CHECK_ARG(fwd->rgb && fwd->depth && fwd->opacity && fwd->hit_ids && fwd->hit_counts && fwd->hit_capacity > 0,
-              "grtx_trace_backward: the forward outputs need rgb, depth, opacity and a hit-id list");
+    CHECK_ARG(!fwd->hit_ids || (fwd->rgb && fwd->depth && fwd->opacity && fwd->hit_counts && fwd->hit_capacity > 0),
+              "grtx_trace_backward: with a hit-id list the forward outputs need rgb, depth, opacity and hit counts");
+    CHECK_ARG(fwd->hit_capacity >= 0, "grtx_trace_backward: negative hit capacity");
+    CHECK_ARG(p->k >= 1 && p->k <= 64 && p->T_min >= 0.f && p->T_min < 1.f &&
+                  (p->mode == GRTX_MODE_CHECKPOINT || p->mode == GRTX_MODE_RESTART) && p->defer_capacity >= 0 &&
+                  p->evict_capacity >= 0 && p->defer_capacity <= (1 << 20) && p->evict_capacity <= (1 << 20),
+              "grtx_trace_backward: bad trace parameters");
     CHECK_ARG(grad_rgb || grad_depth || grad_opacity, "grtx_trace_backward: no output gradient given");
     CHECK_ARG(!rays->t_far && !rays->transmittance && !rays->kind,
               "grtx_trace_backward: rays with t_far, a starting transmittance or continuation rays are not "
@@ -228,7 +233,7 @@ grtx_status grtx_trace_backward(const grtx_bvh* bvh, const grtx_gaussians* g, co
     }
     tr = own;
   }
-  return grtx::trace_backward(g, rays, p, fwd, grad_rgb, grad_depth, grad_opacity, grads, tr,
+  return grtx::trace_backward(&bvh->impl, g, rays, p, fwd, grad_rgb, grad_depth, grad_opacity, grads, tr,
                               static_cast<hipStream_t>(stream));
 }
 

@@ -157,9 +157,9 @@ __global__ void __launch_bounds__(kBlock) k_bwd_pairs(BwdArgs A) {
       continue;
     }
     // ---- recompute the hit
-    const float* q4 = A.quats + 4 * i;
-    const float qn = sqrtf(q4[0] * q4[0] + q4[1] * q4[1] + q4[2] * q4[2] + q4[3] * q4[3]);
-    const float w = q4[0] / qn, x = q4[1] / qn, y = q4[2] / qn, z = q4[3] / qn;
+    const float4 q4 = reinterpret_cast<const float4*>(A.quats)[i];
+    const float qn = sqrtf(q4.x * q4.x + q4.y * q4.y + q4.z * q4.z + q4.w * q4.w);
+    const float w = q4.x / qn, x = q4.y / qn, y = q4.z / qn, z = q4.w / qn;
     float R[3][3];
     R[0][0] = 1.f - 2.f * (y * y + z * z); R[0][1] = 2.f * (x * y - w * z);       R[0][2] = 2.f * (x * z + w * y);
     R[1][0] = 2.f * (x * y + w * z);       R[1][1] = 1.f - 2.f * (x * x + z * z); R[1][2] = 2.f * (y * z - w * x);
@@ -185,13 +185,28 @@ __global__ void __launch_bounds__(kBlock) k_bwd_pairs(BwdArgs A) {
     const float alpha = o * G;
     float c[3];
     bool pos[3];
-    const float* shp = A.sh + i * 3 * ncoef;
+    float acc[3] = {0.5f, 0.5f, 0.5f};
+    if (A.sh_degree == 3) {
+      // the 48 coefficients as twelve 16-B loads, all in flight before the sums
+      const float4* sp4 = reinterpret_cast<const float4*>(A.sh + i * 48);
+      float4 shv[12];
+#pragma unroll
+      for (int q = 0; q < 12; ++q) shv[q] = sp4[q];
+#pragma unroll
+      for (int q = 0; q < 12; ++q) {
+        const float* vv = reinterpret_cast<const float*>(&shv[q]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[(4 * q + e) % 3] += Y[(4 * q + e) / 3] * vv[e];
+      }
+    } else {
+      const float* shp = A.sh + i * 3 * ncoef;
+      for (int ch = 0; ch < 3; ++ch)
+        for (int k = 0; k < 16; ++k)
+          if (k < ncoef) acc[ch] += Y[k] * shp[3 * k + ch];
+    }
     for (int ch = 0; ch < 3; ++ch) {
-      float acc = 0.5f;
-      for (int k = 0; k < 16; ++k)
-        if (k < ncoef) acc += Y[k] * shp[3 * k + ch];
-      pos[ch] = acc > 0.f;
-      c[ch] = pos[ch] ? acc : 0.f;
+      pos[ch] = acc[ch] > 0.f;
+      c[ch] = pos[ch] ? acc[ch] : 0.f;
     }
     // ---- compositing derivatives
     const float wgt = T * alpha;
@@ -254,15 +269,24 @@ __global__ void __launch_bounds__(kBlock) k_bwd_pairs(BwdArgs A) {
   }
 }
 
-// Per Gaussian: [first[g], last[g]) in the sorted records (empty when untouched).
-__global__ void __launch_bounds__(kBlock) k_bwd_segments(const uint64_t* __restrict__ key, int64_t P, int64_t n_gauss,
+// Total number of records: the last ray's offset plus its count.
+__global__ void k_bwd_total(const uint32_t* __restrict__ off, const uint32_t* __restrict__ cnt, int64_t R,
+                            uint32_t* __restrict__ total) {
+  if (threadIdx.x == 0) *total = off[R - 1] + cnt[R - 1];
+}
+
+// Per Gaussian: [first[g], last[g]) in the sorted records (empty when untouched). The
+// number of records is read on the device; a fixed grid strides over them.
+__global__ void __launch_bounds__(kBlock) k_bwd_segments(const uint64_t* __restrict__ key,
+                                                         const uint32_t* __restrict__ total, int64_t n_gauss,
                                                          uint32_t* __restrict__ first, uint32_t* __restrict__ last) {
-  const int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (p >= P) return;
-  const uint64_t k = key[p];
-  if (k >= (uint64_t)n_gauss) return;
-  if (p == 0 || key[p - 1] != k) first[k] = (uint32_t)p;
-  if (p == P - 1 || key[p + 1] != k) last[k] = (uint32_t)(p + 1);
+  const int64_t P = *total;
+  for (int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x; p < P; p += (int64_t)gridDim.x * kBlock) {
+    const uint64_t k = key[p];
+    if (k >= (uint64_t)n_gauss) continue;
+    if (p == 0 || key[p - 1] != k) first[k] = (uint32_t)p;
+    if (p == P - 1 || key[p + 1] != k) last[k] = (uint32_t)(p + 1);
+  }
 }
 
 struct ReduceArgs {
@@ -355,7 +379,10 @@ inline unsigned grid(int64_t n, int per = kBlock) { return (unsigned)std::max<in
 
 }  // namespace
 
-grtx_status trace_backward(const grtx_gaussians* g, const grtx_rays* r, const grtx_trace_params* p,
+// Hit-list capacity of the re-trace when the forward outputs carry no list.
+constexpr int kRetraceCap = 256;
+
+grtx_status trace_backward(const Bvh* bvh, const grtx_gaussians* g, const grtx_rays* r, const grtx_trace_params* p,
                            const grtx_trace_outputs* fwd, const float* grad_rgb, const float* grad_depth,
                            const float* grad_opacity, const grtx_gaussian_grads* grads, unsigned int* truncated,
                            hipStream_t s) {
@@ -364,25 +391,40 @@ grtx_status trace_backward(const grtx_gaussians* g, const grtx_rays* r, const gr
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, truncated);
   GRTX_LAUNCH_CHECK();
   if (R == 0 || N == 0) return GRTX_OK;
-  if ((double)R * (double)std::max(fwd->hit_capacity, 0) >= 4294967295.0) {
-    set_error("trace_backward: %lld rays x %d listed hits exceed 2^32 records", (long long)R, fwd->hit_capacity);
+  const bool retrace = fwd->hit_ids == nullptr;
+  const int cap = !retrace ? fwd->hit_capacity : (fwd->hit_capacity > 0 ? fwd->hit_capacity : kRetraceCap);
+  // every record of the pass lives in scratch sized for the bound rays x cap, so that the
+  // host never waits for the actual number (which stays on the device)
+  const int64_t Pmax = R * (int64_t)cap;
+  if (Pmax >= ((int64_t)1 << 32) - 1) {
+    set_error("trace_backward: %lld rays x %d listed hits exceed 2^32 records", (long long)R, cap);
     return GRTX_ERR_INVALID_ARG;
   }
   Scratch sc(s);
-  // 1. records per ray and their offsets (one host read of the total)
-  uint32_t *cnt = nullptr, *off = nullptr;
+  grtx_trace_outputs fo = *fwd;
+  if (retrace) {
+    // the blended ids are not given: trace again with a list (the trace is deterministic,
+    // so its outputs equal the forward's)
+    float* outs = nullptr;
+    GRTX_TRY(sc.get(&outs, 5 * R));
+    GRTX_TRY(sc.get(&fo.hit_ids, Pmax));
+    GRTX_TRY(sc.get(&fo.hit_counts, R));
+    fo.rgb = outs;
+    fo.depth = outs + 3 * R;
+    fo.opacity = outs + 4 * R;
+    fo.stats = nullptr;
+    fo.hit_capacity = cap;
+    GRTX_TRY(trace(bvh, r, p, &fo, s));
+  }
+  // 1. records per ray, their offsets and the total (on the device)
+  uint32_t *cnt = nullptr, *off = nullptr, *total = nullptr;
   GRTX_TRY(sc.get(&cnt, R));
   GRTX_TRY(sc.get(&off, R));
-  hipLaunchKernelGGL(k_bwd_count, dim3(grid(R)), dim3(kBlock), 0, s, fwd->hit_counts, R, fwd->hit_capacity, cnt,
-                     truncated);
+  GRTX_TRY(sc.get(&total, 1));
+  hipLaunchKernelGGL(k_bwd_count, dim3(grid(R)), dim3(kBlock), 0, s, fo.hit_counts, R, cap, cnt, truncated);
   GRTX_LAUNCH_CHECK();
   GRTX_TRY(exclusive_scan_u32(cnt, off, R, s));
-  uint32_t tail[2] = {0u, 0u};
-  GRTX_HIP(hipMemcpyAsync(&tail[0], off + (R - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  GRTX_HIP(hipMemcpyAsync(&tail[1], cnt + (R - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  GRTX_HIP(hipStreamSynchronize(s));
-  const int64_t P = (int64_t)tail[0] + tail[1];
-  if (P == 0) return GRTX_OK;
+  hipLaunchKernelGGL(k_bwd_total, dim3(1), dim3(64), 0, s, off, cnt, R, total);
   // 2. one record per (ray, blended hit)
   BwdArgs a{};
   a.means = g->means;
@@ -394,12 +436,12 @@ grtx_status trace_backward(const grtx_gaussians* g, const grtx_rays* r, const gr
   a.ray_o = r->origins;
   a.ray_d = r->dirs;
   a.n_rays = R;
-  a.rgb = fwd->rgb;
-  a.depth = fwd->depth;
-  a.opacity = fwd->opacity;
-  a.hit_ids = fwd->hit_ids;
-  a.hit_counts = fwd->hit_counts;
-  a.hit_cap = fwd->hit_capacity;
+  a.rgb = fo.rgb;
+  a.depth = fo.depth;
+  a.opacity = fo.opacity;
+  a.hit_ids = fo.hit_ids;
+  a.hit_counts = fo.hit_counts;
+  a.hit_cap = cap;
   a.bg0 = p->bg[0];
   a.bg1 = p->bg[1];
   a.bg2 = p->bg[2];
@@ -408,27 +450,31 @@ grtx_status trace_backward(const grtx_gaussians* g, const grtx_rays* r, const gr
   a.g_opacity = grad_opacity;
   a.n_gauss = N;
   a.pair_off = off;
-  GRTX_TRY(sc.get(&a.rec, 4 * P));
-  GRTX_TRY(sc.get(&a.key, P));
-  GRTX_TRY(sc.get(&a.val, P));
+  GRTX_TRY(sc.get(&a.rec, 4 * Pmax));
+  GRTX_TRY(sc.get(&a.key, Pmax));
+  GRTX_TRY(sc.get(&a.val, Pmax));
   a.truncated = truncated;
   hipLaunchKernelGGL(k_bwd_pairs, dim3(grid(R)), dim3(kBlock), 0, s, a);
   GRTX_LAUNCH_CHECK();
   // 3. group by Gaussian, keeping ray order inside a Gaussian
   int bits = 1;  // keys are 0..N (N marks a record of no Gaussian)
   while (bits < 63 && ((int64_t)1 << bits) <= N) ++bits;
-
-  GRTX_TRY(sort_by_key(a.key, a.val, P, bits, s));
+  uint64_t *tkeys = nullptr, *skey = nullptr;
+  uint32_t *tvals = nullptr, *sval = nullptr;
+  GRTX_TRY(sc.get(&tkeys, Pmax));
+  GRTX_TRY(sc.get(&tvals, Pmax));
+  GRTX_TRY(sort_by_key_into(a.key, a.val, tkeys, tvals, Pmax, bits, s, total, &skey, &sval));
   // 4. segments and per-Gaussian sums
   uint32_t *first = nullptr, *last = nullptr;
   GRTX_TRY(sc.get(&first, N));
   GRTX_TRY(sc.get(&last, N));
   hipLaunchKernelGGL(k_fill_u32_bwd, dim3(grid(N)), dim3(kBlock), 0, s, first, N);
   hipLaunchKernelGGL(k_fill_u32_bwd, dim3(grid(N)), dim3(kBlock), 0, s, last, N);
-  hipLaunchKernelGGL(k_bwd_segments, dim3(grid(P)), dim3(kBlock), 0, s, a.key, P, N, first, last);
+  hipLaunchKernelGGL(k_bwd_segments, dim3((unsigned)std::min<int64_t>(4096, grid(Pmax))), dim3(kBlock), 0, s, skey,
+                     total, N, first, last);
   ReduceArgs ra{};
   ra.rec = a.rec;
-  ra.order = a.val;
+  ra.order = sval;
   ra.first = first;
   ra.last = last;
   ra.ray_d = r->dirs;

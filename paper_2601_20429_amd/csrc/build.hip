@@ -128,9 +128,12 @@ constexpr int64_t kRadixSmall = (int64_t)256 * kBlock * kRadixItemsSmall;
 // histogram table (a digit's counts over all workgroups), so no scan launch is needed.
 constexpr int kRadixFusedBlocks = 256;
 
+// `n_dev` (may be null) holds the number of keys on the device when the host knows only a
+// bound `n` (the grid is sized for the bound; workgroups past the count see no keys).
 __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
                                                        int items, uint32_t* __restrict__ hist, int nblocks,
-                                                       bool fused) {
+                                                       bool fused, const uint32_t* __restrict__ n_dev) {
+  if (n_dev) n = min(n, (int64_t)*n_dev);
   __shared__ uint32_t s_cnt[256];
   s_cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -252,7 +255,10 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint64_t* __rest
                                                           const uint32_t* __restrict__ vals_in, int64_t n, int shift,
                                                           int items, const uint32_t* __restrict__ offsets,
                                                           int nblocks, bool fused, uint64_t* __restrict__ keys_out,
-                                                          uint32_t* __restrict__ vals_out) {
+                                                          uint32_t* __restrict__ vals_out,
+                                                          const uint32_t* __restrict__ n_dev) {
+  if (n_dev) n = min(n, (int64_t)*n_dev);
+  if ((int64_t)blockIdx.x * kBlock * items >= n) return;  // the whole workgroup is past the keys
   __shared__ uint32_t s_off[256];
   __shared__ uint32_t s_wcnt[kBlock / 64][256];
   const int lane = threadIdx.x & 63;
@@ -743,7 +749,8 @@ inline unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, (n +
 
 
 grtx_status radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t* tvals, int64_t n, Scratch& sc,
-                       hipStream_t s, int passes = 8) {
+                       hipStream_t s, int passes = 8, const uint32_t* n_dev = nullptr, uint64_t** kres = nullptr,
+                       uint32_t** vres = nullptr) {
   const int items = n <= kRadixSmall ? kRadixItemsSmall : kRadixItems;
   const int64_t tile = (int64_t)kBlock * items;
   int nblocks = (int)((n + tile - 1) / tile);
@@ -764,7 +771,8 @@ grtx_status radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t
   uint32_t* vout = tvals;
   for (int pass = 0; pass < passes; ++pass) {
     int shift = 8 * pass;
-    hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kBlock), 0, s, kin, n, shift, items, hist, nblocks, fused);
+    hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kBlock), 0, s, kin, n, shift, items, hist, nblocks, fused,
+                       n_dev);
     if (fused) {
       // the scatter turns the counts into offsets itself
     } else if (nparts > 1 && nparts <= kScanLoopChunks) {
@@ -777,12 +785,15 @@ grtx_status radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t
       hipLaunchKernelGGL(k_scan_down, dim3(1), dim3(kBlock), 0, s, hist, hn, (const uint32_t*)nullptr, offs);
     }
     hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kBlock), 0, s, kin, vin, n, shift, items,
-                       fused ? hist : offs, nblocks, fused, kout, vout);
+                       fused ? hist : offs, nblocks, fused, kout, vout, n_dev);
     GRTX_LAUNCH_CHECK();
     std::swap(kin, kout);
     std::swap(vin, vout);
   }
-  if (kin != keys) {  // an odd number of passes leaves the result in the temporaries
+  if (kres) {  // the caller takes the result where the last pass left it
+    *kres = kin;
+    *vres = vin;
+  } else if (kin != keys) {  // an odd number of passes leaves the result in the temporaries
     GRTX_HIP(hipMemcpyAsync(keys, kin, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
     GRTX_HIP(hipMemcpyAsync(vals, vin, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
   }
@@ -1584,7 +1595,18 @@ grtx_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, hip
   return GRTX_OK;
 }
 
-grtx_status sort_by_key(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, hipStream_t s) {
+grtx_status sort_by_key_into(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t* tvals, int64_t n,
+                             int key_bits, hipStream_t s, const uint32_t* n_dev, uint64_t** kres, uint32_t** vres) {
+  *kres = keys;
+  *vres = vals;
+  if (n <= 1) return GRTX_OK;
+  Scratch sc(s);
+  const int passes = std::max(1, std::min(8, (key_bits + 7) / 8));
+  return radix_sort(keys, vals, tkeys, tvals, n, sc, s, passes, n_dev, kres, vres);
+}
+
+grtx_status sort_by_key(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, hipStream_t s,
+                        const uint32_t* n_dev) {
   if (n <= 1) return GRTX_OK;
   Scratch sc(s);
   uint64_t* tkeys = nullptr;
@@ -1592,7 +1614,7 @@ grtx_status sort_by_key(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits,
   GRTX_TRY(sc.get(&tkeys, n));
   GRTX_TRY(sc.get(&tvals, n));
   const int passes = std::max(1, std::min(8, (key_bits + 7) / 8));
-  return radix_sort(keys, vals, tkeys, tvals, n, sc, s, passes);
+  return radix_sort(keys, vals, tkeys, tvals, n, sc, s, passes, n_dev);
 }
 
 }  // namespace grtx

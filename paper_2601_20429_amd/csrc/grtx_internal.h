@@ -209,8 +209,14 @@ class Scratch {
 // Device utilities of the build, reused by the backward pass (stream-ordered scratch).
 // Exclusive prefix sum of n uint32 values.
 grtx_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
-// Stable LSD radix sort of (keys, vals) by the low key_bits bits of the keys, in place.
-grtx_status sort_by_key(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, hipStream_t s);
+// Stable LSD radix sort of (keys, vals) by the low key_bits bits of the keys, in place. With
+// `n_dev` the first *n_dev (at most n) pairs are sorted, n being the host's bound.
+grtx_status sort_by_key(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, hipStream_t s,
+                        const uint32_t* n_dev = nullptr);
+// The same with caller-owned temporaries (tkeys, tvals of n entries); *kres / *vres receive
+// the arrays that hold the result (the inputs or the temporaries), so nothing is copied.
+grtx_status sort_by_key_into(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t* tvals, int64_t n,
+                             int key_bits, hipStream_t s, const uint32_t* n_dev, uint64_t** kres, uint32_t** vres);
 
 // Secondary rays (objects.hip).
 grtx_status object_rays(const grtx_objects* obj, const grtx_rays* r, float* t_far, float* next_o, float* next_d,
@@ -222,7 +228,7 @@ grtx_status continue_composite(int64_t n, const int32_t* idx, const float* trans
                                const float* crgb, const float* cdepth, const float* copac, float* rgb, float* depth,
                                float* opac, hipStream_t s);
 
-grtx_status trace_backward(const grtx_gaussians* g, const grtx_rays* r, const grtx_trace_params* p,
+grtx_status trace_backward(const Bvh* bvh, const grtx_gaussians* g, const grtx_rays* r, const grtx_trace_params* p,
                            const grtx_trace_outputs* fwd, const float* grad_rgb, const float* grad_depth,
                            const float* grad_opacity, const grtx_gaussian_grads* grads, unsigned int* truncated,
                            hipStream_t s);

@@ -417,12 +417,13 @@ def _gaussians(scene: SceneTensors):
                       scene.opacities.data_ptr(), scene.sh.data_ptr(), scene.n, scene.sh_degree, 0)
 
 
-def trace_backward(bvh: Bvh, origins, dirs, fwd: dict, grad_rgb=None, grad_depth=None, grad_opacity=None,
+def trace_backward(bvh: Bvh, origins, dirs, fwd: dict = None, grad_rgb=None, grad_depth=None, grad_opacity=None,
                    grads: dict = None, k: int = 16, T_min: float = 1e-3, mode: int = CHECKPOINT,
-                   bg=(0.0, 0.0, 0.0), t_near: float = 0.0, stream=None):
+                   bg=(0.0, 0.0, 0.0), t_near: float = 0.0, hit_capacity: int = 0, stream=None):
     """Accumulate dL/d(parameters) into `grads` (dict of tensors shaped like the scene
-    arrays; allocated as zeros when None). `fwd` must hold rgb, depth, opacity, hit_ids and
-    hit_counts of the forward call. Returns (grads, truncated_rays tensor)."""
+    arrays; allocated as zeros when None). `fwd` holds rgb, depth, opacity, hit_ids and
+    hit_counts of the forward call; when None the library traces the rays again with
+    lists of `hit_capacity` entries (0 = 256). Returns (grads, truncated_rays tensor)."""
     sc = bvh.scene
     dev = sc.means.device
     if grads is None:
@@ -433,8 +434,11 @@ def trace_backward(bvh: Bvh, origins, dirs, fwd: dict, grad_rgb=None, grad_depth
     R = int(origins.shape[0])
     rays = _Rays(origins.data_ptr() if R else None, dirs.data_ptr() if R else None, R, t_near, 0, None, None)
     prm = _TraceParams(k, T_min, mode, (C.c_float * 3)(*bg), 0, 0)
-    o = _TraceOutputs(fwd["rgb"].data_ptr(), fwd["depth"].data_ptr(), fwd["opacity"].data_ptr(), None,
-                      fwd["hit_ids"].data_ptr(), fwd["hit_counts"].data_ptr(), int(fwd["hit_ids"].shape[1]), 0)
+    if fwd is None:
+        o = _TraceOutputs(None, None, None, None, None, None, int(hit_capacity), 0)
+    else:
+        o = _TraceOutputs(fwd["rgb"].data_ptr(), fwd["depth"].data_ptr(), fwd["opacity"].data_ptr(), None,
+                          fwd["hit_ids"].data_ptr(), fwd["hit_counts"].data_ptr(), int(fwd["hit_ids"].shape[1]), 0)
     gg = _GaussianGrads(grads["means"].data_ptr(), grads["scales"].data_ptr(), grads["quats"].data_ptr(),
                         grads["opacities"].data_ptr(), grads["sh"].data_ptr())
     g = _gaussians(sc)
