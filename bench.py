@@ -374,7 +374,7 @@ def kernel_k(k):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_trace_k16_scene3m_hbm_traffic.txt")
-TRACE_SOURCES = [os.path.join(ROOT, "paper_2601_20429_amd", "csrc", f) for f in ("trace.hip", "grtx_internal.h")]
+TRACE_SOURCES = [os.path.join(ROOT, "paper_2601_20429_amd", "csrc", "trace.hip")]  # the kernel and its list sizes
 
 
 def source_digest():

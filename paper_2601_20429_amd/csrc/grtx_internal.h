@@ -52,21 +52,10 @@ constexpr uint32_t kNoParent = 0xFFFFFFFFu;
 constexpr int64_t kCutDiv = 2048;
 constexpr int kCutCap = 16384;
 constexpr uint32_t kNoChild = 0xFFFFFFFFu;
-// Default per-ray capacities of the checkpoint (deferred node) and eviction lists. A ray
-// that overflows one falls back to a restart-from-root round, which the other lanes of
-// its wave wait for. At 256/128 such rounds are rare on a 100k-Gaussian scene; structures
-// of more than a million leaves defer several hundred nodes per ray (about a thousand for
-// rays that start inside a 3M-Gaussian scene) and get 2048/512. The serving path keeps
-// 1024/256 for its slot pools.
-constexpr int kDefaultDeferCap = 256;
-constexpr int kDefaultEvictCap = 128;
-constexpr int kLargeDeferCap = 2048;
-constexpr int kLargeEvictCap = 512;
+// Per-ray capacities of the checkpoint (deferred node) and eviction lists of the serving
+// path's slot pools (the trace's defaults live with the trace kernel).
 constexpr int kServeDeferCap = 1024;
 constexpr int kServeEvictCap = 256;
-constexpr int64_t kLargeScene = 1000000;
-inline int default_defer_cap(int64_t n_leaves) { return n_leaves > kLargeScene ? kLargeDeferCap : kDefaultDeferCap; }
-inline int default_evict_cap(int64_t n_leaves) { return n_leaves > kLargeScene ? kLargeEvictCap : kDefaultEvictCap; }
 
 struct Bvh {
   int device = 0;

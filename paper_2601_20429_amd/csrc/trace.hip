@@ -79,7 +79,19 @@ constexpr int kStage = GRTX_STAGE;
 // Work queues. One shared queue keeps a launch's heaviest-first order; one per XCD (8)
 // measured slower.
 constexpr int kChunks = GRTX_CHUNKS;
-constexpr uint64_t kEmptyKey = (0x7F800000ull << 32) | 0xFFFFFFFFull;  // (+inf, max)
+constexpr uint64_t kEmptyKey = (0x7F800000ull << 32) | 0xFFFFFFFFull;  // (+inf, max)// Default per-ray capacities of the checkpoint (deferred node) and eviction lists. A ray
+// that overflows one falls back to a restart-from-root round, which the other lanes of
+// its wave wait for. At 256/128 such rounds are rare on a 100k-Gaussian scene; structures
+// of more than a million leaves defer several hundred nodes per ray (about a thousand for
+// rays that start inside a 3M-Gaussian scene) and get 2048/512.
+constexpr int kDefaultDeferCap = 256;
+constexpr int kDefaultEvictCap = 128;
+constexpr int kLargeDeferCap = 2048;
+constexpr int kLargeEvictCap = 512;
+constexpr int64_t kLargeScene = 1000000;
+inline int default_defer_cap(int64_t n_leaves) { return n_leaves > kLargeScene ? kLargeDeferCap : kDefaultDeferCap; }
+inline int default_evict_cap(int64_t n_leaves) { return n_leaves > kLargeScene ? kLargeEvictCap : kDefaultEvictCap; }
+
 
 enum : int { kIdle = 0, kTrav = 1, kEnd = 2 };
 
