@@ -723,6 +723,112 @@ __global__ void __launch_bounds__(kBlock) k_wide(int64_t n, const uint32_t* __re
                      __uint_as_float(whi[2]));
 }
 
+// ------------------------------------------------------------------ record layout
+// Only the records that the traversal can reach are kept, about a third of the radix
+// tree's internal nodes: the root's, and recursively those its entries list (a record's
+// opened entries are interior to it). They are laid out breadth first: the records of
+// nodes above kLayoutLeaves leaves by one workgroup, level by level, from position 0;
+// each node of at most kLayoutLeaves leaves that such a record lists starts a task, a
+// block of (leaves - 1) positions (the most records its subtree can have) reserved after
+// the first `top_cap` positions, which one thread fills breadth first. So the records a
+// ray meets near each other lie near each other, and the lines fetched hold live records
+// only. `qold` maps each position to the radix-tree node whose record it holds.
+constexpr int64_t kLayoutLeaves = 128;
+constexpr int kLayoutBlock = 1024;
+
+// Reserve and record a task for internal node c (leaf count cnt); returns its position.
+__device__ __forceinline__ uint32_t new_task(uint32_t c, uint32_t cnt, uint32_t top_cap, uint32_t* task_cursor,
+                                             uint32_t* n_tasks, uint2* tasks) {
+  const uint32_t start = top_cap + atomicAdd(task_cursor, cnt - 1u);
+  tasks[atomicAdd(n_tasks, 1u)] = make_uint2(c, start);
+  return start;
+}
+
+// Copy the record of radix-tree node `old` to position `pos` with its internal entries
+// replaced by the positions `pos_of` assigns them.
+template <class F>
+__device__ __forceinline__ void place_record(const float4* __restrict__ wide, uint32_t old, uint32_t pos,
+                                             float4* __restrict__ nodes, F&& pos_of) {
+  const float4* src = wide + (int64_t)kNodeF4 * old;
+  float4 q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[3];
+  uint32_t r[4] = {__float_as_uint(q1.z), __float_as_uint(q1.w), __float_as_uint(q2.x), __float_as_uint(q2.y)};
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (r[j] != kNoChild && !(r[j] & kLeafFlag)) r[j] = pos_of(r[j]);
+  q1.z = __uint_as_float(r[0]);
+  q1.w = __uint_as_float(r[1]);
+  q2.x = __uint_as_float(r[2]);
+  q2.y = __uint_as_float(r[3]);
+  float4* dst = nodes + (int64_t)kNodeF4 * pos;
+  dst[0] = q0;
+  dst[1] = q1;
+  dst[2] = q2;
+  dst[3] = q3;
+}
+
+// The top levels (one workgroup). Root = radix-tree node 0 at position 0; with at most
+// kLayoutLeaves leaves in all, the root itself is the only task (top_cap = 0).
+__global__ void __launch_bounds__(kLayoutBlock) k_layout_top(int64_t m, const float4* __restrict__ wide,
+                                                             const uint32_t* __restrict__ count, uint32_t top_cap,
+                                                             float4* __restrict__ nodes, uint32_t* __restrict__ qold,
+                                                             uint2* __restrict__ tasks, uint32_t* __restrict__ ctr) {
+  __shared__ uint32_t s_next;
+  uint32_t* task_cursor = ctr;
+  uint32_t* n_tasks = ctr + 1;
+  if (m <= kLayoutLeaves) {
+    if (threadIdx.x == 0) {
+      *task_cursor = (uint32_t)(m - 1);
+      *n_tasks = 1u;
+      tasks[0] = make_uint2(0u, 0u);
+    }
+    return;
+  }
+  if (threadIdx.x == 0) {
+    *task_cursor = 0u;
+    *n_tasks = 0u;
+    qold[0] = 0u;
+    s_next = 1u;
+  }
+  __syncthreads();
+  uint32_t begin = 0, end = 1;
+  while (begin < end) {
+    for (uint32_t q = begin + threadIdx.x; q < end; q += kLayoutBlock) {
+      place_record(wide, qold[q], q, nodes, [&](uint32_t c) {
+        const uint32_t cnt = count[c];
+        if (cnt > (uint32_t)kLayoutLeaves) {
+          const uint32_t pos = atomicAdd(&s_next, 1u);
+          qold[pos] = c;
+          return pos;
+        }
+        return new_task(c, cnt, top_cap, task_cursor, n_tasks, tasks);
+      });
+    }
+    __syncthreads();
+    begin = end;
+    end = s_next;
+    __syncthreads();
+  }
+}
+
+// The tasks: one thread fills a block breadth first, using `qold` as its queue.
+__global__ void __launch_bounds__(kBlock) k_layout_tasks(const float4* __restrict__ wide, const uint2* __restrict__ tasks,
+                                                         const uint32_t* __restrict__ ctr, float4* __restrict__ nodes,
+                                                         uint32_t* __restrict__ qold) {
+  const uint32_t n = ctr[1];
+  for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < n; t += gridDim.x * kBlock) {
+    const uint2 task = tasks[t];
+    uint32_t head = task.y, tail = task.y + 1;
+    qold[head] = task.x;
+    while (head < tail) {
+      place_record(wide, qold[head], head, nodes, [&](uint32_t c) {
+        qold[tail] = c;
+        return tail++;
+      });
+      ++head;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ pinhole rays
 
 __global__ void __launch_bounds__(kBlock) k_pinhole(float3 eye, float3 fwd, float3 right, float3 up, int W, int H,
@@ -1351,6 +1457,15 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
   if (n == 0) return GRTX_OK;
   GaussIn gi{g->means, g->scales, g->quats, g->opacities};
   const int64_t nint = m - 1;
+  // node record positions: the top levels in [0, top_cap), then one block per subtree task
+  // (a tree's nodes above kLayoutLeaves leaves can number up to m - 1 when it is lopsided)
+  const int64_t top_cap = m > kLayoutLeaves ? m : 0;
+  const int64_t node_slots = nint > 0 ? top_cap + m : 0;
+  if (node_slots >= (int64_t)kLeafFlag) {
+    set_error("build: %lld leaves exceed the node positions a record reference can hold", (long long)m);
+    return GRTX_ERR_INVALID_ARG;
+  }
+  b->node_slots = node_slots;
   // every array the handle owns in one allocation (each hipMalloc costs host time per frame)
   auto layout = [&](auto&& put) {
     put(&b->codes, m);
@@ -1358,7 +1473,7 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
     put(&b->child, 2 * std::max<int64_t>(nint, 1));
     put(&b->parent, 2 * m - 1);
     put(&b->boxes, 6 * (2 * m - 1));
-    put(&b->nodes, kNodeF4 * std::max<int64_t>(nint, 1));
+    put(&b->nodes, kNodeF4 * std::max<int64_t>(node_slots, 1));
     put(&b->inst, 4 * n);
     if (proxy) put(&b->tris, 3 * m);
     put(&b->roots, 8);
@@ -1501,7 +1616,19 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
                          deep);
     }
     hipLaunchKernelGGL(k_depth_store, dim3(1), dim3(64), 0, s, arrivals, deep, h2, b->depth);
-    hipLaunchKernelGGL(k_wide, dim3(grid_for(nint)), dim3(kBlock), 0, s, m, b->child, b->boxes, b->nodes);
+    // four-wide records of every internal node, then the reachable ones laid out
+    float4* wide = nullptr;
+    uint32_t *qold = nullptr, *ctr = nullptr;
+    uint2* tasks = nullptr;
+    GRTX_TRY(sc.get(&wide, kNodeF4 * nint));
+    GRTX_TRY(sc.get(&qold, node_slots));
+    GRTX_TRY(sc.get(&tasks, m));
+    GRTX_TRY(sc.get(&ctr, 2));
+    hipLaunchKernelGGL(k_wide, dim3(grid_for(nint)), dim3(kBlock), 0, s, m, b->child, b->boxes, wide);
+    hipLaunchKernelGGL(k_layout_top, dim3(1), dim3(kLayoutBlock), 0, s, m, wide, count, (uint32_t)top_cap, b->nodes,
+                       qold, tasks, ctr);
+    hipLaunchKernelGGL(k_layout_tasks, dim3((unsigned)std::min<int64_t>(2048, grid_for(m / 32 + 1))), dim3(kBlock), 0,
+                       s, wide, tasks, ctr, b->nodes, qold);
   } else {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, s, b->parent, 1, kNoParent);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, s, b->depth, 2, 0u);

@@ -17,11 +17,11 @@ namespace grtx {
 // Device data layout
 // ---------------------------------------------------------------------------------------
 //
-// Node record, 64 B (4 x float4), one per internal node of the binary radix tree (node 0
-// = root). A record lists up to four descendants that partition its leaves: starting
-// from the node's two children, the internal entry of largest surface area is replaced
-// by its two children until there are four (records of nodes that no traversal reaches
-// are built but never read). The children's boxes
+// Node record, 64 B (4 x float4), one per internal node of the binary radix tree that the
+// traversal can reach (root at position 0). A record lists up to four descendants that
+// partition its leaves: starting from the node's two children, the internal entry of
+// largest surface area is replaced by its two children until there are four; its
+// internal entries are the positions of their own records. The children's boxes
 // are stored on an 8-bit grid over the node's own box: per axis a an origin o_a (the box
 // minimum) and a power-of-two step s_a with extent / s_a <= 254; child j's planes are
 // o_a + q * s_a with q rounded outward (lo down, hi up), so each stored box contains
@@ -64,7 +64,8 @@ struct Bvh {
   int64_t n_leaves = 0;
   int sh_degree = 0;
   float alpha_min = 0.f;
-  float4* nodes = nullptr;   // [n_leaves-1][kNodeF4]
+  float4* nodes = nullptr;   // [node_slots][kNodeF4]: the reachable records (positions, see k_layout_top)
+  int64_t node_slots = 0;    // positions of `nodes` (some unused between subtree blocks)
   float4* inst = nullptr;    // [n_gauss][4]
   float4* tris = nullptr;    // PROXY20: [n_leaves][3]
   uint64_t* codes = nullptr; // [n_leaves] sorted Morton codes

@@ -248,10 +248,10 @@ grtx_status freeze(Server* sv) {
   int64_t node_base = 0, leaf_base = 0, gauss_base = 0;
   for (size_t i = 0; i < sv->scenes.size(); ++i) {
     const Bvh* b = sv->scenes[i];
-    const int64_t nint = b->n_leaves - 1;
-    if (nint > 0)
-      hipLaunchKernelGGL(k_merge_nodes, dim3((unsigned)((nint + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, b->nodes,
-                         nint, (uint32_t)node_base, (uint32_t)leaf_base, sv->nodes + kNodeF4 * node_base);
+    const int64_t slots = b->node_slots;
+    if (slots > 0)
+      hipLaunchKernelGGL(k_merge_nodes, dim3((unsigned)((slots + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, b->nodes,
+                         slots, (uint32_t)node_base, (uint32_t)leaf_base, sv->nodes + kNodeF4 * node_base);
     hipLaunchKernelGGL(k_merge_inst, dim3((unsigned)((b->n_gauss + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                        b->inst, b->n_gauss, (uint32_t)gauss_base, sv->inst + 4 * leaf_base);
     GRTX_HIP(hipMemcpyAsync(sv->sh + gauss_base * 3 * ncoef, b->sh, sizeof(float) * 3 * ncoef * b->n_gauss,
@@ -259,7 +259,7 @@ grtx_status freeze(Server* sv) {
     hipLaunchKernelGGL(k_merge_root, dim3(1), dim3(64), 0, s, b->roots, (uint32_t)node_base, (uint32_t)leaf_base,
                        sv->roots + 8 * i);
     GRTX_LAUNCH_CHECK();
-    node_base += std::max<int64_t>(nint, 0);
+    node_base += slots;
     leaf_base += b->n_leaves;
     gauss_base += b->n_gauss;
   }
@@ -507,7 +507,7 @@ grtx_status serve_add_scene(Server* sv, const Bvh* b, int32_t* scene_id) {
   GRTX_HIP(hipStreamSynchronize(b->build_stream));
   sv->sh_degree = b->sh_degree;
   sv->scenes.push_back(b);
-  sv->total_nodes += std::max<int64_t>(b->n_leaves - 1, 0);
+  sv->total_nodes += b->node_slots;
   sv->total_leaves += b->n_leaves;
   sv->total_gauss += b->n_gauss;
   *scene_id = (int32_t)sv->scenes.size() - 1;
