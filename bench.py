@@ -323,6 +323,26 @@ def run_ksweep(bvh, o, d, cam, cfg, stream, ks=(4, 8, 16, 32, 64)):
     return res
 
 
+def run_single_round(bvh, sets, T_min, stream, caps=(512, 1024, 2048)):
+    """Single-round tracing (collect every hit of a ray, then sort and blend) for each list
+    capacity: time, nodes per ray and the rays whose hits overflowed the list (incomplete
+    results). `sets` = [(label, origins, dirs, image_width)]."""
+    from paper_2601_20429_amd import grtx
+    res = {}
+    for cap in caps:
+        for label, o, d, w in sets:
+            kw = dict(k=16, T_min=T_min, mode=grtx.SINGLE_ROUND, collect_capacity=cap, image_width=w)
+            out = grtx.trace(bvh, o, d, **kw)
+            ms = time_launch(lambda: grtx.trace(bvh, o, d, out=out, **kw), stream, 2)
+            c = stat_sums(grtx.trace(bvh, o, d, stats=True, **kw))
+            n = int(o.shape[0])
+            res[f"cap{cap}_{label}"] = dict(ms=round(ms, 3), mrays_s=round(n / (ms * 1e-3) / 1e6, 2),
+                                            nodes_per_ray=round((c["nodes"] + c["leaves"]) / n, 1),
+                                            incomplete_rays=c["fallbacks"])
+            del out
+    return res
+
+
 def run_backward(stream):
     """Differentiation workload: 200k Gaussians, 512x512 rays, k = 16; the forward pass keeps
     each ray's blended ids, the backward pass replays them (and, timed separately, traces
@@ -374,7 +394,8 @@ def kernel_k(k):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_trace_k16_scene3m_hbm_traffic.txt")
-TRACE_SOURCES = [os.path.join(ROOT, "paper_2601_20429_amd", "csrc", "trace.hip")]  # the kernel and its list sizes
+# the trace kernel, its list sizes and its device helpers
+TRACE_SOURCES = [os.path.join(ROOT, "paper_2601_20429_amd", "csrc", f) for f in ("trace.hip", "trace_common.h")]
 
 
 def source_digest():
@@ -579,6 +600,8 @@ def run_frame100k(args, stream):
     if not args.no_ksweep:
         res["ksweep"] = run_ksweep(bvh, oo, dd, cam, cfg, stream)
         log("ksweep", json.dumps(res["ksweep"]))
+        res["single_round"] = run_single_round(bvh, [("primary", oo, dd, cam.width)], cfg["T_min"], stream)
+        log("single round", json.dumps(res["single_round"]))
     return res
 
 
@@ -620,7 +643,7 @@ def main():
     ap.add_argument("--mode", choices=["checkpoint", "restart"], default="checkpoint")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the restart-mode and k = 32 runs of the step")
-    ap.add_argument("--cpu-rays", type=int, default=4096)
+    ap.add_argument("--cpu-rays", type=int, default=8192)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="first copy this many GiB device-to-device (a reference kernel for HBM counters)")
@@ -693,6 +716,13 @@ def main():
         log("compare", json.dumps(cmp))
         extra["k32"] = k32 = work.summary(32, mode, max(3, args.steps // 2), 1)
         log("k32", json.dumps(k32))
+        bvh3 = grtx.build(work.st, alpha_min=work.amin)
+        po, pd = grtx.pinhole_rays(work.cam, device=dev)
+        extra["single_round"] = run_single_round(
+            bvh3, [("primary", po, pd, work.cam.width), ("incoherent", work.io, work.id, 0)], work.cfg["T_min"],
+            stream, caps=(2048,))
+        log("single round", json.dumps(extra["single_round"]))
+        del bvh3, po, pd
         if mode == grtx.CHECKPOINT:
             extra["checkpoint_speedup_step"] = cmp["step_ms"] / head["step_ms"]
             extra["checkpoint_speedup_trace"] = (cmp["primary_trace_ms"] + cmp["incoherent_trace_ms"]) / (

@@ -64,7 +64,21 @@ typedef enum grtx_bvh_kind {
  *   replay; Listing 1).
  * RESTART: each round restarts from the root with t_min = the last blended hit
  *   (Sec. III-A; the multi-round baseline). Both modes give identical outputs. */
-typedef enum grtx_mode { GRTX_MODE_CHECKPOINT = 0, GRTX_MODE_RESTART = 1 } grtx_mode;
+typedef enum grtx_mode {
+  GRTX_MODE_CHECKPOINT = 0,
+  GRTX_MODE_RESTART = 1,
+  /* SINGLE_ROUND: the single-round alternative the paper weighs against multi-round
+   *   tracing (Sec. III-C, Observation II): one traversal collects all of a ray's hits,
+   *   unsorted, into a list of collect_capacity entries (no early termination during the
+   *   traversal), which is then sorted and blended with early termination. k is not used.
+   *   A ray with more hits than the list holds gets an incomplete result (the first hits
+   *   in traversal order) and its GRTX_STAT_FALLBACKS counter set to 1; otherwise it
+   *   blends the hits the other modes blend, in the same order, with colour and depth
+   *   equal up to rounding (its accumulation runs in a kernel of its own). SPHERE_INSTANCE
+   *   structures, unbounded rays without a starting transmittance; not available through
+   *   grtx_trace_noalloc. */
+  GRTX_MODE_SINGLE_ROUND = 2
+} grtx_mode;
 
 /* Scene parameters (Sec. II-B). All device pointers, float32, C-contiguous:
  *   means [count,3]; scales [count,3] linear standard deviation per axis;
@@ -170,6 +184,8 @@ typedef struct grtx_trace_params {
   float bg[3];
   int32_t defer_capacity;
   int32_t evict_capacity;
+  int32_t collect_capacity; /* SINGLE_ROUND: hits listed per ray, 0 = 2048, at most 8192 */
+  int32_t reserved;
 } grtx_trace_params;
 
 /* Per-ray counters written to grtx_trace_outputs.stats. */

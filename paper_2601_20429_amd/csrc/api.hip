@@ -140,7 +140,9 @@ static grtx_status check_trace_args(const char* fn, const grtx_bvh* bvh, const g
   CHECK_ARG(rays->count >= 0 && rays->count < ((int64_t)1 << 40), "%s: bad ray count", fn);
   CHECK_ARG(p->k >= 1 && p->k <= 64, "%s: k must be 1..64, got %d", fn, p->k);
   CHECK_ARG(p->T_min >= 0.f && p->T_min < 1.f, "%s: T_min must be in [0,1)", fn);
-  CHECK_ARG(p->mode == GRTX_MODE_CHECKPOINT || p->mode == GRTX_MODE_RESTART, "%s: unknown mode %d", fn, p->mode);
+  CHECK_ARG(p->mode == GRTX_MODE_CHECKPOINT || p->mode == GRTX_MODE_RESTART || p->mode == GRTX_MODE_SINGLE_ROUND,
+            "%s: unknown mode %d", fn, p->mode);
+  CHECK_ARG(p->collect_capacity >= 0 && p->collect_capacity <= 8192, "%s: collect_capacity must be 0..8192", fn);
   CHECK_ARG(p->defer_capacity >= 0 && p->evict_capacity >= 0 && p->defer_capacity <= (1 << 20) &&
                 p->evict_capacity <= (1 << 20),
             "%s: list capacities must be 0..2^20", fn);
@@ -171,27 +173,8 @@ grtx_status grtx_trace_noalloc(const grtx_bvh* bvh, const grtx_rays* rays, const
 grtx_status grtx_trace(const grtx_bvh* bvh, const grtx_rays* rays, const grtx_trace_params* p,
                        const grtx_trace_outputs* out, void* stream) {
   grtx::clear_error();
-  CHECK_ARG(bvh && rays && p && out, "grtx_trace: null argument");
-  CHECK_ARG(rays->count >= 0 && rays->count < ((int64_t)1 << 40), "grtx_trace: bad ray count");
-  CHECK_ARG(p->k >= 1 && p->k <= 64, "grtx_trace: k must be 1..64, got %d", p->k);
-  CHECK_ARG(p->T_min >= 0.f && p->T_min < 1.f, "grtx_trace: T_min must be in [0,1)");
-  CHECK_ARG(p->mode == GRTX_MODE_CHECKPOINT || p->mode == GRTX_MODE_RESTART, "grtx_trace: unknown mode %d", p->mode);
-  CHECK_ARG(p->defer_capacity >= 0 && p->evict_capacity >= 0 && p->defer_capacity <= (1 << 20) &&
-                p->evict_capacity <= (1 << 20),
-            "grtx_trace: list capacities must be 0..2^20");
-  CHECK_ARG(rays->t_near >= 0.f && std::isfinite(rays->t_near), "grtx_trace: t_near must be finite and >= 0");
-  CHECK_ARG(rays->image_width >= 0, "grtx_trace: negative image width");
-  {
-    const int nc = !!rays->next_origins + !!rays->next_dirs + !!rays->path + !!rays->kind;
-    CHECK_ARG(nc == 0 || nc == 4, "grtx_trace: give all four continuation arrays or none");
-    CHECK_ARG(nc == 0 || (rays->t_far && rays->t_near == 0.f),
-              "grtx_trace: continuation rays need t_far and t_near = 0");
-  }
-  if (rays->count > 0) {
-    CHECK_ARG(rays->origins && rays->dirs, "grtx_trace: null ray arrays");
-    CHECK_ARG(out->rgb && out->depth && out->opacity, "grtx_trace: null output arrays");
-    CHECK_ARG(!out->hit_ids || out->hit_capacity > 0, "grtx_trace: hit_ids given with hit_capacity <= 0");
-  }
+  grtx_status st = check_trace_args("grtx_trace", bvh, rays, p, out);
+  if (st != GRTX_OK) return st;
   return grtx::trace(&bvh->impl, rays, p, out, static_cast<hipStream_t>(stream));
 }
 
@@ -211,7 +194,9 @@ grtx_status grtx_trace_backward(const grtx_bvh* bvh, const grtx_gaussians* g, co
               "grtx_trace_backward: with a hit-id list the forward outputs need rgb, depth, opacity and hit counts");
     CHECK_ARG(fwd->hit_capacity >= 0, "grtx_trace_backward: negative hit capacity");
     CHECK_ARG(p->k >= 1 && p->k <= 64 && p->T_min >= 0.f && p->T_min < 1.f &&
-                  (p->mode == GRTX_MODE_CHECKPOINT || p->mode == GRTX_MODE_RESTART) && p->defer_capacity >= 0 &&
+                  (p->mode == GRTX_MODE_CHECKPOINT || p->mode == GRTX_MODE_RESTART ||
+                   p->mode == GRTX_MODE_SINGLE_ROUND) &&
+                  p->collect_capacity >= 0 && p->collect_capacity <= 8192 && p->defer_capacity >= 0 &&
                   p->evict_capacity >= 0 && p->defer_capacity <= (1 << 20) && p->evict_capacity <= (1 << 20),
               "grtx_trace_backward: bad trace parameters");
     CHECK_ARG(grad_rgb || grad_depth || grad_opacity, "grtx_trace_backward: no output gradient given");

@@ -151,6 +151,9 @@ struct TraceScene {
 };
 grtx_status launch_trace(const TraceScene& sc, const grtx_rays* r, const grtx_trace_params* p,
                          const grtx_trace_outputs* o, hipStream_t s);
+// Single-round mode of launch_trace (single.hip).
+grtx_status trace_single_round(const TraceScene& b, const grtx_rays* r, const grtx_trace_params* p,
+                               const grtx_trace_outputs* o, hipStream_t s);
 // Centre-out processing order of the 8x8 tiles of a tiles_x x tiles_y image (device array,
 // kept until the process ends).
 grtx_status centre_out_order(int device, int tiles_x, int tiles_y, const uint32_t** out);

@@ -28,6 +28,7 @@ PROXY20 = 1
 ICO_INSTANCE = 2
 CHECKPOINT = 0
 RESTART = 1
+SINGLE_ROUND = 2
 
 STAT_NODES, STAT_LEAVES, STAT_ROUNDS, STAT_BLENDED, STAT_DEFERRED, STAT_FETCH_FREE, STAT_EVICTED, \
     STAT_FALLBACKS, STAT_STACK_DROPS = range(9)
@@ -73,7 +74,8 @@ class _Objects(C.Structure):
 
 class _TraceParams(C.Structure):
     _fields_ = [("k", C.c_int32), ("T_min", C.c_float), ("mode", C.c_int32), ("bg", C.c_float * 3),
-                ("defer_capacity", C.c_int32), ("evict_capacity", C.c_int32)]
+                ("defer_capacity", C.c_int32), ("evict_capacity", C.c_int32), ("collect_capacity", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class _TraceOutputs(C.Structure):
@@ -279,12 +281,14 @@ def trace(bvh: Bvh, origins: torch.Tensor, dirs: torch.Tensor, k: int = 16, T_mi
           mode: int = CHECKPOINT, bg=(0.0, 0.0, 0.0), t_near: float = 0.0, image_width: int = 0,
           stats: bool = False, hit_capacity: int = 0, defer_capacity: int = 0, evict_capacity: int = 0,
           out=None, stream=None, t_far: torch.Tensor = None, transmittance: torch.Tensor = None,
-          continuation: dict = None, _entry: str = "grtx_trace"):
+          continuation: dict = None, collect_capacity: int = 0, _entry: str = "grtx_trace"):
     """Render rays; returns dict(rgb [R,3], depth [R], opacity [R], and optionally stats
     [R,9] int32, hit_ids [R,cap] int32, hit_counts [R] int32). t_far [R] bounds the rays at
     a surface; transmittance [R] is what each ray starts with (both optional float32).
     continuation: the dict of `object_rays` (next_o, next_d, path, kind); rays that reach
-    their surface then go on along their continuation ray in the same launch."""
+    their surface then go on along their continuation ray in the same launch.
+    mode SINGLE_ROUND collects up to `collect_capacity` hits per ray (0 = 2048), then sorts
+    and blends them."""
     R = int(origins.shape[0])
     dev = origins.device
     if out is None:
@@ -304,7 +308,7 @@ def trace(bvh: Bvh, origins: torch.Tensor, dirs: torch.Tensor, k: int = 16, T_mi
         rays.next_dirs = continuation["next_d"].data_ptr()
         rays.path = continuation["path"].data_ptr()
         rays.kind = continuation["kind"].data_ptr()
-    prm = _TraceParams(k, T_min, mode, (C.c_float * 3)(*bg), defer_capacity, evict_capacity)
+    prm = _TraceParams(k, T_min, mode, (C.c_float * 3)(*bg), defer_capacity, evict_capacity, collect_capacity)
     o = _TraceOutputs(out["rgb"].data_ptr() if R else None, out["depth"].data_ptr() if R else None,
                       out["opacity"].data_ptr() if R else None,
                       out["stats"].data_ptr() if "stats" in out and R else None,

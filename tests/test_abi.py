@@ -60,10 +60,11 @@ def test_trace_rejects_bad_arguments():
     fake = C.c_void_p(1)  # never dereferenced: validation fails first
     rays = grtx._Rays(None, None, 4, 0.0, 0)
     out = grtx._TraceOutputs(None, None, None, None, None, None, 0, 0)
-    for k, T, mode, tn in [(0, 1e-3, 0, 0.0), (65, 1e-3, 0, 0.0), (4, 1.0, 0, 0.0), (4, 1e-3, 2, 0.0),
-                           (4, 1e-3, 0, -1.0)]:
+    for k, T, mode, tn, cc in [(0, 1e-3, 0, 0.0, 0), (65, 1e-3, 0, 0.0, 0), (4, 1.0, 0, 0.0, 0),
+                               (4, 1e-3, 3, 0.0, 0), (4, 1e-3, 0, -1.0, 0), (4, 1e-3, 2, 0.0, 8193),
+                               (4, 1e-3, 2, 0.0, -1)]:
         rays.t_near = tn
-        prm = grtx._TraceParams(k, T, mode, (C.c_float * 3)(0, 0, 0), 0, 0)
+        prm = grtx._TraceParams(k, T, mode, (C.c_float * 3)(0, 0, 0), 0, 0, cc)
         assert L.grtx_trace(fake, C.byref(rays), C.byref(prm), C.byref(out), None) == grtx.ERR_INVALID_ARG
         assert L.grtx_trace_noalloc(fake, C.byref(rays), C.byref(prm), C.byref(out), None) == grtx.ERR_INVALID_ARG
     rays.t_near = 0.0

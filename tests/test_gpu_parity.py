@@ -341,6 +341,69 @@ def test_modes_and_k_bit_identical():
                 assert np.array_equal(cur[key], base[key]), (k, mode, key)
 
 
+@pytest.mark.parametrize("cap", [2048, 512])
+def test_single_round_equals_checkpoint(cap):
+    """Single-round mode (collect all hits, then sort and blend) blends the same hits in
+    the same order as the checkpointed k-buffer trace on every ray whose hits fit its list
+    (here all of them: primary rays of the 100k scene and incoherent rays), with colour,
+    depth and opacity equal up to rounding (1e-5; the accumulation runs in another kernel,
+    so a ray whose transmittance ends within rounding of T_min may stop one hit apart:
+    at most a fraction 1e-3 of the rays)."""
+    say("single round", cap)
+    scene = inputs.cluster_scene(2, 100_000, 3)
+    cam = inputs.orbit_camera(160, 120)
+    po, pd = grtx.pinhole_rays(cam)
+    io, id_ = (dev(a) for a in inputs.incoherent_rays(33, 4096))
+    bvh = build(scene)
+    for o, d, w in [(po, pd, cam.width), (io, id_, 0)]:
+        a = grtx.trace(bvh, o, d, k=16, T_min=T_MIN, image_width=w, hit_capacity=512, stats=True)
+        b = grtx.trace(bvh, o, d, k=16, T_min=T_MIN, image_width=w, hit_capacity=512, stats=True,
+                       mode=grtx.SINGLE_ROUND, collect_capacity=cap)
+        torch.cuda.synchronize()
+        over = int(b["stats"][:, grtx.STAT_FALLBACKS].sum())
+        say(dict(rays=int(o.shape[0]), overflowed=over, nodes_single=float(b["stats"][:, :2].sum()) / o.shape[0],
+                 nodes_checkpoint=float(a["stats"][:, :2].sum()) / o.shape[0]))
+        flag = b["stats"][:, grtx.STAT_FALLBACKS].bool()  # hits beyond the list: incomplete
+        if cap >= 2048:
+            assert over == 0
+        same = (a["hit_counts"] == b["hit_counts"]) & (a["hit_ids"] == b["hit_ids"]).all(1)
+        R = int(o.shape[0])
+        apart = ~same & ~flag
+        assert int(apart.sum()) <= max(1, R // 1000), int(apart.sum())
+        same = same & ~flag
+        T_b = 1 - b["opacity"][apart]
+        assert bool(((T_b - T_MIN).abs() < 1e-5).all())
+        for key in ("rgb", "depth", "opacity"):
+            err = float((a[key][same] - b[key][same]).abs().max())
+            say(key, "max |single - checkpoint|", err)
+            assert err <= 1e-5, key
+        assert torch.equal(b["stats"][:, grtx.STAT_ROUNDS], torch.ones_like(b["stats"][:, 0]))
+
+
+def test_single_round_plain_parity_and_overflow():
+    """The plain 1k-Gaussian case in single-round mode against the oracle; with a list of
+    8 hits the rays with more hits are flagged, and the others still equal the k-buffer
+    trace."""
+    say("single round plain")
+    scene = inputs.small_scene(1, 1000)
+    o, d = oracle_rays(inputs.orbit_camera(64, 64))
+    bvh = build(scene)
+    g = render(bvh, o, d, k=4, mode=grtx.SINGLE_ROUND, cap=256)
+    assert int(g["stats"][:, grtx.STAT_FALLBACKS].sum()) == 0
+    ref = oracle.render(scene, o, d, AMIN, T_MIN, cap=256)
+    say(parity.compare_render(scene, o, d, g, ref, AMIN, T_MIN, label="single round plain"))
+    small = grtx.trace(bvh, dev(o), dev(d), k=4, T_min=T_MIN, mode=grtx.SINGLE_ROUND, collect_capacity=8,
+                       stats=True)
+    full = grtx.trace(bvh, dev(o), dev(d), k=4, T_min=T_MIN, stats=True)
+    torch.cuda.synchronize()
+    flag = small["stats"][:, grtx.STAT_FALLBACKS].bool()
+    n = int(flag.sum())
+    say(dict(flagged=n, rays=o.shape[0]))
+    assert 0 < n < o.shape[0]
+    for key in ("rgb", "depth", "opacity"):
+        assert float((small[key][~flag] - full[key][~flag]).abs().max()) <= 1e-5, key
+
+
 def test_round_structure():
     """Per-round content: round r blends the sorted hits of ranks [(r-1)k, rk), so the
     number of rounds follows from the oracle's blended and total hit counts."""
