@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define GRTX_VERSION 3
+#define GRTX_VERSION 4
 
 typedef enum grtx_status {
   GRTX_OK = 0,
@@ -400,28 +400,37 @@ grtx_status grtx_trace_backward(const grtx_bvh* bvh, const grtx_gaussians* g, co
                                 uint32_t* truncated_rays, void* stream);
 
 /* ---------------------------------------------------------------------------------------
- * Serving: continuous batching of render requests over several device-resident scenes.
- * A worker thread admits queued requests first come, first served while the memory they
- * hold fits the budget, packs all admitted requests (any scenes, any resolutions) into
- * one trace launch per batch, and runs batches on `slots` streams so that a batch formed
- * while another runs overlaps with it on the device. Results are identical to tracing
- * each request alone with grtx_pinhole_rays + grtx_trace on its scene.
+ * Serving: render requests over several device-resident scenes, traced by one persistent
+ * kernel fed from a work queue (an extension of the method to a serving workload; each
+ * ray is traced as in grtx_trace, Sec. III-A and IV-B).
+ * A worker thread admits queued requests first come, first served while their outputs
+ * fit the memory budget and publishes each admitted request to a queue in host memory.
+ * One kernel launch, resident on all but a few CUs, takes the published requests' 8x8
+ * pixel tiles as its lanes fall idle, generates each pixel's ray from the request's
+ * camera, and flags the request in host memory when its last pixel is written; a request
+ * published while the kernel runs joins it. The launch ends once no work has been taken
+ * for `idle_exit_us` (freeing the device for other work) and the next publication starts
+ * another. Results are identical to tracing each request alone with grtx_pinhole_rays +
+ * grtx_trace on its scene.
  * ------------------------------------------------------------------------------------- */
 typedef struct grtx_server grtx_server;
 
-/* memory_budget: device bytes the server may hold (scene set copy, per-slot checkpoint
- *   pools, and per request its rays and outputs until released).
- * slots: streams, i.e. batches that may be in flight at once (0 = 2).
- * k, T_min, mode, bg: as in grtx_trace_params, for every request.
- * max_batch_rays: rays per batch (0 = 2^23); larger requests are refused. */
+/* memory_budget: device bytes the server may hold (the serving kernel's checkpoint pool,
+ *   the scene set copy, and per admitted request its outputs until released; the outputs
+ *   live in an arena grown in chunks of at least 1 GiB within the budget).
+ * k, T_min, mode, bg: as in grtx_trace_params, for every request (mode CHECKPOINT or
+ *   RESTART).
+ * max_request_rays: pixels per request (0 = 2^22, also the largest accepted); larger
+ *   requests are refused.
+ * idle_exit_us: how long the kernel waits for new work before it ends (0 = 2000). */
 typedef struct grtx_serve_config {
   int64_t memory_budget;
-  int32_t slots;
   int32_t k;
   float T_min;
   int32_t mode;
-  int32_t max_batch_rays;
+  int32_t max_request_rays;
   float bg[3];
+  int32_t idle_exit_us;
 } grtx_serve_config;
 
 /* A render request: pinhole camera (as grtx_camera) on scene `scene_id`. */
@@ -437,7 +446,9 @@ typedef struct grtx_request {
 
 /* Result of a finished request: device arrays rgb [H*W,3], depth [H*W], opacity [H*W]
  * (row-major pixels), owned by the server until grtx_serve_release; timestamps in
- * seconds since the server was created (submitted, admitted, launched, finished). */
+ * seconds since the server was created: submitted, admitted (outputs placed and the
+ * request published to the kernel; t_launch is the same moment), finished (seen by the
+ * worker). */
 typedef struct grtx_request_result {
   const float* rgb;
   const float* depth;
@@ -450,14 +461,18 @@ typedef struct grtx_request_result {
   double t_done;
 } grtx_request_result;
 
-/* Latency percentiles over finished requests (submission to completion), and throughput
- * over the span from the first launch to the last completion. */
+/* Latency percentiles over finished requests (submission to completion), throughput
+ * over the span from the first publication to the last completion, the budget's use
+ * (bytes held by admitted requests, bytes the budget leaves for outputs, bytes of arena
+ * allocated) and the number of kernel launches so far. */
 typedef struct grtx_serve_stats {
   int64_t submitted;
   int64_t completed;
   int64_t rays_completed;
   int64_t bytes_in_use;
   int64_t bytes_available;
+  int64_t bytes_arena;
+  int64_t launches;
   double p50_ms;
   double p99_ms;
   double mean_ms;
@@ -470,7 +485,7 @@ typedef struct grtx_serve_stats {
 grtx_status grtx_serve_request_bytes(const grtx_request* r, int64_t* bytes);
 
 /* Create a server on the current device. GRTX_ERR_CAPACITY if the budget cannot even
- * hold the slots' checkpoint pools. */
+ * hold the serving kernel's checkpoint pool. */
 grtx_status grtx_serve_create(const grtx_serve_config* cfg, grtx_server** out);
 
 /* Register a built SPHERE_INSTANCE structure (all scenes share one SH degree) before the
@@ -480,11 +495,11 @@ grtx_status grtx_serve_create(const grtx_serve_config* cfg, grtx_server** out);
 grtx_status grtx_serve_add_scene(grtx_server* s, const grtx_bvh* bvh, int32_t* scene_id);
 
 /* Queue a request; *ticket identifies it. GRTX_ERR_CAPACITY if it can never fit the
- * budget or the batch size. Thread-safe. */
+ * budget or max_request_rays. Thread-safe. */
 grtx_status grtx_serve_submit(grtx_server* s, const grtx_request* r, uint64_t* ticket);
 
 /* GRTX_OK with *res filled once the request has finished, GRTX_ERR_NOT_READY while it
- * is queued or in flight, GRTX_ERR_DEVICE if its batch failed. Thread-safe. */
+ * is queued or in flight, GRTX_ERR_DEVICE if its launch failed. Thread-safe. */
 grtx_status grtx_serve_poll(grtx_server* s, uint64_t ticket, grtx_request_result* res);
 
 /* Copy a finished request's outputs into caller-owned DEVICE arrays (rgb [H*W,3],
@@ -492,12 +507,14 @@ grtx_status grtx_serve_poll(grtx_server* s, uint64_t ticket, grtx_request_result
 grtx_status grtx_serve_copy_result(grtx_server* s, uint64_t ticket, float* rgb, float* depth, float* opacity,
                                    void* stream);
 
-/* Free a finished request's outputs (and its share of the budget). */
+/* Free a finished request's outputs (and its share of the budget), or withdraw a
+ * request that is still queued; GRTX_ERR_NOT_READY while it is in flight. */
 grtx_status grtx_serve_release(grtx_server* s, uint64_t ticket);
 
 grtx_status grtx_serve_get_stats(grtx_server* s, grtx_serve_stats* st);
 
-/* Stop the worker after the batches in flight and free everything. NULL is accepted. */
+/* Stop: the kernel finishes the published requests, queued ones are dropped, and
+ * everything is freed. NULL is accepted. */
 grtx_status grtx_serve_destroy(grtx_server* s);
 
 /* Message of the last failure on the calling thread ("" if none). */

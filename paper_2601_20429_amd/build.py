@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgrtx.so")
 SOURCES = ["api.hip", "build.hip", "trace.hip", "single.hip", "backward.hip", "serve.hip", "objects.hip"]
-HEADERS = ["grtx_internal.h", "trace_common.h"]
+HEADERS = ["grtx_internal.h", "trace_common.h", "camera.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

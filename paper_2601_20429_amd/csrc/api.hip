@@ -293,11 +293,12 @@ grtx_status grtx_serve_create(const grtx_serve_config* cfg, grtx_server** out) {
   grtx::clear_error();
   CHECK_ARG(cfg && out, "grtx_serve_create: null argument");
   CHECK_ARG(cfg->memory_budget > 0, "grtx_serve_create: memory_budget must be positive");
-  CHECK_ARG(cfg->slots >= 0 && cfg->slots <= 16, "grtx_serve_create: slots must be 0..16");
   CHECK_ARG(cfg->k >= 1 && cfg->k <= 64, "grtx_serve_create: k must be 1..64");
   CHECK_ARG(cfg->T_min >= 0.f && cfg->T_min < 1.f, "grtx_serve_create: T_min must be in [0,1)");
   CHECK_ARG(cfg->mode == GRTX_MODE_CHECKPOINT || cfg->mode == GRTX_MODE_RESTART, "grtx_serve_create: unknown mode");
-  CHECK_ARG(cfg->max_batch_rays >= 0, "grtx_serve_create: negative max_batch_rays");
+  CHECK_ARG(cfg->max_request_rays >= 0 && cfg->max_request_rays <= (1 << grtx::kServePixelBits),
+            "grtx_serve_create: max_request_rays must be 0..2^22");
+  CHECK_ARG(cfg->idle_exit_us >= 0 && cfg->idle_exit_us <= 10000000, "grtx_serve_create: idle_exit_us must be 0..1e7");
   grtx::Server* sv = nullptr;
   grtx_status st = grtx::serve_create(cfg, &sv);
   if (st != GRTX_OK) return st;

@@ -22,6 +22,7 @@
 #include <cmath>
 #include <type_traits>
 
+#include "camera.h"
 #include "grtx_internal.h"
 
 namespace grtx {
@@ -831,23 +832,20 @@ __global__ void __launch_bounds__(kBlock) k_layout_tasks(const float4* __restric
 
 // ------------------------------------------------------------------ pinhole rays
 
-__global__ void __launch_bounds__(kBlock) k_pinhole(float3 eye, float3 fwd, float3 right, float3 up, int W, int H,
-                                                    float* __restrict__ origins, float* __restrict__ dirs) {
+__global__ void __launch_bounds__(kBlock) k_pinhole(CameraFrame cf, int W, int H, float* __restrict__ origins,
+                                                    float* __restrict__ dirs) {
   int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   if (i >= (int64_t)W * H) return;
   int y = (int)(i / W), x = (int)(i - (int64_t)y * W);
-  float sx = 2.f * ((float)x + 0.5f) / (float)W - 1.f;
-  float sy = 1.f - 2.f * ((float)y + 0.5f) / (float)H;
-  float dx = fwd.x + sx * right.x + sy * up.x;
-  float dy = fwd.y + sx * right.y + sy * up.y;
-  float dz = fwd.z + sx * right.z + sy * up.z;
-  float inv = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
-  origins[3 * i + 0] = eye.x;
-  origins[3 * i + 1] = eye.y;
-  origins[3 * i + 2] = eye.z;
-  dirs[3 * i + 0] = dx * inv;
-  dirs[3 * i + 1] = dy * inv;
-  dirs[3 * i + 2] = dz * inv;
+  float dx, dy, dz;
+  pinhole_dir(cf.fwd[0], cf.fwd[1], cf.fwd[2], cf.right[0], cf.right[1], cf.right[2], cf.up[0], cf.up[1], cf.up[2], x, y,
+              W, H, &dx, &dy, &dz);
+  origins[3 * i + 0] = cf.eye[0];
+  origins[3 * i + 1] = cf.eye[1];
+  origins[3 * i + 2] = cf.eye[2];
+  dirs[3 * i + 0] = dx;
+  dirs[3 * i + 1] = dy;
+  dirs[3 * i + 2] = dz;
 }
 
 inline unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + kBlock - 1) / kBlock); }
@@ -1666,35 +1664,13 @@ grtx_status export_topology(const Bvh* b, uint32_t* child, uint32_t* parent, uin
 }
 
 grtx_status pinhole_rays(const grtx_camera* cam, float* origins, float* dirs, hipStream_t s) {
-  double e[3], f[3], r[3], u[3];
-  for (int a = 0; a < 3; ++a) {
-    e[a] = cam->eye[a];
-    f[a] = (double)cam->target[a] - cam->eye[a];
-  }
-  double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
-  for (double& x : f) x /= fl;
-  const float* up = cam->up;
-  r[0] = f[1] * up[2] - f[2] * up[1];
-  r[1] = f[2] * up[0] - f[0] * up[2];
-  r[2] = f[0] * up[1] - f[1] * up[0];
-  double rl = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-  if (!(fl > 0.0) || !(rl > 0.0)) {
+  CameraFrame cf;
+  if (!camera_frame(cam->eye, cam->target, cam->up, cam->fov_y_deg, cam->width, cam->height, &cf)) {
     set_error("pinhole camera: degenerate eye/target/up");
     return GRTX_ERR_INVALID_ARG;
   }
-  for (double& x : r) x /= rl;
-  u[0] = r[1] * f[2] - r[2] * f[1];
-  u[1] = r[2] * f[0] - r[0] * f[2];
-  u[2] = r[0] * f[1] - r[1] * f[0];
-  double th = std::tan(0.5 * (double)cam->fov_y_deg * M_PI / 180.0);
-  double aspect = (double)cam->width / (double)cam->height;
-  float3 E = make_float3((float)e[0], (float)e[1], (float)e[2]);
-  float3 F = make_float3((float)f[0], (float)f[1], (float)f[2]);
-  float3 R = make_float3((float)(r[0] * th * aspect), (float)(r[1] * th * aspect), (float)(r[2] * th * aspect));
-  float3 U = make_float3((float)(u[0] * th), (float)(u[1] * th), (float)(u[2] * th));
   int64_t n = (int64_t)cam->width * cam->height;
-  hipLaunchKernelGGL(k_pinhole, dim3(grid_for(n)), dim3(kBlock), 0, s, E, F, R, U, cam->width, cam->height, origins,
-                     dirs);
+  hipLaunchKernelGGL(k_pinhole, dim3(grid_for(n)), dim3(kBlock), 0, s, cf, cam->width, cam->height, origins, dirs);
   GRTX_LAUNCH_CHECK();
   return GRTX_OK;
 }

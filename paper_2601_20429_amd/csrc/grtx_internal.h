@@ -53,9 +53,72 @@ constexpr int64_t kCutDiv = 2048;
 constexpr int kCutCap = 16384;
 constexpr uint32_t kNoChild = 0xFFFFFFFFu;
 // Per-ray capacities of the checkpoint (deferred node) and eviction lists of the serving
-// path's slot pools (the trace's defaults live with the trace kernel).
+// kernel's pool (the trace's defaults live with the trace kernel).
 constexpr int kServeDeferCap = 1024;
 constexpr int kServeEvictCap = 256;
+
+// ---------------------------------------------------------------------------------------
+// Serving work queue
+// ---------------------------------------------------------------------------------------
+//
+// Requests are numbered j = 0, 1, ... in publication order and live in ring slot
+// j % kServeRing from publication until the kernel reports them finished; the host
+// publishes request j only once the request before it in that slot has finished. A
+// request's work items are its 8x8 pixel tiles x 64 (items of a ragged edge tile that
+// fall outside the image are skipped). A served ray's id is slot << kServePixelBits |
+// pixel, so a request holds at most 2^kServePixelBits pixels.
+constexpr int kServeRing = 1024;
+constexpr int kServePixelBits = 22;
+
+// One request as the host publishes it (fine-grained host memory, read by the kernel).
+struct ServeDesc {
+  uint32_t seq;       // request number j
+  uint32_t n_work;    // work items: tiles x 64
+  int32_t width, height, tiles_x, scene;
+  uint32_t n_pixels;  // width x height: rays whose outputs complete the request
+  uint32_t pad;
+  uint64_t order;     // device address of the tile order (uint32 per tile), 0 for row-major
+  uint64_t out;       // device address of the outputs: rgb [n,3], depth [n], opacity [n]
+  float eye[3], fwd[3], right[3], up[3];
+};
+
+// Host side of the queue, in fine-grained (coherent) pinned host memory.
+struct ServeHost {
+  uint64_t published;           // requests published; written after their descriptors
+  uint32_t stop;                // set by the host: finish the published work, then exit
+  uint32_t pad;
+  uint32_t done[kServeRing];    // set to 1 by the kernel when the slot's request finished
+  ServeDesc ring[kServeRing];
+};
+
+// Per ring slot on the device: the claim counter, (request << 32) | work items claimed
+// (it may run past the request's items: claims beyond them are empty), and the count of
+// the request's finished rays, on separate 64-B lines.
+struct alignas(128) ServeSlot {
+  uint64_t claim;
+  uint32_t pad0[14];
+  uint32_t done;
+  uint32_t pad1[15];
+};
+
+// Device side of the queue (device memory; read with device-scope atomic loads, written
+// with atomics, so every XCD sees one value).
+//   state: bit 63 closing (no more requests are taken), bits 32..62 requests published
+//          to the kernel, bits 0..31 the request whose items are being handed out.
+//   A request's descriptor and claim counter are set up (by the lane that reads the
+//   host's count, under poll_lock) before the published count covers it.
+constexpr uint64_t kServeClosing = 1ull << 63;
+constexpr uint32_t kServeNoRequest = 0xFFFFFFFFu;
+struct ServeDev {
+  uint64_t state;
+  uint64_t pad_a[7];
+  uint64_t last_poll;     // wall clock of the last read of the host's count
+  uint64_t inited;        // requests whose descriptor and claim counter are set up
+  uint32_t poll_lock;
+  uint32_t pad_b[11];
+  ServeSlot slot[kServeRing];
+  ServeDesc desc[kServeRing];
+};
 
 struct Bvh {
   int device = 0;
@@ -154,6 +217,24 @@ grtx_status launch_trace(const TraceScene& sc, const grtx_rays* r, const grtx_tr
 // Single-round mode of launch_trace (single.hip).
 grtx_status trace_single_round(const TraceScene& b, const grtx_rays* r, const grtx_trace_params* p,
                                const grtx_trace_outputs* o, hipStream_t s);
+// The serving kernel: a persistent trace launch over the merged scene set that takes
+// requests from the work queue until the host stops it or no work has been taken for
+// `idle_ticks` of the device wall clock (then it sets `closing` and its waves exit once
+// their rays are done). `pool` holds serve_pool_bytes(k) bytes.
+struct ServeLaunch {
+  TraceScene scene;
+  int k;
+  float T_min;
+  int mode;
+  float bg[3];
+  ServeHost* host;
+  ServeDev* dev;
+  void* pool;
+  uint64_t poll_ticks;
+  uint64_t idle_ticks;
+};
+grtx_status launch_serve(const ServeLaunch& L, hipStream_t s);
+int64_t serve_pool_bytes(int k);
 // Centre-out processing order of the 8x8 tiles of a tiles_x x tiles_y image (device array,
 // kept until the process ends).
 grtx_status centre_out_order(int device, int tiles_x, int tiles_y, const uint32_t** out);

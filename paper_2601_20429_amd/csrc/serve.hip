@@ -1,14 +1,19 @@
-// Serving: continuous batching of render requests over several device-resident scenes.
+// Serving: render requests over several device-resident scenes, traced by one persistent
+// kernel that takes work from a queue the host appends to.
 //
 // Scenes are merged once into one device scene set (node, leaf and Gaussian indices
-// offset per scene; one root entry per scene), so one trace launch can mix rays of any
-// scenes: each ray carries its scene index and starts at that scene's root. A worker
-// thread admits queued requests while their memory fits the budget, packs every admitted
-// request into the next batch (rays of all its requests generated on the device, in 8x8
-// tiles per image), and launches the batch on a free stream; batches on different
-// streams overlap on the device, so requests that arrive while one batch runs go out in
-// the next one without waiting for it. Completion is observed with events; latency is
-// measured from submission to the completion of the request's batch.
+// offset per scene; one root entry per scene), so one launch can trace rays of any scene:
+// each ray carries its scene index and starts at that scene's root. A worker thread
+// admits queued requests first come, first served while their outputs fit the memory
+// budget (their outputs are placed in a pooled device arena) and publishes each admitted
+// request to the work queue; the serving kernel, launched when work is published and no
+// launch is running, takes the requests' 8x8 pixel tiles as its lanes fall idle,
+// generates their rays from the request's camera, writes each pixel's outputs, and raises
+// the request's flag in host memory when its last pixel is written. A request that arrives
+// while the kernel runs joins it: its tiles go to the next lanes that fall idle. The
+// kernel ends once no work has been taken for the idle time (or the server stops), and
+// the next publication starts it again. Latency is measured from submission to the
+// worker seeing the request's flag.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,18 +23,26 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
 #include <vector>
 
+#include "camera.h"
 #include "grtx_internal.h"
 
 namespace grtx {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kMaxBatchRequests = 1024;
+// Output arena: device memory in chunks of at least this size, grown as admission needs
+// and kept until the server is destroyed; request outputs are placed first-fit.
+constexpr int64_t kArenaChunk = (int64_t)1 << 30;
+constexpr int64_t kArenaAlign = 256;
+// Wall-clock interval between the kernel's reads of the host's published count.
+constexpr int kPollMicros = 4;
+constexpr int kDefaultIdleMicros = 2000;
 
 // ------------------------------------------------------------------ scene-set merge
 
@@ -76,81 +89,6 @@ __global__ void k_merge_root(const float* __restrict__ src, uint32_t node_base, 
   if (threadIdx.x == 7) dst[7] = 0.f;
 }
 
-// ------------------------------------------------------------------ batch rays and outputs
-
-// One request of a batch, as the device sees it.
-struct ReqDev {
-  float eye[3];
-  float fwd[3];
-  float right[3];  // right * tan(fov/2) * aspect
-  float up[3];     // true up * tan(fov/2)
-  int32_t width, height;
-  int64_t ray_offset;  // first batch ray of the request
-  int32_t scene;
-  int32_t tiled;       // rays in 8x8 tiles (width and height multiples of 8)
-  const uint32_t* order;  // tile processing order (centre-out) when tiled
-  float* rgb;          // request outputs, row-major pixels
-  float* depth;
-  float* opacity;
-};
-
-__device__ __forceinline__ int find_request(const ReqDev* __restrict__ rq, int nreq, int64_t i) {
-  int lo = 0, hi = nreq - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (rq[mid].ray_offset <= i) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
-__device__ __forceinline__ int64_t pixel_of(const ReqDev& q, int64_t j) {
-  if (!q.tiled) return j;
-  const int64_t tiles_x = q.width / 8;
-  const int64_t tile = q.order[j >> 6];
-  const int within = (int)(j & 63);
-  const int64_t ty = tile / tiles_x, tx = tile - ty * tiles_x;
-  return (ty * 8 + (within >> 3)) * q.width + tx * 8 + (within & 7);
-}
-
-// Rays of every request of the batch; the arithmetic is the single-camera generator's.
-__global__ void __launch_bounds__(kBlock) k_batch_rays(const ReqDev* __restrict__ rq, int nreq, int64_t total,
-                                                       float* __restrict__ origins, float* __restrict__ dirs,
-                                                       int32_t* __restrict__ ray_scene) {
-  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (i >= total) return;
-  const ReqDev& q = rq[find_request(rq, nreq, i)];
-  const int64_t pix = pixel_of(q, i - q.ray_offset);
-  const int W = q.width, H = q.height;
-  const int y = (int)(pix / W), x = (int)(pix - (int64_t)y * W);
-  float sx = 2.f * ((float)x + 0.5f) / (float)W - 1.f;
-  float sy = 1.f - 2.f * ((float)y + 0.5f) / (float)H;
-  float dx = q.fwd[0] + sx * q.right[0] + sy * q.up[0];
-  float dy = q.fwd[1] + sx * q.right[1] + sy * q.up[1];
-  float dz = q.fwd[2] + sx * q.right[2] + sy * q.up[2];
-  float inv = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
-  origins[3 * i + 0] = q.eye[0];
-  origins[3 * i + 1] = q.eye[1];
-  origins[3 * i + 2] = q.eye[2];
-  dirs[3 * i + 0] = dx * inv;
-  dirs[3 * i + 1] = dy * inv;
-  dirs[3 * i + 2] = dz * inv;
-  ray_scene[i] = q.scene;
-}
-
-__global__ void __launch_bounds__(kBlock) k_batch_scatter(const ReqDev* __restrict__ rq, int nreq, int64_t total,
-                                                          const float* __restrict__ rgb,
-                                                          const float* __restrict__ depth,
-                                                          const float* __restrict__ opac) {
-  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (i >= total) return;
-  const ReqDev& q = rq[find_request(rq, nreq, i)];
-  const int64_t pix = pixel_of(q, i - q.ray_offset);
-  q.rgb[3 * pix + 0] = rgb[3 * i + 0];
-  q.rgb[3 * pix + 1] = rgb[3 * i + 1];
-  q.rgb[3 * pix + 2] = rgb[3 * i + 2];
-  q.depth[pix] = depth[i];
-  q.opacity[pix] = opac[i];
-}
 
 double now_s() {
   using namespace std::chrono;
@@ -159,11 +97,10 @@ double now_s() {
 
 }  // namespace
 
-// Bytes a request holds while admitted: its rays (origins, directions, scene index), the
-// batch outputs and its own outputs.
+// Bytes a request holds while admitted: its outputs (rgb, depth, opacity).
 int64_t request_bytes(const grtx_request* r) {
   const int64_t n = (int64_t)r->width * r->height;
-  return n * (24 + 4 + 20 + 20);
+  return n * 20;
 }
 
 struct Server {
@@ -181,33 +118,42 @@ struct Server {
   int64_t total_leaves = 0, total_nodes = 0, total_gauss = 0;
   std::vector<void*> scene_allocs;
   int64_t scene_bytes = 0;
-  // slots: one stream each, with batch buffers
-  struct Slot {
-    hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
-    float* rays = nullptr;     // origins then directions
-    int32_t* rscene = nullptr;
-    float* out = nullptr;      // rgb, depth, opacity
-    ReqDev* table_dev = nullptr;
-    ReqDev* table_host = nullptr;  // pinned
-    int64_t cap = 0;
-    bool busy = false;
-    std::vector<uint64_t> tickets;
-    int64_t rays_in_batch = 0;
+  // work queue and kernel
+  hipStream_t stream = nullptr;
+  hipEvent_t kernel_done = nullptr;
+  bool kernel_running = false;
+  ServeHost* host = nullptr;      // fine-grained pinned host memory
+  ServeHost* host_dev = nullptr;  // its device address
+  ServeDev* dev = nullptr;
+  void* pool = nullptr;
+  int64_t fixed_bytes = 0;        // kernel pool and queue
+  uint64_t poll_ticks = 0, idle_ticks = 0;
+  uint64_t published = 0;         // requests published so far (request numbers)
+  uint64_t slot_ticket[kServeRing] = {};  // ticket of the request in each slot (0: free)
+  std::vector<int> in_flight;     // slots of published, unfinished requests
+  int64_t launches = 0;
+  // output arena
+  struct Chunk {
+    char* base = nullptr;
+    int64_t size = 0;
+    std::map<int64_t, int64_t> free;  // offset -> length, coalesced
   };
-  std::vector<Slot> slots;
-  int64_t pool_bytes_per_slot = 0;
+  std::vector<Chunk> chunks;
+  int64_t arena_bytes = 0;
   // requests
   struct Req {
     grtx_request r{};
     int64_t rays = 0, bytes = 0;
     double t_submit = 0, t_admit = 0, t_launch = 0, t_done = 0;
+    const uint32_t* order = nullptr;
     float* out = nullptr;
-    int state = 0;  // 0 queued, 1 admitted, 2 launched, 3 done, 4 failed
+    int chunk = -1;
+    int64_t offset = 0, span = 0;
+    int state = 0;  // 0 queued, 1 admitted and published, 3 done, 4 failed
   };
   std::mutex mu;
   std::condition_variable cv;
-  std::deque<uint64_t> queued, admitted;
+  std::deque<uint64_t> queued;
   std::unordered_map<uint64_t, Req> reqs;
   uint64_t next_ticket = 1;
   int64_t in_use = 0, available = 0;
@@ -239,7 +185,7 @@ grtx_status sv_alloc(Server* sv, T** p, size_t count) {
 
 grtx_status freeze(Server* sv) {
   if (sv->frozen) return GRTX_OK;
-  hipStream_t s = sv->slots[0].stream;
+  hipStream_t s = sv->stream;
   SV_TRY(sv_alloc(sv, &sv->nodes, kNodeF4 * (size_t)std::max<int64_t>(sv->total_nodes, 1)));
   SV_TRY(sv_alloc(sv, &sv->inst, 4 * (size_t)sv->total_gauss));
   const int ncoef = (sv->sh_degree + 1) * (sv->sh_degree + 1);
@@ -269,181 +215,232 @@ grtx_status freeze(Server* sv) {
   return GRTX_OK;
 }
 
-void camera_basis(const grtx_request& r, ReqDev& q) {
-  double f[3], rr[3], u[3];
-  for (int a = 0; a < 3; ++a) f[a] = (double)r.target[a] - r.eye[a];
-  double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
-  for (double& x : f) x /= fl;
-  rr[0] = f[1] * r.up[2] - f[2] * r.up[1];
-  rr[1] = f[2] * r.up[0] - f[0] * r.up[2];
-  rr[2] = f[0] * r.up[1] - f[1] * r.up[0];
-  double rl = std::sqrt(rr[0] * rr[0] + rr[1] * rr[1] + rr[2] * rr[2]);
-  for (double& x : rr) x /= rl;
-  u[0] = rr[1] * f[2] - rr[2] * f[1];
-  u[1] = rr[2] * f[0] - rr[0] * f[2];
-  u[2] = rr[0] * f[1] - rr[1] * f[0];
-  double th = std::tan(0.5 * (double)r.fov_y_deg * M_PI / 180.0);
-  double aspect = (double)r.width / (double)r.height;
+// First-fit placement of `bytes` in the arena's chunks; false if no free range holds it.
+bool arena_place(Server* sv, int64_t bytes, int* chunk, int64_t* offset, int64_t* span) {
+  const int64_t need = (bytes + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
+  for (size_t c = 0; c < sv->chunks.size(); ++c) {
+    auto& fl = sv->chunks[c].free;
+    for (auto it = fl.begin(); it != fl.end(); ++it) {
+      if (it->second < need) continue;
+      const int64_t off = it->first, len = it->second;
+      fl.erase(it);
+      if (len > need) fl.emplace(off + need, len - need);
+      *chunk = (int)c;
+      *offset = off;
+      *span = need;
+      return true;
+    }
+  }
+  return false;
+}
+
+void arena_free(Server* sv, int chunk, int64_t offset, int64_t span) {
+  auto& fl = sv->chunks[chunk].free;
+  auto it = fl.emplace(offset, span).first;
+  auto nx = std::next(it);
+  if (nx != fl.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    fl.erase(nx);
+  }
+  if (it != fl.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      fl.erase(it);
+    }
+  }
+}
+
+// Write request `rq` (admitted, ticket t) into its ring slot and publish it (lock held).
+void publish_locked(Server* sv, uint64_t t, Server::Req& rq) {
+  const uint64_t j = sv->published;
+  const int slot = (int)(j % kServeRing);
+  ServeDesc& d = sv->host->ring[slot];
+  CameraFrame cf;
+  camera_frame(rq.r.eye, rq.r.target, rq.r.up, rq.r.fov_y_deg, rq.r.width, rq.r.height, &cf);
+  const int tiles_x = (rq.r.width + 7) / 8, tiles_y = (rq.r.height + 7) / 8;
+  d.seq = (uint32_t)j;
+  d.n_work = (uint32_t)((int64_t)tiles_x * tiles_y * 64);
+  d.width = rq.r.width;
+  d.height = rq.r.height;
+  d.tiles_x = tiles_x;
+  d.scene = rq.r.scene_id;
+  d.n_pixels = (uint32_t)rq.rays;
+  d.pad = 0;
+  d.order = reinterpret_cast<uint64_t>(rq.order);
+  d.out = reinterpret_cast<uint64_t>(rq.out);
   for (int a = 0; a < 3; ++a) {
-    q.eye[a] = r.eye[a];
-    q.fwd[a] = (float)f[a];
-    q.right[a] = (float)(rr[a] * th * aspect);
-    q.up[a] = (float)(u[a] * th);
+    d.eye[a] = cf.eye[a];
+    d.fwd[a] = cf.fwd[a];
+    d.right[a] = cf.right[a];
+    d.up[a] = cf.up[a];
   }
-  q.width = r.width;
-  q.height = r.height;
-  q.tiled = (r.width % 8 == 0 && r.height % 8 == 0) ? 1 : 0;
+  sv->host->done[slot] = 0;
+  // the descriptor and the cleared flag reach memory before the count that publishes them
+  std::atomic_thread_fence(std::memory_order_release);
+  __atomic_store_n(&sv->host->published, j + 1, __ATOMIC_RELEASE);
+  sv->published = j + 1;
+  sv->slot_ticket[slot] = t;
+  sv->in_flight.push_back(slot);
+  rq.state = 1;
+  rq.t_admit = rq.t_launch = now_s() - sv->t0;
+  if (sv->first_launch < 0) sv->first_launch = rq.t_launch;
 }
 
-// Launch one batch on `slot` with the tickets in `batch` (lock not held).
-grtx_status launch_batch(Server* sv, Server::Slot& slot, const std::vector<uint64_t>& batch,
-                         const std::vector<Server::Req>& rq) {
-  int64_t total = 0;
-  for (const auto& r : rq) total += r.rays;
-  if (total > slot.cap) {
-    if (slot.rays) GRTX_HIP(hipFree(slot.rays));
-    if (slot.rscene) GRTX_HIP(hipFree(slot.rscene));
-    if (slot.out) GRTX_HIP(hipFree(slot.out));
-    GRTX_HIP(hipMalloc(&slot.rays, sizeof(float) * 6 * total));
-    GRTX_HIP(hipMalloc(&slot.rscene, sizeof(int32_t) * total));
-    GRTX_HIP(hipMalloc(&slot.out, sizeof(float) * 5 * total));
-    slot.cap = total;
-  }
-  int64_t off = 0;
-  for (size_t i = 0; i < rq.size(); ++i) {
-    ReqDev& q = slot.table_host[i];
-    camera_basis(rq[i].r, q);
-    q.order = nullptr;
-    if (q.tiled) GRTX_TRY(centre_out_order(sv->device, q.width / 8, q.height / 8, &q.order));
-    q.ray_offset = off;
-    q.scene = rq[i].r.scene_id;
-    const int64_t n = rq[i].rays;
-    q.rgb = rq[i].out;
-    q.depth = rq[i].out + 3 * n;
-    q.opacity = rq[i].out + 4 * n;
-    off += n;
-  }
-  hipStream_t s = slot.stream;
-  const int nreq = (int)rq.size();
-  GRTX_HIP(hipMemcpyAsync(slot.table_dev, slot.table_host, sizeof(ReqDev) * nreq, hipMemcpyHostToDevice, s));
-  float* o = slot.rays;
-  float* d = slot.rays + 3 * total;
-  const unsigned grid = (unsigned)((total + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_batch_rays, dim3(grid), dim3(kBlock), 0, s, slot.table_dev, nreq, total, o, d, slot.rscene);
-  GRTX_LAUNCH_CHECK();
-  TraceScene sc{sv->nodes, sv->inst, nullptr, sv->sh, sv->sh_degree, sv->roots, slot.rscene,
-                GRTX_BVH_SPHERE_INSTANCE, sv->total_leaves};
-  grtx_rays rays{o, d, total, 0.f, 0};
-  grtx_trace_params p{};
-  p.k = sv->cfg.k;
-  p.T_min = sv->cfg.T_min;
-  p.mode = sv->cfg.mode;
-  for (int a = 0; a < 3; ++a) p.bg[a] = sv->cfg.bg[a];
-  p.defer_capacity = kServeDeferCap;  // what the slot pools were reserved for
-  p.evict_capacity = kServeEvictCap;
-  grtx_trace_outputs out{};
-  out.rgb = slot.out;
-  out.depth = slot.out + 3 * total;
-  out.opacity = slot.out + 4 * total;
-  SV_TRY(launch_trace(sc, &rays, &p, &out, s));
-  hipLaunchKernelGGL(k_batch_scatter, dim3(grid), dim3(kBlock), 0, s, slot.table_dev, nreq, total, out.rgb, out.depth,
-                     out.opacity);
-  GRTX_LAUNCH_CHECK();
-  GRTX_HIP(hipEventRecord(slot.done, s));
-  slot.rays_in_batch = total;
-  (void)batch;
-  return GRTX_OK;
-}
-
-void admit_locked(Server* sv) {
+// Admit and publish queued requests, first come, first served, while their outputs fit
+// the budget and the arena and the next ring slot is free (lock held). Returns the
+// arena growth the head of the queue waits for (0 if none).
+int64_t admit_locked(Server* sv) {
   while (!sv->queued.empty()) {
     auto it = sv->reqs.find(sv->queued.front());
     if (it == sv->reqs.end()) {  // released while queued
       sv->queued.pop_front();
       continue;
     }
-    auto& r = it->second;
-    if (sv->in_use + r.bytes > sv->available) break;  // first come, first served
-    void* q = nullptr;
-    if (hipMalloc(&q, sizeof(float) * 5 * r.rays) != hipSuccess) break;
-    r.out = static_cast<float*>(q);
+    Server::Req& r = it->second;
+    if (sv->in_use + r.bytes > sv->available) return 0;  // waits for releases
+    if (sv->slot_ticket[sv->published % kServeRing] != 0) return 0;  // ring slot still busy
+    int chunk = -1;
+    int64_t off = 0, span = 0;
+    if (!arena_place(sv, r.bytes, &chunk, &off, &span)) {
+      // a new chunk, if the budget still has room for one that holds the request
+      const int64_t room = sv->available - sv->arena_bytes;
+      const int64_t want = std::min(room, std::max(kArenaChunk, (r.bytes + kArenaAlign - 1) / kArenaAlign * kArenaAlign));
+      return want >= r.bytes ? want : 0;
+    }
+    r.chunk = chunk;
+    r.offset = off;
+    r.span = span;
+    r.out = reinterpret_cast<float*>(sv->chunks[chunk].base + off);
     sv->in_use += r.bytes;
-    r.state = 1;
-    r.t_admit = now_s() - sv->t0;
-    sv->admitted.push_back(sv->queued.front());
+    const uint64_t t = it->first;
     sv->queued.pop_front();
+    publish_locked(sv, t, r);
   }
+  return 0;
+}
+
+// Mark the in-flight requests failed (their launch failed or did not finish; lock held).
+void fail_in_flight_locked(Server* sv, const char* why) {
+  snprintf(sv->worker_error, sizeof sv->worker_error, "%s", why);
+  for (int slot : sv->in_flight) {
+    auto it = sv->reqs.find(sv->slot_ticket[slot]);
+    if (it != sv->reqs.end()) it->second.state = 4;
+    sv->slot_ticket[slot] = 0;
+  }
+  sv->in_flight.clear();
+  sv->cv.notify_all();
 }
 
 void worker_main(Server* sv) {
   (void)hipSetDevice(sv->device);
   while (!sv->stop.load()) {
     bool progressed = false;
-    // completions
-    for (auto& slot : sv->slots) {
-      if (!slot.busy) continue;
-      hipError_t q = hipEventQuery(slot.done);
-      if (q == hipErrorNotReady) continue;
+    // the launch ended: every flag it raised is in host memory by now
+    if (sv->kernel_running) {
+      const hipError_t q = hipEventQuery(sv->kernel_done);
+      if (q != hipErrorNotReady) {
+        sv->kernel_running = false;
+        progressed = true;
+        if (q != hipSuccess) {
+          std::lock_guard<std::mutex> g(sv->mu);
+          char msg[256];
+          snprintf(msg, sizeof msg, "serving kernel failed: %s", hipGetErrorString(q));
+          fail_in_flight_locked(sv, msg);
+        }
+      }
+    }
+    int64_t grow = 0;
+    {
       std::lock_guard<std::mutex> g(sv->mu);
+      // completions
       const double t = now_s() - sv->t0;
-      for (uint64_t tk : slot.tickets) {
-        auto it = sv->reqs.find(tk);
-        if (it == sv->reqs.end()) continue;
-        it->second.state = q == hipSuccess ? 3 : 4;
-        it->second.t_done = t;
-        if (q == hipSuccess) {
+      for (size_t i = 0; i < sv->in_flight.size();) {
+        const int slot = sv->in_flight[i];
+        if (__atomic_load_n(&sv->host->done[slot], __ATOMIC_ACQUIRE) == 0) {
+          ++i;
+          continue;
+        }
+        auto it = sv->reqs.find(sv->slot_ticket[slot]);
+        if (it != sv->reqs.end()) {
+          it->second.state = 3;
+          it->second.t_done = t;
           sv->latencies.push_back(t - it->second.t_submit);
           ++sv->completed;
           sv->rays_completed += it->second.rays;
         }
+        sv->last_done = t;
+        sv->slot_ticket[slot] = 0;
+        sv->in_flight[i] = sv->in_flight.back();
+        sv->in_flight.pop_back();
+        progressed = true;
       }
-      if (q != hipSuccess) snprintf(sv->worker_error, sizeof sv->worker_error, "batch failed: %s", hipGetErrorString(q));
-      sv->last_done = t;
-      slot.tickets.clear();
-      slot.busy = false;
-      progressed = true;
-      sv->cv.notify_all();
+      if (progressed) sv->cv.notify_all();
+      // admission and publication
+      const uint64_t before = sv->published;
+      grow = admit_locked(sv);
+      if (sv->published != before) progressed = true;
     }
-    // admission and launch
-    for (auto& slot : sv->slots) {
-      if (slot.busy) continue;
-      std::vector<uint64_t> batch;
-      std::vector<Server::Req> rq;
+    if (grow > 0) {
+      // a new arena chunk, allocated without the lock (no device synchronisation)
+      void* p = nullptr;
+      const hipError_t e = hipMalloc(&p, (size_t)grow);
+      std::lock_guard<std::mutex> g(sv->mu);
+      if (e == hipSuccess) {
+        Server::Chunk c;
+        c.base = static_cast<char*>(p);
+        c.size = grow;
+        c.free.emplace(0, grow);
+        sv->chunks.push_back(std::move(c));
+        sv->arena_bytes += grow;
+        progressed = true;
+      } else {
+        (void)hipGetLastError();
+        snprintf(sv->worker_error, sizeof sv->worker_error, "arena growth of %lld bytes failed", (long long)grow);
+      }
+    }
+    // (re)start the kernel while published work is unfinished
+    if (!sv->kernel_running) {
+      bool pending;
       {
         std::lock_guard<std::mutex> g(sv->mu);
-        admit_locked(sv);
-        int64_t rays = 0;
-        const double t_launch = now_s() - sv->t0;
-        while (!sv->admitted.empty() && (int)batch.size() < kMaxBatchRequests) {
-          auto& r = sv->reqs[sv->admitted.front()];
-          if (!batch.empty() && rays + r.rays > sv->cfg.max_batch_rays) break;
-          batch.push_back(sv->admitted.front());
-          sv->admitted.pop_front();
-          r.state = 2;
-          r.t_launch = t_launch;
-          rays += r.rays;
-          rq.push_back(r);
+        pending = !sv->in_flight.empty();
+      }
+      if (pending) {
+        ServeLaunch L{};
+        L.scene = TraceScene{sv->nodes, sv->inst, nullptr, sv->sh, sv->sh_degree, sv->roots, nullptr,
+                             GRTX_BVH_SPHERE_INSTANCE, sv->total_leaves};
+        L.k = sv->cfg.k;
+        L.T_min = sv->cfg.T_min;
+        L.mode = sv->cfg.mode;
+        for (int a = 0; a < 3; ++a) L.bg[a] = sv->cfg.bg[a];
+        L.host = sv->host_dev;
+        L.dev = sv->dev;
+        L.pool = sv->pool;
+        L.poll_ticks = sv->poll_ticks;
+        L.idle_ticks = sv->idle_ticks;
+        grtx_status st = launch_serve(L, sv->stream);
+        if (st == GRTX_OK && hipEventRecord(sv->kernel_done, sv->stream) != hipSuccess) st = GRTX_ERR_DEVICE;
+        if (st == GRTX_OK) {
+          sv->kernel_running = true;
+          ++sv->launches;
+        } else {
+          std::lock_guard<std::mutex> g(sv->mu);
+          char msg[256];
+          snprintf(msg, sizeof msg, "serving launch failed: %s", grtx_last_error());
+          fail_in_flight_locked(sv, msg);
         }
-        if (!batch.empty() && sv->first_launch < 0) sv->first_launch = rq.front().t_launch;
+        progressed = true;
       }
-      if (batch.empty()) break;
-      grtx_status st = launch_batch(sv, slot, batch, rq);
-      std::lock_guard<std::mutex> g(sv->mu);
-      if (st != GRTX_OK) {
-        snprintf(sv->worker_error, sizeof sv->worker_error, "launch failed: %s", grtx_last_error());
-        for (uint64_t tk : batch) sv->reqs[tk].state = 4;
-        sv->cv.notify_all();
-      } else {
-        slot.tickets = batch;
-        slot.busy = true;
-      }
-      progressed = true;
     }
     if (!progressed) {
       std::unique_lock<std::mutex> lk(sv->mu);
-      sv->cv.wait_for(lk, std::chrono::microseconds(50));
+      sv->cv.wait_for(lk, std::chrono::microseconds(sv->in_flight.empty() ? 200 : 20));
     }
   }
+  // stop: the kernel finishes the published work and leaves
+  __atomic_store_n(&sv->host->stop, 1u, __ATOMIC_RELEASE);
+  (void)hipStreamSynchronize(sv->stream);
 }
 
 }  // namespace
@@ -451,32 +448,52 @@ void worker_main(Server* sv) {
 grtx_status serve_create(const grtx_serve_config* cfg, Server** out) {
   auto* sv = new Server();
   sv->cfg = *cfg;
-  if (sv->cfg.slots <= 0) sv->cfg.slots = 2;
-  if (sv->cfg.max_batch_rays <= 0) sv->cfg.max_batch_rays = 1 << 23;
+  if (sv->cfg.max_request_rays <= 0) sv->cfg.max_request_rays = 1 << kServePixelBits;
+  if (sv->cfg.idle_exit_us <= 0) sv->cfg.idle_exit_us = kDefaultIdleMicros;
   sv->t0 = now_s();
   hipError_t e = hipGetDevice(&sv->device);
-  if (e != hipSuccess) {
-    set_error("grtx_serve_create: %s", hipGetErrorString(e));
+  int clock_khz = 0;
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, sv->device);
+  if (e != hipSuccess || clock_khz <= 0) {
+    set_error("grtx_serve_create: %s", e != hipSuccess ? hipGetErrorString(e) : "no wall clock rate");
     delete sv;
     return GRTX_ERR_DEVICE;
   }
-  // the checkpoint pool of each slot's trace launches counts against the budget
-  const int K = cfg->k <= 4 ? 4 : cfg->k <= 8 ? 8 : cfg->k <= 16 ? 16 : cfg->k <= 32 ? 32 : 64;
-  sv->pool_bytes_per_slot = trace_pool_bytes(K, kServeDeferCap, kServeEvictCap);
-  sv->available = cfg->memory_budget - sv->cfg.slots * sv->pool_bytes_per_slot;
-  if (sv->available <= 0) {
-    set_error("grtx_serve_create: budget %lld bytes is below the %d slots' checkpoint pools (%lld bytes each)",
-              (long long)cfg->memory_budget, sv->cfg.slots, (long long)sv->pool_bytes_per_slot);
+  sv->poll_ticks = std::max<uint64_t>(1, (uint64_t)clock_khz * kPollMicros / 1000);
+  sv->idle_ticks = std::max<uint64_t>(1, (uint64_t)clock_khz * (uint64_t)sv->cfg.idle_exit_us / 1000);
+  // the kernel's checkpoint pool and the queue count against the budget
+  const int64_t pool_bytes = serve_pool_bytes(cfg->k);
+  sv->fixed_bytes = pool_bytes + (int64_t)sizeof(ServeDev);
+  sv->available = cfg->memory_budget - sv->fixed_bytes;
+  if (pool_bytes <= 0 || sv->available <= 0) {
+    set_error("grtx_serve_create: budget %lld bytes is below the serving kernel's checkpoint pool (%lld bytes)",
+              (long long)cfg->memory_budget, (long long)pool_bytes);
     delete sv;
     return GRTX_ERR_CAPACITY;
   }
-  sv->slots.resize(sv->cfg.slots);
-  for (auto& slot : sv->slots) {
-    if (hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&slot.done, hipEventDisableTiming) != hipSuccess ||
-        hipMalloc(&slot.table_dev, sizeof(ReqDev) * kMaxBatchRequests) != hipSuccess ||
-        hipHostMalloc(&slot.table_host, sizeof(ReqDev) * kMaxBatchRequests, hipHostMallocDefault) != hipSuccess) {
-      set_error("grtx_serve_create: stream/buffer setup failed");
+  if (hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&sv->kernel_done, hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&sv->host), sizeof(ServeHost),
+                    hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
+      hipHostGetDevicePointer(reinterpret_cast<void**>(&sv->host_dev), sv->host, 0) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&sv->dev), sizeof(ServeDev)) != hipSuccess ||
+      hipMalloc(&sv->pool, (size_t)pool_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("grtx_serve_create: stream/queue setup failed");
+    serve_destroy(sv);
+    return GRTX_ERR_DEVICE;
+  }
+  std::memset(static_cast<void*>(sv->host), 0, sizeof(ServeHost));
+  {
+    // empty queue: nothing published, every claim counter naming no request and past any
+    // request's items
+    std::vector<ServeDev> init(1);
+    ServeDev& q = init[0];
+    std::memset(static_cast<void*>(&q), 0, sizeof(ServeDev));
+    for (auto& sl : q.slot) sl.claim = ((uint64_t)kServeNoRequest << 32) | 0x80000000u;
+    if (hipMemcpy(sv->dev, &q, sizeof(ServeDev), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("grtx_serve_create: queue setup failed");
       serve_destroy(sv);
       return GRTX_ERR_DEVICE;
     }
@@ -515,6 +532,20 @@ grtx_status serve_add_scene(Server* sv, const Bvh* b, int32_t* scene_id) {
 }
 
 grtx_status serve_submit(Server* sv, const grtx_request* r, uint64_t* ticket) {
+  CameraFrame cf;
+  if (!camera_frame(r->eye, r->target, r->up, r->fov_y_deg, r->width, r->height, &cf)) {
+    set_error("grtx_serve_submit: degenerate eye/target/up");
+    return GRTX_ERR_INVALID_ARG;
+  }
+  const int64_t rays = (int64_t)r->width * r->height;
+  if (rays > sv->cfg.max_request_rays) {
+    set_error("grtx_serve_submit: request of %lld rays; the server takes at most %d", (long long)rays,
+              sv->cfg.max_request_rays);
+    return GRTX_ERR_CAPACITY;
+  }
+  // the tile order of this image size (made once per size, outside the server's lock)
+  const uint32_t* order = nullptr;
+  SV_TRY(centre_out_order(sv->device, (r->width + 7) / 8, (r->height + 7) / 8, &order));
   std::lock_guard<std::mutex> g(sv->mu);
   if (r->scene_id < 0 || r->scene_id >= (int32_t)sv->scenes.size()) {
     set_error("grtx_serve_submit: unknown scene %d", r->scene_id);
@@ -523,11 +554,12 @@ grtx_status serve_submit(Server* sv, const grtx_request* r, uint64_t* ticket) {
   if (!sv->frozen) SV_TRY(freeze(sv));
   Server::Req q;
   q.r = *r;
-  q.rays = (int64_t)r->width * r->height;
+  q.rays = rays;
   q.bytes = request_bytes(r);
-  if (q.bytes > sv->available || q.rays > sv->cfg.max_batch_rays) {
-    set_error("grtx_serve_submit: request needs %lld bytes / %lld rays; the server holds %lld bytes / %lld rays",
-              (long long)q.bytes, (long long)q.rays, (long long)sv->available, (long long)sv->cfg.max_batch_rays);
+  q.order = order;
+  if (q.bytes > sv->available) {
+    set_error("grtx_serve_submit: request needs %lld bytes; the server holds %lld bytes for outputs",
+              (long long)q.bytes, (long long)sv->available);
     return GRTX_ERR_CAPACITY;
   }
   q.t_submit = now_s() - sv->t0;
@@ -574,19 +606,20 @@ grtx_status serve_release(Server* sv, uint64_t ticket) {
     set_error("grtx_serve_release: unknown ticket %llu", (unsigned long long)ticket);
     return GRTX_ERR_INVALID_ARG;
   }
-  if (it->second.state == 1 || it->second.state == 2) {
+  Server::Req& q = it->second;
+  if (q.state == 1) {
     set_error("grtx_serve_release: request %llu is still in flight", (unsigned long long)ticket);
     return GRTX_ERR_NOT_READY;
   }
-  if (it->second.state == 0) {
-    // withdrawn before admission: it leaves the queue and is never launched or counted
-    auto q = std::find(sv->queued.begin(), sv->queued.end(), ticket);
-    if (q != sv->queued.end()) sv->queued.erase(q);
+  if (q.state == 0) {
+    // withdrawn before admission: it leaves the queue and is never published or counted
+    auto p = std::find(sv->queued.begin(), sv->queued.end(), ticket);
+    if (p != sv->queued.end()) sv->queued.erase(p);
     --sv->submitted;
   }
-  if (it->second.out) {
-    GRTX_HIP(hipFree(it->second.out));
-    sv->in_use -= it->second.bytes;
+  if (q.chunk >= 0) {
+    arena_free(sv, q.chunk, q.offset, q.span);
+    sv->in_use -= q.bytes;
   }
   sv->reqs.erase(it);
   sv->cv.notify_all();
@@ -601,6 +634,8 @@ grtx_status serve_stats(Server* sv, grtx_serve_stats* st) {
   s.rays_completed = sv->rays_completed;
   s.bytes_in_use = sv->in_use;
   s.bytes_available = sv->available;
+  s.bytes_arena = sv->arena_bytes;
+  s.launches = sv->launches;
   std::vector<double> l = sv->latencies;
   if (!l.empty()) {
     std::sort(l.begin(), l.end());
@@ -629,19 +664,16 @@ grtx_status serve_destroy(Server* sv) {
     sv->stop.store(true);
     sv->cv.notify_all();
     sv->worker.join();
+  } else if (sv->host) {
+    __atomic_store_n(&sv->host->stop, 1u, __ATOMIC_RELEASE);
   }
-  for (auto& slot : sv->slots) {
-    if (slot.stream) (void)hipStreamSynchronize(slot.stream);
-    if (slot.rays) (void)hipFree(slot.rays);
-    if (slot.rscene) (void)hipFree(slot.rscene);
-    if (slot.out) (void)hipFree(slot.out);
-    if (slot.table_dev) (void)hipFree(slot.table_dev);
-    if (slot.table_host) (void)hipHostFree(slot.table_host);
-    if (slot.done) (void)hipEventDestroy(slot.done);
-    if (slot.stream) (void)hipStreamDestroy(slot.stream);
-  }
-  for (auto& kv : sv->reqs)
-    if (kv.second.out) (void)hipFree(kv.second.out);
+  if (sv->stream) (void)hipStreamSynchronize(sv->stream);
+  for (auto& c : sv->chunks) (void)hipFree(c.base);
+  if (sv->pool) (void)hipFree(sv->pool);
+  if (sv->dev) (void)hipFree(sv->dev);
+  if (sv->host) (void)hipHostFree(sv->host);
+  if (sv->kernel_done) (void)hipEventDestroy(sv->kernel_done);
+  if (sv->stream) (void)hipStreamDestroy(sv->stream);
   for (void* p : sv->scene_allocs) (void)hipFree(p);
   delete sv;
   return GRTX_OK;

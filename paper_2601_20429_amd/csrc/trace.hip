@@ -40,6 +40,7 @@
 #include <tuple>
 #include <vector>
 
+#include "camera.h"
 #include "grtx_internal.h"
 #include "trace_common.h"
 
@@ -124,6 +125,10 @@ struct TraceArgs {
   unsigned int* counter;  // kChunks work counters
   int64_t chunk_len;      // work items per chunk (a multiple of 64)
   const uint32_t* tile_order;  // processing order of the 8x8 tiles, or null (row-major)
+  ServeHost* sv_host;          // serving kernel: the work queue (host and device sides)
+  ServeDev* sv_dev;
+  uint64_t sv_poll_ticks;      // wall-clock ticks between reads of the host's count
+  uint64_t sv_idle_ticks;      // wall-clock ticks without work before the launch winds down
 };
 
 template <int K>
@@ -216,6 +221,146 @@ __device__ __forceinline__ bool ico_entry(float4 r0, float4 r1, float4 r2, float
   return !outside_parallel && te <= tx;
 }
 
+// ------------------------------------------------------------------ serving work queue
+// Host memory is read with system-scope loads (they bypass the GPU's caches); the
+// device-side queue with device-scope atomics, so that all XCDs see one value; served
+// outputs are written with device-scope stores, which write through the XCD's L2.
+__device__ __forceinline__ uint32_t ld_sys(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint64_t ld_sys64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint32_t ld_dev(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_dev64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Device wall clock (constant rate, hipDeviceAttributeWallClockRate kHz).
+__device__ __forceinline__ uint64_t wall_clock() { return __builtin_amdgcn_s_memrealtime(); }
+// Wait until this wave's earlier memory writes are complete.
+__device__ __forceinline__ void wait_writes() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+__device__ __forceinline__ void st_dev_u32(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t state_cur(uint64_t st) { return (uint32_t)st; }
+__device__ __forceinline__ uint32_t state_pub(uint64_t st) { return (uint32_t)(st >> 32) & 0x7FFFFFFFu; }
+typedef unsigned long long ull;
+
+// Descriptors the poller sets up per read of the host's count (bounds one lane's work).
+constexpr int kServePollBatch = 64;
+
+// Set up the requests the host has published since the last read: copy their
+// descriptors into the device ring, start their claim counters, then raise the published
+// count in the state word. One lane at a time (poll_lock), at most once per poll_ticks
+// over the launch. A stop from the host closes the queue once everything published has
+// been handed out.
+__device__ __forceinline__ void serve_poll(ServeDev* q, const ServeHost* h, uint64_t poll_ticks) {
+  const uint64_t now = wall_clock();
+  if (now - ld_dev64(&q->last_poll) < poll_ticks) return;  // (a clock behind wraps: poll)
+  if (atomicCAS(&q->poll_lock, 0u, 1u) != 0u) return;
+  atomicExch(reinterpret_cast<ull*>(&q->last_poll), (ull)now);
+  const uint64_t hp = ld_sys64(&h->published);
+  const uint32_t stop = ld_sys(&h->stop);
+  const uint64_t inited = ld_dev64(&q->inited);
+  const uint64_t upto = hp < inited + kServePollBatch ? hp : inited + kServePollBatch;
+  for (uint64_t j = inited; j < upto; ++j) {
+    const uint32_t slot = (uint32_t)(j % kServeRing);
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&h->ring[slot]);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&q->desc[slot]);
+    uint32_t v[sizeof(ServeDesc) / 4];
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(ServeDesc) / 4); ++i) v[i] = ld_sys(src + i);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(ServeDesc) / 4); ++i) st_dev_u32(dst + i, v[i]);
+    wait_writes();  // the descriptor is in place before its counter names the request
+    atomicExch(reinterpret_cast<ull*>(&q->slot[slot].claim), (ull)(j << 32));
+  }
+  if (upto > inited) atomicExch(reinterpret_cast<ull*>(&q->inited), (ull)upto);
+  // the state word also changes when the current request moves on or the queue closes;
+  // each failed swap means one of those happened
+  uint64_t st = ld_dev64(&q->state);
+  for (int a = 0; a < 1024 && state_pub(st) < (uint32_t)upto; ++a) {
+    const uint64_t nst = (st & (kServeClosing | 0xFFFFFFFFull)) | ((uint64_t)((uint32_t)upto & 0x7FFFFFFFu) << 32);
+    const uint64_t seen = atomicCAS(reinterpret_cast<ull*>(&q->state), (ull)st, (ull)nst);
+    if (seen == st) {
+      st = nst;
+      break;
+    }
+    st = seen;
+  }
+  if (stop && upto == hp && state_cur(st) >= state_pub(st)) atomicOr(reinterpret_cast<ull*>(&q->state), (ull)kServeClosing);
+  atomicExch(&q->poll_lock, 0u);
+}
+
+// One lane claims up to `cnt` work items for its wave. Fast path: one atomic add on the
+// claim counter of the wave's current request (*myj, in LDS); a counter that names a
+// later request (the slot was reused) hands out that request's items, which are just as
+// much unclaimed. When the request has no items left, the state word moves past it (if
+// it still names it) and the request it names next becomes the wave's. Returns the
+// number of items claimed (0: none now; *closed is set when the queue is closing);
+// *j_out / *o_out receive their request and first item, and the wave's descriptor copy
+// `wd` (LDS) then holds that request.
+__device__ __forceinline__ uint32_t serve_claim(ServeDev* q, const ServeHost* h, uint32_t cnt, uint64_t poll_ticks,
+                                                uint32_t* myj, ServeDesc* wd, uint32_t* j_out, uint32_t* o_out,
+                                                uint32_t* closed) {
+  *closed = 0;
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    const uint32_t jj = *myj;
+    if (jj != kServeNoRequest) {
+      const uint64_t old = atomicAdd(reinterpret_cast<ull*>(&q->slot[jj % kServeRing].claim), (ull)cnt);
+      const uint32_t seq = (uint32_t)(old >> 32), o = (uint32_t)old;
+      if ((int32_t)(seq - jj) >= 0) {
+        if (wd->seq != seq) {
+          const uint32_t* src = reinterpret_cast<const uint32_t*>(&q->desc[seq % kServeRing]);
+          uint32_t v[sizeof(ServeDesc) / 4];
+#pragma unroll
+          for (int i = 0; i < (int)(sizeof(ServeDesc) / 4); ++i) v[i] = ld_dev(src + i);
+          uint32_t* dst = reinterpret_cast<uint32_t*>(wd);
+#pragma unroll
+          for (int i = 0; i < (int)(sizeof(ServeDesc) / 4); ++i) dst[i] = v[i];
+        }
+        const uint32_t n = wd->seq == seq ? wd->n_work : 0u;
+        if (o < n) {
+          *myj = seq;
+          *j_out = seq;
+          *o_out = o;
+          return cnt < n - o ? cnt : n - o;
+        }
+        uint64_t st = ld_dev64(&q->state);
+        for (int a = 0; a < 4 && state_cur(st) == seq; ++a) {
+          const uint64_t seen = atomicCAS(reinterpret_cast<ull*>(&q->state), (ull)st,
+                                          (ull)((st & ~0xFFFFFFFFull) | (uint32_t)(seq + 1)));
+          if (seen == st) break;
+          st = seen;
+        }
+      }
+      *myj = kServeNoRequest;
+    }
+    uint64_t st = ld_dev64(&q->state);
+    if (st & kServeClosing) {
+      *closed = 1;
+      return 0;
+    }
+    if (state_cur(st) >= state_pub(st)) {
+      serve_poll(q, h, poll_ticks);
+      st = ld_dev64(&q->state);
+      if (st & kServeClosing) {
+        *closed = 1;
+        return 0;
+      }
+      if (state_cur(st) >= state_pub(st)) return 0;
+    }
+    *myj = state_cur(st);
+  }
+  return 0;
+}
+
 // The kernel's arguments, read again from the argument segment (scalar loads) at each use
 // site inside the ray loop: the empty asm statement hides that the pointer is the same every
 // time, so the compiler does not hold every field in scalar registers for the whole kernel
@@ -228,12 +373,21 @@ __device__ __forceinline__ KernArgs& kernel_args() {
   return *p;
 }
 
-template <int K, int LEAF, bool STATS>
+// SERVE: the serving kernel. Work comes from the serving queue instead of the ray arrays:
+// each ray is generated from its request's camera, its outputs go to the request's
+// buffers, and the lane that completes a request raises its flag in host memory. Idle
+// waves wait for new requests and leave once the queue closes.
+template <int K, int LEAF, bool STATS, bool SERVE = false>
 __global__ void __launch_bounds__(kTraceBlock)
     __attribute__((amdgpu_waves_per_eu(K <= 32 ? GRTX_MIN_WAVES : 1, 8))) k_trace(TraceArgs Args) {
   __shared__ uint2 s_stack[kLdsStack * kTraceBlock];
   __shared__ uint2 s_dst[kStage * kTraceBlock];  // destination node-list entries not yet written out
   __shared__ uint32_t s_stat[STATS ? GRTX_STATS_FIELDS : 1][kTraceBlock];  // per-lane counters
+  // serving: each wave's copy of its current request, each lane's output address and its
+  // request's pixel count
+  __shared__ ServeDesc s_desc[SERVE ? kWaves : 1];
+  __shared__ uint32_t s_myj[SERVE ? kWaves : 1];
+  __shared__ uint32_t s_out[SERVE ? 3 : 1][SERVE ? kTraceBlock : 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -282,6 +436,14 @@ __global__ void __launch_bounds__(kTraceBlock)
   bool exhausted = false;
   int chunk = (int)(blockIdx.x % kChunks);
   int chunks_tried = 0;
+  bool nowork = false;       // serving: the last claim found no work
+  uint64_t idle_since = 0;   // serving: when the wave last ran out of rays (lane 0)
+  if constexpr (SERVE) {
+    if (lane == 0) {
+      s_desc[tid >> 6].seq = ~0u;
+      s_myj[tid >> 6] = kServeNoRequest;
+    }
+  }
 
   auto root_start = [&]() __attribute__((always_inline)) {
     // (Re)start at the root; subtrees that end before tmin are culled.
@@ -360,11 +522,88 @@ __global__ void __launch_bounds__(kTraceBlock)
   while (true) {
     KernArgs& A = kernel_args();
     // ---------------------------------------------------------------- refill idle lanes
-    // The work items are split into kChunks contiguous chunks, each with its own counter
-    // (one chunk by default). With several, a wave starts on chunk blockIdx % kChunks
-    // (workgroups are dealt round-robin to the 8 XCDs) and moves on to the next chunk when
-    // its own is drained.
-    if (!exhausted) {
+    // Serving: one lane claims work items of one request for the wave's idle lanes
+    // (serve_claim), which generate their rays from the request's camera.
+    // Otherwise the work items are split into kChunks contiguous chunks, each with its own
+    // counter (one chunk by default). With several, a wave starts on chunk
+    // blockIdx % kChunks (workgroups are dealt round-robin to the 8 XCDs) and moves on to
+    // the next chunk when its own is drained.
+    if constexpr (SERVE) {
+      const uint64_t idle = __ballot(state == kIdle);
+      if (idle && !exhausted) {
+        const int leader = __ffsll((unsigned long long)idle) - 1;
+        uint32_t take = 0, j = 0, o = 0, closed = 0;
+        if (lane == leader)
+          take = serve_claim(A.sv_dev, A.sv_host, (uint32_t)__popcll(idle), A.sv_poll_ticks, &s_myj[tid >> 6],
+                             &s_desc[tid >> 6], &j, &o, &closed);
+        take = __shfl(take, leader);
+        j = __shfl(j, leader);
+        o = __shfl(o, leader);
+        closed = __shfl(closed, leader);
+        nowork = take == 0;
+        if (closed) exhausted = true;
+        const uint32_t rank = (uint32_t)__popcll(idle & lt_mask);
+        if (state == kIdle && rank < take) {
+          const ServeDesc& d = s_desc[tid >> 6];
+          const uint32_t w = o + rank;
+          const uint32_t* order = reinterpret_cast<const uint32_t*>(d.order);
+          const uint32_t tile = order ? order[w >> 6] : w >> 6;
+          const uint32_t ty = tile / (uint32_t)d.tiles_x, tx = tile - ty * (uint32_t)d.tiles_x;
+          const int px = (int)(tx * 8 + (w & 7)), py = (int)(ty * 8 + ((w >> 3) & 7));
+          if (px < d.width && py < d.height) {
+            const uint32_t pix = (uint32_t)py * (uint32_t)d.width + (uint32_t)px;
+            ray = (int)(((j % kServeRing) << kServePixelBits) | pix);
+            s_out[0][tid] = (uint32_t)d.out;
+            s_out[1][tid] = (uint32_t)(d.out >> 32);
+            s_out[2][tid] = d.n_pixels;
+            sid = d.scene;
+            ox = d.eye[0]; oy = d.eye[1]; oz = d.eye[2];
+            pinhole_dir(d.fwd[0], d.fwd[1], d.fwd[2], d.right[0], d.right[1], d.right[2], d.up[0], d.up[1], d.up[2], px,
+                        py, d.width, d.height, &dx, &dy, &dz);
+            ix = safe_inv(dx); iy = safe_inv(dy); iz = safe_inv(dz);
+            oix = ox * ix; oiy = oy * iy; oiz = oz * iz;
+            tfar = INFINITY;
+            kbuf_reset(kb, A.k);
+            tmin = 0;
+            C0 = C1 = C2 = Dp = 0.f;
+            T = 1.f;
+            nblend = 0;
+            par = 0;
+            nsrc_n = nsrc_i = ndst_n = 0;
+            esrc_n = esrc_i = edst_n = 0;
+            overflow = false;
+            have_key = false;
+            root_start();
+            state = kTrav;
+          }
+        }
+      }
+      if (__ballot(state != kIdle) == 0) {
+        if (exhausted) break;
+        if (nowork) {
+          // nothing to trace: wait for new requests (checking about every 14 us at first,
+          // every 110 us after 100 us), and once this wave has found no work for
+          // idle_ticks, close the queue: every wave leaves when its rays are done, and the
+          // host starts a new launch for later requests
+          uint32_t quit = 0, naps = 4;
+          if (lane == 0) {
+            const uint64_t now = wall_clock();
+            if (idle_since == 0) idle_since = now;
+            if (now - idle_since > A.sv_idle_ticks) {
+              atomicOr(reinterpret_cast<ull*>(&A.sv_dev->state), (ull)kServeClosing);
+              quit = 1;
+            }
+            if (now - idle_since > 25 * A.sv_poll_ticks) naps = 32;
+          }
+          if (__shfl(quit, 0)) break;
+          naps = __shfl(naps, 0);
+#pragma unroll 1
+          for (uint32_t z = 0; z < naps; ++z) __builtin_amdgcn_s_sleep(127);
+          continue;
+        }
+      }
+      idle_since = 0;
+    } else if (!exhausted) {
       uint64_t idle = __ballot(state == kIdle);
       if (idle) {
         int cnt = __popcll(idle);
@@ -427,8 +666,10 @@ __global__ void __launch_bounds__(kTraceBlock)
         }
       }
     }
-    if (__ballot(state != kIdle) == 0) {
-      if (exhausted) break;
+    if constexpr (!SERVE) {
+      if (__ballot(state != kIdle) == 0) {
+        if (exhausted) break;
+      }
     }
 
     // ---------------------------------------------------------------- traversal
@@ -441,7 +682,7 @@ __global__ void __launch_bounds__(kTraceBlock)
     while (true) {
       const uint64_t trav = __ballot(state == kTrav);
       if (!trav) break;
-      const uint64_t waiting = __ballot(state == kEnd) | (exhausted ? 0ull : __ballot(state == kIdle));
+      const uint64_t waiting = __ballot(state == kEnd) | (exhausted || nowork ? 0ull : __ballot(state == kIdle));
       if (__popcll(waiting) >= kRefillThreshold) break;
       const uint64_t tmax = kb[K - 1];
       const float tmax_t = key_t(tmax);
@@ -709,6 +950,36 @@ __global__ void __launch_bounds__(kTraceBlock)
         overflow = false;
         root_start();
         state = kTrav;
+      } else if (done && SERVE) {
+        // served ray: outputs to the request's buffers, written through to device scope;
+        // then one count per request among the lanes finishing here, and the lane whose
+        // count completes a request resets its counter and raises its flag in host memory
+        const uint32_t slot = (uint32_t)ray >> kServePixelBits;
+        const uint32_t pix = (uint32_t)ray & ((1u << kServePixelBits) - 1u);
+        float* out = reinterpret_cast<float*>(((uint64_t)s_out[1][tid] << 32) | s_out[0][tid]);
+        const uint32_t n = s_out[2][tid];
+        st_dev(out + 3 * (int64_t)pix + 0, C0 + T * A.bg0);
+        st_dev(out + 3 * (int64_t)pix + 1, C1 + T * A.bg1);
+        st_dev(out + 3 * (int64_t)pix + 2, C2 + T * A.bg2);
+        st_dev(out + 3 * (int64_t)n + pix, Dp);
+        st_dev(out + 4 * (int64_t)n + pix, 1.f - T);
+        wait_writes();
+        uint64_t fin = __ballot(true);
+        while (fin) {
+          const int l0 = __ffsll((unsigned long long)fin) - 1;
+          const uint32_t s0 = __shfl(slot, l0);
+          const uint64_t same = __ballot(slot == s0);
+          if (lane == l0) {
+            const uint32_t c = (uint32_t)__popcll(same);
+            if (atomicAdd(&A.sv_dev->slot[s0].done, c) + c == n) {
+              atomicExch(&A.sv_dev->slot[s0].done, 0u);
+              wait_writes();
+              __hip_atomic_store(&A.sv_host->done[s0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+          }
+          fin &= ~same;
+        }
+        state = kIdle;
       } else if (done) {
         // the background shows only through rays that no surface ends
         const float bgT = tfar == INFINITY ? T : 0.f;
@@ -926,7 +1197,87 @@ grtx_status launch_k(int K, const TraceArgs& a, int blocks, hipStream_t s) {
   }
 }
 
+// The serving kernel leaves this many CUs' worth of workgroup slots free, so that other
+// work on the device (copies of results, other streams' kernels) is not shut out while it
+// runs.
+constexpr int kServeSpareCUs = 8;
+
+template <int K>
+int serve_blocks_per_cu() {
+  int nb = 0;
+  const hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<K, kLeafSphere, false, true>, kTraceBlock, 0);
+  return e == hipSuccess ? std::max(1, nb) : 1;
+}
+
+inline int serve_k(int k) { return k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64; }
+
+int serve_blocks(int K) {
+  int device = 0, cus = 0;
+  if (hipGetDevice(&device) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+  const int bpc = K == 4 ? serve_blocks_per_cu<4>() : K == 8 ? serve_blocks_per_cu<8>()
+                : K == 16 ? serve_blocks_per_cu<16>() : K == 32 ? serve_blocks_per_cu<32>() : serve_blocks_per_cu<64>();
+  return std::max(1, cus - kServeSpareCUs) * bpc;
+}
+
+inline int64_t serve_rows(int K) {
+  return kSpillRows + 2 * (int64_t)stage_round(kServeDeferCap) + 2 * (int64_t)stage_round(kServeEvictCap) + K;
+}
+
 }  // namespace
+
+int64_t serve_pool_bytes(int k) {
+  const int K = serve_k(k);
+  return (int64_t)serve_blocks(K) * kWaves * serve_rows(K) * 64 * (int64_t)sizeof(uint2);
+}
+
+namespace {
+// Reopen the queue for a new launch (stream-ordered after the previous one).
+__global__ void k_serve_reopen(ServeDev* q) {
+  if (threadIdx.x == 0) atomicAnd(reinterpret_cast<unsigned long long*>(&q->state), ~(unsigned long long)kServeClosing);
+}
+}  // namespace
+
+grtx_status launch_serve(const ServeLaunch& L, hipStream_t s) {
+  const int K = serve_k(L.k);
+  const int blocks = serve_blocks(K);
+  if (blocks <= 0) {
+    set_error("serving: no device");
+    return GRTX_ERR_DEVICE;
+  }
+  TraceArgs a{};
+  a.nodes = L.scene.nodes;
+  a.inst = L.scene.inst;
+  a.sh = L.scene.sh;
+  a.roots = L.scene.roots;
+  a.sh_degree = L.scene.sh_degree;
+  a.t_near = 0.f;
+  a.k = L.k;
+  a.T_min = L.T_min;
+  a.mode = L.mode;
+  a.bg0 = L.bg[0];
+  a.bg1 = L.bg[1];
+  a.bg2 = L.bg[2];
+  a.pool = static_cast<uint2*>(L.pool);
+  a.rows_per_wave = serve_rows(K);
+  a.cap_d = stage_round(kServeDeferCap);
+  a.cap_e = stage_round(kServeEvictCap);
+  a.sv_host = L.host;
+  a.sv_dev = L.dev;
+  a.sv_poll_ticks = L.poll_ticks;
+  a.sv_idle_ticks = L.idle_ticks;
+  hipLaunchKernelGGL(k_serve_reopen, dim3(1), dim3(64), 0, s, L.dev);
+  switch (K) {
+    case 4: hipLaunchKernelGGL((k_trace<4, kLeafSphere, false, true>), dim3(blocks), dim3(kTraceBlock), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_trace<8, kLeafSphere, false, true>), dim3(blocks), dim3(kTraceBlock), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_trace<16, kLeafSphere, false, true>), dim3(blocks), dim3(kTraceBlock), 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_trace<32, kLeafSphere, false, true>), dim3(blocks), dim3(kTraceBlock), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_trace<64, kLeafSphere, false, true>), dim3(blocks), dim3(kTraceBlock), 0, s, a); break;
+  }
+  GRTX_LAUNCH_CHECK();
+  return GRTX_OK;
+}
 
 // Centre-out tile order of an image: rings of tiles by distance from the image centre,
 // each ring by angle. Rays near the centre of an object-centred view cross the most

@@ -95,8 +95,8 @@ class _Camera(C.Structure):
 
 
 class _ServeConfig(C.Structure):
-    _fields_ = [("memory_budget", C.c_int64), ("slots", C.c_int32), ("k", C.c_int32), ("T_min", C.c_float),
-                ("mode", C.c_int32), ("max_batch_rays", C.c_int32), ("bg", C.c_float * 3)]
+    _fields_ = [("memory_budget", C.c_int64), ("k", C.c_int32), ("T_min", C.c_float), ("mode", C.c_int32),
+                ("max_request_rays", C.c_int32), ("bg", C.c_float * 3), ("idle_exit_us", C.c_int32)]
 
 
 class _Request(C.Structure):
@@ -112,7 +112,8 @@ class _RequestResult(C.Structure):
 
 class _ServeStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rays_completed", C.c_int64),
-                ("bytes_in_use", C.c_int64), ("bytes_available", C.c_int64), ("p50_ms", C.c_double),
+                ("bytes_in_use", C.c_int64), ("bytes_available", C.c_int64), ("bytes_arena", C.c_int64),
+                ("launches", C.c_int64), ("p50_ms", C.c_double),
                 ("p99_ms", C.c_double), ("mean_ms", C.c_double), ("max_ms", C.c_double), ("busy_s", C.c_double),
                 ("mrays_per_s", C.c_double)]
 
@@ -464,11 +465,12 @@ def request_bytes(camera):
 
 
 class Server:
-    """Continuous-batching render server (grtx_serve_*)."""
+    """Render server: one persistent trace kernel fed from a request queue (grtx_serve_*)."""
 
-    def __init__(self, memory_budget, slots=2, k=16, T_min=1e-3, mode=CHECKPOINT, max_batch_rays=0,
-                 bg=(0.0, 0.0, 0.0)):
-        cfg = _ServeConfig(int(memory_budget), slots, k, T_min, mode, max_batch_rays, (C.c_float * 3)(*bg))
+    def __init__(self, memory_budget, k=16, T_min=1e-3, mode=CHECKPOINT, max_request_rays=0, bg=(0.0, 0.0, 0.0),
+                 idle_exit_us=0):
+        cfg = _ServeConfig(int(memory_budget), k, T_min, mode, max_request_rays, (C.c_float * 3)(*bg),
+                           int(idle_exit_us))
         h = C.c_void_p()
         _check(lib().grtx_serve_create(C.byref(cfg), C.byref(h)))
         self.handle = h

@@ -29,7 +29,7 @@ def test_header_symbols_exported():
 
 def test_version_and_null_destroy():
     L = grtx.lib()
-    assert L.grtx_version() == 3
+    assert L.grtx_version() == 4
     assert L.grtx_bvh_destroy(None) == grtx.OK
 
 
@@ -113,19 +113,22 @@ def test_binding_raises_on_error():
 
 
 def test_serving_request_bytes_and_validation():
-    """Admission accounting is host-only: a request holds its rays (24 B origin and
-    direction + 4 B scene index), batch outputs (20 B) and its own outputs (20 B) per
-    pixel. Bad server configurations are refused before any device call."""
+    """Admission accounting is host-only: a request holds its outputs (rgb, depth and
+    opacity, 20 B per pixel; its rays are generated inside the serving kernel). Bad server
+    configurations are refused before any device call."""
     from paper_2601_20429_amd import inputs
     cam = inputs.orbit_camera(800, 600)
-    assert grtx.request_bytes(cam) == 800 * 600 * 68
+    assert grtx.request_bytes(cam) == 800 * 600 * 20
     L = grtx.lib()
     h = C.c_void_p()
-    for cfg in [grtx._ServeConfig(0, 2, 16, 1e-3, 0, 0, (C.c_float * 3)()),
-                grtx._ServeConfig(1 << 30, 2, 0, 1e-3, 0, 0, (C.c_float * 3)()),
-                grtx._ServeConfig(1 << 30, 2, 16, 1.0, 0, 0, (C.c_float * 3)()),
-                grtx._ServeConfig(1 << 30, 99, 16, 1e-3, 0, 0, (C.c_float * 3)()),
-                grtx._ServeConfig(1 << 30, 2, 16, 1e-3, 5, 0, (C.c_float * 3)())]:
+    bg = (C.c_float * 3)()
+    for cfg in [grtx._ServeConfig(0, 16, 1e-3, 0, 0, bg, 0),               # no budget
+                grtx._ServeConfig(1 << 30, 0, 1e-3, 0, 0, bg, 0),          # k = 0
+                grtx._ServeConfig(1 << 30, 16, 1.0, 0, 0, bg, 0),          # T_min = 1
+                grtx._ServeConfig(1 << 30, 16, 1e-3, 5, 0, bg, 0),         # unknown mode
+                grtx._ServeConfig(1 << 30, 16, 1e-3, 0, (1 << 22) + 1, bg, 0),  # requests beyond 2^22 pixels
+                grtx._ServeConfig(1 << 30, 16, 1e-3, 0, -1, bg, 0),
+                grtx._ServeConfig(1 << 30, 16, 1e-3, 0, 0, bg, -5)]:       # negative idle time
         assert L.grtx_serve_create(C.byref(cfg), C.byref(h)) == grtx.ERR_INVALID_ARG
     assert h.value is None
     assert L.grtx_serve_destroy(None) == grtx.OK
