@@ -683,6 +683,11 @@ def main():
                     help="only the backward-pass timing, printed as its JSON object (for profiler runs)")
     ap.add_argument("--serving-only", action="store_true",
                     help="only the serving runs, printed as one JSON object (for profiler runs)")
+    ap.add_argument("--frame100k-only", action="store_true",
+                    help="only the 100k-Gaussian frame in checkpoint and restart mode, printed as its JSON "
+                         "object (for profiler runs)")
+    ap.add_argument("--with-secondary", action="store_true",
+                    help="with --frame100k-only: also the secondary-ray workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); sharding the rays over "
@@ -711,6 +716,11 @@ def main():
 
     if args.backward_only:
         print(json.dumps(run_backward(stream)), flush=True)
+        return
+    if args.frame100k_only:
+        args.no_compare = args.no_proxy = args.no_ksweep = True
+        args.no_secondary = not args.with_secondary
+        print(json.dumps(run_frame100k(args, stream)), flush=True)
         return
     if args.serving_only:
         summary, cap, runs, swept = run_serving(args.serve_requests, (inputs.SERVE["rate"], args.serve_low_rate))

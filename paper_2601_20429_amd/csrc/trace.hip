@@ -63,6 +63,12 @@ constexpr int kRefillThreshold = GRTX_REFILL_THRESHOLD;  // idle lanes that end 
 #define GRTX_STAGE 8
 #endif
 constexpr int kStage = GRTX_STAGE;
+// Eviction-list appends gathered the same way, kStageE entries at a time (0: written one
+// by one); kStageE divides kStage.
+#ifndef GRTX_EVICT_STAGE
+#define GRTX_EVICT_STAGE 0
+#endif
+constexpr int kStageE = GRTX_EVICT_STAGE;
 #ifndef GRTX_CHUNKS
 #define GRTX_CHUNKS 1
 #endif
@@ -382,6 +388,7 @@ __global__ void __launch_bounds__(kTraceBlock)
     __attribute__((amdgpu_waves_per_eu(K <= 32 ? GRTX_MIN_WAVES : 1, 8))) k_trace(TraceArgs Args) {
   __shared__ uint2 s_stack[kLdsStack * kTraceBlock];
   __shared__ uint2 s_dst[kStage * kTraceBlock];  // destination node-list entries not yet written out
+  __shared__ uint2 s_edst[kStageE > 0 ? kStageE * kTraceBlock : 1];  // eviction-list entries likewise
   __shared__ uint32_t s_stat[STATS ? GRTX_STATS_FIELDS : 1][kTraceBlock];  // per-lane counters
   // serving: each wave's copy of its current request, each lane's output address and its
   // request's pixel count
@@ -479,11 +486,29 @@ __global__ void __launch_bounds__(kTraceBlock)
     }
   };
 
+  // the destination eviction list's chunk at `pos` (a multiple of kStageE) from LDS to HBM
+  auto flush_evict = [&](int pos) __attribute__((always_inline)) {
+    if constexpr (kStageE > 0) {
+      uint4* q = reinterpret_cast<uint4*>(&LROW(rowE + (par ^ 1) * Args.cap_e + pos));
+#pragma unroll
+      for (int j = 0; j < kStageE / 2; ++j) {
+        const uint2 a = s_edst[(2 * j) * kTraceBlock + tid], b = s_edst[(2 * j + 1) * kTraceBlock + tid];
+        q[j] = make_uint4(a.x, a.y, b.x, b.y);
+      }
+    }
+  };
+
   auto evict = [&](uint64_t k64) __attribute__((always_inline)) {
     if (!ckpt) return;
     if (edst_n < Args.cap_e) {
-      LROW(rowE + (par ^ 1) * Args.cap_e + edst_n) = make_uint2((uint32_t)k64, (uint32_t)(k64 >> 32));
-      ++edst_n;
+      if constexpr (kStageE > 0) {
+        s_edst[(edst_n & (kStageE - 1)) * kTraceBlock + tid] = make_uint2((uint32_t)k64, (uint32_t)(k64 >> 32));
+        ++edst_n;
+        if ((edst_n & (kStageE - 1)) == 0) flush_evict(edst_n - kStageE);
+      } else {
+        LROW(rowE + (par ^ 1) * Args.cap_e + edst_n) = make_uint2((uint32_t)k64, (uint32_t)(k64 >> 32));
+        ++edst_n;
+      }
       STAT(GRTX_STAT_EVICTED);
     } else {
       overflow = true;
@@ -1012,6 +1037,9 @@ __global__ void __launch_bounds__(kTraceBlock)
           // resume: this round's destination lists become the next round's sources (the
           // last, partial chunk of deferred nodes goes out first)
           if (ndst_n & (kStage - 1)) flush_dst(ndst_n & ~(kStage - 1));
+          if constexpr (kStageE > 0) {
+            if (edst_n & (kStageE - 1)) flush_evict(edst_n & ~(kStageE - 1));
+          }
           par ^= 1;
           nsrc_n = ndst_n;
           nsrc_i = 0;
