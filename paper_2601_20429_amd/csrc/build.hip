@@ -731,9 +731,10 @@ __global__ void __launch_bounds__(kBlock) k_wide(int64_t n, const uint32_t* __re
 // nodes above kLayoutLeaves leaves by one workgroup, level by level, from position 0;
 // each node of at most kLayoutLeaves leaves that such a record lists starts a task, a
 // block of (leaves - 1) positions (the most records its subtree can have) reserved after
-// the first `top_cap` positions, which one thread fills breadth first. So the records a
+// the first `top_cap` positions, which one wave fills breadth first. So the records a
 // ray meets near each other lie near each other, and the lines fetched hold live records
-// only. `qold` maps each position to the radix-tree node whose record it holds.
+// only. `qold` maps each position of the top levels to the radix-tree node whose record it
+// holds.
 constexpr int64_t kLayoutLeaves = 128;
 constexpr int kLayoutBlock = 1024;
 
@@ -767,26 +768,25 @@ __device__ __forceinline__ void place_record(const float4* __restrict__ wide, ui
   dst[3] = q3;
 }
 
-// The top levels (one workgroup). Root = radix-tree node 0 at position 0; with at most
-// kLayoutLeaves leaves in all, the root itself is the only task (top_cap = 0).
+// The top levels (one workgroup; its counters live in LDS until the end). Root = radix-tree
+// node 0 at position 0; with at most kLayoutLeaves leaves in all, the root itself is the
+// only task (top_cap = 0).
 __global__ void __launch_bounds__(kLayoutBlock) k_layout_top(int64_t m, const float4* __restrict__ wide,
                                                              const uint32_t* __restrict__ count, uint32_t top_cap,
                                                              float4* __restrict__ nodes, uint32_t* __restrict__ qold,
                                                              uint2* __restrict__ tasks, uint32_t* __restrict__ ctr) {
-  __shared__ uint32_t s_next;
-  uint32_t* task_cursor = ctr;
-  uint32_t* n_tasks = ctr + 1;
+  __shared__ uint32_t s_next, s_cursor, s_tasks;
   if (m <= kLayoutLeaves) {
     if (threadIdx.x == 0) {
-      *task_cursor = (uint32_t)(m - 1);
-      *n_tasks = 1u;
+      ctr[0] = (uint32_t)(m - 1);
+      ctr[1] = 1u;
       tasks[0] = make_uint2(0u, 0u);
     }
     return;
   }
   if (threadIdx.x == 0) {
-    *task_cursor = 0u;
-    *n_tasks = 0u;
+    s_cursor = 0u;
+    s_tasks = 0u;
     qold[0] = 0u;
     s_next = 1u;
   }
@@ -801,7 +801,7 @@ __global__ void __launch_bounds__(kLayoutBlock) k_layout_top(int64_t m, const fl
           qold[pos] = c;
           return pos;
         }
-        return new_task(c, cnt, top_cap, task_cursor, n_tasks, tasks);
+        return new_task(c, cnt, top_cap, &s_cursor, &s_tasks, tasks);
       });
     }
     __syncthreads();
@@ -809,23 +809,74 @@ __global__ void __launch_bounds__(kLayoutBlock) k_layout_top(int64_t m, const fl
     end = s_next;
     __syncthreads();
   }
+  if (threadIdx.x == 0) {
+    ctr[0] = s_cursor;
+    ctr[1] = s_tasks;
+  }
 }
 
-// The tasks: one thread fills a block breadth first, using `qold` as its queue.
+// The tasks: one wave fills a block breadth first, a level at a time. The records of one
+// level belong to disjoint subtrees of two leaves or more, so a block of at most
+// kLayoutLeaves leaves has at most kLayoutLeaves / 2 = 64 records per level: one per lane.
+// Each lane places its record, its internal entries taking the next positions in lane and
+// entry order (the order a sequential breadth-first fill gives), and passes their
+// radix-tree nodes through LDS to the lanes that place them on the next level.
+static_assert(kLayoutLeaves / 2 <= 64, "a level of a layout block must fit one wave");
 __global__ void __launch_bounds__(kBlock) k_layout_tasks(const float4* __restrict__ wide, const uint2* __restrict__ tasks,
-                                                         const uint32_t* __restrict__ ctr, float4* __restrict__ nodes,
-                                                         uint32_t* __restrict__ qold) {
+                                                         const uint32_t* __restrict__ ctr, float4* __restrict__ nodes) {
+  __shared__ uint32_t s_next[kBlock / 64][64];
   const uint32_t n = ctr[1];
-  for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < n; t += gridDim.x * kBlock) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t below = lane ? ~0ull >> (64 - lane) : 0ull;
+  for (uint32_t t = blockIdx.x * (kBlock / 64) + w; t < n; t += gridDim.x * (kBlock / 64)) {
     const uint2 task = tasks[t];
-    uint32_t head = task.y, tail = task.y + 1;
-    qold[head] = task.x;
-    while (head < tail) {
-      place_record(wide, qold[head], head, nodes, [&](uint32_t c) {
-        qold[tail] = c;
-        return tail++;
-      });
-      ++head;
+    uint32_t begin = task.y, width = 1, old = task.x;
+    while (width > 0) {
+      const bool mine = (uint32_t)lane < width;
+      float4 q0{}, q1{}, q2{}, q3{};
+      if (mine) {
+        const float4* src = wide + (int64_t)kNodeF4 * old;
+        q0 = src[0];
+        q1 = src[1];
+        q2 = src[2];
+        q3 = src[3];
+      }
+      uint32_t r[4] = {__float_as_uint(q1.z), __float_as_uint(q1.w), __float_as_uint(q2.x), __float_as_uint(q2.y)};
+      bool in[4];
+      uint32_t below_n = 0, total = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        in[j] = mine && r[j] != kNoChild && !(r[j] & kLeafFlag);
+        const uint64_t m = __ballot(in[j]);
+        below_n += (uint32_t)__popcll(m & below);
+        total += (uint32_t)__popcll(m);
+      }
+      const uint32_t nbeg = begin + width;
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // last level's reads of s_next are done
+      if (mine) {
+        uint32_t k = below_n;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (in[j]) {
+            s_next[w][k] = r[j];
+            r[j] = nbeg + k;
+            ++k;
+          }
+        }
+        q1.z = __uint_as_float(r[0]);
+        q1.w = __uint_as_float(r[1]);
+        q2.x = __uint_as_float(r[2]);
+        q2.y = __uint_as_float(r[3]);
+        float4* dst = nodes + (int64_t)kNodeF4 * (begin + (uint32_t)lane);
+        dst[0] = q0;
+        dst[1] = q1;
+        dst[2] = q2;
+        dst[3] = q3;
+      }
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // this level's writes to s_next are done
+      width = total < 64u ? total : 64u;  // (total <= 64 by the bound above)
+      old = (uint32_t)lane < width ? s_next[w][lane] : 0u;
+      begin = nbeg;
     }
   }
 }
@@ -1625,8 +1676,9 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
     hipLaunchKernelGGL(k_wide, dim3(grid_for(nint)), dim3(kBlock), 0, s, m, b->child, b->boxes, wide);
     hipLaunchKernelGGL(k_layout_top, dim3(1), dim3(kLayoutBlock), 0, s, m, wide, count, (uint32_t)top_cap, b->nodes,
                        qold, tasks, ctr);
-    hipLaunchKernelGGL(k_layout_tasks, dim3((unsigned)std::min<int64_t>(2048, grid_for(m / 32 + 1))), dim3(kBlock), 0,
-                       s, wide, tasks, ctr, b->nodes, qold);
+    // a wave per task; the tasks number about m / 64 (a grid-stride loop takes any more)
+    hipLaunchKernelGGL(k_layout_tasks, dim3((unsigned)std::min<int64_t>(2048, m / (64 * (kBlock / 64)) + 1)),
+                       dim3(kBlock), 0, s, wide, tasks, ctr, b->nodes);
   } else {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, s, b->parent, 1, kNoParent);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, s, b->depth, 2, 0u);

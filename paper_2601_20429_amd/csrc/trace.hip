@@ -64,9 +64,12 @@ constexpr int kRefillThreshold = GRTX_REFILL_THRESHOLD;  // idle lanes that end 
 #endif
 constexpr int kStage = GRTX_STAGE;
 // Eviction-list appends gathered the same way, kStageE entries at a time (0: written one
-// by one); kStageE divides kStage.
+// by one); kStageE divides kStage. Two entries (16-B writes) measured 1-2% faster than
+// single entries on the 3M-Gaussian workload; four (with a smaller LDS stack or deferred
+// stage, to keep three workgroups per CU) were slower. The serving kernel, whose LDS also
+// holds its request copies, writes them one by one.
 #ifndef GRTX_EVICT_STAGE
-#define GRTX_EVICT_STAGE 0
+#define GRTX_EVICT_STAGE 2
 #endif
 constexpr int kStageE = GRTX_EVICT_STAGE;
 #ifndef GRTX_CHUNKS
@@ -77,16 +80,26 @@ constexpr int kStageE = GRTX_EVICT_STAGE;
 constexpr int kChunks = GRTX_CHUNKS;
 // Default per-ray capacities of the checkpoint (deferred node) and eviction lists. A ray
 // that overflows one falls back to a restart-from-root round, which the other lanes of
-// its wave wait for. At 256/128 such rounds are rare on a 100k-Gaussian scene; structures
-// of more than a million leaves defer several hundred nodes per ray (about a thousand for
-// rays that start inside a 3M-Gaussian scene) and get 2048/512.
+// its wave wait for. At 256/128 such rounds are rare on a 100k-Gaussian scene. Structures
+// of more than a million leaves defer several hundred nodes per ray, and rays that start
+// inside a 3M-Gaussian scene over a thousand, with a long tail: at 2048/512, 2% of such
+// rays fell back and the launch took 9% longer than at 8192/2048 (0.01% fall back). The
+// lists are per lane, not per ray, so 8192/2048 costs about 33 GB at k = 16 for 3072
+// waves, affordable in 288 GB. The allocation-free entry point, whose lists share a fixed
+// scratch, keeps 2048/512 there so that enough workgroups fit.
 constexpr int kDefaultDeferCap = 256;
 constexpr int kDefaultEvictCap = 128;
-constexpr int kLargeDeferCap = 2048;
-constexpr int kLargeEvictCap = 512;
+constexpr int kLargeDeferCap = 8192;
+constexpr int kLargeEvictCap = 2048;
+constexpr int kNoAllocLargeDeferCap = 2048;
+constexpr int kNoAllocLargeEvictCap = 512;
 constexpr int64_t kLargeScene = 1000000;
-inline int default_defer_cap(int64_t n_leaves) { return n_leaves > kLargeScene ? kLargeDeferCap : kDefaultDeferCap; }
-inline int default_evict_cap(int64_t n_leaves) { return n_leaves > kLargeScene ? kLargeEvictCap : kDefaultEvictCap; }
+inline int default_defer_cap(int64_t n_leaves, bool noalloc) {
+  return n_leaves <= kLargeScene ? kDefaultDeferCap : noalloc ? kNoAllocLargeDeferCap : kLargeDeferCap;
+}
+inline int default_evict_cap(int64_t n_leaves, bool noalloc) {
+  return n_leaves <= kLargeScene ? kDefaultEvictCap : noalloc ? kNoAllocLargeEvictCap : kLargeEvictCap;
+}
 
 
 enum : int { kIdle = 0, kTrav = 1, kEnd = 2 };
@@ -388,7 +401,8 @@ __global__ void __launch_bounds__(kTraceBlock)
     __attribute__((amdgpu_waves_per_eu(K <= 32 ? GRTX_MIN_WAVES : 1, 8))) k_trace(TraceArgs Args) {
   __shared__ uint2 s_stack[kLdsStack * kTraceBlock];
   __shared__ uint2 s_dst[kStage * kTraceBlock];  // destination node-list entries not yet written out
-  __shared__ uint2 s_edst[kStageE > 0 ? kStageE * kTraceBlock : 1];  // eviction-list entries likewise
+  constexpr int kStageEv = SERVE ? 0 : kStageE;
+  __shared__ uint2 s_edst[kStageEv > 0 ? kStageEv * kTraceBlock : 1];  // eviction-list entries likewise
   __shared__ uint32_t s_stat[STATS ? GRTX_STATS_FIELDS : 1][kTraceBlock];  // per-lane counters
   // serving: each wave's copy of its current request, each lane's output address and its
   // request's pixel count
@@ -486,12 +500,12 @@ __global__ void __launch_bounds__(kTraceBlock)
     }
   };
 
-  // the destination eviction list's chunk at `pos` (a multiple of kStageE) from LDS to HBM
+  // the destination eviction list's chunk at `pos` (a multiple of kStageEv) from LDS to HBM
   auto flush_evict = [&](int pos) __attribute__((always_inline)) {
-    if constexpr (kStageE > 0) {
+    if constexpr (kStageEv > 0) {
       uint4* q = reinterpret_cast<uint4*>(&LROW(rowE + (par ^ 1) * Args.cap_e + pos));
 #pragma unroll
-      for (int j = 0; j < kStageE / 2; ++j) {
+      for (int j = 0; j < kStageEv / 2; ++j) {
         const uint2 a = s_edst[(2 * j) * kTraceBlock + tid], b = s_edst[(2 * j + 1) * kTraceBlock + tid];
         q[j] = make_uint4(a.x, a.y, b.x, b.y);
       }
@@ -501,10 +515,10 @@ __global__ void __launch_bounds__(kTraceBlock)
   auto evict = [&](uint64_t k64) __attribute__((always_inline)) {
     if (!ckpt) return;
     if (edst_n < Args.cap_e) {
-      if constexpr (kStageE > 0) {
-        s_edst[(edst_n & (kStageE - 1)) * kTraceBlock + tid] = make_uint2((uint32_t)k64, (uint32_t)(k64 >> 32));
+      if constexpr (kStageEv > 0) {
+        s_edst[(edst_n & (kStageEv - 1)) * kTraceBlock + tid] = make_uint2((uint32_t)k64, (uint32_t)(k64 >> 32));
         ++edst_n;
-        if ((edst_n & (kStageE - 1)) == 0) flush_evict(edst_n - kStageE);
+        if ((edst_n & (kStageEv - 1)) == 0) flush_evict(edst_n - kStageEv);
       } else {
         LROW(rowE + (par ^ 1) * Args.cap_e + edst_n) = make_uint2((uint32_t)k64, (uint32_t)(k64 >> 32));
         ++edst_n;
@@ -1037,8 +1051,8 @@ __global__ void __launch_bounds__(kTraceBlock)
           // resume: this round's destination lists become the next round's sources (the
           // last, partial chunk of deferred nodes goes out first)
           if (ndst_n & (kStage - 1)) flush_dst(ndst_n & ~(kStage - 1));
-          if constexpr (kStageE > 0) {
-            if (edst_n & (kStageE - 1)) flush_evict(edst_n & ~(kStageE - 1));
+          if constexpr (kStageEv > 0) {
+            if (edst_n & (kStageEv - 1)) flush_evict(edst_n & ~(kStageEv - 1));
           }
           par ^= 1;
           nsrc_n = ndst_n;
@@ -1438,8 +1452,8 @@ grtx_status launch_trace_in(const TraceScene& b, const grtx_rays* r, const grtx_
   int64_t need_blocks = (R + kTraceBlock - 1) / kTraceBlock;
   if (blocks > need_blocks) blocks = (int)std::max<int64_t>(1, need_blocks);
 
-  const int cap_d = stage_round(p->defer_capacity > 0 ? p->defer_capacity : default_defer_cap(b.n_leaves));
-  const int cap_e = stage_round(p->evict_capacity > 0 ? p->evict_capacity : default_evict_cap(b.n_leaves));
+  const int cap_d = stage_round(p->defer_capacity > 0 ? p->defer_capacity : default_defer_cap(b.n_leaves, noalloc));
+  const int cap_e = stage_round(p->evict_capacity > 0 ? p->evict_capacity : default_evict_cap(b.n_leaves, noalloc));
   const int64_t rows = kSpillRows + 2 * (int64_t)cap_d + 2 * (int64_t)cap_e + K;
   const size_t need = (size_t)blocks * kWaves * rows * 64 * sizeof(uint2) + 256;
 
