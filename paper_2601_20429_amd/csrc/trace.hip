@@ -78,9 +78,11 @@ constexpr int kStageE = GRTX_EVICT_STAGE;
 // Work queues. One shared queue keeps a launch's heaviest-first order; one per XCD (8)
 // measured slower.
 constexpr int kChunks = GRTX_CHUNKS;
-// Default per-ray capacities of the checkpoint (deferred node) and eviction lists. A ray
-// that overflows one falls back to a restart-from-root round, which the other lanes of
-// its wave wait for. At 256/128 such rounds are rare on a 100k-Gaussian scene. Structures
+// Default per-ray capacities of the checkpoint (deferred node) and eviction lists. An entry
+// that finds its list full is dropped and lowers the ray's key limit to its smallest key;
+// the ray goes on from its checkpoint and falls back to a restart-from-root round (which
+// the other lanes of its wave wait for) only if its blending reaches that limit. At
+// 256/128 such rounds are rare on a 100k-Gaussian scene. Structures
 // of more than a million leaves defer several hundred nodes per ray, and rays that start
 // inside a 3M-Gaussian scene over a thousand, with a long tail: at 2048/512, 2% of such
 // rays fell back and the launch took 9% longer than at 8192/2048 (0.01% fall back). The
@@ -452,7 +454,10 @@ __global__ void __launch_bounds__(kTraceBlock)
   int par = 0;                              // which list of each pair is the source
   int nsrc_n = 0, nsrc_i = 0, ndst_n = 0;   // deferred nodes
   int esrc_n = 0, esrc_i = 0, edst_n = 0;   // evicted hits
-  int overflow = 0;
+  // Every hit nearer than `lim` is either blended, in the k-buffer, in a list, or in a
+  // deferred subtree; hits from distance `lim` on may have been dropped by a full list
+  // (infinity: none).
+  float lim = INFINITY;
   int nblend = 0;
   bool exhausted = false;
   int chunk = (int)(blockIdx.x % kChunks);
@@ -488,16 +493,62 @@ __global__ void __launch_bounds__(kTraceBlock)
     }
   };
 
+  // A nearly full destination list is compacted in place (from the top of the traversal
+  // loop, so that the appends in the node and leaf steps always find room): the entries
+  // nearer than a threshold stay, the rest are dropped and the limit comes down to the
+  // threshold. The threshold starts halfway between the nearest and the farthest entry and
+  // halves its distance to the nearest until at most three quarters of the entries stay
+  // (after four halvings none stay). Entries a ray needs before early termination are
+  // usually the near ones, so it seldom reaches the limit. `row0` is the list's first row,
+  // `n` its length (all of it in HBM). Returns the entries kept.
+  auto compact = [&](int row0, int n) __attribute__((always_inline)) -> int {
+    float lo = INFINITY, hi = 0.f;
+#pragma unroll 1
+    for (int i = 0; i + 1 < n; i += 2) {
+      const uint4 v = *reinterpret_cast<const uint4*>(&LROW(row0 + i));
+      lo = fminf(lo, fminf(__uint_as_float(v.y), __uint_as_float(v.w)));
+      hi = fmaxf(hi, fmaxf(__uint_as_float(v.y), __uint_as_float(v.w)));
+    }
+    if (n & 1) {
+      const float t = __uint_as_float(LROW(row0 + n - 1).y);
+      lo = fminf(lo, t);
+      hi = fmaxf(hi, t);
+    }
+    float thr = lo + 0.5f * (hi - lo);
+    int m = n;
+#pragma unroll 1
+    for (int it = 0; it < 4; ++it) {
+      int w = 0;
+#pragma unroll 1
+      for (int i = 0; i < m; ++i) {
+        const uint2 e = LROW(row0 + i);
+        if (__uint_as_float(e.y) < thr) LROW(row0 + w++) = e;
+      }
+      m = w;
+      if (4 * m <= 3 * n) break;
+      thr = lo + 0.5f * (thr - lo);
+    }
+    if (4 * m > 3 * n) {
+      m = 0;
+      thr = lo;
+    }
+    lim = fminf(lim, thr);
+    return m;
+  };
+
   auto defer = [&](uint32_t ref, float t) __attribute__((always_inline)) {
     if (!ckpt) return;
-    if (ndst_n < Args.cap_d) {
-      s_dst[(ndst_n & (kStage - 1)) * kTraceBlock + tid] = make_uint2(ref, __float_as_uint(t));
-      ++ndst_n;
-      if ((ndst_n & (kStage - 1)) == 0) flush_dst(ndst_n - kStage);
-      STAT(GRTX_STAT_DEFERRED);
-    } else {
-      overflow = true;
+    // every hit of the subtree lies at t or beyond: a subtree at or beyond the limit is not
+    // kept (nor one that finds the list full, which compaction prevents)
+    if (t >= lim) return;
+    if (ndst_n == Args.cap_d) {
+      lim = t;
+      return;
     }
+    s_dst[(ndst_n & (kStage - 1)) * kTraceBlock + tid] = make_uint2(ref, __float_as_uint(t));
+    ++ndst_n;
+    if ((ndst_n & (kStage - 1)) == 0) flush_dst(ndst_n - kStage);
+    STAT(GRTX_STAT_DEFERRED);
   };
 
   // the destination eviction list's chunk at `pos` (a multiple of kStageEv) from LDS to HBM
@@ -514,18 +565,44 @@ __global__ void __launch_bounds__(kTraceBlock)
 
   auto evict = [&](uint64_t k64) __attribute__((always_inline)) {
     if (!ckpt) return;
-    if (edst_n < Args.cap_e) {
-      if constexpr (kStageEv > 0) {
-        s_edst[(edst_n & (kStageEv - 1)) * kTraceBlock + tid] = make_uint2((uint32_t)k64, (uint32_t)(k64 >> 32));
-        ++edst_n;
-        if ((edst_n & (kStageEv - 1)) == 0) flush_evict(edst_n - kStageEv);
-      } else {
-        LROW(rowE + (par ^ 1) * Args.cap_e + edst_n) = make_uint2((uint32_t)k64, (uint32_t)(k64 >> 32));
-        ++edst_n;
-      }
-      STAT(GRTX_STAT_EVICTED);
+    if (key_t(k64) >= lim) return;
+    if (edst_n == Args.cap_e) {
+      lim = key_t(k64);
+      return;
+    }
+    if constexpr (kStageEv > 0) {
+      s_edst[(edst_n & (kStageEv - 1)) * kTraceBlock + tid] = make_uint2((uint32_t)k64, (uint32_t)(k64 >> 32));
+      ++edst_n;
+      if ((edst_n & (kStageEv - 1)) == 0) flush_evict(edst_n - kStageEv);
     } else {
-      overflow = true;
+      LROW(rowE + (par ^ 1) * Args.cap_e + edst_n) = make_uint2((uint32_t)k64, (uint32_t)(k64 >> 32));
+      ++edst_n;
+    }
+    STAT(GRTX_STAT_EVICTED);
+  };
+
+  // Room for one traversal iteration's appends (at most five deferred nodes: one carried
+  // entry and four children; at most one evicted hit), made by compaction; the partial
+  // staging chunk goes out first and its survivors come back to LDS.
+  auto make_room = [&]() __attribute__((always_inline)) {
+    if (ndst_n > Args.cap_d - 5) {
+      const int row0 = rowN + (par ^ 1) * Args.cap_d;
+      if (ndst_n & (kStage - 1)) flush_dst(ndst_n & ~(kStage - 1));
+      ndst_n = compact(row0, ndst_n);
+#pragma unroll 1
+      for (int j = ndst_n & ~(kStage - 1); j < ndst_n; ++j) s_dst[(j & (kStage - 1)) * kTraceBlock + tid] = LROW(row0 + j);
+    }
+    if (edst_n > Args.cap_e - 1) {
+      const int row0 = rowE + (par ^ 1) * Args.cap_e;
+      if constexpr (kStageEv > 0) {
+        if (edst_n & (kStageEv - 1)) flush_evict(edst_n & ~(kStageEv - 1));
+      }
+      edst_n = compact(row0, edst_n);
+      if constexpr (kStageEv > 0) {
+#pragma unroll 1
+        for (int j = edst_n & ~(kStageEv - 1); j < edst_n; ++j)
+          s_edst[(j & (kStageEv - 1)) * kTraceBlock + tid] = LROW(row0 + j);
+      }
     }
   };
 
@@ -610,7 +687,7 @@ __global__ void __launch_bounds__(kTraceBlock)
             par = 0;
             nsrc_n = nsrc_i = ndst_n = 0;
             esrc_n = esrc_i = edst_n = 0;
-            overflow = false;
+            lim = INFINITY;
             have_key = false;
             root_start();
             state = kTrav;
@@ -693,7 +770,7 @@ __global__ void __launch_bounds__(kTraceBlock)
             par = 0;
             nsrc_n = nsrc_i = ndst_n = 0;
             esrc_n = esrc_i = edst_n = 0;
-            overflow = false;
+            lim = INFINITY;
             have_key = false;
             if constexpr (STATS) {
 #pragma unroll
@@ -723,6 +800,7 @@ __global__ void __launch_bounds__(kTraceBlock)
       if (!trav) break;
       const uint64_t waiting = __ballot(state == kEnd) | (exhausted || nowork ? 0ull : __ballot(state == kIdle));
       if (__popcll(waiting) >= kRefillThreshold) break;
+      if (state == kTrav && ckpt) make_room();
       const uint64_t tmax = kb[K - 1];
       const float tmax_t = key_t(tmax);
       if (state == kTrav && !has_cur && !have_key) {
@@ -894,12 +972,21 @@ __global__ void __launch_bounds__(kTraceBlock)
       // proxy keys carry the Gaussian id: a mesh crossed exactly on an edge reports the
       // same Gaussian twice with adjacent keys; only the first is blended
       uint32_t prev_id = tmin == 0ull ? 0xFFFFFFFFu : (uint32_t)tmin;
-      // the next entry's key is read while the current one blends
+      // the next entry's key is read while the current one blends; blending stops at the
+      // first hit at or beyond the limit (hits there may be missing), and `lastp` is the last
+      // key taken
       uint2 kv = PARK(K - A.k);
+      uint64_t lastp = tmin;
+      bool stopped = false;
 #pragma unroll 1
       for (int j = K - A.k; j < K && !ert; ++j) {
         const uint64_t x = ((uint64_t)kv.y << 32) | kv.x;
         if (x == kEmptyKey) break;
+        if (key_t(x) >= lim) {
+          stopped = true;
+          break;
+        }
+        lastp = x;
         kv = PARK(j + 1 < K ? j + 1 : j);  // unconditional: no join right after the load
         const uint32_t p = (uint32_t)x;
         const float4* ip = A.inst + 4 * (int64_t)p;
@@ -964,7 +1051,9 @@ __global__ void __launch_bounds__(kTraceBlock)
       // the old entries are dead from the park on and hold no registers through the blend
       kbuf_reset(kb, A.k);
       const bool full = last != kEmptyKey;
-      const bool done = ert || !full || (ckpt && !overflow && ndst_n == 0 && edst_n == 0);
+      // with a limit, "no hit left" holds only below it
+      const bool limited = lim != INFINITY;
+      const bool done = ert || (!limited && (!full || (ckpt && ndst_n == 0 && edst_n == 0)));
       // A segment that reached its surface with T >= T_min goes on along its reflected or
       // refracted ray in the same lane: colour, transmittance and the hit list carry over,
       // and the continuation's distances start at the bent path length.
@@ -986,7 +1075,7 @@ __global__ void __launch_bounds__(kTraceBlock)
         par = 0;
         nsrc_n = nsrc_i = ndst_n = 0;
         esrc_n = esrc_i = edst_n = 0;
-        overflow = false;
+        lim = INFINITY;
         root_start();
         state = kTrav;
       } else if (done && SERVE) {
@@ -1039,11 +1128,13 @@ __global__ void __launch_bounds__(kTraceBlock)
         }
         state = kIdle;
       } else {
-        tmin = last;
-        if (!ckpt || overflow) {
-          // restart from the root beyond the last blended hit
+        tmin = lastp;
+        if (!ckpt || stopped || (limited && (!full || (ndst_n == 0 && edst_n == 0)))) {
+          // restart from the root beyond the last blended hit: restart mode, or a
+          // checkpoint whose lists dropped entries and whose remaining keys below the
+          // limit are all blended
           if (ckpt) STAT(GRTX_STAT_FALLBACKS);
-          overflow = false;
+          lim = INFINITY;
           nsrc_n = nsrc_i = ndst_n = 0;
           esrc_n = esrc_i = edst_n = 0;
           root_start();

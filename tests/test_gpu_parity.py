@@ -491,6 +491,31 @@ def test_list_overflow_falls_back_to_restart():
     assert fb > fa and fb > 0, (fa, fb)
 
 
+@pytest.mark.parametrize("caps", [(8, 8), (24, 16), (64, 40)])
+def test_full_lists_compact_and_keep_results(caps):
+    """Rays that start at Gaussian centres inside dense clusters defer and evict more than
+    small lists hold: a full list is compacted (the near entries stay, the limit comes down)
+    and the ray restarts from the root only if its blending reaches the limit. Colour,
+    depth, opacity and the blended hits equal the default lists' bit for bit, and the oracle
+    by the per-ray rule."""
+    say("compaction", caps)
+    scene = inputs.cluster_scene(2, 100_000, 3)
+    rng = np.random.default_rng(71)
+    pick = rng.choice(scene.n, 768, replace=False)
+    o = scene.means[pick].astype(np.float32)
+    d = rng.normal(size=(768, 3))
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    bvh = build(scene)
+    a = render(bvh, o, d, k=8, cap=512)
+    b = render(bvh, o, d, k=8, cap=512, defer_capacity=caps[0], evict_capacity=caps[1])
+    for key in ["rgb", "depth", "opacity", "hit_counts", "hit_ids"]:
+        assert np.array_equal(a[key], b[key]), (caps, key)
+    assert int(b["stats"][:, grtx.STAT_DEFERRED].max()) > caps[0]  # more entries than a list holds went through
+    ref = oracle.render(scene, o, d, AMIN, T_MIN, cap=512)
+    s = parity.compare_render(scene, o, d, b, ref, AMIN, T_MIN, label=f"compaction {caps}")
+    say(s, "fallbacks", int(b["stats"][:, grtx.STAT_FALLBACKS].sum()))
+
+
 def test_degenerate_inputs():
     say("degenerate")
     o = np.float32([[0, -3, 0], [0, -3, 0]])
