@@ -51,7 +51,8 @@ namespace {
 #define GRTX_REFILL_THRESHOLD 32
 #endif
 // Waves per SIMD the trace kernel is register-budgeted for up to k = 32 (at most 170
-// VGPRs): three, which k <= 32 reach without scratch; k = 64 keeps the compiler's choice.
+// VGPRs): three, which k <= 32 reach with a few dozen bytes of scratch per lane on cold
+// paths; k = 64 is held to two (256 VGPRs).
 #ifndef GRTX_MIN_WAVES
 #define GRTX_MIN_WAVES 3
 #endif
@@ -72,6 +73,8 @@ constexpr int kStage = GRTX_STAGE;
 #define GRTX_EVICT_STAGE 2
 #endif
 constexpr int kStageE = GRTX_EVICT_STAGE;
+// Traversal iterations between checks for list room (a power of two).
+constexpr int kRoomEvery = 8;
 #ifndef GRTX_CHUNKS
 #define GRTX_CHUNKS 1
 #endif
@@ -400,7 +403,7 @@ __device__ __forceinline__ KernArgs& kernel_args() {
 // waves wait for new requests and leave once the queue closes.
 template <int K, int LEAF, bool STATS, bool SERVE = false>
 __global__ void __launch_bounds__(kTraceBlock)
-    __attribute__((amdgpu_waves_per_eu(K <= 32 ? GRTX_MIN_WAVES : 1, 8))) k_trace(TraceArgs Args) {
+    __attribute__((amdgpu_waves_per_eu(K <= 32 ? GRTX_MIN_WAVES : 2, 8))) k_trace(TraceArgs Args) {
   __shared__ uint2 s_stack[kLdsStack * kTraceBlock];
   __shared__ uint2 s_dst[kStage * kTraceBlock];  // destination node-list entries not yet written out
   constexpr int kStageEv = SERVE ? 0 : kStageE;
@@ -462,6 +465,7 @@ __global__ void __launch_bounds__(kTraceBlock)
   bool exhausted = false;
   int chunk = (int)(blockIdx.x % kChunks);
   int chunks_tried = 0;
+  int room_tick = 0;  // traversal iterations of the wave, for the list-room check
   bool nowork = false;       // serving: the last claim found no work
   uint64_t idle_since = 0;   // serving: when the wave last ran out of rays (lane 0)
   if constexpr (SERVE) {
@@ -502,27 +506,37 @@ __global__ void __launch_bounds__(kTraceBlock)
   // usually the near ones, so it seldom reaches the limit. `row0` is the list's first row,
   // `n` its length (all of it in HBM). Returns the entries kept.
   auto compact = [&](int row0, int n) __attribute__((always_inline)) -> int {
+    if (n == 0) return 0;
+    // eight entries per step, their four 16-B loads in flight together (a list's rows are
+    // a multiple of 8 long and 16-B aligned, so a step may read past n inside the list)
     float lo = INFINITY, hi = 0.f;
 #pragma unroll 1
-    for (int i = 0; i + 1 < n; i += 2) {
-      const uint4 v = *reinterpret_cast<const uint4*>(&LROW(row0 + i));
-      lo = fminf(lo, fminf(__uint_as_float(v.y), __uint_as_float(v.w)));
-      hi = fmaxf(hi, fmaxf(__uint_as_float(v.y), __uint_as_float(v.w)));
+    for (int i = 0; i < n; i += 8) {
+      uint4 v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = *reinterpret_cast<const uint4*>(&LROW(row0 + i + 2 * q));
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float a = __uint_as_float(v[q].y), b = __uint_as_float(v[q].w);
+        if (i + 2 * q < n) lo = fminf(lo, a), hi = fmaxf(hi, a);
+        if (i + 2 * q + 1 < n) lo = fminf(lo, b), hi = fmaxf(hi, b);
+      }
     }
-    if (n & 1) {
-      const float t = __uint_as_float(LROW(row0 + n - 1).y);
-      lo = fminf(lo, t);
-      hi = fmaxf(hi, t);
-    }
-    float thr = lo + 0.5f * (hi - lo);
+    float thr = fminf(lo + 0.5f * (hi - lo), lim);
     int m = n;
 #pragma unroll 1
     for (int it = 0; it < 4; ++it) {
       int w = 0;
 #pragma unroll 1
-      for (int i = 0; i < m; ++i) {
-        const uint2 e = LROW(row0 + i);
-        if (__uint_as_float(e.y) < thr) LROW(row0 + w++) = e;
+      for (int i = 0; i < m; i += 8) {
+        uint4 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = *reinterpret_cast<const uint4*>(&LROW(row0 + i + 2 * q));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (i + 2 * q < m && __uint_as_float(v[q].y) < thr) LROW(row0 + w++) = make_uint2(v[q].x, v[q].y);
+          if (i + 2 * q + 1 < m && __uint_as_float(v[q].w) < thr) LROW(row0 + w++) = make_uint2(v[q].z, v[q].w);
+        }
       }
       m = w;
       if (4 * m <= 3 * n) break;
@@ -536,13 +550,13 @@ __global__ void __launch_bounds__(kTraceBlock)
     return m;
   };
 
+  // (Entries at or beyond the limit may still be appended: the next compaction drops
+  // them. One that finds its list full is dropped at once and lowers the limit to it:
+  // every hit of a subtree lies at its entry distance or beyond.)
   auto defer = [&](uint32_t ref, float t) __attribute__((always_inline)) {
     if (!ckpt) return;
-    // every hit of the subtree lies at t or beyond: a subtree at or beyond the limit is not
-    // kept (nor one that finds the list full, which compaction prevents)
-    if (t >= lim) return;
     if (ndst_n == Args.cap_d) {
-      lim = t;
+      lim = fminf(lim, t);
       return;
     }
     s_dst[(ndst_n & (kStage - 1)) * kTraceBlock + tid] = make_uint2(ref, __float_as_uint(t));
@@ -565,9 +579,8 @@ __global__ void __launch_bounds__(kTraceBlock)
 
   auto evict = [&](uint64_t k64) __attribute__((always_inline)) {
     if (!ckpt) return;
-    if (key_t(k64) >= lim) return;
     if (edst_n == Args.cap_e) {
-      lim = key_t(k64);
+      lim = fminf(lim, key_t(k64));
       return;
     }
     if constexpr (kStageEv > 0) {
@@ -581,18 +594,20 @@ __global__ void __launch_bounds__(kTraceBlock)
     STAT(GRTX_STAT_EVICTED);
   };
 
-  // Room for one traversal iteration's appends (at most five deferred nodes: one carried
-  // entry and four children; at most one evicted hit), made by compaction; the partial
-  // staging chunk goes out first and its survivors come back to LDS.
+  // Room for kRoomEvery traversal iterations' appends (each appends at most five deferred
+  // nodes: one carried entry and four children; and at most one evicted hit), made by
+  // compaction; the partial staging chunk goes out first and its survivors come back to
+  // LDS. (Lists shorter than that margin are compacted at every check; an append that
+  // still finds its list full is dropped and lowers the limit.)
   auto make_room = [&]() __attribute__((always_inline)) {
-    if (ndst_n > Args.cap_d - 5) {
+    if (ndst_n > Args.cap_d - 5 * kRoomEvery) {
       const int row0 = rowN + (par ^ 1) * Args.cap_d;
       if (ndst_n & (kStage - 1)) flush_dst(ndst_n & ~(kStage - 1));
       ndst_n = compact(row0, ndst_n);
 #pragma unroll 1
       for (int j = ndst_n & ~(kStage - 1); j < ndst_n; ++j) s_dst[(j & (kStage - 1)) * kTraceBlock + tid] = LROW(row0 + j);
     }
-    if (edst_n > Args.cap_e - 1) {
+    if (edst_n > Args.cap_e - kRoomEvery) {
       const int row0 = rowE + (par ^ 1) * Args.cap_e;
       if constexpr (kStageEv > 0) {
         if (edst_n & (kStageEv - 1)) flush_evict(edst_n & ~(kStageEv - 1));
@@ -800,7 +815,7 @@ __global__ void __launch_bounds__(kTraceBlock)
       if (!trav) break;
       const uint64_t waiting = __ballot(state == kEnd) | (exhausted || nowork ? 0ull : __ballot(state == kIdle));
       if (__popcll(waiting) >= kRefillThreshold) break;
-      if (state == kTrav && ckpt) make_room();
+      if ((++room_tick & (kRoomEvery - 1)) == 0 && state == kTrav && ckpt) make_room();
       const uint64_t tmax = kb[K - 1];
       const float tmax_t = key_t(tmax);
       if (state == kTrav && !has_cur && !have_key) {

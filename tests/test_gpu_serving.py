@@ -117,11 +117,11 @@ def test_admission_under_memory_pressure():
             for _ in range(3)]
     rb = grtx.request_bytes(cams[0])
     # the budget's fixed part (kernel pool, queue, scene copy), read from a probe server
-    probe = grtx.Server(memory_budget=8 << 30, k=16, T_min=1e-3)
+    probe = grtx.Server(memory_budget=16 << 30, k=16, T_min=1e-3)
     probe.add_scene(bvh)
     t = probe.submit(0, cams[0])
     wait_all(probe, [t], 30)
-    fixed = (8 << 30) - probe.stats()["bytes_available"]
+    fixed = (16 << 30) - probe.stats()["bytes_available"]
     probe.release(t)
     probe.close()
     srv = grtx.Server(memory_budget=fixed + rb + rb // 2, k=16, T_min=1e-3)
@@ -200,7 +200,7 @@ def test_request_too_large_is_refused():
     say("serving capacity")
     scene = inputs.cluster_scene(10, 20_000, 3)
     bvh = grtx.build(grtx.SceneTensors.from_scene(scene, "cuda"), alpha_min=AMIN)
-    srv = grtx.Server(memory_budget=8 << 30, k=16, max_request_rays=1 << 16)
+    srv = grtx.Server(memory_budget=16 << 30, k=16, max_request_rays=1 << 16)
     srv.add_scene(bvh)
     with pytest.raises(grtx.GrtxError) as e:
         srv.submit(0, inputs.orbit_camera(512, 512))  # more pixels than a request may hold
