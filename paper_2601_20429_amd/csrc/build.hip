@@ -881,6 +881,32 @@ __global__ void __launch_bounds__(kBlock) k_layout_tasks(const float4* __restric
   }
 }
 
+// ------------------------------------------------------------------ density grid
+// Leaves per cell of a kDensityRes^3 grid over the leaf centres' bounds. A thread counts
+// kDensityRun consecutive sorted leaves and adds each run of equal cells with one atomic.
+constexpr int kDensityRun = 16;
+__global__ void __launch_bounds__(kBlock) k_density(const float* __restrict__ pts, const uint32_t* __restrict__ perm,
+                                                    int64_t m, const float* __restrict__ bounds,
+                                                    uint32_t* __restrict__ grid) {
+  const int64_t i0 = (blockIdx.x * (int64_t)kBlock + threadIdx.x) * kDensityRun;
+  if (i0 >= m) return;
+  int cur = -1;
+  uint32_t run = 0;
+  const int64_t i1 = i0 + kDensityRun < m ? i0 + kDensityRun : m;
+  for (int64_t i = i0; i < i1; ++i) {
+    const float* p = pts + 3 * (int64_t)perm[i];
+    const int c = density_cell(p[0], p[1], p[2], bounds);
+    if (c == cur) {
+      ++run;
+    } else {
+      if (run) atomicAdd(grid + cur, run);
+      cur = c;
+      run = 1;
+    }
+  }
+  if (run) atomicAdd(grid + cur, run);
+}
+
 // ------------------------------------------------------------------ pinhole rays
 
 __global__ void __launch_bounds__(kBlock) k_pinhole(CameraFrame cf, int W, int H, float* __restrict__ origins,
@@ -1529,6 +1555,8 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
     put(&b->cut, 2 * (int64_t)kCutCap);
     put(&b->n_cut, 1);
     put(&b->depth, 2);
+    put(&b->density, kDensityCells);
+    put(&b->dbox, 6);
   };
   size_t total = 0;
   layout([&](auto** p, int64_t count) {
@@ -1580,6 +1608,13 @@ grtx_status build_bvh(const grtx_gaussians* g, grtx_bvh_kind kind, float alpha_m
   hipLaunchKernelGGL(k_morton, dim3(grid_for(m)), dim3(kBlock), 0, s, points, m, bounds, b->codes, b->perm);
   GRTX_LAUNCH_CHECK();
   GRTX_TRY(radix_sort(b->codes, b->perm, tkeys, tvals, m, sc, s));
+  // leaves per cell of the density grid, over the leaf centres' bounds (in sorted order, so
+  // that a thread's leaves mostly share a cell)
+  GRTX_HIP(hipMemcpyAsync(b->dbox, bounds, 6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(kDensityCells)), dim3(kBlock), 0, s, b->density, (int64_t)kDensityCells,
+                     0u);
+  hipLaunchKernelGGL(k_density, dim3(grid_for((m + kDensityRun - 1) / kDensityRun)), dim3(kBlock), 0, s, points,
+                     b->perm, m, bounds, b->density);
   if (proxy) {
     hipLaunchKernelGGL(k_proxy_leaves, dim3(grid_for(m)), dim3(kBlock), 0, s, b->perm, m, ttmp, tbox, b->tris,
                        b->boxes);

@@ -51,6 +51,20 @@ constexpr uint32_t kNoParent = 0xFFFFFFFFu;
 // most max(1, leaves / kCutDiv) leaves, at most kCutCap of them.
 constexpr int64_t kCutDiv = 2048;
 constexpr int kCutCap = 16384;
+// Density grid kept for ordering rays that form no image: leaves per cell of a
+// kDensityRes^3 grid over the leaf centres' bounds (`dbox`: lo xyz, hi xyz).
+constexpr int kDensityRes = 64;
+constexpr int kDensityCells = kDensityRes * kDensityRes * kDensityRes;
+__device__ __forceinline__ int density_axis(float p, float lo, float hi) {
+  const float e = hi - lo;
+  const int c = e > 0.f ? (int)((p - lo) / e * (float)kDensityRes) : 0;
+  return c < 0 ? 0 : c >= kDensityRes ? kDensityRes - 1 : c;
+}
+// Cell of point (x, y, z) in the grid over box (lo xyz, hi xyz); points outside are clamped.
+__device__ __forceinline__ int density_cell(float x, float y, float z, const float* box) {
+  return density_axis(x, box[0], box[3]) +
+         kDensityRes * (density_axis(y, box[1], box[4]) + kDensityRes * density_axis(z, box[2], box[5]));
+}
 constexpr uint32_t kNoChild = 0xFFFFFFFFu;
 // Per-ray capacities of the checkpoint (deferred node) and eviction lists of the serving
 // kernel's pool (the trace's defaults live with the trace kernel): 2048/512 served the
@@ -143,6 +157,8 @@ struct Bvh {
   float4* cut = nullptr;     // [kCutCap][2]: subtree boxes (lo, leaf count) (hi, 0), see k_cut_write
   uint32_t* n_cut = nullptr; // device [1]: entries of `cut` (may exceed kCutCap; read the minimum)
   uint32_t* depth = nullptr; // device [2]: tree depth in internal nodes, 1 if restructured
+  uint32_t* density = nullptr;  // [kDensityCells] leaves per grid cell
+  float* dbox = nullptr;        // device [6]: the grid's box
   const float* opacities = nullptr; // borrowed
   const float* sh = nullptr;        // borrowed
   hipStream_t build_stream = nullptr;
@@ -213,6 +229,8 @@ struct TraceScene {
   int64_t n_leaves;
   const float4* cut = nullptr;      // subtree cut for tile cost estimates, or null
   const uint32_t* n_cut = nullptr;
+  const uint32_t* density = nullptr;  // density grid for ray order estimates, or null
+  const float* dbox = nullptr;
 };
 grtx_status launch_trace(const TraceScene& sc, const grtx_rays* r, const grtx_trace_params* p,
                          const grtx_trace_outputs* o, hipStream_t s);

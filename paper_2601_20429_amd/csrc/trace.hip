@@ -149,6 +149,7 @@ struct TraceArgs {
   unsigned int* counter;  // kChunks work counters
   int64_t chunk_len;      // work items per chunk (a multiple of 64)
   const uint32_t* tile_order;  // processing order of the 8x8 tiles, or null (row-major)
+  const uint32_t* ray_order;   // processing order of rays that form no image, or null
   ServeHost* sv_host;          // serving kernel: the work queue (host and device sides)
   ServeDev* sv_dev;
   uint64_t sv_poll_ticks;      // wall-clock ticks between reads of the host's count
@@ -764,7 +765,7 @@ __global__ void __launch_bounds__(kTraceBlock)
               int64_t px = tx * 8 + (within & 7), py = ty * 8 + (within >> 3);
               if (px < A.image_w && py < A.image_h) r = (int)(py * A.image_w + px);
             } else {
-              r = (int)w;
+              r = A.ray_order ? (int)A.ray_order[w] : (int)w;
             }
           }
           if (r >= 0) {
@@ -1273,6 +1274,70 @@ __global__ void __launch_bounds__(256) k_tile_order(const uint32_t* __restrict__
 }
 
 // Outputs of rays that meet nothing (a structure without leaves).
+// Order of rays that form no image: the few rays that start where the leaves are densest
+// run longest (one that starts inside a dense cluster enters the box of every Gaussian
+// around its origin), and started late they set the end of the launch. Each ray gets a
+// bucket of the density at its origin (quarter octaves of the leaf count of its grid cell;
+// 0 outside the grid or in an empty cell); the top buckets that together hold at most
+// kHeavyFrac of the rays go first, and every other ray keeps the caller's order after them.
+// (Ordering all rays by cost was slower than the caller's order: the heaviest then run
+// together and their waves diverge the most.)
+constexpr int kOrderBuckets = 128;
+constexpr float kHeavyFrac = 0.02f;
+constexpr int64_t kOrderMinRays = 65536;
+
+__global__ void k_zero_u32(uint32_t* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+__global__ void __launch_bounds__(256) k_ray_bucket(const float* __restrict__ ro, int64_t R, const float* __restrict__ box,
+                                                    const uint32_t* __restrict__ density, uint32_t* __restrict__ bucket,
+                                                    uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kOrderBuckets];
+  for (int i = threadIdx.x; i < kOrderBuckets; i += 256) h[i] = 0u;
+  __syncthreads();
+  const int64_t r = blockIdx.x * (int64_t)256 + threadIdx.x;
+  if (r < R) {
+    const float x = ro[3 * r], y = ro[3 * r + 1], z = ro[3 * r + 2];
+    const bool inside = x >= box[0] && y >= box[1] && z >= box[2] && x <= box[3] && y <= box[4] && z <= box[5];
+    const uint32_t d = inside ? density[density_cell(x, y, z, box)] : 0u;
+    const int q = d == 0u ? 0 : 1 + (int)(4.f * log2f((float)d));
+    const uint32_t bk = (uint32_t)(q < kOrderBuckets ? q : kOrderBuckets - 1);
+    bucket[r] = bk;
+    atomicAdd(&h[bk], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kOrderBuckets; i += 256)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+__global__ void k_ray_split(const uint32_t* __restrict__ hist, int64_t R, uint32_t* __restrict__ thr) {
+  if (threadIdx.x != 0) return;
+  const uint64_t cap = (uint64_t)(kHeavyFrac * (float)R);
+  uint64_t acc = 0;
+  uint32_t t = kOrderBuckets;  // none
+  for (int b = kOrderBuckets - 1; b >= 1; --b) {
+    if (acc + hist[b] > cap) break;
+    acc += hist[b];
+    t = (uint32_t)b;
+  }
+  *thr = t;
+}
+
+__global__ void __launch_bounds__(256) k_ray_flags(const uint32_t* __restrict__ bucket, int64_t R,
+                                                   const uint32_t* __restrict__ thr, uint32_t* __restrict__ flag) {
+  const int64_t r = blockIdx.x * (int64_t)256 + threadIdx.x;
+  if (r < R) flag[r] = bucket[r] >= *thr ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(256) k_ray_order(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ pos,
+                                                   int64_t R, uint32_t* __restrict__ order) {
+  const int64_t r = blockIdx.x * (int64_t)256 + threadIdx.x;
+  if (r >= R) return;
+  const uint32_t heavy = pos[R - 1] + flag[R - 1];
+  order[flag[r] ? pos[r] : heavy + (uint32_t)r - pos[r]] = (uint32_t)r;
+}
+
 __global__ void __launch_bounds__(256) k_fill_background(float* rgb, float* depth, float* opac, uint32_t* stats,
                                                          int32_t* hit_counts, const float* tfar,
                                                          const float* trans, int64_t n, float b0, float b1,
@@ -1474,7 +1539,7 @@ int64_t trace_pool_bytes(int K, int cap_d, int cap_e) {
 grtx_status trace(const Bvh* b, const grtx_rays* r, const grtx_trace_params* p, const grtx_trace_outputs* o,
                   hipStream_t s) {
   TraceScene sc{b->nodes, b->inst, b->tris, b->sh, b->sh_degree, b->roots, nullptr, b->kind, b->n_leaves, b->cut,
-                b->n_cut};
+                b->n_cut, b->density, b->dbox};
   return launch_trace(sc, r, p, o, s);
 }
 
@@ -1677,6 +1742,22 @@ grtx_status launch_trace_in(const TraceScene& b, const grtx_rays* r, const grtx_
       hipLaunchKernelGGL(k_tile_order, dim3(g), dim3(256), 0, s, base, flag, pos, nt, order);
       a.tile_order = order;
     }
+  }
+  if (a.image_w == 0 && !noalloc && b.density && R >= kOrderMinRays && R < (int64_t)0xFFFFFFFF) {
+    // heaviest rays first (see k_ray_bucket)
+    uint32_t* buf = nullptr;
+    GRTX_TRY(order_scratch->get(&buf, 4 * (size_t)R + kOrderBuckets + 1));
+    uint32_t *bucket = buf, *flag = buf + R, *pos = buf + 2 * R, *order = buf + 3 * R;
+    uint32_t *hist = buf + 4 * R, *thr = hist + kOrderBuckets;
+    const unsigned g = (unsigned)((R + 255) / 256);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, s, hist, kOrderBuckets);
+    hipLaunchKernelGGL(k_ray_bucket, dim3(g), dim3(256), 0, s, r->origins, R, b.dbox, b.density, bucket, hist);
+    hipLaunchKernelGGL(k_ray_split, dim3(1), dim3(64), 0, s, hist, R, thr);
+    hipLaunchKernelGGL(k_ray_flags, dim3(g), dim3(256), 0, s, bucket, R, thr, flag);
+    GRTX_TRY(exclusive_scan_u32(flag, pos, R, s));
+    hipLaunchKernelGGL(k_ray_order, dim3(g), dim3(256), 0, s, flag, pos, R, order);
+    GRTX_LAUNCH_CHECK();
+    a.ray_order = order;
   }
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, pool->counter);
   return leaf == kLeafTri ? launch_k<kLeafTri>(K, a, blocks, s)
