@@ -47,16 +47,18 @@
 namespace grtx {
 namespace {
 
-#ifndef GRTX_REFILL_THRESHOLD
-#define GRTX_REFILL_THRESHOLD 32
-#endif
 // Waves per SIMD the trace kernel is register-budgeted for up to k = 32 (at most 170
 // VGPRs): three, which k <= 32 reach with a few dozen bytes of scratch per lane on cold
 // paths; k = 64 is held to two (256 VGPRs).
 #ifndef GRTX_MIN_WAVES
 #define GRTX_MIN_WAVES 3
 #endif
-constexpr int kRefillThreshold = GRTX_REFILL_THRESHOLD;  // idle lanes that end a traversal burst
+// Idle or finished lanes that end a traversal burst for a refill: 32 for structures of up
+// to a million leaves, 16 above (on the 3M-Gaussian workload 16 was 5% faster on its
+// incoherent rays than 32, and 12 or 8 no better; on a 100k-Gaussian frame 32 is 1% faster
+// than 16).
+constexpr int kRefillSmall = 32;
+constexpr int kRefillLarge = 16;
 // Deferred-node list appends gather in LDS and go out to the lane's HBM block kStage
 // entries at a time (one contiguous write of kStage x 8 B instead of kStage scattered
 // 8-B writes from the wave). List capacities are rounded up to a multiple of kStage.
@@ -150,6 +152,7 @@ struct TraceArgs {
   int64_t chunk_len;      // work items per chunk (a multiple of 64)
   const uint32_t* tile_order;  // processing order of the 8x8 tiles, or null (row-major)
   const uint32_t* ray_order;   // processing order of rays that form no image, or null
+  int refill;                  // idle lanes that end a traversal burst
   ServeHost* sv_host;          // serving kernel: the work queue (host and device sides)
   ServeDev* sv_dev;
   uint64_t sv_poll_ticks;      // wall-clock ticks between reads of the host's count
@@ -815,7 +818,7 @@ __global__ void __launch_bounds__(kTraceBlock)
       const uint64_t trav = __ballot(state == kTrav);
       if (!trav) break;
       const uint64_t waiting = __ballot(state == kEnd) | (exhausted || nowork ? 0ull : __ballot(state == kIdle));
-      if (__popcll(waiting) >= kRefillThreshold) break;
+      if (__popcll(waiting) >= A.refill) break;
       if ((++room_tick & (kRoomEvery - 1)) == 0 && state == kTrav && ckpt) make_room();
       const uint64_t tmax = kb[K - 1];
       const float tmax_t = key_t(tmax);
@@ -1480,6 +1483,7 @@ grtx_status launch_serve(const ServeLaunch& L, hipStream_t s) {
   a.sv_dev = L.dev;
   a.sv_poll_ticks = L.poll_ticks;
   a.sv_idle_ticks = L.idle_ticks;
+  a.refill = L.scene.n_leaves > kLargeScene ? kRefillLarge : kRefillSmall;
   hipLaunchKernelGGL(k_serve_reopen, dim3(1), dim3(64), 0, s, L.dev);
   switch (K) {
     case 4: hipLaunchKernelGGL((k_trace<4, kLeafSphere, false, true>), dim3(blocks), dim3(kTraceBlock), 0, s, a); break;
@@ -1707,6 +1711,7 @@ grtx_status launch_trace_in(const TraceScene& b, const grtx_rays* r, const grtx_
   a.rows_per_wave = rows;
   a.cap_d = cap_d;
   a.cap_e = cap_e;
+  a.refill = b.n_leaves > kLargeScene ? kRefillLarge : kRefillSmall;
   a.chunk_len = ((a.n_work + 64 * kChunks - 1) / (64 * kChunks)) * 64;
   uint32_t* order_buf = nullptr;
   // (the allocation-free path keeps the tiles in row-major order: no scratch, same results)
