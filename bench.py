@@ -444,8 +444,8 @@ def profile_fields(path):
 
 def measured_traffic(args):
     """HBM bytes per launch of the timed trace kernel from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration, mean over the step's
-    two launches), or None when that summary was taken on other kernel sources or another
+    (FETCH_SIZE + WRITE_SIZE of the step's one launch, scaled by the copy-kernel
+    calibration), or None when that summary was taken on other kernel sources or another
     launch configuration."""
     if args.k != 16 or args.mode != "checkpoint":
         return None
@@ -459,8 +459,9 @@ def measured_traffic(args):
 
 
 class Workload3M:
-    """The 3M-Gaussian workload, resident on the GPU: scene parameters, the 2M incoherent
-    rays and output buffers for both ray sets."""
+    """The 3M-Gaussian workload, resident on the GPU: scene parameters, one ray buffer that
+    holds the 2M incoherent rays followed by the 1920x1080 frame's rays (written by the
+    step's ray generation), and one output buffer."""
 
     def __init__(self, dev):
         import numpy as np
@@ -473,39 +474,48 @@ class Workload3M:
         self.st = grtx.SceneTensors.from_scene(self.scene, dev)
         self.cam = inputs.orbit_camera(cfg["width"], cfg["height"])
         io, id_ = inputs.incoherent_rays(cfg["incoherent_seed"], cfg["incoherent"])
-        self.io, self.id = torch.from_numpy(io).to(dev), torch.from_numpy(id_).to(dev)
         self.n_prim, self.n_inc = self.cam.n_rays, cfg["incoherent"]
         self.rays = self.n_prim + self.n_inc
-        mk = lambda R: dict(rgb=torch.empty((R, 3), dtype=torch.float32, device=dev),
-                            depth=torch.empty(R, dtype=torch.float32, device=dev),
-                            opacity=torch.empty(R, dtype=torch.float32, device=dev))
-        self.out_p, self.out_i = mk(self.n_prim), mk(self.n_inc)
+        self.o = torch.empty((self.rays, 3), dtype=torch.float32, device=dev)
+        self.d = torch.empty((self.rays, 3), dtype=torch.float32, device=dev)
+        self.o[:self.n_inc] = torch.from_numpy(io)
+        self.d[:self.n_inc] = torch.from_numpy(id_)
+        self.io, self.id = self.o[:self.n_inc], self.d[:self.n_inc]
+        self.po, self.pd = self.o[self.n_inc:], self.d[self.n_inc:]
         self.dev = dev
+        self.out = self.outputs(self.rays)
+
+    def outputs(self, R):
+        import torch
+        return dict(rgb=torch.empty((R, 3), dtype=torch.float32, device=self.dev),
+                    depth=torch.empty(R, dtype=torch.float32, device=self.dev),
+                    opacity=torch.empty(R, dtype=torch.float32, device=self.dev))
+
+    def trace_kw(self, k, mode):
+        return dict(k=k, T_min=self.cfg["T_min"], mode=mode, image_width=self.cam.width, image_begin=self.n_inc)
 
     def step(self, k, mode, events=None):
-        """One step: raygen + build + trace of both ray sets; with `events` (a list), HIP
-        events on the launch stream bracket each trace call."""
+        """One step: raygen + build + one trace launch over both ray sets (the incoherent
+        rays first, then the frame's 8x8 tiles); with `events` (a list), HIP events on the
+        launch stream bracket the trace call."""
         import torch
 
         from paper_2601_20429_amd import grtx
         stream = torch.cuda.current_stream()
-        po, pd = grtx.pinhole_rays(self.cam, device=self.dev)
+        grtx.pinhole_rays(self.cam, out=(self.po, self.pd))
         bvh = grtx.build(self.st, alpha_min=self.amin)
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)] if events is not None else None
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)] if events is not None else None
         if ev:
             ev[0].record(stream)
-        grtx.trace(bvh, po, pd, k=k, T_min=self.cfg["T_min"], mode=mode, image_width=self.cam.width, out=self.out_p)
+        grtx.trace(bvh, self.o, self.d, out=self.out, **self.trace_kw(k, mode))
         if ev:
             ev[1].record(stream)
-        grtx.trace(bvh, self.io, self.id, k=k, T_min=self.cfg["T_min"], mode=mode, out=self.out_i)
-        if ev:
-            ev[2].record(stream)
             events.append(ev)
         return bvh
 
     def timed(self, k, mode, steps, warmup):
-        """Step time (ms, host clock over `steps` synchronised steps) and the mean launch
-        time (ms, HIP events) of the primary and incoherent traces."""
+        """Step time (ms, host clock over `steps` synchronised steps) and the mean duration
+        (ms, HIP events) of the step's trace launch."""
         import numpy as np
         import torch
         keep = [self.step(k, mode) for _ in range(warmup)]
@@ -517,42 +527,60 @@ class Workload3M:
             keep.append(self.step(k, mode, ev))
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
-        prim = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
-        inc = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+        trace = float(np.mean([a.elapsed_time(b) for a, b in ev]))
         keep.clear()
-        return ms, prim, inc
+        return ms, trace
 
-    def counters(self, k, mode):
-        """Summed per-ray counters of both ray sets (deterministic: an untimed run with the
-        counters on sees exactly the timed work)."""
+    def alone(self, k, mode, reps=3):
+        """Launch time (ms, HIP events) of each ray set traced on its own (a diagnostic:
+        the step traces both in one launch)."""
         import torch
 
         from paper_2601_20429_amd import grtx
-        po, pd = grtx.pinhole_rays(self.cam, device=self.dev)
+        stream = torch.cuda.current_stream()
+        grtx.pinhole_rays(self.cam, out=(self.po, self.pd))
         bvh = grtx.build(self.st, alpha_min=self.amin)
-        cp = stat_sums(grtx.trace(bvh, po, pd, k=k, T_min=self.cfg["T_min"], mode=mode,
-                                  image_width=self.cam.width, stats=True))
-        ci = stat_sums(grtx.trace(bvh, self.io, self.id, k=k, T_min=self.cfg["T_min"], mode=mode, stats=True))
+        op, oi = self.outputs(self.n_prim), self.outputs(self.n_inc)
+        kw = dict(k=k, T_min=self.cfg["T_min"], mode=mode)
+        for _ in range(2):
+            grtx.trace(bvh, self.po, self.pd, image_width=self.cam.width, out=op, **kw)
+            grtx.trace(bvh, self.io, self.id, out=oi, **kw)
+        tp = time_launch(lambda: grtx.trace(bvh, self.po, self.pd, image_width=self.cam.width, out=op, **kw),
+                         stream, reps)
+        ti = time_launch(lambda: grtx.trace(bvh, self.io, self.id, out=oi, **kw), stream, reps)
+        return tp, ti
+
+    def counters(self, k, mode):
+        """Summed per-ray counters of each ray set in the step's launch (deterministic: an
+        untimed run with the counters on sees exactly the timed work)."""
+        import torch
+
+        from paper_2601_20429_amd import grtx
+        grtx.pinhole_rays(self.cam, out=(self.po, self.pd))
+        bvh = grtx.build(self.st, alpha_min=self.amin)
+        st = grtx.trace(bvh, self.o, self.d, stats=True, **self.trace_kw(k, mode))["stats"]
+        cp = stat_sums({"stats": st[self.n_inc:]})
+        ci = stat_sums({"stats": st[:self.n_inc]})
         torch.cuda.synchronize()
         info = bvh.info()
         return cp, ci, info
 
     def summary(self, k, mode, steps, warmup):
-        ms, tp, ti = self.timed(k, mode, steps, warmup)
+        ms, tt = self.timed(k, mode, steps, warmup)
+        tp, ti = self.alone(k, mode)
         cp, ci, info = self.counters(k, mode)
         bp = alg_bytes(cp, 3, self.n_prim)
         bi = alg_bytes(ci, 3, self.n_inc)
         return dict(k=k, mode="checkpoint" if mode == 0 else "restart", step_ms=ms,
                     mrays_s=self.rays / (ms * 1e-3) / 1e6,
-                    primary_trace_ms=tp, incoherent_trace_ms=ti,
-                    primary_mrays_s=self.n_prim / (tp * 1e-3) / 1e6,
-                    incoherent_mrays_s=self.n_inc / (ti * 1e-3) / 1e6,
+                    trace_ms=tt, trace_mrays_s=self.rays / (tt * 1e-3) / 1e6,
+                    primary_alone_ms=tp, incoherent_alone_ms=ti,
+                    primary_alone_mrays_s=self.n_prim / (tp * 1e-3) / 1e6,
+                    incoherent_alone_mrays_s=self.n_inc / (ti * 1e-3) / 1e6,
                     primary=per_ray(cp, self.n_prim), incoherent=per_ray(ci, self.n_inc),
                     nodes_per_ray=(cp["nodes"] + cp["leaves"] + ci["nodes"] + ci["leaves"]) / self.rays,
                     algorithmic_bytes_primary=bp, algorithmic_bytes_incoherent=bi,
-                    primary_algorithmic_GBs=bp / (tp * 1e-3) / 1e9,
-                    incoherent_algorithmic_GBs=bi / (ti * 1e-3) / 1e9,
-                    trace_algorithmic_GBs=(bp + bi) / ((tp + ti) * 1e-3) / 1e9,
+                    trace_algorithmic_GBs=(bp + bi) / (tt * 1e-3) / 1e9,
                     tree_depth=info["depth"], bvh_bytes=info["device_bytes"])
 
 
@@ -733,15 +761,15 @@ def main():
     head = work.summary(args.k, mode, args.steps, args.warmup)
     log("headline", json.dumps(head))
     extra = dict(headline=head)
-    # the dominant kernel: the trace, launched twice per step (primary frame, incoherent rays)
-    launch_ms = 0.5 * (head["primary_trace_ms"] + head["incoherent_trace_ms"])
-    launch_bytes = 0.5 * (head["algorithmic_bytes_primary"] + head["algorithmic_bytes_incoherent"])
+    # the dominant kernel: the trace, one launch per step over both ray sets
+    launch_ms = head["trace_ms"]
+    launch_bytes = head["algorithmic_bytes_primary"] + head["algorithmic_bytes_incoherent"]
     achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
     traffic = measured_traffic(args)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": f"k_trace<{kernel_k(args.k)}, 0, false>",
-                "per_launch": "mean of the step's two launches (1920x1080 primary frame, 2M incoherent rays)",
+                "per_launch": "the step's one launch: 2M incoherent rays, then the 1920x1080 frame's 8x8 tiles",
                 "algorithmic_bytes_per_launch": launch_bytes, "launch_ms": launch_ms,
                 "hbm_measured_GBs": None if traffic is None else traffic / (launch_ms * 1e-3) / 1e9,
                 "hbm_measured_frac": None if traffic is None else traffic / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -755,16 +783,15 @@ def main():
         extra["k32"] = k32 = work.summary(32, mode, max(3, args.steps // 2), 1)
         log("k32", json.dumps(k32))
         bvh3 = grtx.build(work.st, alpha_min=work.amin)
-        po, pd = grtx.pinhole_rays(work.cam, device=dev)
+        grtx.pinhole_rays(work.cam, out=(work.po, work.pd))
         extra["single_round"] = run_single_round(
-            bvh3, [("primary", po, pd, work.cam.width), ("incoherent", work.io, work.id, 0)], work.cfg["T_min"],
-            stream, caps=(2048,))
+            bvh3, [("primary", work.po, work.pd, work.cam.width), ("incoherent", work.io, work.id, 0)],
+            work.cfg["T_min"], stream, caps=(2048,))
         log("single round", json.dumps(extra["single_round"]))
-        del bvh3, po, pd
+        del bvh3
         if mode == grtx.CHECKPOINT:
             extra["checkpoint_speedup_step"] = cmp["step_ms"] / head["step_ms"]
-            extra["checkpoint_speedup_trace"] = (cmp["primary_trace_ms"] + cmp["incoherent_trace_ms"]) / (
-                head["primary_trace_ms"] + head["incoherent_trace_ms"])
+            extra["checkpoint_speedup_trace"] = cmp["trace_ms"] / head["trace_ms"]
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -807,7 +834,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": inputs.SCENE3M["name"], "gaussians": 3_000_000, "primary_rays": 1920 * 1080,
                    "incoherent_rays": 2_000_000, "k": args.k, "mode": args.mode, "sh_degree": 3,
-                   "bvh": "sphere-instance LBVH", "step": "raygen + LBVH build + trace of both ray sets"},
+                   "bvh": "sphere-instance LBVH", "step": "raygen + LBVH build + one trace launch over both ray sets"},
         "nodes_per_ray": head["nodes_per_ray"],
         "roofline": roofline,
         "cpu_baseline": cpu,

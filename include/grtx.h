@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define GRTX_VERSION 4
+#define GRTX_VERSION 5
 
 typedef enum grtx_status {
   GRTX_OK = 0,
@@ -139,9 +139,13 @@ typedef struct grtx_bvh_info {
 } grtx_bvh_info;
 
 /* Rays: device origins [count,3] and unit-length directions [count,3], float32.
- * t_near >= 0: hits need an entry distance > t_near. image_width > 0 declares the rays
- * to be a row-major image of that width; the kernel then schedules them in 8x8 pixel
- * tiles (results are unaffected).
+ * t_near >= 0: hits need an entry distance > t_near. image_width > 0 declares rays
+ * image_begin..count-1 to be a row-major image of that width (image_begin = 0: all of
+ * them); the kernel then schedules those in 8x8 pixel tiles, after the rays before
+ * image_begin, which form no image. One launch thus traces an image together with a
+ * set of other rays, and the image's cheaper tiles fill the end of the launch. Results
+ * are unaffected. image_begin must lie in 0..count, and be 0 when image_width is 0; a
+ * trace launch takes at most 2^31-1 rays, counting an image's 8x8 tiles whole.
  * Optional, for ray paths traced in segments (secondary rays, below):
  *   t_far [count] float32 (NULL = unbounded): the ray ends on a surface at that distance;
  *     hits need a key distance < t_far, and a bounded ray (t_far < +inf) gets no
@@ -167,6 +171,7 @@ typedef struct grtx_rays {
   const float* next_dirs;
   const float* path;
   const int32_t* kind;
+  int64_t image_begin;
 } grtx_rays;
 
 /* k: k-buffer size, 1..64 (Sec. III-A). T_min: a ray stops after the hit that brings

@@ -148,6 +148,8 @@ static grtx_status check_trace_args(const char* fn, const grtx_bvh* bvh, const g
             "%s: list capacities must be 0..2^20", fn);
   CHECK_ARG(rays->t_near >= 0.f && std::isfinite(rays->t_near), "%s: t_near must be finite and >= 0", fn);
   CHECK_ARG(rays->image_width >= 0, "%s: negative image width", fn);
+  CHECK_ARG(rays->image_begin >= 0 && rays->image_begin <= rays->count, "%s: image_begin must be 0..count", fn);
+  CHECK_ARG(rays->image_begin == 0 || rays->image_width > 0, "%s: image_begin given without image_width", fn);
   {
     const int nc = !!rays->next_origins + !!rays->next_dirs + !!rays->path + !!rays->kind;
     CHECK_ARG(nc == 0 || nc == 4, "%s: give all four continuation arrays or none", fn);

@@ -129,6 +129,7 @@ struct TraceArgs {
   const int32_t* ray_kind;
   int64_t n_rays;
   int64_t n_work;
+  int64_t n_free;             // rays 0..n_free-1 form no image; the image's rays follow
   int image_w;
   int image_h;
   int tiles_x;
@@ -761,14 +762,15 @@ __global__ void __launch_bounds__(kTraceBlock)
           int64_t w = (int64_t)chunk * A.chunk_len + base + rank;
           int r = -1;
           if (rank < avail && w < A.n_work) {
-            if (A.image_w > 0) {
-              int64_t tile = A.tile_order ? (int64_t)A.tile_order[w >> 6] : w >> 6;
-              int within = (int)(w & 63);
+            if (w < A.n_free) {
+              r = A.ray_order ? (int)A.ray_order[w] : (int)w;
+            } else {
+              const int64_t wi = w - A.n_free;
+              int64_t tile = A.tile_order ? (int64_t)A.tile_order[wi >> 6] : wi >> 6;
+              int within = (int)(wi & 63);
               int64_t ty = tile / A.tiles_x, tx = tile - ty * A.tiles_x;
               int64_t px = tx * 8 + (within & 7), py = ty * 8 + (within >> 3);
-              if (px < A.image_w && py < A.image_h) r = (int)(py * A.image_w + px);
-            } else {
-              r = A.ray_order ? (int)A.ray_order[w] : (int)w;
+              if (px < A.image_w && py < A.image_h) r = (int)(A.n_free + py * A.image_w + px);
             }
           }
           if (r >= 0) {
@@ -1681,17 +1683,26 @@ grtx_status launch_trace_in(const TraceScene& b, const grtx_rays* r, const grtx_
   a.ray_kind = r->kind;
   a.n_rays = R;
   a.t_near = r->t_near;
-  if (r->image_width > 0 && R % r->image_width == 0) {
+  // rays 0..image_begin-1 form no image and are taken first; the image's rays follow
+  const int64_t n_img = R - r->image_begin;
+  if (r->image_width > 0 && r->image_begin >= 0 && n_img > 0 && n_img % r->image_width == 0) {
+    a.n_free = r->image_begin;
     a.image_w = r->image_width;
-    a.image_h = (int)(R / r->image_width);
+    a.image_h = (int)(n_img / r->image_width);
     a.tiles_x = (a.image_w + 7) / 8;
     int64_t tiles_y = (a.image_h + 7) / 8;
-    a.n_work = (int64_t)a.tiles_x * tiles_y * 64;
+    a.n_work = a.n_free + (int64_t)a.tiles_x * tiles_y * 64;
   } else {
+    a.n_free = R;
     a.image_w = 0;
     a.image_h = 0;
     a.tiles_x = 0;
     a.n_work = R;
+  }
+  if (a.n_work > (int64_t)INT32_MAX) {
+    set_error("grtx_trace: %lld rays (%lld work items with the image's 8x8 tiles) exceed one launch's 2^31-1",
+              (long long)R, (long long)a.n_work);
+    return GRTX_ERR_INVALID_ARG;
   }
   a.k = p->k;
   a.T_min = p->T_min;
@@ -1717,10 +1728,11 @@ grtx_status launch_trace_in(const TraceScene& b, const grtx_rays* r, const grtx_
   // (the allocation-free path keeps the tiles in row-major order: no scratch, same results)
   std::unique_ptr<Scratch> order_scratch;
   if (!noalloc) order_scratch.reset(new Scratch(s));
+  const int64_t F = a.n_free;
   if (a.image_w > 0 && !noalloc) {
     // Tiles heaviest first, so that the longest rays do not start last: by estimated cost
     // where the structure carries a subtree cut, centre-out within equal estimates.
-    const int64_t nt = a.n_work / 64;
+    const int64_t nt = (a.n_work - F) / 64;
     const uint32_t* base = nullptr;
     GRTX_TRY(centre_out_order(device, a.tiles_x, (int)(nt / a.tiles_x), &base));
     // scratch: estimate keys (8 B) and order (4 B) per tile, then three more words per tile
@@ -1730,7 +1742,8 @@ grtx_status launch_trace_in(const TraceScene& b, const grtx_rays* r, const grtx_
       uint64_t* keys = reinterpret_cast<uint64_t*>(order_buf);
       uint32_t* est_order = order_buf + 2 * nt;
       hipLaunchKernelGGL(k_tile_estimate, dim3((unsigned)((nt + kEstTiles - 1) / kEstTiles)), dim3(256), 0, s, b.cut,
-                         b.n_cut, r->origins, r->dirs, a.image_w, a.image_h, a.tiles_x, nt, base, keys, est_order);
+                         b.n_cut, r->origins + 3 * F, r->dirs + 3 * F, a.image_w, a.image_h, a.tiles_x, nt, base,
+                         keys, est_order);
       GRTX_TRY(sort_by_key(keys, est_order, nt, 8, s));
       base = est_order;
     }
@@ -1741,26 +1754,26 @@ grtx_status launch_trace_in(const TraceScene& b, const grtx_rays* r, const grtx_
       uint32_t* pos = flag + nt;
       uint32_t* order = pos + nt;
       const unsigned g = (unsigned)((nt + 255) / 256);
-      hipLaunchKernelGGL(k_tile_heavy, dim3(g), dim3(256), 0, s, r->kind, base, a.image_w, a.image_h, a.tiles_x, nt,
-                         flag);
+      hipLaunchKernelGGL(k_tile_heavy, dim3(g), dim3(256), 0, s, r->kind + F, base, a.image_w, a.image_h, a.tiles_x,
+                         nt, flag);
       GRTX_TRY(exclusive_scan_u32(flag, pos, nt, s));
       hipLaunchKernelGGL(k_tile_order, dim3(g), dim3(256), 0, s, base, flag, pos, nt, order);
       a.tile_order = order;
     }
   }
-  if (a.image_w == 0 && !noalloc && b.density && R >= kOrderMinRays && R < (int64_t)0xFFFFFFFF) {
+  if (!noalloc && b.density && F >= kOrderMinRays) {
     // heaviest rays first (see k_ray_bucket)
     uint32_t* buf = nullptr;
-    GRTX_TRY(order_scratch->get(&buf, 4 * (size_t)R + kOrderBuckets + 1));
-    uint32_t *bucket = buf, *flag = buf + R, *pos = buf + 2 * R, *order = buf + 3 * R;
-    uint32_t *hist = buf + 4 * R, *thr = hist + kOrderBuckets;
-    const unsigned g = (unsigned)((R + 255) / 256);
+    GRTX_TRY(order_scratch->get(&buf, 4 * (size_t)F + kOrderBuckets + 1));
+    uint32_t *bucket = buf, *flag = buf + F, *pos = buf + 2 * F, *order = buf + 3 * F;
+    uint32_t *hist = buf + 4 * F, *thr = hist + kOrderBuckets;
+    const unsigned g = (unsigned)((F + 255) / 256);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, s, hist, kOrderBuckets);
-    hipLaunchKernelGGL(k_ray_bucket, dim3(g), dim3(256), 0, s, r->origins, R, b.dbox, b.density, bucket, hist);
-    hipLaunchKernelGGL(k_ray_split, dim3(1), dim3(64), 0, s, hist, R, thr);
-    hipLaunchKernelGGL(k_ray_flags, dim3(g), dim3(256), 0, s, bucket, R, thr, flag);
-    GRTX_TRY(exclusive_scan_u32(flag, pos, R, s));
-    hipLaunchKernelGGL(k_ray_order, dim3(g), dim3(256), 0, s, flag, pos, R, order);
+    hipLaunchKernelGGL(k_ray_bucket, dim3(g), dim3(256), 0, s, r->origins, F, b.dbox, b.density, bucket, hist);
+    hipLaunchKernelGGL(k_ray_split, dim3(1), dim3(64), 0, s, hist, F, thr);
+    hipLaunchKernelGGL(k_ray_flags, dim3(g), dim3(256), 0, s, bucket, F, thr, flag);
+    GRTX_TRY(exclusive_scan_u32(flag, pos, F, s));
+    hipLaunchKernelGGL(k_ray_order, dim3(g), dim3(256), 0, s, flag, pos, F, order);
     GRTX_LAUNCH_CHECK();
     a.ray_order = order;
   }

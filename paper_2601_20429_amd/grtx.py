@@ -63,7 +63,8 @@ class _BvhInfo(C.Structure):
 class _Rays(C.Structure):
     _fields_ = [("origins", C.c_void_p), ("dirs", C.c_void_p), ("count", C.c_int64), ("t_near", C.c_float),
                 ("image_width", C.c_int32), ("t_far", C.c_void_p), ("transmittance", C.c_void_p),
-                ("next_origins", C.c_void_p), ("next_dirs", C.c_void_p), ("path", C.c_void_p), ("kind", C.c_void_p)]
+                ("next_origins", C.c_void_p), ("next_dirs", C.c_void_p), ("path", C.c_void_p), ("kind", C.c_void_p),
+                ("image_begin", C.c_int64)]
 
 
 class _Objects(C.Structure):
@@ -268,10 +269,18 @@ def build(scene: SceneTensors, kind: int = SPHERE_INSTANCE, alpha_min: float = 1
     return Bvh(h, scene, kind, alpha_min)
 
 
-def pinhole_rays(camera, device="cuda", stream=None):
+def pinhole_rays(camera, device="cuda", stream=None, out=None):
+    """Pinhole rays of `camera` in row-major pixel order: origins, unit directions [W*H,3]
+    float32; into `out` = (origins, dirs) when given (contiguous, float32)."""
     n = camera.width * camera.height
-    o = torch.empty((n, 3), dtype=torch.float32, device=device)
-    d = torch.empty((n, 3), dtype=torch.float32, device=device)
+    if out is not None:
+        o, d = out
+        for t in (o, d):
+            if t.shape != (n, 3) or t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError(f"pinhole_rays: out tensors must be contiguous float32 [{n},3]")
+    else:
+        o = torch.empty((n, 3), dtype=torch.float32, device=device)
+        d = torch.empty((n, 3), dtype=torch.float32, device=device)
     cam = _Camera((C.c_float * 3)(*camera.eye), (C.c_float * 3)(*camera.target), (C.c_float * 3)(*camera.up),
                   camera.fov_y_deg, camera.width, camera.height)
     _check(lib().grtx_pinhole_rays(C.byref(cam), _ptr(o), _ptr(d), _stream(stream)))
@@ -280,7 +289,7 @@ def pinhole_rays(camera, device="cuda", stream=None):
 
 def trace(bvh: Bvh, origins: torch.Tensor, dirs: torch.Tensor, k: int = 16, T_min: float = 1e-3,
           mode: int = CHECKPOINT, bg=(0.0, 0.0, 0.0), t_near: float = 0.0, image_width: int = 0,
-          stats: bool = False, hit_capacity: int = 0, defer_capacity: int = 0, evict_capacity: int = 0,
+          image_begin: int = 0, stats: bool = False, hit_capacity: int = 0, defer_capacity: int = 0, evict_capacity: int = 0,
           out=None, stream=None, t_far: torch.Tensor = None, transmittance: torch.Tensor = None,
           continuation: dict = None, collect_capacity: int = 0, _entry: str = "grtx_trace"):
     """Render rays; returns dict(rgb [R,3], depth [R], opacity [R], and optionally stats
@@ -288,6 +297,8 @@ def trace(bvh: Bvh, origins: torch.Tensor, dirs: torch.Tensor, k: int = 16, T_mi
     a surface; transmittance [R] is what each ray starts with (both optional float32).
     continuation: the dict of `object_rays` (next_o, next_d, path, kind); rays that reach
     their surface then go on along their continuation ray in the same launch.
+    image_width > 0: rays image_begin.. form a row-major image of that width, traced after
+    the rays before image_begin (scheduling only).
     mode SINGLE_ROUND collects up to `collect_capacity` hits per ray (0 = 2048), then sorts
     and blends them."""
     R = int(origins.shape[0])
@@ -304,6 +315,7 @@ def trace(bvh: Bvh, origins: torch.Tensor, dirs: torch.Tensor, k: int = 16, T_mi
     rays = _Rays(origins.data_ptr() if R else None, dirs.data_ptr() if R else None, R, t_near, image_width,
                  t_far.data_ptr() if t_far is not None and R else None,
                  transmittance.data_ptr() if transmittance is not None and R else None)
+    rays.image_begin = image_begin
     if continuation is not None and R:
         rays.next_origins = continuation["next_o"].data_ptr()
         rays.next_dirs = continuation["next_d"].data_ptr()

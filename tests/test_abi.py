@@ -29,7 +29,7 @@ def test_header_symbols_exported():
 
 def test_version_and_null_destroy():
     L = grtx.lib()
-    assert L.grtx_version() == 4
+    assert L.grtx_version() == 5
     assert L.grtx_bvh_destroy(None) == grtx.OK
 
 
@@ -73,6 +73,12 @@ def test_trace_rejects_bad_arguments():
     assert b"null" in L.grtx_last_error()
     assert L.grtx_trace_noalloc(fake, C.byref(rays), C.byref(prm), C.byref(out), None) == grtx.ERR_INVALID_ARG
     assert b"grtx_trace_noalloc: null" in L.grtx_last_error()
+    # the image part: image_begin in 0..count, and only with an image width
+    for width, begin in [(2, -1), (2, 5), (0, 2)]:
+        bad = grtx._Rays(fake, fake, 4, 0.0, width)
+        bad.image_begin = begin
+        assert L.grtx_trace(fake, C.byref(bad), C.byref(prm), C.byref(out), None) == grtx.ERR_INVALID_ARG
+        assert b"image_begin" in L.grtx_last_error()
     cam = grtx._Camera((C.c_float * 3)(0, -3, 0), (C.c_float * 3)(0, 0, 0), (C.c_float * 3)(0, 0, 1), 60.0, 0, 4)
     assert L.grtx_pinhole_rays(C.byref(cam), C.c_void_p(1), C.c_void_p(1), None) == grtx.ERR_INVALID_ARG
 

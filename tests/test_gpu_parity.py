@@ -574,18 +574,58 @@ def test_scene3m_full_size_sampled(k):
     ro, rd = oracle_rays(cam)
     io, id_ = inputs.incoherent_rays(cfg["incoherent_seed"], cfg["incoherent"])
     bvh = build(scene)
-    for label, o, d, width, seed in [("primary", ro, rd, cfg["width"], 7), ("incoherent", io, id_, 0, 8)]:
-        out = grtx.trace(bvh, dev(o), dev(d), k=k, T_min=T_MIN, image_width=width, hit_capacity=512, stats=True)
-        torch.cuda.synchronize()
-        assert bool(torch.isfinite(out["rgb"]).all())
-        assert int(out["stats"][:, grtx.STAT_ROUNDS].min()) >= 1  # every ray was finished
+    # one launch, as the benchmark's step traces them: the incoherent rays, then the image
+    n_inc = io.shape[0]
+    out = grtx.trace(bvh, dev(np.concatenate([io, ro])), dev(np.concatenate([id_, rd])), k=k, T_min=T_MIN,
+                     image_width=cfg["width"], image_begin=n_inc, hit_capacity=512, stats=True)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(out["rgb"]).all())
+    assert int(out["stats"][:, grtx.STAT_ROUNDS].min()) >= 1  # every ray was finished
+    for label, o, d, first, seed in [("primary", ro, rd, n_inc, 7), ("incoherent", io, id_, 0, 8)]:
         idx = inputs.ray_subsample(seed, o.shape[0], 192)
-        ti = torch.from_numpy(idx).cuda()
+        ti = torch.from_numpy(idx + first).cuda()
         sub = {name: v.index_select(0, ti).cpu().numpy() for name, v in out.items()}
         ref = oracle.render(scene, o[idx], d[idx], AMIN, T_MIN, cap=512)
         s = parity.compare_render(scene, o[idx], d[idx], sub, ref, AMIN, T_MIN, label=f"3M {label} k={k}")
         say(s)
-        del out
+    del out
+
+
+@pytest.mark.parametrize("width,height,n_free", [(160, 120, 70_000), (100, 37, 5_003), (64, 64, 0)])
+def test_image_after_free_rays_one_launch(width, height, n_free):
+    """Rays that form no image and an image traced in one launch (image_begin): each ray's
+    outputs, hit list and counters are bit-equal to those of its own set traced alone
+    (scheduling only; 70,000 free rays are enough for the density ordering, 5,003 are
+    not; a 100x37 image has ragged tiles), and sampled rays of both parts match the
+    oracle. With image_begin = count every ray is a free ray."""
+    say("image after free rays", width, height, n_free)
+    scene = inputs.cluster_scene(2, 100_000, 3)
+    cam = inputs.orbit_camera(width, height)
+    po, pd = oracle_rays(cam)
+    fo, fd = inputs.incoherent_rays(44, n_free) if n_free else (np.zeros((0, 3), np.float32),) * 2
+    bvh = build(scene)
+    ho, hd = np.concatenate([fo, po]), np.concatenate([fd, pd])
+    o, d = dev(ho), dev(hd)
+    kw = dict(k=16, T_min=T_MIN, hit_capacity=256, stats=True)
+    both = grtx.trace(bvh, o, d, image_width=width, image_begin=n_free, **kw)
+    img = grtx.trace(bvh, dev(po), dev(pd), image_width=width, **kw)
+    free = grtx.trace(bvh, dev(fo), dev(fd), **kw) if n_free else None
+    flat = grtx.trace(bvh, o, d, image_width=width, image_begin=o.shape[0], **kw)  # no image part
+    torch.cuda.synchronize()
+    for key in both:
+        assert torch.equal(both[key][n_free:], img[key]), key
+        assert torch.equal(flat[key], both[key]), key
+        if free is not None:
+            assert torch.equal(both[key][:n_free], free[key]), key
+    g = {key: v.cpu().numpy() for key, v in both.items()}
+    for first, n, seed in [(0, n_free, 3), (n_free, po.shape[0], 4)]:
+        if n == 0:
+            continue
+        idx = inputs.ray_subsample(seed, n, 256) + first
+        ref = oracle.render(scene, ho[idx], hd[idx], AMIN, T_MIN, cap=256)
+        sub = {key: v[idx] for key, v in g.items()}
+        say(parity.compare_render(scene, ho[idx], hd[idx], sub, ref, AMIN, T_MIN,
+                                  label=f"one launch {width}x{height}+{n_free}"))
 
 
 # ------------------------------------------------------------------------ proxy-mesh baseline

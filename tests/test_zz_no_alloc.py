@@ -1,6 +1,7 @@
 """The allocation-free trace entry point (grtx_trace_noalloc) against grtx_trace, through
-the C ABI: two calls in a row on the same device scratch, the second with fewer rays, each
-bit-identical to grtx_trace's outputs. Needs an MI355X."""
+the C ABI: three calls in a row on the same device scratch, each with fewer rays than the
+one before (the last traces free rays and an image in one launch), each bit-identical to
+grtx_trace's outputs. Needs an MI355X."""
 import sys
 
 import numpy as np
@@ -46,6 +47,20 @@ def test_noalloc_equals_trace_twice():
         torch.cuda.synchronize()
         for key in ["rgb", "depth", "opacity", "hit_ids", "hit_counts", "stats"]:
             assert torch.equal(got[key], ref[key]), (cam.width, key)
+    # a third call, smaller still: 1000 free rays and a 64x48 image in one launch
+    cam = inputs.orbit_camera(64, 48)
+    say("noalloc", "1000 free rays +", cam.width, cam.height)
+    po, pd = grtx.pinhole_rays(cam)
+    fo, fd = (torch.from_numpy(a).cuda() for a in inputs.incoherent_rays(5, 1000))
+    o, d = torch.cat([fo, po]), torch.cat([fd, pd])
+    R = int(o.shape[0])
+    ref = grtx.trace(bvh, o, d, k=16, T_min=1e-3, image_width=cam.width, image_begin=1000, stats=True,
+                     hit_capacity=256)
+    got = grtx.trace_noalloc(bvh, o, d, _outputs(R, 256), k=16, T_min=1e-3, image_width=cam.width,
+                             image_begin=1000)
+    torch.cuda.synchronize()
+    for key in ["rgb", "depth", "opacity", "hit_ids", "hit_counts", "stats"]:
+        assert torch.equal(got[key], ref[key]), ("one launch", key)
     # list capacities beyond the scratch are refused before any launch
     o, d = grtx.pinhole_rays(inputs.orbit_camera(8, 8))
     with pytest.raises(grtx.GrtxError) as e:
