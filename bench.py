@@ -565,9 +565,9 @@ class Workload3M:
         info = bvh.info()
         return cp, ci, info
 
-    def summary(self, k, mode, steps, warmup):
+    def summary(self, k, mode, steps, warmup, alone=True):
         ms, tt = self.timed(k, mode, steps, warmup)
-        tp, ti = self.alone(k, mode)
+        tp, ti = self.alone(k, mode) if alone else (None, None)
         cp, ci, info = self.counters(k, mode)
         bp = alg_bytes(cp, 3, self.n_prim)
         bi = alg_bytes(ci, 3, self.n_inc)
@@ -575,8 +575,8 @@ class Workload3M:
                     mrays_s=self.rays / (ms * 1e-3) / 1e6,
                     trace_ms=tt, trace_mrays_s=self.rays / (tt * 1e-3) / 1e6,
                     primary_alone_ms=tp, incoherent_alone_ms=ti,
-                    primary_alone_mrays_s=self.n_prim / (tp * 1e-3) / 1e6,
-                    incoherent_alone_mrays_s=self.n_inc / (ti * 1e-3) / 1e6,
+                    primary_alone_mrays_s=self.n_prim / (tp * 1e-3) / 1e6 if tp else None,
+                    incoherent_alone_mrays_s=self.n_inc / (ti * 1e-3) / 1e6 if ti else None,
                     primary=per_ray(cp, self.n_prim), incoherent=per_ray(ci, self.n_inc),
                     nodes_per_ray=(cp["nodes"] + cp["leaves"] + ci["nodes"] + ci["leaves"]) / self.rays,
                     algorithmic_bytes_primary=bp, algorithmic_bytes_incoherent=bi,
@@ -758,7 +758,8 @@ def main():
     work = Workload3M(dev)
     log(f"workload {work.cfg['name']}: {work.cfg['n']} Gaussians, {work.n_prim} + {work.n_inc} rays, k={args.k}, "
         f"mode={args.mode}")
-    head = work.summary(args.k, mode, args.steps, args.warmup)
+    # (profiler runs see only the step's launches: no separate launches of each ray set)
+    head = work.summary(args.k, mode, args.steps, args.warmup, alone=not args.headline_only)
     log("headline", json.dumps(head))
     extra = dict(headline=head)
     # the dominant kernel: the trace, one launch per step over both ray sets
