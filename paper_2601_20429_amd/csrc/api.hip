@@ -151,6 +151,13 @@ static grtx_status check_trace_args(const char* fn, const grtx_bvh* bvh, const g
   CHECK_ARG(rays->image_begin >= 0 && rays->image_begin <= rays->count, "%s: image_begin must be 0..count", fn);
   CHECK_ARG(rays->image_begin == 0 || rays->image_width > 0, "%s: image_begin given without image_width", fn);
   {
+    int64_t n_free = 0, image_h = 0;
+    const int64_t work = grtx::trace_work_items(rays, &n_free, &image_h);
+    CHECK_ARG(work <= grtx::kMaxTraceWork,
+              "%s: %lld rays make %lld work items (an image's 8x8 tiles count whole); one launch takes at most "
+              "2^31-1", fn, (long long)rays->count, (long long)work);
+  }
+  {
     const int nc = !!rays->next_origins + !!rays->next_dirs + !!rays->path + !!rays->kind;
     CHECK_ARG(nc == 0 || nc == 4, "%s: give all four continuation arrays or none", fn);
     CHECK_ARG(nc == 0 || (rays->t_far && rays->t_near == 0.f), "%s: continuation rays need t_far and t_near = 0",
@@ -188,7 +195,7 @@ grtx_status grtx_trace_backward(const grtx_bvh* bvh, const grtx_gaussians* g, co
   CHECK_ARG(bvh && g && rays && p && fwd && grads, "grtx_trace_backward: null argument");
   CHECK_ARG(g->count == bvh->impl.n_gauss && g->sh_degree == bvh->impl.sh_degree,
             "grtx_trace_backward: Gaussians differ from those the structure was built from");
-  CHECK_ARG(rays->count >= 0 && rays->count < ((int64_t)1 << 40), "grtx_trace_backward: bad ray count");
+  CHECK_ARG(rays->count >= 0 && rays->count <= grtx::kMaxTraceWork, "grtx_trace_backward: bad ray count");
   if (rays->count > 0 && g->count > 0) {
     CHECK_ARG(g->means && g->scales && g->quats && g->opacities && g->sh, "grtx_trace_backward: null Gaussian array");
     CHECK_ARG(rays->origins && rays->dirs, "grtx_trace_backward: null ray arrays");

@@ -13,6 +13,25 @@
 
 namespace grtx {
 
+// Work items of one trace launch: the rays before image_begin one each, then the image's
+// 8x8 tiles 64 each (the image being rays image_begin..count-1 in rows of image_width;
+// rays that do not divide into such rows are all taken one by one). The launch's work
+// counter and ray indices are 32-bit, so a launch takes at most 2^31-1 items.
+inline int64_t trace_work_items(const grtx_rays* r, int64_t* n_free, int64_t* image_h) {
+  const int64_t R = r->count;
+  const int64_t n_img = R - r->image_begin;
+  if (r->image_width > 0 && r->image_begin >= 0 && n_img > 0 && n_img % r->image_width == 0) {
+    *n_free = r->image_begin;
+    *image_h = n_img / r->image_width;
+    const int64_t tiles_x = ((int64_t)r->image_width + 7) / 8, tiles_y = (*image_h + 7) / 8;
+    return r->image_begin + tiles_x * tiles_y * 64;
+  }
+  *n_free = R;
+  *image_h = 0;
+  return R;
+}
+constexpr int64_t kMaxTraceWork = 0x7FFFFFFF;
+
 // ---------------------------------------------------------------------------------------
 // Device data layout
 // ---------------------------------------------------------------------------------------

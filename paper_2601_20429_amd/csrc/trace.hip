@@ -1684,26 +1684,15 @@ grtx_status launch_trace_in(const TraceScene& b, const grtx_rays* r, const grtx_
   a.n_rays = R;
   a.t_near = r->t_near;
   // rays 0..image_begin-1 form no image and are taken first; the image's rays follow
-  const int64_t n_img = R - r->image_begin;
-  if (r->image_width > 0 && r->image_begin >= 0 && n_img > 0 && n_img % r->image_width == 0) {
-    a.n_free = r->image_begin;
-    a.image_w = r->image_width;
-    a.image_h = (int)(n_img / r->image_width);
-    a.tiles_x = (a.image_w + 7) / 8;
-    int64_t tiles_y = (a.image_h + 7) / 8;
-    a.n_work = a.n_free + (int64_t)a.tiles_x * tiles_y * 64;
-  } else {
-    a.n_free = R;
-    a.image_w = 0;
-    a.image_h = 0;
-    a.tiles_x = 0;
-    a.n_work = R;
-  }
-  if (a.n_work > (int64_t)INT32_MAX) {
-    set_error("grtx_trace: %lld rays (%lld work items with the image's 8x8 tiles) exceed one launch's 2^31-1",
-              (long long)R, (long long)a.n_work);
+  int64_t image_h = 0;
+  a.n_work = trace_work_items(r, &a.n_free, &image_h);
+  if (a.n_work > kMaxTraceWork) {  // (the ABI layer refuses such launches first)
+    set_error("trace: %lld work items exceed one launch's 2^31-1", (long long)a.n_work);
     return GRTX_ERR_INVALID_ARG;
   }
+  a.image_h = (int)image_h;
+  a.image_w = image_h > 0 ? r->image_width : 0;
+  a.tiles_x = (a.image_w + 7) / 8;
   a.k = p->k;
   a.T_min = p->T_min;
   a.mode = p->mode;

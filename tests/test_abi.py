@@ -79,6 +79,12 @@ def test_trace_rejects_bad_arguments():
         bad.image_begin = begin
         assert L.grtx_trace(fake, C.byref(bad), C.byref(prm), C.byref(out), None) == grtx.ERR_INVALID_ARG
         assert b"image_begin" in L.grtx_last_error()
+    # one launch takes at most 2^31-1 work items; an image's 8x8 tiles count whole, so a
+    # one-pixel-wide image of 2^28 rays makes 2^31 items
+    for count, width in [(1 << 31, 0), (1 << 28, 1)]:
+        big = grtx._Rays(fake, fake, count, 0.0, width)
+        assert L.grtx_trace(fake, C.byref(big), C.byref(prm), C.byref(out), None) == grtx.ERR_INVALID_ARG
+        assert b"2^31-1" in L.grtx_last_error()
     cam = grtx._Camera((C.c_float * 3)(0, -3, 0), (C.c_float * 3)(0, 0, 0), (C.c_float * 3)(0, 0, 1), 60.0, 0, 4)
     assert L.grtx_pinhole_rays(C.byref(cam), C.c_void_p(1), C.c_void_p(1), None) == grtx.ERR_INVALID_ARG
 
