@@ -678,10 +678,23 @@ def cpu_baseline(work, sample_rays):
             cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
     except OSError:
         pass
+    # the oracle's CPU model of the method (FP64 binary-BVH traversal in rounds of k, with
+    # checkpoints) on the same rays; its BVH build is timed apart with a one-ray call
+    t0 = time.perf_counter()
+    oracle.model_render(work.scene, ro[:1], rd[:1], 16, oracle.CHECKPOINT, oracle.RULE_KBUF_MAX, work.amin,
+                        work.cfg["T_min"], nthreads=threads)
+    t_build = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.model_render(work.scene, ro, rd, 16, oracle.CHECKPOINT, oracle.RULE_KBUF_MAX, work.amin,
+                        work.cfg["T_min"], nthreads=threads)
+    t_model = time.perf_counter() - t0
+    model = dict(value=len(idx) / max(t_model - t_build, 1e-9) / 1e6, unit="Mrays/s", cores=threads,
+                 kind="cpu model of the method (FP64, binary radix-tree BVH, k = 16, checkpoints)",
+                 build_s=t_build, sample="the same rays")
     return dict(value=len(idx) / dt / 1e6, unit="Mrays/s", cores=threads, kind="oracle",
                 sample=f"{len(idx)} of the step's {work.rays} rays ({len(ip)} primary, {len(ii)} incoherent; "
                        f"seeded subsample) against all {work.cfg['n']} Gaussians, FP64 brute force, {dt:.1f} s",
-                host_cpu=cpu_model, host_threads_visible=os.cpu_count())
+                host_cpu=cpu_model, host_threads_visible=os.cpu_count(), cpu_model_of_method=model)
 
 
 def main():

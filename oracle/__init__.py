@@ -74,6 +74,15 @@ def lib():
             L.oracle_sh_basis.argtypes = [C.c_int, C.c_int, PD]
             L.oracle_icosahedron.restype = C.c_int
             L.oracle_icosahedron.argtypes = [PD, C.POINTER(i32)]
+            L.oracle_model_render.restype = C.c_int
+            L.oracle_model_render.argtypes = [PD, PD, PD, PD, PD, i64, C.c_int, i64, PD, PD, d, d, C.c_int, C.c_int,
+                                              C.c_int, C.c_int, C.c_int, PD, PD, PD, C.POINTER(i32),
+                                              C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i64)]
+            L.oracle_model_round_state.restype = C.c_int
+            L.oracle_model_round_state.argtypes = [PD, PD, PD, PD, PD, i64, C.c_int, PD, PD, d, d, C.c_int, C.c_int,
+                                                   C.c_int, C.c_int, C.POINTER(i64), PD, C.POINTER(i32),
+                                                   C.POINTER(i64), PD, C.POINTER(i32), C.c_int, C.POINTER(i64),
+                                                   C.POINTER(i64), PD, C.POINTER(i32), C.c_int, PD, C.POINTER(i64)]
             _lib = L
     return _lib
 
@@ -304,3 +313,85 @@ def icosahedron():
     f = np.zeros((20, 3), np.int32)
     L.oracle_icosahedron(_p(v, C.c_double), _p(f, C.c_int32))
     return v, f
+
+
+# --------------------------------------------------------------------------------------
+# CPU model of the method (multi-round k-buffer traversal with checkpoints)
+
+CHECKPOINT, RESTART = 0, 1
+RULE_KBUF_MAX, RULE_PAPER = 0, 1
+
+
+def model_render(scene, origins, dirs, k, mode=CHECKPOINT, rule=RULE_KBUF_MAX, alpha_min=1.0 / 255.0,
+                 T_min=1e-3, cap=0, nthreads=None):
+    """The method itself on the CPU in FP64 (Sec. III-B, IV): rounds of k-buffer hit
+    collection over the oracle's radix tree with exact Gaussian boxes, each round blended
+    front to back, resuming from checkpoint lists (mode CHECKPOINT) or from the root
+    (RESTART). rule: the round's cull distance t_max once the k-buffer is full, its
+    farthest key (RULE_KBUF_MAX) or the nearest key it rejected or pushed out (RULE_PAPER,
+    the walkthrough of Sec. IV-B). t_near = 0, black background.
+    Returns rgb, depth, opacity, nblend, rounds and counts [R,4] (internal nodes visited,
+    leaves tested, nodes deferred, hits evicted); with cap > 0 also the first `cap`
+    blended ids and the round that blended each (round_of)."""
+    L = lib()
+    if nthreads is None:
+        nthreads = min(16, os.cpu_count() or 1)
+    o = _f64(origins).reshape(-1, 3)
+    d = _f64(dirs).reshape(-1, 3)
+    R = o.shape[0]
+    m, s, q, op, sh = _scene_args(scene)
+    rgb = np.zeros((R, 3), np.float64)
+    depth = np.zeros(R, np.float64)
+    opac = np.zeros(R, np.float64)
+    nblend = np.zeros(R, np.int32)
+    rounds = np.zeros(R, np.int32)
+    counts = np.zeros((R, 4), np.int64)
+    ids = np.full((R, max(cap, 1)), -1, np.int32) if cap > 0 else None
+    round_of = np.zeros((R, max(cap, 1)), np.int32) if cap > 0 else None
+    rc = L.oracle_model_render(_p(m, C.c_double), _p(s, C.c_double), _p(q, C.c_double), _p(op, C.c_double),
+                               _p(sh, C.c_double), scene.n, scene.sh_degree, R, _p(o, C.c_double),
+                               _p(d, C.c_double), alpha_min, T_min, k, mode, rule, cap, nthreads,
+                               _p(rgb, C.c_double), _p(depth, C.c_double), _p(opac, C.c_double),
+                               _p(nblend, C.c_int32), _p(ids, C.c_int32), _p(round_of, C.c_int32),
+                               _p(rounds, C.c_int32), _p(counts, C.c_int64))
+    if rc != 0:
+        raise RuntimeError(f"oracle_model_render failed ({rc})")
+    out = dict(rgb=rgb, depth=depth, opacity=opac, nblend=nblend, rounds=rounds, counts=counts)
+    if cap > 0:
+        out.update(ids=ids, round_of=round_of)
+    return out
+
+
+def model_round_state(scene, origin, direction, k, round_, mode=CHECKPOINT, rule=RULE_KBUF_MAX,
+                      alpha_min=1.0 / 255.0, T_min=1e-3, cap=256):
+    """One ray's state at the end of round `round_` of the CPU model, before that round
+    blends: the k-buffer (ids, distances), the eviction list (ids, distances), the deferred
+    nodes (the range of sorted leaf positions under each, in oracle_lbvh_topology's order,
+    and its entry distance) and t_max (distance, id; inf while the k-buffer was not full).
+    None if the ray finishes earlier."""
+    L = lib()
+    o = _f64(origin).reshape(3)
+    d = _f64(direction).reshape(3)
+    m, s, q, op, sh = _scene_args(scene)
+    kid = np.zeros(k, np.int64)
+    kt = np.zeros(k, np.float64)
+    eid = np.zeros(cap, np.int64)
+    et = np.zeros(cap, np.float64)
+    df = np.zeros(cap, np.int64)
+    dl = np.zeros(cap, np.int64)
+    dt = np.zeros(cap, np.float64)
+    nk, ne, nd = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    tt, ti = C.c_double(0.0), C.c_int64(0)
+    rc = L.oracle_model_round_state(_p(m, C.c_double), _p(s, C.c_double), _p(q, C.c_double), _p(op, C.c_double),
+                                    _p(sh, C.c_double), scene.n, scene.sh_degree, _p(o, C.c_double),
+                                    _p(d, C.c_double), alpha_min, T_min, k, mode, rule, round_,
+                                    _p(kid, C.c_int64), _p(kt, C.c_double), C.byref(nk), _p(eid, C.c_int64),
+                                    _p(et, C.c_double), C.byref(ne), cap, _p(df, C.c_int64), _p(dl, C.c_int64),
+                                    _p(dt, C.c_double), C.byref(nd), cap, C.byref(tt), C.byref(ti))
+    if rc != 0:
+        return None
+    if ne.value > cap or nd.value > cap:
+        raise RuntimeError("model_round_state: lists longer than cap")
+    return dict(kbuf_ids=kid[:nk.value], kbuf_t=kt[:nk.value], evicted_ids=eid[:ne.value], evicted_t=et[:ne.value],
+                deferred_first=df[:nd.value], deferred_last=dl[:nd.value], deferred_t=dt[:nd.value],
+                tmax_t=tt.value, tmax_id=ti.value)

@@ -38,6 +38,10 @@
  * The LBVH reference (Morton codes, stable sort, radix tree) gives the topology that
  * the GPU build must reproduce bit for bit; its tree is the plain top-down definition
  * (split each key range where the highest differing key bit changes).
+ *
+ * The last section is a CPU model of the method itself (rounds of k-buffer hit
+ * collection over that tree, resuming from checkpoints), pinned against the brute-force
+ * render and the paper's walkthrough; the GPU path is never compared with it.
  */
 #include <math.h>
 #include <pthread.h>
@@ -896,4 +900,580 @@ int oracle_lbvh_topology_search(int64_t n, const float *means, uint64_t *sorted_
 int oracle_lbvh_topology(int64_t n, const float *means, uint64_t *sorted_codes, uint32_t *perm,
                          uint32_t *child, uint32_t *parent) {
   return oracle_lbvh_topology_search(n, means, sorted_codes, perm, child, parent, 0);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* CPU model of the method: multi-round k-buffer traversal with checkpoints               */
+/* ------------------------------------------------------------------------------------ */
+/*
+ * The rendering method itself, step by step on the CPU in FP64 (Sec. III-B and IV: rounds
+ * of k-nearest hit collection into a k-buffer, each followed by blending, with the
+ * traversal of the next round resuming from a checkpoint). It is checked against the
+ * brute-force render above (the same hits must blend in the same order, with the same
+ * arithmetic) and gives the per-round state the paper's walkthrough describes.
+ *
+ * Structure: a binary BVH, the radix tree of oracle_lbvh_topology over the Gaussians,
+ * with each Gaussian's exact bounding-ellipsoid box and each internal node's box the
+ * union of its children's; every box is widened by a relative 1e-9 so that rounding
+ * never puts a box entry beyond the entry of the ellipsoid inside it.
+ *
+ * Per ray and round:
+ *   - the k-buffer holds the k nearest keys (t0, id) found in the round, sorted;
+ *   - t_max, the round's cull key, is +inf until the k-buffer is full. Rule KBUF_MAX:
+ *     t_max is then the k-buffer's farthest key. Rule PAPER (the walkthrough of
+ *     Sec. IV-B): t_max is the nearest key rejected by, or pushed out of, the full
+ *     k-buffer, that is the first such key and the ones below it;
+ *   - a hit beyond the full k-buffer's farthest key is rejected, and one pushed out of it
+ *     by a nearer hit is evicted: both go to the eviction list;
+ *   - a node whose entry distance (raised to its parent's entry, so that entries never
+ *     decrease along a path) lies beyond t_max is not visited; in CHECKPOINT mode it goes
+ *     to the deferred-node list with that entry;
+ *   - at the end of the round the k-buffer is blended front to back (Eq. 1) with early
+ *     termination.
+ * CHECKPOINT: the next round first offers the evicted hits to the empty k-buffer, then
+ * takes the deferred nodes in list order, each traversed depth first, nearest child
+ * first; a listed node whose entry is beyond the new t_max is listed again without a
+ * visit. The ray is done at early termination or when both lists are empty.
+ * RESTART: every round starts at the root; subtrees that end before the last blended
+ * key and keys not beyond it are skipped. The ray is done at early termination or after
+ * a round whose k-buffer did not fill.
+ */
+
+#define MODEL_CHECKPOINT 0
+#define MODEL_RESTART 1
+#define RULE_KBUF_MAX 0
+#define RULE_PAPER 1
+
+typedef struct {
+  double t;
+  int64_t id;
+} mkey_t;
+
+static int mkey_lt(mkey_t a, mkey_t b) { return a.t < b.t || (a.t == b.t && a.id < b.id); }
+
+typedef struct {
+  uint32_t ref; /* internal node index, or LEAF_FLAG | sorted position */
+  double t;     /* entry distance */
+} ment_t;
+
+typedef struct {
+  ment_t *a;
+  size_t n, cap;
+} mnvec_t;
+
+typedef struct {
+  mkey_t *a;
+  size_t n, cap;
+} mkvec_t;
+
+static void mn_push(mnvec_t *v, uint32_t ref, double t) {
+  if (v->n == v->cap) {
+    v->cap = v->cap ? 2 * v->cap : 64;
+    v->a = (ment_t *)realloc(v->a, v->cap * sizeof(ment_t));
+  }
+  v->a[v->n].ref = ref;
+  v->a[v->n].t = t;
+  ++v->n;
+}
+
+static void mk_push(mkvec_t *v, mkey_t k) {
+  if (v->n == v->cap) {
+    v->cap = v->cap ? 2 * v->cap : 64;
+    v->a = (mkey_t *)realloc(v->a, v->cap * sizeof(mkey_t));
+  }
+  v->a[v->n++] = k;
+}
+
+typedef struct {
+  int64_t n;
+  uint32_t *child;  /* [(n-1)*2] */
+  uint32_t *perm;   /* sorted position -> Gaussian */
+  double *lo, *hi;  /* [2n-1][3]: internal node i at i, leaf p at n-1+p */
+  int64_t *first, *last; /* sorted-position range under each node, same indexing */
+  uint32_t root;
+} mbvh_t;
+
+static int64_t mb_index(const mbvh_t *B, uint32_t ref) {
+  return (ref & LEAF_FLAG) ? B->n - 1 + (int64_t)(ref & ~LEAF_FLAG) : (int64_t)ref;
+}
+
+/* boxes and leaf ranges of internal node i and everything below it */
+static void mb_fill(mbvh_t *B, uint32_t i) {
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  int64_t first = INT64_MAX, last = -1;
+  for (int c = 0; c < 2; ++c) {
+    uint32_t ch = B->child[2 * i + c];
+    if (!(ch & LEAF_FLAG)) mb_fill(B, ch);
+    int64_t x = mb_index(B, ch);
+    for (int a = 0; a < 3; ++a) {
+      if (B->lo[3 * x + a] < lo[a]) lo[a] = B->lo[3 * x + a];
+      if (B->hi[3 * x + a] > hi[a]) hi[a] = B->hi[3 * x + a];
+    }
+    if (B->first[x] < first) first = B->first[x];
+    if (B->last[x] > last) last = B->last[x];
+  }
+  for (int a = 0; a < 3; ++a) {
+    const double pad = 1e-9 * (1.0 + fmax(fabs(lo[a]), fabs(hi[a])));
+    B->lo[3 * i + a] = lo[a] - pad;
+    B->hi[3 * i + a] = hi[a] + pad;
+  }
+  B->first[i] = first;
+  B->last[i] = last;
+}
+
+static void mb_free(mbvh_t *B) {
+  free(B->child);
+  free(B->perm);
+  free(B->lo);
+  free(B->hi);
+  free(B->first);
+  free(B->last);
+}
+
+static int mb_build(const scene_t *s, double alpha_min, mbvh_t *B) {
+  const int64_t n = s->n;
+  memset(B, 0, sizeof *B);
+  B->n = n;
+  if (n <= 0) return OR_OK;
+  float *mf = (float *)malloc(sizeof(float) * 3 * (size_t)n);
+  uint64_t *codes = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+  uint32_t *parent = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(2 * n - 1));
+  double *glo = (double *)malloc(sizeof(double) * 3 * (size_t)n), *ghi = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+  int32_t *act = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  B->child = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n > 1 ? 2 * (n - 1) : 1));
+  B->perm = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+  B->lo = (double *)malloc(sizeof(double) * 3 * (size_t)(2 * n - 1));
+  B->hi = (double *)malloc(sizeof(double) * 3 * (size_t)(2 * n - 1));
+  B->first = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * n - 1));
+  B->last = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * n - 1));
+  int rc = OR_OK;
+  if (!mf || !codes || !parent || !glo || !ghi || !act || !B->child || !B->perm || !B->lo || !B->hi || !B->first ||
+      !B->last) {
+    rc = OR_ERR_MEM;
+    goto done;
+  }
+  for (int64_t i = 0; i < 3 * n; ++i) mf[i] = (float)s->means[i];
+  rc = oracle_lbvh_topology(n, mf, codes, B->perm, B->child, parent);
+  if (rc != OR_OK) goto done;
+  oracle_gaussian_aabb(s->means, s->scales, s->quats, s->opac, n, alpha_min, glo, ghi, act);
+  for (int64_t p = 0; p < n; ++p) {
+    const int64_t g = B->perm[p], x = n - 1 + p;
+    for (int a = 0; a < 3; ++a) {
+      const double pad = 1e-9 * (1.0 + fmax(fabs(glo[3 * g + a]), fabs(ghi[3 * g + a])));
+      B->lo[3 * x + a] = glo[3 * g + a] - pad;
+      B->hi[3 * x + a] = ghi[3 * g + a] + pad;
+    }
+    B->first[x] = B->last[x] = p;
+  }
+  if (n == 1) {
+    B->root = LEAF_FLAG;
+  } else {
+    B->root = 0;
+    mb_fill(B, 0);
+  }
+done:
+  free(mf);
+  free(codes);
+  free(parent);
+  free(glo);
+  free(ghi);
+  free(act);
+  if (rc != OR_OK) mb_free(B);
+  return rc;
+}
+
+/* Slab test of box x: entry and exit distances of the line; 0 if it misses the box. */
+static int mb_slab(const mbvh_t *B, int64_t x, const double o[3], const double d[3], double *tn, double *tf) {
+  double a0 = -INFINITY, a1 = INFINITY;
+  for (int a = 0; a < 3; ++a) {
+    const double lo = B->lo[3 * x + a], hi = B->hi[3 * x + a];
+    if (d[a] == 0.0) {
+      if (o[a] < lo || o[a] > hi) return 0;
+      continue;
+    }
+    double t0 = (lo - o[a]) / d[a], t1 = (hi - o[a]) / d[a];
+    if (t0 > t1) {
+      const double tt = t0;
+      t0 = t1;
+      t1 = tt;
+    }
+    if (t0 > a0) a0 = t0;
+    if (t1 < a1) a1 = t1;
+  }
+  if (!(a0 <= a1)) return 0;
+  *tn = a0;
+  *tf = a1;
+  return 1;
+}
+
+typedef struct {
+  int k, mode, rule;
+  double alpha_min, T_min;
+} mparams_t;
+
+typedef struct {
+  double rgb[3], depth, opacity;
+  int32_t nblend, rounds;
+  int64_t nodes, leaves, deferred, evicted;
+} mres_t;
+
+/* end-of-round state of one round (before its blend), for one ray */
+typedef struct {
+  int round;
+  mkvec_t kbuf, ev;
+  mnvec_t def;
+  mkey_t tmax;
+  int logged;
+} mlog_t;
+
+typedef struct {
+  const mbvh_t *B;
+  const og_t *g;
+  const scene_t *s;
+  const mparams_t *P;
+  double o[3], d[3];
+  mkvec_t kbuf, esrc, edst;
+  mnvec_t nsrc, ndst, stack;
+  mkey_t tmax, tmin;
+  mres_t *res;
+} mray_t;
+
+static void m_offer(mray_t *R, mkey_t key) {
+  mkvec_t *kb = &R->kbuf;
+  const int k = R->P->k;
+  if ((int)kb->n == k && mkey_lt(kb->a[k - 1], key)) {
+    /* rejected: beyond the full k-buffer */
+    if (R->P->mode == MODEL_CHECKPOINT) mk_push(&R->edst, key), ++R->res->evicted;
+    if (R->P->rule == RULE_PAPER && mkey_lt(key, R->tmax)) R->tmax = key;
+    return;
+  }
+  /* sorted insertion; a full buffer pushes out its farthest key */
+  mk_push(kb, key);
+  size_t j = kb->n - 1;
+  while (j > 0 && mkey_lt(key, kb->a[j - 1])) {
+    kb->a[j] = kb->a[j - 1];
+    --j;
+  }
+  kb->a[j] = key;
+  if ((int)kb->n > k) {
+    const mkey_t out = kb->a[--kb->n];
+    if (R->P->mode == MODEL_CHECKPOINT) mk_push(&R->edst, out), ++R->res->evicted;
+    if (R->P->rule == RULE_PAPER && mkey_lt(out, R->tmax)) R->tmax = out;
+  }
+  if (R->P->rule == RULE_KBUF_MAX && (int)kb->n == k) R->tmax = kb->a[k - 1];
+}
+
+static void m_defer(mray_t *R, uint32_t ref, double t) {
+  if (R->P->mode == MODEL_CHECKPOINT) {
+    mn_push(&R->ndst, ref, t);
+    ++R->res->deferred;
+  }
+}
+
+/* depth-first traversal of the subtree at `ref` (entry distance t) */
+static void m_traverse(mray_t *R, uint32_t ref, double t) {
+  const mbvh_t *B = R->B;
+  const int restart = R->P->mode == MODEL_RESTART;
+  R->stack.n = 0;
+  mn_push(&R->stack, ref, t);
+  while (R->stack.n) {
+    const ment_t e = R->stack.a[--R->stack.n];
+    if (e.t > R->tmax.t) { /* t_max came down since the node was reached */
+      m_defer(R, e.ref, e.t);
+      continue;
+    }
+    if (e.ref & LEAF_FLAG) {
+      ++R->res->leaves;
+      const int64_t gid = B->perm[e.ref & ~LEAF_FLAG];
+      double t0;
+      if (!ellipsoid_entry(R->g + gid, R->o, R->d, 0.0, &t0)) continue;
+      const mkey_t key = {t0, gid};
+      if (restart && !mkey_lt(R->tmin, key)) continue; /* blended in an earlier round */
+      m_offer(R, key);
+      continue;
+    }
+    ++R->res->nodes;
+    double tc[2];
+    uint32_t rc[2];
+    int nc = 0;
+    for (int c = 0; c < 2; ++c) {
+      const uint32_t ch = B->child[2 * e.ref + c];
+      double tn, tf;
+      if (!mb_slab(B, mb_index(B, ch), R->o, R->d, &tn, &tf)) continue;
+      if (tf < 0.0) continue;                    /* behind the ray origin */
+      if (restart && tf < R->tmin.t) continue;   /* ends before the last blended key */
+      const double te = tn > e.t ? tn : e.t;     /* entries never decrease along a path */
+      if (te > R->tmax.t) {
+        m_defer(R, ch, te);
+        continue;
+      }
+      rc[nc] = ch;
+      tc[nc] = te;
+      ++nc;
+    }
+    /* nearer child on top of the stack */
+    if (nc == 2 && tc[1] > tc[0]) {
+      mn_push(&R->stack, rc[1], tc[1]);
+      mn_push(&R->stack, rc[0], tc[0]);
+    } else {
+      for (int c = 0; c < nc; ++c) mn_push(&R->stack, rc[c], tc[c]);
+    }
+  }
+}
+
+static void m_copy_log(mray_t *R, mlog_t *L) {
+  L->kbuf.n = L->ev.n = L->def.n = 0;
+  for (size_t i = 0; i < R->kbuf.n; ++i) mk_push(&L->kbuf, R->kbuf.a[i]);
+  for (size_t i = 0; i < R->edst.n; ++i) mk_push(&L->ev, R->edst.a[i]);
+  for (size_t i = 0; i < R->ndst.n; ++i) mn_push(&L->def, R->ndst.a[i].ref, R->ndst.a[i].t);
+  L->tmax = R->tmax;
+  L->logged = 1;
+}
+
+/* One ray through all its rounds. ids / round_of: the first `cap` blended hits. */
+static void m_ray(mray_t *R, int cap, int32_t *ids, int32_t *round_of, mlog_t *L) {
+  const mbvh_t *B = R->B;
+  const mparams_t *P = R->P;
+  mres_t *res = R->res;
+  memset(res, 0, sizeof *res);
+  R->nsrc.n = R->ndst.n = R->esrc.n = R->edst.n = R->kbuf.n = 0;
+  R->tmin.t = -INFINITY;
+  R->tmin.id = -1;
+  double root_t = 0.0, root_f = 0.0;
+  const int root_hit = B->n > 0 && mb_slab(B, mb_index(B, B->root), R->o, R->d, &root_t, &root_f) && root_f >= 0.0;
+  if (root_hit) mn_push(&R->nsrc, B->root, root_t);
+  double T = 1.0, C[3] = {0, 0, 0}, D = 0.0;
+  int nb = 0, done = 0;
+  while (!done) {
+    ++res->rounds;
+    R->kbuf.n = R->edst.n = R->ndst.n = 0;
+    R->tmax.t = INFINITY;
+    R->tmax.id = INT64_MAX;
+    if (P->mode == MODEL_CHECKPOINT) {
+      for (size_t i = 0; i < R->esrc.n; ++i) m_offer(R, R->esrc.a[i]);
+      for (size_t i = 0; i < R->nsrc.n; ++i) {
+        const ment_t e = R->nsrc.a[i];
+        if (e.t > R->tmax.t)
+          m_defer(R, e.ref, e.t);
+        else
+          m_traverse(R, e.ref, e.t);
+      }
+    } else if (root_hit) {
+      m_traverse(R, B->root, root_t);
+    }
+    if (L && L->round == res->rounds) m_copy_log(R, L);
+    const int full = (int)R->kbuf.n == P->k;
+    int ert = 0;
+    for (size_t i = 0; i < R->kbuf.n; ++i) {
+      const mkey_t key = R->kbuf.a[i];
+      double alpha, talpha, c[3];
+      max_response(R->g + key.id, R->o, R->d, &alpha, &talpha);
+      sh_colour(R->s, key.id, R->d, c);
+      const double w = T * alpha;
+      for (int ch = 0; ch < 3; ++ch) C[ch] += w * c[ch];
+      D += w * talpha;
+      T *= (1.0 - alpha);
+      if (nb < cap) {
+        if (ids) ids[nb] = (int32_t)key.id;
+        if (round_of) round_of[nb] = res->rounds;
+      }
+      ++nb;
+      R->tmin = key;
+      if (T < P->T_min) {
+        ert = 1;
+        break;
+      }
+    }
+    if (ert) {
+      done = 1;
+    } else if (P->mode == MODEL_CHECKPOINT) {
+      /* the lists of this round are the next round's sources */
+      mnvec_t tn = R->nsrc;
+      R->nsrc = R->ndst;
+      R->ndst = tn;
+      mkvec_t te = R->esrc;
+      R->esrc = R->edst;
+      R->edst = te;
+      done = R->nsrc.n == 0 && R->esrc.n == 0;
+    } else {
+      done = !full;
+    }
+  }
+  for (int ch = 0; ch < 3; ++ch) res->rgb[ch] = C[ch];
+  res->depth = D;
+  res->opacity = 1.0 - T;
+  res->nblend = nb;
+}
+
+static void m_ray_free(mray_t *R) {
+  free(R->kbuf.a);
+  free(R->esrc.a);
+  free(R->edst.a);
+  free(R->nsrc.a);
+  free(R->ndst.a);
+  free(R->stack.a);
+}
+
+typedef struct {
+  const mbvh_t *B;
+  const og_t *g;
+  const scene_t *s;
+  const mparams_t *P;
+  const double *ro, *rd;
+  int64_t r0, r1;
+  int cap;
+  double *rgb, *depth, *opac;
+  int32_t *nblend, *ids, *round_of, *rounds;
+  int64_t *counts;
+} mjob_t;
+
+static void *m_worker(void *arg) {
+  mjob_t *J = (mjob_t *)arg;
+  mray_t R;
+  memset(&R, 0, sizeof R);
+  R.B = J->B;
+  R.g = J->g;
+  R.s = J->s;
+  R.P = J->P;
+  mres_t res;
+  R.res = &res;
+  for (int64_t r = J->r0; r < J->r1; ++r) {
+    for (int a = 0; a < 3; ++a) {
+      R.o[a] = J->ro[3 * r + a];
+      R.d[a] = J->rd[3 * r + a];
+    }
+    m_ray(&R, J->cap, J->ids ? J->ids + r * J->cap : NULL, J->round_of ? J->round_of + r * J->cap : NULL, NULL);
+    for (int ch = 0; ch < 3; ++ch) J->rgb[3 * r + ch] = res.rgb[ch];
+    J->depth[r] = res.depth;
+    J->opac[r] = res.opacity;
+    if (J->nblend) J->nblend[r] = res.nblend;
+    if (J->rounds) J->rounds[r] = res.rounds;
+    if (J->counts) {
+      J->counts[4 * r + 0] = res.nodes;
+      J->counts[4 * r + 1] = res.leaves;
+      J->counts[4 * r + 2] = res.deferred;
+      J->counts[4 * r + 3] = res.evicted;
+    }
+  }
+  m_ray_free(&R);
+  return NULL;
+}
+
+/* The method on the CPU for R rays (unit directions, t_near = 0, black background).
+ * k >= 1; mode MODEL_CHECKPOINT or MODEL_RESTART; rule RULE_KBUF_MAX or RULE_PAPER.
+ * Outputs per ray: rgb[3], depth, opacity; optionally the number of blended hits and of
+ * rounds, the first `cap` blended ids and the round that blended each, and four counts
+ * (internal nodes visited, leaves tested, nodes deferred, hits evicted). */
+int oracle_model_render(const double *means, const double *scales, const double *quats, const double *opac,
+                        const double *sh, int64_t n, int sh_degree, int64_t nrays, const double *ray_o,
+                        const double *ray_d, double alpha_min, double T_min, int k, int mode, int rule, int cap,
+                        int nthreads, double *rgb, double *depth, double *opacity, int32_t *nblend, int32_t *ids,
+                        int32_t *round_of, int32_t *rounds, int64_t *counts) {
+  if (n < 0 || nrays < 0 || k < 1 || (mode != MODEL_CHECKPOINT && mode != MODEL_RESTART) ||
+      (rule != RULE_KBUF_MAX && rule != RULE_PAPER) || cap < 0)
+    return OR_ERR_ARG;
+  scene_t s = {means, scales, quats, opac, sh, n, sh_degree};
+  mparams_t P = {k, mode, rule, alpha_min, T_min};
+  mbvh_t B;
+  int rc = mb_build(&s, alpha_min, &B);
+  if (rc != OR_OK) return rc;
+  og_t *g = prepare_all(&s, alpha_min, 0);
+  if (!g) {
+    mb_free(&B);
+    return OR_ERR_MEM;
+  }
+  int nt = resolve_threads(nthreads);
+  if (nt > nrays) nt = nrays > 0 ? (int)nrays : 1;
+  pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nt);
+  mjob_t *jobs = (mjob_t *)malloc(sizeof(mjob_t) * (size_t)nt);
+  if (!th || !jobs) {
+    free(th);
+    free(jobs);
+    free_all(g, n);
+    mb_free(&B);
+    return OR_ERR_MEM;
+  }
+  for (int t = 0; t < nt; ++t) {
+    mjob_t J = {&B, g, &s, &P, ray_o, ray_d, nrays * t / nt, nrays * (t + 1) / nt, cap, rgb, depth, opacity,
+                nblend, ids, round_of, rounds, counts};
+    jobs[t] = J;
+    pthread_create(th + t, NULL, m_worker, jobs + t);
+  }
+  for (int t = 0; t < nt; ++t) pthread_join(th[t], NULL);
+  free(th);
+  free(jobs);
+  free_all(g, n);
+  mb_free(&B);
+  return OR_OK;
+}
+
+/* The state of one ray at the end of round `round` (1-based), before that round blends:
+ * the k-buffer's keys (ids, distances), the eviction list, the deferred nodes (the range
+ * of sorted leaf positions under each, as oracle_lbvh_topology orders them, and its entry
+ * distance) and t_max (distance and id; +inf and INT64_MAX while the k-buffer was not
+ * full). *n_* receive the full list lengths; at most the given capacities are written.
+ * Returns OR_ERR_ARG when the ray finishes before that round. */
+int oracle_model_round_state(const double *means, const double *scales, const double *quats, const double *opac,
+                             const double *sh, int64_t n, int sh_degree, const double *ray_o, const double *ray_d,
+                             double alpha_min, double T_min, int k, int mode, int rule, int round,
+                             int64_t *kbuf_ids, double *kbuf_t, int32_t *n_kbuf, int64_t *ev_ids, double *ev_t,
+                             int32_t *n_ev, int ev_cap, int64_t *def_first, int64_t *def_last, double *def_t,
+                             int32_t *n_def, int def_cap, double *tmax_t, int64_t *tmax_id) {
+  if (n < 0 || k < 1 || round < 1 || (mode != MODEL_CHECKPOINT && mode != MODEL_RESTART) ||
+      (rule != RULE_KBUF_MAX && rule != RULE_PAPER))
+    return OR_ERR_ARG;
+  scene_t s = {means, scales, quats, opac, sh, n, sh_degree};
+  mparams_t P = {k, mode, rule, alpha_min, T_min};
+  mbvh_t B;
+  int rc = mb_build(&s, alpha_min, &B);
+  if (rc != OR_OK) return rc;
+  og_t *g = prepare_all(&s, alpha_min, 0);
+  if (!g) {
+    mb_free(&B);
+    return OR_ERR_MEM;
+  }
+  mray_t R;
+  memset(&R, 0, sizeof R);
+  mres_t res;
+  R.B = &B;
+  R.g = g;
+  R.s = &s;
+  R.P = &P;
+  R.res = &res;
+  for (int a = 0; a < 3; ++a) {
+    R.o[a] = ray_o[a];
+    R.d[a] = ray_d[a];
+  }
+  mlog_t L;
+  memset(&L, 0, sizeof L);
+  L.round = round;
+  m_ray(&R, 0, NULL, NULL, &L);
+  if (L.logged) {
+    *n_kbuf = (int32_t)L.kbuf.n;
+    for (size_t i = 0; i < L.kbuf.n && (int)i < k; ++i) {
+      kbuf_ids[i] = L.kbuf.a[i].id;
+      kbuf_t[i] = L.kbuf.a[i].t;
+    }
+    *n_ev = (int32_t)L.ev.n;
+    for (size_t i = 0; i < L.ev.n && (int)i < ev_cap; ++i) {
+      ev_ids[i] = L.ev.a[i].id;
+      ev_t[i] = L.ev.a[i].t;
+    }
+    *n_def = (int32_t)L.def.n;
+    for (size_t i = 0; i < L.def.n && (int)i < def_cap; ++i) {
+      const int64_t x = mb_index(&B, L.def.a[i].ref);
+      def_first[i] = B.first[x];
+      def_last[i] = B.last[x];
+      def_t[i] = L.def.a[i].t;
+    }
+    *tmax_t = L.tmax.t;
+    *tmax_id = L.tmax.id;
+  }
+  free(L.kbuf.a);
+  free(L.ev.a);
+  free(L.def.a);
+  m_ray_free(&R);
+  free_all(g, n);
+  mb_free(&B);
+  return L.logged ? OR_OK : OR_ERR_ARG;
 }
