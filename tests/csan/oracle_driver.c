@@ -23,6 +23,18 @@ int oracle_object_rays(const double *sphere, const double *mirror, double eps, i
                        const double *ray_d, double t_near, double *t_far, double *next_o, double *next_d,
                        double *path, int32_t *kind);
 
+int oracle_model_render(const double *means, const double *scales, const double *quats, const double *opac,
+                        const double *sh, int64_t n, int sh_degree, int64_t nrays, const double *ray_o,
+                        const double *ray_d, double alpha_min, double T_min, int k, int mode, int rule, int cap,
+                        int nthreads, double *rgb, double *depth, double *opacity, int32_t *nblend, int32_t *ids,
+                        int32_t *round_of, int32_t *rounds, int64_t *counts);
+int oracle_model_round_state(const double *means, const double *scales, const double *quats, const double *opac,
+                             const double *sh, int64_t n, int sh_degree, const double *ray_o, const double *ray_d,
+                             double alpha_min, double T_min, int k, int mode, int rule, int round,
+                             int64_t *kbuf_ids, double *kbuf_t, int32_t *n_kbuf, int64_t *ev_ids, double *ev_t,
+                             int32_t *n_ev, int ev_cap, int64_t *def_first, int64_t *def_last, double *def_t,
+                             int32_t *n_def, int def_cap, double *tmax_t, int64_t *tmax_id);
+
 static uint64_t state = 0x9E3779B97F4A7C15ull;
 static double urand(void) { /* xorshift64*, a plain test-input generator */
   state ^= state >> 12; state ^= state << 25; state ^= state >> 27;
@@ -80,6 +92,31 @@ int main(void) {
   double v[36];
   int32_t f[60];
   if (oracle_icosahedron(v, f)) return 5;
+  /* the CPU model of the method: every mode and rule, k from 1 to above the hit count,
+   * on the scene and on a one-Gaussian scene; then one ray's round-2 state */
+  int32_t *ro = malloc(sizeof(int32_t) * R * CAP), *nr = malloc(sizeof(int32_t) * R);
+  int64_t *cnt = malloc(sizeof(int64_t) * 4 * R);
+  for (int k = 1; k <= 64; k *= 4)
+    for (int mode = 0; mode <= 1; ++mode)
+      for (int rule = 0; rule <= 1; ++rule) {
+        if (oracle_model_render(means, scales, quats, opac, sh, N, L, R, o, d, 1.0 / 255.0, 1e-3, k, mode, rule, CAP,
+                                4, rgb, dep, op, nb, ids, ro, nr, cnt))
+          return 9;
+        if (oracle_model_render(means, scales, quats, opac, sh, 1, L, R, o, d, 1.0 / 255.0, 1e-3, k, mode, rule, 0, 2,
+                                rgb, dep, op, NULL, NULL, NULL, NULL, NULL))
+          return 10;
+      }
+  {
+    int64_t ki[4], ei[CAP], df[CAP], dl[CAP], ti;
+    double kt[4], et[CAP], dt[CAP], tt;
+    int32_t nk, ne, nd;
+    int best = 0;
+    for (int r = 0; r < R; ++r)
+      if (nb[r] > nb[best]) best = r; /* most blended hits: several rounds at k = 4 */
+    (void)oracle_model_round_state(means, scales, quats, opac, sh, N, L, o + 3 * best, d + 3 * best, 1.0 / 255.0, 1e-3,
+                                   4, 0, 1, 2, ki, kt, &nk, ei, et, &ne, CAP, df, dl, dt, &nd, CAP, &tt, &ti);
+  }
+  free(ro); free(nr); free(cnt);
   printf("ok %.6f\n", rgb[0] + dep[R / 2]);
   free(means); free(scales); free(quats); free(opac); free(sh); free(fm); free(o); free(d); free(rgb);
   free(dep); free(op); free(nb); free(nh); free(ids); free(ta); free(tk); free(codes); free(perm);
