@@ -379,17 +379,18 @@ def run_backward(stream):
     o, d = grtx.pinhole_rays(cam)
     bvh = grtx.build(st, alpha_min=float(np.float32(cfg["alpha_min"])))
     cap = 256
-    fwd = grtx.trace(bvh, o, d, k=cfg["k"], T_min=cfg["T_min"], hit_capacity=cap)
+    W = cam.width  # the rays form an image: 8x8 tile scheduling
+    fwd = grtx.trace(bvh, o, d, k=cfg["k"], T_min=cfg["T_min"], hit_capacity=cap, image_width=W)
     g_rgb = torch.ones_like(fwd["rgb"])
     grads = dict(means=torch.zeros_like(st.means), scales=torch.zeros_like(st.scales),
                  quats=torch.zeros_like(st.quats), opacities=torch.zeros_like(st.opacities),
                  sh=torch.zeros_like(st.sh))
-    f_ms = time_launch(lambda: grtx.trace(bvh, o, d, k=cfg["k"], T_min=cfg["T_min"], hit_capacity=cap, out=fwd),
-                       stream, 3)
+    f_ms = time_launch(lambda: grtx.trace(bvh, o, d, k=cfg["k"], T_min=cfg["T_min"], hit_capacity=cap, out=fwd,
+                                          image_width=W), stream, 3)
     b_ms = time_launch(lambda: grtx.trace_backward(bvh, o, d, fwd, grad_rgb=g_rgb, grads=grads, k=cfg["k"],
                                                    T_min=cfg["T_min"]), stream, 5)
     r_ms = time_launch(lambda: grtx.trace_backward(bvh, o, d, None, grad_rgb=g_rgb, grads=grads, k=cfg["k"],
-                                                   T_min=cfg["T_min"], hit_capacity=cap), stream, 3)
+                                                   T_min=cfg["T_min"], hit_capacity=cap, image_width=W), stream, 3)
     R = cam.n_rays
     counts = fwd["hit_counts"].clamp(max=cap)
     P = int(counts.sum())

@@ -27,6 +27,9 @@ class RenderSettings:
     kind: int = grtx.SPHERE_INSTANCE
     bg: tuple = (0.0, 0.0, 0.0)
     hit_capacity: int = 512
+    # > 0: the rays are a row-major image of this width (8x8 tile scheduling; results are
+    # unaffected)
+    image_width: int = 0
     # after each backward, read the number of rays whose blended hits overflowed the list
     # (a device-to-host read) and warn: their gradients miss the hits past the list
     check_truncation: bool = True
@@ -42,7 +45,7 @@ class GRTXRender(torch.autograd.Function):
         o = origins.detach().contiguous()
         d = dirs.detach().contiguous()
         out = grtx.trace(bvh, o, d, k=settings.k, T_min=settings.T_min, mode=settings.mode, bg=settings.bg,
-                         hit_capacity=settings.hit_capacity)
+                         hit_capacity=settings.hit_capacity, image_width=settings.image_width)
         ctx.bvh = bvh
         ctx.settings = settings
         ctx.save_for_backward(o, d, out["rgb"], out["depth"], out["opacity"], out["hit_ids"], out["hit_counts"])

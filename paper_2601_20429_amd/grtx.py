@@ -436,11 +436,13 @@ def _gaussians(scene: SceneTensors):
 
 def trace_backward(bvh: Bvh, origins, dirs, fwd: dict = None, grad_rgb=None, grad_depth=None, grad_opacity=None,
                    grads: dict = None, k: int = 16, T_min: float = 1e-3, mode: int = CHECKPOINT,
-                   bg=(0.0, 0.0, 0.0), t_near: float = 0.0, hit_capacity: int = 0, stream=None):
+                   bg=(0.0, 0.0, 0.0), t_near: float = 0.0, hit_capacity: int = 0, stream=None,
+                   image_width: int = 0):
     """Accumulate dL/d(parameters) into `grads` (dict of tensors shaped like the scene
     arrays; allocated as zeros when None). `fwd` holds rgb, depth, opacity, hit_ids and
     hit_counts of the forward call; when None the library traces the rays again with
-    lists of `hit_capacity` entries (0 = 256). Returns (grads, truncated_rays tensor)."""
+    lists of `hit_capacity` entries (0 = 256), scheduled as an image of `image_width` when
+    given. Returns (grads, truncated_rays tensor)."""
     sc = bvh.scene
     dev = sc.means.device
     if grads is None:
@@ -449,7 +451,7 @@ def trace_backward(bvh: Bvh, origins, dirs, fwd: dict = None, grad_rgb=None, gra
                      sh=torch.zeros_like(sc.sh))
     truncated = torch.zeros(1, dtype=torch.int32, device=dev)
     R = int(origins.shape[0])
-    rays = _Rays(origins.data_ptr() if R else None, dirs.data_ptr() if R else None, R, t_near, 0, None, None)
+    rays = _Rays(origins.data_ptr() if R else None, dirs.data_ptr() if R else None, R, t_near, image_width, None, None)
     prm = _TraceParams(k, T_min, mode, (C.c_float * 3)(*bg), 0, 0)
     if fwd is None:
         o = _TraceOutputs(None, None, None, None, None, None, int(hit_capacity), 0)

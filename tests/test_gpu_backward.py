@@ -135,7 +135,8 @@ def test_gradients_match_oracle_finite_differences(loss):
 
 def test_backward_retraces_without_a_hit_list():
     """Without the forward's hit-id list the backward pass traces the rays again: the
-    gradients equal those from the listed forward bit for bit."""
+    gradients equal those from the listed forward bit for bit, also when the rays are
+    scheduled as an image."""
     say("backward re-trace")
     scene = inputs.cluster_scene(7, 20_000, 3)
     st = grtx.SceneTensors.from_scene(scene, "cuda")
@@ -147,10 +148,17 @@ def test_backward_retraces_without_a_hit_list():
     a, ta = grtx.trace_backward(bvh, o, d, fwd, grad_rgb=g_rgb, grad_depth=g_dep, k=16, T_min=T_MIN)
     b, tb = grtx.trace_backward(bvh, o, d, None, grad_rgb=g_rgb, grad_depth=g_dep, k=16, T_min=T_MIN,
                                 hit_capacity=256)
+    # the same re-trace scheduled as a 128-wide image, and a forward traced that way
+    c, tc = grtx.trace_backward(bvh, o, d, None, grad_rgb=g_rgb, grad_depth=g_dep, k=16, T_min=T_MIN,
+                                hit_capacity=256, image_width=128)
+    fwd_img = grtx.trace(bvh, o, d, k=16, T_min=T_MIN, hit_capacity=256, image_width=128)
     torch.cuda.synchronize()
-    assert int(ta.item()) == 0 and int(tb.item()) == 0
+    assert int(ta.item()) == 0 and int(tb.item()) == 0 and int(tc.item()) == 0
     for key in a:
         assert torch.equal(a[key], b[key]), key
+        assert torch.equal(a[key], c[key]), key
+    for key in fwd:
+        assert torch.equal(fwd[key], fwd_img[key]), key
     assert float(a["means"].abs().sum()) > 0
 
 
