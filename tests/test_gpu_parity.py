@@ -591,6 +591,22 @@ def test_scene3m_full_size_sampled(k):
     del out
 
 
+def test_image_part_that_does_not_divide_into_rows():
+    """Rays after image_begin that do not divide into rows of image_width are all taken as
+    free rays (scheduling only): outputs, hit lists and counters bit-equal to a trace that
+    declares no image."""
+    say("ragged image part")
+    scene = inputs.cluster_scene(2, 100_000, 3)
+    bvh = build(scene)
+    o, d = (dev(a) for a in inputs.incoherent_rays(45, 10_007))
+    kw = dict(k=16, T_min=T_MIN, hit_capacity=128, stats=True)
+    a = grtx.trace(bvh, o, d, image_width=100, image_begin=3, **kw)  # 10,004 rays: not rows of 100
+    b = grtx.trace(bvh, o, d, **kw)
+    torch.cuda.synchronize()
+    for key in a:
+        assert torch.equal(a[key], b[key]), key
+
+
 @pytest.mark.parametrize("width,height,n_free", [(160, 120, 70_000), (100, 37, 5_003), (64, 64, 0)])
 def test_image_after_free_rays_one_launch(width, height, n_free):
     """Rays that form no image and an image traced in one launch (image_begin): each ray's
