@@ -658,7 +658,9 @@ def run_frame100k(args, stream):
 
 def cpu_baseline(work, sample_rays):
     """The oracle (FP64 brute force over every ray/Gaussian pair) on a seeded sample of the
-    step's rays, on the host threads this process may use."""
+    step's rays, on the host threads this process may use; beside it the oracle's CPU model
+    of the method on the same rays, in checkpoint and restart mode (its rate, node visits
+    against distinct nodes visited, and the checkpoint a ray carries between rounds)."""
     import numpy as np
 
     import oracle
@@ -686,12 +688,25 @@ def cpu_baseline(work, sample_rays):
                         work.cfg["T_min"], nthreads=threads)
     t_build = time.perf_counter() - t0
     t0 = time.perf_counter()
-    oracle.model_render(work.scene, ro, rd, 16, oracle.CHECKPOINT, oracle.RULE_KBUF_MAX, work.amin,
-                        work.cfg["T_min"], nthreads=threads)
+    mc = oracle.model_render(work.scene, ro, rd, 16, oracle.CHECKPOINT, oracle.RULE_KBUF_MAX, work.amin,
+                             work.cfg["T_min"], nthreads=threads)
     t_model = time.perf_counter() - t0
+    mr = oracle.model_render(work.scene, ro, rd, 16, oracle.RESTART, oracle.RULE_KBUF_MAX, work.amin,
+                             work.cfg["T_min"], nthreads=threads)
+
+    def visits(m):
+        # per ray on the binary tree: visits of nodes and leaves, distinct ones, and the
+        # largest checkpoint carried between rounds (8 B per deferred node or evicted hit)
+        c = m["counts"].astype(np.float64)
+        v, u = c[:, 0] + c[:, 1], c[:, 4]
+        return dict(visits_per_ray=float(v.mean()), distinct_per_ray=float(u.mean()),
+                    visits_per_distinct=float(v.sum() / max(u.sum(), 1.0)), rounds_per_ray=float(m["rounds"].mean()),
+                    checkpoint_bytes_per_ray_mean=float(8 * c[:, 5].mean()),
+                    checkpoint_bytes_per_ray_max=float(8 * c[:, 5].max()))
     model = dict(value=len(idx) / max(t_model - t_build, 1e-9) / 1e6, unit="Mrays/s", cores=threads,
                  kind="cpu model of the method (FP64, binary radix-tree BVH, k = 16, checkpoints)",
-                 build_s=t_build, sample="the same rays")
+                 build_s=t_build, sample="the same rays",
+                 checkpoint=visits(mc), restart=visits(mr))
     return dict(value=len(idx) / dt / 1e6, unit="Mrays/s", cores=threads, kind="oracle",
                 sample=f"{len(idx)} of the step's {work.rays} rays ({len(ip)} primary, {len(ii)} incoherent; "
                        f"seeded subsample) against all {work.cfg['n']} Gaussians, FP64 brute force, {dt:.1f} s",

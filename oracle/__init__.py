@@ -330,9 +330,10 @@ def model_render(scene, origins, dirs, k, mode=CHECKPOINT, rule=RULE_KBUF_MAX, a
     (RESTART). rule: the round's cull distance t_max once the k-buffer is full, its
     farthest key (RULE_KBUF_MAX) or the nearest key it rejected or pushed out (RULE_PAPER,
     the walkthrough of Sec. IV-B). t_near = 0, black background.
-    Returns rgb, depth, opacity, nblend, rounds and counts [R,4] (internal nodes visited,
-    leaves tested, nodes deferred, hits evicted); with cap > 0 also the first `cap`
-    blended ids and the round that blended each (round_of)."""
+    Returns rgb, depth, opacity, nblend, rounds and counts [R,6] (internal nodes visited,
+    leaves tested, nodes deferred, hits evicted, distinct nodes and leaves visited, and the
+    largest checkpoint carried between rounds in entries); with cap > 0 also the first
+    `cap` blended ids and the round that blended each (round_of)."""
     L = lib()
     if nthreads is None:
         nthreads = min(16, os.cpu_count() or 1)
@@ -345,7 +346,7 @@ def model_render(scene, origins, dirs, k, mode=CHECKPOINT, rule=RULE_KBUF_MAX, a
     opac = np.zeros(R, np.float64)
     nblend = np.zeros(R, np.int32)
     rounds = np.zeros(R, np.int32)
-    counts = np.zeros((R, 4), np.int64)
+    counts = np.zeros((R, 6), np.int64)
     ids = np.full((R, max(cap, 1)), -1, np.int32) if cap > 0 else None
     round_of = np.zeros((R, max(cap, 1)), np.int32) if cap > 0 else None
     rc = L.oracle_model_render(_p(m, C.c_double), _p(s, C.c_double), _p(q, C.c_double), _p(op, C.c_double),

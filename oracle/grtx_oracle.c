@@ -1115,6 +1115,8 @@ typedef struct {
   double rgb[3], depth, opacity;
   int32_t nblend, rounds;
   int64_t nodes, leaves, deferred, evicted;
+  int64_t unique;  /* distinct nodes and leaves visited */
+  int64_t peak;    /* largest checkpoint carried between rounds: deferred nodes + evicted hits */
 } mres_t;
 
 /* end-of-round state of one round (before its blend), for one ray */
@@ -1136,7 +1138,26 @@ typedef struct {
   mnvec_t nsrc, ndst, stack;
   mkey_t tmax, tmin;
   mres_t *res;
+  uint64_t *seen;     /* one bit per node and leaf: visited by this ray */
+  uint32_t *touched;  /* words of `seen` set by this ray, cleared after it */
+  size_t ntouched, touched_cap;
 } mray_t;
+
+/* count a visit of node or leaf index x (mb_index) as new or repeated */
+static void m_visit(mray_t *R, int64_t x) {
+  uint64_t *w = R->seen + (x >> 6);
+  const uint64_t bit = 1ull << (x & 63);
+  if (*w & bit) return;
+  if (*w == 0) {
+    if (R->ntouched == R->touched_cap) {
+      R->touched_cap = R->touched_cap ? 2 * R->touched_cap : 256;
+      R->touched = (uint32_t *)realloc(R->touched, R->touched_cap * sizeof(uint32_t));
+    }
+    R->touched[R->ntouched++] = (uint32_t)(x >> 6);
+  }
+  *w |= bit;
+  ++R->res->unique;
+}
 
 static void m_offer(mray_t *R, mkey_t key) {
   mkvec_t *kb = &R->kbuf;
@@ -1182,6 +1203,7 @@ static void m_traverse(mray_t *R, uint32_t ref, double t) {
       m_defer(R, e.ref, e.t);
       continue;
     }
+    m_visit(R, mb_index(B, e.ref));
     if (e.ref & LEAF_FLAG) {
       ++R->res->leaves;
       const int64_t gid = B->perm[e.ref & ~LEAF_FLAG];
@@ -1284,6 +1306,7 @@ static void m_ray(mray_t *R, int cap, int32_t *ids, int32_t *round_of, mlog_t *L
         break;
       }
     }
+    if ((int64_t)(R->ndst.n + R->edst.n) > res->peak) res->peak = (int64_t)(R->ndst.n + R->edst.n);
     if (ert) {
       done = 1;
     } else if (P->mode == MODEL_CHECKPOINT) {
@@ -1303,9 +1326,20 @@ static void m_ray(mray_t *R, int cap, int32_t *ids, int32_t *round_of, mlog_t *L
   res->depth = D;
   res->opacity = 1.0 - T;
   res->nblend = nb;
+  for (size_t i = 0; i < R->ntouched; ++i) R->seen[R->touched[i]] = 0;
+  R->ntouched = 0;
+}
+
+/* per-ray visit bitmap over the 2n-1 nodes and leaves */
+static int m_ray_init(mray_t *R, const mbvh_t *B) {
+  const int64_t words = (2 * B->n - 1 + 63) / 64 + 1;
+  R->seen = (uint64_t *)calloc((size_t)words, sizeof(uint64_t));
+  return R->seen ? OR_OK : OR_ERR_MEM;
 }
 
 static void m_ray_free(mray_t *R) {
+  free(R->seen);
+  free(R->touched);
   free(R->kbuf.a);
   free(R->esrc.a);
   free(R->edst.a);
@@ -1325,6 +1359,7 @@ typedef struct {
   double *rgb, *depth, *opac;
   int32_t *nblend, *ids, *round_of, *rounds;
   int64_t *counts;
+  int failed;
 } mjob_t;
 
 static void *m_worker(void *arg) {
@@ -1337,6 +1372,10 @@ static void *m_worker(void *arg) {
   R.P = J->P;
   mres_t res;
   R.res = &res;
+  if (m_ray_init(&R, J->B) != OR_OK) {
+    J->failed = 1;
+    return NULL;
+  }
   for (int64_t r = J->r0; r < J->r1; ++r) {
     for (int a = 0; a < 3; ++a) {
       R.o[a] = J->ro[3 * r + a];
@@ -1349,10 +1388,13 @@ static void *m_worker(void *arg) {
     if (J->nblend) J->nblend[r] = res.nblend;
     if (J->rounds) J->rounds[r] = res.rounds;
     if (J->counts) {
-      J->counts[4 * r + 0] = res.nodes;
-      J->counts[4 * r + 1] = res.leaves;
-      J->counts[4 * r + 2] = res.deferred;
-      J->counts[4 * r + 3] = res.evicted;
+      int64_t *c = J->counts + 6 * r;
+      c[0] = res.nodes;
+      c[1] = res.leaves;
+      c[2] = res.deferred;
+      c[3] = res.evicted;
+      c[4] = res.unique;
+      c[5] = res.peak;
     }
   }
   m_ray_free(&R);
@@ -1362,8 +1404,10 @@ static void *m_worker(void *arg) {
 /* The method on the CPU for R rays (unit directions, t_near = 0, black background).
  * k >= 1; mode MODEL_CHECKPOINT or MODEL_RESTART; rule RULE_KBUF_MAX or RULE_PAPER.
  * Outputs per ray: rgb[3], depth, opacity; optionally the number of blended hits and of
- * rounds, the first `cap` blended ids and the round that blended each, and four counts
- * (internal nodes visited, leaves tested, nodes deferred, hits evicted). */
+ * rounds, the first `cap` blended ids and the round that blended each, and six counts
+ * (internal nodes visited, leaves tested, nodes deferred, hits evicted, distinct nodes
+ * and leaves visited, and the largest checkpoint carried from one round to the next in
+ * entries: deferred nodes plus evicted hits). */
 int oracle_model_render(const double *means, const double *scales, const double *quats, const double *opac,
                         const double *sh, int64_t n, int sh_degree, int64_t nrays, const double *ray_o,
                         const double *ray_d, double alpha_min, double T_min, int k, int mode, int rule, int cap,
@@ -1395,16 +1439,20 @@ int oracle_model_render(const double *means, const double *scales, const double 
   }
   for (int t = 0; t < nt; ++t) {
     mjob_t J = {&B, g, &s, &P, ray_o, ray_d, nrays * t / nt, nrays * (t + 1) / nt, cap, rgb, depth, opacity,
-                nblend, ids, round_of, rounds, counts};
+                nblend, ids, round_of, rounds, counts, 0};
     jobs[t] = J;
     pthread_create(th + t, NULL, m_worker, jobs + t);
   }
-  for (int t = 0; t < nt; ++t) pthread_join(th[t], NULL);
+  int failed = 0;
+  for (int t = 0; t < nt; ++t) {
+    pthread_join(th[t], NULL);
+    failed |= jobs[t].failed;
+  }
   free(th);
   free(jobs);
   free_all(g, n);
   mb_free(&B);
-  return OR_OK;
+  return failed ? OR_ERR_MEM : OR_OK;
 }
 
 /* The state of one ray at the end of round `round` (1-based), before that round blends:
@@ -1440,6 +1488,11 @@ int oracle_model_round_state(const double *means, const double *scales, const do
   R.s = &s;
   R.P = &P;
   R.res = &res;
+  if (m_ray_init(&R, &B) != OR_OK) {
+    free_all(g, n);
+    mb_free(&B);
+    return OR_ERR_MEM;
+  }
   for (int a = 0; a < 3; ++a) {
     R.o[a] = ray_o[a];
     R.d[a] = ray_d[a];

@@ -95,7 +95,7 @@ int main(void) {
   /* the CPU model of the method: every mode and rule, k from 1 to above the hit count,
    * on the scene and on a one-Gaussian scene; then one ray's round-2 state */
   int32_t *ro = malloc(sizeof(int32_t) * R * CAP), *nr = malloc(sizeof(int32_t) * R);
-  int64_t *cnt = malloc(sizeof(int64_t) * 4 * R);
+  int64_t *cnt = malloc(sizeof(int64_t) * 6 * R);
   for (int k = 1; k <= 64; k *= 4)
     for (int mode = 0; mode <= 1; ++mode)
       for (int rule = 0; rule <= 1; ++rule) {

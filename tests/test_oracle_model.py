@@ -65,13 +65,17 @@ def test_model_equals_brute_force(n, dup):
 def test_model_rounds_blend_consecutive_ranks():
     """Round r blends the hits of sorted ranks (r-1)k .. rk-1 (each round collects the k
     nearest hits not yet blended), and the ray takes ceil(n/k) rounds for n blended hits,
-    or one more when the last round filled its k-buffer and found nothing beyond."""
+    or one more when the last round filled its k-buffer and found nothing beyond. With
+    checkpoints no node or leaf is visited twice."""
     scene = dense_tiny(31, 64)
     o, d = rays(32, 8, 96)
     for k in (1, 3, 4, 16):
         for mode in MODES:
             for rule in RULES:
                 m = oracle.model_render(scene, o, d, k, mode, rule, AMIN, T_MIN, cap=512)
+                c = m["counts"]
+                if mode == oracle.CHECKPOINT:  # no node or leaf visited twice
+                    assert np.array_equal(c[:, 0] + c[:, 1], c[:, 4]), (k, rule)
                 for r in range(o.shape[0]):
                     nb = int(m["nblend"][r])
                     assert np.array_equal(m["round_of"][r, :nb], np.arange(nb) // k + 1), (k, mode, rule, r)
@@ -81,8 +85,8 @@ def test_model_rounds_blend_consecutive_ranks():
 
 def test_model_scene100k_and_checkpoint_saves_fetches():
     """A 100k-Gaussian SH-degree-3 scene: primary and incoherent rays at k = 16 match the
-    brute force in both modes; checkpointing visits fewer nodes than restart from root and
-    each mode's visits are the same for both t_max rules where the k-buffer alone decides."""
+    brute force in both modes. Checkpointing visits every node and leaf at most once and
+    fewer in all than restart from root, whose rays of several rounds visit some twice."""
     scene = inputs.cluster_scene(2, 100_000, 3)
     cam = inputs.orbit_camera(64, 64)
     po, pd = oracle.pinhole_rays(cam)
@@ -93,9 +97,17 @@ def test_model_scene100k_and_checkpoint_saves_fetches():
     fetched = {}
     for mode in MODES:
         _, m = check_same(scene, o, d, 16, mode, oracle.RULE_KBUF_MAX)
-        fetched[mode] = int(m["counts"][:, 0].sum() + m["counts"][:, 1].sum())
+        c = m["counts"]
+        visits = c[:, 0] + c[:, 1]
+        fetched[mode] = int(visits.sum())
         if mode == oracle.RESTART:
-            assert int(m["counts"][:, 2].sum()) == 0 and int(m["counts"][:, 3].sum()) == 0
+            assert int(c[:, 2].sum()) == 0 and int(c[:, 3].sum()) == 0 and int(c[:, 5].sum()) == 0
+            # rays of several rounds walk the top of the tree again each round
+            multi = m["rounds"] > 1
+            assert multi.any() and (visits[multi] > c[multi, 4]).all()
+        else:
+            # checkpointing visits no node and no leaf twice
+            assert np.array_equal(visits, c[:, 4])
     assert fetched[oracle.CHECKPOINT] < fetched[oracle.RESTART], fetched
 
 
