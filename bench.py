@@ -685,14 +685,15 @@ def cpu_baseline(work, sample_rays):
     # checkpoints) on the same rays; its BVH build is timed apart with a one-ray call
     t0 = time.perf_counter()
     oracle.model_render(work.scene, ro[:1], rd[:1], 16, oracle.CHECKPOINT, oracle.RULE_KBUF_MAX, work.amin,
-                        work.cfg["T_min"], nthreads=threads)
+                        work.cfg["T_min"], nthreads=threads, distinct=False)
     t_build = time.perf_counter() - t0
     t0 = time.perf_counter()
-    mc = oracle.model_render(work.scene, ro, rd, 16, oracle.CHECKPOINT, oracle.RULE_KBUF_MAX, work.amin,
-                             work.cfg["T_min"], nthreads=threads)
+    oracle.model_render(work.scene, ro, rd, 16, oracle.CHECKPOINT, oracle.RULE_KBUF_MAX, work.amin,
+                        work.cfg["T_min"], nthreads=threads, distinct=False)
     t_model = time.perf_counter() - t0
-    mr = oracle.model_render(work.scene, ro, rd, 16, oracle.RESTART, oracle.RULE_KBUF_MAX, work.amin,
-                             work.cfg["T_min"], nthreads=threads)
+    # (untimed: the same rays with distinct visits counted, in both modes)
+    mc, mr = (oracle.model_render(work.scene, ro, rd, 16, m, oracle.RULE_KBUF_MAX, work.amin, work.cfg["T_min"],
+                                  nthreads=threads) for m in (oracle.CHECKPOINT, oracle.RESTART))
 
     def visits(m):
         # per ray on the binary tree: visits of nodes and leaves, distinct ones, and the

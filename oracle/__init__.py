@@ -77,7 +77,8 @@ def lib():
             L.oracle_model_render.restype = C.c_int
             L.oracle_model_render.argtypes = [PD, PD, PD, PD, PD, i64, C.c_int, i64, PD, PD, d, d, C.c_int, C.c_int,
                                               C.c_int, C.c_int, C.c_int, PD, PD, PD, C.POINTER(i32),
-                                              C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i64)]
+                                              C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i64),
+                                              C.c_int]
             L.oracle_model_round_state.restype = C.c_int
             L.oracle_model_round_state.argtypes = [PD, PD, PD, PD, PD, i64, C.c_int, PD, PD, d, d, C.c_int, C.c_int,
                                                    C.c_int, C.c_int, C.POINTER(i64), PD, C.POINTER(i32),
@@ -323,7 +324,7 @@ RULE_KBUF_MAX, RULE_PAPER = 0, 1
 
 
 def model_render(scene, origins, dirs, k, mode=CHECKPOINT, rule=RULE_KBUF_MAX, alpha_min=1.0 / 255.0,
-                 T_min=1e-3, cap=0, nthreads=None):
+                 T_min=1e-3, cap=0, nthreads=None, distinct=True):
     """The method itself on the CPU in FP64 (Sec. III-B, IV): rounds of k-buffer hit
     collection over the oracle's radix tree with exact Gaussian boxes, each round blended
     front to back, resuming from checkpoint lists (mode CHECKPOINT) or from the root
@@ -332,8 +333,9 @@ def model_render(scene, origins, dirs, k, mode=CHECKPOINT, rule=RULE_KBUF_MAX, a
     the walkthrough of Sec. IV-B). t_near = 0, black background.
     Returns rgb, depth, opacity, nblend, rounds and counts [R,6] (internal nodes visited,
     leaves tested, nodes deferred, hits evicted, distinct nodes and leaves visited, and the
-    largest checkpoint carried between rounds in entries); with cap > 0 also the first
-    `cap` blended ids and the round that blended each (round_of)."""
+    largest checkpoint carried between rounds in entries; the distinct count only with
+    `distinct`, which costs a visit bitmap per thread); with cap > 0 also the first `cap`
+    blended ids and the round that blended each (round_of)."""
     L = lib()
     if nthreads is None:
         nthreads = min(16, os.cpu_count() or 1)
@@ -354,7 +356,7 @@ def model_render(scene, origins, dirs, k, mode=CHECKPOINT, rule=RULE_KBUF_MAX, a
                                _p(d, C.c_double), alpha_min, T_min, k, mode, rule, cap, nthreads,
                                _p(rgb, C.c_double), _p(depth, C.c_double), _p(opac, C.c_double),
                                _p(nblend, C.c_int32), _p(ids, C.c_int32), _p(round_of, C.c_int32),
-                               _p(rounds, C.c_int32), _p(counts, C.c_int64))
+                               _p(rounds, C.c_int32), _p(counts, C.c_int64), 1 if distinct else 0)
     if rc != 0:
         raise RuntimeError(f"oracle_model_render failed ({rc})")
     out = dict(rgb=rgb, depth=depth, opacity=opac, nblend=nblend, rounds=rounds, counts=counts)

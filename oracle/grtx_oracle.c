@@ -1203,7 +1203,7 @@ static void m_traverse(mray_t *R, uint32_t ref, double t) {
       m_defer(R, e.ref, e.t);
       continue;
     }
-    m_visit(R, mb_index(B, e.ref));
+    if (R->seen) m_visit(R, mb_index(B, e.ref));
     if (e.ref & LEAF_FLAG) {
       ++R->res->leaves;
       const int64_t gid = B->perm[e.ref & ~LEAF_FLAG];
@@ -1326,7 +1326,8 @@ static void m_ray(mray_t *R, int cap, int32_t *ids, int32_t *round_of, mlog_t *L
   res->depth = D;
   res->opacity = 1.0 - T;
   res->nblend = nb;
-  for (size_t i = 0; i < R->ntouched; ++i) R->seen[R->touched[i]] = 0;
+  if (R->seen)
+    for (size_t i = 0; i < R->ntouched; ++i) R->seen[R->touched[i]] = 0;
   R->ntouched = 0;
 }
 
@@ -1359,6 +1360,7 @@ typedef struct {
   double *rgb, *depth, *opac;
   int32_t *nblend, *ids, *round_of, *rounds;
   int64_t *counts;
+  int distinct;
   int failed;
 } mjob_t;
 
@@ -1372,7 +1374,7 @@ static void *m_worker(void *arg) {
   R.P = J->P;
   mres_t res;
   R.res = &res;
-  if (m_ray_init(&R, J->B) != OR_OK) {
+  if (J->distinct && m_ray_init(&R, J->B) != OR_OK) {
     J->failed = 1;
     return NULL;
   }
@@ -1407,12 +1409,13 @@ static void *m_worker(void *arg) {
  * rounds, the first `cap` blended ids and the round that blended each, and six counts
  * (internal nodes visited, leaves tested, nodes deferred, hits evicted, distinct nodes
  * and leaves visited, and the largest checkpoint carried from one round to the next in
- * entries: deferred nodes plus evicted hits). */
+ * entries: deferred nodes plus evicted hits; the distinct count only with `distinct`, which
+ * costs a visit bitmap per thread, otherwise 0). */
 int oracle_model_render(const double *means, const double *scales, const double *quats, const double *opac,
                         const double *sh, int64_t n, int sh_degree, int64_t nrays, const double *ray_o,
                         const double *ray_d, double alpha_min, double T_min, int k, int mode, int rule, int cap,
                         int nthreads, double *rgb, double *depth, double *opacity, int32_t *nblend, int32_t *ids,
-                        int32_t *round_of, int32_t *rounds, int64_t *counts) {
+                        int32_t *round_of, int32_t *rounds, int64_t *counts, int distinct) {
   if (n < 0 || nrays < 0 || k < 1 || (mode != MODEL_CHECKPOINT && mode != MODEL_RESTART) ||
       (rule != RULE_KBUF_MAX && rule != RULE_PAPER) || cap < 0)
     return OR_ERR_ARG;
@@ -1439,7 +1442,7 @@ int oracle_model_render(const double *means, const double *scales, const double 
   }
   for (int t = 0; t < nt; ++t) {
     mjob_t J = {&B, g, &s, &P, ray_o, ray_d, nrays * t / nt, nrays * (t + 1) / nt, cap, rgb, depth, opacity,
-                nblend, ids, round_of, rounds, counts, 0};
+                nblend, ids, round_of, rounds, counts, distinct, 0};
     jobs[t] = J;
     pthread_create(th + t, NULL, m_worker, jobs + t);
   }

@@ -27,7 +27,7 @@ int oracle_model_render(const double *means, const double *scales, const double 
                         const double *sh, int64_t n, int sh_degree, int64_t nrays, const double *ray_o,
                         const double *ray_d, double alpha_min, double T_min, int k, int mode, int rule, int cap,
                         int nthreads, double *rgb, double *depth, double *opacity, int32_t *nblend, int32_t *ids,
-                        int32_t *round_of, int32_t *rounds, int64_t *counts);
+                        int32_t *round_of, int32_t *rounds, int64_t *counts, int distinct);
 int oracle_model_round_state(const double *means, const double *scales, const double *quats, const double *opac,
                              const double *sh, int64_t n, int sh_degree, const double *ray_o, const double *ray_d,
                              double alpha_min, double T_min, int k, int mode, int rule, int round,
@@ -100,10 +100,10 @@ int main(void) {
     for (int mode = 0; mode <= 1; ++mode)
       for (int rule = 0; rule <= 1; ++rule) {
         if (oracle_model_render(means, scales, quats, opac, sh, N, L, R, o, d, 1.0 / 255.0, 1e-3, k, mode, rule, CAP,
-                                4, rgb, dep, op, nb, ids, ro, nr, cnt))
+                                4, rgb, dep, op, nb, ids, ro, nr, cnt, rule))
           return 9;
         if (oracle_model_render(means, scales, quats, opac, sh, 1, L, R, o, d, 1.0 / 255.0, 1e-3, k, mode, rule, 0, 2,
-                                rgb, dep, op, NULL, NULL, NULL, NULL, NULL))
+                                rgb, dep, op, NULL, NULL, NULL, NULL, NULL, 1))
           return 10;
       }
   {
