@@ -291,7 +291,8 @@ grtx_status grtx_trace(const grtx_bvh* bvh, const grtx_rays* rays, const grtx_tr
  * holds from the library's first use on it until the process ends. As many persistent
  * workgroups run as their lists fit in it (about 2.1 MiB per workgroup at k = 16 with
  * the 256/128 default capacities, 11 MiB with 2048/512), so throughput can be below
- * grtx_trace's; image rays are taken in row-major tile order. GRTX_ERR_CAPACITY when not
+ * grtx_trace's; image rays are taken in row-major tile order and other rays in the
+ * caller's order (grtx_trace orders both by estimated cost). GRTX_ERR_CAPACITY when not
  * even one workgroup's lists fit (lower defer_capacity / evict_capacity). Every call on a
  * device uses that device's one array: calls that overlap on one device (different
  * streams or threads without ordering between them) race and give wrong results; calls
