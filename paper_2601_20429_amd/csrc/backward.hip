@@ -147,14 +147,27 @@ __global__ void __launch_bounds__(kBlock) k_bwd_pairs(BwdArgs A) {
   const int ncoef = (A.sh_degree + 1) * (A.sh_degree + 1);
 
   float T = 1.f, Cacc[3] = {0.f, 0.f, 0.f}, Dacc = 0.f;
+  // The hits of a ray are replayed in order, one at a time, and the longest ray sets the
+  // kernel's end: each step reads the next hit's id ahead and issues all of its own hit's
+  // parameter loads (SH included) together, so fewer memory latencies separate two steps.
+  int32_t i_cur = A.hit_ids[r * A.hit_cap];
+  asm volatile("" ::"v"(i_cur));  // (in hand on entry too: the loop head then waits for nothing)
   for (int h = 0; h < n; ++h) {
-    const int64_t i = A.hit_ids[r * A.hit_cap + h];
+    const int32_t i_ahead = A.hit_ids[r * A.hit_cap + (h + 1 < n ? h + 1 : h)];  // (the last re-reads its own)
+    const int64_t i = i_cur;
     if (i < 0 || i >= A.n_gauss) {  // not a Gaussian of this scene: an empty record, sorted last
       const uint32_t pi = base + (uint32_t)h;
       for (int q = 0; q < 4; ++q) A.rec[4 * (int64_t)pi + q] = make_float4(0.f, 0.f, 0.f, 0.f);
       A.key[pi] = (uint64_t)A.n_gauss;
       A.val[pi] = pi;
+      i_cur = i_ahead;
       continue;
+    }
+    float4 shv[12];
+    if (A.sh_degree == 3) {
+      const float4* sp4 = reinterpret_cast<const float4*>(A.sh + i * 48);
+#pragma unroll
+      for (int q = 0; q < 12; ++q) shv[q] = sp4[q];
     }
     // ---- recompute the hit
     const float4 q4 = reinterpret_cast<const float4*>(A.quats)[i];
@@ -187,11 +200,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_pairs(BwdArgs A) {
     bool pos[3];
     float acc[3] = {0.5f, 0.5f, 0.5f};
     if (A.sh_degree == 3) {
-      // the 48 coefficients as twelve 16-B loads, all in flight before the sums
-      const float4* sp4 = reinterpret_cast<const float4*>(A.sh + i * 48);
-      float4 shv[12];
-#pragma unroll
-      for (int q = 0; q < 12; ++q) shv[q] = sp4[q];
+      // the 48 coefficients, loaded above as twelve 16-B loads
 #pragma unroll
       for (int q = 0; q < 12; ++q) {
         const float* vv = reinterpret_cast<const float*>(&shv[q]);
@@ -258,6 +267,9 @@ __global__ void __launch_bounds__(kBlock) k_bwd_pairs(BwdArgs A) {
     const float gz = 2.f * (-2.f * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] - 2.f * z * gR[1][1] +
                             y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
     const float dot = w * gw + x * gx + y * gy + z * gz;
+    // the id read ahead is in hand before this step's stores go out (an empty asm that
+    // takes it as an input), so the next step does not wait for them
+    asm volatile("" ::"v"(i_ahead));
     const uint32_t pi = base + (uint32_t)h;
     float4* rp = A.rec + 4 * (int64_t)pi;
     rp[0] = make_float4(g_mu[0], g_mu[1], g_mu[2], g_s[0]);
@@ -266,6 +278,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_pairs(BwdArgs A) {
     rp[3] = make_float4(gcol[1], gcol[2], __uint_as_float((uint32_t)r), 0.f);
     A.key[pi] = (uint64_t)i;
     A.val[pi] = pi;
+    i_cur = i_ahead;
   }
 }
 
