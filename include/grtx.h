@@ -197,7 +197,10 @@ typedef struct grtx_trace_params {
   int32_t reserved;
 } grtx_trace_params;
 
-/* Per-ray counters written to grtx_trace_outputs.stats. */
+/* Per-ray counters written to grtx_trace_outputs.stats. They count the work a ray took.
+ * Where a checkpoint list fills and is compacted, the point at which that happens follows
+ * the launch's scheduling, so the counts of entries written and of the work after it can
+ * differ between launches; the blended count and the rounds, like the outputs, cannot. */
 enum {
   GRTX_STAT_NODES = 0,      /* internal nodes fetched and tested */
   GRTX_STAT_LEAVES = 1,     /* leaf primitives fetched and tested */
@@ -276,8 +279,8 @@ grtx_status grtx_bvh_destroy(grtx_bvh* bvh);
 grtx_status grtx_pinhole_rays(const grtx_camera* cam, float* origins, float* dirs, void* stream);
 
 /* Render `rays` against `bvh` (Sec. III-A pipeline with Sec. IV-B checkpointing).
- * Deterministic: the same inputs give bit-identical outputs, in either mode and for
- * any k. The library keeps a per-(device, stream) pool of per-ray checkpoint storage and
+ * Deterministic: the same inputs give bit-identical colour, depth, opacity and hit lists,
+ * in either mode, for any k and whatever the scheduling (see the counters above). The library keeps a per-(device, stream) pool of per-ray checkpoint storage and
  * grows it on demand (GRTX_ERR_OUT_OF_MEMORY if it cannot). Calls on one stream are
  * ordered; calls on different streams use different pools. */
 grtx_status grtx_trace(const grtx_bvh* bvh, const grtx_rays* rays, const grtx_trace_params* p,

@@ -390,3 +390,42 @@ def test_secondary_full_size_launch():
                                      image_width=cfg["width"]))
     for key in ("rgb", "depth", "opacity"):
         assert np.array_equal(a[key], b[key]), key
+
+
+def test_continued_rays_with_free_rays_in_one_launch():
+    """Free rays ahead of an image in one launch (image_begin) with the glass and the
+    mirror, continuation fused: each ray's outputs and hit list are bit-equal to its own
+    set traced alone (the image's tiles that hold continued rays go first within the
+    image, found through the kind array past image_begin), and so are its blended count
+    and rounds. (The other counters count work, which depends on when a full checkpoint
+    list was compacted, and that depends on the launch's scheduling.)"""
+    say("continuation, free rays + image in one launch")
+    scene = inputs.cluster_scene(2, 100_000, 3)
+    bvh = build(scene)
+    cam = inputs.orbit_camera(160, 120)
+    po, pd = grtx.pinhole_rays(cam)
+    fo, fd = (dev(a) for a in inputs.incoherent_rays(46, 3_001, box=1.0))
+    o, d = torch.cat([fo, po]), torch.cat([fd, pd])
+    nf = int(fo.shape[0])
+    ob = grtx.object_rays(OBJS, o, d)
+    kw = dict(k=16, T_min=T_MIN, hit_capacity=256, stats=True)
+
+    def part(a, b):
+        return {key: v[a:b].contiguous() for key, v in ob.items()}
+
+    both = grtx.trace(bvh, o, d, image_width=cam.width, image_begin=nf, t_far=ob["t_far"], continuation=ob, **kw)
+    pf, pi = part(0, nf), part(nf, int(o.shape[0]))
+    free = grtx.trace(bvh, fo, fd, t_far=pf["t_far"], continuation=pf, **kw)
+    img = grtx.trace(bvh, po, pd, image_width=cam.width, t_far=pi["t_far"], continuation=pi, **kw)
+    torch.cuda.synchronize()
+    assert int((pi["kind"] > 0).sum()) > 100 and int((pf["kind"] > 0).sum()) > 10
+    for key in ("rgb", "depth", "opacity", "hit_ids", "hit_counts"):
+        assert torch.equal(both[key][:nf], free[key]), key
+        assert torch.equal(both[key][nf:], img[key]), key
+    st = both["stats"]
+    for f in (grtx.STAT_BLENDED, grtx.STAT_ROUNDS, grtx.STAT_STACK_DROPS):
+        assert torch.equal(st[:nf, f], free["stats"][:, f]), f
+        assert torch.equal(st[nf:, f], img["stats"][:, f]), f
+    diff = [int((torch.cat([st[:nf], st[nf:]]) != torch.cat([free["stats"], img["stats"]]))[:, f].sum())
+            for f in range(grtx.STATS_FIELDS)]
+    say("rays whose work counters differ, per field:", diff)
