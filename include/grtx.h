@@ -200,7 +200,8 @@ typedef struct grtx_trace_params {
 /* Per-ray counters written to grtx_trace_outputs.stats. They count the work a ray took.
  * Where a checkpoint list fills and is compacted, the point at which that happens follows
  * the launch's scheduling, so the counts of entries written and of the work after it can
- * differ between launches; the blended count and the rounds, like the outputs, cannot. */
+ * differ between launches, and so can the rounds of a ray that then restarts from the
+ * root (GRTX_STAT_FALLBACKS); the blended count, like the outputs, cannot. */
 enum {
   GRTX_STAT_NODES = 0,      /* internal nodes fetched and tested */
   GRTX_STAT_LEAVES = 1,     /* leaf primitives fetched and tested */

@@ -593,8 +593,8 @@ def test_scene3m_full_size_sampled(k):
 
 def test_image_part_that_does_not_divide_into_rows():
     """Rays after image_begin that do not divide into rows of image_width are all taken as
-    free rays (scheduling only): outputs, hit lists and counters bit-equal to a trace that
-    declares no image."""
+    free rays (scheduling only): outputs, hit lists and blended counts bit-equal to a trace
+    that declares no image."""
     say("ragged image part")
     scene = inputs.cluster_scene(2, 100_000, 3)
     bvh = build(scene)
@@ -603,14 +603,16 @@ def test_image_part_that_does_not_divide_into_rows():
     a = grtx.trace(bvh, o, d, image_width=100, image_begin=3, **kw)  # 10,004 rays: not rows of 100
     b = grtx.trace(bvh, o, d, **kw)
     torch.cuda.synchronize()
-    for key in a:
+    for key in ("rgb", "depth", "opacity", "hit_ids", "hit_counts"):
         assert torch.equal(a[key], b[key]), key
+    assert torch.equal(a["stats"][:, grtx.STAT_BLENDED], b["stats"][:, grtx.STAT_BLENDED])
 
 
 @pytest.mark.parametrize("width,height,n_free", [(160, 120, 70_000), (100, 37, 5_003), (64, 64, 0)])
 def test_image_after_free_rays_one_launch(width, height, n_free):
     """Rays that form no image and an image traced in one launch (image_begin): each ray's
-    outputs, hit list and counters are bit-equal to those of its own set traced alone
+    outputs, hit list, blended count and (where no ray restarted after a list compaction)
+    rounds are bit-equal to those of its own set traced alone
     (scheduling only; 70,000 free rays are enough for the density ordering, 5,003 are
     not; a 100x37 image has ragged tiles), and sampled rays of both parts match the
     oracle. With image_begin = count every ray is a free ray."""
@@ -628,11 +630,20 @@ def test_image_after_free_rays_one_launch(width, height, n_free):
     free = grtx.trace(bvh, dev(fo), dev(fd), **kw) if n_free else None
     flat = grtx.trace(bvh, o, d, image_width=width, image_begin=o.shape[0], **kw)  # no image part
     torch.cuda.synchronize()
-    for key in both:
+    for key in ("rgb", "depth", "opacity", "hit_ids", "hit_counts"):
         assert torch.equal(both[key][n_free:], img[key]), key
         assert torch.equal(flat[key], both[key]), key
         if free is not None:
             assert torch.equal(both[key][:n_free], free[key]), key
+    # counters that do not follow the scheduling (the others count work, which depends on
+    # when a full checkpoint list was compacted)
+    alone = torch.cat([free["stats"], img["stats"]]) if free is not None else img["stats"]
+    for other in (alone, flat["stats"]):
+        for f in (grtx.STAT_BLENDED, grtx.STAT_STACK_DROPS):
+            assert torch.equal(both["stats"][:, f], other[:, f]), f
+        # rounds too, where neither launch restarted a ray from the root after a compaction
+        ok = (both["stats"][:, grtx.STAT_FALLBACKS] == 0) & (other[:, grtx.STAT_FALLBACKS] == 0)
+        assert torch.equal(both["stats"][ok, grtx.STAT_ROUNDS], other[ok, grtx.STAT_ROUNDS])
     g = {key: v.cpu().numpy() for key, v in both.items()}
     for first, n, seed in [(0, n_free, 3), (n_free, po.shape[0], 4)]:
         if n == 0:
