@@ -552,8 +552,9 @@ class Workload3M:
         return tp, ti
 
     def counters(self, k, mode):
-        """Summed per-ray counters of each ray set in the step's launch (deterministic: an
-        untimed run with the counters on sees exactly the timed work)."""
+        """Summed per-ray counters of each ray set in the step's launch, from an untimed run
+        with the counters on: the timed launch's work, except for the few rays whose
+        checkpoint lists fill and are compacted at a point that follows the scheduling."""
         import torch
 
         from paper_2601_20429_amd import grtx
