@@ -712,7 +712,36 @@ def cpu_baseline(work, sample_rays):
     return dict(value=len(idx) / dt / 1e6, unit="Mrays/s", cores=threads, kind="oracle",
                 sample=f"{len(idx)} of the step's {work.rays} rays ({len(ip)} primary, {len(ii)} incoherent; "
                        f"seeded subsample) against all {work.cfg['n']} Gaussians, FP64 brute force, {dt:.1f} s",
-                host_cpu=cpu_model, host_threads_visible=os.cpu_count(), cpu_model_of_method=model)
+                host_cpu=cpu_model, host_threads_visible=os.cpu_count(), cpu_model_of_method=model,
+                whole_frames=cpu_whole_frames(threads))
+
+
+def cpu_whole_frames(threads):
+    """The oracle and its CPU model of the method over whole frames of the two smaller
+    workloads: the plain 1k-Gaussian 64x64 frame at k = 4 (both), and the 100k-Gaussian
+    800x800 frame at k = 16 (the model; the brute force would take hours)."""
+    import numpy as np
+
+    import oracle
+    from paper_2601_20429_amd import inputs
+    out = {}
+    for cfg, brute in ((inputs.PLAIN, True), (inputs.SCENE100K, False)):
+        scene = inputs.make_workload_scene(cfg)
+        o, d = oracle.pinhole_rays(inputs.orbit_camera(cfg["width"], cfg["height"]))
+        o, d = o.astype(np.float32), d.astype(np.float32)
+        amin = float(np.float32(cfg["alpha_min"]))
+        res = dict(rays=int(o.shape[0]), k=cfg["k"], cores=threads)
+        if brute:
+            t0 = time.perf_counter()
+            oracle.render(scene, o, d, amin, cfg["T_min"], nthreads=threads)
+            res["oracle_mrays_s"] = o.shape[0] / (time.perf_counter() - t0) / 1e6
+        t0 = time.perf_counter()
+        oracle.model_render(scene, o, d, cfg["k"], oracle.CHECKPOINT, oracle.RULE_KBUF_MAX, amin, cfg["T_min"],
+                            nthreads=threads, distinct=False)
+        res["cpu_model_mrays_s"] = o.shape[0] / (time.perf_counter() - t0) / 1e6
+        res["note"] = "the CPU model's rate includes its BVH build"
+        out[cfg["name"]] = res
+    return out
 
 
 def main():
