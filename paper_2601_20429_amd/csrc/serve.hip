@@ -517,7 +517,7 @@ grtx_status serve_add_scene(Server* sv, const Bvh* b, int32_t* scene_id) {
     set_error("grtx_serve_add_scene: all scenes must share one SH degree");
     return GRTX_ERR_INVALID_ARG;
   }
-  if (sv->total_leaves + b->n_leaves >= (int64_t)kLeafFlag) {
+  if (sv->total_leaves + b->n_leaves >= (int64_t)kLeafFlag || sv->total_nodes + b->node_slots >= (int64_t)kLeafFlag) {
     set_error("grtx_serve_add_scene: scene set too large");
     return GRTX_ERR_CAPACITY;
   }
