@@ -246,8 +246,8 @@ typedef struct grtx_camera {
 } grtx_camera;
 
 /* Build the acceleration structure (LBVH: Morton codes of the means, stable radix
- * sort, radix tree, bottom-up refit, then, unless p->plain_lbvh, one bottom-up pass of
- * treelet restructuring) over `g`. Enqueued on `stream`; the handle may be
+ * sort, radix tree, bottom-up refit, then, unless p->plain_lbvh, bottom-up passes of
+ * treelet restructuring: one, three above 2^20 leaves) over `g`. Enqueued on `stream`; the handle may be
  * used for grtx_trace on the same stream right away. On success *out receives a new
  * handle (free it with grtx_bvh_destroy). */
 grtx_status grtx_build(const grtx_gaussians* g, grtx_bvh_kind kind, const grtx_build_params* p,
