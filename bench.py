@@ -417,8 +417,9 @@ def kernel_k(k):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_trace_k16_scene3m_hbm_traffic.txt")
-# the trace kernel, its list sizes and its device helpers
-TRACE_SOURCES = [os.path.join(ROOT, "paper_2601_20429_amd", "csrc", f) for f in ("trace.hip", "trace_common.h")]
+# what the traced launch's traffic depends on: the trace kernel, its list sizes and device
+# helpers, and the build of the tree it walks
+TRACE_SOURCES = [os.path.join(ROOT, "paper_2601_20429_amd", "csrc", f) for f in ("trace.hip", "trace_common.h", "build.hip")]
 
 
 def source_digest():
