@@ -591,6 +591,35 @@ def test_scene3m_full_size_sampled(k):
     del out
 
 
+def test_scene3m_restart_equals_checkpoint():
+    """The largest workload's one launch (2M incoherent rays, then the 1920x1080 frame's
+    tiles), k = 16, in both modes: restart from the root gives bit-identical colour, depth,
+    opacity, hit lists and blended counts, and fetches more nodes on both ray sets (the
+    comparison of Sec. V-B at full size)."""
+    cfg = inputs.SCENE3M
+    say("scene 3M restart against checkpoint")
+    scene = inputs.cluster_scene(cfg["seed"], cfg["n"], 3)
+    cam = inputs.orbit_camera(cfg["width"], cfg["height"])
+    ro, rd = oracle_rays(cam)
+    io, id_ = inputs.incoherent_rays(cfg["incoherent_seed"], cfg["incoherent"])
+    bvh = build(scene)
+    n_inc = io.shape[0]
+    o, d = dev(np.concatenate([io, ro])), dev(np.concatenate([id_, rd]))
+    kw = dict(k=16, T_min=T_MIN, image_width=cfg["width"], image_begin=n_inc, hit_capacity=64, stats=True)
+    a = grtx.trace(bvh, o, d, mode=grtx.CHECKPOINT, **kw)
+    b = grtx.trace(bvh, o, d, mode=grtx.RESTART, **kw)
+    torch.cuda.synchronize()
+    for key in ("rgb", "depth", "opacity", "hit_ids", "hit_counts"):
+        assert torch.equal(a[key], b[key]), key
+    assert torch.equal(a["stats"][:, grtx.STAT_BLENDED], b["stats"][:, grtx.STAT_BLENDED])
+    for label, sl in (("incoherent", slice(0, n_inc)), ("primary", slice(n_inc, None))):
+        fa = int(a["stats"][sl, grtx.STAT_NODES].sum())
+        fb = int(b["stats"][sl, grtx.STAT_NODES].sum())
+        say(dict(set=label, node_fetches_checkpoint=fa, node_fetches_restart=fb))
+        assert fb > fa, label
+    del a, b
+
+
 def test_image_part_that_does_not_divide_into_rows():
     """Rays after image_begin that do not divide into rows of image_width are all taken as
     free rays (scheduling only): outputs, hit lists and blended counts bit-equal to a trace
