@@ -178,14 +178,14 @@ typedef struct grtx_rays {
  * its transmittance below T_min (early ray termination, Sec. III-A), in [0, 1).
  * mode: grtx_mode. bg: background colour added with the remaining transmittance.
  * defer_capacity / evict_capacity: per-ray entries of the checkpoint lists (0 = the
- * defaults: 256 deferred nodes and 128 evicted hits, or 8192 and 2048 for structures of
+ * defaults: 256 deferred nodes and 128 evicted hits, or 12288 and 3072 for structures of
  * more than a million leaves, where grtx_trace_noalloc takes 2048 and 512), rounded up
  * to a multiple of 8. A nearly full list is compacted: its nearer entries stay and the
  * ray's distance limit comes down to where the dropped ones begin; the ray falls back to
  * a restart-from-root round only if its blending reaches that limit. Results are the same
  * for every capacity. The lists live in a per-stream pool of
  * 512 B x (288 + 2 x defer + 2 x evict + k) per wave in flight (3072 waves at k <= 32:
- * about 1.7 GB with 256/128, 33 GB with 8192/2048), kept for later calls on the stream. */
+ * about 1.7 GB with 256/128, 49 GB with 12288/3072), kept for later calls on the stream. */
 typedef struct grtx_trace_params {
   int32_t k;
   float T_min;

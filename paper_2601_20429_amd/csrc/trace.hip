@@ -90,14 +90,17 @@ constexpr int kChunks = GRTX_CHUNKS;
 // 256/128 such rounds are rare on a 100k-Gaussian scene. Structures
 // of more than a million leaves defer several hundred nodes per ray, and rays that start
 // inside a 3M-Gaussian scene over a thousand, with a long tail: at 2048/512, 2% of such
-// rays fell back and the launch took 9% longer than at 8192/2048 (0.01% fall back). The
-// lists are per lane, not per ray, so 8192/2048 costs about 33 GB at k = 16 for 3072
-// waves, affordable in 288 GB. The allocation-free entry point, whose lists share a fixed
-// scratch, keeps 2048/512 there so that enough workgroups fit.
+// rays fell back and the launch took 9% longer than at 8192/2048. At 8192/2048 a few of
+// the heaviest rays of 2M still fell back on three of four seeds of incoherent rays, each
+// restart costing its ray tens of thousands of visits and the launch 18-37%; at
+// 12288/3072 none did on any of them. The lists are per lane, not per ray: 12288/3072
+// costs about 48 GB at k = 16 for 3072 waves, affordable in 288 GB. The allocation-free
+// entry point, whose lists share a fixed scratch, keeps 2048/512 there so that enough
+// workgroups fit.
 constexpr int kDefaultDeferCap = 256;
 constexpr int kDefaultEvictCap = 128;
-constexpr int kLargeDeferCap = 8192;
-constexpr int kLargeEvictCap = 2048;
+constexpr int kLargeDeferCap = 12288;
+constexpr int kLargeEvictCap = 3072;
 constexpr int kNoAllocLargeDeferCap = 2048;
 constexpr int kNoAllocLargeEvictCap = 512;
 constexpr int64_t kLargeScene = 1000000;
@@ -1658,7 +1661,8 @@ grtx_status launch_trace_in(const TraceScene& b, const grtx_rays* r, const grtx_
       if (pool->ptr) GRTX_HIP(hipFreeAsync(pool->ptr, s));
       pool->ptr = nullptr;
       pool->bytes = 0;
-      size_t want = need + need / 4;
+      // some room to grow into, at most 1 GiB of it
+      size_t want = need + std::min<size_t>(need / 4, (size_t)1 << 30);
       GRTX_HIP(hipMallocAsync(&pool->ptr, want, s));
       pool->bytes = want;
       pool->counter = reinterpret_cast<unsigned int*>(pool->ptr);
