@@ -552,6 +552,34 @@ class Workload3M:
         ti = time_launch(lambda: grtx.trace(bvh, self.io, self.id, out=oi, **kw), stream, reps)
         return tp, ti
 
+    def other_seeds(self, k, seeds=(34, 35, 36), reps=2):
+        """The step's launch, checkpointed, with other seeds of the same incoherent-ray
+        distribution in place of the step's (whether the checkpoint lists hold the heaviest
+        rays of other draws too): launch time (HIP events), rays that fell back to a
+        restart round, and the costliest ray's node and leaf visits."""
+        import torch
+
+        from paper_2601_20429_amd import grtx, inputs
+        stream = torch.cuda.current_stream()
+        grtx.pinhole_rays(self.cam, out=(self.po, self.pd))
+        bvh = grtx.build(self.st, alpha_min=self.amin)
+        o, d = torch.empty_like(self.o), torch.empty_like(self.d)
+        o[self.n_inc:], d[self.n_inc:] = self.po, self.pd
+        out = self.outputs(self.rays)
+        kw = self.trace_kw(k, grtx.CHECKPOINT)
+        res = {}
+        for sd in seeds:
+            io, id_ = inputs.incoherent_rays(sd, self.n_inc)
+            o[:self.n_inc] = torch.from_numpy(io).to(self.dev)
+            d[:self.n_inc] = torch.from_numpy(id_).to(self.dev)
+            ms = time_launch(lambda: grtx.trace(bvh, o, d, out=out, **kw), stream, reps)
+            st = grtx.trace(bvh, o, d, stats=True, **kw)["stats"].to(torch.int64)
+            vis = st[:, grtx.STAT_NODES] + st[:, grtx.STAT_LEAVES]
+            res[f"incoherent_seed_{sd}"] = dict(trace_ms=ms, fallbacks=int(st[:, grtx.STAT_FALLBACKS].sum()),
+                                                max_visits_per_ray=int(vis.max()))
+            del st, vis
+        return res
+
     def counters(self, k, mode):
         """Summed per-ray counters of each ray set in the step's launch, from an untimed run
         with the counters on: the timed launch's work, except for the few rays whose
@@ -854,6 +882,8 @@ def main():
         if mode == grtx.CHECKPOINT:
             extra["checkpoint_speedup_step"] = cmp["step_ms"] / head["step_ms"]
             extra["checkpoint_speedup_trace"] = cmp["trace_ms"] / head["trace_ms"]
+        extra["other_incoherent_seeds"] = work.other_seeds(args.k)
+        log("other seeds", json.dumps(extra["other_incoherent_seeds"]))
 
     cpu = None
     if not args.no_cpu_baseline:
