@@ -185,7 +185,8 @@ typedef struct grtx_rays {
  * a restart-from-root round only if its blending reaches that limit. Results are the same
  * for every capacity. The lists live in a per-stream pool of
  * 512 B x (288 + 2 x defer + 2 x evict + k) per wave in flight (3072 waves at k <= 32:
- * about 1.7 GB with 256/128, 49 GB with 12288/3072), kept for later calls on the stream. */
+ * about 1.7 GB with 256/128, 49 GB with 12288/3072), kept for later calls on the stream;
+ * RESTART keeps no lists and takes 512 B x (288 + k) per wave. */
 typedef struct grtx_trace_params {
   int32_t k;
   float T_min;

@@ -277,8 +277,6 @@ int64_t serve_pool_bytes(int k);
 // Centre-out processing order of the 8x8 tiles of a tiles_x x tiles_y image (device array,
 // kept until the process ends).
 grtx_status centre_out_order(int device, int tiles_x, int tiles_y, const uint32_t** out);
-// Bytes of the per-stream checkpoint pool a trace with k-buffer width K allocates.
-int64_t trace_pool_bytes(int K, int cap_d, int cap_e);
 
 struct Server;
 int64_t request_bytes(const grtx_request* r);

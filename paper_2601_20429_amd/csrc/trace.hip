@@ -1532,19 +1532,6 @@ grtx_status centre_out_order(int device, int tiles_x, int tiles_y, const uint32_
   return GRTX_OK;
 }
 
-int64_t trace_pool_bytes(int K, int cap_d, int cap_e) {
-  int device = 0, cus = 0;
-  if (hipGetDevice(&device) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
-  const int64_t blocks = (int64_t)cus * std::max(blocks_per_cu_k<kLeafSphere>(K, false),
-                                                 blocks_per_cu_k<kLeafSphere>(K, true));
-  cap_d = stage_round(cap_d);
-  cap_e = stage_round(cap_e);
-  const int64_t rows = kSpillRows + 2 * (int64_t)cap_d + 2 * (int64_t)cap_e + K;
-  const int64_t need = blocks * kWaves * rows * 64 * (int64_t)sizeof(uint2) + 256;
-  return need + need / 4;
-}
-
 grtx_status trace(const Bvh* b, const grtx_rays* r, const grtx_trace_params* p, const grtx_trace_outputs* o,
                   hipStream_t s) {
   TraceScene sc{b->nodes, b->inst, b->tris, b->sh, b->sh_degree, b->roots, nullptr, b->kind, b->n_leaves, b->cut,
@@ -1632,8 +1619,12 @@ grtx_status launch_trace_in(const TraceScene& b, const grtx_rays* r, const grtx_
   int64_t need_blocks = (R + kTraceBlock - 1) / kTraceBlock;
   if (blocks > need_blocks) blocks = (int)std::max<int64_t>(1, need_blocks);
 
-  const int cap_d = stage_round(p->defer_capacity > 0 ? p->defer_capacity : default_defer_cap(b.n_leaves, noalloc));
-  const int cap_e = stage_round(p->evict_capacity > 0 ? p->evict_capacity : default_evict_cap(b.n_leaves, noalloc));
+  // restart rounds keep no lists: their lanes hold only the stack spill and the park
+  const bool lists = p->mode == GRTX_MODE_CHECKPOINT;
+  const int cap_d =
+      lists ? stage_round(p->defer_capacity > 0 ? p->defer_capacity : default_defer_cap(b.n_leaves, noalloc)) : 0;
+  const int cap_e =
+      lists ? stage_round(p->evict_capacity > 0 ? p->evict_capacity : default_evict_cap(b.n_leaves, noalloc)) : 0;
   const int64_t rows = kSpillRows + 2 * (int64_t)cap_d + 2 * (int64_t)cap_e + K;
   const size_t need = (size_t)blocks * kWaves * rows * 64 * sizeof(uint2) + 256;
 
