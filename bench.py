@@ -580,6 +580,39 @@ class Workload3M:
             del st, vis
         return res
 
+    def two_streams(self, k, steps, warmup=2):
+        """The step issued on the launch stream and a second stream in turn, each with its
+        own ray and output buffers, so that a frame's ray generation and build overlap the
+        previous frame's trace: whole-job throughput of the same work, reported beside the
+        sequential step."""
+        import torch
+
+        from paper_2601_20429_amd import grtx
+        streams = [torch.cuda.current_stream(), torch.cuda.Stream(device=self.o.device)]
+        o2, d2 = torch.empty_like(self.o), torch.empty_like(self.d)
+        o2[:self.n_inc], d2[:self.n_inc] = self.io, self.id
+        bufs = [(self.o, self.d, self.out), (o2, d2, self.outputs(self.rays))]
+        torch.cuda.synchronize()
+
+        def step(i):
+            s = streams[i % 2]
+            o, d, out = bufs[i % 2]
+            with torch.cuda.stream(s):
+                grtx.pinhole_rays(self.cam, out=(o[self.n_inc:], d[self.n_inc:]), stream=s)
+                bvh = grtx.build(self.st, alpha_min=self.amin, stream=s)
+                grtx.trace(bvh, o, d, out=out, stream=s, **self.trace_kw(k, grtx.CHECKPOINT))
+            return bvh
+
+        keep = [step(i) for i in range(warmup)]
+        torch.cuda.synchronize()
+        keep.clear()
+        t0 = time.perf_counter()
+        keep = [step(i) for i in range(steps)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        keep.clear()
+        return dict(step_ms=ms, mrays_s=self.rays / (ms * 1e-3) / 1e6)
+
     def counters(self, k, mode):
         """Summed per-ray counters of each ray set in the step's launch, from an untimed run
         with the counters on: the timed launch's work, except for the few rays whose
@@ -884,6 +917,9 @@ def main():
             extra["checkpoint_speedup_trace"] = cmp["trace_ms"] / head["trace_ms"]
         extra["other_incoherent_seeds"] = work.other_seeds(args.k)
         log("other seeds", json.dumps(extra["other_incoherent_seeds"]))
+        if mode == grtx.CHECKPOINT:
+            extra["two_streams"] = work.two_streams(args.k, max(4, args.steps))
+            log("two streams", json.dumps(extra["two_streams"]))
 
     cpu = None
     if not args.no_cpu_baseline:
