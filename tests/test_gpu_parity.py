@@ -620,6 +620,33 @@ def test_scene3m_restart_equals_checkpoint():
     del a, b
 
 
+def test_two_streams_in_turn_equal_one_stream():
+    """Frames issued on two streams in turn (ray generation, build and trace each; every
+    stream with its own scratch arena and checkpoint pool, consecutive frames overlapping
+    on the device) give the same outputs and hit lists, bit for bit, as one stream."""
+    say("two streams in turn")
+    scene = inputs.cluster_scene(2, 100_000, 3)
+    st = grtx.SceneTensors.from_scene(scene, "cuda")
+    cam = inputs.orbit_camera(320, 240)
+    kw = dict(k=16, T_min=T_MIN, image_width=cam.width, hit_capacity=64)
+    o, d = grtx.pinhole_rays(cam)
+    ref = grtx.trace(grtx.build(st, alpha_min=AMIN), o, d, **kw)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    keep, outs = [], []
+    for i in range(6):
+        s = streams[i % 2]
+        with torch.cuda.stream(s):
+            oi, di = grtx.pinhole_rays(cam, stream=s)
+            bvh = grtx.build(st, alpha_min=AMIN, stream=s)
+            outs.append(grtx.trace(bvh, oi, di, stream=s, **kw))
+        keep.append((bvh, oi, di))
+    torch.cuda.synchronize()
+    for i, out in enumerate(outs):
+        for key in ("rgb", "depth", "opacity", "hit_ids", "hit_counts"):
+            assert torch.equal(out[key], ref[key]), (i, key)
+
+
 def test_image_part_that_does_not_divide_into_rows():
     """Rays after image_begin that do not divide into rows of image_width are all taken as
     free rays (scheduling only): outputs, hit lists and blended counts bit-equal to a trace
